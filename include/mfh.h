@@ -1,0 +1,210 @@
+/*
+ * mfh.h -- C ABI of the HODLR-accelerated multifrontal solver (gfx950).
+ *
+ * Solves A x = b for a sparse symmetric positive definite finite-element
+ * stiffness matrix A (Sec. 1 of Aminfar & Darve, "A Fast and Memory Efficient
+ * Sparse Solver with Applications to Finite-Element Matrices"): a
+ * low-accuracy multifrontal factorisation whose large frontal matrices are
+ * HODLR-compressed (Sec. 4.2) is used as the preconditioner of GMRES
+ * (Sec. 3).  A plain dense-front multifrontal factorisation (Sec. 4.1) is
+ * available through the same calls for comparison.
+ *
+ * Conventions
+ *  - No torch types cross this boundary: plain host or device pointers and
+ *    sizes.  "host" pointers are read during the call and may be freed after
+ *    it returns; "device" pointers are borrowed, must stay valid until the
+ *    work enqueued on the given stream has finished, and are never freed by
+ *    the library.
+ *  - Handles are owned by the library and released by the matching *_free.
+ *    A numeric handle keeps a reference to the data it needs from its
+ *    symbolic handle; the symbolic handle must outlive it.
+ *  - Every call returns an mf_status; on a non-OK status mf_last_error()
+ *    returns a message for the calling thread.  No exception crosses the ABI.
+ *  - One handle is used from one thread/stream at a time; distinct handles
+ *    may be used concurrently.
+ *  - Multi right-hand-side vectors are column-major n x nrhs float64 arrays
+ *    (column k starts at k*n), in the caller's original unknown ordering.
+ *  - Streams: a hipStream_t passed as void*; NULL means the null stream.
+ *    Streams are used at their default priority.
+ */
+#ifndef MFH_H
+#define MFH_H
+
+#include <stdint.h>
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MF_OK = 0,
+  MF_EINVAL = 1,      /* malformed argument (CSR, sizes, options)            */
+  MF_ENOMEM = 2,      /* device or host allocation failed                    */
+  MF_EBUDGET = 3,     /* estimated bytes exceed the caller's budget          */
+  MF_ENOTSPD = 4,     /* a Cholesky pivot was not positive                   */
+  MF_ENOCONV = 5,     /* GMRES hit maxit before reaching tol                 */
+  MF_ECAPACITY = 6,   /* a block rank exceeded the configured rank capacity  */
+  MF_EHIP = 7,        /* a HIP runtime call failed                           */
+  MF_ESTATE = 8       /* call not valid for this handle (e.g. no GPU)        */
+} mf_status;
+
+typedef struct mf_symbolic_s mf_symbolic_t;   /* opaque */
+typedef struct mf_numeric_s mf_numeric_t;     /* opaque */
+
+/* arithmetic of the factor and of the preconditioner apply */
+enum { MF_FP64 = 0, MF_FP32 = 1 };
+/* factorisation method */
+enum { MF_METHOD_HODLR = 0, MF_METHOD_DENSE = 1 };
+
+typedef struct {
+  int32_t method;       /* MF_METHOD_HODLR (Sec. 4.2) or MF_METHOD_DENSE (Sec. 4.1) */
+  int32_t precision;    /* MF_FP64 or MF_FP32 (factors and apply)                   */
+  int32_t n_c;          /* HODLR only: fronts with n_p + n_f < n_c are dense (Table 1 "n_c") */
+  int32_t bdlr_depth;   /* BDLR depth d (Sec. 2.2, Table 1 "d"); < 0: every row/column    */
+  int32_t bdlr_cap;     /* at most this many BDLR rows (and columns) per block              */
+  int32_t adaptive;     /* 1: continue complete pivoting over the whole block until the
+                           pivot-ratio rule holds there (max-norm error < eps*|u_11|)     */
+  int32_t rank_cap;     /* capacity per block rank; exceeding it -> MF_ECAPACITY            */
+  int32_t reserved;
+  double eps;           /* low-rank tolerance (Sec. 2.2: stop when |u_r+1,r+1/u_11| < eps) */
+  void* stream;         /* hipStream_t, borrowed; NULL = null stream                      */
+} mf_opts;
+
+typedef struct {
+  int32_t restart;      /* Krylov dimension m of GMRES(m); default 30      */
+  int32_t maxit;        /* total iterations per right-hand side; default 4000 */
+  void* stream;         /* hipStream_t, borrowed; NULL = null stream       */
+} mf_gmres_opts;
+
+typedef struct {
+  int32_t iters;        /* GMRES iterations spent on this right-hand side   */
+  int32_t converged;    /* 1 if ||b - A x||_2 <= tol ||b||_2                 */
+  double relres;        /* final true relative residual                      */
+} mf_gmres_info;
+
+typedef struct {
+  int64_t n, nnz, nfronts, nlevels, max_front, max_npiv;
+} mf_symbolic_info;
+
+typedef struct {
+  int64_t persistent_bytes;   /* factor bytes kept for the apply (all device arrays of the factor) */
+  int64_t peak_bytes;         /* peak device bytes held by the library during mf_factor             */
+  int64_t workspace_bytes;    /* front workspace (dense staging) part of the peak                   */
+  int64_t nblocks;            /* compressed off-diagonal blocks                                      */
+  int64_t rank_sum;           /* sum of block ranks                                                  */
+  int32_t rank_max;
+  int32_t dense_fronts;       /* fronts factored densely                                             */
+  int32_t hodlr_fronts;
+  int32_t status_bits;        /* device status word (1: non-positive pivot, 2: rank capacity)        */
+  double factor_seconds;      /* wall time of mf_factor (host clock, synchronised)                   */
+} mf_factor_info;
+
+/* Fill *o with defaults: HODLR, FP32, n_c 0, d 4, cap 128, adaptive 1,
+ * rank_cap 256, eps 1e-4, null stream. */
+mf_status mf_opts_default(mf_opts* o);
+mf_status mf_gmres_opts_default(mf_gmres_opts* o);
+
+/*
+ * Symbolic analysis (Sec. 4.1.1): nested-dissection ordering by coordinate
+ * median vertex separators, elimination tree, pivot sets I_p (contiguous in
+ * the new order), coupling sets S_p (Eq. couplingSet), frontal sets I_p^f,
+ * relative extend-add maps, the map of A's lower entries into fronts, HODLR
+ * cluster trees of every front.  Host-only integer work: needs no GPU.
+ *   n        number of unknowns (>= 1)
+ *   rowptr   host int32[n+1], colind host int32[rowptr[n]]: full symmetric
+ *            pattern of A, columns sorted and unique within each row,
+ *            diagonal present.  Explicit zeros count as structure.
+ *   coords   host float64[n*dim] (row-major: node i at coords[i*dim..]),
+ *            positions used by the separator rule; dim in 1..3
+ *   leaf     nested-dissection leaf size, also the HODLR leaf size (>= 1)
+ * Errors: MF_EINVAL for a malformed pattern (unsorted, out of range,
+ * duplicate, missing diagonal, asymmetric), MF_ENOMEM.
+ */
+mf_status mf_analyze(int32_t n, const int32_t* rowptr, const int32_t* colind,
+                     const double* coords, int32_t dim, int32_t leaf,
+                     mf_symbolic_t** out);
+mf_status mf_symbolic_get_info(const mf_symbolic_t* s, mf_symbolic_info* info);
+
+/*
+ * Read-only export of the analysis, for bit-exact comparison.  `what`
+ * selects an int32 array (codes below); if buf is NULL or cap is too small,
+ * only *len is set.  BDLR sets (Sec. 2.2) need mf_symbolic_bdlr first.
+ */
+enum {
+  MF_EXP_PERM = 0,        /* perm[new] = old                                   */
+  MF_EXP_FRONT = 1,       /* per front: start, npiv, nf, parent, height, nchild */
+  MF_EXP_UPD = 2,         /* concatenated I_p^f lists (new indices)            */
+  MF_EXP_UPD_PTR = 3,     /* nfronts+1 offsets into MF_EXP_UPD                  */
+  MF_EXP_RELMAP = 4,      /* concatenated relative maps (same offsets as UPD)  */
+  MF_EXP_ASM = 5,         /* per lower entry: front, row, col, csr index       */
+  MF_EXP_BLOCKS = 6,      /* per block: front, kind(0 top,1 pp,2 ff), r0, nr, c0, nc, level */
+  MF_EXP_BDLR_I = 7,      /* concatenated BDLR row sets (front positions)       */
+  MF_EXP_BDLR_IPTR = 8,   /* nblocks+1 offsets                                  */
+  MF_EXP_BDLR_J = 9,
+  MF_EXP_BDLR_JPTR = 10
+};
+mf_status mf_symbolic_export(const mf_symbolic_t* s, int32_t what, int32_t* buf,
+                             int64_t cap, int64_t* len);
+/* Compute (and cache in the handle) the BDLR sets of every block for depth d
+ * (< 0: all) and set-size cap (>= 1).  Host-only. */
+mf_status mf_symbolic_bdlr(mf_symbolic_t* s, int32_t depth, int32_t cap);
+void mf_symbolic_free(mf_symbolic_t* s);
+
+/*
+ * Numeric factorisation on the current HIP device.
+ *   vals   host float64[nnz]: A's values in the CSR order given to mf_analyze
+ *   eps    low-rank tolerance (overrides opts->eps); ignored for DENSE
+ *   leaf   HODLR leaf size; 0 or the analysis leaf (one value serves both)
+ *   opts   nullable (defaults)
+ * HODLR (Sec. 4.2): each front F_p = F_bar_p (+) children's updates is
+ * staged in device memory; fronts with n_p + n_f >= n_c are compressed
+ * (F_fp ~= W V^T, F_pp and F_ff HODLR, Sec. 2.1) by the BDLR skeleton
+ * (Sec. 2.2, Eq. Bhat), F_pp is factored by recursive Sherman-Morrison-
+ * Woodbury, and U_p = F_ff^HODLR - W S W^T with S = V^T F_pp^{-1} V
+ * (Eq. update_HODLR_Parent) goes to the parent.  DENSE (Sec. 4.1): Cholesky
+ * of F_pp and U_p = F_ff - F_fp F_pp^{-1} F_pf (Eq. update).
+ * Synchronous: returns after the factor is complete.
+ * Errors: MF_EINVAL, MF_ENOMEM, MF_ENOTSPD, MF_ECAPACITY, MF_EHIP,
+ * MF_ESTATE (no GPU).
+ */
+mf_status mf_factor(const mf_symbolic_t* s, const double* vals, double eps,
+                    int32_t leaf, const mf_opts* opts, mf_numeric_t** out);
+mf_status mf_factor_get_info(const mf_numeric_t* f, mf_factor_info* info);
+/* Per-block ranks of the factor in MF_EXP_BLOCKS order (-1 for blocks of
+ * dense fronts); buf NULL -> only *len. */
+mf_status mf_factor_ranks(const mf_numeric_t* f, int32_t* buf, int64_t cap, int64_t* len);
+void mf_factor_free(mf_numeric_t* f);
+
+/*
+ * Preconditioner apply z = M^{-1} r: the multifrontal upward pass
+ * (Eq. upward) and downward pass (Eq. downward) with F_pp^{-1} replaced by
+ * the HODLR solve for compressed fronts (Sec. 4.2.2).
+ *   r, z   device float64[n*nrhs], column-major, original ordering; may not alias
+ *   stream hipStream_t or NULL; asynchronous
+ */
+mf_status mf_apply(mf_numeric_t* f, int32_t nrhs, const double* r, double* z, void* stream);
+
+/*
+ * Right-preconditioned flexible GMRES(m) with M = the factor (Sec. 3):
+ * x0 = 0, classical Gram-Schmidt with reorthogonalisation in float64, stop
+ * when ||b - A x||_2 <= tol ||b||_2 (true residual, float64 SpMV with A) for
+ * every right-hand side.
+ *   b, x   device float64[n*nrhs], column-major, original ordering
+ *   info   host array of nrhs entries (may be NULL)
+ * Synchronous.  Returns MF_ENOCONV (x = last iterate, info filled) when a
+ * right-hand side does not converge within maxit.
+ */
+mf_status gmres_solve(mf_numeric_t* f, int32_t nrhs, const double* b, double* x,
+                      double tol, const mf_gmres_opts* opts, mf_gmres_info* info);
+
+/* y = A x with the factor's device copy of A (float64 CSR), column-major
+ * n x nrhs device arrays; asynchronous on stream. */
+mf_status mf_spmv(mf_numeric_t* f, int32_t nrhs, const double* x, double* y, void* stream);
+
+const char* mf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MFH_H */

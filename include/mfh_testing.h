@@ -1,0 +1,48 @@
+/*
+ * mfh_testing.h -- kernel-level test hooks of libmfh (not part of the
+ * solver API).  Each hook runs one batched kernel of the library on a single
+ * problem so that tests can compare it with a plain reference.  All pointers
+ * are device pointers; `precision` is MF_FP64 (double data) or MF_FP32
+ * (float data); calls are synchronous and return an mf_status.
+ */
+#ifndef MFH_TESTING_H
+#define MFH_TESTING_H
+
+#include "mfh.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Lane layout of the 16x16x4 MFMA accumulator: for lane l and value v,
+ * rows[4l+v] / cols[4l+v] are the output row / column that value holds and
+ * assumed[4l+v] the row the GEMM epilogue assumes (host int32[256] each). */
+mf_status mfh_test_mfma_layout(int32_t precision, int32_t* rows, int32_t* cols, int32_t* assumed);
+
+/* C = alpha * op(A) * op(B) + beta * C through the grouped MFMA GEMM;
+ * flags as the library's GemmFlags (1 lower-only C, 2/4 op(A) lower/upper,
+ * 8/16 op(B) lower/upper triangular). */
+mf_status mfh_test_gemm(int32_t precision, int32_t m, int32_t n, int32_t k, const void* A, int32_t lda,
+                        int32_t opA, const void* B, int32_t ldb, int32_t opB, void* C, int32_t ldc,
+                        double alpha, double beta, int32_t flags);
+
+/* In-place Cholesky of the n x n lower triangle of A (n <= 128) and the
+ * explicit inverse of the factor into Inv (full square, zeros above).
+ * *status_out receives the kernel's status word (1: non-positive pivot). */
+mf_status mfh_test_potrf(int32_t precision, int32_t n, void* A, int32_t lda, void* Inv, int32_t ldi,
+                         int32_t* status_out);
+
+/* Skeleton compression (Sec. 2.2, Eq. Bhat) of the block
+ * F(r0:r0+nr, c0:c0+nc) of an ld-strided matrix F from BDLR row/column
+ * sets I, J (device int32, positions in F; at most 126 (FP64) / 180 (FP32)
+ * entries each).  U (nr x cap) and V (nc x cap) receive C~ and R~^T;
+ * the block of F is overwritten by the residual when adaptive != 0.
+ * *rank_out receives the final rank. */
+mf_status mfh_test_skeleton(int32_t precision, void* F, int32_t ld, int32_t r0, int32_t nr, int32_t c0,
+                            int32_t nc, const int32_t* I, int32_t nI, const int32_t* J, int32_t nJ, double eps,
+                            int32_t adaptive, int32_t cap, void* U, void* V, int32_t* rank_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MFH_TESTING_H */

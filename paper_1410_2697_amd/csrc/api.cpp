@@ -1,0 +1,246 @@
+// C ABI entry points (include/mfh.h).  Converts exceptions into status codes
+// and keeps a per-thread message for mf_last_error().
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+
+#include "../../include/mfh.h"
+#include "numeric.h"
+#include "symbolic.h"
+
+struct mf_symbolic_s {
+  mfh::Symbolic s;
+};
+struct mf_numeric_s {
+  std::unique_ptr<mfh::NumericBase> n;
+};
+
+namespace {
+thread_local std::string g_err;
+mf_status fail(mf_status c, const std::string& m) {
+  g_err = m;
+  return c;
+}
+mf_status gpu_present() {
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || n < 1) {
+    (void)hipGetLastError();
+    return fail(MF_ESTATE, "no HIP device is visible");
+  }
+  return MF_OK;
+}
+template <typename V>
+mf_status export_vec(const V& v, int32_t* buf, int64_t cap, int64_t* len) {
+  if (len) *len = (int64_t)v.size();
+  if (!buf) return MF_OK;
+  if (cap < (int64_t)v.size()) return fail(MF_EINVAL, "export buffer too small");
+  for (size_t i = 0; i < v.size(); ++i) buf[i] = (int32_t)v[i];
+  return MF_OK;
+}
+}  // namespace
+
+#define MF_GUARD_BEGIN try {
+#define MF_GUARD_END                                                   \
+  }                                                                    \
+  catch (const mfh::Err& e) { return fail(e.code, e.msg); }            \
+  catch (const std::bad_alloc&) { return fail(MF_ENOMEM, "host allocation failed"); } \
+  catch (const std::exception& e) { return fail(MF_EINVAL, e.what()); }
+
+extern "C" {
+
+mf_status mf_opts_default(mf_opts* o) {
+  if (!o) return fail(MF_EINVAL, "null opts");
+  std::memset(o, 0, sizeof(*o));
+  o->method = MF_METHOD_HODLR;
+  o->precision = MF_FP32;
+  o->n_c = 0;
+  o->bdlr_depth = 4;
+  o->bdlr_cap = 128;
+  o->adaptive = 1;
+  o->rank_cap = 256;
+  o->eps = 1e-4;
+  o->stream = nullptr;
+  return MF_OK;
+}
+
+mf_status mf_gmres_opts_default(mf_gmres_opts* o) {
+  if (!o) return fail(MF_EINVAL, "null opts");
+  o->restart = 30;
+  o->maxit = 4000;
+  o->stream = nullptr;
+  return MF_OK;
+}
+
+mf_status mf_analyze(int32_t n, const int32_t* rowptr, const int32_t* colind, const double* coords, int32_t dim,
+                     int32_t leaf, mf_symbolic_t** out) {
+  MF_GUARD_BEGIN
+  if (!out) return fail(MF_EINVAL, "null output handle");
+  *out = nullptr;
+  if (n < 1 || !rowptr || !colind || !coords) return fail(MF_EINVAL, "null or empty input");
+  auto h = std::make_unique<mf_symbolic_s>();
+  std::string e = mfh::analyze(n, rowptr, colind, coords, dim, leaf, h->s);
+  if (!e.empty()) return fail(MF_EINVAL, e);
+  *out = h.release();
+  return MF_OK;
+  MF_GUARD_END
+}
+
+mf_status mf_symbolic_get_info(const mf_symbolic_t* sh, mf_symbolic_info* info) {
+  if (!sh || !info) return fail(MF_EINVAL, "null argument");
+  const mfh::Symbolic& s = sh->s;
+  info->n = s.n;
+  info->nnz = s.nnz;
+  info->nfronts = (int64_t)s.fronts.size();
+  info->nlevels = (int64_t)s.levels.size();
+  int64_t mf = 0, mp = 0;
+  for (auto& f : s.fronts) { mf = std::max<int64_t>(mf, f.n()); mp = std::max<int64_t>(mp, f.npiv); }
+  info->max_front = mf;
+  info->max_npiv = mp;
+  return MF_OK;
+}
+
+mf_status mf_symbolic_export(const mf_symbolic_t* sh, int32_t what, int32_t* buf, int64_t cap, int64_t* len) {
+  MF_GUARD_BEGIN
+  if (!sh) return fail(MF_EINVAL, "null handle");
+  const mfh::Symbolic& s = sh->s;
+  std::vector<int64_t> v;
+  switch (what) {
+    case MF_EXP_PERM: return export_vec(s.perm, buf, cap, len);
+    case MF_EXP_FRONT:
+      for (auto& f : s.fronts) {
+        v.push_back(f.start); v.push_back(f.npiv); v.push_back(f.nf());
+        v.push_back(f.parent); v.push_back(f.height); v.push_back((int64_t)f.children.size());
+      }
+      return export_vec(v, buf, cap, len);
+    case MF_EXP_UPD:
+      for (auto& f : s.fronts) v.insert(v.end(), f.upd.begin(), f.upd.end());
+      return export_vec(v, buf, cap, len);
+    case MF_EXP_UPD_PTR:
+      v.push_back(0);
+      for (auto& f : s.fronts) v.push_back(v.back() + f.nf());
+      return export_vec(v, buf, cap, len);
+    case MF_EXP_RELMAP:
+      for (auto& f : s.fronts) {
+        if (f.relmap.size() != f.upd.size()) v.insert(v.end(), f.upd.size(), -1);
+        else v.insert(v.end(), f.relmap.begin(), f.relmap.end());
+      }
+      return export_vec(v, buf, cap, len);
+    case MF_EXP_ASM:
+      for (size_t e = 0; e < s.asm_src.size(); ++e) {
+        v.push_back(s.asm_front[e]); v.push_back(s.asm_row[e]); v.push_back(s.asm_col[e]); v.push_back(s.asm_src[e]);
+      }
+      return export_vec(v, buf, cap, len);
+    case MF_EXP_BLOCKS:
+      for (size_t p = 0; p < s.fronts.size(); ++p)
+        for (auto& b : s.fronts[p].blocks) {
+          v.push_back((int64_t)p); v.push_back(b.kind); v.push_back(b.r0); v.push_back(b.nr);
+          v.push_back(b.c0); v.push_back(b.nc); v.push_back(b.level);
+        }
+      return export_vec(v, buf, cap, len);
+    case MF_EXP_BDLR_I:
+    case MF_EXP_BDLR_IPTR:
+    case MF_EXP_BDLR_J:
+    case MF_EXP_BDLR_JPTR:
+      if (s.bdlr_depth == -2) return fail(MF_ESTATE, "call mf_symbolic_bdlr first");
+      if (what == MF_EXP_BDLR_I) return export_vec(s.bdlr_I, buf, cap, len);
+      if (what == MF_EXP_BDLR_IPTR) return export_vec(s.bdlr_Iptr, buf, cap, len);
+      if (what == MF_EXP_BDLR_J) return export_vec(s.bdlr_J, buf, cap, len);
+      return export_vec(s.bdlr_Jptr, buf, cap, len);
+    default: return fail(MF_EINVAL, "unknown export code");
+  }
+  MF_GUARD_END
+}
+
+mf_status mf_symbolic_bdlr(mf_symbolic_t* sh, int32_t depth, int32_t cap) {
+  MF_GUARD_BEGIN
+  if (!sh) return fail(MF_EINVAL, "null handle");
+  if (cap < 1) return fail(MF_EINVAL, "cap must be >= 1");
+  mfh::compute_bdlr(sh->s, depth, cap);
+  return MF_OK;
+  MF_GUARD_END
+}
+
+void mf_symbolic_free(mf_symbolic_t* s) { delete s; }
+
+mf_status mf_factor(const mf_symbolic_t* sh, const double* vals, double eps, int32_t leaf, const mf_opts* opts,
+                    mf_numeric_t** out) {
+  MF_GUARD_BEGIN
+  if (!out) return fail(MF_EINVAL, "null output handle");
+  *out = nullptr;
+  if (!sh || !vals) return fail(MF_EINVAL, "null argument");
+  mf_opts o;
+  if (opts) o = *opts; else mf_opts_default(&o);
+  o.eps = eps;
+  if (o.method != MF_METHOD_HODLR && o.method != MF_METHOD_DENSE) return fail(MF_EINVAL, "unknown method");
+  if (o.precision != MF_FP64 && o.precision != MF_FP32) return fail(MF_EINVAL, "unknown precision");
+  if (!(eps >= 0.0) || eps >= 1.0) return fail(MF_EINVAL, "eps must be in [0, 1)");
+  if (leaf != 0 && leaf != sh->s.leaf) return fail(MF_EINVAL, "leaf must be 0 or the analysis leaf size");
+  if (o.method == MF_METHOD_HODLR) {
+    if (sh->s.leaf > 128) return fail(MF_EINVAL, "HODLR leaves are limited to 128");
+    if (o.bdlr_cap < 1 || o.rank_cap < 1) return fail(MF_EINVAL, "bdlr_cap and rank_cap must be >= 1");
+    if (o.rank_cap > 512) return fail(MF_EINVAL, "rank_cap is limited to 512");
+    const int maxcap = o.precision == MF_FP64 ? 126 : 180;
+    if (o.bdlr_cap > maxcap) return fail(MF_EINVAL, "bdlr_cap too large for the LDS pivot kernel");
+  }
+  mf_status g = gpu_present();
+  if (g != MF_OK) return g;
+  auto h = std::make_unique<mf_numeric_s>();
+  h->n = mfh::make_numeric(sh->s, vals, o);
+  *out = h.release();
+  return MF_OK;
+  MF_GUARD_END
+}
+
+mf_status mf_factor_get_info(const mf_numeric_t* f, mf_factor_info* info) {
+  if (!f || !info) return fail(MF_EINVAL, "null argument");
+  *info = f->n->info;
+  info->peak_bytes = f->n->ms.peak;
+  return MF_OK;
+}
+
+mf_status mf_factor_ranks(const mf_numeric_t* f, int32_t* buf, int64_t cap, int64_t* len) {
+  if (!f) return fail(MF_EINVAL, "null handle");
+  return export_vec(f->n->ranks, buf, cap, len);
+}
+
+void mf_factor_free(mf_numeric_t* f) { delete f; }
+
+mf_status mf_apply(mf_numeric_t* f, int32_t nrhs, const double* r, double* z, void* stream) {
+  MF_GUARD_BEGIN
+  if (!f || !r || !z || nrhs < 1) return fail(MF_EINVAL, "bad argument");
+  if (r == z) return fail(MF_EINVAL, "r and z may not alias");
+  f->n->apply(nrhs, r, z, static_cast<hipStream_t>(stream));
+  return MF_OK;
+  MF_GUARD_END
+}
+
+mf_status mf_spmv(mf_numeric_t* f, int32_t nrhs, const double* x, double* y, void* stream) {
+  MF_GUARD_BEGIN
+  if (!f || !x || !y || nrhs < 1 || x == y) return fail(MF_EINVAL, "bad argument");
+  f->n->spmv(nrhs, x, y, 1.0, 0.0, static_cast<hipStream_t>(stream));
+  return MF_OK;
+  MF_GUARD_END
+}
+
+mf_status gmres_solve(mf_numeric_t* f, int32_t nrhs, const double* b, double* x, double tol,
+                      const mf_gmres_opts* opts, mf_gmres_info* info) {
+  MF_GUARD_BEGIN
+  if (!f || !b || !x || nrhs < 1 || b == x) return fail(MF_EINVAL, "bad argument");
+  if (!(tol > 0.0)) return fail(MF_EINVAL, "tol must be > 0");
+  mf_gmres_opts o;
+  if (opts) o = *opts; else mf_gmres_opts_default(&o);
+  if (o.restart < 1 || o.restart > 60 || o.maxit < 1) return fail(MF_EINVAL, "restart must be 1..60, maxit >= 1");
+  mf_status s = MF_OK;
+  f->n->gmres(nrhs, b, x, tol, o, info, &s);
+  if (s == MF_ENOCONV) return fail(MF_ENOCONV, "GMRES did not reach tol within maxit");
+  return s;
+  MF_GUARD_END
+}
+
+const char* mf_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,205 @@
+// Device kernels of the multifrontal path and their launch descriptors.
+// All matrices are column-major.  Every launch processes a list of
+// independent problems ("grouped"/batched), so one launch covers all fronts
+// of an elimination-tree level.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace mfh {
+
+constexpr int kTile = 64;            // GEMM output tile (rows and columns)
+constexpr double kTieRel = 1.0 / 1048576.0;   // 2^-20: near-ties in complete pivoting
+
+enum GemmFlags : int {
+  GF_LOWER_C = 1,   // write only C(i, j) with i >= j (symmetric updates)
+  GF_A_LOWER = 2,   // op(A)(i, kk) == 0 for kk > i
+  GF_A_UPPER = 4,   // op(A)(i, kk) == 0 for kk < i
+  GF_B_LOWER = 8,   // op(B)(kk, j) == 0 for kk < j
+  GF_B_UPPER = 16,  // op(B)(kk, j) == 0 for kk > j
+};
+
+// C = alpha * op(A) * op(B) + beta * C ; op(A) m x k, op(B) k x n.
+// If kdev != nullptr the inner dimension is *kdev (a rank produced on the
+// device); k is then an upper bound used only for validation.
+template <typename T>
+struct GemmDesc {
+  const T* A;
+  const T* B;
+  T* C;
+  const int* kdev;
+  int m, n, k;
+  int lda, ldb, ldc;
+  int opA, opB;      // 0: N, 1: T
+  int flags;
+  int tile0;         // first launch tile of this problem
+  int tiles_m;
+  int pad;
+  double alpha, beta;
+};
+
+// In-place Cholesky of an n x n diagonal block (n <= 128) and, if Inv is
+// set, its explicit lower-triangular inverse (full square written, zeros
+// above the diagonal).
+template <typename T>
+struct PotrfDesc {
+  T* A;
+  T* Inv;
+  int lda, ldi, n, pad;
+};
+
+// Phase 1 of the BDLR skeleton (Eq. Bhat): complete-pivot LU of
+// B_hat = F(I, J) held in LDS.
+template <typename T>
+struct SkelDesc {
+  const T* F;
+  const int* I;
+  const int* J;
+  int* piv_r;        // out, front positions, capacity min(nI, nJ)
+  int* piv_c;
+  T* M;              // out: r x r LU (unit-lower L below, U on/above), ld = ldm
+  int* rank;         // out: phase-1 rank
+  double* u11;       // out: |u_11| (0 if none)
+  int ld, nI, nJ, ldm;
+};
+
+// C~ = B(:, J_r) U_r^{-1} (rows of U) and R~^T = (L_r^{-1} B(I_r, :))^T
+// (rows of V) for a block B = F(r0 : r0+nr, c0 : c0+nc).
+template <typename T>
+struct SkelFacDesc {
+  const T* F;
+  const int* piv_r;
+  const int* piv_c;
+  const T* M;
+  const int* rank;
+  T* U;
+  T* V;
+  int ld, r0, nr, c0, nc, ldm, ldu, ldv;
+  int wg0;           // first launch workgroup of this block
+  int wgU;           // workgroups for the U rows (the rest do V rows)
+};
+
+// Phase 2: continue complete pivoting on E = B - U V^T (held in place in
+// the front) until the pivot-ratio rule holds over the whole block.
+template <typename T>
+struct Phase2Desc {
+  T* F;
+  const int* piv_r;
+  const int* piv_c;
+  const int* rank1;
+  const double* u11;
+  T* U;
+  T* V;
+  int* rank;         // out: final rank
+  int ld, r0, nr, c0, nc, ldu, ldv, cap;
+};
+
+// child update (front positions [npc, npc+nfc) of the child buffer) scatter
+// added into the parent front through the relative map.
+template <typename T>
+struct ExtAddDesc {
+  const T* child;
+  T* parent;
+  const int* relmap;
+  int ldc, npc, nfc, ldp;
+  int tile0, tiles_r;
+};
+
+template <typename S, typename D>
+struct CopyDesc {   // dst(i, j) = alpha * src(i, j) (+ dst if accumulate)
+  const S* src;
+  D* dst;
+  int rows, cols, lds, ldd;
+  int accumulate;
+  int tile0, tiles_r, pad;
+  double alpha;
+};
+
+// K = [[P(0:r, c:c+r), I], [I, P(r:2r, c:c+r)]] in float64 (2r x 2r, ld 2r)
+// and Pa = float64 copy of P(:, 0:c).
+template <typename T>
+struct CapDesc {
+  const T* P;
+  double* K;
+  double* Pa;
+  int r, c, ldp, pad;
+};
+
+struct InvDesc {      // Gauss-Jordan inverse with partial pivoting, float64
+  double* A;          // n x 2n work (ld n), A(:, 0:n) preset to K
+  int n, pad;
+};
+
+// upward-pass front vector: t(0:npiv) = xn(start:start+npiv), t(npiv:) = 0,
+// then t(relmap_c) += child's t_c(npiv_c:) for each child in order.
+template <typename T>
+struct VecAsmDesc {
+  T* t;
+  const T* xs;            // xn + start
+  const T* ct[2];
+  const int* crel[2];
+  int nhat, npiv, ldt, ldx;
+  int nchild;
+  int cnp[2], cnf[2], cld[2];
+};
+
+template <typename T>
+struct VecGatherDesc {    // t(0:nf, :) = xn(upd, :)
+  T* t;
+  const int* upd;
+  int nf, ldt;
+};
+
+// ---- launchers (all asynchronous on `st`; descriptor arrays are device) ----
+// MFMA accumulator layout probe (one wave, 64 x 4 entries per output)
+template <typename T>
+void launch_mfma_probe(int* rows, int* cols, int* assumed, hipStream_t st);
+template <typename T>
+void launch_gemm(const GemmDesc<T>* d, int ndesc, int tiles, hipStream_t st);
+template <typename T>
+void launch_potrf(const PotrfDesc<T>* d, int ndesc, int nmax, int* status, hipStream_t st);
+template <typename T>
+void launch_skel(const SkelDesc<T>* d, int ndesc, size_t lds_bytes, double eps, hipStream_t st);
+template <typename T>
+void launch_skelfac(const SkelFacDesc<T>* d, int ndesc, int wgs, int rmax, hipStream_t st);
+template <typename T>
+void launch_phase2(const Phase2Desc<T>* d, int ndesc, int maxrc, double eps, int* status, hipStream_t st);
+template <typename T>
+void launch_extadd(const ExtAddDesc<T>* d, int ndesc, int tiles, hipStream_t st);
+template <typename S, typename D>
+void launch_copy(const CopyDesc<S, D>* d, int ndesc, int tiles, hipStream_t st);
+template <typename T>
+void launch_cap(const CapDesc<T>* d, int ndesc, hipStream_t st);
+void launch_gj_inverse(const InvDesc* d, int ndesc, int* status, hipStream_t st);
+template <typename T>
+void launch_fill(T* p, int64_t n, T v, hipStream_t st);
+template <typename T>
+void launch_assemble(T* base, const int64_t* dest, const int* src, const double* vals, int64_t cnt,
+                     hipStream_t st);
+template <typename T>
+void launch_vec_asm(const VecAsmDesc<T>* d, int ndesc, int nrhs, hipStream_t st);
+template <typename T>
+void launch_vec_gather(const VecGatherDesc<T>* d, int ndesc, const T* xn, int N, int nrhs,
+                       hipStream_t st);
+template <typename T>
+void launch_perm_in(const double* r, T* xn, const int* perm, int N, int nrhs, hipStream_t st);
+template <typename T>
+void launch_perm_out(const T* xn, double* z, const int* iperm, int N, int nrhs, hipStream_t st);
+
+// float64 CSR SpMV, column-major n x nrhs; y = alpha*A*x + beta*y
+void launch_spmv(const int* rowptr, const int* colind, const double* vals, const double* x,
+                 double* y, int n, int nrhs, double alpha, double beta, hipStream_t st);
+// dots[i*nrhs + k] (+)= <X_i(:,k), w(:,k)> for i < nv; X_i = X + i*ld*nrhs...
+void launch_mdot(const double* X, int64_t xstride, int nv, const double* w, int n, int nrhs,
+                 double* partial, double* out, int accumulate, hipStream_t st);
+void launch_maxpy(const double* X, int64_t xstride, int nv, const double* coef, double* w, int n,
+                  int nrhs, double sign, hipStream_t st);
+void launch_scale_cols(const double* w, double* v, const double* norms, int n, int nrhs,
+                       hipStream_t st);
+void launch_xupdate(const double* Z, int64_t zstride, int nv, const double* y, double* x, int n,
+                    int nrhs, hipStream_t st);
+void launch_axpby(const double* a, const double* b, double* c, double alpha, double beta, int64_t n,
+                  hipStream_t st);
+
+}  // namespace mfh

@@ -1,0 +1,804 @@
+// Device kernels for gfx950 (CDNA4, wave64).  See kernels.h for the
+// descriptor of each launch.
+#include "kernels.h"
+
+#include <climits>
+
+namespace mfh {
+
+namespace {
+
+constexpr int kWave = 64;
+
+template <typename T>
+__device__ __forceinline__ T noise_rel();
+template <>
+__device__ __forceinline__ double noise_rel<double>() { return 64.0 * 1.1102230246251565e-16; }
+template <>
+__device__ __forceinline__ float noise_rel<float>() { return 64.0f * 5.9604644775390625e-08f; }
+
+__device__ __forceinline__ double wave_max(double v) {
+  for (int o = kWave / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
+  return v;
+}
+__device__ __forceinline__ int wave_min(int v) {
+  for (int o = kWave / 2; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, kWave));
+  return v;
+}
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+// block-wide reductions; every thread receives the result
+__device__ double block_max(double v, double* sh) {
+  v = wave_max(v);
+  const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+  __syncthreads();
+  if (l == 0) sh[w] = v;
+  __syncthreads();
+  double r = sh[0];
+  for (int i = 1; i < (int)(blockDim.x / kWave); ++i) r = fmax(r, sh[i]);
+  return r;
+}
+__device__ int block_min(int v, int* sh) {
+  v = wave_min(v);
+  const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+  __syncthreads();
+  if (l == 0) sh[w] = v;
+  __syncthreads();
+  int r = sh[0];
+  for (int i = 1; i < (int)(blockDim.x / kWave); ++i) r = min(r, sh[i]);
+  return r;
+}
+__device__ double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+  __syncthreads();
+  if (l == 0) sh[w] = v;
+  __syncthreads();
+  double r = sh[0];
+  for (int i = 1; i < (int)(blockDim.x / kWave); ++i) r += sh[i];
+  return r;
+}
+
+template <typename D>
+__device__ __forceinline__ int find_desc(const D* d, int n, int key) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (d[mid].tile0 <= key) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// 16x16x4 MFMA: lane l supplies A(l%16, l/16) and B(l/16, l%16); its four
+// accumulator values hold D(row(l/16, v), l%16), v = 0..3.  The row map
+// differs between the float64 and float32 instructions.
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  __device__ static __forceinline__ v4 run(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static __forceinline__ int row(int lk, int v) { return lk + 4 * v; }
+};
+template <>
+struct Mfma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  __device__ static __forceinline__ v4 run(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static __forceinline__ int row(int lk, int v) { return 4 * lk + v; }
+};
+
+// ---------------------------------------------------------------- GEMM ----
+// 64x64 output tile per workgroup, 4 waves each owning a 32x32 quadrant as
+// 2x2 MFMA 16x16x4 tiles; K staged through LDS in steps of 16.
+template <typename T>
+__global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc<T>* __restrict__ descs, int ndesc) {
+  constexpr int BM = kTile, BN = kTile, BK = 16;
+  __shared__ T As[BK][BM + 1];
+  __shared__ T Bs[BK][BN + 1];
+  typedef typename Mfma<T>::v4 v4;
+  const int tid = threadIdx.x;
+  const int di = find_desc(descs, ndesc, (int)blockIdx.x);
+  const GemmDesc<T>& d = descs[di];
+  const int lt = (int)blockIdx.x - d.tile0;
+  const int m0 = (lt % d.tiles_m) * BM, n0 = (lt / d.tiles_m) * BN;
+  const int m = d.m, n = d.n, flags = d.flags;
+  const int k = d.kdev ? *d.kdev : d.k;
+  if ((flags & GF_LOWER_C) && n0 >= m0 + BM) return;
+  int kb0 = 0, kend = k;
+  if (flags & GF_A_LOWER) kend = min(kend, m0 + BM);
+  if (flags & GF_B_UPPER) kend = min(kend, n0 + BN);
+  if (flags & GF_A_UPPER) kb0 = max(kb0, m0);
+  if (flags & GF_B_LOWER) kb0 = max(kb0, n0);
+  kb0 = (kb0 / BK) * BK;
+  const T* __restrict__ A = d.A;
+  const T* __restrict__ B = d.B;
+  const int lda = d.lda, ldb = d.ldb, opA = d.opA, opB = d.opB;
+  v4 acc00 = {0, 0, 0, 0}, acc01 = {0, 0, 0, 0}, acc10 = {0, 0, 0, 0}, acc11 = {0, 0, 0, 0};
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int li = lane & 15, lk = lane >> 4;
+  for (int kb = kb0; kb < kend; kb += BK) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      int i, kk;
+      if (opA == 0) { i = tid & 63; kk = (tid >> 6) + 4 * q; }
+      else { kk = tid & 15; i = (tid >> 4) + 16 * q; }
+      const int gi = m0 + i, gk = kb + kk;
+      T v = 0;
+      if (gi < m && gk < kend)
+        v = opA == 0 ? A[gi + (size_t)gk * lda] : A[gk + (size_t)gi * lda];
+      As[kk][i] = v;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      int j, kk;
+      if (opB == 0) { kk = tid & 15; j = (tid >> 4) + 16 * q; }
+      else { j = tid & 63; kk = (tid >> 6) + 4 * q; }
+      const int gj = n0 + j, gk = kb + kk;
+      T v = 0;
+      if (gj < n && gk < kend)
+        v = opB == 0 ? B[gk + (size_t)gj * ldb] : B[gj + (size_t)gk * ldb];
+      Bs[kk][j] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < BK / 4; ++ks) {
+      const int kq = ks * 4 + lk;
+      const T a0 = As[kq][wm + li], a1 = As[kq][wm + 16 + li];
+      const T b0 = Bs[kq][wn + li], b1 = Bs[kq][wn + 16 + li];
+      acc00 = Mfma<T>::run(a0, b0, acc00);
+      acc01 = Mfma<T>::run(a0, b1, acc01);
+      acc10 = Mfma<T>::run(a1, b0, acc10);
+      acc11 = Mfma<T>::run(a1, b1, acc11);
+    }
+    __syncthreads();
+  }
+  const T alpha = (T)d.alpha, beta = (T)d.beta;
+  T* __restrict__ C = d.C;
+  const int ldc = d.ldc;
+  const v4* accs[4] = {&acc00, &acc01, &acc10, &acc11};
+#pragma unroll
+  for (int ab = 0; ab < 4; ++ab) {
+    const int a = ab >> 1, b = ab & 1;
+    const v4 acc = *accs[ab];
+    const int col = n0 + wn + b * 16 + li;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = m0 + wm + a * 16 + Mfma<T>::row(lk, v);
+      if (row < m && col < n && (!(flags & GF_LOWER_C) || row >= col)) {
+        T* c = C + row + (size_t)col * ldc;
+        T val = alpha * acc[v];
+        if (beta != (T)0) val += beta * *c;
+        *c = val;
+      }
+    }
+  }
+}
+
+// One wave: D = A B with A(i,0) = i, B(0,j) = 1 (so D(i,j) = i), and with
+// A(i,0) = 1, B(0,j) = j (so D(i,j) = j); reports where each lane's four
+// accumulator values sit, next to the row map the GEMM epilogue assumes.
+template <typename T>
+__global__ void mfma_probe_kernel(int* rows, int* cols, int* assumed) {
+  typedef typename Mfma<T>::v4 v4;
+  const int l = threadIdx.x, li = l & 15, lk = l >> 4;
+  v4 d1 = {0, 0, 0, 0}, d2 = {0, 0, 0, 0};
+  d1 = Mfma<T>::run(lk == 0 ? (T)li : (T)0, lk == 0 ? (T)1 : (T)0, d1);
+  d2 = Mfma<T>::run(lk == 0 ? (T)1 : (T)0, lk == 0 ? (T)li : (T)0, d2);
+  for (int v = 0; v < 4; ++v) {
+    rows[l * 4 + v] = (int)d1[v];
+    cols[l * 4 + v] = (int)d2[v];
+    assumed[l * 4 + v] = Mfma<T>::row(lk, v);
+  }
+}
+
+// ------------------------------------------------------- small Cholesky ----
+template <typename T, int NMAX>
+__global__ __launch_bounds__(256) void potrf_kernel(const PotrfDesc<T>* __restrict__ descs, int* status) {
+  __shared__ T S[NMAX * NMAX];
+  const PotrfDesc<T> d = descs[blockIdx.x];
+  const int n = d.n, tid = threadIdx.x, nt = blockDim.x;
+  for (int idx = tid; idx < n * n; idx += nt) {
+    const int i = idx % n, j = idx / n;
+    S[idx] = i >= j ? d.A[i + (size_t)j * d.lda] : (T)0;
+  }
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    T djj = S[j + j * n];
+    const bool bad = !(djj > (T)0);
+    if (bad) djj = (T)1;
+    const T ljj = sqrt(djj);
+    __syncthreads();
+    if (tid == 0) {
+      S[j + j * n] = ljj;
+      if (bad) atomicOr(status, 1);
+    }
+    for (int i = j + 1 + tid; i < n; i += nt) S[i + j * n] /= ljj;
+    __syncthreads();
+    const int mm = n - j - 1;
+    for (int idx = tid; idx < mm * mm; idx += nt) {
+      const int ii = idx % mm, kk = idx / mm;
+      if (ii >= kk) S[(j + 1 + ii) + (j + 1 + kk) * n] -= S[(j + 1 + ii) + j * n] * S[(j + 1 + kk) + j * n];
+    }
+    __syncthreads();
+  }
+  for (int idx = tid; idx < n * n; idx += nt) {
+    const int i = idx % n, j = idx / n;
+    if (i >= j) d.A[i + (size_t)j * d.lda] = S[idx];
+  }
+  if (d.Inv) {
+    for (int c = tid; c < n; c += nt) {
+      T* X = d.Inv + (size_t)c * d.ldi;
+      for (int i = 0; i < c; ++i) X[i] = (T)0;
+      X[c] = (T)1 / S[c + c * n];
+      for (int i = c + 1; i < n; ++i) {
+        T s = 0;
+        for (int j = c; j < i; ++j) s += S[i + j * n] * X[j];
+        X[i] = -s / S[i + i * n];
+      }
+    }
+  }
+}
+
+// --------------------------------------------- skeleton, phase 1 (LDS) ----
+template <typename T>
+__global__ __launch_bounds__(1024) void skel_kernel(const SkelDesc<T>* __restrict__ descs, double eps) {
+  extern __shared__ __align__(16) char smem[];
+  __shared__ double redd[16];
+  __shared__ int redi[16];
+  const SkelDesc<T> d = descs[blockIdx.x];
+  const int nI = d.nI, nJ = d.nJ, tid = threadIdx.x, nt = blockDim.x;
+  const int kmax = min(nI, nJ);
+  T* Bh = reinterpret_cast<T*>(smem);
+  int* pa = reinterpret_cast<int*>(Bh + (size_t)nI * nJ);
+  int* pb = pa + kmax;
+  char* lr = reinterpret_cast<char*>(pb + kmax);
+  char* lc = lr + nI;
+  const int tot = nI * nJ;
+  for (int idx = tid; idx < tot; idx += nt) {
+    const int a = idx % nI, b = idx / nI;
+    Bh[idx] = d.F[d.I[a] + (size_t)d.J[b] * d.ld];
+  }
+  for (int a = tid; a < nI; a += nt) lr[a] = 1;
+  for (int b = tid; b < nJ; b += nt) lc[b] = 1;
+  __syncthreads();
+  const T stop_rel = (T)fmax(eps, (double)noise_rel<T>());
+  T u11 = 0;
+  int r = 0;
+  for (int s = 0; s < kmax; ++s) {
+    double mx = 0.0;
+    for (int idx = tid; idx < tot; idx += nt) {
+      const int a = idx % nI, b = idx / nI;
+      if (lr[a] && lc[b]) mx = fmax(mx, (double)fabs(Bh[idx]));
+    }
+    const double mxall = block_max(mx, redd);
+    if (!(mxall > 0.0)) break;
+    const T thr = (T)(1.0 - kTieRel) * (T)mxall;
+    int best = INT_MAX;
+    for (int idx = tid; idx < tot; idx += nt) {
+      const int a = idx % nI, b = idx / nI;
+      if (lr[a] && lc[b] && fabs(Bh[idx]) >= thr) { best = idx; break; }
+    }
+    const int pidx = block_min(best, redi);
+    const int as = pidx % nI, bs = pidx / nI;
+    const T piv = Bh[pidx];
+    if (s == 0) u11 = fabs(piv);
+    if (fabs(piv) < stop_rel * u11) break;
+    __syncthreads();
+    if (tid == 0) {
+      pa[s] = as; pb[s] = bs;
+      d.piv_r[s] = d.I[as];
+      d.piv_c[s] = d.J[bs];
+    }
+    for (int a = tid; a < nI; a += nt)
+      if (lr[a] && a != as) Bh[a + bs * nI] /= piv;
+    __syncthreads();
+    for (int idx = tid; idx < tot; idx += nt) {
+      const int a = idx % nI, b = idx / nI;
+      if (lr[a] && lc[b] && a != as && b != bs) Bh[idx] -= Bh[a + bs * nI] * Bh[as + b * nI];
+    }
+    __syncthreads();
+    if (tid == 0) { lr[as] = 0; lc[bs] = 0; }
+    __syncthreads();
+    r = s + 1;
+  }
+  __syncthreads();
+  if (tid == 0) { *d.rank = r; *d.u11 = (double)u11; }
+  for (int idx = tid; idx < r * r; idx += nt) {
+    const int s = idx % r, t = idx / r;
+    d.M[s + (size_t)t * d.ldm] = Bh[pa[s] + pb[t] * nI];
+  }
+}
+
+// ------------------------------------- skeleton factors C~ and R~^T -------
+template <typename T>
+__global__ __launch_bounds__(256) void skelfac_kernel(const SkelFacDesc<T>* __restrict__ descs, int ndesc) {
+  extern __shared__ __align__(16) char smem[];
+  T* Ms = reinterpret_cast<T*>(smem);
+  int lo = 0, hi = ndesc - 1;
+  while (lo < hi) { int mid = (lo + hi + 1) >> 1; if (descs[mid].wg0 <= (int)blockIdx.x) lo = mid; else hi = mid - 1; }
+  const SkelFacDesc<T> d = descs[lo];
+  const int r = *d.rank;
+  for (int idx = threadIdx.x; idx < r * r; idx += blockDim.x)
+    Ms[idx] = d.M[(idx % r) + (size_t)(idx / r) * d.ldm];
+  __syncthreads();
+  const int local = (int)blockIdx.x - d.wg0;
+  if (local < d.wgU) {
+    const int i = local * blockDim.x + threadIdx.x;
+    if (i >= d.nr) return;
+    const T* Frow = d.F + d.r0 + i;
+    T* U = d.U + i;
+    for (int s = 0; s < r; ++s) {       // x U_r = B(i, J_r)
+      T x = Frow[(size_t)d.piv_c[s] * d.ld];
+      for (int t = 0; t < s; ++t) x -= U[(size_t)t * d.ldu] * Ms[t + s * r];
+      U[(size_t)s * d.ldu] = x / Ms[s + s * r];
+    }
+  } else {
+    const int a = (local - d.wgU) * blockDim.x + threadIdx.x;
+    if (a >= d.nc) return;
+    const T* Fcol = d.F + (size_t)(d.c0 + a) * d.ld;
+    T* V = d.V + a;
+    for (int s = 0; s < r; ++s) {       // L_r y = B(I_r, a), unit diagonal
+      T y = Fcol[d.piv_r[s]];
+      for (int t = 0; t < s; ++t) y -= Ms[s + t * r] * V[(size_t)t * d.ldv];
+      V[(size_t)s * d.ldv] = y;
+    }
+  }
+}
+
+// -------------------------------- skeleton, phase 2 (full block residual) --
+template <typename T>
+__global__ __launch_bounds__(1024) void phase2_kernel(const Phase2Desc<T>* __restrict__ descs, double eps,
+                                                      int* status) {
+  extern __shared__ __align__(16) char smem[];
+  __shared__ double redd[16];
+  __shared__ int redi[16];
+  const Phase2Desc<T> d = descs[blockIdx.x];
+  const int nr = d.nr, nc = d.nc, tid = threadIdx.x, nt = blockDim.x;
+  char* lr = smem;
+  char* lc = smem + nr;
+  const int r1 = *d.rank1;
+  double u11 = *d.u11;
+  for (int a = tid; a < nr; a += nt) lr[a] = 1;
+  for (int b = tid; b < nc; b += nt) lc[b] = 1;
+  __syncthreads();
+  for (int s = tid; s < r1; s += nt) { lr[d.piv_r[s] - d.r0] = 0; lc[d.piv_c[s] - d.c0] = 0; }
+  __syncthreads();
+  T* E = d.F + d.r0 + (size_t)d.c0 * d.ld;
+  const int ld = d.ld;
+  const int tot = nr * nc;
+  const double stop_rel = fmax(eps, (double)noise_rel<T>());
+  int r = r1;
+  for (;;) {
+    double mx = 0.0;
+    for (int idx = tid; idx < tot; idx += nt) {
+      const int a = idx % nr, b = idx / nr;
+      if (lr[a] && lc[b]) mx = fmax(mx, (double)fabs(E[a + (size_t)b * ld]));
+    }
+    const double mxall = block_max(mx, redd);
+    if (!(mxall > 0.0)) break;
+    const T thr = (T)(1.0 - kTieRel) * (T)mxall;
+    int best = INT_MAX;
+    for (int idx = tid; idx < tot; idx += nt) {
+      const int a = idx % nr, b = idx / nr;
+      if (lr[a] && lc[b] && fabs(E[a + (size_t)b * ld]) >= thr) { best = idx; break; }
+    }
+    const int pidx = block_min(best, redi);
+    const int as = pidx % nr, bs = pidx / nr;
+    const T piv = E[as + (size_t)bs * ld];
+    if (u11 == 0.0) u11 = fabs((double)piv);
+    if (fabs((double)piv) < stop_rel * u11) break;
+    if (r >= d.cap) {
+      if (tid == 0) atomicOr(status, 2);
+      break;
+    }
+    T* Uc = d.U + (size_t)r * d.ldu;
+    T* Vc = d.V + (size_t)r * d.ldv;
+    for (int a = tid; a < nr; a += nt) Uc[a] = E[a + (size_t)bs * ld];
+    for (int b = tid; b < nc; b += nt) Vc[b] = E[as + (size_t)b * ld] / piv;
+    __syncthreads();
+    for (int idx = tid; idx < tot; idx += nt) {
+      const int a = idx % nr, b = idx / nr;
+      E[a + (size_t)b * ld] -= Uc[a] * Vc[b];
+    }
+    __syncthreads();
+    if (tid == 0) { lr[as] = 0; lc[bs] = 0; }
+    ++r;
+    __syncthreads();
+  }
+  if (tid == 0) *d.rank = r;
+}
+
+// ----------------------------------------------------------- extend-add ----
+template <typename T>
+__global__ __launch_bounds__(256) void extadd_kernel(const ExtAddDesc<T>* __restrict__ descs, int ndesc) {
+  const int di = find_desc(descs, ndesc, (int)blockIdx.x);
+  const ExtAddDesc<T>& d = descs[di];
+  const int lt = (int)blockIdx.x - d.tile0;
+  const int tr = lt % d.tiles_r, tc = lt / d.tiles_r;
+  if (tc > tr) return;
+  const int nfc = d.nfc;
+  for (int e = threadIdx.x; e < kTile * kTile; e += blockDim.x) {
+    const int a = tr * kTile + (e & 63), b = tc * kTile + (e >> 6);
+    if (a < nfc && b < nfc && a >= b) {
+      const T v = d.child[(d.npc + a) + (size_t)(d.npc + b) * d.ldc];
+      d.parent[d.relmap[a] + (size_t)d.relmap[b] * d.ldp] += v;
+    }
+  }
+}
+
+// ----------------------------------------------------------------- copy ----
+template <typename S, typename D>
+__global__ __launch_bounds__(256) void copy_kernel(const CopyDesc<S, D>* __restrict__ descs, int ndesc) {
+  const int di = find_desc(descs, ndesc, (int)blockIdx.x);
+  const CopyDesc<S, D>& d = descs[di];
+  const int lt = (int)blockIdx.x - d.tile0;
+  const int tr = lt % d.tiles_r, tc = lt / d.tiles_r;
+  for (int e = threadIdx.x; e < kTile * kTile; e += blockDim.x) {
+    const int i = tr * kTile + (e & 63), j = tc * kTile + (e >> 6);
+    if (i < d.rows && j < d.cols) {
+      D v = (D)(d.alpha * (double)d.src[i + (size_t)j * d.lds]);
+      D* o = d.dst + i + (size_t)j * d.ldd;
+      if (d.accumulate) v += *o;
+      *o = v;
+    }
+  }
+}
+
+// ------------------------------------------------- SMW capacitance -------
+template <typename T>
+__global__ __launch_bounds__(256) void cap_kernel(const CapDesc<T>* __restrict__ descs) {
+  const CapDesc<T> d = descs[blockIdx.x];
+  const int r = d.r, n = 2 * r;
+  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+    const int i = idx % n, j = idx / n;
+    double v;
+    if (i < r && j < r) v = (double)d.P[i + (size_t)(d.c + j) * d.ldp];
+    else if (i >= r && j >= r) v = (double)d.P[i + (size_t)(d.c + j - r) * d.ldp];
+    else v = (i < r) ? (i == j - r ? 1.0 : 0.0) : (i - r == j ? 1.0 : 0.0);
+    d.K[i + (size_t)j * n] = v;                         // left half of [K | I]
+    d.K[i + (size_t)(j + n) * n] = (i == j) ? 1.0 : 0.0; // right half
+  }
+  for (int idx = threadIdx.x; idx < n * d.c; idx += blockDim.x) {
+    const int i = idx % n, j = idx / n;
+    d.Pa[i + (size_t)j * n] = (double)d.P[i + (size_t)j * d.ldp];
+  }
+}
+
+__global__ __launch_bounds__(1024) void gj_kernel(const InvDesc* __restrict__ descs, int* status) {
+  __shared__ double f[1024];
+  __shared__ double redd[16];
+  __shared__ int redi[16];
+  const InvDesc d = descs[blockIdx.x];
+  const int n = d.n, tid = threadIdx.x, nt = blockDim.x;
+  double* A = d.A;
+  for (int j = 0; j < n; ++j) {
+    double mx = 0.0;
+    for (int i = j + tid; i < n; i += nt) mx = fmax(mx, fabs(A[i + (size_t)j * n]));
+    const double mxall = block_max(mx, redd);
+    int best = INT_MAX;
+    for (int i = j + tid; i < n; i += nt)
+      if (fabs(A[i + (size_t)j * n]) == mxall) { best = i; break; }
+    int p = block_min(best, redi);
+    if (!(mxall > 0.0)) {
+      if (tid == 0) atomicOr(status, 4);
+      p = j;
+    }
+    if (p != j)
+      for (int c = tid; c < 2 * n; c += nt) {
+        const double t = A[j + (size_t)c * n];
+        A[j + (size_t)c * n] = A[p + (size_t)c * n];
+        A[p + (size_t)c * n] = t;
+      }
+    __syncthreads();
+    double pv = A[j + (size_t)j * n];
+    if (!(fabs(pv) > 0.0)) pv = 1.0;
+    const double inv = 1.0 / pv;
+    __syncthreads();
+    for (int c = tid; c < 2 * n; c += nt) A[j + (size_t)c * n] *= inv;
+    __syncthreads();
+    for (int i = tid; i < n; i += nt) f[i] = (i == j) ? 0.0 : A[i + (size_t)j * n];
+    __syncthreads();
+    for (int idx = tid; idx < n * 2 * n; idx += nt) {
+      const int i = idx % n, c = idx / n;
+      if (i != j) A[i + (size_t)c * n] -= f[i] * A[j + (size_t)c * n];
+    }
+    __syncthreads();
+  }
+}
+
+// --------------------------------------------------------- misc vectors ----
+template <typename T>
+__global__ void fill_kernel(T* p, int64_t n, T v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+template <typename T>
+__global__ void assemble_kernel(T* base, const int64_t* __restrict__ dest, const int* __restrict__ src,
+                                const double* __restrict__ vals, int64_t cnt) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x)
+    base[dest[i]] = (T)vals[src[i]];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void vec_asm_kernel(const VecAsmDesc<T>* __restrict__ descs, int nrhs) {
+  const VecAsmDesc<T> d = descs[blockIdx.x];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int k = 0; k < nrhs; ++k) {
+    T* t = d.t + (size_t)k * d.ldt;
+    const T* x = d.xs + (size_t)k * d.ldx;
+    for (int i = tid; i < d.nhat; i += nt) t[i] = i < d.npiv ? x[i] : (T)0;
+  }
+  __syncthreads();
+  for (int c = 0; c < d.nchild; ++c) {   // children in order: no two threads touch one entry
+    for (int k = 0; k < nrhs; ++k) {
+      T* t = d.t + (size_t)k * d.ldt;
+      const T* ct = d.ct[c] + d.cnp[c] + (size_t)k * d.cld[c];
+      for (int a = tid; a < d.cnf[c]; a += nt) t[d.crel[c][a]] += ct[a];
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void vec_gather_kernel(const VecGatherDesc<T>* __restrict__ descs, const T* xn,
+                                                         int N, int nrhs) {
+  const VecGatherDesc<T> d = descs[blockIdx.x];
+  for (int idx = threadIdx.x; idx < d.nf * nrhs; idx += blockDim.x) {
+    const int a = idx % d.nf, k = idx / d.nf;
+    d.t[a + (size_t)k * d.ldt] = xn[d.upd[a] + (size_t)k * N];
+  }
+}
+
+template <typename T>
+__global__ void perm_in_kernel(const double* r, T* xn, const int* perm, int N, int nrhs) {
+  const int64_t tot = (int64_t)N * nrhs;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < tot; idx += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(idx % N);
+    const int64_t k = idx / N;
+    xn[idx] = (T)r[perm[i] + k * N];
+  }
+}
+
+template <typename T>
+__global__ void perm_out_kernel(const T* xn, double* z, const int* iperm, int N, int nrhs) {
+  const int64_t tot = (int64_t)N * nrhs;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < tot; idx += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(idx % N);
+    const int64_t k = idx / N;
+    z[idx] = (double)xn[iperm[i] + k * N];
+  }
+}
+
+// ------------------------------------------------------- Krylov / SpMV ----
+__global__ void spmv_kernel(const int* __restrict__ rowptr, const int* __restrict__ colind,
+                            const double* __restrict__ vals, const double* __restrict__ x, double* y, int n,
+                            double alpha, double beta) {
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = blockIdx.y;
+  if (row >= n) return;
+  const double* xk = x + (size_t)k * n;
+  double s = 0.0;
+  for (int j = rowptr[row]; j < rowptr[row + 1]; ++j) s += vals[j] * xk[colind[j]];
+  double* yo = y + (size_t)k * n + row;
+  *yo = beta == 0.0 ? alpha * s : alpha * s + beta * *yo;
+}
+
+constexpr int kMdotMax = 64;
+// partial[(chunk * nrhs + k) * nv + i] = sum over the chunk of X_i(:,k) .* w(:,k)
+__global__ __launch_bounds__(256) void mdot_partial_kernel(const double* X, int64_t xstride, int nv, const double* w,
+                                                           int n, int nrhs, double* partial) {
+  __shared__ double red[16];
+  const int chunk = blockIdx.x, k = blockIdx.y;
+  const int per = (n + gridDim.x - 1) / gridDim.x;
+  const int lo = chunk * per, hi = min(n, lo + per);
+  double acc[kMdotMax];
+  for (int i = 0; i < nv; ++i) acc[i] = 0.0;
+  const double* wk = w + (size_t)k * n;
+  for (int row = lo + threadIdx.x; row < hi; row += blockDim.x) {
+    const double wv = wk[row];
+    for (int i = 0; i < nv; ++i) acc[i] += X[i * xstride + (size_t)k * n + row] * wv;
+  }
+  for (int i = 0; i < nv; ++i) {
+    const double s = block_sum(acc[i], red);
+    if (threadIdx.x == 0) partial[((size_t)chunk * nrhs + k) * nv + i] = s;
+  }
+}
+
+__global__ void mdot_reduce_kernel(const double* partial, int nchunk, int nv, int nrhs, double* out, int accumulate) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;   // idx = i * nrhs + k
+  if (idx >= nv * nrhs) return;
+  const int i = idx / nrhs, k = idx % nrhs;
+  double s = 0.0;
+  for (int c = 0; c < nchunk; ++c) s += partial[((size_t)c * nrhs + k) * nv + i];
+  out[idx] = accumulate ? out[idx] + s : s;
+}
+
+__global__ void maxpy_kernel(const double* X, int64_t xstride, int nv, const double* coef, double* w, int n, int nrhs,
+                             double sign) {
+  const int64_t tot = (int64_t)n * nrhs;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < tot; idx += (int64_t)gridDim.x * blockDim.x) {
+    const int k = (int)(idx / n);
+    double s = 0.0;
+    for (int i = 0; i < nv; ++i) s += coef[i * nrhs + k] * X[i * xstride + idx];
+    w[idx] += sign * s;
+  }
+}
+
+__global__ void scale_cols_kernel(const double* w, double* v, const double* nrm2, int n, int nrhs) {
+  const int64_t tot = (int64_t)n * nrhs;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < tot; idx += (int64_t)gridDim.x * blockDim.x) {
+    const int k = (int)(idx / n);
+    const double nn = sqrt(nrm2[k]);
+    v[idx] = nn > 0.0 ? w[idx] / nn : 0.0;
+  }
+}
+
+__global__ void xupdate_kernel(const double* Z, int64_t zstride, int nv, const double* y, double* x, int n, int nrhs) {
+  const int64_t tot = (int64_t)n * nrhs;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < tot; idx += (int64_t)gridDim.x * blockDim.x) {
+    const int k = (int)(idx / n);
+    double s = 0.0;
+    for (int i = 0; i < nv; ++i) s += y[i * nrhs + k] * Z[i * zstride + idx];
+    x[idx] += s;
+  }
+}
+
+__global__ void axpby_kernel(const double* a, const double* b, double* c, double alpha, double beta, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    c[i] = alpha * a[i] + beta * b[i];
+}
+
+inline int grid_for(int64_t n, int block = 256, int cap = 8192) {
+  int64_t g = (n + block - 1) / block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ launchers ----
+template <typename T>
+void launch_gemm(const GemmDesc<T>* d, int ndesc, int tiles, hipStream_t st) {
+  if (ndesc <= 0 || tiles <= 0) return;
+  hipLaunchKernelGGL(gemm_kernel<T>, dim3(tiles), dim3(256), 0, st, d, ndesc);
+}
+template <typename T>
+void launch_mfma_probe(int* rows, int* cols, int* assumed, hipStream_t st) {
+  hipLaunchKernelGGL(mfma_probe_kernel<T>, dim3(1), dim3(64), 0, st, rows, cols, assumed);
+}
+template void launch_mfma_probe<float>(int*, int*, int*, hipStream_t);
+template void launch_mfma_probe<double>(int*, int*, int*, hipStream_t);
+template <typename T>
+void launch_potrf(const PotrfDesc<T>* d, int ndesc, int nmax, int* status, hipStream_t st) {
+  if (ndesc <= 0) return;
+  if (nmax <= 64) hipLaunchKernelGGL((potrf_kernel<T, 64>), dim3(ndesc), dim3(256), 0, st, d, status);
+  else hipLaunchKernelGGL((potrf_kernel<T, 128>), dim3(ndesc), dim3(256), 0, st, d, status);
+}
+template <typename T>
+void launch_skel(const SkelDesc<T>* d, int ndesc, size_t lds, double eps, hipStream_t st) {
+  if (ndesc <= 0) return;
+  hipLaunchKernelGGL(skel_kernel<T>, dim3(ndesc), dim3(1024), lds, st, d, eps);
+}
+template <typename T>
+void launch_skelfac(const SkelFacDesc<T>* d, int ndesc, int wgs, int rmax, hipStream_t st) {
+  if (ndesc <= 0 || wgs <= 0) return;
+  hipLaunchKernelGGL(skelfac_kernel<T>, dim3(wgs), dim3(256), (size_t)rmax * rmax * sizeof(T), st, d, ndesc);
+}
+template <typename T>
+void launch_phase2(const Phase2Desc<T>* d, int ndesc, int maxrc, double eps, int* status, hipStream_t st) {
+  if (ndesc <= 0) return;
+  hipLaunchKernelGGL(phase2_kernel<T>, dim3(ndesc), dim3(1024), (size_t)maxrc, st, d, eps, status);
+}
+template <typename T>
+void launch_extadd(const ExtAddDesc<T>* d, int ndesc, int tiles, hipStream_t st) {
+  if (ndesc <= 0 || tiles <= 0) return;
+  hipLaunchKernelGGL(extadd_kernel<T>, dim3(tiles), dim3(256), 0, st, d, ndesc);
+}
+template <typename S, typename D>
+void launch_copy(const CopyDesc<S, D>* d, int ndesc, int tiles, hipStream_t st) {
+  if (ndesc <= 0 || tiles <= 0) return;
+  hipLaunchKernelGGL((copy_kernel<S, D>), dim3(tiles), dim3(256), 0, st, d, ndesc);
+}
+template <typename T>
+void launch_cap(const CapDesc<T>* d, int ndesc, hipStream_t st) {
+  if (ndesc <= 0) return;
+  hipLaunchKernelGGL(cap_kernel<T>, dim3(ndesc), dim3(256), 0, st, d);
+}
+void launch_gj_inverse(const InvDesc* d, int ndesc, int* status, hipStream_t st) {
+  if (ndesc <= 0) return;
+  hipLaunchKernelGGL(gj_kernel, dim3(ndesc), dim3(1024), 0, st, d, status);
+}
+template <typename T>
+void launch_fill(T* p, int64_t n, T v, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(fill_kernel<T>, dim3(grid_for(n)), dim3(256), 0, st, p, n, v);
+}
+template <typename T>
+void launch_assemble(T* base, const int64_t* dest, const int* src, const double* vals, int64_t cnt, hipStream_t st) {
+  if (cnt <= 0) return;
+  hipLaunchKernelGGL(assemble_kernel<T>, dim3(grid_for(cnt)), dim3(256), 0, st, base, dest, src, vals, cnt);
+}
+template <typename T>
+void launch_vec_asm(const VecAsmDesc<T>* d, int ndesc, int nrhs, hipStream_t st) {
+  if (ndesc <= 0) return;
+  hipLaunchKernelGGL(vec_asm_kernel<T>, dim3(ndesc), dim3(256), 0, st, d, nrhs);
+}
+template <typename T>
+void launch_vec_gather(const VecGatherDesc<T>* d, int ndesc, const T* xn, int N, int nrhs, hipStream_t st) {
+  if (ndesc <= 0) return;
+  hipLaunchKernelGGL(vec_gather_kernel<T>, dim3(ndesc), dim3(256), 0, st, d, xn, N, nrhs);
+}
+template <typename T>
+void launch_perm_in(const double* r, T* xn, const int* perm, int N, int nrhs, hipStream_t st) {
+  hipLaunchKernelGGL(perm_in_kernel<T>, dim3(grid_for((int64_t)N * nrhs)), dim3(256), 0, st, r, xn, perm, N, nrhs);
+}
+template <typename T>
+void launch_perm_out(const T* xn, double* z, const int* iperm, int N, int nrhs, hipStream_t st) {
+  hipLaunchKernelGGL(perm_out_kernel<T>, dim3(grid_for((int64_t)N * nrhs)), dim3(256), 0, st, xn, z, iperm, N, nrhs);
+}
+
+void launch_spmv(const int* rowptr, const int* colind, const double* vals, const double* x, double* y, int n,
+                 int nrhs, double alpha, double beta, hipStream_t st) {
+  hipLaunchKernelGGL(spmv_kernel, dim3((n + 255) / 256, nrhs), dim3(256), 0, st, rowptr, colind, vals, x, y, n,
+                     alpha, beta);
+}
+void launch_mdot(const double* X, int64_t xstride, int nv, const double* w, int n, int nrhs, double* partial,
+                 double* out, int accumulate, hipStream_t st) {
+  const int nchunk = 64;
+  hipLaunchKernelGGL(mdot_partial_kernel, dim3(nchunk, nrhs), dim3(256), 0, st, X, xstride, nv, w, n, nrhs, partial);
+  hipLaunchKernelGGL(mdot_reduce_kernel, dim3((nv * nrhs + 255) / 256), dim3(256), 0, st, partial, nchunk, nv, nrhs,
+                     out, accumulate);
+}
+void launch_maxpy(const double* X, int64_t xstride, int nv, const double* coef, double* w, int n, int nrhs,
+                  double sign, hipStream_t st) {
+  hipLaunchKernelGGL(maxpy_kernel, dim3(grid_for((int64_t)n * nrhs)), dim3(256), 0, st, X, xstride, nv, coef, w, n,
+                     nrhs, sign);
+}
+void launch_scale_cols(const double* w, double* v, const double* norms, int n, int nrhs, hipStream_t st) {
+  hipLaunchKernelGGL(scale_cols_kernel, dim3(grid_for((int64_t)n * nrhs)), dim3(256), 0, st, w, v, norms, n, nrhs);
+}
+void launch_xupdate(const double* Z, int64_t zstride, int nv, const double* y, double* x, int n, int nrhs,
+                    hipStream_t st) {
+  hipLaunchKernelGGL(xupdate_kernel, dim3(grid_for((int64_t)n * nrhs)), dim3(256), 0, st, Z, zstride, nv, y, x, n,
+                     nrhs);
+}
+void launch_axpby(const double* a, const double* b, double* c, double alpha, double beta, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(axpby_kernel, dim3(grid_for(n)), dim3(256), 0, st, a, b, c, alpha, beta, n);
+}
+
+#define MFH_INST(T)                                                                              \
+  template void launch_gemm<T>(const GemmDesc<T>*, int, int, hipStream_t);                       \
+  template void launch_potrf<T>(const PotrfDesc<T>*, int, int, int*, hipStream_t);               \
+  template void launch_skel<T>(const SkelDesc<T>*, int, size_t, double, hipStream_t);            \
+  template void launch_skelfac<T>(const SkelFacDesc<T>*, int, int, int, hipStream_t);            \
+  template void launch_phase2<T>(const Phase2Desc<T>*, int, int, double, int*, hipStream_t);     \
+  template void launch_extadd<T>(const ExtAddDesc<T>*, int, int, hipStream_t);                   \
+  template void launch_cap<T>(const CapDesc<T>*, int, hipStream_t);                              \
+  template void launch_fill<T>(T*, int64_t, T, hipStream_t);                                     \
+  template void launch_assemble<T>(T*, const int64_t*, const int*, const double*, int64_t,       \
+                                   hipStream_t);                                                 \
+  template void launch_vec_asm<T>(const VecAsmDesc<T>*, int, int, hipStream_t);                  \
+  template void launch_vec_gather<T>(const VecGatherDesc<T>*, int, const T*, int, int,           \
+                                     hipStream_t);                                               \
+  template void launch_perm_in<T>(const double*, T*, const int*, int, int, hipStream_t);         \
+  template void launch_perm_out<T>(const T*, double*, const int*, int, int, hipStream_t);
+
+MFH_INST(float)
+MFH_INST(double)
+template void launch_copy<float, float>(const CopyDesc<float, float>*, int, int, hipStream_t);
+template void launch_copy<double, double>(const CopyDesc<double, double>*, int, int, hipStream_t);
+template void launch_copy<float, double>(const CopyDesc<float, double>*, int, int, hipStream_t);
+template void launch_copy<double, float>(const CopyDesc<double, float>*, int, int, hipStream_t);
+template void launch_fill<int>(int*, int64_t, int, hipStream_t);
+
+}  // namespace mfh

@@ -1,0 +1,86 @@
+// Numeric factor, preconditioner apply and GMRES driver (host side).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/mfh.h"
+#include "kernels.h"
+#include "symbolic.h"
+
+namespace mfh {
+
+struct Err {
+  mf_status code;
+  std::string msg;
+};
+
+// Device memory accounting shared by all allocations of one factor.
+struct MemStats {
+  int64_t current = 0, peak = 0;
+  void add(int64_t b) { current += b; if (current > peak) peak = current; }
+  void sub(int64_t b) { current -= b; }
+};
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  MemStats* ms = nullptr;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release();
+  void alloc(size_t b, MemStats* m);        // throws Err on failure
+  void ensure(size_t b, MemStats* m, hipStream_t st);   // grows (synchronising) when needed
+  template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+// Bump allocator over device chunks for the persistent factor arrays.
+struct Arena {
+  std::vector<std::unique_ptr<DevBuf>> chunks;
+  size_t off = 0;
+  int64_t used = 0;
+  MemStats* ms = nullptr;
+  void* alloc(size_t bytes);
+  template <typename T> T* alloc_n(int64_t n) { return static_cast<T*>(alloc((size_t)std::max<int64_t>(n, 1) * sizeof(T))); }
+};
+
+// Host blob of descriptor arrays uploaded in one copy.
+struct Blob {
+  std::vector<char> h;
+  template <typename D>
+  size_t add(const std::vector<D>& v) {
+    size_t o = (h.size() + 255) & ~size_t(255);
+    h.resize(o + v.size() * sizeof(D));
+    if (!v.empty()) memcpy(h.data() + o, v.data(), v.size() * sizeof(D));
+    return o;
+  }
+};
+
+class NumericBase {
+ public:
+  virtual ~NumericBase() = default;
+  virtual void apply(int nrhs, const double* r, double* z, hipStream_t st) = 0;
+  void spmv(int nrhs, const double* x, double* y, double alpha, double beta, hipStream_t st);
+  void gmres(int nrhs, const double* b, double* x, double tol, const mf_gmres_opts& o, mf_gmres_info* info,
+             mf_status* st_out);
+  mf_factor_info info{};
+  std::vector<int> ranks;        // per global block, -1 for dense fronts
+  const Symbolic* sym = nullptr;
+  mf_opts opts{};
+  MemStats ms;
+  int device = 0;
+  // device copy of A (original order) and permutations
+  DevBuf d_rowptr, d_colind, d_vals, d_perm, d_iperm, d_status;
+  // GMRES workspace
+  DevBuf g_V, g_Z, g_w, g_r, g_small, g_partial;
+};
+
+std::unique_ptr<NumericBase> make_numeric(const Symbolic& s, const double* vals, const mf_opts& o);
+
+}  // namespace mfh

@@ -1,0 +1,1239 @@
+// Numeric multifrontal factorisation (dense fronts, Sec. 4.1, and
+// HODLR-compressed fronts, Sec. 4.2), the preconditioner apply (Sec. 4.1.2,
+// Sec. 4.2.2) and the GMRES driver (Sec. 3).
+//
+// Data flow per elimination-tree level (fronts grouped by height, so every
+// child is finished before its parent):
+//   1. zero the level's front buffers (dense n_hat x n_hat staging in HBM),
+//   2. scatter A's lower entries into them (F_bar_p, Eq. fbar),
+//   3. extend-add the children's update matrices (two launches: first and
+//      second children, so no two workgroups add into one entry),
+//   4. dense fronts: blocked right-looking partial Cholesky (64-wide
+//      panels: LDS Cholesky of the diagonal block, MFMA panel and trailing
+//      updates), the explicit inverse of L_pp by recursive doubling; the
+//      trailing block left in place is U_p (Eq. update),
+//   5. HODLR fronts: skeleton compression of every off-diagonal block
+//      (phase 1 in LDS, phase 2 on the full-block residual), one host
+//      synchronisation to read the ranks, then the SMW factorisation of F_pp
+//      by a bottom-up sweep over all HODLR levels, X = F_pp^{-1} V,
+//      S = V^T X and the update U_p = F_ff^HODLR - W S W^T written in place.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "numeric.h"
+
+namespace mfh {
+
+#define HIPCHK(x)                                                                              \
+  do {                                                                                         \
+    hipError_t e_ = (x);                                                                       \
+    if (e_ != hipSuccess) throw Err{MF_EHIP, std::string(#x) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+void DevBuf::release() {
+  if (p) {
+    (void)hipFree(p);
+    if (ms) ms->sub((int64_t)bytes);
+  }
+  p = nullptr;
+  bytes = 0;
+}
+
+void DevBuf::alloc(size_t b, MemStats* m) {
+  release();
+  ms = m;
+  if (b == 0) b = 256;
+  hipError_t e = hipMalloc(&p, b);
+  if (e != hipSuccess) {
+    p = nullptr;
+    (void)hipGetLastError();
+    throw Err{MF_ENOMEM, "hipMalloc of " + std::to_string(b) + " bytes failed"};
+  }
+  bytes = b;
+  if (ms) ms->add((int64_t)b);
+}
+
+void DevBuf::ensure(size_t b, MemStats* m, hipStream_t st) {
+  if (p && b <= bytes) return;
+  if (p) HIPCHK(hipStreamSynchronize(st));
+  alloc(std::max(b, bytes + bytes / 2), m);
+}
+
+void* Arena::alloc(size_t bytes) {
+  bytes = (bytes + 255) & ~size_t(255);
+  if (chunks.empty() || off + bytes > chunks.back()->bytes) {
+    size_t cb = std::max(bytes, (size_t)64 << 20);
+    chunks.push_back(std::make_unique<DevBuf>());
+    chunks.back()->alloc(cb, ms);
+    off = 0;
+  }
+  void* p = static_cast<char*>(chunks.back()->p) + off;
+  off += bytes;
+  used += (int64_t)bytes;
+  return p;
+}
+
+namespace {
+
+inline int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+// Uploads descriptor blobs; device memory and host copies live until the
+// pool is destroyed, so no upload can race with a pending reader.
+struct DescPool {
+  Arena ar;
+  std::vector<std::vector<char>> keep;
+  char* upload(Blob& b, hipStream_t st) {
+    if (b.h.empty()) return nullptr;
+    void* d = ar.alloc(b.h.size());
+    keep.push_back(std::move(b.h));
+    b.h = std::vector<char>();
+    HIPCHK(hipMemcpyAsync(d, keep.back().data(), keep.back().size(), hipMemcpyHostToDevice, st));
+    return static_cast<char*>(d);
+  }
+};
+
+template <typename T>
+GemmDesc<T> gd(const T* A, int lda, int opA, const T* B, int ldb, int opB, T* C, int ldc, int m, int n, int k,
+               double alpha, double beta, int flags = 0, const int* kdev = nullptr) {
+  GemmDesc<T> d{};
+  d.A = A; d.B = B; d.C = C; d.kdev = kdev;
+  d.m = m; d.n = n; d.k = k;
+  d.lda = lda; d.ldb = ldb; d.ldc = ldc;
+  d.opA = opA; d.opB = opB;
+  d.flags = flags;
+  d.alpha = alpha; d.beta = beta;
+  return d;
+}
+
+// assigns tile0/tiles_m; returns total tiles
+template <typename T>
+int finalize_gemm(std::vector<GemmDesc<T>>& v) {
+  int t = 0;
+  std::vector<GemmDesc<T>> out;
+  out.reserve(v.size());
+  for (auto& d : v) {
+    if (d.m <= 0 || d.n <= 0) continue;
+    d.tiles_m = cdiv(d.m, kTile);
+    d.tile0 = t;
+    t += d.tiles_m * cdiv(d.n, kTile);
+    out.push_back(d);
+  }
+  v.swap(out);
+  return t;
+}
+
+template <typename S, typename D>
+CopyDesc<S, D> cd(const S* src, int lds, D* dst, int ldd, int rows, int cols, double alpha = 1.0, int acc = 0) {
+  CopyDesc<S, D> d{};
+  d.src = src; d.dst = dst; d.lds = lds; d.ldd = ldd; d.rows = rows; d.cols = cols;
+  d.alpha = alpha; d.accumulate = acc;
+  return d;
+}
+
+template <typename S, typename D>
+int finalize_copy(std::vector<CopyDesc<S, D>>& v) {
+  int t = 0;
+  std::vector<CopyDesc<S, D>> out;
+  for (auto& d : v) {
+    if (d.rows <= 0 || d.cols <= 0) continue;
+    d.tiles_r = cdiv(d.rows, kTile);
+    d.tile0 = t;
+    t += d.tiles_r * cdiv(d.cols, kTile);
+    out.push_back(d);
+  }
+  v.swap(out);
+  return t;
+}
+
+// a batch of GEMMs / copies recorded for a later upload
+template <typename T>
+struct GemmBatch {
+  std::vector<GemmDesc<T>> v;
+  size_t off = 0;
+  int tiles = 0, n = 0;
+  void stage(Blob& b) { tiles = finalize_gemm(v); n = (int)v.size(); off = b.add(v); }
+  void launch(const char* base, hipStream_t st) const {
+    if (n) launch_gemm<T>(reinterpret_cast<const GemmDesc<T>*>(base + off), n, tiles, st);
+  }
+};
+template <typename S, typename D>
+struct CopyBatch {
+  std::vector<CopyDesc<S, D>> v;
+  size_t off = 0;
+  int tiles = 0, n = 0;
+  void stage(Blob& b) { tiles = finalize_copy(v); n = (int)v.size(); off = b.add(v); }
+  void launch(const char* base, hipStream_t st) const {
+    if (n) launch_copy<S, D>(reinterpret_cast<const CopyDesc<S, D>*>(base + off), n, tiles, st);
+  }
+};
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+constexpr int kNB = 64;          // dense panel width
+constexpr int kLdsMax = 160 * 1024;
+
+}  // namespace
+
+// =========================================================== Numeric<T> ====
+template <typename T>
+class Numeric : public NumericBase {
+ public:
+  Numeric(const Symbolic& s, const double* vals, const mf_opts& o);
+  void apply(int nrhs, const double* r, double* z, hipStream_t st) override;
+
+ private:
+  struct FN {
+    bool dense = true;
+    T* F = nullptr;           // staging buffer (transient)
+    int ld = 0;
+    T* Linv = nullptr;        // dense: npiv x npiv, ld npiv
+    T* Lfp = nullptr;         // dense: nf x npiv, ld nf
+    T* G = nullptr;           // HODLR: npiv x w (Y columns per HODLR level, X in the first r_top)
+    int w = 0, r_top = 0;
+    std::vector<int> col;     // c_l per pp-tree level
+    T* W = nullptr;           // HODLR: nf x r_top
+    std::vector<T*> nodeU, nodeV, nodeK, leafInv;   // per pp-tree node
+    std::vector<int> nodeR;   // rank per pp-tree node (internal)
+  };
+  std::vector<FN> fn;
+  Arena arena;
+  DescPool dp;
+  DevBuf ws, scrA, scrB, d_asm_dest, d_asm_src, d_relmap, d_bdlr;
+  std::vector<int64_t> relmap_off;
+  std::vector<int64_t> asm_lvl_off;
+  std::vector<int> bI, bIptr, bJ, bJptr;
+  int64_t bdlr_J_base = 0;
+  hipStream_t st = nullptr;
+  T* wsT = nullptr;
+
+  void dense_level(const std::vector<int>& D);
+  void hodlr_level(const std::vector<int>& H);
+
+  struct Rec {
+    int kind;                 // 0 gemm T, 1 copy TT, 2 vec_asm, 3 vec_gather
+    size_t off;
+    int n, tiles;
+  };
+  struct Plan {
+    int nrhs = 0;
+    DevBuf work;
+    char* desc = nullptr;
+    DescPool dp;
+    std::vector<Rec> recs;
+    T* xn = nullptr;
+  };
+  std::map<int, std::unique_ptr<Plan>> plans;
+  Plan* get_plan(int nrhs);
+};
+
+template <typename T>
+Numeric<T>::Numeric(const Symbolic& s, const double* vals, const mf_opts& o) {
+  const double t0 = now_s();
+  sym = &s;
+  opts = o;
+  st = static_cast<hipStream_t>(o.stream);
+  arena.ms = &ms;
+  dp.ar.ms = &ms;
+  HIPCHK(hipGetDevice(&device));
+  const int n = s.n;
+  const int nfr = (int)s.fronts.size();
+  const bool hodlr = o.method == MF_METHOD_HODLR;
+
+  d_rowptr.alloc((n + 1) * sizeof(int), &ms);
+  d_colind.alloc(s.nnz * sizeof(int), &ms);
+  d_vals.alloc(s.nnz * sizeof(double), &ms);
+  d_perm.alloc(n * sizeof(int), &ms);
+  d_iperm.alloc(n * sizeof(int), &ms);
+  d_status.alloc(sizeof(int), &ms);
+  HIPCHK(hipMemcpyAsync(d_rowptr.p, s.rowptr.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(d_colind.p, s.colind.data(), s.nnz * sizeof(int), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(d_vals.p, vals, s.nnz * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(d_perm.p, s.perm.data(), n * sizeof(int), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(d_iperm.p, s.iperm.data(), n * sizeof(int), hipMemcpyHostToDevice, st));
+  launch_fill<int>(d_status.as<int>(), 1, 0, st);
+
+  fn.resize(nfr);
+  for (int p = 0; p < nfr; ++p) {
+    const Front& f = s.fronts[p];
+    fn[p].dense = !hodlr || f.n() < o.n_c;
+    fn[p].ld = f.n();
+  }
+
+  // ---- front workspace plan: one region per level, first fit over offsets
+  const int H = (int)s.levels.size();
+  std::vector<int64_t> reg_off(H), reg_elems(H);
+  std::vector<int> reg_end(H);
+  std::vector<int64_t> front_elem_off(nfr);
+  {
+    struct Iv { int64_t off, len; int end; };
+    std::vector<Iv> live;
+    int64_t peak = 0;
+    for (int h = 0; h < H; ++h) {
+      int64_t tot = 0;
+      int end = h;
+      for (int p : s.levels[h]) {
+        front_elem_off[p] = tot;
+        const int64_t nn = s.fronts[p].n();
+        tot += (nn * nn + 63) & ~int64_t(63);
+        int par = s.fronts[p].parent;
+        end = std::max(end, par >= 0 ? s.fronts[par].height : h);
+      }
+      live.erase(std::remove_if(live.begin(), live.end(), [&](const Iv& v) { return v.end < h; }), live.end());
+      std::sort(live.begin(), live.end(), [](const Iv& a, const Iv& b) { return a.off < b.off; });
+      int64_t pos = 0;
+      for (const Iv& v : live) {
+        if (v.off - pos >= tot) break;
+        pos = std::max(pos, v.off + v.len);
+      }
+      reg_off[h] = pos;
+      reg_elems[h] = tot;
+      reg_end[h] = end;
+      live.push_back({pos, tot, end});
+      peak = std::max(peak, pos + tot);
+    }
+    ws.alloc(std::max<int64_t>(peak, 1) * sizeof(T), &ms);
+    info.workspace_bytes = peak * (int64_t)sizeof(T);
+  }
+  wsT = ws.as<T>();
+  for (int h = 0; h < H; ++h)
+    for (int p : s.levels[h]) fn[p].F = wsT + reg_off[h] + front_elem_off[p];
+
+  // ---- assembly map by level, relative maps
+  {
+    std::vector<std::vector<int64_t>> dest(H);
+    std::vector<std::vector<int>> src(H);
+    for (size_t e = 0; e < s.asm_src.size(); ++e) {
+      const int p = s.asm_front[e];
+      const int h = s.fronts[p].height;
+      dest[h].push_back((fn[p].F - wsT) + s.asm_row[e] + (int64_t)s.asm_col[e] * fn[p].ld);
+      src[h].push_back(s.asm_src[e]);
+    }
+    asm_lvl_off.assign(H + 1, 0);
+    std::vector<int64_t> hd;
+    std::vector<int> hs;
+    for (int h = 0; h < H; ++h) {
+      asm_lvl_off[h] = (int64_t)hd.size();
+      hd.insert(hd.end(), dest[h].begin(), dest[h].end());
+      hs.insert(hs.end(), src[h].begin(), src[h].end());
+    }
+    asm_lvl_off[H] = (int64_t)hd.size();
+    d_asm_dest.alloc(hd.size() * sizeof(int64_t), &ms);
+    d_asm_src.alloc(hs.size() * sizeof(int), &ms);
+    HIPCHK(hipMemcpyAsync(d_asm_dest.p, hd.data(), hd.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d_asm_src.p, hs.data(), hs.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));     // host vectors go out of scope
+    std::vector<int> rm;
+    relmap_off.assign(nfr, 0);
+    for (int p = 0; p < nfr; ++p) {
+      relmap_off[p] = (int64_t)rm.size();
+      rm.insert(rm.end(), s.fronts[p].relmap.begin(), s.fronts[p].relmap.end());
+    }
+    d_relmap.alloc(std::max<size_t>(rm.size(), 1) * sizeof(int), &ms);
+    HIPCHK(hipMemcpyAsync(d_relmap.p, rm.data(), rm.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  if (hodlr) {
+    bdlr_sets(s, o.bdlr_depth, o.bdlr_cap, bI, bIptr, bJ, bJptr);
+    std::vector<int> all(bI);
+    bdlr_J_base = (int64_t)all.size();
+    all.insert(all.end(), bJ.begin(), bJ.end());
+    d_bdlr.alloc(std::max<size_t>(all.size(), 1) * sizeof(int), &ms);
+    HIPCHK(hipMemcpyAsync(d_bdlr.p, all.data(), all.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  ranks.assign(s.nblocks, -1);
+
+  // ---- level loop
+  for (int h = 0; h < H; ++h) {
+    const auto& L = s.levels[h];
+    launch_fill<T>(wsT + reg_off[h], reg_elems[h], (T)0, st);
+    launch_assemble<T>(wsT, d_asm_dest.as<int64_t>() + asm_lvl_off[h], d_asm_src.as<int>() + asm_lvl_off[h],
+                       d_vals.as<double>(), asm_lvl_off[h + 1] - asm_lvl_off[h], st);
+    for (int slot = 0; slot < 2; ++slot) {
+      std::vector<ExtAddDesc<T>> ev;
+      int tiles = 0;
+      for (int p : L) {
+        const Front& f = s.fronts[p];
+        if ((int)f.children.size() <= slot) continue;
+        const int c = f.children[slot];
+        const Front& fc = s.fronts[c];
+        if (fc.nf() == 0) continue;
+        ExtAddDesc<T> d{};
+        d.child = fn[c].F; d.parent = fn[p].F; d.relmap = d_relmap.as<int>() + relmap_off[c];
+        d.ldc = fn[c].ld; d.npc = fc.npiv; d.nfc = fc.nf(); d.ldp = fn[p].ld;
+        d.tiles_r = cdiv(fc.nf(), kTile);
+        d.tile0 = tiles;
+        tiles += d.tiles_r * d.tiles_r;
+        ev.push_back(d);
+      }
+      if (!ev.empty()) {
+        Blob b;
+        size_t off = b.add(ev);
+        char* base = dp.upload(b, st);
+        launch_extadd<T>(reinterpret_cast<const ExtAddDesc<T>*>(base + off), (int)ev.size(), tiles, st);
+      }
+    }
+    std::vector<int> D, Hf;
+    for (int p : L) (fn[p].dense ? D : Hf).push_back(p);
+    dense_level(D);
+    hodlr_level(Hf);
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(st));
+  int status = 0;
+  HIPCHK(hipMemcpy(&status, d_status.p, sizeof(int), hipMemcpyDeviceToHost));
+  info.status_bits = status;
+  // release transient storage
+  ws.release();
+  scrA.release();
+  scrB.release();
+  d_asm_dest.release();
+  d_asm_src.release();
+  d_bdlr.release();
+  info.persistent_bytes = arena.used;
+  info.peak_bytes = ms.peak;
+  int dn = 0, hn = 0;
+  for (auto& x : fn) (x.dense ? dn : hn)++;
+  info.dense_fronts = dn;
+  info.hodlr_fronts = hn;
+  int64_t nb = 0, rs = 0;
+  int rmax = 0;
+  for (int r : ranks)
+    if (r >= 0) { nb++; rs += r; rmax = std::max(rmax, r); }
+  info.nblocks = nb;
+  info.rank_sum = rs;
+  info.rank_max = rmax;
+  info.factor_seconds = now_s() - t0;
+  if (status & 1) throw Err{MF_ENOTSPD, "non-positive pivot in a Cholesky factorisation"};
+  if (status & 4) throw Err{MF_ENOTSPD, "singular SMW capacitance matrix"};
+  if (status & 2) throw Err{MF_ECAPACITY, "a block rank exceeded rank_cap"};
+}
+
+// ------------------------------------------------------------ dense fronts
+template <typename T>
+void Numeric<T>::dense_level(const std::vector<int>& D) {
+  if (D.empty()) return;
+  const Symbolic& s = *sym;
+  int64_t linv_tot = 0;
+  int maxnp = 0;
+  for (int p : D) {
+    const Front& f = s.fronts[p];
+    linv_tot += (int64_t)f.npiv * f.npiv;
+    maxnp = std::max(maxnp, f.npiv);
+  }
+  T* linv = arena.alloc_n<T>(linv_tot);
+  launch_fill<T>(linv, linv_tot, (T)0, st);
+  for (int p : D) {
+    const Front& f = s.fronts[p];
+    fn[p].Linv = linv;
+    linv += (int64_t)f.npiv * f.npiv;
+    if (f.nf() > 0) fn[p].Lfp = arena.alloc_n<T>((int64_t)f.nf() * f.npiv);
+  }
+  Blob b;
+  struct Step { size_t po; int pn; GemmBatch<T> panel, syrk; };
+  std::vector<Step> steps;
+  for (int k = 0; k < maxnp; k += kNB) {
+    Step sp;
+    std::vector<PotrfDesc<T>> pv;
+    for (int p : D) {
+      const Front& f = s.fronts[p];
+      if (k >= f.npiv) continue;
+      FN& x = fn[p];
+      const int kb = std::min(kNB, f.npiv - k);
+      const int ld = x.ld, nh = f.n();
+      PotrfDesc<T> pd{};
+      pd.A = x.F + k + (int64_t)k * ld; pd.lda = ld; pd.n = kb;
+      pd.Inv = x.Linv + k + (int64_t)k * f.npiv; pd.ldi = f.npiv;
+      pv.push_back(pd);
+      const int rest = nh - k - kb;
+      if (rest > 0) {
+        T* P = x.F + (k + kb) + (int64_t)k * ld;
+        // P <- P L_kk^{-T}   (in place: a tile owns its rows across all kb columns)
+        sp.panel.v.push_back(gd<T>(P, ld, 0, pd.Inv, f.npiv, 1, P, ld, rest, kb, kb, 1.0, 0.0, GF_B_UPPER));
+        // trailing lower update: T <- T - P P^T
+        sp.syrk.v.push_back(gd<T>(P, ld, 0, P, ld, 1, x.F + (k + kb) + (int64_t)(k + kb) * ld, ld, rest, rest, kb,
+                                  -1.0, 1.0, GF_LOWER_C));
+      }
+    }
+    sp.pn = (int)pv.size();
+    sp.po = b.add(pv);
+    sp.panel.stage(b);
+    sp.syrk.stage(b);
+    steps.push_back(std::move(sp));
+  }
+  // recursive doubling for the off-diagonal blocks of L_pp^{-1}:
+  // [A 0; B C]^{-1} = [A^{-1} 0; -C^{-1} B A^{-1}  C^{-1}]
+  struct Dbl { GemmBatch<T> t1, x; };
+  std::vector<Dbl> dbl;
+  int64_t tmax = 0;
+  for (int sz = kNB; sz < maxnp; sz *= 2) {
+    int64_t need = 0;
+    for (int p : D) {
+      const int np = s.fronts[p].npiv;
+      for (int i0 = 0; i0 + sz < np; i0 += 2 * sz) need += (int64_t)std::min(sz, np - i0 - sz) * sz;
+    }
+    tmax = std::max(tmax, need);
+  }
+  scrB.ensure(std::max<int64_t>(tmax, 1) * sizeof(T), &ms, st);
+  for (int sz = kNB; sz < maxnp; sz *= 2) {
+    Dbl dd;
+    T* tp = scrB.as<T>();
+    for (int p : D) {
+      const Front& f = s.fronts[p];
+      const int np = f.npiv, ld = fn[p].ld;
+      T* Li = fn[p].Linv;
+      for (int i0 = 0; i0 + sz < np; i0 += 2 * sz) {
+        const int cs = std::min(sz, np - i0 - sz);
+        const T* L21 = fn[p].F + (i0 + sz) + (int64_t)i0 * ld;
+        dd.t1.v.push_back(gd<T>(L21, ld, 0, Li + i0 + (int64_t)i0 * np, np, 0, tp, cs, cs, sz, sz, 1.0, 0.0,
+                                GF_B_LOWER));
+        dd.x.v.push_back(gd<T>(Li + (i0 + sz) + (int64_t)(i0 + sz) * np, np, 0, tp, cs, 0,
+                               Li + (i0 + sz) + (int64_t)i0 * np, np, cs, sz, cs, -1.0, 0.0, GF_A_LOWER));
+        tp += (int64_t)cs * sz;
+      }
+    }
+    dd.t1.stage(b);
+    dd.x.stage(b);
+    dbl.push_back(std::move(dd));
+  }
+  CopyBatch<T, T> lfp;
+  for (int p : D) {
+    const Front& f = s.fronts[p];
+    if (f.nf() > 0) lfp.v.push_back(cd<T, T>(fn[p].F + f.npiv, fn[p].ld, fn[p].Lfp, f.nf(), f.nf(), f.npiv));
+  }
+  lfp.stage(b);
+  const char* base = dp.upload(b, st);
+  int* status = d_status.as<int>();
+  for (auto& sp : steps) {
+    launch_potrf<T>(reinterpret_cast<const PotrfDesc<T>*>(base + sp.po), sp.pn, kNB, status, st);
+    sp.panel.launch(base, st);
+    sp.syrk.launch(base, st);
+  }
+  for (auto& dd : dbl) {
+    dd.t1.launch(base, st);
+    dd.x.launch(base, st);
+  }
+  lfp.launch(base, st);
+}
+
+// ------------------------------------------------------------ HODLR fronts
+template <typename T>
+void Numeric<T>::hodlr_level(const std::vector<int>& Hs) {
+  if (Hs.empty()) return;
+  const Symbolic& s = *sym;
+  const double eps = opts.eps;
+  const bool adaptive = opts.adaptive != 0;
+  struct BR {
+    int p, bi, gb, nI, nJ, kcap, capr;
+    int *pr, *pc, *rank1, *rank;
+    double* u11;
+    T *M, *U, *V;
+  };
+  std::vector<BR> br;
+  for (int p : Hs) {
+    const Front& f = s.fronts[p];
+    for (int bi = 0; bi < (int)f.blocks.size(); ++bi) {
+      const Block& B = f.blocks[bi];
+      BR x{};
+      x.p = p; x.bi = bi; x.gb = s.block_base[p] + bi;
+      x.nI = bIptr[x.gb + 1] - bIptr[x.gb];
+      x.nJ = bJptr[x.gb + 1] - bJptr[x.gb];
+      x.kcap = std::min(x.nI, x.nJ);
+      x.capr = std::max(std::min({B.nr, B.nc, opts.rank_cap}), x.kcap);
+      br.push_back(x);
+    }
+  }
+  const int nb = (int)br.size();
+  // ---- phase A scratch
+  auto al = [](size_t v) { return (v + 255) & ~size_t(255); };
+  size_t need = al(nb * sizeof(int)) * 2 + al(nb * sizeof(double));
+  for (auto& x : br) {
+    const Block& B = s.fronts[x.p].blocks[x.bi];
+    need += 2 * al(std::max(x.kcap, 1) * sizeof(int));
+    need += al((size_t)std::max(x.kcap * x.kcap, 1) * sizeof(T));
+    need += al((size_t)B.nr * x.capr * sizeof(T)) + al((size_t)B.nc * x.capr * sizeof(T));
+  }
+  scrA.ensure(need, &ms, st);
+  char* cur = static_cast<char*>(scrA.p);
+  auto take = [&](size_t bytes) { char* r = cur; cur += al(bytes); return r; };
+  int* rank1 = reinterpret_cast<int*>(take(nb * sizeof(int)));
+  int* rankf = reinterpret_cast<int*>(take(nb * sizeof(int)));
+  double* u11 = reinterpret_cast<double*>(take(nb * sizeof(double)));
+  for (int i = 0; i < nb; ++i) {
+    BR& x = br[i];
+    const Block& B = s.fronts[x.p].blocks[x.bi];
+    x.pr = reinterpret_cast<int*>(take(std::max(x.kcap, 1) * sizeof(int)));
+    x.pc = reinterpret_cast<int*>(take(std::max(x.kcap, 1) * sizeof(int)));
+    x.M = reinterpret_cast<T*>(take((size_t)std::max(x.kcap * x.kcap, 1) * sizeof(T)));
+    x.U = reinterpret_cast<T*>(take((size_t)B.nr * x.capr * sizeof(T)));
+    x.V = reinterpret_cast<T*>(take((size_t)B.nc * x.capr * sizeof(T)));
+    x.rank1 = rank1 + i;
+    x.rank = adaptive ? rankf + i : rank1 + i;
+    x.u11 = u11 + i;
+  }
+  Blob b;
+  std::vector<SkelDesc<T>> sk;
+  std::vector<SkelFacDesc<T>> sf;
+  std::vector<Phase2Desc<T>> p2;
+  GemmBatch<T> resid;
+  size_t lds_sk = 0;
+  int rmax1 = 1, wgs = 0, maxrc = 1;
+  const int* dI = d_bdlr.as<int>();
+  const int* dJ = d_bdlr.as<int>() + bdlr_J_base;
+  for (auto& x : br) {
+    const Block& B = s.fronts[x.p].blocks[x.bi];
+    const FN& fx = fn[x.p];
+    SkelDesc<T> d{};
+    d.F = fx.F; d.ld = fx.ld;
+    d.I = dI + bIptr[x.gb]; d.nI = x.nI;
+    d.J = dJ + bJptr[x.gb]; d.nJ = x.nJ;
+    d.piv_r = x.pr; d.piv_c = x.pc; d.M = x.M; d.ldm = std::max(x.kcap, 1);
+    d.rank = x.rank1; d.u11 = x.u11;
+    sk.push_back(d);
+    lds_sk = std::max(lds_sk, (size_t)x.nI * x.nJ * sizeof(T) + 2 * (size_t)x.kcap * sizeof(int) + x.nI + x.nJ + 64);
+    rmax1 = std::max(rmax1, x.kcap);
+    SkelFacDesc<T> f{};
+    f.F = fx.F; f.ld = fx.ld; f.r0 = B.r0; f.nr = B.nr; f.c0 = B.c0; f.nc = B.nc;
+    f.piv_r = x.pr; f.piv_c = x.pc; f.M = x.M; f.ldm = std::max(x.kcap, 1); f.rank = x.rank1;
+    f.U = x.U; f.ldu = B.nr; f.V = x.V; f.ldv = B.nc;
+    f.wgU = cdiv(B.nr, 256);
+    f.wg0 = wgs;
+    wgs += f.wgU + cdiv(B.nc, 256);
+    sf.push_back(f);
+    if (adaptive) {
+      // E = B - U V^T in place (k = phase-1 rank, read on the device)
+      resid.v.push_back(gd<T>(x.U, B.nr, 0, x.V, B.nc, 1, fx.F + B.r0 + (int64_t)B.c0 * fx.ld, fx.ld, B.nr, B.nc,
+                              x.kcap, -1.0, 1.0, 0, x.rank1));
+      Phase2Desc<T> q{};
+      q.F = fx.F; q.ld = fx.ld; q.r0 = B.r0; q.nr = B.nr; q.c0 = B.c0; q.nc = B.nc;
+      q.piv_r = x.pr; q.piv_c = x.pc; q.rank1 = x.rank1; q.u11 = x.u11;
+      q.U = x.U; q.ldu = B.nr; q.V = x.V; q.ldv = B.nc; q.cap = x.capr; q.rank = x.rank;
+      p2.push_back(q);
+      maxrc = std::max(maxrc, B.nr + B.nc);
+    }
+  }
+  if (lds_sk > (size_t)kLdsMax)
+    throw Err{MF_EINVAL, "BDLR sets too large for LDS: lower bdlr_cap"};
+  if ((size_t)rmax1 * rmax1 * sizeof(T) > (size_t)kLdsMax)
+    throw Err{MF_EINVAL, "phase-1 rank bound too large for LDS: lower bdlr_cap"};
+  if (maxrc > kLdsMax) throw Err{MF_EINVAL, "block too large for the phase-2 kernel"};
+  const size_t osk = b.add(sk), osf = b.add(sf), op2 = b.add(p2);
+  resid.stage(b);
+  const char* base = dp.upload(b, st);
+  launch_skel<T>(reinterpret_cast<const SkelDesc<T>*>(base + osk), nb, lds_sk, eps, st);
+  launch_skelfac<T>(reinterpret_cast<const SkelFacDesc<T>*>(base + osf), nb, wgs, rmax1, st);
+  if (adaptive) {
+    resid.launch(base, st);
+    launch_phase2<T>(reinterpret_cast<const Phase2Desc<T>*>(base + op2), nb, maxrc, eps, d_status.as<int>(), st);
+  }
+  // ---- the one synchronisation of the level: ranks to the host
+  std::vector<int> hr(nb);
+  int status = 0;
+  HIPCHK(hipMemcpyAsync(hr.data(), adaptive ? rankf : rank1, nb * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(&status, d_status.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(st));
+  if (status & 2) throw Err{MF_ECAPACITY, "a block rank exceeded rank_cap"};
+  for (int i = 0; i < nb; ++i) ranks[br[i].gb] = hr[i];
+
+  // ---- phase B
+  std::map<std::pair<int, int>, int> bidx;   // (front, block) -> br index
+  for (int i = 0; i < nb; ++i) bidx[{br[i].p, br[i].bi}] = i;
+  Blob b2;
+  CopyBatch<T, T> cp;        // scratch U/V -> persistent, G initialisation
+  std::vector<PotrfDesc<T>> leaves;
+  GemmBatch<T> lg1, lg2;
+  int Lmax = 0;
+  int64_t g_tot = 0, t1_tot = 0;
+  for (int p : Hs) {
+    const Front& f = s.fronts[p];
+    FN& x = fn[p];
+    const int nt = (int)f.pp_tree.size();
+    x.nodeU.assign(nt, nullptr); x.nodeV.assign(nt, nullptr); x.nodeK.assign(nt, nullptr);
+    x.leafInv.assign(nt, nullptr); x.nodeR.assign(nt, 0);
+    x.r_top = f.nf() > 0 ? hr[bidx[{p, 0}]] : 0;
+    int depth = 0;
+    for (auto& t : f.pp_tree) depth = std::max(depth, t.level + 1);
+    std::vector<int> rml(depth, 0);
+    for (int i = 0; i < nt; ++i) {
+      const TreeNode& t = f.pp_tree[i];
+      if (t.left >= 0) {
+        const int r = hr[bidx[{p, t.block}]];
+        x.nodeR[i] = r;
+        rml[t.level] = std::max(rml[t.level], r);
+        Lmax = std::max(Lmax, t.level + 1);
+      }
+    }
+    x.col.assign(depth + 1, 0);
+    x.col[0] = x.r_top;
+    for (int l = 0; l < depth; ++l) x.col[l + 1] = x.col[l] + rml[l];
+    x.w = x.col[depth];
+    g_tot += (int64_t)f.npiv * x.w;
+    for (auto& t : f.pp_tree)
+      if (t.left < 0) t1_tot += (int64_t)t.size * x.w;
+  }
+  T* gall = arena.alloc_n<T>(g_tot);
+  if (g_tot > 0) launch_fill<T>(gall, g_tot, (T)0, st);
+  for (int p : Hs) {
+    const Front& f = s.fronts[p];
+    FN& x = fn[p];
+    x.G = gall;
+    gall += (int64_t)f.npiv * x.w;
+    if (x.r_top > 0) {
+      const BR& t = br[bidx[{p, 0}]];
+      x.W = arena.alloc_n<T>((int64_t)f.nf() * x.r_top);
+      cp.v.push_back(cd<T, T>(t.U, f.nf(), x.W, f.nf(), f.nf(), x.r_top));
+      cp.v.push_back(cd<T, T>(t.V, f.npiv, x.G, f.npiv, f.npiv, x.r_top));   // V_top -> X columns
+    }
+    for (int i = 0; i < (int)f.pp_tree.size(); ++i) {
+      const TreeNode& t = f.pp_tree[i];
+      if (t.left < 0) {
+        x.leafInv[i] = arena.alloc_n<T>((int64_t)t.size * t.size);
+        PotrfDesc<T> d{};
+        d.A = x.F + t.off + (int64_t)t.off * x.ld; d.lda = x.ld; d.n = t.size;
+        d.Inv = x.leafInv[i]; d.ldi = t.size;
+        leaves.push_back(d);
+        continue;
+      }
+      const int r = x.nodeR[i];
+      const BR& bb = br[bidx[{p, t.block}]];
+      const TreeNode& a = f.pp_tree[t.left];
+      const TreeNode& be = f.pp_tree[t.right];
+      x.nodeU[i] = arena.alloc_n<T>((int64_t)be.size * r);
+      x.nodeV[i] = arena.alloc_n<T>((int64_t)a.size * r);
+      x.nodeK[i] = arena.alloc_n<T>((int64_t)4 * r * r);
+      cp.v.push_back(cd<T, T>(bb.U, be.size, x.nodeU[i], be.size, be.size, r));
+      cp.v.push_back(cd<T, T>(bb.V, a.size, x.nodeV[i], a.size, a.size, r));
+      const int c = x.col[t.level];
+      cp.v.push_back(cd<T, T>(bb.V, a.size, x.G + a.off + (int64_t)c * f.npiv, f.npiv, a.size, r));
+      cp.v.push_back(cd<T, T>(bb.U, be.size, x.G + be.off + (int64_t)c * f.npiv, f.npiv, be.size, r));
+    }
+  }
+  // leaf solves on G:  G_leaf <- L^{-T} L^{-1} G_leaf
+  scrB.ensure(std::max<int64_t>(t1_tot, 1) * sizeof(T), &ms, st);
+  {
+    T* tp = scrB.as<T>();
+    for (int p : Hs) {
+      const Front& f = s.fronts[p];
+      FN& x = fn[p];
+      if (x.w == 0) continue;
+      for (int i = 0; i < (int)f.pp_tree.size(); ++i) {
+        const TreeNode& t = f.pp_tree[i];
+        if (t.left >= 0) continue;
+        lg1.v.push_back(gd<T>(x.leafInv[i], t.size, 0, x.G + t.off, f.npiv, 0, tp, t.size, t.size, x.w, t.size, 1.0,
+                              0.0, GF_A_LOWER));
+        lg2.v.push_back(gd<T>(x.leafInv[i], t.size, 1, tp, t.size, 0, x.G + t.off, f.npiv, t.size, x.w, t.size, 1.0,
+                              0.0, GF_A_UPPER));
+        tp += (int64_t)t.size * x.w;
+      }
+    }
+  }
+  const size_t oleaf = b2.add(leaves);
+  cp.stage(b2);
+  lg1.stage(b2);
+  lg2.stage(b2);
+  const char* base2 = dp.upload(b2, st);
+  cp.launch(base2, st);
+  launch_potrf<T>(reinterpret_cast<const PotrfDesc<T>*>(base2 + oleaf), (int)leaves.size(), s.leaf,
+                  d_status.as<int>(), st);
+  lg1.launch(base2, st);
+  lg2.launch(base2, st);
+
+  // ---- SMW sweep, deepest HODLR level first
+  for (int l = Lmax - 1; l >= 0; --l) {
+    struct NodeRef { int p, i, r, c; };
+    std::vector<NodeRef> nodes;
+    size_t nP = 0, nK = 0, nPa = 0, nQ = 0;
+    for (int p : Hs) {
+      const Front& f = s.fronts[p];
+      for (int i = 0; i < (int)f.pp_tree.size(); ++i) {
+        const TreeNode& t = f.pp_tree[i];
+        if (t.left < 0 || t.level != l || fn[p].nodeR[i] == 0) continue;
+        const int r = fn[p].nodeR[i], c = fn[p].col[l];
+        nodes.push_back({p, i, r, c});
+        nP += al((size_t)2 * r * (c + r) * sizeof(T));
+        nK += al((size_t)2 * r * 4 * r * sizeof(double));
+        nPa += al((size_t)2 * r * std::max(c, 1) * sizeof(double));
+        nQ += al((size_t)2 * r * std::max(c, 1) * sizeof(double)) + al((size_t)2 * r * std::max(c, 1) * sizeof(T));
+      }
+    }
+    if (nodes.empty()) continue;
+    scrB.ensure(nP + nK + nPa + nQ, &ms, st);
+    char* cb = static_cast<char*>(scrB.p);
+    auto tk = [&](size_t bytes) { char* r = cb; cb += al(bytes); return r; };
+    Blob b3;
+    GemmBatch<T> gP, gC;
+    GemmBatch<double> gQ;
+    std::vector<CapDesc<T>> capd;
+    std::vector<InvDesc> invd;
+    CopyBatch<double, T> cQ, cK;
+    for (auto& nr : nodes) {
+      const Front& f = s.fronts[nr.p];
+      FN& x = fn[nr.p];
+      const TreeNode& t = f.pp_tree[nr.i];
+      const TreeNode& a = f.pp_tree[t.left];
+      const TreeNode& be = f.pp_tree[t.right];
+      const int r = nr.r, c = nr.c, n2 = 2 * r;
+      T* P = reinterpret_cast<T*>(tk((size_t)n2 * (c + r) * sizeof(T)));
+      double* K = reinterpret_cast<double*>(tk((size_t)n2 * 2 * n2 * sizeof(double)));
+      double* Pa = reinterpret_cast<double*>(tk((size_t)n2 * std::max(c, 1) * sizeof(double)));
+      double* Q64 = reinterpret_cast<double*>(tk((size_t)n2 * std::max(c, 1) * sizeof(double)));
+      T* Q = reinterpret_cast<T*>(tk((size_t)n2 * std::max(c, 1) * sizeof(T)));
+      // P = [V^T G(alpha, 0:c+r); U^T G(beta, 0:c+r)]
+      gP.v.push_back(gd<T>(x.nodeV[nr.i], a.size, 1, x.G + a.off, f.npiv, 0, P, n2, r, c + r, a.size, 1.0, 0.0));
+      gP.v.push_back(gd<T>(x.nodeU[nr.i], be.size, 1, x.G + be.off, f.npiv, 0, P + r, n2, r, c + r, be.size, 1.0,
+                           0.0));
+      CapDesc<T> cdsc{};
+      cdsc.P = P; cdsc.ldp = n2; cdsc.r = r; cdsc.c = c; cdsc.K = K; cdsc.Pa = Pa;
+      capd.push_back(cdsc);
+      InvDesc iv{};
+      iv.A = K; iv.n = n2;
+      invd.push_back(iv);
+      const double* Kinv = K + (size_t)n2 * n2;
+      if (c > 0) {
+        gQ.v.push_back(gd<double>(Kinv, n2, 0, Pa, n2, 0, Q64, n2, n2, c, n2, 1.0, 0.0));
+        cQ.v.push_back(cd<double, T>(Q64, n2, Q, n2, n2, c));
+        // G(alpha, 0:c) -= Y_alpha Q(0:r, :) ; G(beta, 0:c) -= Y_beta Q(r:2r, :)
+        gC.v.push_back(gd<T>(x.G + a.off + (int64_t)c * f.npiv, f.npiv, 0, Q, n2, 0, x.G + a.off, f.npiv, a.size, c,
+                             r, -1.0, 1.0));
+        gC.v.push_back(gd<T>(x.G + be.off + (int64_t)c * f.npiv, f.npiv, 0, Q + r, n2, 0, x.G + be.off, f.npiv,
+                             be.size, c, r, -1.0, 1.0));
+      }
+      cK.v.push_back(cd<double, T>(Kinv, n2, x.nodeK[nr.i], n2, n2, n2));
+    }
+    gP.stage(b3);
+    const size_t ocap = b3.add(capd), oinv = b3.add(invd);
+    gQ.stage(b3);
+    cQ.stage(b3);
+    gC.stage(b3);
+    cK.stage(b3);
+    const char* base3 = dp.upload(b3, st);
+    gP.launch(base3, st);
+    launch_cap<T>(reinterpret_cast<const CapDesc<T>*>(base3 + ocap), (int)capd.size(), st);
+    launch_gj_inverse(reinterpret_cast<const InvDesc*>(base3 + oinv), (int)invd.size(), d_status.as<int>(), st);
+    gQ.launch(base3, st);
+    cQ.launch(base3, st);
+    gC.launch(base3, st);
+    cK.launch(base3, st);
+  }
+
+  // ---- Schur complement update of the ff part:  U_p = F_ff^HODLR - W S W^T
+  {
+    size_t need2 = 0;
+    for (int p : Hs) {
+      const Front& f = s.fronts[p];
+      const int r = fn[p].r_top;
+      if (r == 0) continue;
+      need2 += al((size_t)f.npiv * r * 8) * 2 + al((size_t)f.nf() * r * 8) * 2 + al((size_t)r * r * 8) +
+               al((size_t)f.nf() * r * sizeof(T));
+    }
+    scrB.ensure(std::max<size_t>(need2, 256), &ms, st);
+    char* cb = static_cast<char*>(scrB.p);
+    auto tk = [&](size_t bytes) { char* r = cb; cb += al(bytes); return r; };
+    Blob b4;
+    CopyBatch<T, double> c64;
+    GemmBatch<double> gS, gWt;
+    CopyBatch<double, T> cW;
+    GemmBatch<T> gff, gup;
+    for (int p : Hs) {
+      const Front& f = s.fronts[p];
+      FN& x = fn[p];
+      const int npv = f.npiv, nf = f.nf();
+      // F_ff off-diagonal blocks <- U V^T (compressed form, written densely for the parent)
+      for (int bi = 0; bi < (int)f.blocks.size(); ++bi) {
+        const Block& B = f.blocks[bi];
+        if (B.kind != 2) continue;
+        const BR& bb = br[bidx[{p, bi}]];
+        gff.v.push_back(gd<T>(bb.U, B.nr, 0, bb.V, B.nc, 1, x.F + B.r0 + (int64_t)B.c0 * x.ld, x.ld, B.nr, B.nc,
+                              hr[bidx[{p, bi}]], 1.0, 0.0));
+      }
+      const int r = x.r_top;
+      if (r == 0) continue;
+      const BR& tb = br[bidx[{p, 0}]];
+      double* V64 = reinterpret_cast<double*>(tk((size_t)npv * r * 8));
+      double* X64 = reinterpret_cast<double*>(tk((size_t)npv * r * 8));
+      double* W64 = reinterpret_cast<double*>(tk((size_t)nf * r * 8));
+      double* Wt64 = reinterpret_cast<double*>(tk((size_t)nf * r * 8));
+      double* S64 = reinterpret_cast<double*>(tk((size_t)r * r * 8));
+      T* Wt = reinterpret_cast<T*>(tk((size_t)nf * r * sizeof(T)));
+      c64.v.push_back(cd<T, double>(tb.V, npv, V64, npv, npv, r));
+      c64.v.push_back(cd<T, double>(x.G, npv, X64, npv, npv, r));
+      c64.v.push_back(cd<T, double>(x.W, nf, W64, nf, nf, r));
+      gS.v.push_back(gd<double>(V64, npv, 1, X64, npv, 0, S64, r, r, r, npv, 1.0, 0.0));       // S = V^T X
+      gWt.v.push_back(gd<double>(W64, nf, 0, S64, r, 0, Wt64, nf, nf, r, r, 1.0, 0.0));        // W S
+      cW.v.push_back(cd<double, T>(Wt64, nf, Wt, nf, nf, r));
+      gup.v.push_back(gd<T>(Wt, nf, 0, x.W, nf, 1, x.F + npv + (int64_t)npv * x.ld, x.ld, nf, nf, r, -1.0, 1.0,
+                            GF_LOWER_C));
+    }
+    c64.stage(b4);
+    gS.stage(b4);
+    gWt.stage(b4);
+    cW.stage(b4);
+    gff.stage(b4);
+    gup.stage(b4);
+    const char* base4 = dp.upload(b4, st);
+    c64.launch(base4, st);
+    gS.launch(base4, st);
+    gWt.launch(base4, st);
+    cW.launch(base4, st);
+    gff.launch(base4, st);
+    gup.launch(base4, st);
+  }
+}
+
+// ================================================================ apply ====
+template <typename T>
+typename Numeric<T>::Plan* Numeric<T>::get_plan(int nrhs) {
+  auto it = plans.find(nrhs);
+  if (it != plans.end()) return it->second.get();
+  const Symbolic& s = *sym;
+  auto pl = std::make_unique<Plan>();
+  pl->nrhs = nrhs;
+  pl->dp.ar.ms = &ms;
+  const int nfr = (int)s.fronts.size();
+  const int N = s.n;
+  // workspace layout (elements of T)
+  int64_t tot = (int64_t)N * nrhs;
+  std::vector<int64_t> t_off(nfr), z_off(nfr), h_off(nfr);
+  std::vector<std::vector<int64_t>> q_off(nfr), l_off(nfr);
+  for (int p = 0; p < nfr; ++p) {
+    const Front& f = s.fronts[p];
+    t_off[p] = tot; tot += (int64_t)f.n() * nrhs;
+    z_off[p] = tot; tot += (int64_t)f.npiv * nrhs;
+    if (!fn[p].dense) {
+      h_off[p] = tot; tot += (int64_t)std::max(fn[p].r_top, 1) * nrhs;
+      q_off[p].assign(f.pp_tree.size(), 0);
+      l_off[p].assign(f.pp_tree.size(), 0);
+      for (size_t i = 0; i < f.pp_tree.size(); ++i) {
+        const TreeNode& t = f.pp_tree[i];
+        if (t.left >= 0) { q_off[p][i] = tot; tot += (int64_t)4 * std::max(fn[p].nodeR[i], 1) * nrhs; }
+        else { l_off[p][i] = tot; tot += (int64_t)t.size * nrhs; }
+      }
+    }
+  }
+  pl->work.alloc(tot * sizeof(T), &ms);
+  T* wk = static_cast<T*>(pl->work.p);
+  pl->xn = wk;
+  Blob b;
+  auto rec_gemm = [&](GemmBatch<T>& g) {
+    g.stage(b);
+    if (g.n) pl->recs.push_back({0, g.off, g.n, g.tiles});
+  };
+  auto rec_copy = [&](CopyBatch<T, T>& c) {
+    c.stage(b);
+    if (c.n) pl->recs.push_back({1, c.off, c.n, c.tiles});
+  };
+  const int H = (int)s.levels.size();
+  // upward pass
+  for (int h = 0; h < H; ++h) {
+    std::vector<VecAsmDesc<T>> va;
+    GemmBatch<T> u1, u2, lf1, lf2;
+    CopyBatch<T, T> zc;
+    int Lmax = 0;
+    for (int p : s.levels[h]) {
+      const Front& f = s.fronts[p];
+      const FN& x = fn[p];
+      VecAsmDesc<T> d{};
+      d.t = wk + t_off[p]; d.xs = pl->xn + f.start; d.nhat = f.n(); d.npiv = f.npiv; d.ldt = f.n(); d.ldx = N;
+      d.nchild = (int)f.children.size();
+      for (int ci = 0; ci < d.nchild && ci < 2; ++ci) {
+        const int c = f.children[ci];
+        const Front& fc = s.fronts[c];
+        d.ct[ci] = wk + t_off[c]; d.crel[ci] = fc.relmap.empty() ? nullptr : d_relmap.as<int>() + relmap_off[c];
+        d.cnp[ci] = fc.npiv; d.cnf[ci] = fc.nf(); d.cld[ci] = fc.n();
+      }
+      va.push_back(d);
+      T* t = wk + t_off[p];
+      T* z = wk + z_off[p];
+      const int np = f.npiv, nf = f.nf(), nh = f.n();
+      if (x.dense) {
+        u1.v.push_back(gd<T>(x.Linv, np, 0, t, nh, 0, z, np, np, nrhs, np, 1.0, 0.0, GF_A_LOWER));
+        if (nf > 0) u2.v.push_back(gd<T>(x.Lfp, nf, 0, z, np, 0, t + np, nh, nf, nrhs, np, -1.0, 1.0));
+      } else {
+        T* hb = wk + h_off[p];
+        if (x.r_top > 0) {
+          u1.v.push_back(gd<T>(x.G, np, 1, t, nh, 0, hb, x.r_top, x.r_top, nrhs, np, 1.0, 0.0));   // X^T t_p
+          u2.v.push_back(gd<T>(x.W, nf, 0, hb, x.r_top, 0, t + np, nh, nf, nrhs, x.r_top, -1.0, 1.0));
+        }
+        zc.v.push_back(cd<T, T>(t, nh, z, np, np, nrhs));
+        for (size_t i = 0; i < f.pp_tree.size(); ++i) {
+          const TreeNode& tn = f.pp_tree[i];
+          if (tn.left >= 0) { Lmax = std::max(Lmax, tn.level + 1); continue; }
+          T* T1 = wk + l_off[p][i];
+          lf1.v.push_back(gd<T>(x.leafInv[i], tn.size, 0, z + tn.off, np, 0, T1, tn.size, tn.size, nrhs, tn.size, 1.0,
+                                0.0, GF_A_LOWER));
+          lf2.v.push_back(gd<T>(x.leafInv[i], tn.size, 1, T1, tn.size, 0, z + tn.off, np, tn.size, nrhs, tn.size, 1.0,
+                                0.0, GF_A_UPPER));
+        }
+      }
+    }
+    {
+      size_t o = b.add(va);
+      pl->recs.push_back({2, o, (int)va.size(), 0});
+    }
+    rec_gemm(u1);
+    rec_gemm(u2);
+    rec_copy(zc);
+    rec_gemm(lf1);
+    rec_gemm(lf2);
+    for (int l = Lmax - 1; l >= 0; --l) {
+      GemmBatch<T> g1, g2, g3;
+      for (int p : s.levels[h]) {
+        if (fn[p].dense) continue;
+        const Front& f = s.fronts[p];
+        const FN& x = fn[p];
+        T* z = wk + z_off[p];
+        const int np = f.npiv;
+        for (size_t i = 0; i < f.pp_tree.size(); ++i) {
+          const TreeNode& t = f.pp_tree[i];
+          if (t.left < 0 || t.level != l || x.nodeR[i] == 0) continue;
+          const TreeNode& a = f.pp_tree[t.left];
+          const TreeNode& be = f.pp_tree[t.right];
+          const int r = x.nodeR[i], n2 = 2 * r, c = x.col[l];
+          T* q = wk + q_off[p][i];
+          T* q2 = q + (int64_t)n2 * nrhs;
+          g1.v.push_back(gd<T>(x.nodeV[i], a.size, 1, z + a.off, np, 0, q, n2, r, nrhs, a.size, 1.0, 0.0));
+          g1.v.push_back(gd<T>(x.nodeU[i], be.size, 1, z + be.off, np, 0, q + r, n2, r, nrhs, be.size, 1.0, 0.0));
+          g2.v.push_back(gd<T>(x.nodeK[i], n2, 0, q, n2, 0, q2, n2, n2, nrhs, n2, 1.0, 0.0));
+          g3.v.push_back(gd<T>(x.G + a.off + (int64_t)c * np, np, 0, q2, n2, 0, z + a.off, np, a.size, nrhs, r, -1.0,
+                               1.0));
+          g3.v.push_back(gd<T>(x.G + be.off + (int64_t)c * np, np, 0, q2 + r, n2, 0, z + be.off, np, be.size, nrhs, r,
+                               -1.0, 1.0));
+        }
+      }
+      rec_gemm(g1);
+      rec_gemm(g2);
+      rec_gemm(g3);
+    }
+  }
+  // downward pass
+  for (int h = H - 1; h >= 0; --h) {
+    std::vector<VecGatherDesc<T>> vg;
+    GemmBatch<T> d1, d2;
+    CopyBatch<T, T> xo;
+    for (int p : s.levels[h]) {
+      const Front& f = s.fronts[p];
+      const FN& x = fn[p];
+      const int np = f.npiv, nf = f.nf(), nh = f.n();
+      T* t = wk + t_off[p];
+      T* z = wk + z_off[p];
+      if (nf > 0) {
+        VecGatherDesc<T> g{};
+        g.t = t + np; g.upd = d_relmap.as<int>();   // placeholder, replaced below
+        g.nf = nf; g.ldt = nh;
+        vg.push_back(g);
+      }
+      if (x.dense) {
+        if (nf > 0) d1.v.push_back(gd<T>(x.Lfp, nf, 1, t + np, nh, 0, z, np, np, nrhs, nf, -1.0, 1.0));
+        d2.v.push_back(gd<T>(x.Linv, np, 1, z, np, 0, pl->xn + f.start, N, np, nrhs, np, 1.0, 0.0, GF_A_UPPER));
+      } else {
+        T* hb = wk + h_off[p];
+        if (x.r_top > 0) {
+          d1.v.push_back(gd<T>(x.W, nf, 1, t + np, nh, 0, hb, x.r_top, x.r_top, nrhs, nf, 1.0, 0.0));
+          d2.v.push_back(gd<T>(x.G, np, 0, hb, x.r_top, 0, z, np, np, nrhs, x.r_top, -1.0, 1.0));
+        }
+        xo.v.push_back(cd<T, T>(z, np, pl->xn + f.start, N, np, nrhs));
+      }
+    }
+    // the gather needs each front's I_p^f on the device
+    if (!vg.empty()) {
+      std::vector<int> upd;
+      std::vector<int64_t> uo;
+      for (int p : s.levels[h]) {
+        const Front& f = s.fronts[p];
+        if (f.nf() == 0) continue;
+        uo.push_back((int64_t)upd.size());
+        upd.insert(upd.end(), f.upd.begin(), f.upd.end());
+      }
+      Blob ub;
+      size_t o = ub.add(upd);
+      const char* ubase = pl->dp.upload(ub, st);
+      for (size_t i = 0; i < vg.size(); ++i) vg[i].upd = reinterpret_cast<const int*>(ubase + o) + uo[i];
+      size_t ov = b.add(vg);
+      pl->recs.push_back({3, ov, (int)vg.size(), 0});
+    }
+    rec_gemm(d1);
+    rec_gemm(d2);
+    rec_copy(xo);
+  }
+  pl->desc = pl->dp.upload(b, st);
+  HIPCHK(hipStreamSynchronize(st));
+  Plan* raw = pl.get();
+  plans[nrhs] = std::move(pl);
+  return raw;
+}
+
+template <typename T>
+void Numeric<T>::apply(int nrhs, const double* r, double* z, hipStream_t stream) {
+  hipStream_t keep = st;
+  st = stream;
+  Plan* pl = get_plan(nrhs);
+  st = keep;
+  const int N = sym->n;
+  launch_perm_in<T>(r, pl->xn, d_perm.as<int>(), N, nrhs, stream);
+  for (const Rec& rc : pl->recs) {
+    const char* base = pl->desc + rc.off;
+    switch (rc.kind) {
+      case 0: launch_gemm<T>(reinterpret_cast<const GemmDesc<T>*>(base), rc.n, rc.tiles, stream); break;
+      case 1: launch_copy<T, T>(reinterpret_cast<const CopyDesc<T, T>*>(base), rc.n, rc.tiles, stream); break;
+      case 2: launch_vec_asm<T>(reinterpret_cast<const VecAsmDesc<T>*>(base), rc.n, nrhs, stream); break;
+      case 3: launch_vec_gather<T>(reinterpret_cast<const VecGatherDesc<T>*>(base), rc.n, pl->xn, N, nrhs, stream);
+        break;
+    }
+  }
+  launch_perm_out<T>(pl->xn, z, d_iperm.as<int>(), N, nrhs, stream);
+  HIPCHK(hipGetLastError());
+}
+
+// ================================================================ GMRES ====
+void NumericBase::spmv(int nrhs, const double* x, double* y, double alpha, double beta, hipStream_t st) {
+  launch_spmv(d_rowptr.as<int>(), d_colind.as<int>(), d_vals.as<double>(), x, y, sym->n, nrhs, alpha, beta, st);
+}
+
+void NumericBase::gmres(int nrhs, const double* b, double* x, double tol, const mf_gmres_opts& o,
+                        mf_gmres_info* info_out, mf_status* st_out) {
+  hipStream_t st = static_cast<hipStream_t>(o.stream);
+  const int N = sym->n, m = std::max(1, o.restart);
+  const int64_t vs = (int64_t)N * nrhs;
+  g_V.ensure((size_t)(m + 1) * vs * 8, &ms, st);
+  g_Z.ensure((size_t)m * vs * 8, &ms, st);
+  g_w.ensure((size_t)vs * 8, &ms, st);
+  g_r.ensure((size_t)vs * 8, &ms, st);
+  const int nsmall = 3 * (m + 2) * nrhs + 4 * nrhs;
+  g_small.ensure((size_t)nsmall * 8, &ms, st);
+  g_partial.ensure((size_t)64 * (m + 2) * nrhs * 8, &ms, st);
+  double* V = g_V.as<double>();
+  double* Z = g_Z.as<double>();
+  double* w = g_w.as<double>();
+  double* r = g_r.as<double>();
+  double* sm = g_small.as<double>();
+  double* h1 = sm;                        // (m+1) x nrhs
+  double* h2 = sm + (m + 1) * nrhs;       // (m+1) x nrhs
+  double* nr2 = sm + 2 * (m + 1) * nrhs;  // nrhs
+  double* ydev = nr2 + nrhs;              // m x nrhs
+  double* part = g_partial.as<double>();
+
+  std::vector<double> hs((size_t)2 * (m + 1) * nrhs + nrhs);
+  auto read_small = [&](int count) {
+    HIPCHK(hipMemcpyAsync(hs.data(), sm, count * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+  };
+  // ||b||
+  launch_mdot(b, 0, 1, b, N, nrhs, part, nr2, 0, st);
+  HIPCHK(hipMemcpyAsync(hs.data(), nr2, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  std::vector<double> bnorm(nrhs), beta(nrhs);
+  for (int k = 0; k < nrhs; ++k) bnorm[k] = std::sqrt(hs[k]);
+  launch_fill<double>(x, vs, 0.0, st);
+  launch_axpby(b, b, r, 1.0, 0.0, vs, st);
+  beta = bnorm;
+  std::vector<int> iters(nrhs, 0), conv(nrhs, 0);
+  std::vector<double> H((size_t)nrhs * (m + 1) * m), cs((size_t)nrhs * m), sn((size_t)nrhs * m),
+      g((size_t)nrhs * (m + 1)), ybuf((size_t)m * nrhs);
+  const int maxit = o.maxit;
+  for (;;) {
+    bool any = false;
+    std::vector<double> nrm2(nrhs);
+    for (int k = 0; k < nrhs; ++k) {
+      if (beta[k] <= tol * bnorm[k]) conv[k] = 1;
+      const bool act = !conv[k] && iters[k] < maxit;
+      any |= act;
+      nrm2[k] = act ? beta[k] * beta[k] : 0.0;   // inactive columns get a zero basis
+    }
+    if (!any) break;
+    std::vector<char> act(nrhs);
+    for (int k = 0; k < nrhs; ++k) act[k] = !conv[k] && iters[k] < maxit;
+    HIPCHK(hipMemcpyAsync(nr2, nrm2.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
+    launch_scale_cols(r, V, nr2, N, nrhs, st);
+    std::fill(H.begin(), H.end(), 0.0);
+    std::fill(g.begin(), g.end(), 0.0);
+    for (int k = 0; k < nrhs; ++k) g[(size_t)k * (m + 1)] = act[k] ? beta[k] : 0.0;
+    int jend = 0;
+    std::vector<int> jk(nrhs, 0);          // Arnoldi columns used by each rhs this cycle
+    std::vector<char> frozen(nrhs, 0);
+    for (int j = 0; j < m; ++j) {
+      double* Vj = V + (int64_t)j * vs;
+      double* Zj = Z + (int64_t)j * vs;
+      apply(nrhs, Vj, Zj, st);
+      spmv(nrhs, Zj, w, 1.0, 0.0, st);
+      // classical Gram-Schmidt, twice
+      launch_mdot(V, vs, j + 1, w, N, nrhs, part, h1, 0, st);
+      launch_maxpy(V, vs, j + 1, h1, w, N, nrhs, -1.0, st);
+      launch_mdot(V, vs, j + 1, w, N, nrhs, part, h2, 0, st);
+      launch_maxpy(V, vs, j + 1, h2, w, N, nrhs, -1.0, st);
+      launch_mdot(w, 0, 1, w, N, nrhs, part, nr2, 0, st);
+      launch_scale_cols(w, V + (int64_t)(j + 1) * vs, nr2, N, nrhs, st);
+      read_small(2 * (m + 1) * nrhs + nrhs);
+      bool all_done = true;
+      for (int k = 0; k < nrhs; ++k) {
+        if (!act[k] || frozen[k]) continue;
+        double* Hk = H.data() + (size_t)k * (m + 1) * m;   // column-major (m+1) x m
+        double* gk = g.data() + (size_t)k * (m + 1);
+        double* ck = cs.data() + (size_t)k * m;
+        double* sk = sn.data() + (size_t)k * m;
+        for (int i = 0; i <= j; ++i) Hk[i + (size_t)j * (m + 1)] = hs[i * nrhs + k] + hs[(m + 1) * nrhs + i * nrhs + k];
+        Hk[(j + 1) + (size_t)j * (m + 1)] = std::sqrt(hs[2 * (m + 1) * nrhs + k]);
+        for (int i = 0; i < j; ++i) {
+          const double a = Hk[i + (size_t)j * (m + 1)], bb = Hk[i + 1 + (size_t)j * (m + 1)];
+          Hk[i + (size_t)j * (m + 1)] = ck[i] * a + sk[i] * bb;
+          Hk[i + 1 + (size_t)j * (m + 1)] = -sk[i] * a + ck[i] * bb;
+        }
+        const double a = Hk[j + (size_t)j * (m + 1)], bb = Hk[j + 1 + (size_t)j * (m + 1)];
+        const double den = std::hypot(a, bb);
+        ck[j] = den > 0 ? a / den : 1.0;
+        sk[j] = den > 0 ? bb / den : 0.0;
+        Hk[j + (size_t)j * (m + 1)] = den;
+        Hk[j + 1 + (size_t)j * (m + 1)] = 0.0;
+        gk[j + 1] = -sk[j] * gk[j];
+        gk[j] = ck[j] * gk[j];
+        iters[k]++;
+        jk[k] = j + 1;
+        const bool done = std::fabs(gk[j + 1]) <= tol * bnorm[k] || iters[k] >= maxit || den == 0.0;
+        if (done) frozen[k] = 1;
+        all_done &= done;
+      }
+      jend = j + 1;
+      if (all_done) break;
+    }
+    // y = H^{-1} g per column; x += Z y
+    std::fill(ybuf.begin(), ybuf.end(), 0.0);
+    for (int k = 0; k < nrhs; ++k) {
+      if (!act[k]) continue;
+      const double* Hk = H.data() + (size_t)k * (m + 1) * m;
+      const double* gk = g.data() + (size_t)k * (m + 1);
+      const int kk = jk[k];
+      for (int i = kk - 1; i >= 0; --i) {
+        double sacc = gk[i];
+        for (int c = i + 1; c < kk; ++c) sacc -= Hk[i + (size_t)c * (m + 1)] * ybuf[c * nrhs + k];
+        const double d = Hk[i + (size_t)i * (m + 1)];
+        ybuf[i * nrhs + k] = d != 0.0 ? sacc / d : 0.0;
+      }
+    }
+    HIPCHK(hipMemcpyAsync(ydev, ybuf.data(), (size_t)jend * nrhs * sizeof(double), hipMemcpyHostToDevice, st));
+    launch_xupdate(Z, vs, jend, ydev, x, N, nrhs, st);
+    spmv(nrhs, x, w, 1.0, 0.0, st);
+    launch_axpby(b, w, r, 1.0, -1.0, vs, st);
+    launch_mdot(r, 0, 1, r, N, nrhs, part, nr2, 0, st);
+    HIPCHK(hipMemcpyAsync(hs.data(), nr2, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int k = 0; k < nrhs; ++k) beta[k] = std::sqrt(hs[k]);
+  }
+  bool ok = true;
+  for (int k = 0; k < nrhs; ++k) {
+    const bool c = conv[k] || beta[k] <= tol * bnorm[k];
+    ok &= c;
+    if (info_out) info_out[k] = {iters[k], c ? 1 : 0, bnorm[k] > 0 ? beta[k] / bnorm[k] : 0.0};
+  }
+  *st_out = ok ? MF_OK : MF_ENOCONV;
+}
+
+std::unique_ptr<NumericBase> make_numeric(const Symbolic& s, const double* vals, const mf_opts& o) {
+  if (o.precision == MF_FP64) return std::make_unique<Numeric<double>>(s, vals, o);
+  return std::make_unique<Numeric<float>>(s, vals, o);
+}
+
+}  // namespace mfh

@@ -1,0 +1,337 @@
+// Host-side symbolic analysis of the multifrontal method (Sec. 4.1.1):
+// nested-dissection order, elimination tree, I_p / S_p / I_p^f, relative
+// maps, assembly map, HODLR cluster trees and BDLR sets (Sec. 2.2).
+//
+// Ordering rule (the paper uses nested dissection without fixing a rule):
+// coordinate-median vertex separators.  For a node set S with |S| > leaf:
+// axis = largest coordinate extent (ties -> lowest axis); sort S by
+// (coordinate, original id); c = coordinate of element floor(|S|/2);
+// L = {coord < c}, R = {coord >= c}, Sep = {v in R with a neighbour in L},
+// R' = R \ Sep.  Empty L or Sep -> leaf.  Postorder numbering: L subtree,
+// R' subtree, Sep.  Leaves and separators are numbered in kd order.
+#include "symbolic.h"
+
+#include <algorithm>
+#include <cstring>
+#include <limits>
+#include <numeric>
+#include <tuple>
+
+namespace mfh {
+namespace {
+
+struct NDCtx {
+  int n, dim, leaf;
+  const int32_t* rowptr;
+  const int32_t* colind;
+  const double* coords;
+  std::vector<int> perm;
+  struct TNode { int start, size; std::vector<int> kids; };
+  std::vector<TNode> tree;
+  std::vector<char> inL;
+
+  double co(int v, int a) const { return coords[(int64_t)v * dim + a]; }
+
+  int extent_axis(const std::vector<int>& ids) const {
+    int best = 0;
+    double bext = -1.0;
+    for (int a = 0; a < dim; ++a) {
+      double mn = std::numeric_limits<double>::infinity(), mx = -mn;
+      for (int v : ids) { double c = co(v, a); mn = std::min(mn, c); mx = std::max(mx, c); }
+      double ext = mx - mn;
+      if (a == 0 || ext > bext) { bext = ext; best = a; }   // first maximum wins
+    }
+    return best;
+  }
+
+  void sort_by_axis(std::vector<int>& ids, int ax) const {
+    std::sort(ids.begin(), ids.end(), [&](int x, int y) {
+      double cx = co(x, ax), cy = co(y, ax);
+      if (cx != cy) return cx < cy;
+      return x < y;
+    });
+  }
+
+  void kd_order(std::vector<int> ids, std::vector<int>& out) const {
+    if ((int)ids.size() <= leaf) {
+      std::sort(ids.begin(), ids.end());
+      out.insert(out.end(), ids.begin(), ids.end());
+      return;
+    }
+    int ax = extent_axis(ids);
+    sort_by_axis(ids, ax);
+    size_t m = ids.size() / 2;
+    kd_order(std::vector<int>(ids.begin(), ids.begin() + m), out);
+    kd_order(std::vector<int>(ids.begin() + m, ids.end()), out);
+  }
+
+  int make_leaf(const std::vector<int>& S) {
+    int start = (int)perm.size();
+    kd_order(S, perm);
+    tree.push_back({start, (int)S.size(), {}});
+    return (int)tree.size() - 1;
+  }
+
+  int rec(const std::vector<int>& S) {
+    if ((int)S.size() <= leaf) return make_leaf(S);
+    int ax = extent_axis(S);
+    std::vector<int> srt(S);
+    sort_by_axis(srt, ax);
+    double c = co(srt[S.size() / 2], ax);
+    std::vector<int> L, R;
+    for (int v : S) (co(v, ax) < c ? L : R).push_back(v);
+    if (L.empty()) return make_leaf(S);
+    for (int v : L) inL[v] = 1;
+    std::vector<int> Sep, Rp;
+    for (int v : R) {
+      bool hit = false;
+      for (int k = rowptr[v]; k < rowptr[v + 1]; ++k)
+        if (inL[colind[k]]) { hit = true; break; }
+      (hit ? Sep : Rp).push_back(v);
+    }
+    for (int v : L) inL[v] = 0;
+    if (Sep.empty()) return make_leaf(S);
+    std::vector<int> kids;
+    kids.push_back(rec(L));
+    if (!Rp.empty()) kids.push_back(rec(Rp));
+    int start = (int)perm.size();
+    kd_order(Sep, perm);
+    tree.push_back({start, (int)Sep.size(), kids});
+    return (int)tree.size() - 1;
+  }
+};
+
+void bisect_tree(int off, int size, int leaf, int kind, std::vector<TreeNode>& nodes,
+                 std::vector<Block>& blocks) {
+  nodes.clear();
+  nodes.push_back({off, size, 0});
+  for (size_t i = 0; i < nodes.size(); ++i) {
+    TreeNode t = nodes[i];
+    if (t.size > leaf) {
+      int m = t.size / 2;
+      nodes[i].left = (int)nodes.size();
+      nodes.push_back({t.off, m, t.level + 1});
+      nodes[i].right = (int)nodes.size();
+      nodes.push_back({t.off + m, t.size - m, t.level + 1});
+    }
+  }
+  for (auto& t : nodes) {
+    if (t.left >= 0) {
+      const TreeNode& l = nodes[t.left];
+      const TreeNode& r = nodes[t.right];
+      t.block = (int)blocks.size();
+      blocks.push_back({kind, r.off, r.size, l.off, l.size, t.level});
+    }
+  }
+}
+
+std::string validate(int n, const int32_t* rowptr, const int32_t* colind) {
+  if (n < 1) return "n must be >= 1";
+  if (rowptr[0] != 0) return "rowptr[0] must be 0";
+  for (int i = 0; i < n; ++i) {
+    if (rowptr[i + 1] < rowptr[i]) return "rowptr not monotone";
+    bool diag = false;
+    for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+      int j = colind[k];
+      if (j < 0 || j >= n) return "column index out of range";
+      if (k > rowptr[i] && colind[k - 1] >= j) return "columns not strictly increasing within a row";
+      if (j == i) diag = true;
+    }
+    if (!diag) return "missing diagonal entry in row " + std::to_string(i);
+  }
+  for (int i = 0; i < n; ++i)
+    for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+      int j = colind[k];
+      if (!std::binary_search(colind + rowptr[j], colind + rowptr[j + 1], i))
+        return "pattern is not symmetric";
+    }
+  return "";
+}
+
+}  // namespace
+
+std::string analyze(int n, const int32_t* rowptr, const int32_t* colind, const double* coords,
+                    int dim, int leaf, Symbolic& s) {
+  if (dim < 1 || dim > 3) return "dim must be 1..3";
+  if (leaf < 1) return "leaf must be >= 1";
+  std::string err = validate(n, rowptr, colind);
+  if (!err.empty()) return err;
+  s = Symbolic();
+  s.n = n; s.leaf = leaf; s.dim = dim;
+  s.nnz = rowptr[n];
+  s.rowptr.assign(rowptr, rowptr + n + 1);
+  s.colind.assign(colind, colind + s.nnz);
+
+  NDCtx ctx{n, dim, leaf, rowptr, colind, coords, {}, {}, std::vector<char>(n, 0)};
+  ctx.perm.reserve(n);
+  std::vector<int> all(n);
+  std::iota(all.begin(), all.end(), 0);
+  ctx.rec(all);
+  s.perm = std::move(ctx.perm);
+  s.iperm.assign(n, 0);
+  for (int i = 0; i < n; ++i) s.iperm[s.perm[i]] = i;
+
+  // pattern of P A P^T
+  s.prow.assign(n + 1, 0);
+  for (int r = 0; r < n; ++r) s.prow[s.iperm[r] + 1] = rowptr[r + 1] - rowptr[r];
+  for (int i = 0; i < n; ++i) s.prow[i + 1] += s.prow[i];
+  s.pcol.assign(s.nnz, 0);
+  for (int r = 0; r < n; ++r) {
+    int nr = s.iperm[r];
+    int o = s.prow[nr];
+    for (int k = rowptr[r]; k < rowptr[r + 1]; ++k) s.pcol[o++] = s.iperm[colind[k]];
+    std::sort(s.pcol.begin() + s.prow[nr], s.pcol.begin() + s.prow[nr + 1]);
+  }
+
+  const int nfr = (int)ctx.tree.size();
+  s.fronts.resize(nfr);
+  for (int p = 0; p < nfr; ++p) {
+    Front& f = s.fronts[p];
+    f.start = ctx.tree[p].start;
+    f.npiv = ctx.tree[p].size;
+    f.children = ctx.tree[p].kids;
+    for (int c : f.children) s.fronts[c].parent = p;
+  }
+  std::vector<int> owner(n);
+  for (int p = 0; p < nfr; ++p)
+    for (int i = 0; i < s.fronts[p].npiv; ++i) owner[s.fronts[p].start + i] = p;
+
+  for (int p = 0; p < nfr; ++p) {
+    Front& f = s.fronts[p];
+    int st = f.start, e = f.start + f.npiv;
+    std::vector<int> U;
+    for (int i = st; i < e; ++i)
+      for (int k = s.prow[i]; k < s.prow[i + 1]; ++k)
+        if (s.pcol[k] >= e) U.push_back(s.pcol[k]);           // S_p (Eq. couplingSet)
+    for (int c : f.children)
+      for (int v : s.fronts[c].upd)
+        if (v < st || v >= e) U.push_back(v);
+    std::sort(U.begin(), U.end());
+    U.erase(std::unique(U.begin(), U.end()), U.end());
+    f.upd = std::move(U);
+    int h = 0;
+    for (int c : f.children) h = std::max(h, s.fronts[c].height + 1);
+    f.height = h;
+  }
+  // relative maps
+  for (int p = 0; p < nfr; ++p) {
+    const Front& f = s.fronts[p];
+    for (int c : f.children) {
+      Front& fc = s.fronts[c];
+      fc.relmap.resize(fc.upd.size());
+      for (size_t a = 0; a < fc.upd.size(); ++a) {
+        int g = fc.upd[a];
+        if (g < f.start + f.npiv) fc.relmap[a] = g - f.start;
+        else fc.relmap[a] = f.npiv + (int)(std::lower_bound(f.upd.begin(), f.upd.end(), g) - f.upd.begin());
+      }
+    }
+  }
+  // cluster trees and blocks
+  int nb = 0;
+  s.block_base.assign(nfr + 1, 0);
+  for (int p = 0; p < nfr; ++p) {
+    Front& f = s.fronts[p];
+    f.blocks.clear();
+    if (f.nf() > 0 && f.npiv > 0) f.blocks.push_back({0, f.npiv, f.nf(), 0, f.npiv, -1});
+    bisect_tree(0, f.npiv, leaf, 1, f.pp_tree, f.blocks);
+    if (f.nf() > 0) bisect_tree(f.npiv, f.nf(), leaf, 2, f.ff_tree, f.blocks);
+    else f.ff_tree.clear();
+    s.block_base[p] = nb;
+    nb += (int)f.blocks.size();
+  }
+  s.block_base[nfr] = nb;
+  s.nblocks = nb;
+  // assembly map: lower entries in CSR order
+  for (int r = 0; r < n; ++r)
+    for (int k = rowptr[r]; k < rowptr[r + 1]; ++k) {
+      int i = s.iperm[r], j = s.iperm[colind[k]];
+      if (i < j) continue;
+      int p = owner[j];
+      const Front& f = s.fronts[p];
+      int row = i < f.start + f.npiv ? i - f.start
+                : f.npiv + (int)(std::lower_bound(f.upd.begin(), f.upd.end(), i) - f.upd.begin());
+      s.asm_front.push_back(p);
+      s.asm_row.push_back(row);
+      s.asm_col.push_back(j - f.start);
+      s.asm_src.push_back(k);
+    }
+  int hmax = 0;
+  for (auto& f : s.fronts) hmax = std::max(hmax, f.height);
+  s.levels.assign(hmax + 1, {});
+  for (int p = 0; p < nfr; ++p) s.levels[s.fronts[p].height].push_back(p);
+  return "";
+}
+
+// BDLR sets (Sec. 2.2): interaction graph = A restricted to the front's
+// index set I_p u I_p^f (Sec. 4.2.1).  Rows of a block ranked by BFS distance
+// to the block's column cluster, columns by distance to the row cluster.
+void compute_bdlr(Symbolic& s, int depth, int cap) {
+  if (s.bdlr_depth == depth && s.bdlr_cap == cap) return;
+  bdlr_sets(s, depth, cap, s.bdlr_I, s.bdlr_Iptr, s.bdlr_J, s.bdlr_Jptr);
+  s.bdlr_depth = depth;
+  s.bdlr_cap = cap;
+}
+
+void bdlr_sets(const Symbolic& s, int depth, int cap, std::vector<int>& outI, std::vector<int>& outIptr,
+               std::vector<int>& outJ, std::vector<int>& outJptr) {
+  outI.clear(); outJ.clear();
+  outIptr.assign(1, 0); outJptr.assign(1, 0);
+  std::vector<int> pos_of(s.n, -1);
+  std::vector<int> adjp, adj, dist, frontier, nxt;
+  const long long INF = std::numeric_limits<long long>::max();
+  for (const Front& f : s.fronts) {
+    const int m = f.n();
+    for (int a = 0; a < m; ++a) pos_of[f.global(a)] = a;
+    adjp.assign(m + 1, 0);
+    adj.clear();
+    for (int a = 0; a < m; ++a) {
+      int g = f.global(a);
+      for (int k = s.prow[g]; k < s.prow[g + 1]; ++k) {
+        int b = pos_of[s.pcol[k]];
+        if (b >= 0) adj.push_back(b);
+      }
+      adjp[a + 1] = (int)adj.size();
+    }
+    auto bfs = [&](int lo, int cnt) {
+      dist.assign(m, -1);
+      frontier.clear();
+      for (int a = lo; a < lo + cnt; ++a) { dist[a] = 0; frontier.push_back(a); }
+      for (int k = 1;; ++k) {
+        if (depth >= 0 && k > depth) break;
+        nxt.clear();
+        for (int v : frontier)
+          for (int e = adjp[v]; e < adjp[v + 1]; ++e) {
+            int w = adj[e];
+            if (dist[w] < 0) { dist[w] = k; nxt.push_back(w); }
+          }
+        if (nxt.empty()) break;
+        frontier.swap(nxt);
+      }
+    };
+    auto pick = [&](int lo, int cnt, std::vector<int>& out) {
+      std::vector<std::pair<long long, int>> cand;
+      for (int a = lo; a < lo + cnt; ++a) {
+        int d = dist[a];
+        if (depth >= 0) { if (d >= 1 && d <= depth) cand.push_back({d, a}); }
+        else cand.push_back({d < 0 ? INF : (long long)d, a});
+      }
+      std::sort(cand.begin(), cand.end());
+      size_t k = std::min(cand.size(), (size_t)cap);
+      std::vector<int> sel;
+      for (size_t i = 0; i < k; ++i) sel.push_back(cand[i].second);
+      std::sort(sel.begin(), sel.end());
+      out.insert(out.end(), sel.begin(), sel.end());
+    };
+    for (const Block& b : f.blocks) {
+      bfs(b.c0, b.nc);
+      pick(b.r0, b.nr, outI);
+      outIptr.push_back((int)outI.size());
+      bfs(b.r0, b.nr);
+      pick(b.c0, b.nc, outJ);
+      outJptr.push_back((int)outJ.size());
+    }
+    for (int a = 0; a < m; ++a) pos_of[f.global(a)] = -1;
+  }
+}
+
+}  // namespace mfh

@@ -1,0 +1,159 @@
+// Kernel-level test hooks (include/mfh_testing.h): one problem per call,
+// synchronous, on the null stream.
+#include <string>
+
+#include "../../include/mfh_testing.h"
+#include "kernels.h"
+
+namespace {
+thread_local std::string t_err;
+
+mf_status hip_ok(hipError_t e) {
+  if (e == hipSuccess) return MF_OK;
+  t_err = hipGetErrorString(e);
+  return MF_EHIP;
+}
+
+template <typename T>
+mf_status gemm_t(int m, int n, int k, const void* A, int lda, int opA, const void* B, int ldb, int opB, void* C,
+                 int ldc, double alpha, double beta, int flags) {
+  mfh::GemmDesc<T> d{};
+  d.A = static_cast<const T*>(A); d.B = static_cast<const T*>(B); d.C = static_cast<T*>(C);
+  d.m = m; d.n = n; d.k = k; d.lda = lda; d.ldb = ldb; d.ldc = ldc; d.opA = opA; d.opB = opB;
+  d.flags = flags; d.alpha = alpha; d.beta = beta;
+  d.tiles_m = (m + mfh::kTile - 1) / mfh::kTile;
+  d.tile0 = 0;
+  const int tiles = d.tiles_m * ((n + mfh::kTile - 1) / mfh::kTile);
+  mfh::GemmDesc<T>* dd = nullptr;
+  mf_status s = hip_ok(hipMalloc(&dd, sizeof(d)));
+  if (s != MF_OK) return s;
+  hipMemcpy(dd, &d, sizeof(d), hipMemcpyHostToDevice);
+  mfh::launch_gemm<T>(dd, 1, tiles, nullptr);
+  s = hip_ok(hipDeviceSynchronize());
+  hipFree(dd);
+  return s;
+}
+
+template <typename T>
+mf_status potrf_t(int n, void* A, int lda, void* Inv, int ldi, int* status_out) {
+  mfh::PotrfDesc<T> d{};
+  d.A = static_cast<T*>(A); d.lda = lda; d.n = n; d.Inv = static_cast<T*>(Inv); d.ldi = ldi;
+  mfh::PotrfDesc<T>* dd = nullptr;
+  int* st = nullptr;
+  mf_status s = hip_ok(hipMalloc(&dd, sizeof(d)));
+  if (s == MF_OK) s = hip_ok(hipMalloc(&st, sizeof(int)));
+  if (s != MF_OK) return s;
+  hipMemcpy(dd, &d, sizeof(d), hipMemcpyHostToDevice);
+  hipMemset(st, 0, sizeof(int));
+  mfh::launch_potrf<T>(dd, 1, n, st, nullptr);
+  s = hip_ok(hipDeviceSynchronize());
+  if (s == MF_OK && status_out) hipMemcpy(status_out, st, sizeof(int), hipMemcpyDeviceToHost);
+  hipFree(dd);
+  hipFree(st);
+  return s;
+}
+
+template <typename T>
+mf_status skel_t(void* F, int ld, int r0, int nr, int c0, int nc, const int* I, int nI, const int* J, int nJ,
+                 double eps, int adaptive, int cap, void* U, void* V, int* rank_out) {
+  const int kcap = nI < nJ ? nI : nJ;
+  char* scratch = nullptr;
+  const size_t bytes = 4096 + (size_t)(kcap + 1) * (kcap + 1) * sizeof(T) + 8 * (size_t)(kcap + 1) + 1024;
+  mf_status s = hip_ok(hipMalloc(&scratch, bytes));
+  if (s != MF_OK) return s;
+  int* rank1 = reinterpret_cast<int*>(scratch);
+  int* rank = rank1 + 1;
+  int* status = rank1 + 2;
+  double* u11 = reinterpret_cast<double*>(scratch + 64);
+  int* pr = reinterpret_cast<int*>(scratch + 128);
+  int* pc = pr + kcap + 1;
+  T* M = reinterpret_cast<T*>(scratch + 4096);
+  hipMemset(scratch, 0, 128);
+  mfh::SkelDesc<T> sd{};
+  sd.F = static_cast<T*>(F); sd.ld = ld; sd.I = I; sd.nI = nI; sd.J = J; sd.nJ = nJ;
+  sd.piv_r = pr; sd.piv_c = pc; sd.M = M; sd.ldm = kcap > 0 ? kcap : 1; sd.rank = rank1; sd.u11 = u11;
+  mfh::SkelFacDesc<T> fd{};
+  fd.F = static_cast<T*>(F); fd.ld = ld; fd.r0 = r0; fd.nr = nr; fd.c0 = c0; fd.nc = nc;
+  fd.piv_r = pr; fd.piv_c = pc; fd.M = M; fd.ldm = sd.ldm; fd.rank = rank1;
+  fd.U = static_cast<T*>(U); fd.ldu = nr; fd.V = static_cast<T*>(V); fd.ldv = nc;
+  fd.wgU = (nr + 255) / 256; fd.wg0 = 0;
+  const int wgs = fd.wgU + (nc + 255) / 256;
+  mfh::GemmDesc<T> gdsc{};
+  gdsc.A = fd.U; gdsc.lda = nr; gdsc.B = fd.V; gdsc.ldb = nc; gdsc.opB = 1;
+  gdsc.C = static_cast<T*>(F) + r0 + (size_t)c0 * ld; gdsc.ldc = ld;
+  gdsc.m = nr; gdsc.n = nc; gdsc.k = kcap; gdsc.kdev = rank1; gdsc.alpha = -1.0; gdsc.beta = 1.0;
+  gdsc.tiles_m = (nr + 63) / 64;
+  const int gtiles = gdsc.tiles_m * ((nc + 63) / 64);
+  mfh::Phase2Desc<T> pd{};
+  pd.F = static_cast<T*>(F); pd.ld = ld; pd.r0 = r0; pd.nr = nr; pd.c0 = c0; pd.nc = nc;
+  pd.piv_r = pr; pd.piv_c = pc; pd.rank1 = rank1; pd.u11 = u11; pd.U = fd.U; pd.ldu = nr; pd.V = fd.V;
+  pd.ldv = nc; pd.cap = cap; pd.rank = rank;
+  char* dd = nullptr;
+  s = hip_ok(hipMalloc(&dd, 4096));
+  if (s != MF_OK) { hipFree(scratch); return s; }
+  hipMemcpy(dd, &sd, sizeof(sd), hipMemcpyHostToDevice);
+  hipMemcpy(dd + 1024, &fd, sizeof(fd), hipMemcpyHostToDevice);
+  hipMemcpy(dd + 2048, &gdsc, sizeof(gdsc), hipMemcpyHostToDevice);
+  hipMemcpy(dd + 3072, &pd, sizeof(pd), hipMemcpyHostToDevice);
+  const size_t lds = (size_t)nI * nJ * sizeof(T) + 2 * (size_t)kcap * sizeof(int) + nI + nJ + 64;
+  mfh::launch_skel<T>(reinterpret_cast<mfh::SkelDesc<T>*>(dd), 1, lds, eps, nullptr);
+  mfh::launch_skelfac<T>(reinterpret_cast<mfh::SkelFacDesc<T>*>(dd + 1024), 1, wgs, kcap > 0 ? kcap : 1, nullptr);
+  if (adaptive) {
+    mfh::launch_gemm<T>(reinterpret_cast<mfh::GemmDesc<T>*>(dd + 2048), 1, gtiles, nullptr);
+    mfh::launch_phase2<T>(reinterpret_cast<mfh::Phase2Desc<T>*>(dd + 3072), 1, nr + nc, eps, status, nullptr);
+  }
+  s = hip_ok(hipDeviceSynchronize());
+  if (s == MF_OK) hipMemcpy(rank_out, adaptive ? rank : rank1, sizeof(int), hipMemcpyDeviceToHost);
+  hipFree(dd);
+  hipFree(scratch);
+  return s;
+}
+}  // namespace
+
+extern "C" {
+
+mf_status mfh_test_mfma_layout(int32_t precision, int32_t* rows, int32_t* cols, int32_t* assumed) {
+  if (!rows || !cols || !assumed) return MF_EINVAL;
+  int* d = nullptr;
+  mf_status s = hip_ok(hipMalloc(&d, 3 * 256 * sizeof(int)));
+  if (s != MF_OK) return s;
+  if (precision == MF_FP64) mfh::launch_mfma_probe<double>(d, d + 256, d + 512, nullptr);
+  else mfh::launch_mfma_probe<float>(d, d + 256, d + 512, nullptr);
+  s = hip_ok(hipDeviceSynchronize());
+  if (s == MF_OK) {
+    hipMemcpy(rows, d, 256 * sizeof(int), hipMemcpyDeviceToHost);
+    hipMemcpy(cols, d + 256, 256 * sizeof(int), hipMemcpyDeviceToHost);
+    hipMemcpy(assumed, d + 512, 256 * sizeof(int), hipMemcpyDeviceToHost);
+  }
+  hipFree(d);
+  return s;
+}
+
+mf_status mfh_test_gemm(int32_t precision, int32_t m, int32_t n, int32_t k, const void* A, int32_t lda, int32_t opA,
+                        const void* B, int32_t ldb, int32_t opB, void* C, int32_t ldc, double alpha, double beta,
+                        int32_t flags) {
+  if (m < 0 || n < 0 || k < 0 || !C) return MF_EINVAL;
+  if (precision == MF_FP64) return gemm_t<double>(m, n, k, A, lda, opA, B, ldb, opB, C, ldc, alpha, beta, flags);
+  return gemm_t<float>(m, n, k, A, lda, opA, B, ldb, opB, C, ldc, alpha, beta, flags);
+}
+
+mf_status mfh_test_potrf(int32_t precision, int32_t n, void* A, int32_t lda, void* Inv, int32_t ldi,
+                         int32_t* status_out) {
+  if (n < 1 || n > 128 || !A) return MF_EINVAL;
+  if (precision == MF_FP64) return potrf_t<double>(n, A, lda, Inv, ldi, status_out);
+  return potrf_t<float>(n, A, lda, Inv, ldi, status_out);
+}
+
+mf_status mfh_test_skeleton(int32_t precision, void* F, int32_t ld, int32_t r0, int32_t nr, int32_t c0, int32_t nc,
+                            const int32_t* I, int32_t nI, const int32_t* J, int32_t nJ, double eps, int32_t adaptive,
+                            int32_t cap, void* U, void* V, int32_t* rank_out) {
+  const int maxset = precision == MF_FP64 ? 126 : 180;
+  if (nr < 1 || nc < 1 || nI < 0 || nJ < 0 || nI > maxset || nJ > maxset || nI > nr || nJ > nc || cap < 1 ||
+      nr + nc > 160 * 1024 || cap < (nI < nJ ? nI : nJ) || !F || !U || !V || !rank_out)
+    return MF_EINVAL;
+  if (precision == MF_FP64)
+    return skel_t<double>(F, ld, r0, nr, c0, nc, I, nI, J, nJ, eps, adaptive, cap, U, V, rank_out);
+  return skel_t<float>(F, ld, r0, nr, c0, nc, I, nI, J, nJ, eps, adaptive, cap, U, V, rank_out);
+}
+
+}  // extern "C"

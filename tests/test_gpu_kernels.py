@@ -1,0 +1,178 @@
+"""Kernel-level parity on the GPU: grouped MFMA GEMM, LDS Cholesky + inverse,
+and the skeleton compression against plain float64 references / the
+oracle."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from oracle import hodlr
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(np_colmajor: np.ndarray, ld: int, dtype):
+    """Upload a (rows x cols) matrix as column-major with leading dim ld."""
+    import torch
+    rows, cols = np_colmajor.shape
+    buf = np.zeros((cols, ld), dtype=np.float64)
+    buf[:, :rows] = np_colmajor.T
+    return torch.tensor(buf, dtype=dtype, device="cuda")
+
+
+def _host(t, rows):
+    return t.double().cpu().numpy()[:, :rows].T.copy()
+
+
+def _p(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_mfma_accumulator_layout(gpu_lib, prec):
+    """Each lane's four accumulator values of the 16x16x4 MFMA land on the
+    rows the GEMM epilogue writes them to."""
+    rows = (ctypes.c_int32 * 256)()
+    cols = (ctypes.c_int32 * 256)()
+    assumed = (ctypes.c_int32 * 256)()
+    assert gpu_lib.load().mfh_test_mfma_layout(prec, rows, cols, assumed) == 0
+    r, c, a = np.array(rows), np.array(cols), np.array(assumed)
+    print("prec", prec, "rows", r.reshape(64, 4)[::16].tolist(), "cols", c.reshape(64, 4)[::16].tolist(), flush=True)
+    lane = np.repeat(np.arange(64), 4)
+    assert np.array_equal(c, lane % 16)
+    assert np.array_equal(r, a), (r.reshape(64, 4).tolist())
+
+
+GEMM_CASES = [
+    (1, 1, 1, 0, 0, 0), (64, 64, 64, 0, 0, 0), (100, 37, 70, 0, 1, 0), (130, 1, 257, 1, 0, 0),
+    (5, 200, 3, 1, 1, 0), (129, 129, 65, 0, 1, 1), (96, 20, 96, 0, 0, 2), (96, 20, 96, 1, 0, 4),
+    (50, 70, 70, 0, 1, 16), (50, 70, 70, 0, 0, 8), (77, 77, 0, 0, 0, 0),
+]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("m,n,k,opA,opB,flags", GEMM_CASES)
+def test_gemm(gpu_lib, prec, m, n, k, opA, opB, flags):
+    import torch
+    mfh = gpu_lib
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    rng = np.random.default_rng(m * 1000 + n * 10 + k)
+    Aop = rng.standard_normal((m, k))
+    Bop = rng.standard_normal((k, n))
+    if flags & 2:
+        Aop = np.tril(Aop)
+    if flags & 4:
+        Aop = np.triu(Aop)
+    if flags & 8:
+        Bop = np.tril(Bop)
+    if flags & 16:
+        Bop = np.triu(Bop)
+    C0 = rng.standard_normal((m, n))
+    A = Aop.T.copy() if opA else Aop
+    B = Bop.T.copy() if opB else Bop
+    lda, ldb, ldc = A.shape[0] + 3, B.shape[0] + 1, m + 5
+    dA, dB, dC = _dev(A, lda, dt), _dev(B, ldb, dt), _dev(C0, ldc, dt)
+    alpha, beta = -0.75, 0.5
+    st = mfh.load().mfh_test_gemm(0 if prec == "fp64" else 1, m, n, k, _p(dA), lda, opA, _p(dB), ldb, opB, _p(dC),
+                                  ldc, alpha, beta, flags)
+    assert st == 0
+    # float64 reference from the same (rounded) inputs
+    cast = np.float32 if prec == "fp32" else np.float64
+    Ar = A.astype(cast).astype(np.float64)
+    Br = B.astype(cast).astype(np.float64)
+    C0r = C0.astype(cast).astype(np.float64)
+    ref = alpha * (Ar.T if opA else Ar) @ (Br.T if opB else Br) + beta * C0r
+    st_sync = torch.cuda.synchronize()
+    out = _host(dC, m)
+    if flags & 1:
+        mask = np.tril(np.ones((m, n), dtype=bool))
+        ref = np.where(mask, ref, C0r)
+    tol = 1e-13 if prec == "fp64" else 2e-5
+    scale = max(1.0, np.sqrt(k))
+    assert np.abs(out - ref).max() <= tol * scale * max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("n", [1, 7, 64, 100, 128])
+def test_potrf_inverse(gpu_lib, prec, n):
+    import torch
+    mfh = gpu_lib
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    rng = np.random.default_rng(n)
+    X = rng.standard_normal((n, n))
+    S = X @ X.T + n * np.eye(n)
+    ld = n + 2
+    dA = _dev(S, ld, dt)
+    dI = _dev(np.zeros((n, n)), n, dt)
+    status = ctypes.c_int32(-1)
+    assert mfh.load().mfh_test_potrf(0 if prec == "fp64" else 1, n, _p(dA), ld, _p(dI), n, ctypes.byref(status)) == 0
+    assert status.value == 0
+    L = np.tril(_host(dA, n))
+    Lref = np.linalg.cholesky(S)
+    tol = 1e-12 if prec == "fp64" else 1e-4
+    assert np.abs(L - Lref).max() <= tol * np.abs(Lref).max()
+    Inv = _host(dI, n)
+    assert np.abs(np.triu(Inv, 1)).max() == 0.0
+    assert np.abs(Inv @ Lref - np.eye(n)).max() <= tol * 10
+
+
+def test_potrf_flags_non_spd(gpu_lib):
+    import torch
+    n = 10
+    S = -np.eye(n)
+    dA = _dev(S, n, torch.float64)
+    dI = _dev(np.zeros((n, n)), n, torch.float64)
+    status = ctypes.c_int32(0)
+    assert gpu_lib.load().mfh_test_potrf(0, n, _p(dA), n, _p(dI), n, ctypes.byref(status)) == 0
+    assert status.value & 1
+
+
+def _kernel_matrix(m, n, seed, gap):
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(0, 1, (m, 2)) + np.array([1.0 + gap, 0.0])
+    y = rng.uniform(0, 1, (n, 2))
+    return -np.log(np.linalg.norm(x[:, None, :] - y[None, :, :], axis=2))
+
+
+@pytest.mark.parametrize("adaptive", [0, 1])
+@pytest.mark.parametrize("nr,nc,nI,nJ,eps", [(40, 30, 40, 30, 1e-6), (120, 90, 20, 15, 1e-5), (300, 200, 60, 50, 1e-8),
+                                              (33, 47, 1, 1, 1e-4), (16, 16, 16, 16, 0.0)])
+def test_skeleton_fp64_matches_oracle(gpu_lib, adaptive, nr, nc, nI, nJ, eps):
+    """Same pivots, rank and factors as the float64 oracle (Eq. Bhat plus the
+    adaptive full-block phase)."""
+    import torch
+    mfh = gpu_lib
+    B = _kernel_matrix(nr, nc, nr + nc, 0.4)
+    # embed the block at (r0, c0) of a larger column-major buffer
+    r0, c0, ld = 7, 3, nr + 20
+    F = np.zeros((ld, c0 + nc + 2))
+    F[r0:r0 + nr, c0:c0 + nc] = B
+    dF = _dev(F, ld, torch.float64)
+    rng = np.random.default_rng(1)
+    I = np.sort(rng.choice(nr, nI, replace=False))
+    J = np.sort(rng.choice(nc, nJ, replace=False))
+    dIa = torch.tensor((I + r0).astype(np.int32), device="cuda")
+    dJa = torch.tensor((J + c0).astype(np.int32), device="cuda")
+    cap = min(nr, nc)
+    dU = torch.zeros((cap, nr), dtype=torch.float64, device="cuda")
+    dV = torch.zeros((cap, nc), dtype=torch.float64, device="cuda")
+    rank = ctypes.c_int32(-1)
+    st = mfh.load().mfh_test_skeleton(0, _p(dF), ld, r0, nr, c0, nc, _p(dIa), nI, _p(dJa), nJ, eps, adaptive, cap,
+                                      _p(dU), _p(dV), ctypes.byref(rank))
+    assert st == 0
+    ref = hodlr.skeleton(B, I, J, eps, adaptive=bool(adaptive))
+    assert rank.value == ref.rank
+    r = ref.rank
+    U = dU.cpu().numpy()[:r].T
+    V = dV.cpu().numpy()[:r].T
+    # individual factor columns are divided by the pivots: rounding is
+    # amplified by up to 1/|smallest pivot ratio|, which eps bounds from below;
+    # the product U V^T is far better conditioned
+    amp = 1.0 / max(eps, 1e-14)
+    bmax = np.abs(B).max()
+    assert np.abs(U @ V.T - ref.U @ ref.V.T).max() <= 1e-13 * max(1.0, np.sqrt(amp)) * bmax
+    assert np.abs(U - ref.U).max() <= 1e-15 * amp * max(1.0, np.abs(ref.U).max()) * 100
+    assert np.abs(V - ref.V).max() <= 1e-15 * amp * max(1.0, np.abs(ref.V).max()) * 100
+    if adaptive and eps > 0:
+        E = B - U @ V.T
+        assert np.abs(E).max() < eps * np.abs(B).max() / (1 - 2.0 ** -20) * (1 + 1e-9)

@@ -1,0 +1,153 @@
+"""End-to-end parity of the GPU path (through the C ABI) with the float64
+oracle: dense-front and HODLR factor, preconditioner apply, GMRES."""
+import numpy as np
+import pytest
+
+from mfinputs import q1_grid, p1_kuhn_cube, rhs, make_workload
+from oracle import symbolic, dense_mf, hodlr_mf
+
+pytestmark = pytest.mark.gpu
+
+
+def _to_dev(B):
+    import torch
+    return torch.tensor(np.ascontiguousarray(B.T), dtype=torch.float64, device="cuda")
+
+
+def _to_host(t):
+    return t.cpu().numpy().T.copy()
+
+
+SMALL = [
+    ("q1_2d_64_leaf64", lambda: q1_grid(64, 2), 64),
+    ("q1_3d_12_leaf32", lambda: q1_grid(12, 3), 32),
+    ("p1kuhn_8_leaf32", lambda: p1_kuhn_cube(8, 0.2, 3), 32),
+]
+
+
+@pytest.mark.parametrize("name,maker,leaf", SMALL)
+def test_dense_fp64_apply_matches_oracle(gpu_lib, name, maker, leaf):
+    mfh = gpu_lib
+    p = maker()
+    print(f"case {name} n={p.A.n}", flush=True)
+    sym = mfh.Symbolic.from_csr(p.A, p.coords, leaf)
+    f = mfh.Factor(sym, p.A.vals, 0.0, method="dense", precision="fp64")
+    b = rhs(p.A.n, 3, "normal", 11)
+    z = _to_dev(np.zeros_like(b))
+    f.apply(_to_dev(b), z)
+    ref_sym = symbolic.analyze(p.A, p.coords, leaf)
+    zr = dense_mf.solve(dense_mf.factor(ref_sym, p.A.vals), b)
+    zg = _to_host(z)
+    assert np.abs(zg - zr).max() <= 1e-12 * np.abs(zr).max() * 10
+    info = f.info()
+    assert info["dense_fronts"] == ref_sym.nfronts and info["status_bits"] == 0
+
+
+@pytest.mark.parametrize("name,maker,leaf", SMALL[:2])
+def test_dense_gmres_one_iteration(gpu_lib, name, maker, leaf):
+    mfh = gpu_lib
+    p = maker()
+    sym = mfh.Symbolic.from_csr(p.A, p.coords, leaf)
+    f = mfh.Factor(sym, p.A.vals, 0.0, method="dense", precision="fp64")
+    b = rhs(p.A.n, 2, "uniform", 5)
+    x = _to_dev(np.zeros_like(b))
+    infos = f.gmres(_to_dev(b), x, tol=1e-10)
+    assert all(i["converged"] and i["iters"] == 1 for i in infos), infos
+    xr = np.linalg.solve(p.A.to_dense(), b)
+    assert np.abs(_to_host(x) - xr).max() <= 1e-10 * np.abs(xr).max()
+
+
+HODLR_FP64 = [
+    ("q1_2d_64_leaf64_eps1e-6", lambda: q1_grid(64, 2), 64, 1e-6, 4, 64),
+    ("q1_2d_30_leaf8_eps1e-4", lambda: q1_grid(30, 2), 8, 1e-4, 2, 16),
+    ("q1_3d_12_leaf32_eps1e-4", lambda: q1_grid(12, 3), 32, 1e-4, 4, 64),
+    ("p1kuhn_8_leaf32_eps1e-5", lambda: p1_kuhn_cube(8, 0.2, 3), 32, 1e-5, 3, 48),
+]
+
+
+@pytest.mark.parametrize("name,maker,leaf,eps,depth,cap", HODLR_FP64)
+def test_hodlr_fp64_matches_oracle(gpu_lib, name, maker, leaf, eps, depth, cap):
+    """Same ranks per block and the same preconditioner output as the float64
+    oracle running the same algorithm (BDLR + adaptive skeleton, SMW)."""
+    mfh = gpu_lib
+    p = maker()
+    print(f"case {name} n={p.A.n}", flush=True)
+    sym = mfh.Symbolic.from_csr(p.A, p.coords, leaf)
+    f = mfh.Factor(sym, p.A.vals, eps, method="hodlr", precision="fp64", bdlr_depth=depth, bdlr_cap=cap, n_c=0)
+    ref_sym = symbolic.analyze(p.A, p.coords, leaf)
+    opts = hodlr_mf.Options(eps=eps, depth=depth, cap=cap, n_c=0)
+    hf = hodlr_mf.factor(ref_sym, p.A.vals, opts)
+    ref_ranks = np.concatenate([np.asarray(ff.ranks, dtype=np.int64) for ff in hf.fronts])
+    ranks = f.ranks()
+    assert np.array_equal(ranks, ref_ranks)
+    b = rhs(p.A.n, 2, "normal", 3)
+    z = _to_dev(np.zeros_like(b))
+    f.apply(_to_dev(b), z)
+    zr = hodlr_mf.solve(hf, b)
+    assert np.abs(_to_host(z) - zr).max() <= 1e-9 * np.abs(zr).max()
+
+
+@pytest.mark.parametrize("name,maker,leaf", [("q1_2d_24_leaf16", lambda: q1_grid(24, 2), 16),
+                                             ("q1_3d_8_leaf32", lambda: q1_grid(8, 3), 32)])
+def test_hodlr_eps0_equals_dense(gpu_lib, name, maker, leaf):
+    mfh = gpu_lib
+    p = maker()
+    sym = mfh.Symbolic.from_csr(p.A, p.coords, leaf)
+    f = mfh.Factor(sym, p.A.vals, 0.0, method="hodlr", precision="fp64", bdlr_depth=-1, bdlr_cap=126, n_c=0)
+    b = rhs(p.A.n, 2, "normal", 9)
+    z = _to_dev(np.zeros_like(b))
+    f.apply(_to_dev(b), z)
+    xr = np.linalg.solve(p.A.to_dense(), b)
+    assert np.abs(_to_host(z) - xr).max() <= 1e-10 * np.abs(xr).max()
+
+
+@pytest.mark.parametrize("name,maker,leaf,eps", [("q1_3d_16_leaf32", lambda: q1_grid(16, 3), 32, 1e-4),
+                                                 ("p1kuhn_12_leaf64", lambda: p1_kuhn_cube(12, 0.2, 5), 64, 1e-4)])
+def test_hodlr_fp32_gmres_reaches_oracle_solution(gpu_lib, name, maker, leaf, eps):
+    mfh = gpu_lib
+    p = maker()
+    print(f"case {name} n={p.A.n}", flush=True)
+    sym = mfh.Symbolic.from_csr(p.A, p.coords, leaf)
+    f = mfh.Factor(sym, p.A.vals, eps, method="hodlr", precision="fp32", n_c=0)
+    b = rhs(p.A.n, 4, "normal", 1)
+    x = _to_dev(np.zeros_like(b))
+    infos = f.gmres(_to_dev(b), x, tol=1e-10)
+    assert all(i["converged"] for i in infos), infos
+    xg = _to_host(x)
+    S = p.A.to_scipy()
+    for k in range(b.shape[1]):
+        assert np.linalg.norm(b[:, k] - S @ xg[:, k]) <= 1e-10 * np.linalg.norm(b[:, k])
+    ref_sym = symbolic.analyze(p.A, p.coords, leaf)
+    xr = dense_mf.solve(dense_mf.factor(ref_sym, p.A.vals), b)
+    assert np.linalg.norm(xg - xr) <= 1e-8 * np.linalg.norm(xr)
+
+
+def test_full_size_poisson3d_32_sixteen_rhs(gpu_lib):
+    """3D Q1 Poisson 32^3, FP32 HODLR factor, eps 1e-4, leaf 128, 16 RHS."""
+    mfh = gpu_lib
+    w = make_workload("poisson3d_q1_32")
+    p = w.problem
+    sym = mfh.Symbolic.from_csr(p.A, p.coords, w.leaf)
+    f = mfh.Factor(sym, p.A.vals, w.eps, method="hodlr", precision="fp32", n_c=512)
+    x = _to_dev(np.zeros_like(w.b))
+    infos = f.gmres(_to_dev(w.b), x, tol=w.tol)
+    print("iters", [i["iters"] for i in infos], f.info(), flush=True)
+    assert all(i["converged"] for i in infos)
+    xg = _to_host(x)
+    S = p.A.to_scipy()
+    res = np.linalg.norm(w.b - S @ xg, axis=0) / np.linalg.norm(w.b, axis=0)
+    assert res.max() <= 1e-10
+    # sampled columns against the oracle's exact multifrontal solve
+    ref_sym = symbolic.analyze(p.A, p.coords, w.leaf)
+    cols = [0, 15]
+    xr = dense_mf.solve(dense_mf.factor(ref_sym, p.A.vals), w.b[:, cols])
+    assert np.linalg.norm(xg[:, cols] - xr) <= 1e-8 * np.linalg.norm(xr)
+
+
+def test_not_spd_reports_error(gpu_lib):
+    mfh = gpu_lib
+    p = q1_grid(10, 2)
+    sym = mfh.Symbolic.from_csr(p.A, p.coords, 16)
+    with pytest.raises(mfh.MfError) as e:
+        mfh.Factor(sym, -p.A.vals, 0.0, method="dense", precision="fp64")
+    assert e.value.status == mfh.MF_ENOTSPD

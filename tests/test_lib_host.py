@@ -1,0 +1,150 @@
+"""Host-side tests of the native library (no GPU needed): the C ABI loads and
+exports every declared entry point; the C++ symbolic analysis agrees bit for
+bit with the oracle; malformed inputs are rejected."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1410_2697_amd as mfh
+from mfinputs import q1_grid, p1_kuhn_cube
+from oracle import symbolic
+
+INCLUDE = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include")
+
+
+def declared_functions():
+    names = set()
+    for h in os.listdir(INCLUDE):
+        if not h.endswith(".h"):
+            continue
+        src = open(os.path.join(INCLUDE, h)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names |= set(re.findall(r"\b(?:mf_status|void|const char\s*\*)\s*(\w+)\s*\(", src))
+    return sorted(names)
+
+
+def test_exports_every_declared_symbol():
+    lib = mfh.load()
+    names = declared_functions()
+    assert "mf_analyze" in names and "gmres_solve" in names and "mf_apply" in names and "mf_factor" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    # and the binding declares them all
+    assert set(names) == {s[0] for s in mfh.SIGNATURES}
+
+
+CASES = [
+    ("q1_2d_64_leaf64", lambda: q1_grid(64, 2), 64),
+    ("q1_2d_20_leaf8", lambda: q1_grid(20, 2), 8),
+    ("q1_3d_16_leaf128", lambda: q1_grid(16, 3), 128),
+    ("q1_3d_11_leaf24", lambda: q1_grid(11, 3), 24),
+    ("p1kuhn_9_leaf40", lambda: p1_kuhn_cube(9, 0.2, 7), 40),
+]
+
+
+@pytest.mark.parametrize("name,maker,leaf", CASES)
+def test_symbolic_bit_exact(name, maker, leaf):
+    p = maker()
+    ref = symbolic.analyze(p.A, p.coords, leaf)
+    s = mfh.Symbolic.from_csr(p.A, p.coords, leaf)
+    assert np.array_equal(s.export(mfh.MF_EXP_PERM), ref.perm)
+    fr = s.export(mfh.MF_EXP_FRONT).reshape(-1, 6)
+    assert fr.shape[0] == ref.nfronts
+    want = np.array([[f.start, f.npiv, f.nf, f.parent, f.height, len(f.children)] for f in ref.fronts])
+    assert np.array_equal(fr, want)
+    upd = s.export(mfh.MF_EXP_UPD)
+    assert np.array_equal(upd, np.concatenate([f.upd for f in ref.fronts]))
+    rm = s.export(mfh.MF_EXP_RELMAP)
+    ref_rm = np.concatenate([f.relmap if f.relmap is not None else -np.ones(f.nf, dtype=np.int64)
+                             for f in ref.fronts])
+    assert np.array_equal(rm, ref_rm)
+    asm = s.export(mfh.MF_EXP_ASM).reshape(-1, 4)
+    assert np.array_equal(asm, np.stack([ref.asm_front, ref.asm_row, ref.asm_col, ref.asm_src], axis=1))
+    blk = s.export(mfh.MF_EXP_BLOCKS).reshape(-1, 7)
+    kinds = {"top": 0, "pp": 1, "ff": 2}
+    want_b = np.array([[q, kinds[b.kind], b.r0, b.nr, b.c0, b.nc, b.level]
+                       for q, f in enumerate(ref.fronts) for b in f.blocks])
+    assert np.array_equal(blk, want_b)
+    info = s.info()
+    assert info["nfronts"] == ref.nfronts and info["nlevels"] == len(ref.levels)
+
+
+@pytest.mark.parametrize("name,maker,leaf", CASES[1:])
+@pytest.mark.parametrize("depth,cap", [(1, 1000), (3, 17), (-1, 40)])
+def test_bdlr_sets_bit_exact(name, maker, leaf, depth, cap):
+    p = maker()
+    ref = symbolic.analyze(p.A, p.coords, leaf)
+    s = mfh.Symbolic.from_csr(p.A, p.coords, leaf)
+    s.bdlr(depth, cap)
+    I, Ip = s.export(mfh.MF_EXP_BDLR_I), s.export(mfh.MF_EXP_BDLR_IPTR)
+    J, Jp = s.export(mfh.MF_EXP_BDLR_J), s.export(mfh.MF_EXP_BDLR_JPTR)
+    g = 0
+    for f in ref.fronts:
+        for b in f.blocks:
+            ri, rj = symbolic.bdlr_sets(ref, f, b, depth, cap)
+            assert np.array_equal(I[Ip[g]:Ip[g + 1]], ri)
+            assert np.array_equal(J[Jp[g]:Jp[g + 1]], rj)
+            g += 1
+    assert g == Ip.shape[0] - 1
+
+
+def test_symbolic_full_size_3d_32():
+    p = q1_grid(32, 3)
+    ref = symbolic.analyze(p.A, p.coords, 128)
+    s = mfh.Symbolic.from_csr(p.A, p.coords, 128)
+    assert np.array_equal(s.export(mfh.MF_EXP_PERM), ref.perm)
+    assert np.array_equal(s.export(mfh.MF_EXP_UPD), np.concatenate([f.upd for f in ref.fronts]))
+
+
+def test_malformed_csr_rejected():
+    p = q1_grid(4, 2)
+    rp, ci = p.A.rowptr.copy(), p.A.colind.copy()
+    bad = ci.copy()
+    bad[0], bad[1] = bad[1], bad[0]                    # unsorted row
+    with pytest.raises(mfh.MfError) as e:
+        mfh.Symbolic(p.A.n, rp, bad, p.coords, 4)
+    assert e.value.status == mfh.MF_EINVAL
+    bad = ci.copy()
+    bad[3] = 99                                        # out of range
+    with pytest.raises(mfh.MfError):
+        mfh.Symbolic(p.A.n, rp, bad, p.coords, 4)
+    # asymmetric pattern: drop one off-diagonal entry of row 0
+    k = int(np.flatnonzero(ci[rp[0]:rp[1]] == 1)[0])
+    ci2 = np.delete(ci, k)
+    rp2 = rp.copy()
+    rp2[1:] -= 1
+    with pytest.raises(mfh.MfError):
+        mfh.Symbolic(p.A.n, rp2, ci2, p.coords, 4)
+    with pytest.raises(mfh.MfError):
+        mfh.Symbolic(p.A.n, rp, ci, p.coords, 0)       # leaf 0
+
+
+def test_factor_without_gpu_is_a_clean_error():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    p = q1_grid(6, 2)
+    s = mfh.Symbolic.from_csr(p.A, p.coords, 8)
+    lib = mfh.load()
+    o = mfh.default_opts()
+    h = ctypes.c_void_p()
+    st = lib.mf_factor(s.h, mfh._ptr(p.A.vals), 1e-4, 0, ctypes.byref(o), ctypes.byref(h))
+    assert st == mfh.MF_ESTATE
+    assert b"no HIP device" in lib.mf_last_error()
+
+
+def test_option_validation():
+    p = q1_grid(6, 2)
+    s = mfh.Symbolic.from_csr(p.A, p.coords, 8)
+    lib = mfh.load()
+    h = ctypes.c_void_p()
+    for kw, eps in [({"precision": 7}, 1e-4), ({"method": 9}, 1e-4), ({}, -1.0), ({"bdlr_cap": 0}, 1e-4),
+                    ({"bdlr_cap": 500}, 1e-4)]:
+        o = mfh.default_opts(**kw)
+        st = lib.mf_factor(s.h, mfh._ptr(p.A.vals), eps, 0, ctypes.byref(o), ctypes.byref(h))
+        assert st == mfh.MF_EINVAL, (kw, eps)
+    o = mfh.default_opts()
+    assert lib.mf_factor(s.h, mfh._ptr(p.A.vals), 1e-4, 5, ctypes.byref(o), ctypes.byref(h)) == mfh.MF_EINVAL
