@@ -15,11 +15,12 @@ Compression (Sec. 2.2):
   pivot with |u_{r+1,r+1} / u_11| < eps.  Then C~ = (B Q)(:, 1:r) U_r^{-1}
   and R~ = L_r^{-1} (P B)(1:r, :), and B ~= C~ R~; we store U = C~, V = R~^T.
   (The paper calls the U_r solve lower-triangular; U_r is upper-triangular.)
-  Pivot choice: the entry of largest magnitude; entries within a relative
-  2^-20 of the largest count as tied and the lowest column, then the lowest
-  row (block positions) wins.  This makes the choice reproducible across
-  implementations whose rounding differs, and costs at most that factor in
-  pivot size.
+  Pivot choice: the entry of largest magnitude, with magnitudes compared
+  after truncation to 20 mantissa bits (the float64 bit pattern of |v| with
+  its low 32 bits cleared); entries equal after truncation are tied and the
+  lowest column, then the lowest row (block positions) wins.  The chosen
+  pivot is within a factor (1 - 2^-20) of the largest entry, and the choice
+  is reproducible across implementations whose rounding differs.
 * ``svd``: truncated SVD, rank r = number of singular values >= eps * s_1
   (so ||B - U V^T||_2 = s_{r+1} < eps s_1).
 
@@ -57,6 +58,19 @@ def _stop(piv: float, eps: float, u11: float) -> bool:
     return abs(piv) < max(eps, NOISE_REL) * u11
 
 
+def _pick_pivot(W: np.ndarray, live_r: np.ndarray, live_c: np.ndarray):
+    """(row, col) of the complete-pivoting choice among live entries, or None
+    when every live entry is zero."""
+    q = np.abs(W).view(np.int64) & ~np.int64(0xFFFFFFFF)   # |v| truncated to 20 mantissa bits
+    q = np.where(live_r[:, None] & live_c[None, :], q, -1)
+    qmax = q.max() if q.size else -1
+    if qmax <= 0:
+        return None
+    cand = np.argwhere(q == qmax)
+    k = np.lexsort((cand[:, 0], cand[:, 1]))[0]               # lowest column, then row
+    return int(cand[k, 0]), int(cand[k, 1])
+
+
 @dataclasses.dataclass
 class LowRank:
     U: np.ndarray
@@ -78,15 +92,10 @@ def complete_pivot_lu(Bh: np.ndarray, eps: float):
     rows, cols, lcols, urows = [], [], [], []
     u11 = None
     for _ in range(min(m, n)):
-        A = np.abs(W)
-        A[~live_r, :] = -1.0
-        A[:, ~live_c] = -1.0
-        mx = A.max()
-        if not mx > 0.0:
+        pick = _pick_pivot(W, live_r, live_c)
+        if pick is None:
             break
-        cand = np.argwhere(A >= (1.0 - TIE_REL) * mx)       # (row, col) pairs
-        k = np.lexsort((cand[:, 0], cand[:, 1]))[0]          # lowest col, then row
-        i, j = int(cand[k, 0]), int(cand[k, 1])
+        i, j = pick
         piv = W[i, j]
         if u11 is None:
             u11 = abs(piv)
@@ -160,15 +169,10 @@ def skeleton(B: np.ndarray, I: np.ndarray, J: np.ndarray, eps: float,
         live_c[Jr] = False
         cols_add, rows_add, ir_add, jc_add = [], [], [], []
         while live_r.any() and live_c.any():
-            A = np.abs(E)
-            A[~live_r, :] = -1.0
-            A[:, ~live_c] = -1.0
-            mx = A.max()
-            if not mx > 0.0:
+            pick = _pick_pivot(E, live_r, live_c)
+            if pick is None:
                 break
-            cand = np.argwhere(A >= (1.0 - TIE_REL) * mx)
-            k = np.lexsort((cand[:, 0], cand[:, 1]))[0]
-            i, j = int(cand[k, 0]), int(cand[k, 1])
+            i, j = pick
             piv = E[i, j]
             if u11 is None:
                 u11 = abs(piv)
