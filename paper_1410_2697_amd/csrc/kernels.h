@@ -49,19 +49,28 @@ struct PotrfDesc {
   int lda, ldi, n, pad;
 };
 
-// Phase 1 of the BDLR skeleton (Eq. Bhat): complete-pivot LU of
-// B_hat = F(I, J) held in LDS.
+// Register-resident skeleton (one 1024-thread workgroup per block).
+//  whole-block mode: the block F(r0:r0+nr, c0:c0+nc) lives in registers;
+//    complete pivoting is first confined to the BDLR rows/columns I x J
+//    (phase 1), then, if `adaptive`, runs over the whole block (phase 2);
+//    every pivot appends a column to U and V (phase 1: U = E(:,b)/piv,
+//    V = E(a,:)^T; phase 2: U = E(:,b), V = E(a,:)^T/piv).
+//  submatrix mode: the block is B_hat = F(I, J); phase 1 only; outputs the
+//    in-place LU in pivot order (M) and the pivots, for SkelFacDesc.
 template <typename T>
-struct SkelDesc {
+struct SkRegDesc {
   const T* F;
   const int* I;
   const int* J;
-  int* piv_r;        // out, front positions, capacity min(nI, nJ)
+  int* piv_r;        // front positions, capacity cap
   int* piv_c;
-  T* M;              // out: r x r LU (unit-lower L below, U on/above), ld = ldm
-  int* rank;         // out: phase-1 rank
-  double* u11;       // out: |u_11| (0 if none)
-  int ld, nI, nJ, ldm;
+  T* M;              // submatrix mode: r x r LU, ld = ldm
+  T* U;              // whole-block mode: nr x cap, ld ldu
+  T* V;              // whole-block mode: nc x cap, ld ldv
+  int* rank1;        // phase-1 rank
+  int* rank;         // final rank
+  double* u11;
+  int ld, r0, nr, c0, nc, nI, nJ, ldm, ldu, ldv, cap, pad;
 };
 
 // C~ = B(:, J_r) U_r^{-1} (rows of U) and R~^T = (L_r^{-1} B(I_r, :))^T
@@ -159,8 +168,18 @@ template <typename T>
 void launch_gemm(const GemmDesc<T>* d, int ndesc, int tiles, hipStream_t st);
 template <typename T>
 void launch_potrf(const PotrfDesc<T>* d, int ndesc, int nmax, int* status, hipStream_t st);
+// whole-block register skeleton: blocks up to skreg_full_rows<T>() x skreg_full_cols<T>()
 template <typename T>
-void launch_skel(const SkelDesc<T>* d, int ndesc, size_t lds_bytes, double eps, hipStream_t st);
+void launch_skreg_full(const SkRegDesc<T>* d, int ndesc, double eps, int adaptive, int* status, hipStream_t st);
+// submatrix register skeleton (phase 1 on B_hat): |I|, |J| up to skreg_hat_max<T>()
+template <typename T>
+void launch_skreg_hat(const SkRegDesc<T>* d, int ndesc, double eps, int* status, hipStream_t st);
+template <typename T>
+constexpr int skreg_full_rows() { return sizeof(T) == 8 ? 128 : 256; }
+template <typename T>
+constexpr int skreg_full_cols() { return 256; }
+template <typename T>
+constexpr int skreg_hat_max() { return sizeof(T) == 8 ? 128 : 192; }
 template <typename T>
 void launch_skelfac(const SkelFacDesc<T>* d, int ndesc, int wgs, int rmax, hipStream_t st);
 template <typename T>

@@ -200,120 +200,273 @@ __global__ void mfma_probe_kernel(int* rows, int* cols, int* assumed) {
 }
 
 // ------------------------------------------------------- small Cholesky ----
+// Right-looking Cholesky of the lower triangle held in LDS, then the
+// triangular inverse in place, one column at a time from the right:
+// X(i, j) = -X(j, j) * sum_{k=j+1..i} X(i, k) L(k, j).
 template <typename T, int NMAX>
 __global__ __launch_bounds__(256) void potrf_kernel(const PotrfDesc<T>* __restrict__ descs, int* status) {
-  __shared__ T S[NMAX * NMAX];
+  constexpr int LD = NMAX + 1;
+  __shared__ T S[NMAX * LD];
   const PotrfDesc<T> d = descs[blockIdx.x];
   const int n = d.n, tid = threadIdx.x, nt = blockDim.x;
-  for (int idx = tid; idx < n * n; idx += nt) {
-    const int i = idx % n, j = idx / n;
-    S[idx] = i >= j ? d.A[i + (size_t)j * d.lda] : (T)0;
-  }
+  for (int j = tid >> 6; j < n; j += nt >> 6)
+    for (int i = tid & 63; i < n; i += 64) S[i + j * LD] = i >= j ? d.A[i + (size_t)j * d.lda] : (T)0;
   __syncthreads();
   for (int j = 0; j < n; ++j) {
-    T djj = S[j + j * n];
+    T djj = S[j + j * LD];
     const bool bad = !(djj > (T)0);
     if (bad) djj = (T)1;
     const T ljj = sqrt(djj);
     __syncthreads();
     if (tid == 0) {
-      S[j + j * n] = ljj;
+      S[j + j * LD] = ljj;
       if (bad) atomicOr(status, 1);
     }
-    for (int i = j + 1 + tid; i < n; i += nt) S[i + j * n] /= ljj;
+    const T rinv = (T)1 / ljj;
+    for (int i = j + 1 + tid; i < n; i += nt) S[i + j * LD] *= rinv;
     __syncthreads();
-    const int mm = n - j - 1;
-    for (int idx = tid; idx < mm * mm; idx += nt) {
-      const int ii = idx % mm, kk = idx / mm;
-      if (ii >= kk) S[(j + 1 + ii) + (j + 1 + kk) * n] -= S[(j + 1 + ii) + j * n] * S[(j + 1 + kk) + j * n];
+    for (int c = j + 1 + (tid >> 5); c < n; c += nt >> 5) {
+      const T lc = S[c + j * LD];
+      for (int r = c + (tid & 31); r < n; r += 32) S[r + c * LD] -= S[r + j * LD] * lc;
     }
     __syncthreads();
   }
-  for (int idx = tid; idx < n * n; idx += nt) {
-    const int i = idx % n, j = idx / n;
-    if (i >= j) d.A[i + (size_t)j * d.lda] = S[idx];
+  for (int j = tid >> 6; j < n; j += nt >> 6)
+    for (int i = j + (tid & 63); i < n; i += 64) d.A[i + (size_t)j * d.lda] = S[i + j * LD];
+  if (!d.Inv) return;
+  for (int j = n - 1; j >= 0; --j) {
+    const T djinv = (T)1 / S[j + j * LD];
+    T s = 0;
+    const int i = tid;
+    if (i > j && i < n)
+      for (int k = j + 1; k <= i; ++k) s += S[i + k * LD] * S[k + j * LD];
+    __syncthreads();
+    if (i > j && i < n) S[i + j * LD] = -s * djinv;
+    if (i == j) S[j + j * LD] = djinv;
+    __syncthreads();
   }
-  if (d.Inv) {
-    for (int c = tid; c < n; c += nt) {
-      T* X = d.Inv + (size_t)c * d.ldi;
-      for (int i = 0; i < c; ++i) X[i] = (T)0;
-      X[c] = (T)1 / S[c + c * n];
-      for (int i = c + 1; i < n; ++i) {
-        T s = 0;
-        for (int j = c; j < i; ++j) s += S[i + j * n] * X[j];
-        X[i] = -s / S[i + i * n];
-      }
-    }
-  }
+  for (int j = tid >> 6; j < n; j += nt >> 6)
+    for (int i = tid & 63; i < n; i += 64) d.Inv[i + (size_t)j * d.ldi] = i >= j ? S[i + j * LD] : (T)0;
 }
 
-// --------------------------------------------- skeleton, phase 1 (LDS) ----
-template <typename T>
-__global__ __launch_bounds__(1024) void skel_kernel(const SkelDesc<T>* __restrict__ descs, double eps) {
-  extern __shared__ __align__(16) char smem[];
-  __shared__ double redd[16];
-  __shared__ int redi[16];
-  const SkelDesc<T> d = descs[blockIdx.x];
-  const int nI = d.nI, nJ = d.nJ, tid = threadIdx.x, nt = blockDim.x;
-  const int kmax = min(nI, nJ);
-  T* Bh = reinterpret_cast<T*>(smem);
-  int* pa = reinterpret_cast<int*>(Bh + (size_t)nI * nJ);
-  int* pb = pa + kmax;
-  char* lr = reinterpret_cast<char*>(pb + kmax);
-  char* lc = lr + nI;
-  const int tot = nI * nJ;
-  for (int idx = tid; idx < tot; idx += nt) {
-    const int a = idx % nI, b = idx / nI;
-    Bh[idx] = d.F[d.I[a] + (size_t)d.J[b] * d.ld];
+// ------------------------------------------ register-resident skeleton ----
+// Pivot key: |v| truncated to 20 mantissa bits in the high word, the
+// complement of the column-major index (col * rows + row) in the low word, so
+// the largest key is the largest truncated magnitude with the lowest column,
+// then the lowest row.  A zero magnitude never wins (key 0 = no candidate).
+typedef unsigned long long u64;
+
+__device__ __forceinline__ unsigned qmag(double v) {
+  return (unsigned)(__double_as_longlong(fabs(v)) >> 32);
+}
+__device__ __forceinline__ unsigned qmag(float v) { return (unsigned)__float_as_uint(fabsf(v)) >> 3; }
+
+__device__ __forceinline__ u64 make_key(unsigned q, unsigned idx) {
+  return q == 0u ? 0ull : (((u64)q) << 32) | (u64)(0xFFFFFFFFu - idx);
+}
+
+__device__ __forceinline__ u64 wave_max_u64(u64 v) {
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    const unsigned lo = __shfl_xor((unsigned)(v & 0xFFFFFFFFull), o, kWave);
+    const unsigned hi = __shfl_xor((unsigned)(v >> 32), o, kWave);
+    const u64 w = (((u64)hi) << 32) | lo;
+    v = w > v ? w : v;
   }
-  for (int a = tid; a < nI; a += nt) lr[a] = 1;
-  for (int b = tid; b < nJ; b += nt) lc[b] = 1;
+  return v;
+}
+
+__device__ u64 block_max_u64(u64 v, u64* sh) {
+  v = wave_max_u64(v);
+  const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
   __syncthreads();
+  if (l == 0) sh[w] = v;
+  __syncthreads();
+  u64 r = sh[0];
+  for (int i = 1; i < (int)(blockDim.x / kWave); ++i) r = sh[i] > r ? sh[i] : r;
+  return r;
+}
+
+// Thread t owns rows a = (t & 63) + 64 i (i < RI) and columns
+// b = (t >> 6) + CG j (j < CJ) of the block, CG = NT / 64 column groups.
+template <typename T, int RI, int CJ, bool FULL, int NT>
+__global__ __launch_bounds__(NT) void skreg_kernel(const SkRegDesc<T>* __restrict__ descs, double eps,
+                                                     int adaptive, int* status) {
+  constexpr int CG = NT / 64, MR = RI * 64, MC = CJ * CG;
+  __shared__ T s_row[MC];
+  __shared__ T s_col[MR];
+  __shared__ u64 s_red[16];
+  __shared__ char s_inI[FULL ? MR : 1];
+  __shared__ char s_inJ[FULL ? MC : 1];
+  __shared__ short s_rstep[FULL ? 1 : MR];
+  __shared__ short s_cstep[FULL ? 1 : MC];
+  const SkRegDesc<T> d = descs[blockIdx.x];
+  const int t = threadIdx.x, lane = t & 63, g = t >> 6;
+  const int M = FULL ? d.nr : d.nI, N = FULL ? d.nc : d.nJ;
+  T e[RI][CJ];
+  unsigned rl = 0, cl = 0, inI = 0, inJ = 0;
+#pragma unroll
+  for (int i = 0; i < RI; ++i) {
+    const int a = lane + 64 * i;
+    if (a < M) rl |= 1u << i;
+#pragma unroll
+    for (int j = 0; j < CJ; ++j) {
+      const int b = g + CG * j;
+      if (i == 0 && b < N) cl |= 1u << j;
+      T v = 0;
+      if (a < M && b < N) v = FULL ? d.F[(d.r0 + a) + (size_t)(d.c0 + b) * d.ld] : d.F[d.I[a] + (size_t)d.J[b] * d.ld];
+      e[i][j] = v;
+    }
+  }
+  if (FULL) {
+    for (int a = t; a < MR; a += blockDim.x) s_inI[a] = 0;
+    for (int b = t; b < MC; b += blockDim.x) s_inJ[b] = 0;
+    __syncthreads();
+    for (int k = t; k < d.nI; k += blockDim.x) s_inI[d.I[k] - d.r0] = 1;
+    for (int k = t; k < d.nJ; k += blockDim.x) s_inJ[d.J[k] - d.c0] = 1;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < RI; ++i) if (s_inI[lane + 64 * i]) inI |= 1u << i;
+#pragma unroll
+    for (int j = 0; j < CJ; ++j) if (s_inJ[g + CG * j]) inJ |= 1u << j;
+  } else {
+    for (int a = t; a < MR; a += blockDim.x) s_rstep[a] = -1;
+    for (int b = t; b < MC; b += blockDim.x) s_cstep[b] = -1;
+  }
   const T stop_rel = (T)fmax(eps, (double)noise_rel<T>());
+  int phase = (FULL && !(d.nI > 0 && d.nJ > 0)) ? 2 : 1;
+  int r = 0, r1 = -1;
   T u11 = 0;
-  int r = 0;
-  for (int s = 0; s < kmax; ++s) {
-    double mx = 0.0;
-    for (int idx = tid; idx < tot; idx += nt) {
-      const int a = idx % nI, b = idx / nI;
-      if (lr[a] && lc[b]) mx = fmax(mx, (double)fabs(Bh[idx]));
+  // empty BDLR sets without the adaptive phase: rank 0
+  const bool run = !(FULL && phase == 2 && !adaptive);
+  while (run) {
+    const unsigned smask_r = (phase == 1 && FULL) ? (rl & inI) : rl;
+    const unsigned smask_c = (phase == 1 && FULL) ? (cl & inJ) : cl;
+    // within a thread the index grows with (j, i) in that order, so the first
+    // strict maximum in this loop order is the thread's best key
+    unsigned bq = 0;
+    int bj = 0, bi = 0;
+#pragma unroll
+    for (int j = 0; j < CJ; ++j) {
+      if (!((smask_c >> j) & 1u)) continue;
+#pragma unroll
+      for (int i = 0; i < RI; ++i) {
+        const unsigned q = ((smask_r >> i) & 1u) ? qmag(e[i][j]) : 0u;
+        if (q > bq) { bq = q; bj = j; bi = i; }
+      }
     }
-    const double mxall = block_max(mx, redd);
-    if (!(mxall > 0.0)) break;
-    const T thr = (T)(1.0 - kTieRel) * (T)mxall;
-    int best = INT_MAX;
-    for (int idx = tid; idx < tot; idx += nt) {
-      const int a = idx % nI, b = idx / nI;
-      if (lr[a] && lc[b] && fabs(Bh[idx]) >= thr) { best = idx; break; }
+    const u64 best = make_key(bq, (unsigned)((g + CG * bj) * M + lane + 64 * bi));
+    const u64 K = block_max_u64(best, s_red);
+    bool stop = K == 0ull;
+    int as = 0, bs = 0;
+    T piv = 0;
+    if (!stop) {
+      const unsigned idx = 0xFFFFFFFFu - (unsigned)(K & 0xFFFFFFFFull);
+      as = (int)(idx % (unsigned)M);
+      bs = (int)(idx / (unsigned)M);
+      if (lane == (as & 63)) {
+#pragma unroll
+        for (int i = 0; i < RI; ++i)
+          if (i == (as >> 6)) {
+#pragma unroll
+            for (int j = 0; j < CJ; ++j) s_row[g + CG * j] = e[i][j];
+          }
+      }
+      if (g == (bs % CG)) {
+#pragma unroll
+        for (int j = 0; j < CJ; ++j)
+          if (j == (bs / CG)) {
+#pragma unroll
+            for (int i = 0; i < RI; ++i) s_col[lane + 64 * i] = e[i][j];
+          }
+      }
+      __syncthreads();
+      piv = s_row[bs];
+      if (u11 == (T)0) u11 = fabs(piv);
+      stop = fabs(piv) < stop_rel * u11;
     }
-    const int pidx = block_min(best, redi);
-    const int as = pidx % nI, bs = pidx / nI;
-    const T piv = Bh[pidx];
-    if (s == 0) u11 = fabs(piv);
-    if (fabs(piv) < stop_rel * u11) break;
-    __syncthreads();
-    if (tid == 0) {
-      pa[s] = as; pb[s] = bs;
-      d.piv_r[s] = d.I[as];
-      d.piv_c[s] = d.J[bs];
+    if (stop) {
+      if (FULL && phase == 1 && adaptive) {
+        phase = 2;
+        r1 = r;
+        __syncthreads();
+        continue;
+      }
+      break;
     }
-    for (int a = tid; a < nI; a += nt)
-      if (lr[a] && a != as) Bh[a + bs * nI] /= piv;
-    __syncthreads();
-    for (int idx = tid; idx < tot; idx += nt) {
-      const int a = idx % nI, b = idx / nI;
-      if (lr[a] && lc[b] && a != as && b != bs) Bh[idx] -= Bh[a + bs * nI] * Bh[as + b * nI];
+    if (r >= d.cap) {
+      if (t == 0) atomicOr(status, 2);
+      break;
     }
+    if (t == 0) {
+      d.piv_r[r] = FULL ? d.r0 + as : d.I[as];
+      d.piv_c[r] = FULL ? d.c0 + bs : d.J[bs];
+    }
+    const T rpiv = (T)1 / piv;
+    if (FULL) {
+      T* Uc = d.U + (size_t)r * d.ldu;
+      T* Vc = d.V + (size_t)r * d.ldv;
+      for (int a = t; a < M; a += blockDim.x) Uc[a] = phase == 1 ? s_col[a] / piv : s_col[a];
+      for (int b = t; b < N; b += blockDim.x) Vc[b] = phase == 1 ? s_row[b] : s_row[b] / piv;
+      T li[RI];
+#pragma unroll
+      for (int i = 0; i < RI; ++i) li[i] = s_col[lane + 64 * i] * rpiv;
+#pragma unroll
+      for (int j = 0; j < CJ; ++j) {
+        const T uj = s_row[g + CG * j];
+#pragma unroll
+        for (int i = 0; i < RI; ++i) e[i][j] -= li[i] * uj;
+      }
+    } else {
+      // in-place LU of B_hat: live rows get l = e / piv in the pivot column
+      T li[RI];
+      unsigned upd = 0;   // rows to update: live and not the pivot row
+#pragma unroll
+      for (int i = 0; i < RI; ++i) {
+        const int a = lane + 64 * i;
+        li[i] = s_col[a] * rpiv;
+        if (((rl >> i) & 1u) && a != as) upd |= 1u << i;
+      }
+#pragma unroll
+      for (int j = 0; j < CJ; ++j) {
+        const int b = g + CG * j;
+        const T uj = s_row[b];
+        const bool pc = b == bs, lc = ((cl >> j) & 1u) != 0;
+#pragma unroll
+        for (int i = 0; i < RI; ++i) {
+          if (!((upd >> i) & 1u)) continue;
+          if (pc) e[i][j] = li[i];
+          else if (lc) e[i][j] -= li[i] * uj;
+        }
+      }
+      if (t == 0) { s_rstep[as] = (short)r; s_cstep[bs] = (short)r; }
+    }
+    if (lane == (as & 63)) rl &= ~(1u << (as >> 6));
+    if (g == (bs % CG)) cl &= ~(1u << (bs / CG));
+    ++r;
     __syncthreads();
-    if (tid == 0) { lr[as] = 0; lc[bs] = 0; }
-    __syncthreads();
-    r = s + 1;
   }
-  __syncthreads();
-  if (tid == 0) { *d.rank = r; *d.u11 = (double)u11; }
-  for (int idx = tid; idx < r * r; idx += nt) {
-    const int s = idx % r, t = idx / r;
-    d.M[s + (size_t)t * d.ldm] = Bh[pa[s] + pb[t] * nI];
+  if (r1 < 0) r1 = r;
+  if (t == 0) {
+    *d.rank1 = FULL ? r1 : r;
+    if (d.rank) *d.rank = r;
+    *d.u11 = (double)u11;
+  }
+  if (!FULL) {
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < RI; ++i) {
+      const int a = lane + 64 * i;
+      if (a >= M) continue;
+      const int s = s_rstep[a];
+      if (s < 0) continue;
+#pragma unroll
+      for (int j = 0; j < CJ; ++j) {
+        const int b = g + CG * j;
+        if (b >= N) continue;
+        const int c = s_cstep[b];
+        if (c >= 0) d.M[s + (size_t)c * d.ldm] = e[i][j];
+      }
+    }
   }
 }
 
@@ -358,8 +511,7 @@ template <typename T>
 __global__ __launch_bounds__(1024) void phase2_kernel(const Phase2Desc<T>* __restrict__ descs, double eps,
                                                       int* status) {
   extern __shared__ __align__(16) char smem[];
-  __shared__ double redd[16];
-  __shared__ int redi[16];
+  __shared__ u64 s_red[16];
   const Phase2Desc<T> d = descs[blockIdx.x];
   const int nr = d.nr, nc = d.nc, tid = threadIdx.x, nt = blockDim.x;
   char* lr = smem;
@@ -373,25 +525,35 @@ __global__ __launch_bounds__(1024) void phase2_kernel(const Phase2Desc<T>* __res
   __syncthreads();
   T* E = d.F + d.r0 + (size_t)d.c0 * d.ld;
   const int ld = d.ld;
-  const int tot = nr * nc;
   const double stop_rel = fmax(eps, (double)noise_rel<T>());
   int r = r1;
+  const int w = tid >> 6, lane = tid & 63, nw = nt >> 6;
+  bool pending = false;   // the last appended (U, V) column is still to be subtracted
   for (;;) {
-    double mx = 0.0;
-    for (int idx = tid; idx < tot; idx += nt) {
-      const int a = idx % nr, b = idx / nr;
-      if (lr[a] && lc[b]) mx = fmax(mx, (double)fabs(E[a + (size_t)b * ld]));
+    // one pass: apply the pending rank-1 update, then find the pivot key
+    const T* Up = d.U + (size_t)(r - 1) * d.ldu;
+    const T* Vp = d.V + (size_t)(r - 1) * d.ldv;
+    u64 best = 0;
+    for (int b = w; b < nc; b += nw) {
+      const T vb = pending ? Vp[b] : (T)0;
+      const bool cb = lc[b] != 0;
+      T* Eb = E + (size_t)b * ld;
+      for (int a = lane; a < nr; a += 64) {
+        T x = Eb[a];
+        if (pending) {
+          x -= Up[a] * vb;
+          Eb[a] = x;
+        }
+        if (cb && lr[a]) {
+          const u64 k = make_key(qmag(x), (unsigned)(b * nr + a));
+          best = k > best ? k : best;
+        }
+      }
     }
-    const double mxall = block_max(mx, redd);
-    if (!(mxall > 0.0)) break;
-    const T thr = (T)(1.0 - kTieRel) * (T)mxall;
-    int best = INT_MAX;
-    for (int idx = tid; idx < tot; idx += nt) {
-      const int a = idx % nr, b = idx / nr;
-      if (lr[a] && lc[b] && fabs(E[a + (size_t)b * ld]) >= thr) { best = idx; break; }
-    }
-    const int pidx = block_min(best, redi);
-    const int as = pidx % nr, bs = pidx / nr;
+    const u64 K = block_max_u64(best, s_red);
+    if (K == 0ull) break;
+    const unsigned idx = 0xFFFFFFFFu - (unsigned)(K & 0xFFFFFFFFull);
+    const int as = (int)(idx % (unsigned)nr), bs = (int)(idx / (unsigned)nr);
     const T piv = E[as + (size_t)bs * ld];
     if (u11 == 0.0) u11 = fabs((double)piv);
     if (fabs((double)piv) < stop_rel * u11) break;
@@ -404,13 +566,9 @@ __global__ __launch_bounds__(1024) void phase2_kernel(const Phase2Desc<T>* __res
     for (int a = tid; a < nr; a += nt) Uc[a] = E[a + (size_t)bs * ld];
     for (int b = tid; b < nc; b += nt) Vc[b] = E[as + (size_t)b * ld] / piv;
     __syncthreads();
-    for (int idx = tid; idx < tot; idx += nt) {
-      const int a = idx % nr, b = idx / nr;
-      E[a + (size_t)b * ld] -= Uc[a] * Vc[b];
-    }
-    __syncthreads();
     if (tid == 0) { lr[as] = 0; lc[bs] = 0; }
     ++r;
+    pending = true;
     __syncthreads();
   }
   if (tid == 0) *d.rank = r;
@@ -528,22 +686,19 @@ __global__ void assemble_kernel(T* base, const int64_t* __restrict__ dest, const
     base[dest[i]] = (T)vals[src[i]];
 }
 
+// one workgroup per (front, right-hand side)
 template <typename T>
 __global__ __launch_bounds__(256) void vec_asm_kernel(const VecAsmDesc<T>* __restrict__ descs, int nrhs) {
   const VecAsmDesc<T> d = descs[blockIdx.x];
-  const int tid = threadIdx.x, nt = blockDim.x;
-  for (int k = 0; k < nrhs; ++k) {
-    T* t = d.t + (size_t)k * d.ldt;
-    const T* x = d.xs + (size_t)k * d.ldx;
-    for (int i = tid; i < d.nhat; i += nt) t[i] = i < d.npiv ? x[i] : (T)0;
-  }
+  const int tid = threadIdx.x, nt = blockDim.x, k = blockIdx.y;
+  T* t = d.t + (size_t)k * d.ldt;
+  const T* x = d.xs + (size_t)k * d.ldx;
+  for (int i = tid; i < d.nhat; i += nt) t[i] = i < d.npiv ? x[i] : (T)0;
   __syncthreads();
   for (int c = 0; c < d.nchild; ++c) {   // children in order: no two threads touch one entry
-    for (int k = 0; k < nrhs; ++k) {
-      T* t = d.t + (size_t)k * d.ldt;
-      const T* ct = d.ct[c] + d.cnp[c] + (size_t)k * d.cld[c];
-      for (int a = tid; a < d.cnf[c]; a += nt) t[d.crel[c][a]] += ct[a];
-    }
+    const T* ct = d.ct[c] + d.cnp[c] + (size_t)k * d.cld[c];
+    const int* rel = d.crel[c];
+    for (int a = tid; a < d.cnf[c]; a += nt) t[rel[a]] += ct[a];
     __syncthreads();
   }
 }
@@ -552,10 +707,10 @@ template <typename T>
 __global__ __launch_bounds__(256) void vec_gather_kernel(const VecGatherDesc<T>* __restrict__ descs, const T* xn,
                                                          int N, int nrhs) {
   const VecGatherDesc<T> d = descs[blockIdx.x];
-  for (int idx = threadIdx.x; idx < d.nf * nrhs; idx += blockDim.x) {
-    const int a = idx % d.nf, k = idx / d.nf;
-    d.t[a + (size_t)k * d.ldt] = xn[d.upd[a] + (size_t)k * N];
-  }
+  const int k = blockIdx.y;
+  T* t = d.t + (size_t)k * d.ldt;
+  const T* x = xn + (size_t)k * N;
+  for (int a = threadIdx.x; a < d.nf; a += blockDim.x) t[a] = x[d.upd[a]];
 }
 
 template <typename T>
@@ -579,17 +734,33 @@ __global__ void perm_out_kernel(const T* xn, double* z, const int* iperm, int N,
 }
 
 // ------------------------------------------------------- Krylov / SpMV ----
-__global__ void spmv_kernel(const int* __restrict__ rowptr, const int* __restrict__ colind,
-                            const double* __restrict__ vals, const double* __restrict__ x, double* y, int n,
-                            double alpha, double beta) {
+// one thread per row, all right-hand sides: A's row is read once
+__global__ __launch_bounds__(256) void spmv_kernel(const int* __restrict__ rowptr, const int* __restrict__ colind,
+                                                   const double* __restrict__ vals, const double* __restrict__ x,
+                                                   double* y, int n, int nrhs, double alpha, double beta) {
+  constexpr int KB = 16;
   const int row = blockIdx.x * blockDim.x + threadIdx.x;
-  const int k = blockIdx.y;
   if (row >= n) return;
-  const double* xk = x + (size_t)k * n;
-  double s = 0.0;
-  for (int j = rowptr[row]; j < rowptr[row + 1]; ++j) s += vals[j] * xk[colind[j]];
-  double* yo = y + (size_t)k * n + row;
-  *yo = beta == 0.0 ? alpha * s : alpha * s + beta * *yo;
+  const int j0 = rowptr[row], j1 = rowptr[row + 1];
+  for (int k0 = 0; k0 < nrhs; k0 += KB) {
+    const int kb = min(KB, nrhs - k0);
+    double acc[KB];
+#pragma unroll
+    for (int q = 0; q < KB; ++q) acc[q] = 0.0;
+    for (int j = j0; j < j1; ++j) {
+      const double v = vals[j];
+      const double* xc = x + colind[j] + (size_t)k0 * n;
+#pragma unroll
+      for (int q = 0; q < KB; ++q)
+        if (q < kb) acc[q] += v * xc[(size_t)q * n];
+    }
+#pragma unroll
+    for (int q = 0; q < KB; ++q)
+      if (q < kb) {
+        double* yo = y + (size_t)(k0 + q) * n + row;
+        *yo = beta == 0.0 ? alpha * acc[q] : alpha * acc[q] + beta * *yo;
+      }
+  }
 }
 
 constexpr int kMdotMax = 64;
@@ -685,9 +856,20 @@ void launch_potrf(const PotrfDesc<T>* d, int ndesc, int nmax, int* status, hipSt
   else hipLaunchKernelGGL((potrf_kernel<T, 128>), dim3(ndesc), dim3(256), 0, st, d, status);
 }
 template <typename T>
-void launch_skel(const SkelDesc<T>* d, int ndesc, size_t lds, double eps, hipStream_t st) {
+void launch_skreg_full(const SkRegDesc<T>* d, int ndesc, double eps, int adaptive, int* status, hipStream_t st) {
   if (ndesc <= 0) return;
-  hipLaunchKernelGGL(skel_kernel<T>, dim3(ndesc), dim3(1024), lds, st, d, eps);
+  if constexpr (sizeof(T) == 8)
+    hipLaunchKernelGGL((skreg_kernel<T, 2, 32, true, 512>), dim3(ndesc), dim3(512), 0, st, d, eps, adaptive, status);
+  else
+    hipLaunchKernelGGL((skreg_kernel<T, 4, 32, true, 512>), dim3(ndesc), dim3(512), 0, st, d, eps, adaptive, status);
+}
+template <typename T>
+void launch_skreg_hat(const SkRegDesc<T>* d, int ndesc, double eps, int* status, hipStream_t st) {
+  if (ndesc <= 0) return;
+  if constexpr (sizeof(T) == 8)
+    hipLaunchKernelGGL((skreg_kernel<T, 2, 8, false, 1024>), dim3(ndesc), dim3(1024), 0, st, d, eps, 0, status);
+  else
+    hipLaunchKernelGGL((skreg_kernel<T, 3, 24, false, 512>), dim3(ndesc), dim3(512), 0, st, d, eps, 0, status);
 }
 template <typename T>
 void launch_skelfac(const SkelFacDesc<T>* d, int ndesc, int wgs, int rmax, hipStream_t st) {
@@ -731,12 +913,12 @@ void launch_assemble(T* base, const int64_t* dest, const int* src, const double*
 template <typename T>
 void launch_vec_asm(const VecAsmDesc<T>* d, int ndesc, int nrhs, hipStream_t st) {
   if (ndesc <= 0) return;
-  hipLaunchKernelGGL(vec_asm_kernel<T>, dim3(ndesc), dim3(256), 0, st, d, nrhs);
+  hipLaunchKernelGGL(vec_asm_kernel<T>, dim3(ndesc, nrhs), dim3(256), 0, st, d, nrhs);
 }
 template <typename T>
 void launch_vec_gather(const VecGatherDesc<T>* d, int ndesc, const T* xn, int N, int nrhs, hipStream_t st) {
   if (ndesc <= 0) return;
-  hipLaunchKernelGGL(vec_gather_kernel<T>, dim3(ndesc), dim3(256), 0, st, d, xn, N, nrhs);
+  hipLaunchKernelGGL(vec_gather_kernel<T>, dim3(ndesc, nrhs), dim3(256), 0, st, d, xn, N, nrhs);
 }
 template <typename T>
 void launch_perm_in(const double* r, T* xn, const int* perm, int N, int nrhs, hipStream_t st) {
@@ -749,7 +931,7 @@ void launch_perm_out(const T* xn, double* z, const int* iperm, int N, int nrhs, 
 
 void launch_spmv(const int* rowptr, const int* colind, const double* vals, const double* x, double* y, int n,
                  int nrhs, double alpha, double beta, hipStream_t st) {
-  hipLaunchKernelGGL(spmv_kernel, dim3((n + 255) / 256, nrhs), dim3(256), 0, st, rowptr, colind, vals, x, y, n,
+  hipLaunchKernelGGL(spmv_kernel, dim3((n + 255) / 256), dim3(256), 0, st, rowptr, colind, vals, x, y, n, nrhs,
                      alpha, beta);
 }
 void launch_mdot(const double* X, int64_t xstride, int nv, const double* w, int n, int nrhs, double* partial,
@@ -779,7 +961,8 @@ void launch_axpby(const double* a, const double* b, double* c, double alpha, dou
 #define MFH_INST(T)                                                                              \
   template void launch_gemm<T>(const GemmDesc<T>*, int, int, hipStream_t);                       \
   template void launch_potrf<T>(const PotrfDesc<T>*, int, int, int*, hipStream_t);               \
-  template void launch_skel<T>(const SkelDesc<T>*, int, size_t, double, hipStream_t);            \
+  template void launch_skreg_full<T>(const SkRegDesc<T>*, int, double, int, int*, hipStream_t);  \
+  template void launch_skreg_hat<T>(const SkRegDesc<T>*, int, double, int*, hipStream_t);        \
   template void launch_skelfac<T>(const SkelFacDesc<T>*, int, int, int, hipStream_t);            \
   template void launch_phase2<T>(const Phase2Desc<T>*, int, int, double, int*, hipStream_t);     \
   template void launch_extadd<T>(const ExtAddDesc<T>*, int, int, hipStream_t);                   \

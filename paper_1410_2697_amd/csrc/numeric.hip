@@ -529,6 +529,7 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs) {
   const bool adaptive = opts.adaptive != 0;
   struct BR {
     int p, bi, gb, nI, nJ, kcap, capr;
+    bool full;                 // whole block held in registers by one workgroup
     int *pr, *pc, *rank1, *rank;
     double* u11;
     T *M, *U, *V;
@@ -544,17 +545,18 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs) {
       x.nJ = bJptr[x.gb + 1] - bJptr[x.gb];
       x.kcap = std::min(x.nI, x.nJ);
       x.capr = std::max(std::min({B.nr, B.nc, opts.rank_cap}), x.kcap);
+      x.full = B.nr <= skreg_full_rows<T>() && B.nc <= skreg_full_cols<T>();
       br.push_back(x);
     }
   }
   const int nb = (int)br.size();
-  // ---- phase A scratch
+  // ---- compression scratch (lives until the level's last launch)
   auto al = [](size_t v) { return (v + 255) & ~size_t(255); };
   size_t need = al(nb * sizeof(int)) * 2 + al(nb * sizeof(double));
   for (auto& x : br) {
     const Block& B = s.fronts[x.p].blocks[x.bi];
-    need += 2 * al(std::max(x.kcap, 1) * sizeof(int));
-    need += al((size_t)std::max(x.kcap * x.kcap, 1) * sizeof(T));
+    need += 2 * al(std::max(x.capr, 1) * sizeof(int));
+    if (!x.full) need += al((size_t)std::max(x.kcap * x.kcap, 1) * sizeof(T));
     need += al((size_t)B.nr * x.capr * sizeof(T)) + al((size_t)B.nc * x.capr * sizeof(T));
   }
   scrA.ensure(need, &ms, st);
@@ -566,35 +568,41 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs) {
   for (int i = 0; i < nb; ++i) {
     BR& x = br[i];
     const Block& B = s.fronts[x.p].blocks[x.bi];
-    x.pr = reinterpret_cast<int*>(take(std::max(x.kcap, 1) * sizeof(int)));
-    x.pc = reinterpret_cast<int*>(take(std::max(x.kcap, 1) * sizeof(int)));
-    x.M = reinterpret_cast<T*>(take((size_t)std::max(x.kcap * x.kcap, 1) * sizeof(T)));
+    x.pr = reinterpret_cast<int*>(take(std::max(x.capr, 1) * sizeof(int)));
+    x.pc = reinterpret_cast<int*>(take(std::max(x.capr, 1) * sizeof(int)));
+    x.M = x.full ? nullptr : reinterpret_cast<T*>(take((size_t)std::max(x.kcap * x.kcap, 1) * sizeof(T)));
     x.U = reinterpret_cast<T*>(take((size_t)B.nr * x.capr * sizeof(T)));
     x.V = reinterpret_cast<T*>(take((size_t)B.nc * x.capr * sizeof(T)));
     x.rank1 = rank1 + i;
-    x.rank = adaptive ? rankf + i : rank1 + i;
+    x.rank = rankf + i;
     x.u11 = u11 + i;
   }
   Blob b;
-  std::vector<SkelDesc<T>> sk;
+  std::vector<SkRegDesc<T>> skf, skh;
   std::vector<SkelFacDesc<T>> sf;
   std::vector<Phase2Desc<T>> p2;
   GemmBatch<T> resid;
-  size_t lds_sk = 0;
   int rmax1 = 1, wgs = 0, maxrc = 1;
   const int* dI = d_bdlr.as<int>();
   const int* dJ = d_bdlr.as<int>() + bdlr_J_base;
   for (auto& x : br) {
     const Block& B = s.fronts[x.p].blocks[x.bi];
     const FN& fx = fn[x.p];
-    SkelDesc<T> d{};
-    d.F = fx.F; d.ld = fx.ld;
+    SkRegDesc<T> d{};
+    d.F = fx.F; d.ld = fx.ld; d.r0 = B.r0; d.nr = B.nr; d.c0 = B.c0; d.nc = B.nc;
     d.I = dI + bIptr[x.gb]; d.nI = x.nI;
     d.J = dJ + bJptr[x.gb]; d.nJ = x.nJ;
-    d.piv_r = x.pr; d.piv_c = x.pc; d.M = x.M; d.ldm = std::max(x.kcap, 1);
-    d.rank = x.rank1; d.u11 = x.u11;
-    sk.push_back(d);
-    lds_sk = std::max(lds_sk, (size_t)x.nI * x.nJ * sizeof(T) + 2 * (size_t)x.kcap * sizeof(int) + x.nI + x.nJ + 64);
+    d.piv_r = x.pr; d.piv_c = x.pc;
+    d.rank1 = x.rank1; d.rank = x.rank; d.u11 = x.u11; d.cap = x.capr;
+    if (x.full) {
+      d.U = x.U; d.ldu = B.nr; d.V = x.V; d.ldv = B.nc;
+      skf.push_back(d);
+      continue;
+    }
+    if (x.nI > skreg_hat_max<T>() || x.nJ > skreg_hat_max<T>())
+      throw Err{MF_EINVAL, "BDLR sets larger than the pivot kernel supports: lower bdlr_cap"};
+    d.M = x.M; d.ldm = std::max(x.kcap, 1);
+    skh.push_back(d);
     rmax1 = std::max(rmax1, x.kcap);
     SkelFacDesc<T> f{};
     f.F = fx.F; f.ld = fx.ld; f.r0 = B.r0; f.nr = B.nr; f.c0 = B.c0; f.nc = B.nc;
@@ -616,24 +624,25 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs) {
       maxrc = std::max(maxrc, B.nr + B.nc);
     }
   }
-  if (lds_sk > (size_t)kLdsMax)
-    throw Err{MF_EINVAL, "BDLR sets too large for LDS: lower bdlr_cap"};
   if ((size_t)rmax1 * rmax1 * sizeof(T) > (size_t)kLdsMax)
     throw Err{MF_EINVAL, "phase-1 rank bound too large for LDS: lower bdlr_cap"};
   if (maxrc > kLdsMax) throw Err{MF_EINVAL, "block too large for the phase-2 kernel"};
-  const size_t osk = b.add(sk), osf = b.add(sf), op2 = b.add(p2);
+  const size_t okf = b.add(skf), okh = b.add(skh), osf = b.add(sf), op2 = b.add(p2);
   resid.stage(b);
   const char* base = dp.upload(b, st);
-  launch_skel<T>(reinterpret_cast<const SkelDesc<T>*>(base + osk), nb, lds_sk, eps, st);
-  launch_skelfac<T>(reinterpret_cast<const SkelFacDesc<T>*>(base + osf), nb, wgs, rmax1, st);
+  int* dstat = d_status.as<int>();
+  launch_skreg_full<T>(reinterpret_cast<const SkRegDesc<T>*>(base + okf), (int)skf.size(), eps, adaptive ? 1 : 0,
+                       dstat, st);
+  launch_skreg_hat<T>(reinterpret_cast<const SkRegDesc<T>*>(base + okh), (int)skh.size(), eps, dstat, st);
+  launch_skelfac<T>(reinterpret_cast<const SkelFacDesc<T>*>(base + osf), (int)sf.size(), wgs, rmax1, st);
   if (adaptive) {
     resid.launch(base, st);
-    launch_phase2<T>(reinterpret_cast<const Phase2Desc<T>*>(base + op2), nb, maxrc, eps, d_status.as<int>(), st);
+    launch_phase2<T>(reinterpret_cast<const Phase2Desc<T>*>(base + op2), (int)p2.size(), maxrc, eps, dstat, st);
   }
   // ---- the one synchronisation of the level: ranks to the host
   std::vector<int> hr(nb);
   int status = 0;
-  HIPCHK(hipMemcpyAsync(hr.data(), adaptive ? rankf : rank1, nb * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(hr.data(), rankf, nb * sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(hipMemcpyAsync(&status, d_status.p, sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(st));

@@ -57,21 +57,25 @@ template <typename T>
 mf_status skel_t(void* F, int ld, int r0, int nr, int c0, int nc, const int* I, int nI, const int* J, int nJ,
                  double eps, int adaptive, int cap, void* U, void* V, int* rank_out) {
   const int kcap = nI < nJ ? nI : nJ;
+  const bool full = nr <= mfh::skreg_full_rows<T>() && nc <= mfh::skreg_full_cols<T>();
   char* scratch = nullptr;
-  const size_t bytes = 4096 + (size_t)(kcap + 1) * (kcap + 1) * sizeof(T) + 8 * (size_t)(kcap + 1) + 1024;
+  const size_t bytes = 4096 + (size_t)(kcap + 1) * (kcap + 1) * sizeof(T) + 8 * (size_t)(cap + 1) + 1024;
   mf_status s = hip_ok(hipMalloc(&scratch, bytes));
   if (s != MF_OK) return s;
   int* rank1 = reinterpret_cast<int*>(scratch);
   int* rank = rank1 + 1;
   int* status = rank1 + 2;
   double* u11 = reinterpret_cast<double*>(scratch + 64);
-  int* pr = reinterpret_cast<int*>(scratch + 128);
-  int* pc = pr + kcap + 1;
-  T* M = reinterpret_cast<T*>(scratch + 4096);
+  T* M = reinterpret_cast<T*>(scratch + 128);
+  int* pr = reinterpret_cast<int*>(scratch + 128 + (size_t)(kcap + 1) * (kcap + 1) * sizeof(T));
+  int* pc = pr + cap + 1;
   hipMemset(scratch, 0, 128);
-  mfh::SkelDesc<T> sd{};
-  sd.F = static_cast<T*>(F); sd.ld = ld; sd.I = I; sd.nI = nI; sd.J = J; sd.nJ = nJ;
-  sd.piv_r = pr; sd.piv_c = pc; sd.M = M; sd.ldm = kcap > 0 ? kcap : 1; sd.rank = rank1; sd.u11 = u11;
+  mfh::SkRegDesc<T> sd{};
+  sd.F = static_cast<T*>(F); sd.ld = ld; sd.r0 = r0; sd.nr = nr; sd.c0 = c0; sd.nc = nc;
+  sd.I = I; sd.nI = nI; sd.J = J; sd.nJ = nJ; sd.piv_r = pr; sd.piv_c = pc;
+  sd.rank1 = rank1; sd.rank = rank; sd.u11 = u11; sd.cap = cap;
+  sd.U = static_cast<T*>(U); sd.ldu = nr; sd.V = static_cast<T*>(V); sd.ldv = nc;
+  sd.M = M; sd.ldm = kcap > 0 ? kcap : 1;
   mfh::SkelFacDesc<T> fd{};
   fd.F = static_cast<T*>(F); fd.ld = ld; fd.r0 = r0; fd.nr = nr; fd.c0 = c0; fd.nc = nc;
   fd.piv_r = pr; fd.piv_c = pc; fd.M = M; fd.ldm = sd.ldm; fd.rank = rank1;
@@ -95,15 +99,18 @@ mf_status skel_t(void* F, int ld, int r0, int nr, int c0, int nc, const int* I, 
   hipMemcpy(dd + 1024, &fd, sizeof(fd), hipMemcpyHostToDevice);
   hipMemcpy(dd + 2048, &gdsc, sizeof(gdsc), hipMemcpyHostToDevice);
   hipMemcpy(dd + 3072, &pd, sizeof(pd), hipMemcpyHostToDevice);
-  const size_t lds = (size_t)nI * nJ * sizeof(T) + 2 * (size_t)kcap * sizeof(int) + nI + nJ + 64;
-  mfh::launch_skel<T>(reinterpret_cast<mfh::SkelDesc<T>*>(dd), 1, lds, eps, nullptr);
-  mfh::launch_skelfac<T>(reinterpret_cast<mfh::SkelFacDesc<T>*>(dd + 1024), 1, wgs, kcap > 0 ? kcap : 1, nullptr);
-  if (adaptive) {
-    mfh::launch_gemm<T>(reinterpret_cast<mfh::GemmDesc<T>*>(dd + 2048), 1, gtiles, nullptr);
-    mfh::launch_phase2<T>(reinterpret_cast<mfh::Phase2Desc<T>*>(dd + 3072), 1, nr + nc, eps, status, nullptr);
+  if (full) {
+    mfh::launch_skreg_full<T>(reinterpret_cast<mfh::SkRegDesc<T>*>(dd), 1, eps, adaptive, status, nullptr);
+  } else {
+    mfh::launch_skreg_hat<T>(reinterpret_cast<mfh::SkRegDesc<T>*>(dd), 1, eps, status, nullptr);
+    mfh::launch_skelfac<T>(reinterpret_cast<mfh::SkelFacDesc<T>*>(dd + 1024), 1, wgs, kcap > 0 ? kcap : 1, nullptr);
+    if (adaptive) {
+      mfh::launch_gemm<T>(reinterpret_cast<mfh::GemmDesc<T>*>(dd + 2048), 1, gtiles, nullptr);
+      mfh::launch_phase2<T>(reinterpret_cast<mfh::Phase2Desc<T>*>(dd + 3072), 1, nr + nc, eps, status, nullptr);
+    }
   }
   s = hip_ok(hipDeviceSynchronize());
-  if (s == MF_OK) hipMemcpy(rank_out, adaptive ? rank : rank1, sizeof(int), hipMemcpyDeviceToHost);
+  if (s == MF_OK) hipMemcpy(rank_out, rank, sizeof(int), hipMemcpyDeviceToHost);
   hipFree(dd);
   hipFree(scratch);
   return s;
@@ -147,7 +154,7 @@ mf_status mfh_test_potrf(int32_t precision, int32_t n, void* A, int32_t lda, voi
 mf_status mfh_test_skeleton(int32_t precision, void* F, int32_t ld, int32_t r0, int32_t nr, int32_t c0, int32_t nc,
                             const int32_t* I, int32_t nI, const int32_t* J, int32_t nJ, double eps, int32_t adaptive,
                             int32_t cap, void* U, void* V, int32_t* rank_out) {
-  const int maxset = precision == MF_FP64 ? 126 : 180;
+  const int maxset = precision == MF_FP64 ? 128 : 192;
   if (nr < 1 || nc < 1 || nI < 0 || nJ < 0 || nI > maxset || nJ > maxset || nI > nr || nJ > nc || cap < 1 ||
       nr + nc > 160 * 1024 || cap < (nI < nJ ? nI : nJ) || !F || !U || !V || !rank_out)
     return MF_EINVAL;
