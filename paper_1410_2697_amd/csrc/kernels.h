@@ -23,19 +23,23 @@ enum GemmFlags : int {
 // C = alpha * op(A) * op(B) + beta * C ; op(A) m x k, op(B) k x n.
 // If kdev != nullptr the inner dimension is *kdev (a rank produced on the
 // device); k is then an upper bound used only for validation.
+// Split K (ksplit > 1): workgroup split s sums k in [s*kchunk, (s+1)*kchunk)
+// into part + s*m*n (m x n, ld m); a reduction launch then forms
+// C = alpha * sum_s part_s + beta * C in a fixed order (deterministic).
 template <typename T>
 struct GemmDesc {
   const T* A;
   const T* B;
   T* C;
   const int* kdev;
+  T* part;
   int m, n, k;
   int lda, ldb, ldc;
   int opA, opB;      // 0: N, 1: T
   int flags;
   int tile0;         // first launch tile of this problem
-  int tiles_m;
-  int pad;
+  int tiles_m, tiles_n;
+  int ksplit, kchunk;
   double alpha, beta;
 };
 
@@ -166,6 +170,10 @@ template <typename T>
 void launch_mfma_probe(int* rows, int* cols, int* assumed, hipStream_t st);
 template <typename T>
 void launch_gemm(const GemmDesc<T>* d, int ndesc, int tiles, hipStream_t st);
+// reduction of split-K partial sums: d lists only split problems, with
+// tile0/tiles_m describing this launch's 64 x 64 output tiles
+template <typename T>
+void launch_gemm_reduce(const GemmDesc<T>* d, int ndesc, int tiles, hipStream_t st);
 template <typename T>
 void launch_potrf(const PotrfDesc<T>* d, int ndesc, int nmax, int* status, hipStream_t st);
 // whole-block register skeleton: blocks up to skreg_full_rows<T>() x skreg_full_cols<T>()

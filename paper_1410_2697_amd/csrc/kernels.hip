@@ -107,16 +107,23 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc<T>* __restrict
   const int di = find_desc(descs, ndesc, (int)blockIdx.x);
   const GemmDesc<T>& d = descs[di];
   const int lt = (int)blockIdx.x - d.tile0;
-  const int m0 = (lt % d.tiles_m) * BM, n0 = (lt / d.tiles_m) * BN;
+  const int tm = lt % d.tiles_m, rest = lt / d.tiles_m;
+  const int tn = rest % d.tiles_n, ks = rest / d.tiles_n;
+  const int m0 = tm * BM, n0 = tn * BN;
   const int m = d.m, n = d.n, flags = d.flags;
   const int k = d.kdev ? *d.kdev : d.k;
-  if ((flags & GF_LOWER_C) && n0 >= m0 + BM) return;
+  const bool split = d.ksplit > 1;
+  if ((flags & GF_LOWER_C) && n0 >= m0 + BM) return;   // above the diagonal (never read back)
   int kb0 = 0, kend = k;
   if (flags & GF_A_LOWER) kend = min(kend, m0 + BM);
   if (flags & GF_B_UPPER) kend = min(kend, n0 + BN);
   if (flags & GF_A_UPPER) kb0 = max(kb0, m0);
   if (flags & GF_B_LOWER) kb0 = max(kb0, n0);
   kb0 = (kb0 / BK) * BK;
+  if (split) {                       // this workgroup's share of k (kchunk is a multiple of BK)
+    kb0 = max(kb0, ks * d.kchunk);
+    kend = min(kend, (ks + 1) * d.kchunk);
+  }
   const T* __restrict__ A = d.A;
   const T* __restrict__ B = d.B;
   const int lda = d.lda, ldb = d.ldb, opA = d.opA, opB = d.opB;
@@ -149,8 +156,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc<T>* __restrict
     }
     __syncthreads();
 #pragma unroll
-    for (int ks = 0; ks < BK / 4; ++ks) {
-      const int kq = ks * 4 + lk;
+    for (int k4 = 0; k4 < BK / 4; ++k4) {
+      const int kq = k4 * 4 + lk;
       const T a0 = As[kq][wm + li], a1 = As[kq][wm + 16 + li];
       const T b0 = Bs[kq][wn + li], b1 = Bs[kq][wn + 16 + li];
       acc00 = Mfma<T>::run(a0, b0, acc00);
@@ -161,8 +168,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc<T>* __restrict
     __syncthreads();
   }
   const T alpha = (T)d.alpha, beta = (T)d.beta;
-  T* __restrict__ C = d.C;
-  const int ldc = d.ldc;
+  T* __restrict__ C = split ? d.part + (size_t)ks * m * n : d.C;
+  const int ldc = split ? m : d.ldc;
   const v4* accs[4] = {&acc00, &acc01, &acc10, &acc11};
 #pragma unroll
   for (int ab = 0; ab < 4; ++ab) {
@@ -172,13 +179,40 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc<T>* __restrict
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int row = m0 + wm + a * 16 + Mfma<T>::row(lk, v);
-      if (row < m && col < n && (!(flags & GF_LOWER_C) || row >= col)) {
+      if (row < m && col < n) {
         T* c = C + row + (size_t)col * ldc;
-        T val = alpha * acc[v];
-        if (beta != (T)0) val += beta * *c;
-        *c = val;
+        if (split) {
+          *c = acc[v];
+        } else if (!(flags & GF_LOWER_C) || row >= col) {
+          T val = alpha * acc[v];
+          if (beta != (T)0) val += beta * *c;
+          *c = val;
+        }
       }
     }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void gemm_reduce_kernel(const GemmDesc<T>* __restrict__ descs, int ndesc) {
+  const int di = find_desc(descs, ndesc, (int)blockIdx.x);
+  const GemmDesc<T>& d = descs[di];
+  const int lt = (int)blockIdx.x - d.tile0;
+  const int m0 = (lt % d.tiles_m) * kTile, n0 = (lt / d.tiles_m) * kTile;
+  const int m = d.m, n = d.n, S = d.ksplit;
+  const bool lower = (d.flags & GF_LOWER_C) != 0;
+  const T alpha = (T)d.alpha, beta = (T)d.beta;
+  const size_t mn = (size_t)m * n;
+  for (int e = threadIdx.x; e < kTile * kTile; e += blockDim.x) {
+    const int row = m0 + (e & 63), col = n0 + (e >> 6);
+    if (row >= m || col >= n || (lower && row < col)) continue;
+    const T* p = d.part + row + (size_t)col * m;
+    T s = 0;
+    for (int q = 0; q < S; ++q) s += p[q * mn];
+    T* c = d.C + row + (size_t)col * d.ldc;
+    T val = alpha * s;
+    if (beta != (T)0) val += beta * *c;
+    *c = val;
   }
 }
 
@@ -844,6 +878,11 @@ void launch_gemm(const GemmDesc<T>* d, int ndesc, int tiles, hipStream_t st) {
   hipLaunchKernelGGL(gemm_kernel<T>, dim3(tiles), dim3(256), 0, st, d, ndesc);
 }
 template <typename T>
+void launch_gemm_reduce(const GemmDesc<T>* d, int ndesc, int tiles, hipStream_t st) {
+  if (ndesc <= 0 || tiles <= 0) return;
+  hipLaunchKernelGGL(gemm_reduce_kernel<T>, dim3(tiles), dim3(256), 0, st, d, ndesc);
+}
+template <typename T>
 void launch_mfma_probe(int* rows, int* cols, int* assumed, hipStream_t st) {
   hipLaunchKernelGGL(mfma_probe_kernel<T>, dim3(1), dim3(64), 0, st, rows, cols, assumed);
 }
@@ -960,6 +999,7 @@ void launch_axpby(const double* a, const double* b, double* c, double alpha, dou
 
 #define MFH_INST(T)                                                                              \
   template void launch_gemm<T>(const GemmDesc<T>*, int, int, hipStream_t);                       \
+  template void launch_gemm_reduce<T>(const GemmDesc<T>*, int, int, hipStream_t);                \
   template void launch_potrf<T>(const PotrfDesc<T>*, int, int, int*, hipStream_t);               \
   template void launch_skreg_full<T>(const SkRegDesc<T>*, int, double, int, int*, hipStream_t);  \
   template void launch_skreg_hat<T>(const SkRegDesc<T>*, int, double, int*, hipStream_t);        \

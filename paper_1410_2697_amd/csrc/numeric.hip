@@ -20,7 +20,11 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <atomic>
+#include <condition_variable>
 #include <cstring>
+#include <mutex>
+#include <thread>
 
 #include "numeric.h"
 
@@ -107,18 +111,57 @@ GemmDesc<T> gd(const T* A, int lda, int opA, const T* B, int ldb, int opB, T* C,
   return d;
 }
 
-// assigns tile0/tiles_m; returns total tiles
+// Split-K policy: when a batch has too few 64 x 64 output tiles to fill the
+// chip, its deep products (k >= 2 * kSplitChunk) get several workgroups
+// along k, writing partial sums into `part` (capacity `cap` elements; each
+// problem takes its own region), followed by a fixed-order reduction.
+constexpr int kSplitTarget = 512;   // workgroups wanted per launch (two per CU)
+constexpr int kSplitChunk = 128;    // smallest k range of one split
+constexpr size_t kSplitFactorBytes = size_t(16) << 20;
+constexpr size_t kSplitPlanBytes = size_t(4) << 20;
+
+// assigns tile0/tiles_m/tiles_n/ksplit; returns total tiles; `red` receives
+// the reduction descriptors of split problems (tile0 over output tiles)
 template <typename T>
-int finalize_gemm(std::vector<GemmDesc<T>>& v) {
+int finalize_gemm(std::vector<GemmDesc<T>>& v, T* part, size_t cap, std::vector<GemmDesc<T>>& red, int& rtiles) {
+  red.clear();
+  rtiles = 0;
+  int base = 0;
+  for (const auto& d : v)
+    if (d.m > 0 && d.n > 0) base += cdiv(d.m, kTile) * cdiv(d.n, kTile);
+  const int want = (part && base > 0 && 2 * base <= kSplitTarget) ? kSplitTarget / base : 1;
+  size_t used = 0;
   int t = 0;
   std::vector<GemmDesc<T>> out;
   out.reserve(v.size());
   for (auto& d : v) {
     if (d.m <= 0 || d.n <= 0) continue;
     d.tiles_m = cdiv(d.m, kTile);
+    d.tiles_n = cdiv(d.n, kTile);
+    d.ksplit = 1;
+    d.kchunk = 0;
+    d.part = nullptr;
+    if (want > 1 && !d.kdev && d.k >= 2 * kSplitChunk) {
+      int sp = std::min(want, d.k / kSplitChunk);
+      const int chunk = cdiv(cdiv(d.k, sp), 16) * 16;
+      sp = cdiv(d.k, chunk);
+      const size_t need = (size_t)sp * d.m * d.n;
+      if (sp > 1 && used + need <= cap) {
+        d.ksplit = sp;
+        d.kchunk = chunk;
+        d.part = part + used;
+        used += need;
+      }
+    }
     d.tile0 = t;
-    t += d.tiles_m * cdiv(d.n, kTile);
+    t += d.tiles_m * d.tiles_n * d.ksplit;
     out.push_back(d);
+    if (d.ksplit > 1) {
+      GemmDesc<T> r = d;
+      r.tile0 = rtiles;
+      rtiles += d.tiles_m * d.tiles_n;
+      red.push_back(r);
+    }
   }
   v.swap(out);
   return t;
@@ -150,12 +193,22 @@ int finalize_copy(std::vector<CopyDesc<S, D>>& v) {
 // a batch of GEMMs / copies recorded for a later upload
 template <typename T>
 struct GemmBatch {
-  std::vector<GemmDesc<T>> v;
-  size_t off = 0;
-  int tiles = 0, n = 0;
-  void stage(Blob& b) { tiles = finalize_gemm(v); n = (int)v.size(); off = b.add(v); }
+  std::vector<GemmDesc<T>> v, red;
+  size_t off = 0, roff = 0;
+  int tiles = 0, n = 0, rtiles = 0, rn = 0;
+  // split: split-K partial-sum area (reused by every batch of a stream)
+  void stage(Blob& b, const DevBuf* split = nullptr) {
+    T* part = split ? static_cast<T*>(split->p) : nullptr;
+    const size_t cap = split ? split->bytes / sizeof(T) : 0;
+    tiles = finalize_gemm(v, part, cap, red, rtiles);
+    n = (int)v.size();
+    off = b.add(v);
+    rn = (int)red.size();
+    if (rn) roff = b.add(red);
+  }
   void launch(const char* base, hipStream_t st) const {
     if (n) launch_gemm<T>(reinterpret_cast<const GemmDesc<T>*>(base + off), n, tiles, st);
+    if (rn) launch_gemm_reduce<T>(reinterpret_cast<const GemmDesc<T>*>(base + roff), rn, rtiles, st);
   }
 };
 template <typename S, typename D>
@@ -202,16 +255,26 @@ class Numeric : public NumericBase {
   std::vector<FN> fn;
   Arena arena;
   DescPool dp;
-  DevBuf ws, scrA, scrB, d_asm_dest, d_asm_src, d_relmap, d_bdlr;
+  DevBuf ws, scrA, scrB, d_asm_dest, d_asm_src, d_relmap;
+  DevBuf split;                   // split-K partial sums of the factor's GEMM batches
   std::vector<int64_t> relmap_off;
   std::vector<int64_t> asm_lvl_off;
-  std::vector<int> bI, bIptr, bJ, bJptr;
-  int64_t bdlr_J_base = 0;
+  struct LevelBdlr {              // BDLR sets of one level's HODLR blocks
+    std::vector<int> I, Iptr, J, Jptr;
+    std::map<int, int> first;     // front -> index of its first block in this level
+  };
+  std::vector<LevelBdlr> lvb;
+  std::thread worker;
+  std::mutex mu;
+  std::condition_variable cv;
+  int lvb_ready = 0;
+  bool worker_failed = false;
+  std::atomic<bool> cancel{false};
   hipStream_t st = nullptr;
   T* wsT = nullptr;
 
   void dense_level(const std::vector<int>& D);
-  void hodlr_level(const std::vector<int>& H);
+  void hodlr_level(const std::vector<int>& H, int h);
 
   struct Rec {
     int kind;                 // 0 gemm T, 1 copy TT, 2 vec_asm, 3 vec_gather
@@ -220,7 +283,7 @@ class Numeric : public NumericBase {
   };
   struct Plan {
     int nrhs = 0;
-    DevBuf work;
+    DevBuf work, split;
     char* desc = nullptr;
     DescPool dp;
     std::vector<Rec> recs;
@@ -296,6 +359,7 @@ Numeric<T>::Numeric(const Symbolic& s, const double* vals, const mf_opts& o) {
       peak = std::max(peak, pos + tot);
     }
     ws.alloc(std::max<int64_t>(peak, 1) * sizeof(T), &ms);
+    split.alloc(kSplitFactorBytes, &ms);
     info.workspace_bytes = peak * (int64_t)sizeof(T);
   }
   wsT = ws.as<T>();
@@ -336,14 +400,40 @@ Numeric<T>::Numeric(const Symbolic& s, const double* vals, const mf_opts& o) {
     HIPCHK(hipMemcpyAsync(d_relmap.p, rm.data(), rm.size() * sizeof(int), hipMemcpyHostToDevice, st));
     HIPCHK(hipStreamSynchronize(st));
   }
+  // BDLR sets are host graph work: a worker thread produces them level by
+  // level while the device factors the levels below.
+  lvb.assign(H, {});
+  struct Joiner {
+    Numeric* self;
+    ~Joiner() {
+      self->cancel = true;
+      if (self->worker.joinable()) self->worker.join();
+    }
+  } joiner{this};
   if (hodlr) {
-    bdlr_sets(s, o.bdlr_depth, o.bdlr_cap, bI, bIptr, bJ, bJptr);
-    std::vector<int> all(bI);
-    bdlr_J_base = (int64_t)all.size();
-    all.insert(all.end(), bJ.begin(), bJ.end());
-    d_bdlr.alloc(std::max<size_t>(all.size(), 1) * sizeof(int), &ms);
-    HIPCHK(hipMemcpyAsync(d_bdlr.p, all.data(), all.size() * sizeof(int), hipMemcpyHostToDevice, st));
-    HIPCHK(hipStreamSynchronize(st));
+    worker = std::thread([this, H]() {
+      try {
+        BdlrScratch w;
+        for (int h = 0; h < H && !cancel; ++h) {
+          LevelBdlr& lb = lvb[h];
+          lb.Iptr.assign(1, 0);
+          lb.Jptr.assign(1, 0);
+          for (int p : sym->levels[h]) {
+            if (fn[p].dense) continue;
+            lb.first[p] = (int)lb.Iptr.size() - 1;
+            bdlr_front(*sym, p, opts.bdlr_depth, opts.bdlr_cap, w, lb.I, lb.Iptr, lb.J, lb.Jptr);
+          }
+          std::lock_guard<std::mutex> g(mu);
+          lvb_ready = h + 1;
+          cv.notify_all();
+        }
+      } catch (...) {
+        std::lock_guard<std::mutex> g(mu);
+        worker_failed = true;
+        lvb_ready = H;
+        cv.notify_all();
+      }
+    });
   }
   ranks.assign(s.nblocks, -1);
 
@@ -380,7 +470,7 @@ Numeric<T>::Numeric(const Symbolic& s, const double* vals, const mf_opts& o) {
     std::vector<int> D, Hf;
     for (int p : L) (fn[p].dense ? D : Hf).push_back(p);
     dense_level(D);
-    hodlr_level(Hf);
+    hodlr_level(Hf, h);
   }
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(st));
@@ -393,7 +483,6 @@ Numeric<T>::Numeric(const Symbolic& s, const double* vals, const mf_opts& o) {
   scrB.release();
   d_asm_dest.release();
   d_asm_src.release();
-  d_bdlr.release();
   info.persistent_bytes = arena.used;
   info.peak_bytes = ms.peak;
   int dn = 0, hn = 0;
@@ -461,8 +550,8 @@ void Numeric<T>::dense_level(const std::vector<int>& D) {
     }
     sp.pn = (int)pv.size();
     sp.po = b.add(pv);
-    sp.panel.stage(b);
-    sp.syrk.stage(b);
+    sp.panel.stage(b, &split);
+    sp.syrk.stage(b, &split);
     steps.push_back(std::move(sp));
   }
   // recursive doubling for the off-diagonal blocks of L_pp^{-1}:
@@ -496,8 +585,8 @@ void Numeric<T>::dense_level(const std::vector<int>& D) {
         tp += (int64_t)cs * sz;
       }
     }
-    dd.t1.stage(b);
-    dd.x.stage(b);
+    dd.t1.stage(b, &split);
+    dd.x.stage(b, &split);
     dbl.push_back(std::move(dd));
   }
   CopyBatch<T, T> lfp;
@@ -522,13 +611,30 @@ void Numeric<T>::dense_level(const std::vector<int>& D) {
 
 // ------------------------------------------------------------ HODLR fronts
 template <typename T>
-void Numeric<T>::hodlr_level(const std::vector<int>& Hs) {
+void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
   if (Hs.empty()) return;
   const Symbolic& s = *sym;
   const double eps = opts.eps;
   const bool adaptive = opts.adaptive != 0;
+  {
+    std::unique_lock<std::mutex> lk(mu);
+    cv.wait(lk, [&] { return lvb_ready > h; });
+    if (worker_failed) throw Err{MF_ENOMEM, "BDLR set construction failed"};
+  }
+  const LevelBdlr& lb = lvb[h];
+  const int* dI;
+  const int* dJ;
+  {
+    Blob bb;
+    const size_t oi = bb.add(lb.I), oj = bb.add(lb.J);
+    const char* base = dp.upload(bb, st);
+    dI = reinterpret_cast<const int*>(base + oi);
+    dJ = reinterpret_cast<const int*>(base + oj);
+  }
+  const std::vector<int>& bIptr = lb.Iptr;
+  const std::vector<int>& bJptr = lb.Jptr;
   struct BR {
-    int p, bi, gb, nI, nJ, kcap, capr;
+    int p, bi, gb, lk, nI, nJ, kcap, capr;
     bool full;                 // whole block held in registers by one workgroup
     int *pr, *pc, *rank1, *rank;
     double* u11;
@@ -540,9 +646,9 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs) {
     for (int bi = 0; bi < (int)f.blocks.size(); ++bi) {
       const Block& B = f.blocks[bi];
       BR x{};
-      x.p = p; x.bi = bi; x.gb = s.block_base[p] + bi;
-      x.nI = bIptr[x.gb + 1] - bIptr[x.gb];
-      x.nJ = bJptr[x.gb + 1] - bJptr[x.gb];
+      x.p = p; x.bi = bi; x.gb = s.block_base[p] + bi; x.lk = lb.first.at(p) + bi;
+      x.nI = bIptr[x.lk + 1] - bIptr[x.lk];
+      x.nJ = bJptr[x.lk + 1] - bJptr[x.lk];
       x.kcap = std::min(x.nI, x.nJ);
       x.capr = std::max(std::min({B.nr, B.nc, opts.rank_cap}), x.kcap);
       x.full = B.nr <= skreg_full_rows<T>() && B.nc <= skreg_full_cols<T>();
@@ -583,15 +689,13 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs) {
   std::vector<Phase2Desc<T>> p2;
   GemmBatch<T> resid;
   int rmax1 = 1, wgs = 0, maxrc = 1;
-  const int* dI = d_bdlr.as<int>();
-  const int* dJ = d_bdlr.as<int>() + bdlr_J_base;
   for (auto& x : br) {
     const Block& B = s.fronts[x.p].blocks[x.bi];
     const FN& fx = fn[x.p];
     SkRegDesc<T> d{};
     d.F = fx.F; d.ld = fx.ld; d.r0 = B.r0; d.nr = B.nr; d.c0 = B.c0; d.nc = B.nc;
-    d.I = dI + bIptr[x.gb]; d.nI = x.nI;
-    d.J = dJ + bJptr[x.gb]; d.nJ = x.nJ;
+    d.I = dI + bIptr[x.lk]; d.nI = x.nI;
+    d.J = dJ + bJptr[x.lk]; d.nJ = x.nJ;
     d.piv_r = x.pr; d.piv_c = x.pc;
     d.rank1 = x.rank1; d.rank = x.rank; d.u11 = x.u11; d.cap = x.capr;
     if (x.full) {
@@ -628,7 +732,7 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs) {
     throw Err{MF_EINVAL, "phase-1 rank bound too large for LDS: lower bdlr_cap"};
   if (maxrc > kLdsMax) throw Err{MF_EINVAL, "block too large for the phase-2 kernel"};
   const size_t okf = b.add(skf), okh = b.add(skh), osf = b.add(sf), op2 = b.add(p2);
-  resid.stage(b);
+  resid.stage(b, &split);
   const char* base = dp.upload(b, st);
   int* dstat = d_status.as<int>();
   launch_skreg_full<T>(reinterpret_cast<const SkRegDesc<T>*>(base + okf), (int)skf.size(), eps, adaptive ? 1 : 0,
@@ -743,8 +847,8 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs) {
   }
   const size_t oleaf = b2.add(leaves);
   cp.stage(b2);
-  lg1.stage(b2);
-  lg2.stage(b2);
+  lg1.stage(b2, &split);
+  lg2.stage(b2, &split);
   const char* base2 = dp.upload(b2, st);
   cp.launch(base2, st);
   launch_potrf<T>(reinterpret_cast<const PotrfDesc<T>*>(base2 + oleaf), (int)leaves.size(), s.leaf,
@@ -814,11 +918,11 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs) {
       }
       cK.v.push_back(cd<double, T>(Kinv, n2, x.nodeK[nr.i], n2, n2, n2));
     }
-    gP.stage(b3);
+    gP.stage(b3, &split);
     const size_t ocap = b3.add(capd), oinv = b3.add(invd);
-    gQ.stage(b3);
+    gQ.stage(b3, &split);
     cQ.stage(b3);
-    gC.stage(b3);
+    gC.stage(b3, &split);
     cK.stage(b3);
     const char* base3 = dp.upload(b3, st);
     gP.launch(base3, st);
@@ -879,11 +983,11 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs) {
                             GF_LOWER_C));
     }
     c64.stage(b4);
-    gS.stage(b4);
-    gWt.stage(b4);
+    gS.stage(b4, &split);
+    gWt.stage(b4, &split);
     cW.stage(b4);
-    gff.stage(b4);
-    gup.stage(b4);
+    gff.stage(b4, &split);
+    gup.stage(b4, &split);
     const char* base4 = dp.upload(b4, st);
     c64.launch(base4, st);
     gS.launch(base4, st);
@@ -928,9 +1032,11 @@ typename Numeric<T>::Plan* Numeric<T>::get_plan(int nrhs) {
   T* wk = static_cast<T*>(pl->work.p);
   pl->xn = wk;
   Blob b;
+  pl->split.alloc(kSplitPlanBytes, &ms);
   auto rec_gemm = [&](GemmBatch<T>& g) {
-    g.stage(b);
+    g.stage(b, &pl->split);
     if (g.n) pl->recs.push_back({0, g.off, g.n, g.tiles});
+    if (g.rn) pl->recs.push_back({4, g.roff, g.rn, g.rtiles});
   };
   auto rec_copy = [&](CopyBatch<T, T>& c) {
     c.stage(b);
@@ -1088,6 +1194,7 @@ void Numeric<T>::apply(int nrhs, const double* r, double* z, hipStream_t stream)
     const char* base = pl->desc + rc.off;
     switch (rc.kind) {
       case 0: launch_gemm<T>(reinterpret_cast<const GemmDesc<T>*>(base), rc.n, rc.tiles, stream); break;
+      case 4: launch_gemm_reduce<T>(reinterpret_cast<const GemmDesc<T>*>(base), rc.n, rc.tiles, stream); break;
       case 1: launch_copy<T, T>(reinterpret_cast<const CopyDesc<T, T>*>(base), rc.n, rc.tiles, stream); break;
       case 2: launch_vec_asm<T>(reinterpret_cast<const VecAsmDesc<T>*>(base), rc.n, nrhs, stream); break;
       case 3: launch_vec_gather<T>(reinterpret_cast<const VecGatherDesc<T>*>(base), rc.n, pl->xn, N, nrhs, stream);

@@ -44,8 +44,10 @@ struct NDCtx {
     return best;
   }
 
-  void sort_by_axis(std::vector<int>& ids, int ax) const {
-    std::sort(ids.begin(), ids.end(), [&](int x, int y) {
+  // places the element of rank m in (coordinate, id) order at ids[m], smaller
+  // ones before it, larger ones after (the order inside each part is free)
+  void select_by_axis(std::vector<int>& ids, size_t m, int ax) const {
+    std::nth_element(ids.begin(), ids.begin() + m, ids.end(), [&](int x, int y) {
       double cx = co(x, ax), cy = co(y, ax);
       if (cx != cy) return cx < cy;
       return x < y;
@@ -59,8 +61,8 @@ struct NDCtx {
       return;
     }
     int ax = extent_axis(ids);
-    sort_by_axis(ids, ax);
     size_t m = ids.size() / 2;
+    select_by_axis(ids, m, ax);   // first half = the m smallest in (coordinate, id) order
     kd_order(std::vector<int>(ids.begin(), ids.begin() + m), out);
     kd_order(std::vector<int>(ids.begin() + m, ids.end()), out);
   }
@@ -76,7 +78,7 @@ struct NDCtx {
     if ((int)S.size() <= leaf) return make_leaf(S);
     int ax = extent_axis(S);
     std::vector<int> srt(S);
-    sort_by_axis(srt, ax);
+    select_by_axis(srt, S.size() / 2, ax);
     double c = co(srt[S.size() / 2], ax);
     std::vector<int> L, R;
     for (int v : S) (co(v, ax) < c ? L : R).push_back(v);
@@ -139,12 +141,18 @@ std::string validate(int n, const int32_t* rowptr, const int32_t* colind) {
     }
     if (!diag) return "missing diagonal entry in row " + std::to_string(i);
   }
+  // symmetry: the transpose, built by counting sort (columns come out sorted
+  // within each row), must reproduce the pattern exactly
+  std::vector<int> tp(n + 1, 0), tc(rowptr[n]);
+  for (int k = 0; k < rowptr[n]; ++k) tp[colind[k] + 1]++;
+  for (int i = 0; i < n; ++i) tp[i + 1] += tp[i];
+  std::vector<int> fill(tp.begin(), tp.end() - 1);
   for (int i = 0; i < n; ++i)
-    for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
-      int j = colind[k];
-      if (!std::binary_search(colind + rowptr[j], colind + rowptr[j + 1], i))
-        return "pattern is not symmetric";
-    }
+    for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) tc[fill[colind[k]]++] = i;
+  for (int i = 0; i <= n; ++i)
+    if (tp[i] != rowptr[i]) return "pattern is not symmetric";
+  for (int k = 0; k < rowptr[n]; ++k)
+    if (tc[k] != colind[k]) return "pattern is not symmetric";
   return "";
 }
 
@@ -242,6 +250,11 @@ std::string analyze(int n, const int32_t* rowptr, const int32_t* colind, const d
   s.block_base[nfr] = nb;
   s.nblocks = nb;
   // assembly map: lower entries in CSR order
+  const size_t nlow = (size_t)(s.nnz + n) / 2;
+  s.asm_front.reserve(nlow);
+  s.asm_row.reserve(nlow);
+  s.asm_col.reserve(nlow);
+  s.asm_src.reserve(nlow);
   for (int r = 0; r < n; ++r)
     for (int k = rowptr[r]; k < rowptr[r + 1]; ++k) {
       int i = s.iperm[r], j = s.iperm[colind[k]];
@@ -272,66 +285,80 @@ void compute_bdlr(Symbolic& s, int depth, int cap) {
   s.bdlr_cap = cap;
 }
 
+// One front: appends the sets of each of its blocks to I/J and one offset
+// per block to Iptr/Jptr.
+void bdlr_front(const Symbolic& s, int p, int depth, int cap, BdlrScratch& w, std::vector<int>& outI,
+                std::vector<int>& outIptr, std::vector<int>& outJ, std::vector<int>& outJptr) {
+  const long long INF = std::numeric_limits<long long>::max();
+  const Front& f = s.fronts[p];
+  const int m = f.n();
+  if ((int)w.pos_of.size() != s.n) w.pos_of.assign(s.n, -1);
+  for (int a = 0; a < m; ++a) w.pos_of[f.global(a)] = a;
+  w.adjp.assign(m + 1, 0);
+  w.adj.clear();
+  for (int a = 0; a < m; ++a) {
+    int g = f.global(a);
+    for (int k = s.prow[g]; k < s.prow[g + 1]; ++k) {
+      int b = w.pos_of[s.pcol[k]];
+      if (b >= 0) w.adj.push_back(b);
+    }
+    w.adjp[a + 1] = (int)w.adj.size();
+  }
+  // Multi-source BFS from [lo, lo+cnt).  Once `cap` nodes of the target
+  // range [tlo, tlo+tcnt) are settled, the selection (cap smallest
+  // (distance, position)) can no longer change: stop after that layer.
+  auto bfs = [&](int lo, int cnt, int tlo, int tcnt) {
+    w.dist.assign(m, -1);
+    w.frontier.clear();
+    for (int a = lo; a < lo + cnt; ++a) { w.dist[a] = 0; w.frontier.push_back(a); }
+    int settled = 0;
+    for (int k = 1;; ++k) {
+      if (depth >= 0 && k > depth) break;
+      w.nxt.clear();
+      for (int v : w.frontier)
+        for (int e = w.adjp[v]; e < w.adjp[v + 1]; ++e) {
+          int u = w.adj[e];
+          if (w.dist[u] < 0) {
+            w.dist[u] = k;
+            w.nxt.push_back(u);
+            if (u >= tlo && u < tlo + tcnt) ++settled;
+          }
+        }
+      if (w.nxt.empty() || settled >= cap) break;
+      w.frontier.swap(w.nxt);
+    }
+  };
+  auto pick = [&](int lo, int cnt, std::vector<int>& out) {
+    std::vector<std::pair<long long, int>> cand;
+    for (int a = lo; a < lo + cnt; ++a) {
+      int d = w.dist[a];
+      if (depth >= 0) { if (d >= 1 && d <= depth) cand.push_back({d, a}); }
+      else cand.push_back({d < 0 ? INF : (long long)d, a});
+    }
+    size_t k = std::min(cand.size(), (size_t)cap);
+    std::partial_sort(cand.begin(), cand.begin() + k, cand.end());
+    std::vector<int> sel;
+    for (size_t i = 0; i < k; ++i) sel.push_back(cand[i].second);
+    std::sort(sel.begin(), sel.end());
+    out.insert(out.end(), sel.begin(), sel.end());
+  };
+  for (const Block& b : f.blocks) {
+    bfs(b.c0, b.nc, b.r0, b.nr);
+    pick(b.r0, b.nr, outI);
+    outIptr.push_back((int)outI.size());
+    bfs(b.r0, b.nr, b.c0, b.nc);
+    pick(b.c0, b.nc, outJ);
+    outJptr.push_back((int)outJ.size());
+  }
+  for (int a = 0; a < m; ++a) w.pos_of[f.global(a)] = -1;
+}
+
 void bdlr_sets(const Symbolic& s, int depth, int cap, std::vector<int>& outI, std::vector<int>& outIptr,
                std::vector<int>& outJ, std::vector<int>& outJptr) {
   outI.clear(); outJ.clear();
   outIptr.assign(1, 0); outJptr.assign(1, 0);
-  std::vector<int> pos_of(s.n, -1);
-  std::vector<int> adjp, adj, dist, frontier, nxt;
-  const long long INF = std::numeric_limits<long long>::max();
-  for (const Front& f : s.fronts) {
-    const int m = f.n();
-    for (int a = 0; a < m; ++a) pos_of[f.global(a)] = a;
-    adjp.assign(m + 1, 0);
-    adj.clear();
-    for (int a = 0; a < m; ++a) {
-      int g = f.global(a);
-      for (int k = s.prow[g]; k < s.prow[g + 1]; ++k) {
-        int b = pos_of[s.pcol[k]];
-        if (b >= 0) adj.push_back(b);
-      }
-      adjp[a + 1] = (int)adj.size();
-    }
-    auto bfs = [&](int lo, int cnt) {
-      dist.assign(m, -1);
-      frontier.clear();
-      for (int a = lo; a < lo + cnt; ++a) { dist[a] = 0; frontier.push_back(a); }
-      for (int k = 1;; ++k) {
-        if (depth >= 0 && k > depth) break;
-        nxt.clear();
-        for (int v : frontier)
-          for (int e = adjp[v]; e < adjp[v + 1]; ++e) {
-            int w = adj[e];
-            if (dist[w] < 0) { dist[w] = k; nxt.push_back(w); }
-          }
-        if (nxt.empty()) break;
-        frontier.swap(nxt);
-      }
-    };
-    auto pick = [&](int lo, int cnt, std::vector<int>& out) {
-      std::vector<std::pair<long long, int>> cand;
-      for (int a = lo; a < lo + cnt; ++a) {
-        int d = dist[a];
-        if (depth >= 0) { if (d >= 1 && d <= depth) cand.push_back({d, a}); }
-        else cand.push_back({d < 0 ? INF : (long long)d, a});
-      }
-      std::sort(cand.begin(), cand.end());
-      size_t k = std::min(cand.size(), (size_t)cap);
-      std::vector<int> sel;
-      for (size_t i = 0; i < k; ++i) sel.push_back(cand[i].second);
-      std::sort(sel.begin(), sel.end());
-      out.insert(out.end(), sel.begin(), sel.end());
-    };
-    for (const Block& b : f.blocks) {
-      bfs(b.c0, b.nc);
-      pick(b.r0, b.nr, outI);
-      outIptr.push_back((int)outI.size());
-      bfs(b.r0, b.nr);
-      pick(b.c0, b.nc, outJ);
-      outJptr.push_back((int)outJ.size());
-    }
-    for (int a = 0; a < m; ++a) pos_of[f.global(a)] = -1;
-  }
+  BdlrScratch w;
+  for (int p = 0; p < (int)s.fronts.size(); ++p) bdlr_front(s, p, depth, cap, w, outI, outIptr, outJ, outJptr);
 }
 
 }  // namespace mfh

@@ -53,6 +53,13 @@ struct Symbolic {
 // Returns "" on success or an error message.
 std::string analyze(int n, const int32_t* rowptr, const int32_t* colind, const double* coords,
                     int dim, int leaf, Symbolic& out);
+// Reusable buffers for BDLR set construction.
+struct BdlrScratch {
+  std::vector<int> pos_of, adjp, adj, dist, frontier, nxt;
+};
+// BDLR sets of the blocks of front p (appended; one Iptr/Jptr entry per block).
+void bdlr_front(const Symbolic& s, int p, int depth, int cap, BdlrScratch& w, std::vector<int>& I,
+                std::vector<int>& Iptr, std::vector<int>& J, std::vector<int>& Jptr);
 // BDLR sets of every block (front order, then block order), front positions.
 void bdlr_sets(const Symbolic& s, int depth, int cap, std::vector<int>& I, std::vector<int>& Iptr,
                std::vector<int>& J, std::vector<int>& Jptr);

@@ -16,21 +16,34 @@ mf_status hip_ok(hipError_t e) {
 
 template <typename T>
 mf_status gemm_t(int m, int n, int k, const void* A, int lda, int opA, const void* B, int ldb, int opB, void* C,
-                 int ldc, double alpha, double beta, int flags) {
+                 int ldc, double alpha, double beta, int flags, int kchunk) {
   mfh::GemmDesc<T> d{};
   d.A = static_cast<const T*>(A); d.B = static_cast<const T*>(B); d.C = static_cast<T*>(C);
   d.m = m; d.n = n; d.k = k; d.lda = lda; d.ldb = ldb; d.ldc = ldc; d.opA = opA; d.opB = opB;
   d.flags = flags; d.alpha = alpha; d.beta = beta;
   d.tiles_m = (m + mfh::kTile - 1) / mfh::kTile;
+  d.tiles_n = (n + mfh::kTile - 1) / mfh::kTile;
   d.tile0 = 0;
-  const int tiles = d.tiles_m * ((n + mfh::kTile - 1) / mfh::kTile);
+  d.ksplit = 1;
+  if (kchunk > 0 && k > 0) {
+    d.ksplit = (k + kchunk - 1) / kchunk;
+    d.kchunk = kchunk;
+  }
+  const int otiles = d.tiles_m * d.tiles_n;
+  if (otiles == 0) return MF_OK;
   mfh::GemmDesc<T>* dd = nullptr;
   mf_status s = hip_ok(hipMalloc(&dd, sizeof(d)));
   if (s != MF_OK) return s;
+  if (d.ksplit > 1) {
+    s = hip_ok(hipMalloc(&d.part, (size_t)d.ksplit * m * n * sizeof(T)));
+    if (s != MF_OK) { hipFree(dd); return s; }
+  }
   hipMemcpy(dd, &d, sizeof(d), hipMemcpyHostToDevice);
-  mfh::launch_gemm<T>(dd, 1, tiles, nullptr);
+  mfh::launch_gemm<T>(dd, 1, otiles * d.ksplit, nullptr);
+  if (d.ksplit > 1) mfh::launch_gemm_reduce<T>(dd, 1, otiles, nullptr);
   s = hip_ok(hipDeviceSynchronize());
   hipFree(dd);
+  if (d.part) hipFree(d.part);
   return s;
 }
 
@@ -87,7 +100,9 @@ mf_status skel_t(void* F, int ld, int r0, int nr, int c0, int nc, const int* I, 
   gdsc.C = static_cast<T*>(F) + r0 + (size_t)c0 * ld; gdsc.ldc = ld;
   gdsc.m = nr; gdsc.n = nc; gdsc.k = kcap; gdsc.kdev = rank1; gdsc.alpha = -1.0; gdsc.beta = 1.0;
   gdsc.tiles_m = (nr + 63) / 64;
-  const int gtiles = gdsc.tiles_m * ((nc + 63) / 64);
+  gdsc.tiles_n = (nc + 63) / 64;
+  gdsc.ksplit = 1;
+  const int gtiles = gdsc.tiles_m * gdsc.tiles_n;
   mfh::Phase2Desc<T> pd{};
   pd.F = static_cast<T*>(F); pd.ld = ld; pd.r0 = r0; pd.nr = nr; pd.c0 = c0; pd.nc = nc;
   pd.piv_r = pr; pd.piv_c = pc; pd.rank1 = rank1; pd.u11 = u11; pd.U = fd.U; pd.ldu = nr; pd.V = fd.V;
@@ -138,10 +153,11 @@ mf_status mfh_test_mfma_layout(int32_t precision, int32_t* rows, int32_t* cols, 
 
 mf_status mfh_test_gemm(int32_t precision, int32_t m, int32_t n, int32_t k, const void* A, int32_t lda, int32_t opA,
                         const void* B, int32_t ldb, int32_t opB, void* C, int32_t ldc, double alpha, double beta,
-                        int32_t flags) {
-  if (m < 0 || n < 0 || k < 0 || !C) return MF_EINVAL;
-  if (precision == MF_FP64) return gemm_t<double>(m, n, k, A, lda, opA, B, ldb, opB, C, ldc, alpha, beta, flags);
-  return gemm_t<float>(m, n, k, A, lda, opA, B, ldb, opB, C, ldc, alpha, beta, flags);
+                        int32_t flags, int32_t kchunk) {
+  if (m < 0 || n < 0 || k < 0 || !C || kchunk < 0 || kchunk % 16 != 0) return MF_EINVAL;
+  if (precision == MF_FP64)
+    return gemm_t<double>(m, n, k, A, lda, opA, B, ldb, opB, C, ldc, alpha, beta, flags, kchunk);
+  return gemm_t<float>(m, n, k, A, lda, opA, B, ldb, opB, C, ldc, alpha, beta, flags, kchunk);
 }
 
 mf_status mfh_test_potrf(int32_t precision, int32_t n, void* A, int32_t lda, void* Inv, int32_t ldi,

@@ -43,16 +43,19 @@ def test_mfma_accumulator_layout(gpu_lib, prec):
     assert np.array_equal(r, a), (r.reshape(64, 4).tolist())
 
 
+# (m, n, k, opA, opB, flags, kchunk); kchunk > 0 exercises split K
 GEMM_CASES = [
-    (1, 1, 1, 0, 0, 0), (64, 64, 64, 0, 0, 0), (100, 37, 70, 0, 1, 0), (130, 1, 257, 1, 0, 0),
-    (5, 200, 3, 1, 1, 0), (129, 129, 65, 0, 1, 1), (96, 20, 96, 0, 0, 2), (96, 20, 96, 1, 0, 4),
-    (50, 70, 70, 0, 1, 16), (50, 70, 70, 0, 0, 8), (77, 77, 0, 0, 0, 0),
+    (1, 1, 1, 0, 0, 0, 0), (64, 64, 64, 0, 0, 0, 0), (100, 37, 70, 0, 1, 0, 0), (130, 1, 257, 1, 0, 0, 0),
+    (5, 200, 3, 1, 1, 0, 0), (129, 129, 65, 0, 1, 1, 0), (96, 20, 96, 0, 0, 2, 0), (96, 20, 96, 1, 0, 4, 0),
+    (50, 70, 70, 0, 1, 16, 0), (50, 70, 70, 0, 0, 8, 0), (77, 77, 0, 0, 0, 0, 0),
+    (100, 16, 1000, 1, 0, 0, 128), (130, 130, 300, 0, 1, 1, 64), (96, 20, 96, 0, 0, 2, 32),
+    (96, 20, 96, 1, 0, 4, 16), (50, 70, 70, 0, 1, 16, 16), (70, 50, 333, 1, 1, 8, 48), (7, 9, 20, 0, 0, 0, 64),
 ]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("m,n,k,opA,opB,flags", GEMM_CASES)
-def test_gemm(gpu_lib, prec, m, n, k, opA, opB, flags):
+@pytest.mark.parametrize("m,n,k,opA,opB,flags,kchunk", GEMM_CASES)
+def test_gemm(gpu_lib, prec, m, n, k, opA, opB, flags, kchunk):
     import torch
     mfh = gpu_lib
     dt = torch.float64 if prec == "fp64" else torch.float32
@@ -74,7 +77,7 @@ def test_gemm(gpu_lib, prec, m, n, k, opA, opB, flags):
     dA, dB, dC = _dev(A, lda, dt), _dev(B, ldb, dt), _dev(C0, ldc, dt)
     alpha, beta = -0.75, 0.5
     st = mfh.load().mfh_test_gemm(0 if prec == "fp64" else 1, m, n, k, _p(dA), lda, opA, _p(dB), ldb, opB, _p(dC),
-                                  ldc, alpha, beta, flags)
+                                  ldc, alpha, beta, flags, kchunk)
     assert st == 0
     # float64 reference from the same (rounded) inputs
     cast = np.float32 if prec == "fp32" else np.float64
