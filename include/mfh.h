@@ -62,7 +62,8 @@ typedef struct {
   int32_t precision;    /* MF_FP64 or MF_FP32 (factors and apply)                   */
   int32_t n_c;          /* HODLR only: fronts with n_p + n_f < n_c are dense (Table 1 "n_c") */
   int32_t bdlr_depth;   /* BDLR depth d (Sec. 2.2, Table 1 "d"); < 0: every row/column    */
-  int32_t bdlr_cap;     /* at most this many BDLR rows (and columns) per block              */
+  int32_t bdlr_cap;     /* at most this many BDLR rows (and columns) per block; 0: the most */
+                        /* the pivot kernel takes (128 float64, 192 float32)                */
   int32_t adaptive;     /* 1: continue complete pivoting over the whole block until the
                            pivot-ratio rule holds there (max-norm error < eps*|u_11|)     */
   int32_t rank_cap;     /* capacity per block rank; exceeding it -> MF_ECAPACITY            */
@@ -100,8 +101,9 @@ typedef struct {
   double factor_seconds;      /* wall time of mf_factor (host clock, synchronised)                   */
 } mf_factor_info;
 
-/* Fill *o with defaults: HODLR, FP32, n_c 0, d 4, cap 128, adaptive 1,
- * rank_cap 256, eps 1e-4, null stream. */
+/* Fill *o with defaults: HODLR, FP32, n_c 0, d -1 (no depth limit), cap 0
+ * (the pivot kernel's maximum), adaptive 1, rank_cap 256, eps 1e-4, null
+ * stream. */
 mf_status mf_opts_default(mf_opts* o);
 mf_status mf_gmres_opts_default(mf_gmres_opts* o);
 
@@ -201,6 +203,27 @@ mf_status gmres_solve(mf_numeric_t* f, int32_t nrhs, const double* b, double* x,
 /* y = A x with the factor's device copy of A (float64 CSR), column-major
  * n x nrhs device arrays; asynchronous on stream. */
 mf_status mf_spmv(mf_numeric_t* f, int32_t nrhs, const double* x, double* y, void* stream);
+
+/*
+ * Kernel timing for roofline reports (process-wide, all handles).
+ * mf_prof_start(names): from now on, every launch of the named device
+ * kernels (comma-separated trace names such as "gemm_kernel<float>" or
+ * "phase2_kernel<float>"; NULL or "" = all timed kernels) is bracketed by
+ * two HIP events recorded on the stream it is launched on, and the host
+ * adds up the launch's algorithmic work (flops; bytes that the operation
+ * must move at least once).  mf_prof_stop waits for the recorded events,
+ * writes one mf_kstat per kernel that ran (at most cap; *n = count) and
+ * stops timing.  Timing adds two event records per timed launch.
+ */
+typedef struct {
+  char name[64];        /* device kernel name as it appears in a kernel trace */
+  int64_t launches;
+  double seconds;       /* sum of event-measured launch durations */
+  double flops;         /* algorithmic floating-point operations, all launches */
+  double bytes;         /* algorithmic bytes moved, all launches */
+} mf_kstat;
+mf_status mf_prof_start(const char* names);
+mf_status mf_prof_stop(mf_kstat* out, int32_t cap, int32_t* n);
 
 const char* mf_last_error(void);
 

@@ -56,6 +56,11 @@ class FactorInfo(ctypes.Structure):
                 ("status_bits", ctypes.c_int32), ("factor_seconds", ctypes.c_double)]
 
 
+class KStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 64), ("launches", ctypes.c_int64), ("seconds", ctypes.c_double),
+                ("flops", ctypes.c_double), ("bytes", ctypes.c_double)]
+
+
 class MfError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{STATUS_NAMES[status] if 0 <= status < len(STATUS_NAMES) else status}: {msg}")
@@ -79,6 +84,8 @@ SIGNATURES = [
     ("mf_apply", _I32, [_P, _I32, _P, _P, _P]),
     ("gmres_solve", _I32, [_P, _I32, _P, _P, _D, ctypes.POINTER(GmresOpts), ctypes.POINTER(GmresInfo)]),
     ("mf_spmv", _I32, [_P, _I32, _P, _P, _P]),
+    ("mf_prof_start", _I32, [ctypes.c_char_p]),
+    ("mf_prof_stop", _I32, [ctypes.POINTER(KStat), _I32, ctypes.POINTER(_I32)]),
     ("mf_last_error", ctypes.c_char_p, []),
     # include/mfh_testing.h
     ("mfh_test_mfma_layout", _I32, [_I32, _P, _P, _P]),
@@ -242,3 +249,22 @@ class Factor:
         if getattr(self, "h", None) and _lib is not None:
             _lib.mf_factor_free(self.h)
             self.h = None
+
+
+def prof_start(names=None):
+    """Time every launch of the named device kernels (None: all) with HIP
+    events on their launch streams, adding up their algorithmic work."""
+    arg = None if not names else ",".join(names if not isinstance(names, str) else [names]).encode()
+    _check(load().mf_prof_start(arg))
+
+
+def prof_stop() -> list:
+    """Stop timing; one dict per kernel that ran: name, launches, seconds,
+    flops, bytes (algorithmic work summed over its launches)."""
+    lib = load()
+    cap = 64
+    arr = (KStat * cap)()
+    n = _I32(0)
+    _check(lib.mf_prof_stop(arr, cap, ctypes.byref(n)))
+    return [{"name": arr[i].name.decode(), "launches": int(arr[i].launches), "seconds": float(arr[i].seconds),
+             "flops": float(arr[i].flops), "bytes": float(arr[i].bytes)} for i in range(min(n.value, cap))]

@@ -2,6 +2,7 @@
 // and keeps a per-thread message for mf_last_error().
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -9,6 +10,7 @@
 
 #include "../../include/mfh.h"
 #include "numeric.h"
+#include "prof.h"
 #include "symbolic.h"
 
 struct mf_symbolic_s {
@@ -58,8 +60,8 @@ mf_status mf_opts_default(mf_opts* o) {
   o->method = MF_METHOD_HODLR;
   o->precision = MF_FP32;
   o->n_c = 0;
-  o->bdlr_depth = 4;
-  o->bdlr_cap = 128;
+  o->bdlr_depth = -1;
+  o->bdlr_cap = 0;
   o->adaptive = 1;
   o->rank_cap = 256;
   o->eps = 1e-4;
@@ -181,9 +183,10 @@ mf_status mf_factor(const mf_symbolic_t* sh, const double* vals, double eps, int
   if (leaf != 0 && leaf != sh->s.leaf) return fail(MF_EINVAL, "leaf must be 0 or the analysis leaf size");
   if (o.method == MF_METHOD_HODLR) {
     if (sh->s.leaf > 128) return fail(MF_EINVAL, "HODLR leaves are limited to 128");
-    if (o.bdlr_cap < 1 || o.rank_cap < 1) return fail(MF_EINVAL, "bdlr_cap and rank_cap must be >= 1");
+    if (o.bdlr_cap < 0 || o.rank_cap < 1) return fail(MF_EINVAL, "bdlr_cap must be >= 0 and rank_cap >= 1");
     if (o.rank_cap > 512) return fail(MF_EINVAL, "rank_cap is limited to 512");
-    const int maxcap = o.precision == MF_FP64 ? 126 : 180;
+    const int maxcap = o.precision == MF_FP64 ? 128 : 192;   // B_hat held by one workgroup
+    if (o.bdlr_cap == 0) o.bdlr_cap = maxcap;
     if (o.bdlr_cap > maxcap) return fail(MF_EINVAL, "bdlr_cap too large for the LDS pivot kernel");
   }
   mf_status g = gpu_present();
@@ -238,6 +241,31 @@ mf_status gmres_solve(mf_numeric_t* f, int32_t nrhs, const double* b, double* x,
   f->n->gmres(nrhs, b, x, tol, o, info, &s);
   if (s == MF_ENOCONV) return fail(MF_ENOCONV, "GMRES did not reach tol within maxit");
   return s;
+  MF_GUARD_END
+}
+
+mf_status mf_prof_start(const char* names) {
+  MF_GUARD_BEGIN
+  mfh::prof_start(names ? std::string(names) : std::string());
+  return MF_OK;
+  MF_GUARD_END
+}
+
+mf_status mf_prof_stop(mf_kstat* out, int32_t cap, int32_t* n) {
+  MF_GUARD_BEGIN
+  if (cap < 0 || (cap > 0 && !out)) return fail(MF_EINVAL, "bad output array");
+  const auto t = mfh::prof_stop();
+  const int m = std::min<int>(cap, (int)t.size());
+  for (int i = 0; i < m; ++i) {
+    std::memset(&out[i], 0, sizeof(mf_kstat));
+    std::strncpy(out[i].name, mfh::prof_name(t[i].kind), sizeof(out[i].name) - 1);
+    out[i].launches = t[i].launches;
+    out[i].seconds = t[i].seconds;
+    out[i].flops = t[i].flops;
+    out[i].bytes = t[i].bytes;
+  }
+  if (n) *n = (int32_t)t.size();
+  return MF_OK;
   MF_GUARD_END
 }
 

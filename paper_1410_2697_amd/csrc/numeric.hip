@@ -27,6 +27,7 @@
 #include <thread>
 
 #include "numeric.h"
+#include "prof.h"
 
 namespace mfh {
 
@@ -190,12 +191,65 @@ int finalize_copy(std::vector<CopyDesc<S, D>>& v) {
   return t;
 }
 
+// Algorithmic work of one product: 2 flops per multiply-add that touches a
+// structurally nonzero operand entry and a written C entry (triangular flags
+// and lower-only C count exactly), bytes = operands read once + C written
+// (and read when beta != 0).
+template <typename T>
+double gemm_flops(const GemmDesc<T>& d, int k) {
+  if (d.m <= 0 || d.n <= 0 || k <= 0) return 0.0;
+  const int f = d.flags;
+  const bool lowc = (f & GF_LOWER_C) != 0;
+  const bool af = (f & (GF_A_LOWER | GF_A_UPPER)) != 0, bf = (f & (GF_B_LOWER | GF_B_UPPER)) != 0;
+  auto arange = [&](int i, int& lo, int& hi) {
+    lo = 0; hi = k;
+    if (f & GF_A_LOWER) hi = std::min(hi, i + 1);
+    if (f & GF_A_UPPER) lo = std::max(lo, i);
+  };
+  auto brange = [&](int j, int& lo, int& hi) {
+    lo = 0; hi = k;
+    if (f & GF_B_UPPER) hi = std::min(hi, j + 1);
+    if (f & GF_B_LOWER) lo = std::max(lo, j);
+  };
+  double t = 0.0;
+  if (af && bf) {
+    for (int i = 0; i < d.m; ++i)
+      for (int j = 0; j < (lowc ? std::min(i + 1, d.n) : d.n); ++j) {
+        int a0, a1, b0, b1;
+        arange(i, a0, a1);
+        brange(j, b0, b1);
+        t += std::max(0, std::min(a1, b1) - std::max(a0, b0));
+      }
+  } else if (bf) {
+    for (int j = 0; j < d.n; ++j) {
+      int b0, b1;
+      brange(j, b0, b1);
+      t += (double)(lowc ? std::max(d.m - j, 0) : d.m) * std::max(0, b1 - b0);
+    }
+  } else {
+    for (int i = 0; i < d.m; ++i) {
+      int a0, a1;
+      arange(i, a0, a1);
+      t += (double)(lowc ? std::min(i + 1, d.n) : d.n) * std::max(0, a1 - a0);
+    }
+  }
+  return 2.0 * t;
+}
+template <typename T>
+double gemm_bytes(const GemmDesc<T>& d, int k) {
+  if (d.m <= 0 || d.n <= 0) return 0.0;
+  const double mn = (d.flags & GF_LOWER_C) ? 0.5 * d.m * (d.n + 1.0) : (double)d.m * d.n;
+  return sizeof(T) * ((double)d.m * k + (double)k * d.n + mn * (d.beta != 0.0 ? 2.0 : 1.0));
+}
+
 // a batch of GEMMs / copies recorded for a later upload
 template <typename T>
 struct GemmBatch {
   std::vector<GemmDesc<T>> v, red;
   size_t off = 0, roff = 0;
   int tiles = 0, n = 0, rtiles = 0, rn = 0;
+  double flops = 0, bytes = 0, rbytes = 0;   // work of the descriptors with a host-known k
+  mutable int pid = -1;                      // timing record of the last launch
   // split: split-K partial-sum area (reused by every batch of a stream)
   void stage(Blob& b, const DevBuf* split = nullptr) {
     T* part = split ? static_cast<T*>(split->p) : nullptr;
@@ -205,10 +259,26 @@ struct GemmBatch {
     off = b.add(v);
     rn = (int)red.size();
     if (rn) roff = b.add(red);
+    flops = bytes = rbytes = 0;
+    for (const auto& d : v)
+      if (!d.kdev) {
+        flops += gemm_flops(d, d.k);
+        bytes += gemm_bytes(d, d.k);
+      }
+    for (const auto& d : red)
+      rbytes += sizeof(T) * ((double)d.m * d.n * (d.ksplit + (d.beta != 0.0 ? 2 : 1)));
   }
   void launch(const char* base, hipStream_t st) const {
-    if (n) launch_gemm<T>(reinterpret_cast<const GemmDesc<T>*>(base + off), n, tiles, st);
-    if (rn) launch_gemm_reduce<T>(reinterpret_cast<const GemmDesc<T>*>(base + roff), rn, rtiles, st);
+    if (n) {
+      pid = prof_begin(pk<T>(PK_GEMM_F64), st, flops, bytes);
+      launch_gemm<T>(reinterpret_cast<const GemmDesc<T>*>(base + off), n, tiles, st);
+      prof_end(pid, st);
+    }
+    if (rn) {
+      const int q = prof_begin(pk<T>(PK_GEMM_REDUCE_F64), st, 0.0, rbytes);
+      launch_gemm_reduce<T>(reinterpret_cast<const GemmDesc<T>*>(base + roff), rn, rtiles, st);
+      prof_end(q, st);
+    }
   }
 };
 template <typename S, typename D>
@@ -221,6 +291,24 @@ struct CopyBatch {
     if (n) launch_copy<S, D>(reinterpret_cast<const CopyDesc<S, D>*>(base + off), n, tiles, st);
   }
 };
+
+template <typename T>
+void potrf_work(const std::vector<PotrfDesc<T>>& v, double& flops, double& bytes) {
+  flops = bytes = 0;
+  for (const auto& d : v) {
+    const double n = d.n;
+    flops += n * n * n / 3.0 * (d.Inv ? 2.0 : 1.0);
+    bytes += sizeof(T) * (n * (n + 1) * (d.Inv ? 1.5 : 1.0));
+  }
+}
+template <typename T>
+void timed_potrf(const PotrfDesc<T>* d, const std::vector<PotrfDesc<T>>& hv, int nmax, int* status, hipStream_t st) {
+  double fl, by;
+  potrf_work(hv, fl, by);
+  const int id = prof_begin(pk<T>(nmax <= 64 ? PK_POTRF64_F64 : PK_POTRF128_F64), st, fl, by);
+  launch_potrf<T>(d, (int)hv.size(), nmax, status, st);
+  prof_end(id, st);
+}
 
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -277,9 +365,10 @@ class Numeric : public NumericBase {
   void hodlr_level(const std::vector<int>& H, int h);
 
   struct Rec {
-    int kind;                 // 0 gemm T, 1 copy TT, 2 vec_asm, 3 vec_gather
+    int kind;                 // 0 gemm T, 1 copy TT, 2 vec_asm, 3 vec_gather, 4 split-K reduction
     size_t off;
     int n, tiles;
+    double flops = 0, bytes = 0;
   };
   struct Plan {
     int nrhs = 0;
@@ -464,7 +553,11 @@ Numeric<T>::Numeric(const Symbolic& s, const double* vals, const mf_opts& o) {
         Blob b;
         size_t off = b.add(ev);
         char* base = dp.upload(b, st);
+        double by = 0;
+        for (const auto& d : ev) by += (double)d.nfc * (d.nfc + 1) / 2 * 3 * sizeof(T) + 4.0 * d.nfc;
+        const int id = prof_begin(pk<T>(PK_EXTADD_F64), st, 0.0, by);
         launch_extadd<T>(reinterpret_cast<const ExtAddDesc<T>*>(base + off), (int)ev.size(), tiles, st);
+        prof_end(id, st);
       }
     }
     std::vector<int> D, Hf;
@@ -523,7 +616,7 @@ void Numeric<T>::dense_level(const std::vector<int>& D) {
     if (f.nf() > 0) fn[p].Lfp = arena.alloc_n<T>((int64_t)f.nf() * f.npiv);
   }
   Blob b;
-  struct Step { size_t po; int pn; GemmBatch<T> panel, syrk; };
+  struct Step { size_t po; int pn; std::vector<PotrfDesc<T>> pv; GemmBatch<T> panel, syrk; };
   std::vector<Step> steps;
   for (int k = 0; k < maxnp; k += kNB) {
     Step sp;
@@ -550,6 +643,7 @@ void Numeric<T>::dense_level(const std::vector<int>& D) {
     }
     sp.pn = (int)pv.size();
     sp.po = b.add(pv);
+    sp.pv = std::move(pv);
     sp.panel.stage(b, &split);
     sp.syrk.stage(b, &split);
     steps.push_back(std::move(sp));
@@ -598,7 +692,7 @@ void Numeric<T>::dense_level(const std::vector<int>& D) {
   const char* base = dp.upload(b, st);
   int* status = d_status.as<int>();
   for (auto& sp : steps) {
-    launch_potrf<T>(reinterpret_cast<const PotrfDesc<T>*>(base + sp.po), sp.pn, kNB, status, st);
+    timed_potrf<T>(reinterpret_cast<const PotrfDesc<T>*>(base + sp.po), sp.pv, kNB, status, st);
     sp.panel.launch(base, st);
     sp.syrk.launch(base, st);
   }
@@ -735,23 +829,69 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
   resid.stage(b, &split);
   const char* base = dp.upload(b, st);
   int* dstat = d_status.as<int>();
+  // timing records; their work is added once the ranks are back on the host
+  const int id_f = skf.empty() ? -1 : prof_begin(pk<T>(PK_SKREG_FULL_F64), st, 0.0, 0.0);
   launch_skreg_full<T>(reinterpret_cast<const SkRegDesc<T>*>(base + okf), (int)skf.size(), eps, adaptive ? 1 : 0,
                        dstat, st);
+  prof_end(id_f, st);
+  const int id_h = skh.empty() ? -1 : prof_begin(pk<T>(PK_SKREG_HAT_F64), st, 0.0, 0.0);
   launch_skreg_hat<T>(reinterpret_cast<const SkRegDesc<T>*>(base + okh), (int)skh.size(), eps, dstat, st);
+  prof_end(id_h, st);
+  const int id_s = sf.empty() ? -1 : prof_begin(pk<T>(PK_SKELFAC_F64), st, 0.0, 0.0);
   launch_skelfac<T>(reinterpret_cast<const SkelFacDesc<T>*>(base + osf), (int)sf.size(), wgs, rmax1, st);
+  prof_end(id_s, st);
+  int id_2 = -1;
   if (adaptive) {
     resid.launch(base, st);
+    id_2 = p2.empty() ? -1 : prof_begin(pk<T>(PK_PHASE2_F64), st, 0.0, 0.0);
     launch_phase2<T>(reinterpret_cast<const Phase2Desc<T>*>(base + op2), (int)p2.size(), maxrc, eps, dstat, st);
+    prof_end(id_2, st);
   }
   // ---- the one synchronisation of the level: ranks to the host
-  std::vector<int> hr(nb);
+  std::vector<int> hr(nb), h1(nb);
   int status = 0;
   HIPCHK(hipMemcpyAsync(hr.data(), rankf, nb * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(h1.data(), rank1, nb * sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(hipMemcpyAsync(&status, d_status.p, sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(st));
   if (status & 2) throw Err{MF_ECAPACITY, "a block rank exceeded rank_cap"};
   for (int i = 0; i < nb; ++i) ranks[br[i].gb] = hr[i];
+  // work of the rank-dependent launches: each pivot step of the whole-block
+  // kernels updates the block once; the phase-1 kernel on B_hat reads it once
+  // and updates it per step; the factor kernel solves with the r x r LU for
+  // every row and column; phase 2 makes one pass (read + write) per step plus
+  // the final search.
+  {
+    double ff = 0, fb = 0, hf = 0, hb = 0, sfl = 0, sb = 0, rf = 0, rb = 0, pf = 0, pb = 0;
+    for (int i = 0; i < nb; ++i) {
+      const BR& x = br[i];
+      const Block& B = s.fronts[x.p].blocks[x.bi];
+      const double e = (double)B.nr * B.nc;
+      if (x.full) {
+        ff += 2.0 * e * hr[i];
+        fb += sizeof(T) * (e + (double)(B.nr + B.nc) * hr[i]);
+        continue;
+      }
+      const double eh = (double)x.nI * x.nJ, r1 = h1[i];
+      hf += 2.0 * eh * r1;
+      hb += sizeof(T) * (eh + r1 * r1) + 8.0 * r1;
+      sfl += (double)(B.nr + B.nc) * r1 * r1;
+      sb += sizeof(T) * ((double)(B.nr + B.nc) * r1 * 2);
+      if (adaptive) {
+        rf += 2.0 * e * r1;
+        rb += sizeof(T) * ((double)(B.nr + B.nc) * r1 + 2.0 * e);
+        const double steps = hr[i] - h1[i] + 1;
+        pf += 2.0 * e * steps;
+        pb += sizeof(T) * 2.0 * e * steps;
+      }
+    }
+    prof_add(id_f, ff, fb);
+    prof_add(id_h, hf, hb);
+    prof_add(id_s, sfl, sb);
+    prof_add(resid.pid, rf, rb);
+    prof_add(id_2, pf, pb);
+  }
 
   // ---- phase B
   std::map<std::pair<int, int>, int> bidx;   // (front, block) -> br index
@@ -851,8 +991,7 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
   lg2.stage(b2, &split);
   const char* base2 = dp.upload(b2, st);
   cp.launch(base2, st);
-  launch_potrf<T>(reinterpret_cast<const PotrfDesc<T>*>(base2 + oleaf), (int)leaves.size(), s.leaf,
-                  d_status.as<int>(), st);
+  timed_potrf<T>(reinterpret_cast<const PotrfDesc<T>*>(base2 + oleaf), leaves, s.leaf, d_status.as<int>(), st);
   lg1.launch(base2, st);
   lg2.launch(base2, st);
 
@@ -927,7 +1066,16 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
     const char* base3 = dp.upload(b3, st);
     gP.launch(base3, st);
     launch_cap<T>(reinterpret_cast<const CapDesc<T>*>(base3 + ocap), (int)capd.size(), st);
-    launch_gj_inverse(reinterpret_cast<const InvDesc*>(base3 + oinv), (int)invd.size(), d_status.as<int>(), st);
+    {
+      double fl = 0, by = 0;     // Gauss-Jordan on [K | I]: n steps over an n x 2n array
+      for (const auto& d : invd) {
+        fl += 4.0 * d.n * (double)d.n * d.n;
+        by += 8.0 * 2.0 * (2.0 * d.n * d.n);
+      }
+      const int id = prof_begin(PK_GJ, st, fl, by);
+      launch_gj_inverse(reinterpret_cast<const InvDesc*>(base3 + oinv), (int)invd.size(), d_status.as<int>(), st);
+      prof_end(id, st);
+    }
     gQ.launch(base3, st);
     cQ.launch(base3, st);
     gC.launch(base3, st);
@@ -1035,8 +1183,8 @@ typename Numeric<T>::Plan* Numeric<T>::get_plan(int nrhs) {
   pl->split.alloc(kSplitPlanBytes, &ms);
   auto rec_gemm = [&](GemmBatch<T>& g) {
     g.stage(b, &pl->split);
-    if (g.n) pl->recs.push_back({0, g.off, g.n, g.tiles});
-    if (g.rn) pl->recs.push_back({4, g.roff, g.rn, g.rtiles});
+    if (g.n) pl->recs.push_back({0, g.off, g.n, g.tiles, g.flops, g.bytes});
+    if (g.rn) pl->recs.push_back({4, g.roff, g.rn, g.rtiles, 0.0, g.rbytes});
   };
   auto rec_copy = [&](CopyBatch<T, T>& c) {
     c.stage(b);
@@ -1193,8 +1341,18 @@ void Numeric<T>::apply(int nrhs, const double* r, double* z, hipStream_t stream)
   for (const Rec& rc : pl->recs) {
     const char* base = pl->desc + rc.off;
     switch (rc.kind) {
-      case 0: launch_gemm<T>(reinterpret_cast<const GemmDesc<T>*>(base), rc.n, rc.tiles, stream); break;
-      case 4: launch_gemm_reduce<T>(reinterpret_cast<const GemmDesc<T>*>(base), rc.n, rc.tiles, stream); break;
+      case 0: {
+        const int id = prof_begin(pk<T>(PK_GEMM_F64), stream, rc.flops, rc.bytes);
+        launch_gemm<T>(reinterpret_cast<const GemmDesc<T>*>(base), rc.n, rc.tiles, stream);
+        prof_end(id, stream);
+        break;
+      }
+      case 4: {
+        const int id = prof_begin(pk<T>(PK_GEMM_REDUCE_F64), stream, 0.0, rc.bytes);
+        launch_gemm_reduce<T>(reinterpret_cast<const GemmDesc<T>*>(base), rc.n, rc.tiles, stream);
+        prof_end(id, stream);
+        break;
+      }
       case 1: launch_copy<T, T>(reinterpret_cast<const CopyDesc<T, T>*>(base), rc.n, rc.tiles, stream); break;
       case 2: launch_vec_asm<T>(reinterpret_cast<const VecAsmDesc<T>*>(base), rc.n, nrhs, stream); break;
       case 3: launch_vec_gather<T>(reinterpret_cast<const VecGatherDesc<T>*>(base), rc.n, pl->xn, N, nrhs, stream);
@@ -1207,7 +1365,11 @@ void Numeric<T>::apply(int nrhs, const double* r, double* z, hipStream_t stream)
 
 // ================================================================ GMRES ====
 void NumericBase::spmv(int nrhs, const double* x, double* y, double alpha, double beta, hipStream_t st) {
+  // CSR read once, x gathered once per right-hand side, y written (and read)
+  const double by = 12.0 * sym->nnz + 4.0 * (sym->n + 1) + 8.0 * sym->n * nrhs * (beta != 0.0 ? 3.0 : 2.0);
+  const int id = prof_begin(PK_SPMV, st, 2.0 * sym->nnz * nrhs, by);
   launch_spmv(d_rowptr.as<int>(), d_colind.as<int>(), d_vals.as<double>(), x, y, sym->n, nrhs, alpha, beta, st);
+  prof_end(id, st);
 }
 
 void NumericBase::gmres(int nrhs, const double* b, double* x, double tol, const mf_gmres_opts& o,

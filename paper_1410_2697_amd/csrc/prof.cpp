@@ -1,0 +1,146 @@
+// Per-kernel event timing (see prof.h).
+#include "prof.h"
+
+#include <atomic>
+#include <mutex>
+#include <sstream>
+
+namespace mfh {
+namespace {
+
+const char* const kNames[PK_COUNT] = {
+    "gemm_kernel<double>",        "gemm_kernel<float>",
+    "gemm_reduce_kernel<double>", "gemm_reduce_kernel<float>",
+    "potrf_kernel<double, 64>",   "potrf_kernel<float, 64>",
+    "potrf_kernel<double, 128>",  "potrf_kernel<float, 128>",
+    "skreg_kernel<double, 2, 32, true, 512>", "skreg_kernel<float, 4, 32, true, 512>",
+    "skreg_kernel<double, 2, 8, false, 1024>", "skreg_kernel<float, 3, 24, false, 512>",
+    "skelfac_kernel<double>",     "skelfac_kernel<float>",
+    "phase2_kernel<double>",      "phase2_kernel<float>",
+    "extadd_kernel<double>",      "extadd_kernel<float>",
+    "gj_kernel",
+    "spmv_kernel",
+};
+
+struct Rec {
+  int kind;
+  hipEvent_t a, b;
+  double flops, bytes;
+};
+
+struct State {
+  std::mutex mu;
+  std::atomic<uint64_t> mask{0};
+  int session = 0;
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+};
+State& S() {
+  static State s;
+  return s;
+}
+
+constexpr int kIdxBits = 24;
+
+hipEvent_t take(State& s) {
+  if (!s.pool.empty()) {
+    hipEvent_t e = s.pool.back();
+    s.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+Rec* find(State& s, int id) {
+  if (id < 0 || (id >> kIdxBits) != (s.session & 0x3F)) return nullptr;
+  const size_t i = (size_t)(id & ((1 << kIdxBits) - 1));
+  return i < s.recs.size() ? &s.recs[i] : nullptr;
+}
+
+}  // namespace
+
+const char* prof_name(int kind) { return (kind >= 0 && kind < PK_COUNT) ? kNames[kind] : "?"; }
+
+int prof_begin(int kind, hipStream_t st, double flops, double bytes) {
+  State& s = S();
+  if (!((s.mask.load(std::memory_order_relaxed) >> kind) & 1)) return -1;
+  std::lock_guard<std::mutex> g(s.mu);
+  if (s.recs.size() >= (size_t(1) << kIdxBits)) return -1;
+  Rec r{kind, take(s), take(s), flops, bytes};
+  if (!r.a || !r.b || hipEventRecord(r.a, st) != hipSuccess) {
+    if (r.a) s.pool.push_back(r.a);
+    if (r.b) s.pool.push_back(r.b);
+    return -1;
+  }
+  s.recs.push_back(r);
+  return ((s.session & 0x3F) << kIdxBits) | (int)(s.recs.size() - 1);
+}
+
+void prof_end(int id, hipStream_t st) {
+  if (id < 0) return;
+  State& s = S();
+  std::lock_guard<std::mutex> g(s.mu);
+  if (Rec* r = find(s, id)) (void)hipEventRecord(r->b, st);
+}
+
+void prof_add(int id, double flops, double bytes) {
+  if (id < 0) return;
+  State& s = S();
+  std::lock_guard<std::mutex> g(s.mu);
+  if (Rec* r = find(s, id)) {
+    r->flops += flops;
+    r->bytes += bytes;
+  }
+}
+
+void prof_start(const std::string& names) {
+  State& s = S();
+  std::lock_guard<std::mutex> g(s.mu);
+  uint64_t m = 0;
+  if (names.empty()) {
+    m = (uint64_t(1) << PK_COUNT) - 1;
+  } else {
+    std::stringstream ss(names);
+    std::string tok;
+    while (std::getline(ss, tok, ','))
+      for (int k = 0; k < PK_COUNT; ++k)
+        if (tok == kNames[k]) m |= uint64_t(1) << k;
+  }
+  for (Rec& r : s.recs) {
+    s.pool.push_back(r.a);
+    s.pool.push_back(r.b);
+  }
+  s.recs.clear();
+  ++s.session;
+  s.mask.store(m);
+}
+
+std::vector<ProfTotal> prof_stop() {
+  State& s = S();
+  std::lock_guard<std::mutex> g(s.mu);
+  s.mask.store(0);
+  std::vector<ProfTotal> t(PK_COUNT);
+  for (int k = 0; k < PK_COUNT; ++k) t[k] = ProfTotal{k, 0, 0.0, 0.0, 0.0};
+  for (Rec& r : s.recs) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      ProfTotal& x = t[r.kind];
+      x.launches += 1;
+      x.seconds += 1e-3 * ms;
+      x.flops += r.flops;
+      x.bytes += r.bytes;
+    }
+    s.pool.push_back(r.a);
+    s.pool.push_back(r.b);
+  }
+  s.recs.clear();
+  ++s.session;
+  std::vector<ProfTotal> out;
+  for (auto& x : t)
+    if (x.launches > 0) out.push_back(x);
+  return out;
+}
+
+}  // namespace mfh

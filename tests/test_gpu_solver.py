@@ -151,3 +151,29 @@ def test_not_spd_reports_error(gpu_lib):
     with pytest.raises(mfh.MfError) as e:
         mfh.Factor(sym, -p.A.vals, 0.0, method="dense", precision="fp64")
     assert e.value.status == mfh.MF_ENOTSPD
+
+
+def test_kernel_timing_reports_work(gpu_lib):
+    """Event timing around launches: every timed kernel reports launches, a
+    positive duration, and the GEMM flops counted on the host."""
+    mfh = gpu_lib
+    import torch
+    p = q1_grid(16, 3)
+    print(f"case prof q1_3d_16 n={p.A.n}", flush=True)
+    sym = mfh.Symbolic.from_csr(p.A, p.coords, 32)
+    mfh.prof_start()
+    f = mfh.Factor(sym, p.A.vals, 1e-4, method="hodlr", precision="fp32", n_c=64)
+    b = rhs(p.A.n, 2, "normal", 3)
+    f.gmres(_to_dev(b), _to_dev(np.zeros_like(b)), tol=1e-10)
+    torch.cuda.synchronize()
+    stats = {s["name"]: s for s in mfh.prof_stop()}
+    print(sorted(stats), flush=True)
+    for name in ("gemm_kernel<float>", "spmv_kernel", "potrf_kernel<float, 64>"):
+        assert name in stats and stats[name]["launches"] > 0 and stats[name]["seconds"] > 0, name
+    assert stats["gemm_kernel<float>"]["flops"] > 0
+    assert stats["spmv_kernel"]["bytes"] >= 12.0 * p.A.nnz
+    # timing only the named kernel leaves the others untimed
+    mfh.prof_start(["spmv_kernel"])
+    f.gmres(_to_dev(b), _to_dev(np.zeros_like(b)), tol=1e-10)
+    torch.cuda.synchronize()
+    assert [s["name"] for s in mfh.prof_stop()] == ["spmv_kernel"]

@@ -141,10 +141,19 @@ def test_option_validation():
     s = mfh.Symbolic.from_csr(p.A, p.coords, 8)
     lib = mfh.load()
     h = ctypes.c_void_p()
-    for kw, eps in [({"precision": 7}, 1e-4), ({"method": 9}, 1e-4), ({}, -1.0), ({"bdlr_cap": 0}, 1e-4),
+    for kw, eps in [({"precision": 7}, 1e-4), ({"method": 9}, 1e-4), ({}, -1.0), ({"bdlr_cap": -1}, 1e-4),
                     ({"bdlr_cap": 500}, 1e-4)]:
         o = mfh.default_opts(**kw)
         st = lib.mf_factor(s.h, mfh._ptr(p.A.vals), eps, 0, ctypes.byref(o), ctypes.byref(h))
         assert st == mfh.MF_EINVAL, (kw, eps)
     o = mfh.default_opts()
     assert lib.mf_factor(s.h, mfh._ptr(p.A.vals), 1e-4, 5, ctypes.byref(o), ctypes.byref(h)) == mfh.MF_EINVAL
+
+
+def test_prof_start_stop_without_launches():
+    """Kernel timing starts and stops on the host; with no launches nothing is reported."""
+    import paper_1410_2697_amd as mfh
+    mfh.prof_start(["gemm_kernel<float>", "no_such_kernel"])
+    assert mfh.prof_stop() == []
+    mfh.prof_start()
+    assert mfh.prof_stop() == []
