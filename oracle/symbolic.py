@@ -26,9 +26,9 @@ What it computes, following Sec. 4.1.1 of the paper:
 * per front: the HODLR cluster trees (top split [I_p | I_p^f]; each part
   bisected at floor(m/2) until it has at most ``leaf`` indices) and their
   off-diagonal blocks.
-* BDLR row/column sets of each off-diagonal block (Sec. 2.2): in the graph of
-  A restricted to the block's indices, rows of the block within graph
-  distance <= d of the block's column cluster and vice versa.  At most
+* BDLR row/column sets of each off-diagonal block (Sec. 2.2, Sec. 4.2.1): in
+  the graph of A restricted to the front's whole index set, rows of the block
+  within graph distance <= d of the block's column cluster and vice versa.  At most
   ``cap`` indices are kept, closest first (ties -> lower position).
   ``d < 0`` means every index (unreachable ones last).
 
