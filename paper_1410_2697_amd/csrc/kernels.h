@@ -129,20 +129,27 @@ struct CopyDesc {   // dst(i, j) = alpha * src(i, j) (+ dst if accumulate)
   double alpha;
 };
 
-// K = [[P(0:r, c:c+r), I], [I, P(r:2r, c:c+r)]] in float64 (2r x 2r, ld 2r)
-// and Pa = float64 copy of P(:, 0:c).
+// SMW capacitance K = [[A, I], [I, B]] with A = P(0:r, c:c+r) (V^T Y_alpha)
+// and B = P(r:2r, c:c+r) (U^T Y_beta).  Its inverse is formed from the r x r
+// matrix M = (I - A B)^{-1}:  K^{-1} = [[-B M, I + B M A], [M, -M A]].
+// This kernel writes A and B in float64 (r x r each, ld r), the identity into
+// Kinv(r:2r, 0:r) (to become I - A B) and Kinv(0:r, r:2r) (to become
+// I + B M A), and Pa = float64 copy of P(:, 0:c) (ld 2r).
 template <typename T>
 struct CapDesc {
   const T* P;
-  double* K;
+  double* Kinv;      // 2r x 2r, ld 2r
+  double* A;
+  double* B;
   double* Pa;
   int r, c, ldp, pad;
 };
 
-struct InvDesc {      // Gauss-Jordan inverse with partial pivoting, float64
-  double* A;          // n x 2n work (ld n), A(:, 0:n) preset to K
-  int n, pad;
+struct InvDesc {      // in-place Gauss-Jordan inverse with partial pivoting, float64
+  double* A;          // n x n, leading dimension ld
+  int n, ld;
 };
+constexpr int kInvMax = 1024;   // largest n of InvDesc
 
 // upward-pass front vector: t(0:npiv) = xn(start:start+npiv), t(npiv:) = 0,
 // then t(relmap_c) += child's t_c(npiv_c:) for each child in order.

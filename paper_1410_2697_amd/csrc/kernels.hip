@@ -234,16 +234,21 @@ __global__ void mfma_probe_kernel(int* rows, int* cols, int* assumed) {
 }
 
 // ------------------------------------------------------- small Cholesky ----
-// Right-looking Cholesky of the lower triangle held in LDS, then the
-// triangular inverse in place, one column at a time from the right:
-// X(i, j) = -X(j, j) * sum_{k=j+1..i} X(i, k) L(k, j).
-template <typename T, int NMAX>
-__global__ __launch_bounds__(256) void potrf_kernel(const PotrfDesc<T>* __restrict__ descs, int* status) {
-  constexpr int LD = NMAX + 1;
+// Right-looking Cholesky of the lower triangle held in LDS, fused with the
+// inverse X = L^{-1}: after column j of L is final, row j of X is divided by
+// L(j, j) and X(i, 0:j+1) -= L(i, j) X(j, 0:j+1) for i > j (forward
+// substitution of L X = I, one rank-1 step per column).  X's strictly lower
+// part is stored transposed in the unused upper triangle of the same LDS
+// array (X(i, k) at S[k + i LD], k < i) and its diagonal in xd.
+template <typename T, int NMAX, int NT>
+__global__ __launch_bounds__(NT) void potrf_kernel(const PotrfDesc<T>* __restrict__ descs, int* status) {
+  constexpr int LD = NMAX + 1, NW = NT / 64;
   __shared__ T S[NMAX * LD];
+  __shared__ T xd[NMAX];
   const PotrfDesc<T> d = descs[blockIdx.x];
-  const int n = d.n, tid = threadIdx.x, nt = blockDim.x;
-  for (int j = tid >> 6; j < n; j += nt >> 6)
+  const int n = d.n, tid = threadIdx.x;
+  const bool inv = d.Inv != nullptr;
+  for (int j = tid >> 6; j < n; j += NW)
     for (int i = tid & 63; i < n; i += 64) S[i + j * LD] = i >= j ? d.A[i + (size_t)j * d.lda] : (T)0;
   __syncthreads();
   for (int j = 0; j < n; ++j) {
@@ -251,36 +256,34 @@ __global__ __launch_bounds__(256) void potrf_kernel(const PotrfDesc<T>* __restri
     const bool bad = !(djj > (T)0);
     if (bad) djj = (T)1;
     const T ljj = sqrt(djj);
-    __syncthreads();
+    const T rinv = (T)1 / ljj;
+    __syncthreads();   // every thread has read L(j, j) before it is overwritten
     if (tid == 0) {
       S[j + j * LD] = ljj;
+      xd[j] = rinv;
       if (bad) atomicOr(status, 1);
     }
-    const T rinv = (T)1 / ljj;
-    for (int i = j + 1 + tid; i < n; i += nt) S[i + j * LD] *= rinv;
+    for (int i = j + 1 + tid; i < n; i += NT) S[i + j * LD] *= rinv;      // column j of L
+    if (inv)
+      for (int k = tid; k < j; k += NT) S[k + j * LD] *= rinv;            // row j of X
     __syncthreads();
-    for (int c = j + 1 + (tid >> 5); c < n; c += nt >> 5) {
+    // trailing update of A and the rank-1 step of X, 32-lane groups per column / row
+    for (int c = j + 1 + (tid >> 5); c < n; c += NT / 32) {
       const T lc = S[c + j * LD];
       for (int r = c + (tid & 31); r < n; r += 32) S[r + c * LD] -= S[r + j * LD] * lc;
+      if (inv) {
+        // X(c, k) -= L(c, j) X(j, k), k <= j   (X(c, k) at S[k + c LD])
+        for (int k = tid & 31; k <= j; k += 32) S[k + c * LD] -= lc * (k == j ? xd[j] : S[k + j * LD]);
+      }
     }
     __syncthreads();
   }
-  for (int j = tid >> 6; j < n; j += nt >> 6)
+  for (int j = tid >> 6; j < n; j += NW)
     for (int i = j + (tid & 63); i < n; i += 64) d.A[i + (size_t)j * d.lda] = S[i + j * LD];
-  if (!d.Inv) return;
-  for (int j = n - 1; j >= 0; --j) {
-    const T djinv = (T)1 / S[j + j * LD];
-    T s = 0;
-    const int i = tid;
-    if (i > j && i < n)
-      for (int k = j + 1; k <= i; ++k) s += S[i + k * LD] * S[k + j * LD];
-    __syncthreads();
-    if (i > j && i < n) S[i + j * LD] = -s * djinv;
-    if (i == j) S[j + j * LD] = djinv;
-    __syncthreads();
-  }
-  for (int j = tid >> 6; j < n; j += nt >> 6)
-    for (int i = tid & 63; i < n; i += 64) d.Inv[i + (size_t)j * d.ldi] = i >= j ? S[i + j * LD] : (T)0;
+  if (!inv) return;
+  for (int j = tid >> 6; j < n; j += NW)
+    for (int i = tid & 63; i < n; i += 64)
+      d.Inv[i + (size_t)j * d.ldi] = i > j ? S[j + i * LD] : (i == j ? xd[i] : (T)0);
 }
 
 // ------------------------------------------ register-resident skeleton ----
@@ -649,14 +652,13 @@ template <typename T>
 __global__ __launch_bounds__(256) void cap_kernel(const CapDesc<T>* __restrict__ descs) {
   const CapDesc<T> d = descs[blockIdx.x];
   const int r = d.r, n = 2 * r;
-  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
-    const int i = idx % n, j = idx / n;
-    double v;
-    if (i < r && j < r) v = (double)d.P[i + (size_t)(d.c + j) * d.ldp];
-    else if (i >= r && j >= r) v = (double)d.P[i + (size_t)(d.c + j - r) * d.ldp];
-    else v = (i < r) ? (i == j - r ? 1.0 : 0.0) : (i - r == j ? 1.0 : 0.0);
-    d.K[i + (size_t)j * n] = v;                         // left half of [K | I]
-    d.K[i + (size_t)(j + n) * n] = (i == j) ? 1.0 : 0.0; // right half
+  for (int idx = threadIdx.x; idx < r * r; idx += blockDim.x) {
+    const int i = idx % r, j = idx / r;
+    d.A[idx] = (double)d.P[i + (size_t)(d.c + j) * d.ldp];
+    d.B[idx] = (double)d.P[(r + i) + (size_t)(d.c + j) * d.ldp];
+    const double e = i == j ? 1.0 : 0.0;
+    d.Kinv[(r + i) + (size_t)j * n] = e;
+    d.Kinv[i + (size_t)(r + j) * n] = e;
   }
   for (int idx = threadIdx.x; idx < n * d.c; idx += blockDim.x) {
     const int i = idx % n, j = idx / n;
@@ -664,44 +666,64 @@ __global__ __launch_bounds__(256) void cap_kernel(const CapDesc<T>* __restrict__
   }
 }
 
+// In-place inverse of an n x n float64 matrix by Gauss-Jordan elimination
+// with partial pivoting (largest |A(i,k)|, lowest i on ties).  Step k swaps
+// rows k and p, turns column k into the k-th unit column while the inverse
+// builds up in its place, and the recorded row interchanges are undone as
+// column interchanges in reverse order at the end.  One workgroup per
+// matrix; a zero pivot column sets status bit 4.
 __global__ __launch_bounds__(1024) void gj_kernel(const InvDesc* __restrict__ descs, int* status) {
-  __shared__ double f[1024];
+  __shared__ double f[kInvMax];
+  __shared__ double rowk[kInvMax];
+  __shared__ int perm[kInvMax];
   __shared__ double redd[16];
   __shared__ int redi[16];
   const InvDesc d = descs[blockIdx.x];
-  const int n = d.n, tid = threadIdx.x, nt = blockDim.x;
+  const int n = d.n, ld = d.ld, tid = threadIdx.x, nt = blockDim.x;
   double* A = d.A;
-  for (int j = 0; j < n; ++j) {
+  for (int k = 0; k < n; ++k) {
     double mx = 0.0;
-    for (int i = j + tid; i < n; i += nt) mx = fmax(mx, fabs(A[i + (size_t)j * n]));
+    for (int i = k + tid; i < n; i += nt) mx = fmax(mx, fabs(A[i + (size_t)k * ld]));
     const double mxall = block_max(mx, redd);
     int best = INT_MAX;
-    for (int i = j + tid; i < n; i += nt)
-      if (fabs(A[i + (size_t)j * n]) == mxall) { best = i; break; }
+    for (int i = k + tid; i < n; i += nt)
+      if (fabs(A[i + (size_t)k * ld]) == mxall) { best = i; break; }
     int p = block_min(best, redi);
     if (!(mxall > 0.0)) {
       if (tid == 0) atomicOr(status, 4);
-      p = j;
+      p = k;
     }
-    if (p != j)
-      for (int c = tid; c < 2 * n; c += nt) {
-        const double t = A[j + (size_t)c * n];
-        A[j + (size_t)c * n] = A[p + (size_t)c * n];
-        A[p + (size_t)c * n] = t;
-      }
-    __syncthreads();
-    double pv = A[j + (size_t)j * n];
+    if (tid == 0) perm[k] = p;
+    double pv = A[p + (size_t)k * ld];
     if (!(fabs(pv) > 0.0)) pv = 1.0;
     const double inv = 1.0 / pv;
-    __syncthreads();
-    for (int c = tid; c < 2 * n; c += nt) A[j + (size_t)c * n] *= inv;
-    __syncthreads();
-    for (int i = tid; i < n; i += nt) f[i] = (i == j) ? 0.0 : A[i + (size_t)j * n];
-    __syncthreads();
-    for (int idx = tid; idx < n * 2 * n; idx += nt) {
-      const int i = idx % n, c = idx / n;
-      if (i != j) A[i + (size_t)c * n] -= f[i] * A[j + (size_t)c * n];
+    __syncthreads();   // every thread has read the pivot before rows move
+    for (int c = tid; c < n; c += nt) {
+      const double vk = A[k + (size_t)c * ld], vp = A[p + (size_t)c * ld];
+      const double nk = (c == k ? 1.0 : vp) * inv;   // new row k; A(k,k) becomes 1/pivot
+      rowk[c] = nk;
+      A[k + (size_t)c * ld] = nk;
+      if (p != k) A[p + (size_t)c * ld] = vk;
     }
+    __syncthreads();
+    for (int i = tid; i < n; i += nt) f[i] = (i == k) ? 0.0 : A[i + (size_t)k * ld];
+    __syncthreads();
+    for (int idx = tid; idx < n * n; idx += nt) {
+      const int i = idx % n, c = idx / n;
+      if (i == k) continue;
+      double* a = A + i + (size_t)c * ld;
+      *a = (c == k ? 0.0 : *a) - f[i] * rowk[c];
+    }
+    __syncthreads();
+  }
+  for (int k = n - 1; k >= 0; --k) {
+    const int p = perm[k];
+    if (p != k)
+      for (int i = tid; i < n; i += nt) {
+        const double t = A[i + (size_t)k * ld];
+        A[i + (size_t)k * ld] = A[i + (size_t)p * ld];
+        A[i + (size_t)p * ld] = t;
+      }
     __syncthreads();
   }
 }
@@ -891,8 +913,8 @@ template void launch_mfma_probe<double>(int*, int*, int*, hipStream_t);
 template <typename T>
 void launch_potrf(const PotrfDesc<T>* d, int ndesc, int nmax, int* status, hipStream_t st) {
   if (ndesc <= 0) return;
-  if (nmax <= 64) hipLaunchKernelGGL((potrf_kernel<T, 64>), dim3(ndesc), dim3(256), 0, st, d, status);
-  else hipLaunchKernelGGL((potrf_kernel<T, 128>), dim3(ndesc), dim3(256), 0, st, d, status);
+  if (nmax <= 64) hipLaunchKernelGGL((potrf_kernel<T, 64, 256>), dim3(ndesc), dim3(256), 0, st, d, status);
+  else hipLaunchKernelGGL((potrf_kernel<T, 128, 512>), dim3(ndesc), dim3(512), 0, st, d, status);
 }
 template <typename T>
 void launch_skreg_full(const SkRegDesc<T>* d, int ndesc, double eps, int adaptive, int* status, hipStream_t st) {

@@ -1008,7 +1008,7 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
         const int r = fn[p].nodeR[i], c = fn[p].col[l];
         nodes.push_back({p, i, r, c});
         nP += al((size_t)2 * r * (c + r) * sizeof(T));
-        nK += al((size_t)2 * r * 4 * r * sizeof(double));
+        nK += al((size_t)6 * r * r * sizeof(double));
         nPa += al((size_t)2 * r * std::max(c, 1) * sizeof(double));
         nQ += al((size_t)2 * r * std::max(c, 1) * sizeof(double)) + al((size_t)2 * r * std::max(c, 1) * sizeof(T));
       }
@@ -1019,7 +1019,7 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
     auto tk = [&](size_t bytes) { char* r = cb; cb += al(bytes); return r; };
     Blob b3;
     GemmBatch<T> gP, gC;
-    GemmBatch<double> gQ;
+    GemmBatch<double> gQ, gM, gX1, gX2;
     std::vector<CapDesc<T>> capd;
     std::vector<InvDesc> invd;
     CopyBatch<double, T> cQ, cK;
@@ -1031,7 +1031,9 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
       const TreeNode& be = f.pp_tree[t.right];
       const int r = nr.r, c = nr.c, n2 = 2 * r;
       T* P = reinterpret_cast<T*>(tk((size_t)n2 * (c + r) * sizeof(T)));
-      double* K = reinterpret_cast<double*>(tk((size_t)n2 * 2 * n2 * sizeof(double)));
+      double* Kinv = reinterpret_cast<double*>(tk((size_t)6 * r * r * sizeof(double)));
+      double* A64 = Kinv + (size_t)n2 * n2;
+      double* B64 = A64 + (size_t)r * r;
       double* Pa = reinterpret_cast<double*>(tk((size_t)n2 * std::max(c, 1) * sizeof(double)));
       double* Q64 = reinterpret_cast<double*>(tk((size_t)n2 * std::max(c, 1) * sizeof(double)));
       T* Q = reinterpret_cast<T*>(tk((size_t)n2 * std::max(c, 1) * sizeof(T)));
@@ -1040,12 +1042,18 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
       gP.v.push_back(gd<T>(x.nodeU[nr.i], be.size, 1, x.G + be.off, f.npiv, 0, P + r, n2, r, c + r, be.size, 1.0,
                            0.0));
       CapDesc<T> cdsc{};
-      cdsc.P = P; cdsc.ldp = n2; cdsc.r = r; cdsc.c = c; cdsc.K = K; cdsc.Pa = Pa;
+      cdsc.P = P; cdsc.ldp = n2; cdsc.r = r; cdsc.c = c; cdsc.Kinv = Kinv; cdsc.A = A64; cdsc.B = B64;
+      cdsc.Pa = Pa;
       capd.push_back(cdsc);
+      // K^{-1} = [[-B M, I + B M A], [M, -M A]], M = (I - A B)^{-1} built in Kinv(r:2r, 0:r)
+      double* M = Kinv + r;
+      gM.v.push_back(gd<double>(A64, r, 0, B64, r, 0, M, n2, r, r, r, -1.0, 1.0));
       InvDesc iv{};
-      iv.A = K; iv.n = n2;
+      iv.A = M; iv.n = r; iv.ld = n2;
       invd.push_back(iv);
-      const double* Kinv = K + (size_t)n2 * n2;
+      gX1.v.push_back(gd<double>(B64, r, 0, M, n2, 0, Kinv, n2, r, r, r, -1.0, 0.0));                 // -B M
+      gX1.v.push_back(gd<double>(M, n2, 0, A64, r, 0, Kinv + r + (size_t)r * n2, n2, r, r, r, -1.0, 0.0));  // -M A
+      gX2.v.push_back(gd<double>(Kinv, n2, 0, A64, r, 0, Kinv + (size_t)r * n2, n2, r, r, r, -1.0, 1.0));  // I + B M A
       if (c > 0) {
         gQ.v.push_back(gd<double>(Kinv, n2, 0, Pa, n2, 0, Q64, n2, n2, c, n2, 1.0, 0.0));
         cQ.v.push_back(cd<double, T>(Q64, n2, Q, n2, n2, c));
@@ -1059,6 +1067,9 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
     }
     gP.stage(b3, &split);
     const size_t ocap = b3.add(capd), oinv = b3.add(invd);
+    gM.stage(b3, &split);
+    gX1.stage(b3, &split);
+    gX2.stage(b3, &split);
     gQ.stage(b3, &split);
     cQ.stage(b3);
     gC.stage(b3, &split);
@@ -1066,16 +1077,19 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
     const char* base3 = dp.upload(b3, st);
     gP.launch(base3, st);
     launch_cap<T>(reinterpret_cast<const CapDesc<T>*>(base3 + ocap), (int)capd.size(), st);
+    gM.launch(base3, st);
     {
-      double fl = 0, by = 0;     // Gauss-Jordan on [K | I]: n steps over an n x 2n array
+      double fl = 0, by = 0;     // in-place Gauss-Jordan: n steps of an n x n rank-1 update
       for (const auto& d : invd) {
-        fl += 4.0 * d.n * (double)d.n * d.n;
-        by += 8.0 * 2.0 * (2.0 * d.n * d.n);
+        fl += 2.0 * d.n * (double)d.n * d.n;
+        by += 8.0 * 2.0 * d.n * (double)d.n;
       }
       const int id = prof_begin(PK_GJ, st, fl, by);
       launch_gj_inverse(reinterpret_cast<const InvDesc*>(base3 + oinv), (int)invd.size(), d_status.as<int>(), st);
       prof_end(id, st);
     }
+    gX1.launch(base3, st);
+    gX2.launch(base3, st);
     gQ.launch(base3, st);
     cQ.launch(base3, st);
     gC.launch(base3, st);

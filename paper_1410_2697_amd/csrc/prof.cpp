@@ -11,8 +11,8 @@ namespace {
 const char* const kNames[PK_COUNT] = {
     "gemm_kernel<double>",        "gemm_kernel<float>",
     "gemm_reduce_kernel<double>", "gemm_reduce_kernel<float>",
-    "potrf_kernel<double, 64>",   "potrf_kernel<float, 64>",
-    "potrf_kernel<double, 128>",  "potrf_kernel<float, 128>",
+    "potrf_kernel<double, 64, 256>",  "potrf_kernel<float, 64, 256>",
+    "potrf_kernel<double, 128, 512>", "potrf_kernel<float, 128, 512>",
     "skreg_kernel<double, 2, 32, true, 512>", "skreg_kernel<float, 4, 32, true, 512>",
     "skreg_kernel<double, 2, 8, false, 1024>", "skreg_kernel<float, 3, 24, false, 512>",
     "skelfac_kernel<double>",     "skelfac_kernel<float>",

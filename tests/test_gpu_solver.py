@@ -168,7 +168,7 @@ def test_kernel_timing_reports_work(gpu_lib):
     torch.cuda.synchronize()
     stats = {s["name"]: s for s in mfh.prof_stop()}
     print(sorted(stats), flush=True)
-    for name in ("gemm_kernel<float>", "spmv_kernel", "potrf_kernel<float, 64>"):
+    for name in ("gemm_kernel<float>", "spmv_kernel", "potrf_kernel<float, 64, 256>"):
         assert name in stats and stats[name]["launches"] > 0 and stats[name]["seconds"] > 0, name
     assert stats["gemm_kernel<float>"]["flops"] > 0
     assert stats["spmv_kernel"]["bytes"] >= 12.0 * p.A.nnz
