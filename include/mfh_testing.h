@@ -36,10 +36,13 @@ mf_status mfh_test_potrf(int32_t precision, int32_t n, void* A, int32_t lda, voi
 
 /* Skeleton compression (Sec. 2.2, Eq. Bhat) of the block
  * F(r0:r0+nr, c0:c0+nc) of an ld-strided matrix F from BDLR row/column
- * sets I, J (device int32, positions in F; at most 126 (FP64) / 180 (FP32)
- * entries each).  U (nr x cap) and V (nc x cap) receive C~ and R~^T;
- * the block of F is overwritten by the residual when adaptive != 0.
- * *rank_out receives the final rank. */
+ * sets I, J (device int32, positions in F; at most 128 (FP64) / 192 (FP32)
+ * entries each).  U (nr x cap) and V (nc x cap) receive C~ and R~^T.
+ * adaptive: 0 = pivoting on B(I, J) only; 1 = then continue over the whole
+ * block, with the block spread over several workgroups when it is larger
+ * than one workgroup's registers and a column slice fits LDS; 2 = as 1 but
+ * with one workgroup streaming the block.  The block of F may be
+ * overwritten by a residual.  *rank_out receives the final rank. */
 mf_status mfh_test_skeleton(int32_t precision, void* F, int32_t ld, int32_t r0, int32_t nr, int32_t c0,
                             int32_t nc, const int32_t* I, int32_t nI, const int32_t* J, int32_t nJ, double eps,
                             int32_t adaptive, int32_t cap, void* U, void* V, int32_t* rank_out);

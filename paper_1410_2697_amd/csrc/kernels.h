@@ -108,6 +108,29 @@ struct Phase2Desc {
   int ld, r0, nr, c0, nc, ldu, ldv, cap;
 };
 
+// Phase 2 spread over workgroups: workgroup j of a block keeps the residual
+// columns [j*wcols, min(nc, (j+1)*wcols)) in LDS for the whole pivot loop.
+// After each step every workgroup publishes its best pivot key and the
+// updated column it belongs to (double-buffered by step parity), then waits
+// at the block's barrier counter; all workgroups then pick the same pivot.
+// Pivots, arithmetic and outputs are those of Phase2Desc.
+template <typename T>
+struct Phase2CoopDesc {
+  const T* F;
+  const int* piv_r;
+  const int* piv_c;
+  const int* rank1;
+  const double* u11;
+  T* U;
+  T* V;
+  int* rank;
+  unsigned* bar;                 // barrier counter, zero before the launch
+  unsigned long long* keys;      // 2 x nwg
+  T* cand;                       // 2 x nwg x nr
+  int ld, r0, nr, c0, nc, ldu, ldv, cap;
+  int wg0, nwg, wcols, pad;
+};
+
 // child update (front positions [npc, npc+nfc) of the child buffer) scatter
 // added into the parent front through the relative map.
 template <typename T>
@@ -199,6 +222,23 @@ template <typename T>
 void launch_skelfac(const SkelFacDesc<T>* d, int ndesc, int wgs, int rmax, hipStream_t st);
 template <typename T>
 void launch_phase2(const Phase2Desc<T>* d, int ndesc, int maxrc, double eps, int* status, hipStream_t st);
+// Multi-workgroup phase 2.  phase2_coop_wcols: columns per workgroup for a
+// block of nr rows (0 when its LDS slice cannot hold one column);
+// phase2_coop_lds: dynamic LDS bytes of a workgroup; phase2_coop_capacity:
+// workgroups that can be resident at once with that LDS (a launch must not
+// exceed it).  The launch is cooperative, so all its workgroups are resident;
+// a barrier wait longer than spin_limit polls sets status bit 8 and ends the
+// loop.  Returns the launch error.
+constexpr int kPhase2CoopLds = 64 * 1024;
+template <typename T>
+int phase2_coop_wcols(int nr);
+template <typename T>
+size_t phase2_coop_lds(int nr, int wcols);
+template <typename T>
+int phase2_coop_capacity(size_t lds);
+template <typename T>
+hipError_t launch_phase2_coop(const Phase2CoopDesc<T>* d, int ndesc, int wgs, size_t lds, double eps, int* status,
+                              int spin_limit, hipStream_t st);
 template <typename T>
 void launch_extadd(const ExtAddDesc<T>* d, int ndesc, int tiles, hipStream_t st);
 template <typename S, typename D>

@@ -611,6 +611,159 @@ __global__ __launch_bounds__(1024) void phase2_kernel(const Phase2Desc<T>* __res
   if (tid == 0) *d.rank = r;
 }
 
+// --------------------------- skeleton, phase 2 over several workgroups ----
+// Barrier of the workgroups of one block: each thread's stores are released
+// at agent scope, thread 0 arrives on the counter and polls it (bounded), then
+// every thread acquires.  Returns false when the poll limit was reached.
+__device__ bool block_group_barrier(unsigned* bar, unsigned target, int spin_limit, int* status, int* s_ok) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int spins = 0;
+    while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(2);
+      if (++spins > spin_limit) {
+        atomicOr(status, 8);
+        ok = 0;
+        break;
+      }
+    }
+    *s_ok = ok;
+  }
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return *s_ok != 0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void phase2_coop_kernel(const Phase2CoopDesc<T>* __restrict__ descs, int ndesc,
+                                                          double eps, int* status, int spin_limit) {
+  extern __shared__ __align__(16) char smem[];
+  __shared__ u64 s_red[16];
+  __shared__ u64 s_key;
+  __shared__ T s_piv;
+  __shared__ int s_ok;
+  int lo = 0, hi = ndesc - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (descs[mid].wg0 <= (int)blockIdx.x) lo = mid; else hi = mid - 1;
+  }
+  const Phase2CoopDesc<T> d = descs[lo];
+  const int j = (int)blockIdx.x - d.wg0;
+  const int nr = d.nr, nwg = d.nwg, tid = threadIdx.x, nt = blockDim.x;
+  const int wave = tid >> 6, lane = tid & 63, nwave = nt >> 6;
+  const int cb0 = j * d.wcols, w = min(d.wcols, d.nc - cb0);
+  T* Es = reinterpret_cast<T*>(smem);              // nr x wcols, ld nr
+  T* u = Es + (size_t)nr * d.wcols;                // pivot column
+  T* vloc = u + nr;                                // own entries of the new V column
+  char* lr = reinterpret_cast<char*>(vloc + d.wcols);
+  char* lc = lr + nr;
+  {
+    const T* E = d.F + d.r0 + (size_t)(d.c0 + cb0) * d.ld;
+    for (int c = wave; c < w; c += nwave)
+      for (int i = lane; i < nr; i += 64) Es[i + (size_t)c * nr] = E[i + (size_t)c * d.ld];
+  }
+  for (int i = tid; i < nr; i += nt) lr[i] = 1;
+  for (int c = tid; c < w; c += nt) lc[c] = 1;
+  __syncthreads();
+  const int r1 = *d.rank1;
+  for (int q = tid; q < r1; q += nt) {
+    lr[d.piv_r[q] - d.r0] = 0;
+    const int cc = d.piv_c[q] - d.c0 - cb0;
+    if (cc >= 0 && cc < w) lc[cc] = 0;
+  }
+  __syncthreads();
+  double u11 = *d.u11;
+  const double stop_rel = fmax(eps, (double)noise_rel<T>());
+  int r = r1;
+  unsigned arrivals = 0;
+  int par = 0;           // parity of the buffers written this step
+  bool pending = false;
+  int a = 0;
+  for (;;) {
+    // update with the pending pivot (if any) and search own columns
+    u64 best = 0;
+    for (int c = wave; c < w; c += nwave) {
+      const T v = pending ? vloc[c] : (T)0;
+      const bool cc = lc[c] != 0;
+      T* col = Es + (size_t)c * nr;
+      const unsigned base = (unsigned)(cb0 + c) * (unsigned)nr;
+      for (int i = lane; i < nr; i += 64) {
+        T x = col[i];
+        if (pending) {
+          x -= u[i] * v;
+          col[i] = x;
+        }
+        if (cc && lr[i]) {
+          const u64 k = make_key(qmag(x), base + (unsigned)i);
+          best = k > best ? k : best;
+        }
+      }
+    }
+    best = block_max_u64(best, s_red);
+    // publish the best key and its column
+    if (best != 0ull) {
+      const unsigned idx = 0xFFFFFFFFu - (unsigned)(best & 0xFFFFFFFFull);
+      const int bc = (int)(idx / (unsigned)nr) - cb0;
+      T* cd = d.cand + ((size_t)par * nwg + j) * nr;
+      for (int i = tid; i < nr; i += nt) cd[i] = Es[i + (size_t)bc * nr];
+    }
+    if (tid == 0) d.keys[(size_t)par * nwg + j] = best;
+    arrivals += (unsigned)nwg;
+    if (!block_group_barrier(d.bar, arrivals, spin_limit, status, &s_ok)) break;
+    // every workgroup picks the same pivot from the published keys
+    if (tid == 0) {
+      u64 K = 0;
+      for (int q = 0; q < nwg; ++q) {
+        const u64 k = d.keys[(size_t)par * nwg + q];
+        K = k > K ? k : K;
+      }
+      s_key = K;
+      T pv = (T)0;
+      if (K != 0ull) {
+        const unsigned idx = 0xFFFFFFFFu - (unsigned)(K & 0xFFFFFFFFull);
+        const int y = (int)(idx / (unsigned)nr) / d.wcols;
+        pv = d.cand[((size_t)par * nwg + y) * nr + (int)(idx % (unsigned)nr)];
+      }
+      s_piv = pv;
+    }
+    __syncthreads();
+    const u64 K = s_key;
+    if (K == 0ull) break;
+    const unsigned idx = 0xFFFFFFFFu - (unsigned)(K & 0xFFFFFFFFull);
+    a = (int)(idx % (unsigned)nr);
+    const int b = (int)(idx / (unsigned)nr);
+    const T piv = s_piv;
+    if (u11 == 0.0) u11 = fabs((double)piv);
+    if (fabs((double)piv) < stop_rel * u11) break;
+    if (r >= d.cap) {
+      if (tid == 0 && j == 0) atomicOr(status, 2);
+      break;
+    }
+    const int y = b / d.wcols;
+    const T* cy = d.cand + ((size_t)par * nwg + y) * nr;
+    for (int i = tid; i < nr; i += nt) u[i] = cy[i];
+    for (int c = tid; c < w; c += nt) vloc[c] = Es[a + (size_t)c * nr] / piv;
+    __syncthreads();
+    {   // this workgroup's share of U(:, r), and V(own columns, r)
+      const int ch = (nr + nwg - 1) / nwg, i0 = j * ch, i1 = min(nr, i0 + ch);
+      for (int i = i0 + tid; i < i1; i += nt) d.U[i + (size_t)r * d.ldu] = u[i];
+      for (int c = tid; c < w; c += nt) d.V[(cb0 + c) + (size_t)r * d.ldv] = vloc[c];
+    }
+    if (tid == 0) {
+      lr[a] = 0;
+      if (b >= cb0 && b < cb0 + w) lc[b - cb0] = 0;
+    }
+    ++r;
+    pending = true;
+    par ^= 1;
+    __syncthreads();
+  }
+  if (tid == 0 && j == 0) *d.rank = r;
+}
+
 // ----------------------------------------------------------- extend-add ----
 template <typename T>
 __global__ __launch_bounds__(256) void extadd_kernel(const ExtAddDesc<T>* __restrict__ descs, int ndesc) {
@@ -943,6 +1096,35 @@ void launch_phase2(const Phase2Desc<T>* d, int ndesc, int maxrc, double eps, int
   hipLaunchKernelGGL(phase2_kernel<T>, dim3(ndesc), dim3(1024), (size_t)maxrc, st, d, eps, status);
 }
 template <typename T>
+int phase2_coop_wcols(int nr) {
+  const long per_col = (long)nr * sizeof(T) + sizeof(T) + 1;
+  const long fixed = (long)nr * (sizeof(T) + 1) + 64;
+  const long w = (kPhase2CoopLds - fixed) / per_col;
+  return w >= 1 ? (int)w : 0;
+}
+template <typename T>
+size_t phase2_coop_lds(int nr, int wcols) {
+  return (size_t)nr * wcols * sizeof(T) + (size_t)nr * sizeof(T) + (size_t)wcols * sizeof(T) + nr + wcols + 16;
+}
+template <typename T>
+int phase2_coop_capacity(size_t lds) {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(phase2_coop_kernel<T>), 256,
+                                                   lds) != hipSuccess)
+    return 0;
+  return per * cus;
+}
+template <typename T>
+hipError_t launch_phase2_coop(const Phase2CoopDesc<T>* d, int ndesc, int wgs, size_t lds, double eps, int* status,
+                              int spin_limit, hipStream_t st) {
+  if (ndesc <= 0 || wgs <= 0) return hipSuccess;
+  void* args[] = {(void*)&d, (void*)&ndesc, (void*)&eps, (void*)&status, (void*)&spin_limit};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(phase2_coop_kernel<T>), dim3(wgs), dim3(256), args,
+                                    (unsigned)lds, st);
+}
+template <typename T>
 void launch_extadd(const ExtAddDesc<T>* d, int ndesc, int tiles, hipStream_t st) {
   if (ndesc <= 0 || tiles <= 0) return;
   hipLaunchKernelGGL(extadd_kernel<T>, dim3(tiles), dim3(256), 0, st, d, ndesc);
@@ -1027,6 +1209,11 @@ void launch_axpby(const double* a, const double* b, double* c, double alpha, dou
   template void launch_skreg_hat<T>(const SkRegDesc<T>*, int, double, int*, hipStream_t);        \
   template void launch_skelfac<T>(const SkelFacDesc<T>*, int, int, int, hipStream_t);            \
   template void launch_phase2<T>(const Phase2Desc<T>*, int, int, double, int*, hipStream_t);     \
+  template int phase2_coop_wcols<T>(int);                                                         \
+  template size_t phase2_coop_lds<T>(int, int);                                                   \
+  template int phase2_coop_capacity<T>(size_t);                                                   \
+  template hipError_t launch_phase2_coop<T>(const Phase2CoopDesc<T>*, int, int, size_t, double, int*, int, \
+                                            hipStream_t);                                         \
   template void launch_extadd<T>(const ExtAddDesc<T>*, int, int, hipStream_t);                   \
   template void launch_cap<T>(const CapDesc<T>*, int, hipStream_t);                              \
   template void launch_fill<T>(T*, int64_t, T, hipStream_t);                                     \

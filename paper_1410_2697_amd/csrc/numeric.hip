@@ -116,6 +116,7 @@ GemmDesc<T> gd(const T* A, int lda, int opA, const T* B, int ldb, int opB, T* C,
 // chip, its deep products (k >= 2 * kSplitChunk) get several workgroups
 // along k, writing partial sums into `part` (capacity `cap` elements; each
 // problem takes its own region), followed by a fixed-order reduction.
+constexpr int kSpinLimit = 1 << 20;   // barrier polls before a phase-2 workgroup gives up
 constexpr int kSplitTarget = 512;   // workgroups wanted per launch (two per CU)
 constexpr int kSplitChunk = 128;    // smallest k range of one split
 constexpr size_t kSplitFactorBytes = size_t(16) << 20;
@@ -730,10 +731,15 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
   struct BR {
     int p, bi, gb, lk, nI, nJ, kcap, capr;
     bool full;                 // whole block held in registers by one workgroup
+    int nwg, wcols;            // phase 2 over nwg workgroups (0: one workgroup streams the block)
     int *pr, *pc, *rank1, *rank;
     double* u11;
     T *M, *U, *V;
+    unsigned long long* keys;
+    T* cand;
   };
+  const size_t coop_lds = kPhase2CoopLds;
+  const int coop_capacity = phase2_coop_capacity<T>(coop_lds);
   std::vector<BR> br;
   for (int p : Hs) {
     const Front& f = s.fronts[p];
@@ -746,6 +752,14 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
       x.kcap = std::min(x.nI, x.nJ);
       x.capr = std::max(std::min({B.nr, B.nc, opts.rank_cap}), x.kcap);
       x.full = B.nr <= skreg_full_rows<T>() && B.nc <= skreg_full_cols<T>();
+      if (!x.full && adaptive) {       // phase 2 over several workgroups when a slice fits LDS
+        const int wc = phase2_coop_wcols<T>(B.nr);
+        if (wc > 0) {
+          x.nwg = cdiv(B.nc, wc);
+          x.wcols = cdiv(B.nc, x.nwg);
+          if (x.nwg > coop_capacity) x.nwg = 0;
+        }
+      }
       br.push_back(x);
     }
   }
@@ -753,8 +767,13 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
   // ---- compression scratch (lives until the level's last launch)
   auto al = [](size_t v) { return (v + 255) & ~size_t(255); };
   size_t need = al(nb * sizeof(int)) * 2 + al(nb * sizeof(double));
+  int ncoop = 0;
   for (auto& x : br) {
     const Block& B = s.fronts[x.p].blocks[x.bi];
+    if (x.nwg > 0) {
+      ++ncoop;
+      need += al((size_t)2 * x.nwg * sizeof(unsigned long long)) + al((size_t)2 * x.nwg * B.nr * sizeof(T));
+    }
     need += 2 * al(std::max(x.capr, 1) * sizeof(int));
     if (!x.full) need += al((size_t)std::max(x.kcap * x.kcap, 1) * sizeof(T));
     need += al((size_t)B.nr * x.capr * sizeof(T)) + al((size_t)B.nc * x.capr * sizeof(T));
@@ -762,6 +781,7 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
   scrA.ensure(need, &ms, st);
   char* cur = static_cast<char*>(scrA.p);
   auto take = [&](size_t bytes) { char* r = cur; cur += al(bytes); return r; };
+  unsigned* bars = reinterpret_cast<unsigned*>(take((size_t)std::max(ncoop, 1) * 256));  // one 256-byte slot each
   int* rank1 = reinterpret_cast<int*>(take(nb * sizeof(int)));
   int* rankf = reinterpret_cast<int*>(take(nb * sizeof(int)));
   double* u11 = reinterpret_cast<double*>(take(nb * sizeof(double)));
@@ -776,11 +796,16 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
     x.rank1 = rank1 + i;
     x.rank = rankf + i;
     x.u11 = u11 + i;
+    if (x.nwg > 0) {
+      x.keys = reinterpret_cast<unsigned long long*>(take((size_t)2 * x.nwg * sizeof(unsigned long long)));
+      x.cand = reinterpret_cast<T*>(take((size_t)2 * x.nwg * B.nr * sizeof(T)));
+    }
   }
   Blob b;
   std::vector<SkRegDesc<T>> skf, skh;
   std::vector<SkelFacDesc<T>> sf;
   std::vector<Phase2Desc<T>> p2;
+  std::vector<Phase2CoopDesc<T>> p2c;
   GemmBatch<T> resid;
   int rmax1 = 1, wgs = 0, maxrc = 1;
   for (auto& x : br) {
@@ -814,6 +839,17 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
       // E = B - U V^T in place (k = phase-1 rank, read on the device)
       resid.v.push_back(gd<T>(x.U, B.nr, 0, x.V, B.nc, 1, fx.F + B.r0 + (int64_t)B.c0 * fx.ld, fx.ld, B.nr, B.nc,
                               x.kcap, -1.0, 1.0, 0, x.rank1));
+      if (x.nwg > 0) {
+        Phase2CoopDesc<T> q{};
+        q.F = fx.F; q.ld = fx.ld; q.r0 = B.r0; q.nr = B.nr; q.c0 = B.c0; q.nc = B.nc;
+        q.piv_r = x.pr; q.piv_c = x.pc; q.rank1 = x.rank1; q.u11 = x.u11;
+        q.U = x.U; q.ldu = B.nr; q.V = x.V; q.ldv = B.nc; q.cap = x.capr; q.rank = x.rank;
+        q.bar = bars + 64 * p2c.size();
+        q.keys = x.keys; q.cand = x.cand;
+        q.nwg = x.nwg; q.wcols = x.wcols;
+        p2c.push_back(q);
+        continue;
+      }
       Phase2Desc<T> q{};
       q.F = fx.F; q.ld = fx.ld; q.r0 = B.r0; q.nr = B.nr; q.c0 = B.c0; q.nc = B.nc;
       q.piv_r = x.pr; q.piv_c = x.pc; q.rank1 = x.rank1; q.u11 = x.u11;
@@ -822,10 +858,21 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
       maxrc = std::max(maxrc, B.nr + B.nc);
     }
   }
+  // cooperative launches: consecutive groups of blocks whose workgroups can all be resident
+  struct CoopGroup { size_t first; int n, wgs; };
+  std::vector<CoopGroup> cgroups;
+  for (size_t i = 0; i < p2c.size(); ++i) {
+    if (cgroups.empty() || cgroups.back().wgs + p2c[i].nwg > coop_capacity)
+      cgroups.push_back({i, 0, 0});
+    CoopGroup& g = cgroups.back();
+    p2c[i].wg0 = g.wgs;
+    g.wgs += p2c[i].nwg;
+    ++g.n;
+  }
   if ((size_t)rmax1 * rmax1 * sizeof(T) > (size_t)kLdsMax)
     throw Err{MF_EINVAL, "phase-1 rank bound too large for LDS: lower bdlr_cap"};
   if (maxrc > kLdsMax) throw Err{MF_EINVAL, "block too large for the phase-2 kernel"};
-  const size_t okf = b.add(skf), okh = b.add(skh), osf = b.add(sf), op2 = b.add(p2);
+  const size_t okf = b.add(skf), okh = b.add(skh), osf = b.add(sf), op2 = b.add(p2), op2c = b.add(p2c);
   resid.stage(b, &split);
   const char* base = dp.upload(b, st);
   int* dstat = d_status.as<int>();
@@ -841,11 +888,23 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
   launch_skelfac<T>(reinterpret_cast<const SkelFacDesc<T>*>(base + osf), (int)sf.size(), wgs, rmax1, st);
   prof_end(id_s, st);
   int id_2 = -1;
+  std::vector<int> coop_ids;
   if (adaptive) {
     resid.launch(base, st);
     id_2 = p2.empty() ? -1 : prof_begin(pk<T>(PK_PHASE2_F64), st, 0.0, 0.0);
     launch_phase2<T>(reinterpret_cast<const Phase2Desc<T>*>(base + op2), (int)p2.size(), maxrc, eps, dstat, st);
     prof_end(id_2, st);
+    if (!p2c.empty()) {
+      launch_fill<float>(reinterpret_cast<float*>(bars), (int64_t)64 * p2c.size(), 0.0f, st);   // barrier counters
+      const auto* dc = reinterpret_cast<const Phase2CoopDesc<T>*>(base + op2c);
+      for (const CoopGroup& g : cgroups) {
+        const int id = prof_begin(pk<T>(PK_PHASE2C_F64), st, 0.0, 0.0);
+        coop_ids.push_back(id);
+        const hipError_t e = launch_phase2_coop<T>(dc + g.first, g.n, g.wgs, coop_lds, eps, dstat, kSpinLimit, st);
+        prof_end(id, st);
+        if (e != hipSuccess) throw Err{MF_EHIP, std::string("phase-2 launch: ") + hipGetErrorString(e)};
+      }
+    }
   }
   // ---- the one synchronisation of the level: ranks to the host
   std::vector<int> hr(nb), h1(nb);
@@ -856,6 +915,7 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(st));
   if (status & 2) throw Err{MF_ECAPACITY, "a block rank exceeded rank_cap"};
+  if (status & 8) throw Err{MF_EHIP, "phase-2 workgroups did not meet at their barrier"};
   for (int i = 0; i < nb; ++i) ranks[br[i].gb] = hr[i];
   // work of the rank-dependent launches: each pivot step of the whole-block
   // kernels updates the block once; the phase-1 kernel on B_hat reads it once
@@ -863,7 +923,7 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
   // every row and column; phase 2 makes one pass (read + write) per step plus
   // the final search.
   {
-    double ff = 0, fb = 0, hf = 0, hb = 0, sfl = 0, sb = 0, rf = 0, rb = 0, pf = 0, pb = 0;
+    double ff = 0, fb = 0, hf = 0, hb = 0, sfl = 0, sb = 0, rf = 0, rb = 0, pf = 0, pb = 0, cf = 0, cbytes = 0;
     for (int i = 0; i < nb; ++i) {
       const BR& x = br[i];
       const Block& B = s.fronts[x.p].blocks[x.bi];
@@ -882,8 +942,13 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
         rf += 2.0 * e * r1;
         rb += sizeof(T) * ((double)(B.nr + B.nc) * r1 + 2.0 * e);
         const double steps = hr[i] - h1[i] + 1;
-        pf += 2.0 * e * steps;
-        pb += sizeof(T) * 2.0 * e * steps;
+        if (x.nwg > 0) {   // slices read once; per step one U and V column
+          cf += 2.0 * e * steps;
+          cbytes += sizeof(T) * (e + (double)(B.nr + B.nc) * (steps - 1));
+        } else {
+          pf += 2.0 * e * steps;
+          pb += sizeof(T) * 2.0 * e * steps;
+        }
       }
     }
     prof_add(id_f, ff, fb);
@@ -891,6 +956,13 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
     prof_add(id_s, sfl, sb);
     prof_add(resid.pid, rf, rb);
     prof_add(id_2, pf, pb);
+    // the cooperative launches share the level's work in proportion to their workgroups
+    if (!coop_ids.empty()) {
+      double tw = 0;
+      for (const CoopGroup& g : cgroups) tw += g.wgs;
+      for (size_t k = 0; k < cgroups.size(); ++k)
+        prof_add(coop_ids[k], cf * cgroups[k].wgs / tw, cbytes * cgroups[k].wgs / tw);
+    }
   }
 
   // ---- phase B

@@ -17,6 +17,7 @@ const char* const kNames[PK_COUNT] = {
     "skreg_kernel<double, 2, 8, false, 1024>", "skreg_kernel<float, 3, 24, false, 512>",
     "skelfac_kernel<double>",     "skelfac_kernel<float>",
     "phase2_kernel<double>",      "phase2_kernel<float>",
+    "phase2_coop_kernel<double>", "phase2_coop_kernel<float>",
     "extadd_kernel<double>",      "extadd_kernel<float>",
     "gj_kernel",
     "spmv_kernel",

@@ -22,6 +22,7 @@ enum ProfKind : int {
   PK_SKREG_HAT_F64, PK_SKREG_HAT_F32,
   PK_SKELFAC_F64, PK_SKELFAC_F32,
   PK_PHASE2_F64, PK_PHASE2_F32,
+  PK_PHASE2C_F64, PK_PHASE2C_F32,
   PK_EXTADD_F64, PK_EXTADD_F32,
   PK_GJ,
   PK_SPMV,

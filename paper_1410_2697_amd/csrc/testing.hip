@@ -115,19 +115,53 @@ mf_status skel_t(void* F, int ld, int r0, int nr, int c0, int nc, const int* I, 
   hipMemcpy(dd + 2048, &gdsc, sizeof(gdsc), hipMemcpyHostToDevice);
   hipMemcpy(dd + 3072, &pd, sizeof(pd), hipMemcpyHostToDevice);
   if (full) {
-    mfh::launch_skreg_full<T>(reinterpret_cast<mfh::SkRegDesc<T>*>(dd), 1, eps, adaptive, status, nullptr);
+    mfh::launch_skreg_full<T>(reinterpret_cast<mfh::SkRegDesc<T>*>(dd), 1, eps, adaptive ? 1 : 0, status, nullptr);
   } else {
     mfh::launch_skreg_hat<T>(reinterpret_cast<mfh::SkRegDesc<T>*>(dd), 1, eps, status, nullptr);
     mfh::launch_skelfac<T>(reinterpret_cast<mfh::SkelFacDesc<T>*>(dd + 1024), 1, wgs, kcap > 0 ? kcap : 1, nullptr);
     if (adaptive) {
       mfh::launch_gemm<T>(reinterpret_cast<mfh::GemmDesc<T>*>(dd + 2048), 1, gtiles, nullptr);
-      mfh::launch_phase2<T>(reinterpret_cast<mfh::Phase2Desc<T>*>(dd + 3072), 1, nr + nc, eps, status, nullptr);
+      const int wc = adaptive == 1 ? mfh::phase2_coop_wcols<T>(nr) : 0;
+      int nwg = wc > 0 ? (nc + wc - 1) / wc : 0;
+      if (nwg > mfh::phase2_coop_capacity<T>(mfh::kPhase2CoopLds)) nwg = 0;
+      if (nwg > 0) {
+        char* cs = nullptr;   // barrier counter, keys, candidate columns
+        const size_t kb = 256 + (size_t)2 * nwg * 8, cb = (size_t)2 * nwg * nr * sizeof(T);
+        s = hip_ok(hipMalloc(&cs, kb + cb));
+        if (s == MF_OK) {
+          hipMemset(cs, 0, 256);
+          mfh::Phase2CoopDesc<T> qd{};
+          qd.F = pd.F; qd.ld = ld; qd.r0 = r0; qd.nr = nr; qd.c0 = c0; qd.nc = nc;
+          qd.piv_r = pr; qd.piv_c = pc; qd.rank1 = rank1; qd.u11 = u11; qd.U = pd.U; qd.ldu = nr; qd.V = pd.V;
+          qd.ldv = nc; qd.cap = cap; qd.rank = rank;
+          qd.bar = reinterpret_cast<unsigned*>(cs);
+          qd.keys = reinterpret_cast<unsigned long long*>(cs + 256);
+          qd.cand = reinterpret_cast<T*>(cs + kb);
+          qd.wg0 = 0; qd.nwg = nwg; qd.wcols = (nc + nwg - 1) / nwg;
+          hipMemcpy(dd + 3072, &qd, sizeof(qd), hipMemcpyHostToDevice);
+          s = hip_ok(mfh::launch_phase2_coop<T>(reinterpret_cast<mfh::Phase2CoopDesc<T>*>(dd + 3072), 1, nwg,
+                                                mfh::kPhase2CoopLds, eps, status, 1 << 20, nullptr));
+          if (s == MF_OK) s = hip_ok(hipDeviceSynchronize());
+          hipFree(cs);
+        }
+        if (s != MF_OK) { hipFree(dd); hipFree(scratch); return s; }
+      } else {
+        mfh::launch_phase2<T>(reinterpret_cast<mfh::Phase2Desc<T>*>(dd + 3072), 1, nr + nc, eps, status, nullptr);
+      }
     }
   }
   s = hip_ok(hipDeviceSynchronize());
-  if (s == MF_OK) hipMemcpy(rank_out, rank, sizeof(int), hipMemcpyDeviceToHost);
+  int stat = 0;
+  if (s == MF_OK) {
+    hipMemcpy(rank_out, rank, sizeof(int), hipMemcpyDeviceToHost);
+    hipMemcpy(&stat, status, sizeof(int), hipMemcpyDeviceToHost);
+  }
   hipFree(dd);
   hipFree(scratch);
+  if (s == MF_OK && (stat & 8)) {
+    t_err = "phase-2 workgroups did not meet at their barrier";
+    return MF_EHIP;
+  }
   return s;
 }
 }  // namespace

@@ -137,13 +137,14 @@ def _kernel_matrix(m, n, seed, gap):
     return -np.log(np.linalg.norm(x[:, None, :] - y[None, :, :], axis=2))
 
 
-@pytest.mark.parametrize("adaptive", [0, 1])
+@pytest.mark.parametrize("adaptive", [0, 1, 2])
 @pytest.mark.parametrize("nr,nc,nI,nJ,eps", [(40, 30, 40, 30, 1e-6), (120, 90, 20, 15, 1e-5), (300, 200, 60, 50, 1e-8),
                                               (33, 47, 1, 1, 1e-4), (16, 16, 16, 16, 0.0), (100, 300, 40, 90, 1e-6),
-                                              (128, 256, 0, 0, 1e-7)])
+                                              (128, 256, 0, 0, 1e-7), (700, 90, 30, 30, 1e-6)])
 def test_skeleton_fp64_matches_oracle(gpu_lib, adaptive, nr, nc, nI, nJ, eps):
     """Same pivots, rank and factors as the float64 oracle (Eq. Bhat plus the
-    adaptive full-block phase)."""
+    adaptive full-block phase; 1 = the large-block phase spread over
+    workgroups, 2 = one workgroup)."""
     import torch
     mfh = gpu_lib
     B = _kernel_matrix(nr, nc, nr + nc, 0.4)
@@ -183,8 +184,10 @@ def test_skeleton_fp64_matches_oracle(gpu_lib, adaptive, nr, nc, nI, nJ, eps):
         assert np.abs(E).max() < eps * np.abs(B).max() / (1 - 2.0 ** -20) * (1 + 1e-9)
 
 
-@pytest.mark.parametrize("nr,nc,nI,nJ", [(200, 150, 40, 40), (600, 300, 120, 100), (256, 256, 16, 16)])
-def test_skeleton_fp32_error_bound(gpu_lib, nr, nc, nI, nJ):
+@pytest.mark.parametrize("adaptive", [1, 2])
+@pytest.mark.parametrize("nr,nc,nI,nJ", [(200, 150, 40, 40), (600, 300, 120, 100), (256, 256, 16, 16),
+                                         (1100, 700, 150, 150)])
+def test_skeleton_fp32_error_bound(gpu_lib, adaptive, nr, nc, nI, nJ):
     """FP32 whole-block and large-block paths: the adaptive skeleton meets the
     max-norm contract (up to float32 rounding of the residual)."""
     import torch
@@ -200,7 +203,7 @@ def test_skeleton_fp32_error_bound(gpu_lib, nr, nc, nI, nJ):
     rank = ctypes.c_int32(-1)
     eps = 1e-4
     st = gpu_lib.load().mfh_test_skeleton(1, _p(dF), ld, 0, nr, 0, nc, _p(torch.tensor(I, device="cuda")), nI,
-                                          _p(torch.tensor(J, device="cuda")), nJ, eps, 1, cap, _p(dU), _p(dV),
+                                          _p(torch.tensor(J, device="cuda")), nJ, eps, adaptive, cap, _p(dU), _p(dV),
                                           ctypes.byref(rank))
     assert st == 0
     r = rank.value
