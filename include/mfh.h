@@ -102,7 +102,7 @@ typedef struct {
 } mf_factor_info;
 
 /* Fill *o with defaults: HODLR, FP32, n_c 0, d -1 (no depth limit), cap 0
- * (the pivot kernel's maximum), adaptive 1, rank_cap 256, eps 1e-4, null
+ * (the pivot kernel's maximum), adaptive 1, rank_cap 512, eps 1e-4, null
  * stream. */
 mf_status mf_opts_default(mf_opts* o);
 mf_status mf_gmres_opts_default(mf_gmres_opts* o);

@@ -41,7 +41,8 @@ mf_status mfh_test_potrf(int32_t precision, int32_t n, void* A, int32_t lda, voi
  * adaptive: 0 = pivoting on B(I, J) only; 1 = then continue over the whole
  * block, with the block spread over several workgroups when it is larger
  * than one workgroup's registers and a column slice fits LDS; 2 = as 1 but
- * with one workgroup streaming the block.  The block of F may be
+ * with one workgroup streaming the block; 3 = as 1 with workgroups of at
+ * most 4 columns updating the block in place.  The block of F may be
  * overwritten by a residual.  *rank_out receives the final rank. */
 mf_status mfh_test_skeleton(int32_t precision, void* F, int32_t ld, int32_t r0, int32_t nr, int32_t c0,
                             int32_t nc, const int32_t* I, int32_t nI, const int32_t* J, int32_t nJ, double eps,

@@ -63,7 +63,7 @@ mf_status mf_opts_default(mf_opts* o) {
   o->bdlr_depth = -1;
   o->bdlr_cap = 0;
   o->adaptive = 1;
-  o->rank_cap = 256;
+  o->rank_cap = 512;
   o->eps = 1e-4;
   o->stream = nullptr;
   return MF_OK;

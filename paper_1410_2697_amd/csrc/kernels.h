@@ -116,7 +116,7 @@ struct Phase2Desc {
 // Pivots, arithmetic and outputs are those of Phase2Desc.
 template <typename T>
 struct Phase2CoopDesc {
-  const T* F;
+  T* F;      
   const int* piv_r;
   const int* piv_c;
   const int* rank1;
@@ -128,7 +128,8 @@ struct Phase2CoopDesc {
   unsigned long long* keys;      // 2 x nwg
   T* cand;                       // 2 x nwg x nr
   int ld, r0, nr, c0, nc, ldu, ldv, cap;
-  int wg0, nwg, wcols, pad;
+  int wg0, nwg, wcols;
+  int slice_lds;                 // host bookkeeping: slices in LDS (1) or in place (0)
 };
 
 // child update (front positions [npc, npc+nfc) of the child buffer) scatter
@@ -222,9 +223,10 @@ template <typename T>
 void launch_skelfac(const SkelFacDesc<T>* d, int ndesc, int wgs, int rmax, hipStream_t st);
 template <typename T>
 void launch_phase2(const Phase2Desc<T>* d, int ndesc, int maxrc, double eps, int* status, hipStream_t st);
-// Multi-workgroup phase 2.  phase2_coop_wcols: columns per workgroup for a
-// block of nr rows (0 when its LDS slice cannot hold one column);
-// phase2_coop_lds: dynamic LDS bytes of a workgroup; phase2_coop_capacity:
+// Multi-workgroup phase 2.  phase2_coop_wcols: columns per workgroup whose
+// slice (nr x wcols) fits a workgroup's LDS (0 when not even one column
+// does); phase2_coop_lds: dynamic LDS bytes of a workgroup, with the slice in
+// LDS or (slice_lds false) updated in place in the front; phase2_coop_capacity:
 // workgroups that can be resident at once with that LDS (a launch must not
 // exceed it).  The launch is cooperative, so all its workgroups are resident;
 // a barrier wait longer than spin_limit polls sets status bit 8 and ends the
@@ -233,12 +235,12 @@ constexpr int kPhase2CoopLds = 64 * 1024;
 template <typename T>
 int phase2_coop_wcols(int nr);
 template <typename T>
-size_t phase2_coop_lds(int nr, int wcols);
+size_t phase2_coop_lds(int nr, int wcols, bool slice_lds);
 template <typename T>
-int phase2_coop_capacity(size_t lds);
+int phase2_coop_capacity(size_t lds, bool slice_lds);
 template <typename T>
-hipError_t launch_phase2_coop(const Phase2CoopDesc<T>* d, int ndesc, int wgs, size_t lds, double eps, int* status,
-                              int spin_limit, hipStream_t st);
+hipError_t launch_phase2_coop(const Phase2CoopDesc<T>* d, int ndesc, int wgs, size_t lds, bool slice_lds,
+                              double eps, int* status, int spin_limit, hipStream_t st);
 template <typename T>
 void launch_extadd(const ExtAddDesc<T>* d, int ndesc, int tiles, hipStream_t st);
 template <typename S, typename D>

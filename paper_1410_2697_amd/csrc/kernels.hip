@@ -1,6 +1,7 @@
 // Device kernels for gfx950 (CDNA4, wave64).  See kernels.h for the
 // descriptor of each launch.
 #include "kernels.h"
+#include "prof.h"
 
 #include <climits>
 
@@ -612,18 +613,22 @@ __global__ __launch_bounds__(1024) void phase2_kernel(const Phase2Desc<T>* __res
 }
 
 // --------------------------- skeleton, phase 2 over several workgroups ----
-// Barrier of the workgroups of one block: each thread's stores are released
-// at agent scope, thread 0 arrives on the counter and polls it (bounded), then
-// every thread acquires.  Returns false when the poll limit was reached.
+// Barrier of the workgroups of one block.  Only the published keys and
+// candidate columns cross workgroups, and they are written and read with
+// agent-scope atomic accesses, which are coherent across the chip by
+// themselves; each thread waits for its stores to complete, then thread 0
+// arrives on the counter and polls it (bounded).  No cache-wide writeback or
+// invalidation is needed, so the slices stay in the caches.  Returns false
+// when the poll limit was reached.
 __device__ bool block_group_barrier(unsigned* bar, unsigned target, int spin_limit, int* status, int* s_ok) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
     int ok = 1;
     __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     int spins = 0;
     while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      __builtin_amdgcn_s_sleep(2);
+      __builtin_amdgcn_s_sleep(1);
       if (++spins > spin_limit) {
         atomicOr(status, 8);
         ok = 0;
@@ -633,11 +638,20 @@ __device__ bool block_group_barrier(unsigned* bar, unsigned target, int spin_lim
     *s_ok = ok;
   }
   __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   return *s_ok != 0;
 }
-
 template <typename T>
+__device__ __forceinline__ void publish(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T fetch(const T* p) {
+  return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// SLICE_LDS: the workgroup's columns are copied to LDS once (the front keeps
+// the phase-1 residual); otherwise they are updated in place in the front.
+template <typename T, bool SLICE_LDS>
 __global__ __launch_bounds__(256) void phase2_coop_kernel(const Phase2CoopDesc<T>* __restrict__ descs, int ndesc,
                                                           double eps, int* status, int spin_limit) {
   extern __shared__ __align__(16) char smem[];
@@ -655,16 +669,24 @@ __global__ __launch_bounds__(256) void phase2_coop_kernel(const Phase2CoopDesc<T
   const int nr = d.nr, nwg = d.nwg, tid = threadIdx.x, nt = blockDim.x;
   const int wave = tid >> 6, lane = tid & 63, nwave = nt >> 6;
   const int cb0 = j * d.wcols, w = min(d.wcols, d.nc - cb0);
-  T* Es = reinterpret_cast<T*>(smem);              // nr x wcols, ld nr
-  T* u = Es + (size_t)nr * d.wcols;                // pivot column
+  T* const Eg = d.F + d.r0 + (size_t)(d.c0 + cb0) * d.ld;
+  T* Es;                                           // own columns, leading dimension les
+  T* u;                                            // pivot column
+  size_t les;
+  if (SLICE_LDS) {
+    Es = reinterpret_cast<T*>(smem);
+    les = nr;
+    u = Es + (size_t)nr * d.wcols;
+    for (int c = wave; c < w; c += nwave)
+      for (int i = lane; i < nr; i += 64) Es[i + (size_t)c * nr] = Eg[i + (size_t)c * d.ld];
+  } else {
+    Es = Eg;
+    les = d.ld;
+    u = reinterpret_cast<T*>(smem);
+  }
   T* vloc = u + nr;                                // own entries of the new V column
   char* lr = reinterpret_cast<char*>(vloc + d.wcols);
   char* lc = lr + nr;
-  {
-    const T* E = d.F + d.r0 + (size_t)(d.c0 + cb0) * d.ld;
-    for (int c = wave; c < w; c += nwave)
-      for (int i = lane; i < nr; i += 64) Es[i + (size_t)c * nr] = E[i + (size_t)c * d.ld];
-  }
   for (int i = tid; i < nr; i += nt) lr[i] = 1;
   for (int c = tid; c < w; c += nt) lc[c] = 1;
   __syncthreads();
@@ -688,7 +710,7 @@ __global__ __launch_bounds__(256) void phase2_coop_kernel(const Phase2CoopDesc<T
     for (int c = wave; c < w; c += nwave) {
       const T v = pending ? vloc[c] : (T)0;
       const bool cc = lc[c] != 0;
-      T* col = Es + (size_t)c * nr;
+      T* col = Es + (size_t)c * les;
       const unsigned base = (unsigned)(cb0 + c) * (unsigned)nr;
       for (int i = lane; i < nr; i += 64) {
         T x = col[i];
@@ -708,28 +730,31 @@ __global__ __launch_bounds__(256) void phase2_coop_kernel(const Phase2CoopDesc<T
       const unsigned idx = 0xFFFFFFFFu - (unsigned)(best & 0xFFFFFFFFull);
       const int bc = (int)(idx / (unsigned)nr) - cb0;
       T* cd = d.cand + ((size_t)par * nwg + j) * nr;
-      for (int i = tid; i < nr; i += nt) cd[i] = Es[i + (size_t)bc * nr];
+      for (int i = tid; i < nr; i += nt) publish(cd + i, Es[i + (size_t)bc * les]);
     }
-    if (tid == 0) d.keys[(size_t)par * nwg + j] = best;
+    if (tid == 0) publish(d.keys + (size_t)par * nwg + j, (unsigned long long)best);
     arrivals += (unsigned)nwg;
     if (!block_group_barrier(d.bar, arrivals, spin_limit, status, &s_ok)) break;
     // every workgroup picks the same pivot from the published keys
-    if (tid == 0) {
-      u64 K = 0;
-      for (int q = 0; q < nwg; ++q) {
-        const u64 k = d.keys[(size_t)par * nwg + q];
-        K = k > K ? k : K;
+    {
+      u64 kq = 0;
+      for (int q = tid; q < nwg; q += nt) {
+        const u64 k = fetch(d.keys + (size_t)par * nwg + q);
+        kq = k > kq ? k : kq;
       }
-      s_key = K;
-      T pv = (T)0;
-      if (K != 0ull) {
-        const unsigned idx = 0xFFFFFFFFu - (unsigned)(K & 0xFFFFFFFFull);
-        const int y = (int)(idx / (unsigned)nr) / d.wcols;
-        pv = d.cand[((size_t)par * nwg + y) * nr + (int)(idx % (unsigned)nr)];
+      const u64 Kall = block_max_u64(kq, s_red);
+      if (tid == 0) {
+        s_key = Kall;
+        T pv = (T)0;
+        if (Kall != 0ull) {
+          const unsigned idx = 0xFFFFFFFFu - (unsigned)(Kall & 0xFFFFFFFFull);
+          const int y = (int)(idx / (unsigned)nr) / d.wcols;
+          pv = fetch(d.cand + ((size_t)par * nwg + y) * nr + (int)(idx % (unsigned)nr));
+        }
+        s_piv = pv;
       }
-      s_piv = pv;
+      __syncthreads();
     }
-    __syncthreads();
     const u64 K = s_key;
     if (K == 0ull) break;
     const unsigned idx = 0xFFFFFFFFu - (unsigned)(K & 0xFFFFFFFFull);
@@ -744,8 +769,8 @@ __global__ __launch_bounds__(256) void phase2_coop_kernel(const Phase2CoopDesc<T
     }
     const int y = b / d.wcols;
     const T* cy = d.cand + ((size_t)par * nwg + y) * nr;
-    for (int i = tid; i < nr; i += nt) u[i] = cy[i];
-    for (int c = tid; c < w; c += nt) vloc[c] = Es[a + (size_t)c * nr] / piv;
+    for (int i = tid; i < nr; i += nt) u[i] = fetch(cy + i);
+    for (int c = tid; c < w; c += nt) vloc[c] = Es[a + (size_t)c * les] / piv;
     __syncthreads();
     {   // this workgroup's share of U(:, r), and V(own columns, r)
       const int ch = (nr + nwg - 1) / nwg, i0 = j * ch, i1 = min(nr, i0 + ch);
@@ -1050,50 +1075,50 @@ inline int grid_for(int64_t n, int block = 256, int cap = 8192) {
 template <typename T>
 void launch_gemm(const GemmDesc<T>* d, int ndesc, int tiles, hipStream_t st) {
   if (ndesc <= 0 || tiles <= 0) return;
-  hipLaunchKernelGGL(gemm_kernel<T>, dim3(tiles), dim3(256), 0, st, d, ndesc);
+  MFH_LAUNCH(gemm_kernel<T>, dim3(tiles), dim3(256), 0, st, d, ndesc);
 }
 template <typename T>
 void launch_gemm_reduce(const GemmDesc<T>* d, int ndesc, int tiles, hipStream_t st) {
   if (ndesc <= 0 || tiles <= 0) return;
-  hipLaunchKernelGGL(gemm_reduce_kernel<T>, dim3(tiles), dim3(256), 0, st, d, ndesc);
+  MFH_LAUNCH(gemm_reduce_kernel<T>, dim3(tiles), dim3(256), 0, st, d, ndesc);
 }
 template <typename T>
 void launch_mfma_probe(int* rows, int* cols, int* assumed, hipStream_t st) {
-  hipLaunchKernelGGL(mfma_probe_kernel<T>, dim3(1), dim3(64), 0, st, rows, cols, assumed);
+  MFH_LAUNCH(mfma_probe_kernel<T>, dim3(1), dim3(64), 0, st, rows, cols, assumed);
 }
 template void launch_mfma_probe<float>(int*, int*, int*, hipStream_t);
 template void launch_mfma_probe<double>(int*, int*, int*, hipStream_t);
 template <typename T>
 void launch_potrf(const PotrfDesc<T>* d, int ndesc, int nmax, int* status, hipStream_t st) {
   if (ndesc <= 0) return;
-  if (nmax <= 64) hipLaunchKernelGGL((potrf_kernel<T, 64, 256>), dim3(ndesc), dim3(256), 0, st, d, status);
-  else hipLaunchKernelGGL((potrf_kernel<T, 128, 512>), dim3(ndesc), dim3(512), 0, st, d, status);
+  if (nmax <= 64) MFH_LAUNCH((potrf_kernel<T, 64, 256>), dim3(ndesc), dim3(256), 0, st, d, status);
+  else MFH_LAUNCH((potrf_kernel<T, 128, 512>), dim3(ndesc), dim3(512), 0, st, d, status);
 }
 template <typename T>
 void launch_skreg_full(const SkRegDesc<T>* d, int ndesc, double eps, int adaptive, int* status, hipStream_t st) {
   if (ndesc <= 0) return;
   if constexpr (sizeof(T) == 8)
-    hipLaunchKernelGGL((skreg_kernel<T, 2, 32, true, 512>), dim3(ndesc), dim3(512), 0, st, d, eps, adaptive, status);
+    MFH_LAUNCH((skreg_kernel<T, 2, 32, true, 512>), dim3(ndesc), dim3(512), 0, st, d, eps, adaptive, status);
   else
-    hipLaunchKernelGGL((skreg_kernel<T, 4, 32, true, 512>), dim3(ndesc), dim3(512), 0, st, d, eps, adaptive, status);
+    MFH_LAUNCH((skreg_kernel<T, 4, 32, true, 512>), dim3(ndesc), dim3(512), 0, st, d, eps, adaptive, status);
 }
 template <typename T>
 void launch_skreg_hat(const SkRegDesc<T>* d, int ndesc, double eps, int* status, hipStream_t st) {
   if (ndesc <= 0) return;
   if constexpr (sizeof(T) == 8)
-    hipLaunchKernelGGL((skreg_kernel<T, 2, 8, false, 1024>), dim3(ndesc), dim3(1024), 0, st, d, eps, 0, status);
+    MFH_LAUNCH((skreg_kernel<T, 2, 8, false, 1024>), dim3(ndesc), dim3(1024), 0, st, d, eps, 0, status);
   else
-    hipLaunchKernelGGL((skreg_kernel<T, 3, 24, false, 512>), dim3(ndesc), dim3(512), 0, st, d, eps, 0, status);
+    MFH_LAUNCH((skreg_kernel<T, 3, 24, false, 512>), dim3(ndesc), dim3(512), 0, st, d, eps, 0, status);
 }
 template <typename T>
 void launch_skelfac(const SkelFacDesc<T>* d, int ndesc, int wgs, int rmax, hipStream_t st) {
   if (ndesc <= 0 || wgs <= 0) return;
-  hipLaunchKernelGGL(skelfac_kernel<T>, dim3(wgs), dim3(256), (size_t)rmax * rmax * sizeof(T), st, d, ndesc);
+  MFH_LAUNCH(skelfac_kernel<T>, dim3(wgs), dim3(256), (size_t)rmax * rmax * sizeof(T), st, d, ndesc);
 }
 template <typename T>
 void launch_phase2(const Phase2Desc<T>* d, int ndesc, int maxrc, double eps, int* status, hipStream_t st) {
   if (ndesc <= 0) return;
-  hipLaunchKernelGGL(phase2_kernel<T>, dim3(ndesc), dim3(1024), (size_t)maxrc, st, d, eps, status);
+  MFH_LAUNCH(phase2_kernel<T>, dim3(ndesc), dim3(1024), (size_t)maxrc, st, d, eps, status);
 }
 template <typename T>
 int phase2_coop_wcols(int nr) {
@@ -1103,102 +1128,104 @@ int phase2_coop_wcols(int nr) {
   return w >= 1 ? (int)w : 0;
 }
 template <typename T>
-size_t phase2_coop_lds(int nr, int wcols) {
-  return (size_t)nr * wcols * sizeof(T) + (size_t)nr * sizeof(T) + (size_t)wcols * sizeof(T) + nr + wcols + 16;
+size_t phase2_coop_lds(int nr, int wcols, bool slice_lds) {
+  return (slice_lds ? (size_t)nr * wcols * sizeof(T) : 0) + (size_t)nr * sizeof(T) + (size_t)wcols * sizeof(T) +
+         nr + wcols + 16;
 }
 template <typename T>
-int phase2_coop_capacity(size_t lds) {
+int phase2_coop_capacity(size_t lds, bool slice_lds) {
   int dev = 0, cus = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(phase2_coop_kernel<T>), 256,
-                                                   lds) != hipSuccess)
-    return 0;
+  const void* k = slice_lds ? reinterpret_cast<const void*>(phase2_coop_kernel<T, true>)
+                            : reinterpret_cast<const void*>(phase2_coop_kernel<T, false>);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, 256, lds) != hipSuccess) return 0;
   return per * cus;
 }
 template <typename T>
-hipError_t launch_phase2_coop(const Phase2CoopDesc<T>* d, int ndesc, int wgs, size_t lds, double eps, int* status,
-                              int spin_limit, hipStream_t st) {
+hipError_t launch_phase2_coop(const Phase2CoopDesc<T>* d, int ndesc, int wgs, size_t lds, bool slice_lds,
+                              double eps, int* status, int spin_limit, hipStream_t st) {
   if (ndesc <= 0 || wgs <= 0) return hipSuccess;
   void* args[] = {(void*)&d, (void*)&ndesc, (void*)&eps, (void*)&status, (void*)&spin_limit};
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(phase2_coop_kernel<T>), dim3(wgs), dim3(256), args,
-                                    (unsigned)lds, st);
+  const void* k = slice_lds ? reinterpret_cast<const void*>(phase2_coop_kernel<T, true>)
+                            : reinterpret_cast<const void*>(phase2_coop_kernel<T, false>);
+  return hipLaunchCooperativeKernel(k, dim3(wgs), dim3(256), args, (unsigned)lds, st);
 }
 template <typename T>
 void launch_extadd(const ExtAddDesc<T>* d, int ndesc, int tiles, hipStream_t st) {
   if (ndesc <= 0 || tiles <= 0) return;
-  hipLaunchKernelGGL(extadd_kernel<T>, dim3(tiles), dim3(256), 0, st, d, ndesc);
+  MFH_LAUNCH(extadd_kernel<T>, dim3(tiles), dim3(256), 0, st, d, ndesc);
 }
 template <typename S, typename D>
 void launch_copy(const CopyDesc<S, D>* d, int ndesc, int tiles, hipStream_t st) {
   if (ndesc <= 0 || tiles <= 0) return;
-  hipLaunchKernelGGL((copy_kernel<S, D>), dim3(tiles), dim3(256), 0, st, d, ndesc);
+  MFH_LAUNCH((copy_kernel<S, D>), dim3(tiles), dim3(256), 0, st, d, ndesc);
 }
 template <typename T>
 void launch_cap(const CapDesc<T>* d, int ndesc, hipStream_t st) {
   if (ndesc <= 0) return;
-  hipLaunchKernelGGL(cap_kernel<T>, dim3(ndesc), dim3(256), 0, st, d);
+  MFH_LAUNCH(cap_kernel<T>, dim3(ndesc), dim3(256), 0, st, d);
 }
 void launch_gj_inverse(const InvDesc* d, int ndesc, int* status, hipStream_t st) {
   if (ndesc <= 0) return;
-  hipLaunchKernelGGL(gj_kernel, dim3(ndesc), dim3(1024), 0, st, d, status);
+  MFH_LAUNCH(gj_kernel, dim3(ndesc), dim3(1024), 0, st, d, status);
 }
 template <typename T>
 void launch_fill(T* p, int64_t n, T v, hipStream_t st) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(fill_kernel<T>, dim3(grid_for(n)), dim3(256), 0, st, p, n, v);
+  MFH_LAUNCH(fill_kernel<T>, dim3(grid_for(n)), dim3(256), 0, st, p, n, v);
 }
 template <typename T>
 void launch_assemble(T* base, const int64_t* dest, const int* src, const double* vals, int64_t cnt, hipStream_t st) {
   if (cnt <= 0) return;
-  hipLaunchKernelGGL(assemble_kernel<T>, dim3(grid_for(cnt)), dim3(256), 0, st, base, dest, src, vals, cnt);
+  MFH_LAUNCH(assemble_kernel<T>, dim3(grid_for(cnt)), dim3(256), 0, st, base, dest, src, vals, cnt);
 }
 template <typename T>
 void launch_vec_asm(const VecAsmDesc<T>* d, int ndesc, int nrhs, hipStream_t st) {
   if (ndesc <= 0) return;
-  hipLaunchKernelGGL(vec_asm_kernel<T>, dim3(ndesc, nrhs), dim3(256), 0, st, d, nrhs);
+  MFH_LAUNCH(vec_asm_kernel<T>, dim3(ndesc, nrhs), dim3(256), 0, st, d, nrhs);
 }
 template <typename T>
 void launch_vec_gather(const VecGatherDesc<T>* d, int ndesc, const T* xn, int N, int nrhs, hipStream_t st) {
   if (ndesc <= 0) return;
-  hipLaunchKernelGGL(vec_gather_kernel<T>, dim3(ndesc, nrhs), dim3(256), 0, st, d, xn, N, nrhs);
+  MFH_LAUNCH(vec_gather_kernel<T>, dim3(ndesc, nrhs), dim3(256), 0, st, d, xn, N, nrhs);
 }
 template <typename T>
 void launch_perm_in(const double* r, T* xn, const int* perm, int N, int nrhs, hipStream_t st) {
-  hipLaunchKernelGGL(perm_in_kernel<T>, dim3(grid_for((int64_t)N * nrhs)), dim3(256), 0, st, r, xn, perm, N, nrhs);
+  MFH_LAUNCH(perm_in_kernel<T>, dim3(grid_for((int64_t)N * nrhs)), dim3(256), 0, st, r, xn, perm, N, nrhs);
 }
 template <typename T>
 void launch_perm_out(const T* xn, double* z, const int* iperm, int N, int nrhs, hipStream_t st) {
-  hipLaunchKernelGGL(perm_out_kernel<T>, dim3(grid_for((int64_t)N * nrhs)), dim3(256), 0, st, xn, z, iperm, N, nrhs);
+  MFH_LAUNCH(perm_out_kernel<T>, dim3(grid_for((int64_t)N * nrhs)), dim3(256), 0, st, xn, z, iperm, N, nrhs);
 }
 
 void launch_spmv(const int* rowptr, const int* colind, const double* vals, const double* x, double* y, int n,
                  int nrhs, double alpha, double beta, hipStream_t st) {
-  hipLaunchKernelGGL(spmv_kernel, dim3((n + 255) / 256), dim3(256), 0, st, rowptr, colind, vals, x, y, n, nrhs,
+  MFH_LAUNCH(spmv_kernel, dim3((n + 255) / 256), dim3(256), 0, st, rowptr, colind, vals, x, y, n, nrhs,
                      alpha, beta);
 }
 void launch_mdot(const double* X, int64_t xstride, int nv, const double* w, int n, int nrhs, double* partial,
                  double* out, int accumulate, hipStream_t st) {
   const int nchunk = 64;
-  hipLaunchKernelGGL(mdot_partial_kernel, dim3(nchunk, nrhs), dim3(256), 0, st, X, xstride, nv, w, n, nrhs, partial);
-  hipLaunchKernelGGL(mdot_reduce_kernel, dim3((nv * nrhs + 255) / 256), dim3(256), 0, st, partial, nchunk, nv, nrhs,
+  MFH_LAUNCH(mdot_partial_kernel, dim3(nchunk, nrhs), dim3(256), 0, st, X, xstride, nv, w, n, nrhs, partial);
+  MFH_LAUNCH(mdot_reduce_kernel, dim3((nv * nrhs + 255) / 256), dim3(256), 0, st, partial, nchunk, nv, nrhs,
                      out, accumulate);
 }
 void launch_maxpy(const double* X, int64_t xstride, int nv, const double* coef, double* w, int n, int nrhs,
                   double sign, hipStream_t st) {
-  hipLaunchKernelGGL(maxpy_kernel, dim3(grid_for((int64_t)n * nrhs)), dim3(256), 0, st, X, xstride, nv, coef, w, n,
+  MFH_LAUNCH(maxpy_kernel, dim3(grid_for((int64_t)n * nrhs)), dim3(256), 0, st, X, xstride, nv, coef, w, n,
                      nrhs, sign);
 }
 void launch_scale_cols(const double* w, double* v, const double* norms, int n, int nrhs, hipStream_t st) {
-  hipLaunchKernelGGL(scale_cols_kernel, dim3(grid_for((int64_t)n * nrhs)), dim3(256), 0, st, w, v, norms, n, nrhs);
+  MFH_LAUNCH(scale_cols_kernel, dim3(grid_for((int64_t)n * nrhs)), dim3(256), 0, st, w, v, norms, n, nrhs);
 }
 void launch_xupdate(const double* Z, int64_t zstride, int nv, const double* y, double* x, int n, int nrhs,
                     hipStream_t st) {
-  hipLaunchKernelGGL(xupdate_kernel, dim3(grid_for((int64_t)n * nrhs)), dim3(256), 0, st, Z, zstride, nv, y, x, n,
+  MFH_LAUNCH(xupdate_kernel, dim3(grid_for((int64_t)n * nrhs)), dim3(256), 0, st, Z, zstride, nv, y, x, n,
                      nrhs);
 }
 void launch_axpby(const double* a, const double* b, double* c, double alpha, double beta, int64_t n, hipStream_t st) {
-  hipLaunchKernelGGL(axpby_kernel, dim3(grid_for(n)), dim3(256), 0, st, a, b, c, alpha, beta, n);
+  MFH_LAUNCH(axpby_kernel, dim3(grid_for(n)), dim3(256), 0, st, a, b, c, alpha, beta, n);
 }
 
 #define MFH_INST(T)                                                                              \
@@ -1210,9 +1237,9 @@ void launch_axpby(const double* a, const double* b, double* c, double alpha, dou
   template void launch_skelfac<T>(const SkelFacDesc<T>*, int, int, int, hipStream_t);            \
   template void launch_phase2<T>(const Phase2Desc<T>*, int, int, double, int*, hipStream_t);     \
   template int phase2_coop_wcols<T>(int);                                                         \
-  template size_t phase2_coop_lds<T>(int, int);                                                   \
-  template int phase2_coop_capacity<T>(size_t);                                                   \
-  template hipError_t launch_phase2_coop<T>(const Phase2CoopDesc<T>*, int, int, size_t, double, int*, int, \
+  template size_t phase2_coop_lds<T>(int, int, bool);                                             \
+  template int phase2_coop_capacity<T>(size_t, bool);                                             \
+  template hipError_t launch_phase2_coop<T>(const Phase2CoopDesc<T>*, int, int, size_t, bool, double, int*, int, \
                                             hipStream_t);                                         \
   template void launch_extadd<T>(const ExtAddDesc<T>*, int, int, hipStream_t);                   \
   template void launch_cap<T>(const CapDesc<T>*, int, hipStream_t);                              \

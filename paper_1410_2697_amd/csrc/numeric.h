@@ -30,6 +30,7 @@ struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
   MemStats* ms = nullptr;
+  int dev = 0;
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;

@@ -23,6 +23,7 @@
 #include <atomic>
 #include <condition_variable>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <thread>
 
@@ -37,9 +38,67 @@ namespace mfh {
     if (e_ != hipSuccess) throw Err{MF_EHIP, std::string(#x) + ": " + hipGetErrorString(e_)}; \
   } while (0)
 
+// Device blocks are cached for reuse instead of freed: a factorisation
+// allocates and releases the same sizes every time, and hipMalloc/hipFree of
+// hundreds of MB cost milliseconds and synchronise the device.  Sizes are
+// rounded (4 KiB below 2 MiB, 2 MiB above); a cached block serves a request
+// up to 25% smaller.  When hipMalloc fails, this device's cached blocks are
+// freed and the allocation retried.  Callers release a block only after the
+// work that uses it has completed.
+namespace {
+struct DevCache {
+  std::mutex mu;
+  std::multimap<size_t, std::pair<int, void*>> free;   // size -> (device, block)
+};
+DevCache& dev_cache() {
+  static DevCache* c = new DevCache();   // lives until the process ends
+  return *c;
+}
+size_t round_bytes(size_t b) {
+  const size_t big = size_t(2) << 20;
+  return b <= big ? (b + 4095) & ~size_t(4095) : (b + big - 1) & ~(big - 1);
+}
+void* dev_malloc(size_t& b, int dev) {
+  b = round_bytes(b);
+  DevCache& c = dev_cache();
+  {
+    std::lock_guard<std::mutex> g(c.mu);
+    for (auto it = c.free.lower_bound(b); it != c.free.end() && it->first <= b + b / 4; ++it)
+      if (it->second.first == dev) {
+        void* p = it->second.second;
+        b = it->first;
+        c.free.erase(it);
+        return p;
+      }
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, b) == hipSuccess) return p;
+  (void)hipGetLastError();
+  {
+    std::lock_guard<std::mutex> g(c.mu);
+    for (auto it = c.free.begin(); it != c.free.end();) {
+      if (it->second.first == dev) {
+        (void)hipFree(it->second.second);
+        it = c.free.erase(it);
+      } else {
+        ++it;
+      }
+    }
+  }
+  if (hipMalloc(&p, b) == hipSuccess) return p;
+  (void)hipGetLastError();
+  return nullptr;
+}
+void dev_free(void* p, size_t b, int dev) {
+  DevCache& c = dev_cache();
+  std::lock_guard<std::mutex> g(c.mu);
+  c.free.insert({b, {dev, p}});
+}
+}  // namespace
+
 void DevBuf::release() {
   if (p) {
-    (void)hipFree(p);
+    dev_free(p, bytes, dev);
     if (ms) ms->sub((int64_t)bytes);
   }
   p = nullptr;
@@ -50,12 +109,13 @@ void DevBuf::alloc(size_t b, MemStats* m) {
   release();
   ms = m;
   if (b == 0) b = 256;
-  hipError_t e = hipMalloc(&p, b);
-  if (e != hipSuccess) {
-    p = nullptr;
+  if (hipGetDevice(&dev) != hipSuccess) {
     (void)hipGetLastError();
-    throw Err{MF_ENOMEM, "hipMalloc of " + std::to_string(b) + " bytes failed"};
+    throw Err{MF_EHIP, "no current HIP device"};
   }
+  const size_t want = b;
+  p = dev_malloc(b, dev);
+  if (!p) throw Err{MF_ENOMEM, "device allocation of " + std::to_string(want) + " bytes failed"};
   bytes = b;
   if (ms) ms->add((int64_t)b);
 }
@@ -325,6 +385,7 @@ template <typename T>
 class Numeric : public NumericBase {
  public:
   Numeric(const Symbolic& s, const double* vals, const mf_opts& o);
+
   void apply(int nrhs, const double* r, double* z, hipStream_t st) override;
 
  private:
@@ -352,8 +413,15 @@ class Numeric : public NumericBase {
     std::vector<int> I, Iptr, J, Jptr;
     std::map<int, int> first;     // front -> index of its first block in this level
   };
+  struct FrontBdlr {              // BDLR sets of one front's blocks (pointers start at 0)
+    std::vector<int> I, Iptr, J, Jptr;
+  };
   std::vector<LevelBdlr> lvb;
-  std::thread worker;
+  std::vector<FrontBdlr> fbd;     // by front
+  std::vector<int> bd_order;      // HODLR fronts, level by level
+  std::vector<int> bd_left;       // fronts of each level still to do
+  std::atomic<int> bd_next{0};
+  std::vector<std::thread> workers;
   std::mutex mu;
   std::condition_variable cv;
   int lvb_ready = 0;
@@ -381,6 +449,12 @@ class Numeric : public NumericBase {
   };
   std::map<int, std::unique_ptr<Plan>> plans;
   Plan* get_plan(int nrhs);
+  // Declared last, so destroyed first (also when the constructor throws):
+  // device blocks go back to the allocator cache only after the work that
+  // may still use them has finished.
+  struct SyncGuard {
+    ~SyncGuard() { (void)hipDeviceSynchronize(); }
+  } sync_guard;
 };
 
 template <typename T>
@@ -416,8 +490,59 @@ Numeric<T>::Numeric(const Symbolic& s, const double* vals, const mf_opts& o) {
     fn[p].ld = f.n();
   }
 
-  // ---- front workspace plan: one region per level, first fit over offsets
+  // BDLR sets are host graph work: worker threads take the HODLR fronts in
+  // level order while the device factors the levels below; a level is ready
+  // once all its fronts are done.
   const int H = (int)s.levels.size();
+  lvb.assign(H, {});
+  fbd.assign(s.fronts.size(), {});
+  bd_left.assign(H, 0);
+  bd_order.clear();
+  for (int h = 0; h < H; ++h)
+    for (int p : s.levels[h])
+      if (!fn[p].dense) {
+        bd_order.push_back(p);
+        ++bd_left[h];
+      }
+  while (lvb_ready < H && bd_left[lvb_ready] == 0) ++lvb_ready;
+  struct Joiner {
+    Numeric* self;
+    ~Joiner() {
+      self->cancel = true;
+      for (auto& t : self->workers)
+        if (t.joinable()) t.join();
+    }
+  } joiner{this};
+  if (hodlr && !bd_order.empty()) {
+    const int nthreads =
+        std::max(1, std::min<int>({(int)std::thread::hardware_concurrency(), 16, (int)bd_order.size()}));
+    for (int t = 0; t < nthreads; ++t)
+      workers.emplace_back([this, H]() {
+        BdlrScratch w;
+        for (;;) {
+          const int i = bd_next.fetch_add(1);
+          if (i >= (int)bd_order.size() || cancel) return;
+          const int p = bd_order[i];
+          const int h = sym->fronts[p].height;
+          bool ok = true;
+          try {
+            FrontBdlr& f = fbd[p];
+            f.Iptr.assign(1, 0);
+            f.Jptr.assign(1, 0);
+            bdlr_front(*sym, p, opts.bdlr_depth, opts.bdlr_cap, w, f.I, f.Iptr, f.J, f.Jptr);
+          } catch (...) {
+            ok = false;
+          }
+          std::lock_guard<std::mutex> g(mu);
+          if (!ok) worker_failed = true;
+          --bd_left[h];
+          while (lvb_ready < H && bd_left[lvb_ready] == 0) ++lvb_ready;
+          if (worker_failed) lvb_ready = H;
+          cv.notify_all();
+        }
+      });
+  }
+  // ---- front workspace plan: one region per level, first fit over offsets
   std::vector<int64_t> reg_off(H), reg_elems(H);
   std::vector<int> reg_end(H);
   std::vector<int64_t> front_elem_off(nfr);
@@ -489,41 +614,6 @@ Numeric<T>::Numeric(const Symbolic& s, const double* vals, const mf_opts& o) {
     d_relmap.alloc(std::max<size_t>(rm.size(), 1) * sizeof(int), &ms);
     HIPCHK(hipMemcpyAsync(d_relmap.p, rm.data(), rm.size() * sizeof(int), hipMemcpyHostToDevice, st));
     HIPCHK(hipStreamSynchronize(st));
-  }
-  // BDLR sets are host graph work: a worker thread produces them level by
-  // level while the device factors the levels below.
-  lvb.assign(H, {});
-  struct Joiner {
-    Numeric* self;
-    ~Joiner() {
-      self->cancel = true;
-      if (self->worker.joinable()) self->worker.join();
-    }
-  } joiner{this};
-  if (hodlr) {
-    worker = std::thread([this, H]() {
-      try {
-        BdlrScratch w;
-        for (int h = 0; h < H && !cancel; ++h) {
-          LevelBdlr& lb = lvb[h];
-          lb.Iptr.assign(1, 0);
-          lb.Jptr.assign(1, 0);
-          for (int p : sym->levels[h]) {
-            if (fn[p].dense) continue;
-            lb.first[p] = (int)lb.Iptr.size() - 1;
-            bdlr_front(*sym, p, opts.bdlr_depth, opts.bdlr_cap, w, lb.I, lb.Iptr, lb.J, lb.Jptr);
-          }
-          std::lock_guard<std::mutex> g(mu);
-          lvb_ready = h + 1;
-          cv.notify_all();
-        }
-      } catch (...) {
-        std::lock_guard<std::mutex> g(mu);
-        worker_failed = true;
-        lvb_ready = H;
-        cv.notify_all();
-      }
-    });
   }
   ranks.assign(s.nblocks, -1);
 
@@ -716,6 +806,20 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
     cv.wait(lk, [&] { return lvb_ready > h; });
     if (worker_failed) throw Err{MF_ENOMEM, "BDLR set construction failed"};
   }
+  {   // this level's sets, fronts in level order
+    LevelBdlr& L = lvb[h];
+    L.Iptr.assign(1, 0);
+    L.Jptr.assign(1, 0);
+    for (int p : Hs) {
+      const FrontBdlr& f = fbd[p];
+      L.first[p] = (int)L.Iptr.size() - 1;
+      const int io = (int)L.I.size(), jo = (int)L.J.size();
+      L.I.insert(L.I.end(), f.I.begin(), f.I.end());
+      L.J.insert(L.J.end(), f.J.begin(), f.J.end());
+      for (size_t k = 1; k < f.Iptr.size(); ++k) L.Iptr.push_back(io + f.Iptr[k]);
+      for (size_t k = 1; k < f.Jptr.size(); ++k) L.Jptr.push_back(jo + f.Jptr[k]);
+    }
+  }
   const LevelBdlr& lb = lvb[h];
   const int* dI;
   const int* dJ;
@@ -732,14 +836,16 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
     int p, bi, gb, lk, nI, nJ, kcap, capr;
     bool full;                 // whole block held in registers by one workgroup
     int nwg, wcols;            // phase 2 over nwg workgroups (0: one workgroup streams the block)
+    bool slds;                 // their column slices live in LDS (else updated in place in the front)
     int *pr, *pc, *rank1, *rank;
     double* u11;
     T *M, *U, *V;
     unsigned long long* keys;
     T* cand;
   };
-  const size_t coop_lds = kPhase2CoopLds;
-  const int coop_capacity = phase2_coop_capacity<T>(coop_lds);
+  const size_t coop_lds = kPhase2CoopLds, coop_lds_g = 48 * 1024;
+  const int coop_capacity = phase2_coop_capacity<T>(coop_lds, true);
+  const int coop_capacity_g = phase2_coop_capacity<T>(coop_lds_g, false);
   std::vector<BR> br;
   for (int p : Hs) {
     const Front& f = s.fronts[p];
@@ -752,12 +858,27 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
       x.kcap = std::min(x.nI, x.nJ);
       x.capr = std::max(std::min({B.nr, B.nc, opts.rank_cap}), x.kcap);
       x.full = B.nr <= skreg_full_rows<T>() && B.nc <= skreg_full_cols<T>();
-      if (!x.full && adaptive) {       // phase 2 over several workgroups when a slice fits LDS
+      if (!x.full && adaptive) {
+        // phase 2 over several workgroups: column slices in LDS when they fit
+        // the resident workgroups, else updated in place (about 64K entries each)
         const int wc = phase2_coop_wcols<T>(B.nr);
-        if (wc > 0) {
-          x.nwg = cdiv(B.nc, wc);
-          x.wcols = cdiv(B.nc, x.nwg);
-          if (x.nwg > coop_capacity) x.nwg = 0;
+        const int nl = wc > 0 ? cdiv(B.nc, wc) : 0;
+        if (nl > 0 && nl <= coop_capacity) {
+          x.nwg = nl;
+          x.wcols = cdiv(B.nc, nl);
+          x.slds = true;
+        } else if (phase2_coop_lds<T>(B.nr, 1, false) + 64 * sizeof(T) <= coop_lds_g) {
+          int ng = std::min(coop_capacity_g, std::max(1, (int)(((int64_t)B.nr * B.nc + 65535) / 65536)));
+          ng = std::min(ng, B.nc);
+          x.wcols = cdiv(B.nc, std::max(ng, 1));
+          x.nwg = cdiv(B.nc, x.wcols);
+          while (phase2_coop_lds<T>(B.nr, x.wcols, false) > coop_lds_g) {   // keep vloc + lc within LDS
+            ++x.nwg;
+            x.wcols = cdiv(B.nc, x.nwg);
+            x.nwg = cdiv(B.nc, x.wcols);
+          }
+          x.slds = false;
+          if (x.nwg > coop_capacity_g) x.nwg = 0;
         }
       }
       br.push_back(x);
@@ -844,9 +965,9 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
         q.F = fx.F; q.ld = fx.ld; q.r0 = B.r0; q.nr = B.nr; q.c0 = B.c0; q.nc = B.nc;
         q.piv_r = x.pr; q.piv_c = x.pc; q.rank1 = x.rank1; q.u11 = x.u11;
         q.U = x.U; q.ldu = B.nr; q.V = x.V; q.ldv = B.nc; q.cap = x.capr; q.rank = x.rank;
-        q.bar = bars + 64 * p2c.size();
         q.keys = x.keys; q.cand = x.cand;
         q.nwg = x.nwg; q.wcols = x.wcols;
+        q.slice_lds = x.slds ? 1 : 0;
         p2c.push_back(q);
         continue;
       }
@@ -858,17 +979,24 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
       maxrc = std::max(maxrc, B.nr + B.nc);
     }
   }
-  // cooperative launches: consecutive groups of blocks whose workgroups can all be resident
-  struct CoopGroup { size_t first; int n, wgs; };
+  // cooperative launches: consecutive groups of blocks of one slice mode
+  // whose workgroups can all be resident (descriptors ordered by mode)
+  std::stable_sort(p2c.begin(), p2c.end(), [](const Phase2CoopDesc<T>& a, const Phase2CoopDesc<T>& b) {
+    return a.slice_lds > b.slice_lds;
+  });
+  struct CoopGroup { size_t first; int n, wgs; bool slds; };
   std::vector<CoopGroup> cgroups;
   for (size_t i = 0; i < p2c.size(); ++i) {
-    if (cgroups.empty() || cgroups.back().wgs + p2c[i].nwg > coop_capacity)
-      cgroups.push_back({i, 0, 0});
+    const bool sl = p2c[i].slice_lds != 0;
+    const int capg = sl ? coop_capacity : coop_capacity_g;
+    if (cgroups.empty() || cgroups.back().slds != sl || cgroups.back().wgs + p2c[i].nwg > capg)
+      cgroups.push_back({i, 0, 0, sl});
     CoopGroup& g = cgroups.back();
     p2c[i].wg0 = g.wgs;
     g.wgs += p2c[i].nwg;
     ++g.n;
   }
+  for (size_t i = 0; i < p2c.size(); ++i) p2c[i].bar = bars + 64 * i;
   if ((size_t)rmax1 * rmax1 * sizeof(T) > (size_t)kLdsMax)
     throw Err{MF_EINVAL, "phase-1 rank bound too large for LDS: lower bdlr_cap"};
   if (maxrc > kLdsMax) throw Err{MF_EINVAL, "block too large for the phase-2 kernel"};
@@ -899,8 +1027,10 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
       const auto* dc = reinterpret_cast<const Phase2CoopDesc<T>*>(base + op2c);
       for (const CoopGroup& g : cgroups) {
         const int id = prof_begin(pk<T>(PK_PHASE2C_F64), st, 0.0, 0.0);
+        prof_stream_start(id, st);
         coop_ids.push_back(id);
-        const hipError_t e = launch_phase2_coop<T>(dc + g.first, g.n, g.wgs, coop_lds, eps, dstat, kSpinLimit, st);
+        const hipError_t e = launch_phase2_coop<T>(dc + g.first, g.n, g.wgs, g.slds ? coop_lds : coop_lds_g, g.slds,
+                                                   eps, dstat, kSpinLimit, st);
         prof_end(id, st);
         if (e != hipSuccess) throw Err{MF_EHIP, std::string("phase-2 launch: ") + hipGetErrorString(e)};
       }

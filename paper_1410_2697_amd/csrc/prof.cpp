@@ -27,7 +27,9 @@ struct Rec {
   int kind;
   hipEvent_t a, b;
   double flops, bytes;
+  int state;        // 0 waiting for a launch, 1 events taken by a launch, 2 recorded here, 3 dropped
 };
+thread_local int t_pending = -1;   // record whose events the next MFH_LAUNCH takes
 
 struct State {
   std::mutex mu;
@@ -69,21 +71,51 @@ int prof_begin(int kind, hipStream_t st, double flops, double bytes) {
   if (!((s.mask.load(std::memory_order_relaxed) >> kind) & 1)) return -1;
   std::lock_guard<std::mutex> g(s.mu);
   if (s.recs.size() >= (size_t(1) << kIdxBits)) return -1;
-  Rec r{kind, take(s), take(s), flops, bytes};
-  if (!r.a || !r.b || hipEventRecord(r.a, st) != hipSuccess) {
+  Rec r{kind, take(s), take(s), flops, bytes, 0};
+  (void)st;
+  if (!r.a || !r.b) {
     if (r.a) s.pool.push_back(r.a);
     if (r.b) s.pool.push_back(r.b);
     return -1;
   }
   s.recs.push_back(r);
-  return ((s.session & 0x3F) << kIdxBits) | (int)(s.recs.size() - 1);
+  t_pending = (int)(s.recs.size() - 1);
+  return ((s.session & 0x3F) << kIdxBits) | t_pending;
+}
+
+bool prof_take(hipEvent_t* start, hipEvent_t* stop) {
+  if (t_pending < 0) return false;
+  State& s = S();
+  std::lock_guard<std::mutex> g(s.mu);
+  const int i = t_pending;
+  t_pending = -1;
+  if (i >= (int)s.recs.size() || s.recs[i].state != 0) return false;
+  s.recs[i].state = 1;
+  *start = s.recs[i].a;
+  *stop = s.recs[i].b;
+  return true;
+}
+
+void prof_stream_start(int id, hipStream_t st) {
+  if (id < 0) return;
+  State& s = S();
+  std::lock_guard<std::mutex> g(s.mu);
+  Rec* r = find(s, id);
+  if (!r || r->state != 0) return;
+  if ((int)(r - s.recs.data()) == t_pending) t_pending = -1;
+  r->state = 2;
+  (void)hipEventRecord(r->a, st);
 }
 
 void prof_end(int id, hipStream_t st) {
   if (id < 0) return;
   State& s = S();
   std::lock_guard<std::mutex> g(s.mu);
-  if (Rec* r = find(s, id)) (void)hipEventRecord(r->b, st);
+  Rec* r = find(s, id);
+  if (!r) return;
+  if ((int)(r - s.recs.data()) == t_pending) t_pending = -1;
+  if (r->state == 2) (void)hipEventRecord(r->b, st);
+  else if (r->state == 0) r->state = 3;   // nothing was launched
 }
 
 void prof_add(int id, double flops, double bytes) {
@@ -114,6 +146,7 @@ void prof_start(const std::string& names) {
     s.pool.push_back(r.b);
   }
   s.recs.clear();
+  t_pending = -1;
   ++s.session;
   s.mask.store(m);
 }
@@ -126,7 +159,8 @@ std::vector<ProfTotal> prof_stop() {
   for (int k = 0; k < PK_COUNT; ++k) t[k] = ProfTotal{k, 0, 0.0, 0.0, 0.0};
   for (Rec& r : s.recs) {
     float ms = 0.f;
-    if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+    if ((r.state == 1 || r.state == 2) && hipEventSynchronize(r.b) == hipSuccess &&
+        hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
       ProfTotal& x = t[r.kind];
       x.launches += 1;
       x.seconds += 1e-3 * ms;

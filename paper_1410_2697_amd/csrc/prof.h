@@ -3,6 +3,7 @@
 // work (flops, bytes) as counted on the host.  Off unless started through
 // mf_prof_start; then each timed launch costs two event records.
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -34,9 +35,27 @@ constexpr int pk(int f64_kind) { return sizeof(T) == 4 ? f64_kind + 1 : f64_kind
 
 const char* prof_name(int kind);
 
-// id >= 0 when the launch is timed; -1 otherwise (all calls then do nothing)
+// id >= 0 when the launch is timed; -1 otherwise (all calls then do nothing).
+// A timed record hands its two events to the next kernel launched by this
+// thread through MFH_LAUNCH, which has the runtime stamp the kernel's own
+// start and end (no launch gap inside the interval).  prof_end records the
+// events on the stream instead when no such launch took them (cooperative
+// launches), and drops the record when nothing was launched.
 int prof_begin(int kind, hipStream_t st, double flops, double bytes);
 void prof_end(int id, hipStream_t st);
+bool prof_take(hipEvent_t* start, hipEvent_t* stop);
+// for a launch that cannot take events: record the start on the stream now
+void prof_stream_start(int id, hipStream_t st);
+
+// launch through here so that a pending timing record gets kernel-stamped events
+#define MFH_LAUNCH(kernel, grid, block, shmem, stream, ...)                                         \
+  do {                                                                                              \
+    hipEvent_t mfh_a_, mfh_b_;                                                                      \
+    if (::mfh::prof_take(&mfh_a_, &mfh_b_))                                                         \
+      hipExtLaunchKernelGGL(kernel, grid, block, shmem, stream, mfh_a_, mfh_b_, 0, __VA_ARGS__);    \
+    else                                                                                            \
+      hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__);                          \
+  } while (0)
 // work known only after the launch (e.g. ranks read back later)
 void prof_add(int id, double flops, double bytes);
 

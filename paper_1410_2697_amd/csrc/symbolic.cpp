@@ -15,10 +15,33 @@
 #include <cstring>
 #include <limits>
 #include <numeric>
+#include <thread>
 #include <tuple>
 
 namespace mfh {
 namespace {
+
+// Runs f(begin, end, worker) over [0, n) split into contiguous chunks, on up
+// to 16 host threads (one when the range is small).
+template <typename F>
+void parallel_for(int n, int min_chunk, F&& f) {
+  const int hw = std::max(1u, std::thread::hardware_concurrency());
+  const int nt = std::max(1, std::min({hw, 16, n / std::max(1, min_chunk)}));
+  if (nt <= 1) {
+    if (n > 0) f(0, n, 0);
+    return;
+  }
+  std::vector<std::thread> th;
+  th.reserve(nt - 1);
+  const int ch = (n + nt - 1) / nt;
+  for (int t = 1; t < nt; ++t) {
+    const int b = t * ch, e = std::min(n, b + ch);
+    if (b < e) th.emplace_back([&f, b, e, t]() { f(b, e, t); });
+  }
+  f(0, std::min(n, ch), 0);
+  for (auto& x : th) x.join();
+}
+int max_workers() { return std::max(1, std::min<int>((int)std::thread::hardware_concurrency(), 16)); }
 
 struct NDCtx {
   int n, dim, leaf;
@@ -184,12 +207,14 @@ std::string analyze(int n, const int32_t* rowptr, const int32_t* colind, const d
   for (int r = 0; r < n; ++r) s.prow[s.iperm[r] + 1] = rowptr[r + 1] - rowptr[r];
   for (int i = 0; i < n; ++i) s.prow[i + 1] += s.prow[i];
   s.pcol.assign(s.nnz, 0);
-  for (int r = 0; r < n; ++r) {
-    int nr = s.iperm[r];
-    int o = s.prow[nr];
-    for (int k = rowptr[r]; k < rowptr[r + 1]; ++k) s.pcol[o++] = s.iperm[colind[k]];
-    std::sort(s.pcol.begin() + s.prow[nr], s.pcol.begin() + s.prow[nr + 1]);
-  }
+  parallel_for(n, 2048, [&](int r0, int r1, int) {
+    for (int r = r0; r < r1; ++r) {
+      const int nr = s.iperm[r];
+      int o = s.prow[nr];
+      for (int k = rowptr[r]; k < rowptr[r + 1]; ++k) s.pcol[o++] = s.iperm[colind[k]];
+      std::sort(s.pcol.begin() + s.prow[nr], s.pcol.begin() + s.prow[nr + 1]);
+    }
+  });
 
   const int nfr = (int)ctx.tree.size();
   s.fronts.resize(nfr);
@@ -204,36 +229,66 @@ std::string analyze(int n, const int32_t* rowptr, const int32_t* colind, const d
   for (int p = 0; p < nfr; ++p)
     for (int i = 0; i < s.fronts[p].npiv; ++i) owner[s.fronts[p].start + i] = p;
 
-  for (int p = 0; p < nfr; ++p) {
+  for (int p = 0; p < nfr; ++p) {     // children come first in postorder
     Front& f = s.fronts[p];
-    int st = f.start, e = f.start + f.npiv;
-    std::vector<int> U;
-    for (int i = st; i < e; ++i)
-      for (int k = s.prow[i]; k < s.prow[i + 1]; ++k)
-        if (s.pcol[k] >= e) U.push_back(s.pcol[k]);           // S_p (Eq. couplingSet)
-    for (int c : f.children)
-      for (int v : s.fronts[c].upd)
-        if (v < st || v >= e) U.push_back(v);
-    std::sort(U.begin(), U.end());
-    U.erase(std::unique(U.begin(), U.end()), U.end());
-    f.upd = std::move(U);
     int h = 0;
     for (int c : f.children) h = std::max(h, s.fronts[c].height + 1);
     f.height = h;
   }
-  // relative maps
-  for (int p = 0; p < nfr; ++p) {
-    const Front& f = s.fronts[p];
-    for (int c : f.children) {
-      Front& fc = s.fronts[c];
-      fc.relmap.resize(fc.upd.size());
-      for (size_t a = 0; a < fc.upd.size(); ++a) {
-        int g = fc.upd[a];
-        if (g < f.start + f.npiv) fc.relmap[a] = g - f.start;
-        else fc.relmap[a] = f.npiv + (int)(std::lower_bound(f.upd.begin(), f.upd.end(), g) - f.upd.begin());
-      }
+  int hmax = 0;
+  for (auto& f : s.fronts) hmax = std::max(hmax, f.height);
+  s.levels.assign(hmax + 1, {});
+  for (int p = 0; p < nfr; ++p) s.levels[s.fronts[p].height].push_back(p);
+  // I_p^f = (S_p u children's I^f) \ I_p, level by level (a level's fronts
+  // only read their children's sets); duplicates are dropped with a
+  // per-worker stamp array before sorting
+  {
+    std::vector<std::vector<int>> stamp(max_workers(), std::vector<int>());
+    for (int h = 0; h <= hmax; ++h) {
+      const std::vector<int>& L = s.levels[h];
+      parallel_for((int)L.size(), 1, [&](int b, int e, int t) {
+        std::vector<int>& mark = stamp[t];
+        if (mark.empty()) mark.assign(n, -1);
+        for (int q = b; q < e; ++q) {
+          const int p = L[q];
+          Front& f = s.fronts[p];
+          const int st = f.start, en = f.start + f.npiv;
+          std::vector<int> U;
+          for (int i = st; i < en; ++i)
+            for (int k = s.prow[i]; k < s.prow[i + 1]; ++k) {
+              const int g = s.pcol[k];
+              if (g >= en && mark[g] != p) {                  // S_p (Eq. couplingSet)
+                mark[g] = p;
+                U.push_back(g);
+              }
+            }
+          for (int c : f.children)
+            for (int v : s.fronts[c].upd)
+              if ((v < st || v >= en) && mark[v] != p) {
+                mark[v] = p;
+                U.push_back(v);
+              }
+          std::sort(U.begin(), U.end());
+          f.upd = std::move(U);
+        }
+      });
     }
   }
+  // relative maps (each child belongs to one parent: fronts are independent)
+  parallel_for(nfr, 16, [&](int b, int e, int) {
+    for (int p = b; p < e; ++p) {
+      const Front& f = s.fronts[p];
+      for (int c : f.children) {
+        Front& fc = s.fronts[c];
+        fc.relmap.resize(fc.upd.size());
+        for (size_t a = 0; a < fc.upd.size(); ++a) {
+          int g = fc.upd[a];
+          if (g < f.start + f.npiv) fc.relmap[a] = g - f.start;
+          else fc.relmap[a] = f.npiv + (int)(std::lower_bound(f.upd.begin(), f.upd.end(), g) - f.upd.begin());
+        }
+      }
+    }
+  });
   // cluster trees and blocks
   int nb = 0;
   s.block_base.assign(nfr + 1, 0);
@@ -249,29 +304,45 @@ std::string analyze(int n, const int32_t* rowptr, const int32_t* colind, const d
   }
   s.block_base[nfr] = nb;
   s.nblocks = nb;
-  // assembly map: lower entries in CSR order
-  const size_t nlow = (size_t)(s.nnz + n) / 2;
-  s.asm_front.reserve(nlow);
-  s.asm_row.reserve(nlow);
-  s.asm_col.reserve(nlow);
-  s.asm_src.reserve(nlow);
-  for (int r = 0; r < n; ++r)
-    for (int k = rowptr[r]; k < rowptr[r + 1]; ++k) {
-      int i = s.iperm[r], j = s.iperm[colind[k]];
-      if (i < j) continue;
-      int p = owner[j];
-      const Front& f = s.fronts[p];
-      int row = i < f.start + f.npiv ? i - f.start
-                : f.npiv + (int)(std::lower_bound(f.upd.begin(), f.upd.end(), i) - f.upd.begin());
-      s.asm_front.push_back(p);
-      s.asm_row.push_back(row);
-      s.asm_col.push_back(j - f.start);
-      s.asm_src.push_back(k);
-    }
-  int hmax = 0;
-  for (auto& f : s.fronts) hmax = std::max(hmax, f.height);
-  s.levels.assign(hmax + 1, {});
-  for (int p = 0; p < nfr; ++p) s.levels[s.fronts[p].height].push_back(p);
+  // assembly map: lower entries in CSR order.  Rows are split over workers:
+  // one pass counts each row's lower entries, a second writes them at their
+  // offsets.
+  {
+    std::vector<int64_t> off(n + 1, 0);
+    parallel_for(n, 2048, [&](int r0, int r1, int) {
+      for (int r = r0; r < r1; ++r) {
+        const int i = s.iperm[r];
+        int c = 0;
+        for (int k = rowptr[r]; k < rowptr[r + 1]; ++k) c += i >= s.iperm[colind[k]];
+        off[r + 1] = c;
+      }
+    });
+    for (int r = 0; r < n; ++r) off[r + 1] += off[r];
+    const size_t tot = (size_t)off[n];
+    s.asm_front.resize(tot);
+    s.asm_row.resize(tot);
+    s.asm_col.resize(tot);
+    s.asm_src.resize(tot);
+    parallel_for(n, 2048, [&](int r0, int r1, int) {
+      for (int r = r0; r < r1; ++r) {
+        int64_t o = off[r];
+        const int i = s.iperm[r];
+        for (int k = rowptr[r]; k < rowptr[r + 1]; ++k) {
+          const int j = s.iperm[colind[k]];
+          if (i < j) continue;
+          const int p = owner[j];
+          const Front& f = s.fronts[p];
+          s.asm_front[o] = p;
+          s.asm_row[o] = i < f.start + f.npiv
+                             ? i - f.start
+                             : f.npiv + (int)(std::lower_bound(f.upd.begin(), f.upd.end(), i) - f.upd.begin());
+          s.asm_col[o] = j - f.start;
+          s.asm_src[o] = k;
+          ++o;
+        }
+      }
+    });
+  }
   return "";
 }
 

@@ -121,9 +121,12 @@ mf_status skel_t(void* F, int ld, int r0, int nr, int c0, int nc, const int* I, 
     mfh::launch_skelfac<T>(reinterpret_cast<mfh::SkelFacDesc<T>*>(dd + 1024), 1, wgs, kcap > 0 ? kcap : 1, nullptr);
     if (adaptive) {
       mfh::launch_gemm<T>(reinterpret_cast<mfh::GemmDesc<T>*>(dd + 2048), 1, gtiles, nullptr);
-      const int wc = adaptive == 1 ? mfh::phase2_coop_wcols<T>(nr) : 0;
+      // 1: slices in LDS; 3: slices updated in place; 2: one workgroup
+      const bool slds = adaptive == 1;
+      int wc = adaptive == 1 ? mfh::phase2_coop_wcols<T>(nr) : (adaptive == 3 ? 4 : 0);
       int nwg = wc > 0 ? (nc + wc - 1) / wc : 0;
-      if (nwg > mfh::phase2_coop_capacity<T>(mfh::kPhase2CoopLds)) nwg = 0;
+      const size_t lds = slds ? (size_t)mfh::kPhase2CoopLds : mfh::phase2_coop_lds<T>(nr, wc, false);
+      if (nwg > mfh::phase2_coop_capacity<T>(lds, slds)) nwg = 0;
       if (nwg > 0) {
         char* cs = nullptr;   // barrier counter, keys, candidate columns
         const size_t kb = 256 + (size_t)2 * nwg * 8, cb = (size_t)2 * nwg * nr * sizeof(T);
@@ -139,8 +142,8 @@ mf_status skel_t(void* F, int ld, int r0, int nr, int c0, int nc, const int* I, 
           qd.cand = reinterpret_cast<T*>(cs + kb);
           qd.wg0 = 0; qd.nwg = nwg; qd.wcols = (nc + nwg - 1) / nwg;
           hipMemcpy(dd + 3072, &qd, sizeof(qd), hipMemcpyHostToDevice);
-          s = hip_ok(mfh::launch_phase2_coop<T>(reinterpret_cast<mfh::Phase2CoopDesc<T>*>(dd + 3072), 1, nwg,
-                                                mfh::kPhase2CoopLds, eps, status, 1 << 20, nullptr));
+          s = hip_ok(mfh::launch_phase2_coop<T>(reinterpret_cast<mfh::Phase2CoopDesc<T>*>(dd + 3072), 1, nwg, lds,
+                                                slds, eps, status, 1 << 20, nullptr));
           if (s == MF_OK) s = hip_ok(hipDeviceSynchronize());
           hipFree(cs);
         }

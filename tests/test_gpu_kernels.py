@@ -137,14 +137,15 @@ def _kernel_matrix(m, n, seed, gap):
     return -np.log(np.linalg.norm(x[:, None, :] - y[None, :, :], axis=2))
 
 
-@pytest.mark.parametrize("adaptive", [0, 1, 2])
+@pytest.mark.parametrize("adaptive", [0, 1, 2, 3])
 @pytest.mark.parametrize("nr,nc,nI,nJ,eps", [(40, 30, 40, 30, 1e-6), (120, 90, 20, 15, 1e-5), (300, 200, 60, 50, 1e-8),
                                               (33, 47, 1, 1, 1e-4), (16, 16, 16, 16, 0.0), (100, 300, 40, 90, 1e-6),
                                               (128, 256, 0, 0, 1e-7), (700, 90, 30, 30, 1e-6)])
 def test_skeleton_fp64_matches_oracle(gpu_lib, adaptive, nr, nc, nI, nJ, eps):
     """Same pivots, rank and factors as the float64 oracle (Eq. Bhat plus the
     adaptive full-block phase; 1 = the large-block phase spread over
-    workgroups, 2 = one workgroup)."""
+    workgroups with slices in LDS, 2 = one workgroup, 3 = spread over
+    workgroups updating the block in place)."""
     import torch
     mfh = gpu_lib
     B = _kernel_matrix(nr, nc, nr + nc, 0.4)
@@ -184,7 +185,7 @@ def test_skeleton_fp64_matches_oracle(gpu_lib, adaptive, nr, nc, nI, nJ, eps):
         assert np.abs(E).max() < eps * np.abs(B).max() / (1 - 2.0 ** -20) * (1 + 1e-9)
 
 
-@pytest.mark.parametrize("adaptive", [1, 2])
+@pytest.mark.parametrize("adaptive", [1, 2, 3])
 @pytest.mark.parametrize("nr,nc,nI,nJ", [(200, 150, 40, 40), (600, 300, 120, 100), (256, 256, 16, 16),
                                          (1100, 700, 150, 150)])
 def test_skeleton_fp32_error_bound(gpu_lib, adaptive, nr, nc, nI, nJ):
