@@ -22,7 +22,7 @@ mf_status mfh_test_mfma_layout(int32_t precision, int32_t* rows, int32_t* cols, 
 /* C = alpha * op(A) * op(B) + beta * C through the grouped MFMA GEMM;
  * flags as the library's GemmFlags (1 lower-only C, 2/4 op(A) lower/upper,
  * 8/16 op(B) lower/upper triangular).  kchunk > 0 splits k into ranges of
- * kchunk (a multiple of 16; MF_EINVAL otherwise), summed by the separate
+ * kchunk (a multiple of 64; MF_EINVAL otherwise), summed by the separate
  * reduction kernel; 0 runs one workgroup per output tile. */
 mf_status mfh_test_gemm(int32_t precision, int32_t m, int32_t n, int32_t k, const void* A, int32_t lda,
                         int32_t opA, const void* B, int32_t ldb, int32_t opB, void* C, int32_t ldc,

@@ -10,6 +10,9 @@
 namespace mfh {
 
 constexpr int kTile = 64;            // GEMM output tile (rows and columns)
+template <typename T>
+constexpr int kGemmBK = sizeof(T) == 4 ? 64 : 32;   // GEMM k step (LDS-staged)
+constexpr int kGemmSplitAlign = 64;  // split-K ranges are multiples of this (and of every k step)
 constexpr double kTieRel = 1.0 / 1048576.0;   // 2^-20: near-ties in complete pivoting
 
 enum GemmFlags : int {
@@ -23,7 +26,8 @@ enum GemmFlags : int {
 // C = alpha * op(A) * op(B) + beta * C ; op(A) m x k, op(B) k x n.
 // If kdev != nullptr the inner dimension is *kdev (a rank produced on the
 // device); k is then an upper bound used only for validation.
-// Split K (ksplit > 1): workgroup split s sums k in [s*kchunk, (s+1)*kchunk)
+// Split K (ksplit > 1, kchunk a multiple of kGemmSplitAlign): workgroup split
+// s sums k in [s*kchunk, (s+1)*kchunk)
 // into part + s*m*n (m x n, ld m); a reduction launch then forms
 // C = alpha * sum_s part_s + beta * C in a fixed order (deterministic).
 template <typename T>

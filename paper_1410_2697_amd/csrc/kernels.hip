@@ -97,10 +97,12 @@ struct Mfma<float> {
 
 // ---------------------------------------------------------------- GEMM ----
 // 64x64 output tile per workgroup, 4 waves each owning a 32x32 quadrant as
-// 2x2 MFMA 16x16x4 tiles; K staged through LDS in steps of 16.
+// 2x2 MFMA 16x16x4 tiles.  K advances in steps of kGemmBK<T> staged through
+// LDS; the next step's operands are loaded into registers while the MFMAs
+// work on the current one.
 template <typename T>
 __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc<T>* __restrict__ descs, int ndesc) {
-  constexpr int BM = kTile, BN = kTile, BK = 16;
+  constexpr int BM = kTile, BN = kTile, BK = kGemmBK<T>, NQ = BK * 64 / 256;
   __shared__ T As[BK][BM + 1];
   __shared__ T Bs[BK][BN + 1];
   typedef typename Mfma<T>::v4 v4;
@@ -121,7 +123,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc<T>* __restrict
   if (flags & GF_A_UPPER) kb0 = max(kb0, m0);
   if (flags & GF_B_LOWER) kb0 = max(kb0, n0);
   kb0 = (kb0 / BK) * BK;
-  if (split) {                       // this workgroup's share of k (kchunk is a multiple of BK)
+  if (split) {                       // this workgroup's share of k (kchunk is a multiple of kGemmSplitAlign)
     kb0 = max(kb0, ks * d.kchunk);
     kend = min(kend, (ks + 1) * d.kchunk);
   }
@@ -132,30 +134,48 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc<T>* __restrict
   const int wave = tid >> 6, lane = tid & 63;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   const int li = lane & 15, lk = lane >> 4;
-  for (int kb = kb0; kb < kend; kb += BK) {
+  // per-thread load coordinates: (row of the tile, k offset) for each of NQ loads
+  // op N: row = tid & 63, k = (tid >> 6) + 4q;   op T: k = tid % BK, row = tid / BK + (256 / BK) q
+  T ra[NQ], rb[NQ];
+  auto load = [&](int kb) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < NQ; ++q) {
       int i, kk;
       if (opA == 0) { i = tid & 63; kk = (tid >> 6) + 4 * q; }
-      else { kk = tid & 15; i = (tid >> 4) + 16 * q; }
+      else { kk = tid % BK; i = tid / BK + (256 / BK) * q; }
       const int gi = m0 + i, gk = kb + kk;
-      T v = 0;
-      if (gi < m && gk < kend)
-        v = opA == 0 ? A[gi + (size_t)gk * lda] : A[gk + (size_t)gi * lda];
-      As[kk][i] = v;
+      ra[q] = (gi < m && gk < kend) ? (opA == 0 ? A[gi + (size_t)gk * lda] : A[gk + (size_t)gi * lda]) : (T)0;
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < NQ; ++q) {
       int j, kk;
-      if (opB == 0) { kk = tid & 15; j = (tid >> 4) + 16 * q; }
+      if (opB == 0) { kk = tid % BK; j = tid / BK + (256 / BK) * q; }
       else { j = tid & 63; kk = (tid >> 6) + 4 * q; }
       const int gj = n0 + j, gk = kb + kk;
-      T v = 0;
-      if (gj < n && gk < kend)
-        v = opB == 0 ? B[gk + (size_t)gj * ldb] : B[gj + (size_t)gk * ldb];
-      Bs[kk][j] = v;
+      rb[q] = (gj < n && gk < kend) ? (opB == 0 ? B[gk + (size_t)gj * ldb] : B[gj + (size_t)gk * ldb]) : (T)0;
     }
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      int i, kk;
+      if (opA == 0) { i = tid & 63; kk = (tid >> 6) + 4 * q; }
+      else { kk = tid % BK; i = tid / BK + (256 / BK) * q; }
+      As[kk][i] = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      int j, kk;
+      if (opB == 0) { kk = tid % BK; j = tid / BK + (256 / BK) * q; }
+      else { j = tid & 63; kk = (tid >> 6) + 4 * q; }
+      Bs[kk][j] = rb[q];
+    }
+  };
+  if (kb0 < kend) load(kb0);
+  for (int kb = kb0; kb < kend; kb += BK) {
+    stash();
     __syncthreads();
+    if (kb + BK < kend) load(kb + BK);      // in flight while the MFMAs run
 #pragma unroll
     for (int k4 = 0; k4 < BK / 4; ++k4) {
       const int kq = k4 * 4 + lk;

@@ -205,7 +205,7 @@ int finalize_gemm(std::vector<GemmDesc<T>>& v, T* part, size_t cap, std::vector<
     d.part = nullptr;
     if (want > 1 && !d.kdev && d.k >= 2 * kSplitChunk) {
       int sp = std::min(want, d.k / kSplitChunk);
-      const int chunk = cdiv(cdiv(d.k, sp), 16) * 16;
+      const int chunk = cdiv(cdiv(d.k, sp), kGemmSplitAlign) * kGemmSplitAlign;
       sp = cdiv(d.k, chunk);
       const size_t need = (size_t)sp * d.m * d.n;
       if (sp > 1 && used + need <= cap) {

@@ -191,7 +191,7 @@ mf_status mfh_test_mfma_layout(int32_t precision, int32_t* rows, int32_t* cols, 
 mf_status mfh_test_gemm(int32_t precision, int32_t m, int32_t n, int32_t k, const void* A, int32_t lda, int32_t opA,
                         const void* B, int32_t ldb, int32_t opB, void* C, int32_t ldc, double alpha, double beta,
                         int32_t flags, int32_t kchunk) {
-  if (m < 0 || n < 0 || k < 0 || !C || kchunk < 0 || kchunk % 16 != 0) return MF_EINVAL;
+  if (m < 0 || n < 0 || k < 0 || !C || kchunk < 0 || kchunk % mfh::kGemmSplitAlign != 0) return MF_EINVAL;
   if (precision == MF_FP64)
     return gemm_t<double>(m, n, k, A, lda, opA, B, ldb, opB, C, ldc, alpha, beta, flags, kchunk);
   return gemm_t<float>(m, n, k, A, lda, opA, B, ldb, opB, C, ldc, alpha, beta, flags, kchunk);

@@ -48,8 +48,9 @@ GEMM_CASES = [
     (1, 1, 1, 0, 0, 0, 0), (64, 64, 64, 0, 0, 0, 0), (100, 37, 70, 0, 1, 0, 0), (130, 1, 257, 1, 0, 0, 0),
     (5, 200, 3, 1, 1, 0, 0), (129, 129, 65, 0, 1, 1, 0), (96, 20, 96, 0, 0, 2, 0), (96, 20, 96, 1, 0, 4, 0),
     (50, 70, 70, 0, 1, 16, 0), (50, 70, 70, 0, 0, 8, 0), (77, 77, 0, 0, 0, 0, 0),
-    (100, 16, 1000, 1, 0, 0, 128), (130, 130, 300, 0, 1, 1, 64), (96, 20, 96, 0, 0, 2, 32),
-    (96, 20, 96, 1, 0, 4, 16), (50, 70, 70, 0, 1, 16, 16), (70, 50, 333, 1, 1, 8, 48), (7, 9, 20, 0, 0, 0, 64),
+    (100, 16, 1000, 1, 0, 0, 128), (130, 130, 300, 0, 1, 1, 64), (96, 20, 200, 0, 0, 2, 64),
+    (96, 20, 200, 1, 0, 4, 64), (50, 70, 170, 0, 1, 16, 64), (70, 50, 333, 1, 1, 8, 128), (7, 9, 20, 0, 0, 0, 64),
+    (65, 33, 129, 1, 1, 0, 0), (200, 130, 31, 0, 0, 1, 0), (64, 64, 200, 0, 1, 16, 0),
 ]
 
 
