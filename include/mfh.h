@@ -99,6 +99,8 @@ typedef struct {
   int32_t hodlr_fronts;
   int32_t status_bits;        /* device status word (1: non-positive pivot, 2: rank capacity)        */
   double factor_seconds;      /* wall time of mf_factor (host clock, synchronised)                   */
+  int64_t resident_bytes;     /* device bytes the handle holds now: factor, copy of A, apply and
+                                 GMRES workspaces                                                    */
 } mf_factor_info;
 
 /* Fill *o with defaults: HODLR, FP32, n_c 0, d -1 (no depth limit), cap 0
@@ -203,6 +205,76 @@ mf_status gmres_solve(mf_numeric_t* f, int32_t nrhs, const double* b, double* x,
 /* y = A x with the factor's device copy of A (float64 CSR), column-major
  * n x nrhs device arrays; asynchronous on stream. */
 mf_status mf_spmv(mf_numeric_t* f, int32_t nrhs, const double* x, double* y, void* stream);
+
+/*
+ * Device bytes of a factorisation with these options, before running it:
+ * *peak = most held during mf_factor, *persistent = what the handle then
+ * keeps, including apply and GMRES(restart) workspaces for nrhs right-hand
+ * sides.  Exact for the front workspace, dense fronts and fixed buffers; the
+ * HODLR part bounds each block rank by min(rows, cols, rank_cap,
+ * 8 sqrt(max(rows, cols))) (ranks grow like sqrt(n), Sec. 1).  Host only.
+ */
+mf_status mf_estimate_bytes(const mf_symbolic_t* sym, const mf_opts* opts, int32_t nrhs, int32_t restart,
+                            int64_t* persistent, int64_t* peak);
+
+/*
+ * Serving: a request server that factors and solves independent systems as
+ * they arrive, several at once on the device (continuous batching).
+ *  - mf_server_submit analyses the request on the caller's thread (copying
+ *    every input) and queues it with its mf_estimate_bytes peak.
+ *  - `slots` worker threads, each with its own HIP stream (default
+ *    priority), take queued requests in arrival order as soon as the head
+ *    request's estimated peak fits the memory budget next to the requests
+ *    running and the factors kept resident; their factorisations and solves
+ *    overlap on the device.  A request larger than the whole budget runs
+ *    when nothing else holds memory.  Resident factors that no request is
+ *    using are dropped, least recently used first, when memory is needed.
+ *  - With keep_factors, a request's factor stays on the device after its
+ *    solve; mf_server_resolve queues another solve with it (repeated
+ *    right-hand sides) until mf_server_release.
+ *  - mf_server_wait blocks until a request is done, copies x (host,
+ *    n x nrhs column-major, original ordering) and fills its timings.
+ * Handles of one server may be used from any thread.
+ */
+typedef struct mf_server_s mf_server_t;
+typedef struct {
+  int32_t slots;          /* requests on the device at once                                   */
+  int32_t leaf;           /* nested-dissection and HODLR leaf size                            */
+  int64_t mem_budget;     /* device bytes for running requests and resident factors;
+                             0 = 80% of the free device memory when the server starts       */
+  double tol;             /* GMRES tolerance (relative residual)                              */
+  mf_opts factor;         /* factorisation options (stream ignored)                           */
+  mf_gmres_opts gmres;    /* GMRES options (stream ignored)                                   */
+  int32_t keep_factors;   /* 1: keep each factor resident for mf_server_resolve               */
+  int32_t reserved;
+} mf_server_opts;
+
+typedef struct {
+  int32_t status;         /* mf_status of the request                                          */
+  int32_t iters_max;      /* largest GMRES iteration count over its right-hand sides           */
+  double relres_max;      /* largest final relative residual                                   */
+  double t_queue;         /* seconds from submit to admission                                  */
+  double t_analyze;       /* symbolic analysis (at submit)                                     */
+  double t_factor;        /* numeric factorisation (0 for a resolve)                           */
+  double t_solve;         /* GMRES, including copies of b and x                                */
+  double t_total;         /* submit to done                                                    */
+  int64_t est_bytes;      /* estimated peak used for admission                                 */
+  int64_t peak_bytes;     /* peak device bytes of its factorisation                            */
+  int64_t resident_bytes; /* device bytes its factor keeps (if resident)                       */
+} mf_request_info;
+
+mf_status mf_server_opts_default(mf_server_opts* o);
+mf_status mf_server_create(const mf_server_opts* o, mf_server_t** out);
+mf_status mf_server_submit(mf_server_t* sv, int32_t n, const int32_t* rowptr, const int32_t* colind,
+                           const double* vals, const double* coords, int32_t dim, int32_t nrhs,
+                           const double* b, int64_t* ticket);
+mf_status mf_server_resolve(mf_server_t* sv, int64_t factor_ticket, int32_t nrhs, const double* b,
+                            int64_t* ticket);
+mf_status mf_server_wait(mf_server_t* sv, int64_t ticket, double* x, mf_request_info* info);
+mf_status mf_server_release(mf_server_t* sv, int64_t factor_ticket);
+/* Bytes the server accounts now (running estimates + resident factors) and its budget. */
+mf_status mf_server_memory(mf_server_t* sv, int64_t* in_use, int64_t* budget);
+void mf_server_destroy(mf_server_t* sv);
 
 /*
  * Kernel timing for roofline reports (process-wide, all handles).

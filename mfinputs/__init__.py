@@ -2,9 +2,9 @@
 path.  Holds input generation only: no ordering, factorisation or solver
 arithmetic lives here."""
 from .fem import Csr, Problem, q1_grid, p1_kuhn_cube, rhs, grf_squared_exponential, lognormal_elements
-from .workloads import WORKLOADS, Workload, make_workload, serving_requests
+from .workloads import WORKLOADS, Workload, make_workload, serving_request, serving_requests
 
 __all__ = [
     "Csr", "Problem", "q1_grid", "p1_kuhn_cube", "rhs", "grf_squared_exponential",
-    "lognormal_elements", "WORKLOADS", "Workload", "make_workload", "serving_requests",
+    "lognormal_elements", "WORKLOADS", "Workload", "make_workload", "serving_request", "serving_requests",
 ]

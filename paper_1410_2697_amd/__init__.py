@@ -53,7 +53,21 @@ class FactorInfo(ctypes.Structure):
     _fields_ = [("persistent_bytes", ctypes.c_int64), ("peak_bytes", ctypes.c_int64),
                 ("workspace_bytes", ctypes.c_int64), ("nblocks", ctypes.c_int64), ("rank_sum", ctypes.c_int64),
                 ("rank_max", ctypes.c_int32), ("dense_fronts", ctypes.c_int32), ("hodlr_fronts", ctypes.c_int32),
-                ("status_bits", ctypes.c_int32), ("factor_seconds", ctypes.c_double)]
+                ("status_bits", ctypes.c_int32), ("factor_seconds", ctypes.c_double),
+                ("resident_bytes", ctypes.c_int64)]
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_int32), ("leaf", ctypes.c_int32), ("mem_budget", ctypes.c_int64),
+                ("tol", ctypes.c_double), ("factor", MfOpts), ("gmres", GmresOpts),
+                ("keep_factors", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class RequestInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iters_max", ctypes.c_int32), ("relres_max", ctypes.c_double),
+                ("t_queue", ctypes.c_double), ("t_analyze", ctypes.c_double), ("t_factor", ctypes.c_double),
+                ("t_solve", ctypes.c_double), ("t_total", ctypes.c_double), ("est_bytes", ctypes.c_int64),
+                ("peak_bytes", ctypes.c_int64), ("resident_bytes", ctypes.c_int64)]
 
 
 class KStat(ctypes.Structure):
@@ -84,6 +98,16 @@ SIGNATURES = [
     ("mf_apply", _I32, [_P, _I32, _P, _P, _P]),
     ("gmres_solve", _I32, [_P, _I32, _P, _P, _D, ctypes.POINTER(GmresOpts), ctypes.POINTER(GmresInfo)]),
     ("mf_spmv", _I32, [_P, _I32, _P, _P, _P]),
+    ("mf_estimate_bytes", _I32, [_P, ctypes.POINTER(MfOpts), _I32, _I32, ctypes.POINTER(_I64),
+                                 ctypes.POINTER(_I64)]),
+    ("mf_server_opts_default", _I32, [ctypes.POINTER(ServerOpts)]),
+    ("mf_server_create", _I32, [ctypes.POINTER(ServerOpts), ctypes.POINTER(_P)]),
+    ("mf_server_submit", _I32, [_P, _I32, _P, _P, _P, _P, _I32, _I32, _P, ctypes.POINTER(_I64)]),
+    ("mf_server_resolve", _I32, [_P, _I64, _I32, _P, ctypes.POINTER(_I64)]),
+    ("mf_server_wait", _I32, [_P, _I64, _P, ctypes.POINTER(RequestInfo)]),
+    ("mf_server_release", _I32, [_P, _I64]),
+    ("mf_server_memory", _I32, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
+    ("mf_server_destroy", None, [_P]),
     ("mf_prof_start", _I32, [ctypes.c_char_p]),
     ("mf_prof_stop", _I32, [ctypes.POINTER(KStat), _I32, ctypes.POINTER(_I32)]),
     ("mf_last_error", ctypes.c_char_p, []),
@@ -268,3 +292,83 @@ def prof_stop() -> list:
     _check(lib.mf_prof_stop(arr, cap, ctypes.byref(n)))
     return [{"name": arr[i].name.decode(), "launches": int(arr[i].launches), "seconds": float(arr[i].seconds),
              "flops": float(arr[i].flops), "bytes": float(arr[i].bytes)} for i in range(min(n.value, cap))]
+
+
+def estimate_bytes(sym: "Symbolic", nrhs: int = 1, restart: int = 30, opts: MfOpts | None = None, **kw) -> dict:
+    """Device bytes of a factorisation before running it (host only)."""
+    o = opts if opts is not None else default_opts(**kw)
+    pe, pk = _I64(0), _I64(0)
+    _check(load().mf_estimate_bytes(sym.h, ctypes.byref(o), int(nrhs), int(restart), ctypes.byref(pe),
+                                    ctypes.byref(pk)))
+    return {"persistent_bytes": pe.value, "peak_bytes": pk.value}
+
+
+class Server:
+    """Continuous-batching request server of the library (see include/mfh.h,
+    "Serving").  submit() analyses on the calling thread and returns a
+    ticket; wait() blocks for a ticket and returns (x, info) with x of shape
+    (n, nrhs).  Calls release the interpreter lock while they block."""
+
+    def __init__(self, slots: int = 4, leaf: int = 128, mem_budget: int = 0, tol: float = 1e-10,
+                 keep_factors: bool = False, restart: int = 30, maxit: int = 4000, **factor_kw):
+        lib = load()
+        o = ServerOpts()
+        _check(lib.mf_server_opts_default(ctypes.byref(o)))
+        o.slots, o.leaf, o.mem_budget, o.tol = int(slots), int(leaf), int(mem_budget), float(tol)
+        o.keep_factors = 1 if keep_factors else 0
+        o.factor = default_opts(**factor_kw)
+        o.gmres.restart, o.gmres.maxit = int(restart), int(maxit)
+        h = ctypes.c_void_p()
+        _check(lib.mf_server_create(ctypes.byref(o), ctypes.byref(h)))
+        self.h = h
+        self._n = {}
+
+    def submit(self, A, coords, b) -> int:
+        b = np.asfortranarray(np.asarray(b, dtype=np.float64).reshape(A.n, -1))
+        rp = np.ascontiguousarray(A.rowptr, dtype=np.int32)
+        ci = np.ascontiguousarray(A.colind, dtype=np.int32)
+        va = np.ascontiguousarray(A.vals, dtype=np.float64)
+        co = np.ascontiguousarray(coords, dtype=np.float64)
+        dim = 1 if co.ndim == 1 else co.shape[1]
+        t = _I64(0)
+        _check(load().mf_server_submit(self.h, int(A.n), _ptr(rp), _ptr(ci), _ptr(va), _ptr(co), dim,
+                                       int(b.shape[1]), _ptr(b), ctypes.byref(t)))
+        self._n[t.value] = (A.n, b.shape[1])
+        return t.value
+
+    def resolve(self, factor_ticket: int, b) -> int:
+        n = self._n[factor_ticket][0]
+        b = np.asfortranarray(np.asarray(b, dtype=np.float64).reshape(n, -1))
+        t = _I64(0)
+        _check(load().mf_server_resolve(self.h, int(factor_ticket), int(b.shape[1]), _ptr(b), ctypes.byref(t)))
+        self._n[t.value] = (n, b.shape[1])
+        return t.value
+
+    def wait(self, ticket: int, raise_on_error: bool = True):
+        n, k = self._n[ticket]
+        x = np.zeros((n, k), dtype=np.float64, order="F")
+        info = RequestInfo()
+        st = load().mf_server_wait(self.h, int(ticket), _ptr(x), ctypes.byref(info))
+        d = {f: getattr(info, f) for f, _ in RequestInfo._fields_}
+        if st != MF_OK and raise_on_error:
+            raise MfError(st, load().mf_last_error().decode())
+        return x, d
+
+    def release(self, factor_ticket: int):
+        _check(load().mf_server_release(self.h, int(factor_ticket)))
+
+    def memory(self) -> dict:
+        u, b = _I64(0), _I64(0)
+        _check(load().mf_server_memory(self.h, ctypes.byref(u), ctypes.byref(b)))
+        return {"in_use": u.value, "budget": b.value}
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().mf_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

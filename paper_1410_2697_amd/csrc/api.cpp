@@ -11,10 +11,14 @@
 #include "../../include/mfh.h"
 #include "numeric.h"
 #include "prof.h"
+#include "server.h"
 #include "symbolic.h"
 
 struct mf_symbolic_s {
   mfh::Symbolic s;
+};
+struct mf_server_s {
+  std::unique_ptr<mfh::Server> s;
 };
 struct mf_numeric_s {
   std::unique_ptr<mfh::NumericBase> n;
@@ -202,6 +206,7 @@ mf_status mf_factor_get_info(const mf_numeric_t* f, mf_factor_info* info) {
   if (!f || !info) return fail(MF_EINVAL, "null argument");
   *info = f->n->info;
   info->peak_bytes = f->n->ms.peak;
+  info->resident_bytes = f->n->ms.current;
   return MF_OK;
 }
 
@@ -217,6 +222,7 @@ mf_status mf_apply(mf_numeric_t* f, int32_t nrhs, const double* r, double* z, vo
   if (!f || !r || !z || nrhs < 1) return fail(MF_EINVAL, "bad argument");
   if (r == z) return fail(MF_EINVAL, "r and z may not alias");
   f->n->apply(nrhs, r, z, static_cast<hipStream_t>(stream));
+  f->n->note_stream(static_cast<hipStream_t>(stream));
   return MF_OK;
   MF_GUARD_END
 }
@@ -225,6 +231,7 @@ mf_status mf_spmv(mf_numeric_t* f, int32_t nrhs, const double* x, double* y, voi
   MF_GUARD_BEGIN
   if (!f || !x || !y || nrhs < 1 || x == y) return fail(MF_EINVAL, "bad argument");
   f->n->spmv(nrhs, x, y, 1.0, 0.0, static_cast<hipStream_t>(stream));
+  f->n->note_stream(static_cast<hipStream_t>(stream));
   return MF_OK;
   MF_GUARD_END
 }
@@ -239,10 +246,109 @@ mf_status gmres_solve(mf_numeric_t* f, int32_t nrhs, const double* b, double* x,
   if (o.restart < 1 || o.restart > 60 || o.maxit < 1) return fail(MF_EINVAL, "restart must be 1..60, maxit >= 1");
   mf_status s = MF_OK;
   f->n->gmres(nrhs, b, x, tol, o, info, &s);
+  f->n->note_stream(static_cast<hipStream_t>(o.stream));
   if (s == MF_ENOCONV) return fail(MF_ENOCONV, "GMRES did not reach tol within maxit");
   return s;
   MF_GUARD_END
 }
+
+mf_status mf_estimate_bytes(const mf_symbolic_t* sym, const mf_opts* opts, int32_t nrhs, int32_t restart,
+                            int64_t* persistent, int64_t* peak) {
+  MF_GUARD_BEGIN
+  if (!sym || nrhs < 1 || restart < 1) return fail(MF_EINVAL, "bad argument");
+  mf_opts o;
+  if (opts) o = *opts; else mf_opts_default(&o);
+  if (o.rank_cap < 1) return fail(MF_EINVAL, "rank_cap must be >= 1");
+  int64_t pe = 0, pk = 0;
+  mfh::estimate_bytes(sym->s, o, nrhs, restart, pe, pk);
+  if (persistent) *persistent = pe;
+  if (peak) *peak = pk;
+  return MF_OK;
+  MF_GUARD_END
+}
+
+mf_status mf_server_opts_default(mf_server_opts* o) {
+  if (!o) return fail(MF_EINVAL, "null opts");
+  std::memset(o, 0, sizeof(*o));
+  o->slots = 4;
+  o->leaf = 128;
+  o->mem_budget = 0;
+  o->tol = 1e-10;
+  mf_opts_default(&o->factor);
+  mf_gmres_opts_default(&o->gmres);
+  o->keep_factors = 0;
+  return MF_OK;
+}
+
+mf_status mf_server_create(const mf_server_opts* o, mf_server_t** out) {
+  MF_GUARD_BEGIN
+  if (!out) return fail(MF_EINVAL, "null out");
+  *out = nullptr;
+  mf_server_opts so;
+  if (o) so = *o; else mf_server_opts_default(&so);
+  mf_opts& fo = so.factor;
+  if (so.leaf < 1) return fail(MF_EINVAL, "leaf must be >= 1");
+  if (fo.method == MF_METHOD_HODLR) {
+    if (so.leaf > 128) return fail(MF_EINVAL, "HODLR leaves are limited to 128");
+    const int maxcap = fo.precision == MF_FP64 ? 128 : 192;
+    if (fo.bdlr_cap == 0) fo.bdlr_cap = maxcap;
+    if (fo.bdlr_cap < 1 || fo.bdlr_cap > maxcap || fo.rank_cap < 1 || fo.rank_cap > 512)
+      return fail(MF_EINVAL, "bdlr_cap or rank_cap out of range");
+  }
+  if (!(fo.eps >= 0.0) || fo.eps >= 1.0) return fail(MF_EINVAL, "eps must be in [0, 1)");
+  if (so.gmres.restart < 1 || so.gmres.restart > 60 || so.gmres.maxit < 1)
+    return fail(MF_EINVAL, "restart must be 1..60, maxit >= 1");
+  mf_status g = gpu_present();
+  if (g != MF_OK) return g;
+  auto h = std::make_unique<mf_server_s>();
+  h->s = std::make_unique<mfh::Server>(so);
+  *out = h.release();
+  return MF_OK;
+  MF_GUARD_END
+}
+
+mf_status mf_server_submit(mf_server_t* sv, int32_t n, const int32_t* rowptr, const int32_t* colind,
+                           const double* vals, const double* coords, int32_t dim, int32_t nrhs,
+                           const double* b, int64_t* ticket) {
+  MF_GUARD_BEGIN
+  if (!sv || !ticket) return fail(MF_EINVAL, "null argument");
+  *ticket = sv->s->submit(n, rowptr, colind, vals, coords, dim, nrhs, b);
+  return MF_OK;
+  MF_GUARD_END
+}
+
+mf_status mf_server_resolve(mf_server_t* sv, int64_t factor_ticket, int32_t nrhs, const double* b,
+                            int64_t* ticket) {
+  MF_GUARD_BEGIN
+  if (!sv || !ticket) return fail(MF_EINVAL, "null argument");
+  *ticket = sv->s->resolve(factor_ticket, nrhs, b);
+  return MF_OK;
+  MF_GUARD_END
+}
+
+mf_status mf_server_wait(mf_server_t* sv, int64_t ticket, double* x, mf_request_info* info) {
+  MF_GUARD_BEGIN
+  if (!sv) return fail(MF_EINVAL, "null server");
+  sv->s->wait(ticket, x, info);
+  return MF_OK;
+  MF_GUARD_END
+}
+
+mf_status mf_server_release(mf_server_t* sv, int64_t factor_ticket) {
+  MF_GUARD_BEGIN
+  if (!sv) return fail(MF_EINVAL, "null server");
+  sv->s->release(factor_ticket);
+  return MF_OK;
+  MF_GUARD_END
+}
+
+mf_status mf_server_memory(mf_server_t* sv, int64_t* in_use, int64_t* budget) {
+  if (!sv) return fail(MF_EINVAL, "null server");
+  sv->s->memory(in_use, budget);
+  return MF_OK;
+}
+
+void mf_server_destroy(mf_server_t* sv) { delete sv; }
 
 mf_status mf_prof_start(const char* names) {
   MF_GUARD_BEGIN

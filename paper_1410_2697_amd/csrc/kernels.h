@@ -232,9 +232,9 @@ void launch_phase2(const Phase2Desc<T>* d, int ndesc, int maxrc, double eps, int
 // does); phase2_coop_lds: dynamic LDS bytes of a workgroup, with the slice in
 // LDS or (slice_lds false) updated in place in the front; phase2_coop_capacity:
 // workgroups that can be resident at once with that LDS (a launch must not
-// exceed it).  The launch is cooperative, so all its workgroups are resident;
-// a barrier wait longer than spin_limit polls sets status bit 8 and ends the
-// loop.  Returns the launch error.
+// exceed it).  Launches are serialised process-wide and the launcher waits
+// for completion (synchronous); a barrier wait longer than spin_limit polls
+// sets status bit 8 and ends the loop.  Returns the launch or wait error.
 constexpr int kPhase2CoopLds = 64 * 1024;
 template <typename T>
 int phase2_coop_wcols(int nr);

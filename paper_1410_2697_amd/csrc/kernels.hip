@@ -4,6 +4,7 @@
 #include "prof.h"
 
 #include <climits>
+#include <mutex>
 
 namespace mfh {
 
@@ -1162,14 +1163,28 @@ int phase2_coop_capacity(size_t lds, bool slice_lds) {
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, 256, lds) != hipSuccess) return 0;
   return per * cus;
 }
+// One multi-workgroup phase-2 launch runs at a time in the process, and the
+// launcher waits for it: two spin-barrier launches on different streams could
+// otherwise each hold resources the other's missing workgroups need.  The
+// grid never exceeds the resident capacity, so on its own a launch always
+// gets all its workgroups resident once other streams' (finite) kernels
+// drain; the bounded barrier poll turns any stall into status bit 8.
+std::mutex& phase2_coop_mutex() {
+  static std::mutex m;
+  return m;
+}
 template <typename T>
 hipError_t launch_phase2_coop(const Phase2CoopDesc<T>* d, int ndesc, int wgs, size_t lds, bool slice_lds,
                               double eps, int* status, int spin_limit, hipStream_t st) {
   if (ndesc <= 0 || wgs <= 0) return hipSuccess;
-  void* args[] = {(void*)&d, (void*)&ndesc, (void*)&eps, (void*)&status, (void*)&spin_limit};
-  const void* k = slice_lds ? reinterpret_cast<const void*>(phase2_coop_kernel<T, true>)
-                            : reinterpret_cast<const void*>(phase2_coop_kernel<T, false>);
-  return hipLaunchCooperativeKernel(k, dim3(wgs), dim3(256), args, (unsigned)lds, st);
+  std::lock_guard<std::mutex> g(phase2_coop_mutex());
+  if (slice_lds)
+    MFH_LAUNCH((phase2_coop_kernel<T, true>), dim3(wgs), dim3(256), lds, st, d, ndesc, eps, status, spin_limit);
+  else
+    MFH_LAUNCH((phase2_coop_kernel<T, false>), dim3(wgs), dim3(256), lds, st, d, ndesc, eps, status, spin_limit);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(st);
 }
 template <typename T>
 void launch_extadd(const ExtAddDesc<T>* d, int ndesc, int tiles, hipStream_t st) {

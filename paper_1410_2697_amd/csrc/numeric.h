@@ -6,6 +6,7 @@
 #include <map>
 #include <memory>
 #include <string>
+#include <mutex>
 #include <vector>
 
 #include "../../include/mfh.h"
@@ -63,6 +64,13 @@ struct Blob {
   }
 };
 
+// throws Err{MF_EHIP} when a HIP call fails
+#define HIPCHK(x)                                                                              \
+  do {                                                                                         \
+    hipError_t e_ = (x);                                                                       \
+    if (e_ != hipSuccess) throw Err{MF_EHIP, std::string(#x) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
 class NumericBase {
  public:
   virtual ~NumericBase() = default;
@@ -80,8 +88,20 @@ class NumericBase {
   DevBuf d_rowptr, d_colind, d_vals, d_perm, d_iperm, d_status;
   // GMRES workspace
   DevBuf g_V, g_Z, g_w, g_r, g_small, g_partial;
+  // Streams this handle has launched work on, each with an event recorded
+  // after its latest work.  Before the handle's device blocks go back to the
+  // allocator cache it waits for these events (not for the whole device,
+  // which may be running other handles' work).
+  void note_stream(hipStream_t st);
+  void wait_streams();
+  std::mutex ev_mu;
+  std::vector<std::pair<hipStream_t, hipEvent_t>> stream_events;
 };
 
 std::unique_ptr<NumericBase> make_numeric(const Symbolic& s, const double* vals, const mf_opts& o);
+int64_t workspace_plan(const Symbolic& s, std::vector<int64_t>& reg_off, std::vector<int64_t>& reg_elems,
+                       std::vector<int64_t>& front_elem_off);
+void estimate_bytes(const Symbolic& s, const mf_opts& o, int nrhs, int restart, int64_t& persistent,
+                    int64_t& peak);
 
 }  // namespace mfh

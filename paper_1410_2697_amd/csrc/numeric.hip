@@ -32,11 +32,6 @@
 
 namespace mfh {
 
-#define HIPCHK(x)                                                                              \
-  do {                                                                                         \
-    hipError_t e_ = (x);                                                                       \
-    if (e_ != hipSuccess) throw Err{MF_EHIP, std::string(#x) + ": " + hipGetErrorString(e_)}; \
-  } while (0)
 
 // Device blocks are cached for reuse instead of freed: a factorisation
 // allocates and releases the same sizes every time, and hipMalloc/hipFree of
@@ -129,7 +124,9 @@ void DevBuf::ensure(size_t b, MemStats* m, hipStream_t st) {
 void* Arena::alloc(size_t bytes) {
   bytes = (bytes + 255) & ~size_t(255);
   if (chunks.empty() || off + bytes > chunks.back()->bytes) {
-    size_t cb = std::max(bytes, (size_t)64 << 20);
+    // chunks grow with use (1 MiB .. 64 MiB), so small factors hold little slack
+    const size_t grow = std::min<size_t>((size_t)64 << 20, std::max<size_t>((size_t)1 << 20, (size_t)used));
+    size_t cb = std::max(bytes, grow);
     chunks.push_back(std::make_unique<DevBuf>());
     chunks.back()->alloc(cb, ms);
     off = 0;
@@ -371,6 +368,47 @@ void timed_potrf(const PotrfDesc<T>* d, const std::vector<PotrfDesc<T>>& hv, int
   prof_end(id, st);
 }
 
+}  // namespace
+
+// Front workspace plan (elements): the fronts of one level share a region;
+// a region lives until the level of its last parent is done; regions are
+// placed first fit over offsets.  Returns the peak.
+int64_t workspace_plan(const Symbolic& s, std::vector<int64_t>& reg_off, std::vector<int64_t>& reg_elems,
+                       std::vector<int64_t>& front_elem_off) {
+  const int H = (int)s.levels.size();
+  reg_off.assign(H, 0);
+  reg_elems.assign(H, 0);
+  front_elem_off.assign(s.fronts.size(), 0);
+  struct Iv { int64_t off, len; int end; };
+  std::vector<Iv> live;
+  int64_t peak = 0;
+  for (int h = 0; h < H; ++h) {
+    int64_t tot = 0;
+    int end = h;
+    for (int p : s.levels[h]) {
+      front_elem_off[p] = tot;
+      const int64_t nn = s.fronts[p].n();
+      tot += (nn * nn + 63) & ~int64_t(63);
+      const int par = s.fronts[p].parent;
+      end = std::max(end, par >= 0 ? s.fronts[par].height : h);
+    }
+    live.erase(std::remove_if(live.begin(), live.end(), [&](const Iv& v) { return v.end < h; }), live.end());
+    std::sort(live.begin(), live.end(), [](const Iv& a, const Iv& b) { return a.off < b.off; });
+    int64_t pos = 0;
+    for (const Iv& v : live) {
+      if (v.off - pos >= tot) break;
+      pos = std::max(pos, v.off + v.len);
+    }
+    reg_off[h] = pos;
+    reg_elems[h] = tot;
+    live.push_back({pos, tot, end});
+    peak = std::max(peak, pos + tot);
+  }
+  return peak;
+}
+
+namespace {
+
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
@@ -449,12 +487,17 @@ class Numeric : public NumericBase {
   };
   std::map<int, std::unique_ptr<Plan>> plans;
   Plan* get_plan(int nrhs);
+  bool constructed = false;
   // Declared last, so destroyed first (also when the constructor throws):
   // device blocks go back to the allocator cache only after the work that
   // may still use them has finished.
   struct SyncGuard {
-    ~SyncGuard() { (void)hipDeviceSynchronize(); }
-  } sync_guard;
+    Numeric* self;
+    ~SyncGuard() {
+      if (!self->constructed) (void)hipStreamSynchronize(self->st);
+      self->wait_streams();
+    }
+  } sync_guard{this};
 };
 
 template <typename T>
@@ -544,35 +587,9 @@ Numeric<T>::Numeric(const Symbolic& s, const double* vals, const mf_opts& o) {
   }
   // ---- front workspace plan: one region per level, first fit over offsets
   std::vector<int64_t> reg_off(H), reg_elems(H);
-  std::vector<int> reg_end(H);
   std::vector<int64_t> front_elem_off(nfr);
   {
-    struct Iv { int64_t off, len; int end; };
-    std::vector<Iv> live;
-    int64_t peak = 0;
-    for (int h = 0; h < H; ++h) {
-      int64_t tot = 0;
-      int end = h;
-      for (int p : s.levels[h]) {
-        front_elem_off[p] = tot;
-        const int64_t nn = s.fronts[p].n();
-        tot += (nn * nn + 63) & ~int64_t(63);
-        int par = s.fronts[p].parent;
-        end = std::max(end, par >= 0 ? s.fronts[par].height : h);
-      }
-      live.erase(std::remove_if(live.begin(), live.end(), [&](const Iv& v) { return v.end < h; }), live.end());
-      std::sort(live.begin(), live.end(), [](const Iv& a, const Iv& b) { return a.off < b.off; });
-      int64_t pos = 0;
-      for (const Iv& v : live) {
-        if (v.off - pos >= tot) break;
-        pos = std::max(pos, v.off + v.len);
-      }
-      reg_off[h] = pos;
-      reg_elems[h] = tot;
-      reg_end[h] = end;
-      live.push_back({pos, tot, end});
-      peak = std::max(peak, pos + tot);
-    }
+    const int64_t peak = workspace_plan(s, reg_off, reg_elems, front_elem_off);
     ws.alloc(std::max<int64_t>(peak, 1) * sizeof(T), &ms);
     split.alloc(kSplitFactorBytes, &ms);
     info.workspace_bytes = peak * (int64_t)sizeof(T);
@@ -661,12 +678,18 @@ Numeric<T>::Numeric(const Symbolic& s, const double* vals, const mf_opts& o) {
   int status = 0;
   HIPCHK(hipMemcpy(&status, d_status.p, sizeof(int), hipMemcpyDeviceToHost));
   info.status_bits = status;
-  // release transient storage
+  // release transient storage (the apply has its own workspaces and descriptors)
   ws.release();
   scrA.release();
   scrB.release();
+  split.release();
   d_asm_dest.release();
   d_asm_src.release();
+  dp.ar.chunks.clear();
+  dp.ar.off = 0;
+  dp.keep.clear();
+  lvb.clear();
+  fbd.clear();
   info.persistent_bytes = arena.used;
   info.peak_bytes = ms.peak;
   int dn = 0, hn = 0;
@@ -681,6 +704,8 @@ Numeric<T>::Numeric(const Symbolic& s, const double* vals, const mf_opts& o) {
   info.rank_sum = rs;
   info.rank_max = rmax;
   info.factor_seconds = now_s() - t0;
+  note_stream(st);
+  constructed = true;
   if (status & 1) throw Err{MF_ENOTSPD, "non-positive pivot in a Cholesky factorisation"};
   if (status & 4) throw Err{MF_ENOTSPD, "singular SMW capacitance matrix"};
   if (status & 2) throw Err{MF_ECAPACITY, "a block rank exceeded rank_cap"};
@@ -979,7 +1004,7 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
       maxrc = std::max(maxrc, B.nr + B.nc);
     }
   }
-  // cooperative launches: consecutive groups of blocks of one slice mode
+  // multi-workgroup launches: consecutive groups of blocks of one slice mode
   // whose workgroups can all be resident (descriptors ordered by mode)
   std::stable_sort(p2c.begin(), p2c.end(), [](const Phase2CoopDesc<T>& a, const Phase2CoopDesc<T>& b) {
     return a.slice_lds > b.slice_lds;
@@ -1027,7 +1052,6 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
       const auto* dc = reinterpret_cast<const Phase2CoopDesc<T>*>(base + op2c);
       for (const CoopGroup& g : cgroups) {
         const int id = prof_begin(pk<T>(PK_PHASE2C_F64), st, 0.0, 0.0);
-        prof_stream_start(id, st);
         coop_ids.push_back(id);
         const hipError_t e = launch_phase2_coop<T>(dc + g.first, g.n, g.wgs, g.slds ? coop_lds : coop_lds_g, g.slds,
                                                    eps, dstat, kSpinLimit, st);
@@ -1086,7 +1110,7 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
     prof_add(id_s, sfl, sb);
     prof_add(resid.pid, rf, rb);
     prof_add(id_2, pf, pb);
-    // the cooperative launches share the level's work in proportion to their workgroups
+    // the multi-workgroup launches share the level's work in proportion to their workgroups
     if (!coop_ids.empty()) {
       double tw = 0;
       for (const CoopGroup& g : cgroups) tw += g.wgs;
@@ -1579,6 +1603,32 @@ void Numeric<T>::apply(int nrhs, const double* r, double* z, hipStream_t stream)
   HIPCHK(hipGetLastError());
 }
 
+void NumericBase::note_stream(hipStream_t st) {
+  std::lock_guard<std::mutex> g(ev_mu);
+  for (auto& e : stream_events)
+    if (e.first == st) {
+      (void)hipEventRecord(e.second, st);
+      return;
+    }
+  hipEvent_t ev = nullptr;
+  if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipStreamSynchronize(st);
+    return;
+  }
+  (void)hipEventRecord(ev, st);
+  stream_events.push_back({st, ev});
+}
+
+void NumericBase::wait_streams() {
+  std::lock_guard<std::mutex> g(ev_mu);
+  for (auto& e : stream_events) {
+    (void)hipEventSynchronize(e.second);
+    (void)hipEventDestroy(e.second);
+  }
+  stream_events.clear();
+}
+
 // ================================================================ GMRES ====
 void NumericBase::spmv(int nrhs, const double* x, double* y, double alpha, double beta, hipStream_t st) {
   // CSR read once, x gathered once per right-hand side, y written (and read)
@@ -1723,6 +1773,56 @@ void NumericBase::gmres(int nrhs, const double* b, double* x, double tol, const 
     if (info_out) info_out[k] = {iters[k], c ? 1 : 0, bnorm[k] > 0 ? beta[k] / bnorm[k] : 0.0};
   }
   *st_out = ok ? MF_OK : MF_ENOCONV;
+}
+
+// Device bytes of a factorisation before it runs.  Exact for the front
+// workspace, the dense fronts and the fixed buffers; the HODLR part assumes
+// every block rank r <= min(rows, cols, rank_cap, 8 sqrt(max(rows, cols)))
+// (ranks grow like sqrt(n), Sec. 1).  persistent = what a resident handle
+// holds with apply and GMRES(restart) workspaces for nrhs right-hand sides;
+// peak = the most held during mf_factor.
+void estimate_bytes(const Symbolic& s, const mf_opts& o, int nrhs, int restart, int64_t& persistent,
+                    int64_t& peak) {
+  const double es = o.precision == MF_FP64 ? 8.0 : 4.0;
+  const bool hodlr = o.method == MF_METHOD_HODLR;
+  std::vector<int64_t> ro, re, fo;
+  const double ws = (double)workspace_plan(s, ro, re, fo) * es;
+  const double csr = 12.0 * s.nnz + 4.0 * (s.n + 1) + 8.0 * s.n;
+  double fac = 0, scratch = 0, apply = 0;
+  std::vector<double> lvl_scratch(s.levels.size(), 0.0);
+  for (const Front& f : s.fronts) {
+    const double np = f.npiv, nf = f.nf();
+    apply += (f.n() + np) * nrhs * es;
+    if (!hodlr || f.n() < o.n_c) {
+      fac += (np * np + nf * np) * es;
+      continue;
+    }
+    auto rk = [&](const Block& B) {
+      const double r = std::min({(double)B.nr, (double)B.nc, (double)o.rank_cap,
+                                 std::ceil(8.0 * std::sqrt((double)std::max(B.nr, B.nc)))});
+      return r;
+    };
+    double w = 0, rtop = 0;
+    for (const Block& B : f.blocks) {
+      const double r = rk(B);
+      if (B.kind == 0) rtop = r;
+      if (B.kind == 1) {
+        fac += (B.nr + B.nc) * r * es + 4.0 * r * r * es;   // U, V and the capacitance inverse
+        w += r;
+        apply += 4.0 * r * nrhs * es;
+      }
+      lvl_scratch[f.height] += (B.nr + B.nc) * std::min((double)o.rank_cap, (double)std::min(B.nr, B.nc)) * es;
+    }
+    for (const TreeNode& t : f.pp_tree)
+      if (t.left < 0) fac += (double)t.size * t.size * es;    // leaf inverses
+    fac += np * (rtop + w) * es + nf * rtop * es;             // G (X and the SMW columns), W
+    apply += rtop * nrhs * es;
+  }
+  for (double v : lvl_scratch) scratch = std::max(scratch, v);
+  const double gm = 8.0 * s.n * nrhs * (2.0 * restart + 3.0);
+  const double fixed = (double)kSplitFactorBytes + (64 << 20);   // split-K partials, one descriptor chunk
+  persistent = (int64_t)(fac + csr + apply + gm + kSplitPlanBytes);
+  peak = (int64_t)(ws + fac + csr + scratch + fixed + 16.0 * s.nnz);
 }
 
 std::unique_ptr<NumericBase> make_numeric(const Symbolic& s, const double* vals, const mf_opts& o) {

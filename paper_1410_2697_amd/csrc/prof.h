@@ -38,9 +38,9 @@ const char* prof_name(int kind);
 // id >= 0 when the launch is timed; -1 otherwise (all calls then do nothing).
 // A timed record hands its two events to the next kernel launched by this
 // thread through MFH_LAUNCH, which has the runtime stamp the kernel's own
-// start and end (no launch gap inside the interval).  prof_end records the
-// events on the stream instead when no such launch took them (cooperative
-// launches), and drops the record when nothing was launched.
+// start and end (no launch gap inside the interval).  For a launch API that
+// cannot take events, prof_stream_start records the start on the stream and
+// prof_end the end; a record that no launch used is dropped.
 int prof_begin(int kind, hipStream_t st, double flops, double bytes);
 void prof_end(int id, hipStream_t st);
 bool prof_take(hipEvent_t* start, hipEvent_t* stop);

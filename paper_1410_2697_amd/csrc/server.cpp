@@ -1,0 +1,295 @@
+// Request server (include/mfh.h, "Serving"): requests are analysed on the
+// submitting thread, queued with their estimated peak device bytes, and
+// admitted in arrival order by worker threads, one HIP stream each, as soon
+// as the head request fits the memory budget beside the running requests and
+// the resident factors.  Admitted requests factor and solve concurrently on
+// their streams.
+#include "server.h"
+
+#include <algorithm>
+#include <chrono>
+
+namespace mfh {
+namespace {
+double now() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+}  // namespace
+
+Server::Server(const mf_server_opts& o) : o_(o) {
+  if (o_.slots < 1 || o_.slots > 16) throw Err{MF_EINVAL, "slots must be 1..16"};
+  if (!(o_.tol > 0.0)) throw Err{MF_EINVAL, "tol must be > 0"};
+  if (hipGetDevice(&dev_) != hipSuccess) {
+    (void)hipGetLastError();
+    throw Err{MF_ESTATE, "no HIP device is visible"};
+  }
+  budget_ = o_.mem_budget;
+  if (budget_ <= 0) {
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+      (void)hipGetLastError();
+      throw Err{MF_EHIP, "hipMemGetInfo failed"};
+    }
+    budget_ = (int64_t)(0.8 * (double)fr);
+  }
+  for (int i = 0; i < o_.slots; ++i) workers_.emplace_back([this]() { worker(); });
+}
+
+Server::~Server() {
+  {
+    std::lock_guard<std::mutex> g(mu_);
+    stop_ = true;
+    for (int64_t id : queue_) {
+      Req& r = *reqs_[id];
+      r.state = 2;
+      r.status = MF_ESTATE;
+      r.err = "server stopped before the request ran";
+    }
+    queue_.clear();
+  }
+  cv_work_.notify_all();
+  cv_done_.notify_all();
+  for (auto& t : workers_) t.join();
+  factors_.clear();   // each factor waits for its own streams' work before freeing
+}
+
+int64_t Server::solve_bytes(int n, int nrhs) const {
+  const int m = std::max(1, o_.gmres.restart);
+  return (int64_t)(8.0 * n * nrhs * (2.0 * m + 6.0)) + (16 << 20);
+}
+
+int64_t Server::submit(int n, const int32_t* rowptr, const int32_t* colind, const double* vals,
+                       const double* coords, int dim, int nrhs, const double* b) {
+  if (n < 1 || !rowptr || !colind || !vals || !coords || !b || nrhs < 1) throw Err{MF_EINVAL, "bad request"};
+  auto r = std::make_unique<Req>();
+  r->t_submit = now();
+  r->sym = std::make_unique<Symbolic>();
+  const std::string e = analyze(n, rowptr, colind, coords, dim, o_.leaf, *r->sym);
+  if (!e.empty()) throw Err{MF_EINVAL, e};
+  r->info.t_analyze = now() - r->t_submit;
+  r->n = n;
+  r->nrhs = nrhs;
+  r->vals.assign(vals, vals + r->sym->nnz);
+  r->b.assign(b, b + (size_t)n * nrhs);
+  int64_t pers = 0, peak = 0;
+  estimate_bytes(*r->sym, o_.factor, nrhs, o_.gmres.restart, pers, peak);
+  r->est = std::max(peak, pers);
+  r->info.est_bytes = r->est;
+  std::lock_guard<std::mutex> g(mu_);
+  if (stop_) throw Err{MF_ESTATE, "server stopped"};
+  r->id = next_id_++;
+  const int64_t id = r->id;
+  queue_.push_back(id);
+  reqs_[id] = std::move(r);
+  cv_work_.notify_all();
+  return id;
+}
+
+int64_t Server::resolve(int64_t factor_ticket, int nrhs, const double* b) {
+  if (!b || nrhs < 1) throw Err{MF_EINVAL, "bad request"};
+  std::lock_guard<std::mutex> g(mu_);
+  if (stop_) throw Err{MF_ESTATE, "server stopped"};
+  auto it = factors_.find(factor_ticket);
+  if (it == factors_.end() || it->second->released) throw Err{MF_ESTATE, "no resident factor for this ticket"};
+  Factor& f = *it->second;
+  auto r = std::make_unique<Req>();
+  r->t_submit = now();
+  r->resolve = true;
+  r->factor_id = factor_ticket;
+  r->n = f.n;
+  r->nrhs = nrhs;
+  r->b.assign(b, b + (size_t)f.n * nrhs);
+  r->est = solve_bytes(f.n, nrhs);
+  r->info.est_bytes = r->est;
+  ++f.users;                      // pinned until the solve is done
+  r->id = next_id_++;
+  const int64_t id = r->id;
+  queue_.push_back(id);
+  reqs_[id] = std::move(r);
+  cv_work_.notify_all();
+  return id;
+}
+
+bool Server::admit_locked(Req& r, std::vector<std::unique_ptr<Factor>>& evicted) {
+  for (;;) {
+    if (in_use_ + r.est <= budget_) return true;
+    // drop the least recently used resident factor nobody is using
+    auto lru = factors_.end();
+    for (auto it = factors_.begin(); it != factors_.end(); ++it)
+      if (it->second->users == 0 && (lru == factors_.end() || it->second->last_use < lru->second->last_use))
+        lru = it;
+    if (lru == factors_.end()) break;
+    in_use_ -= lru->second->bytes;
+    evicted.push_back(std::move(lru->second));
+    factors_.erase(lru);
+  }
+  return running_ == 0;           // larger than the whole budget: run alone
+}
+
+void Server::worker() {
+  (void)hipSetDevice(dev_);
+  hipStream_t st = nullptr;
+  if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipGetLastError();
+    st = nullptr;
+  }
+  DevBuf db, dx;
+  for (;;) {
+    std::vector<std::unique_ptr<Factor>> evicted;
+    Req* r = nullptr;
+    {
+      std::unique_lock<std::mutex> lk(mu_);
+      for (;;) {
+        if (stop_) break;
+        if (!queue_.empty() && admit_locked(*reqs_[queue_.front()], evicted)) break;
+        cv_work_.wait(lk);
+      }
+      if (stop_) break;
+      r = reqs_[queue_.front()].get();
+      queue_.pop_front();
+      r->state = 1;
+      r->info.t_queue = now() - r->t_submit;
+      in_use_ += r->est;
+      ++running_;
+    }
+    evicted.clear();              // waits for their streams, outside the lock
+    run(*r, st, db, dx);
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      in_use_ -= r->est;
+      --running_;
+      r->state = 2;
+      r->info.t_total = now() - r->t_submit;
+    }
+    cv_done_.notify_all();
+    cv_work_.notify_all();
+  }
+  if (st) {
+    (void)hipStreamSynchronize(st);
+    db.release();
+    dx.release();
+    (void)hipStreamDestroy(st);
+  }
+}
+
+void Server::run(Req& r, hipStream_t st, DevBuf& db, DevBuf& dx) {
+  std::unique_ptr<Factor> own;
+  Factor* f = nullptr;
+  try {
+    if (!r.resolve) {
+      mf_opts fo = o_.factor;
+      fo.stream = st;
+      const double t0 = now();
+      own = std::make_unique<Factor>();
+      own->n = r.n;
+      own->sym = std::move(r.sym);
+      own->num = make_numeric(*own->sym, r.vals.data(), fo);
+      r.info.t_factor = now() - t0;
+      r.info.peak_bytes = own->num->ms.peak;
+      r.vals.clear();
+      r.vals.shrink_to_fit();
+      f = own.get();
+    } else {
+      std::lock_guard<std::mutex> g(mu_);
+      f = factors_.at(r.factor_id).get();
+    }
+    const double t1 = now();
+    const size_t bytes = (size_t)r.n * r.nrhs * sizeof(double);
+    db.ensure(bytes, nullptr, st);
+    dx.ensure(bytes, nullptr, st);
+    HIPCHK(hipMemcpyAsync(db.p, r.b.data(), bytes, hipMemcpyHostToDevice, st));
+    mf_gmres_opts go = o_.gmres;
+    go.stream = st;
+    std::vector<mf_gmres_info> gi(r.nrhs);
+    mf_status s = MF_OK;
+    f->num->gmres(r.nrhs, db.as<double>(), dx.as<double>(), o_.tol, go, gi.data(), &s);
+    r.x.resize((size_t)r.n * r.nrhs);
+    HIPCHK(hipMemcpyAsync(r.x.data(), dx.p, bytes, hipMemcpyDeviceToHost, st));
+    f->num->note_stream(st);
+    HIPCHK(hipStreamSynchronize(st));
+    r.info.t_solve = now() - t1;
+    for (const auto& i : gi) {
+      r.info.iters_max = std::max(r.info.iters_max, i.iters);
+      r.info.relres_max = std::max(r.info.relres_max, i.relres);
+    }
+    r.status = s;
+    if (s == MF_ENOCONV) r.err = "GMRES did not reach tol within maxit";
+    r.info.resident_bytes = f->num->ms.current;
+  } catch (const Err& e) {
+    r.status = e.code;
+    r.err = e.msg;
+  } catch (const std::bad_alloc&) {
+    r.status = MF_ENOMEM;
+    r.err = "host allocation failed";
+  } catch (const std::exception& e) {
+    r.status = MF_EINVAL;
+    r.err = e.what();
+  }
+  r.info.status = r.status;
+  std::unique_ptr<Factor> drop;
+  {
+    std::lock_guard<std::mutex> g(mu_);
+    if (r.resolve) {
+      auto it = factors_.find(r.factor_id);
+      if (it != factors_.end()) {
+        Factor& rf = *it->second;
+        --rf.users;
+        rf.last_use = ++clock_;
+        in_use_ += f ? (f->num->ms.current - rf.bytes) : 0;   // a new nrhs may add workspaces
+        rf.bytes = f ? f->num->ms.current : rf.bytes;
+        if (rf.released && rf.users == 0) {
+          in_use_ -= rf.bytes;
+          drop = std::move(it->second);
+          factors_.erase(it);
+        }
+      }
+    } else if (own && o_.keep_factors && (r.status == MF_OK || r.status == MF_ENOCONV)) {
+      own->bytes = own->num->ms.current;
+      own->last_use = ++clock_;
+      in_use_ += own->bytes;
+      factors_[r.id] = std::move(own);
+    }
+  }
+  drop.reset();
+  own.reset();
+}
+
+void Server::wait(int64_t ticket, double* x, mf_request_info* info) {
+  std::unique_ptr<Req> r;
+  {
+    std::unique_lock<std::mutex> lk(mu_);
+    auto it = reqs_.find(ticket);
+    if (it == reqs_.end()) throw Err{MF_EINVAL, "unknown ticket (or already waited for)"};
+    Req* p = it->second.get();
+    cv_done_.wait(lk, [&] { return p->state == 2; });
+    r = std::move(it->second);
+    reqs_.erase(it);
+  }
+  if (info) *info = r->info;
+  if (x && !r->x.empty()) std::copy(r->x.begin(), r->x.end(), x);
+  if (r->status != MF_OK) throw Err{r->status, r->err};
+}
+
+void Server::release(int64_t factor_ticket) {
+  std::unique_ptr<Factor> drop;
+  {
+    std::lock_guard<std::mutex> g(mu_);
+    auto it = factors_.find(factor_ticket);
+    if (it == factors_.end()) throw Err{MF_EINVAL, "no resident factor for this ticket"};
+    it->second->released = true;
+    if (it->second->users == 0) {
+      in_use_ -= it->second->bytes;
+      drop = std::move(it->second);
+      factors_.erase(it);
+    }
+  }
+  cv_work_.notify_all();
+}
+
+void Server::memory(int64_t* in_use, int64_t* budget) {
+  std::lock_guard<std::mutex> g(mu_);
+  if (in_use) *in_use = in_use_;
+  if (budget) *budget = budget_;
+}
+
+}  // namespace mfh

@@ -157,3 +157,25 @@ def test_prof_start_stop_without_launches():
     assert mfh.prof_stop() == []
     mfh.prof_start()
     assert mfh.prof_stop() == []
+
+
+def test_estimate_bytes_dense_part_is_exact():
+    """The estimator's dense-front factor bytes equal the sum over fronts of
+    npiv^2 + nf*npiv entries (explicit inverse of L_pp plus L_fp), and the
+    peak covers at least the front workspace of the largest level."""
+    import paper_1410_2697_amd as mfh
+    from mfinputs import q1_grid
+    p = q1_grid(12, 3)
+    sym = mfh.Symbolic.from_csr(p.A, p.coords, 32)
+    e1 = mfh.estimate_bytes(sym, nrhs=1, restart=30, method="dense", precision="fp64")
+    e2 = mfh.estimate_bytes(sym, nrhs=2, restart=30, method="dense", precision="fp64")
+    ref = symbolic.analyze(p.A, p.coords, 32)
+    dense = sum(f.npiv * f.npiv + f.nf * f.npiv for f in ref.fronts) * 8
+    biggest_level = max(sum(ref.fronts[q].n * ref.fronts[q].n for q in lv) for lv in ref.levels) * 8
+    assert e1["persistent_bytes"] > dense and e1["peak_bytes"] > dense + biggest_level
+    # one more right-hand side adds apply and GMRES(30) workspaces only
+    delta = e2["persistent_bytes"] - e1["persistent_bytes"]
+    n = p.A.n
+    assert delta >= 8 * n * 63 and delta < 8 * n * 63 + 8 * sum(f.n + f.npiv for f in ref.fronts) + 1
+    eh = mfh.estimate_bytes(sym, nrhs=1, restart=30, method="hodlr", precision="fp32", n_c=64)
+    assert 0 < eh["persistent_bytes"] and 0 < eh["peak_bytes"]
