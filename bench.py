@@ -84,7 +84,8 @@ def run_config(mfh, torch, w, method, precision, n_c, steps, warmup, latency_cal
         t0 = time.perf_counter()
         sym = mfh.Symbolic.from_csr(p.A, p.coords, w.leaf)
         t1 = time.perf_counter()
-        f = mfh.Factor(sym, p.A.vals, eps, method=method, precision=precision, n_c=n_c, stream=stream)
+        extra = {"uv_bf16": 1} if (method == "hodlr" and w.params.get("uv_bf16")) else {}
+        f = mfh.Factor(sym, p.A.vals, eps, method=method, precision=precision, n_c=n_c, stream=stream, **extra)
         t2 = time.perf_counter()
         infos = f.gmres(b, x, tol=w.tol, stream=stream)
         torch.cuda.synchronize()
@@ -249,6 +250,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "n": w.problem.A.n, "nnz": w.problem.A.nnz, "nrhs": int(w.b.shape[1]),
                    "leaf": w.leaf, "eps": w.eps, "tol": w.tol, "n_c": args.n_c, "gmres_restart": 30,
+                   "uv_bf16": bool(w.params.get("uv_bf16", False)),
                    "step": "analyze + factor + GMRES of every right-hand side",
                    "arithmetic": "f32 compression, factors and apply; f64 GMRES, SpMV and capacitance inverses"},
         "hodlr_mf": summary(hod),

@@ -67,7 +67,10 @@ typedef struct {
   int32_t adaptive;     /* 1: continue complete pivoting over the whole block until the
                            pivot-ratio rule holds there (max-norm error < eps*|u_11|)     */
   int32_t rank_cap;     /* capacity per block rank; exceeding it -> MF_ECAPACITY            */
-  int32_t reserved;
+  int32_t uv_bf16;      /* HODLR + FP32 only: round the compressed bases U, V (and the F_fp
+                           basis W) to bfloat16 right after compression and keep them in
+                           bfloat16; the factorisation and the apply both use the rounded
+                           values, so the preconditioner is that of the rounded matrix     */
   double eps;           /* low-rank tolerance (Sec. 2.2: stop when |u_r+1,r+1/u_11| < eps) */
   void* stream;         /* hipStream_t, borrowed; NULL = null stream                      */
 } mf_opts;

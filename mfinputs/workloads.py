@@ -45,7 +45,8 @@ def _diffusion3d_grf(n=64, seed=0, nrhs=1):
     p = q1_grid(n, 3, k_elem=np.exp(g), name=f"diffusion3d_grf_{n}")
     b = rhs(p.A.n, nrhs, "normal", seed + 1)
     return Workload(p.name, p, b, leaf=128, eps=1e-3, precision="fp32", tol=1e-10,
-                    params={"grid": n, "dim": 3, "nrhs": nrhs, "corr_len": 0.1, "variance": 1.0})
+                    params={"grid": n, "dim": 3, "nrhs": nrhs, "corr_len": 0.1, "variance": 1.0,
+                            "uv_bf16": True})
 
 
 def _p1kuhn(cells=48, seed=0, nrhs=8):

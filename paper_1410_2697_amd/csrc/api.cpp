@@ -182,6 +182,7 @@ mf_status mf_factor(const mf_symbolic_t* sh, const double* vals, double eps, int
   if (opts) o = *opts; else mf_opts_default(&o);
   o.eps = eps;
   if (o.method != MF_METHOD_HODLR && o.method != MF_METHOD_DENSE) return fail(MF_EINVAL, "unknown method");
+  if (o.uv_bf16 && o.method != MF_METHOD_HODLR) return fail(MF_EINVAL, "uv_bf16 needs MF_METHOD_HODLR");
   if (o.precision != MF_FP64 && o.precision != MF_FP32) return fail(MF_EINVAL, "unknown precision");
   if (!(eps >= 0.0) || eps >= 1.0) return fail(MF_EINVAL, "eps must be in [0, 1)");
   if (leaf != 0 && leaf != sh->s.leaf) return fail(MF_EINVAL, "leaf must be 0 or the analysis leaf size");
@@ -191,6 +192,7 @@ mf_status mf_factor(const mf_symbolic_t* sh, const double* vals, double eps, int
     if (o.rank_cap > 512) return fail(MF_EINVAL, "rank_cap is limited to 512");
     const int maxcap = o.precision == MF_FP64 ? 128 : 192;   // B_hat held by one workgroup
     if (o.bdlr_cap == 0) o.bdlr_cap = maxcap;
+    if (o.uv_bf16 && o.precision != MF_FP32) return fail(MF_EINVAL, "uv_bf16 needs MF_FP32");
     if (o.bdlr_cap > maxcap) return fail(MF_EINVAL, "bdlr_cap too large for the LDS pivot kernel");
   }
   mf_status g = gpu_present();

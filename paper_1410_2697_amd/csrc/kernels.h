@@ -21,6 +21,8 @@ enum GemmFlags : int {
   GF_A_UPPER = 4,   // op(A)(i, kk) == 0 for kk < i
   GF_B_LOWER = 8,   // op(B)(kk, j) == 0 for kk < j
   GF_B_UPPER = 16,  // op(B)(kk, j) == 0 for kk > j
+  GF_A_BF16 = 32,   // A holds bfloat16 bit patterns (T = float only)
+  GF_B_BF16 = 64,   // B holds bfloat16 bit patterns (T = float only)
 };
 
 // C = alpha * op(A) * op(B) + beta * C ; op(A) m x k, op(B) k x n.
@@ -153,7 +155,9 @@ struct CopyDesc {   // dst(i, j) = alpha * src(i, j) (+ dst if accumulate)
   D* dst;
   int rows, cols, lds, ldd;
   int accumulate;
-  int tile0, tiles_r, pad;
+  int tile0, tiles_r;
+  int bf16;          // D = float only: 1 round the value to bfloat16 precision,
+                     // 2 store bfloat16 bit patterns (dst holds 16-bit entries)
   double alpha;
 };
 

@@ -96,6 +96,22 @@ struct Mfma<float> {
   __device__ static __forceinline__ int row(int lk, int v) { return 4 * lk + v; }
 };
 
+// bfloat16: the high 16 bits of a float32; conversion rounds to nearest,
+// ties to even (NaN stays NaN)
+__device__ __forceinline__ float bf16_to_float(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+__device__ __forceinline__ unsigned short float_to_bf16(float v) {
+  const unsigned b = __float_as_uint(v);
+  if ((b & 0x7F800000u) == 0x7F800000u && (b & 0x007FFFFFu)) return (unsigned short)((b >> 16) | 0x0040u);
+  return (unsigned short)((b + 0x7FFFu + ((b >> 16) & 1u)) >> 16);
+}
+template <typename T>
+__device__ __forceinline__ T load_op(const T* p, size_t idx, bool bf16) {
+  if constexpr (sizeof(T) == 4) {
+    if (bf16) return bf16_to_float(reinterpret_cast<const unsigned short*>(p)[idx]);
+  }
+  return p[idx];
+}
+
 // ---------------------------------------------------------------- GEMM ----
 // 64x64 output tile per workgroup, 4 waves each owning a 32x32 quadrant as
 // 2x2 MFMA 16x16x4 tiles.  K advances in steps of kGemmBK<T> staged through
@@ -131,6 +147,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc<T>* __restrict
   const T* __restrict__ A = d.A;
   const T* __restrict__ B = d.B;
   const int lda = d.lda, ldb = d.ldb, opA = d.opA, opB = d.opB;
+  const bool abf = (flags & GF_A_BF16) != 0, bbf = (flags & GF_B_BF16) != 0;
   v4 acc00 = {0, 0, 0, 0}, acc01 = {0, 0, 0, 0}, acc10 = {0, 0, 0, 0}, acc11 = {0, 0, 0, 0};
   const int wave = tid >> 6, lane = tid & 63;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
@@ -145,7 +162,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc<T>* __restrict
       if (opA == 0) { i = tid & 63; kk = (tid >> 6) + 4 * q; }
       else { kk = tid % BK; i = tid / BK + (256 / BK) * q; }
       const int gi = m0 + i, gk = kb + kk;
-      ra[q] = (gi < m && gk < kend) ? (opA == 0 ? A[gi + (size_t)gk * lda] : A[gk + (size_t)gi * lda]) : (T)0;
+      ra[q] = (gi < m && gk < kend)
+                  ? load_op(A, opA == 0 ? gi + (size_t)gk * lda : gk + (size_t)gi * lda, abf)
+                  : (T)0;
     }
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
@@ -153,7 +172,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc<T>* __restrict
       if (opB == 0) { kk = tid % BK; j = tid / BK + (256 / BK) * q; }
       else { j = tid & 63; kk = (tid >> 6) + 4 * q; }
       const int gj = n0 + j, gk = kb + kk;
-      rb[q] = (gj < n && gk < kend) ? (opB == 0 ? B[gk + (size_t)gj * ldb] : B[gj + (size_t)gk * ldb]) : (T)0;
+      rb[q] = (gj < n && gk < kend)
+                  ? load_op(B, opB == 0 ? gk + (size_t)gj * ldb : gj + (size_t)gk * ldb, bbf)
+                  : (T)0;
     }
   };
   auto stash = [&]() {
@@ -839,9 +860,16 @@ __global__ __launch_bounds__(256) void copy_kernel(const CopyDesc<S, D>* __restr
     const int i = tr * kTile + (e & 63), j = tc * kTile + (e >> 6);
     if (i < d.rows && j < d.cols) {
       D v = (D)(d.alpha * (double)d.src[i + (size_t)j * d.lds]);
-      D* o = d.dst + i + (size_t)j * d.ldd;
-      if (d.accumulate) v += *o;
-      *o = v;
+      const size_t o = i + (size_t)j * d.ldd;
+      if constexpr (sizeof(D) == 4) {
+        if (d.bf16 == 2) {
+          reinterpret_cast<unsigned short*>(d.dst)[o] = float_to_bf16(v);
+          continue;
+        }
+        if (d.bf16 == 1) v = bf16_to_float(float_to_bf16(v));
+      }
+      if (d.accumulate) v += d.dst[o];
+      d.dst[o] = v;
     }
   }
 }

@@ -443,6 +443,10 @@ class Numeric : public NumericBase {
   std::vector<FN> fn;
   Arena arena;
   DescPool dp;
+  // n entries of a compressed basis: T, or bfloat16 (2 bytes each) when rounded
+  T* base_alloc(int64_t n, bool bf16) {
+    return bf16 ? reinterpret_cast<T*>(arena.alloc_n<unsigned short>(n)) : arena.alloc_n<T>(n);
+  }
   DevBuf ws, scrA, scrB, d_asm_dest, d_asm_src, d_relmap;
   DevBuf split;                   // split-K partial sums of the factor's GEMM batches
   std::vector<int64_t> relmap_off;
@@ -1119,6 +1123,23 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
     }
   }
 
+  const bool uvbf = sizeof(T) == 4 && opts.uv_bf16 != 0;
+  if (uvbf) {   // bases rounded to bfloat16 once; everything below uses the rounded values
+    CopyBatch<T, T> rnd;
+    for (int i = 0; i < nb; ++i) {
+      const Block& B = s.fronts[br[i].p].blocks[br[i].bi];
+      if (hr[i] == 0) continue;
+      auto c1 = cd<T, T>(br[i].U, B.nr, br[i].U, B.nr, B.nr, hr[i]);
+      auto c2 = cd<T, T>(br[i].V, B.nc, br[i].V, B.nc, B.nc, hr[i]);
+      c1.bf16 = c2.bf16 = 1;
+      rnd.v.push_back(c1);
+      rnd.v.push_back(c2);
+    }
+    Blob rb;
+    rnd.stage(rb);
+    const char* rbase = dp.upload(rb, st);
+    rnd.launch(rbase, st);
+  }
   // ---- phase B
   std::map<std::pair<int, int>, int> bidx;   // (front, block) -> br index
   for (int i = 0; i < nb; ++i) bidx[{br[i].p, br[i].bi}] = i;
@@ -1164,8 +1185,10 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
     gall += (int64_t)f.npiv * x.w;
     if (x.r_top > 0) {
       const BR& t = br[bidx[{p, 0}]];
-      x.W = arena.alloc_n<T>((int64_t)f.nf() * x.r_top);
-      cp.v.push_back(cd<T, T>(t.U, f.nf(), x.W, f.nf(), f.nf(), x.r_top));
+      x.W = base_alloc((int64_t)f.nf() * x.r_top, uvbf);
+      auto cw = cd<T, T>(t.U, f.nf(), x.W, f.nf(), f.nf(), x.r_top);
+      cw.bf16 = uvbf ? 2 : 0;
+      cp.v.push_back(cw);
       cp.v.push_back(cd<T, T>(t.V, f.npiv, x.G, f.npiv, f.npiv, x.r_top));   // V_top -> X columns
     }
     for (int i = 0; i < (int)f.pp_tree.size(); ++i) {
@@ -1182,11 +1205,14 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
       const BR& bb = br[bidx[{p, t.block}]];
       const TreeNode& a = f.pp_tree[t.left];
       const TreeNode& be = f.pp_tree[t.right];
-      x.nodeU[i] = arena.alloc_n<T>((int64_t)be.size * r);
-      x.nodeV[i] = arena.alloc_n<T>((int64_t)a.size * r);
+      x.nodeU[i] = base_alloc((int64_t)be.size * r, uvbf);
+      x.nodeV[i] = base_alloc((int64_t)a.size * r, uvbf);
       x.nodeK[i] = arena.alloc_n<T>((int64_t)4 * r * r);
-      cp.v.push_back(cd<T, T>(bb.U, be.size, x.nodeU[i], be.size, be.size, r));
-      cp.v.push_back(cd<T, T>(bb.V, a.size, x.nodeV[i], a.size, a.size, r));
+      auto cu = cd<T, T>(bb.U, be.size, x.nodeU[i], be.size, be.size, r);
+      auto cv = cd<T, T>(bb.V, a.size, x.nodeV[i], a.size, a.size, r);
+      cu.bf16 = cv.bf16 = uvbf ? 2 : 0;
+      cp.v.push_back(cu);
+      cp.v.push_back(cv);
       const int c = x.col[t.level];
       cp.v.push_back(cd<T, T>(bb.V, a.size, x.G + a.off + (int64_t)c * f.npiv, f.npiv, a.size, r));
       cp.v.push_back(cd<T, T>(bb.U, be.size, x.G + be.off + (int64_t)c * f.npiv, f.npiv, be.size, r));
@@ -1264,8 +1290,9 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
       double* Q64 = reinterpret_cast<double*>(tk((size_t)n2 * std::max(c, 1) * sizeof(double)));
       T* Q = reinterpret_cast<T*>(tk((size_t)n2 * std::max(c, 1) * sizeof(T)));
       // P = [V^T G(alpha, 0:c+r); U^T G(beta, 0:c+r)]
-      gP.v.push_back(gd<T>(x.nodeV[nr.i], a.size, 1, x.G + a.off, f.npiv, 0, P, n2, r, c + r, a.size, 1.0, 0.0));
-      gP.v.push_back(gd<T>(x.nodeU[nr.i], be.size, 1, x.G + be.off, f.npiv, 0, P + r, n2, r, c + r, be.size, 1.0,
+      const BR& nb_ = br[bidx.at({nr.p, t.block})];     // the level's (rounded) bases
+      gP.v.push_back(gd<T>(nb_.V, a.size, 1, x.G + a.off, f.npiv, 0, P, n2, r, c + r, a.size, 1.0, 0.0));
+      gP.v.push_back(gd<T>(nb_.U, be.size, 1, x.G + be.off, f.npiv, 0, P + r, n2, r, c + r, be.size, 1.0,
                            0.0));
       CapDesc<T> cdsc{};
       cdsc.P = P; cdsc.ldp = n2; cdsc.r = r; cdsc.c = c; cdsc.Kinv = Kinv; cdsc.A = A64; cdsc.B = B64;
@@ -1363,11 +1390,11 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
       T* Wt = reinterpret_cast<T*>(tk((size_t)nf * r * sizeof(T)));
       c64.v.push_back(cd<T, double>(tb.V, npv, V64, npv, npv, r));
       c64.v.push_back(cd<T, double>(x.G, npv, X64, npv, npv, r));
-      c64.v.push_back(cd<T, double>(x.W, nf, W64, nf, nf, r));
+      c64.v.push_back(cd<T, double>(tb.U, nf, W64, nf, nf, r));
       gS.v.push_back(gd<double>(V64, npv, 1, X64, npv, 0, S64, r, r, r, npv, 1.0, 0.0));       // S = V^T X
       gWt.v.push_back(gd<double>(W64, nf, 0, S64, r, 0, Wt64, nf, nf, r, r, 1.0, 0.0));        // W S
       cW.v.push_back(cd<double, T>(Wt64, nf, Wt, nf, nf, r));
-      gup.v.push_back(gd<T>(Wt, nf, 0, x.W, nf, 1, x.F + npv + (int64_t)npv * x.ld, x.ld, nf, nf, r, -1.0, 1.0,
+      gup.v.push_back(gd<T>(Wt, nf, 0, tb.U, nf, 1, x.F + npv + (int64_t)npv * x.ld, x.ld, nf, nf, r, -1.0, 1.0,
                             GF_LOWER_C));
     }
     c64.stage(b4);
@@ -1395,6 +1422,7 @@ typename Numeric<T>::Plan* Numeric<T>::get_plan(int nrhs) {
   auto pl = std::make_unique<Plan>();
   pl->nrhs = nrhs;
   pl->dp.ar.ms = &ms;
+  const int bff = (sizeof(T) == 4 && opts.uv_bf16) ? GF_A_BF16 : 0;   // U, V, W kept in bfloat16
   const int nfr = (int)s.fronts.size();
   const int N = s.n;
   // workspace layout (elements of T)
@@ -1460,7 +1488,7 @@ typename Numeric<T>::Plan* Numeric<T>::get_plan(int nrhs) {
         T* hb = wk + h_off[p];
         if (x.r_top > 0) {
           u1.v.push_back(gd<T>(x.G, np, 1, t, nh, 0, hb, x.r_top, x.r_top, nrhs, np, 1.0, 0.0));   // X^T t_p
-          u2.v.push_back(gd<T>(x.W, nf, 0, hb, x.r_top, 0, t + np, nh, nf, nrhs, x.r_top, -1.0, 1.0));
+          u2.v.push_back(gd<T>(x.W, nf, 0, hb, x.r_top, 0, t + np, nh, nf, nrhs, x.r_top, -1.0, 1.0, bff));
         }
         zc.v.push_back(cd<T, T>(t, nh, z, np, np, nrhs));
         for (size_t i = 0; i < f.pp_tree.size(); ++i) {
@@ -1499,8 +1527,8 @@ typename Numeric<T>::Plan* Numeric<T>::get_plan(int nrhs) {
           const int r = x.nodeR[i], n2 = 2 * r, c = x.col[l];
           T* q = wk + q_off[p][i];
           T* q2 = q + (int64_t)n2 * nrhs;
-          g1.v.push_back(gd<T>(x.nodeV[i], a.size, 1, z + a.off, np, 0, q, n2, r, nrhs, a.size, 1.0, 0.0));
-          g1.v.push_back(gd<T>(x.nodeU[i], be.size, 1, z + be.off, np, 0, q + r, n2, r, nrhs, be.size, 1.0, 0.0));
+          g1.v.push_back(gd<T>(x.nodeV[i], a.size, 1, z + a.off, np, 0, q, n2, r, nrhs, a.size, 1.0, 0.0, bff));
+          g1.v.push_back(gd<T>(x.nodeU[i], be.size, 1, z + be.off, np, 0, q + r, n2, r, nrhs, be.size, 1.0, 0.0, bff));
           g2.v.push_back(gd<T>(x.nodeK[i], n2, 0, q, n2, 0, q2, n2, n2, nrhs, n2, 1.0, 0.0));
           g3.v.push_back(gd<T>(x.G + a.off + (int64_t)c * np, np, 0, q2, n2, 0, z + a.off, np, a.size, nrhs, r, -1.0,
                                1.0));
@@ -1536,7 +1564,7 @@ typename Numeric<T>::Plan* Numeric<T>::get_plan(int nrhs) {
       } else {
         T* hb = wk + h_off[p];
         if (x.r_top > 0) {
-          d1.v.push_back(gd<T>(x.W, nf, 1, t + np, nh, 0, hb, x.r_top, x.r_top, nrhs, nf, 1.0, 0.0));
+          d1.v.push_back(gd<T>(x.W, nf, 1, t + np, nh, 0, hb, x.r_top, x.r_top, nrhs, nf, 1.0, 0.0, bff));
           d2.v.push_back(gd<T>(x.G, np, 0, hb, x.r_top, 0, z, np, np, nrhs, x.r_top, -1.0, 1.0));
         }
         xo.v.push_back(cd<T, T>(z, np, pl->xn + f.start, N, np, nrhs));
@@ -1784,6 +1812,7 @@ void NumericBase::gmres(int nrhs, const double* b, double* x, double tol, const 
 void estimate_bytes(const Symbolic& s, const mf_opts& o, int nrhs, int restart, int64_t& persistent,
                     int64_t& peak) {
   const double es = o.precision == MF_FP64 ? 8.0 : 4.0;
+  const double eb = (o.precision == MF_FP32 && o.uv_bf16) ? 2.0 : es;   // stored bases U, V, W
   const bool hodlr = o.method == MF_METHOD_HODLR;
   std::vector<int64_t> ro, re, fo;
   const double ws = (double)workspace_plan(s, ro, re, fo) * es;
@@ -1807,7 +1836,7 @@ void estimate_bytes(const Symbolic& s, const mf_opts& o, int nrhs, int restart, 
       const double r = rk(B);
       if (B.kind == 0) rtop = r;
       if (B.kind == 1) {
-        fac += (B.nr + B.nc) * r * es + 4.0 * r * r * es;   // U, V and the capacitance inverse
+        fac += (B.nr + B.nc) * r * eb + 4.0 * r * r * es;   // U, V and the capacitance inverse
         w += r;
         apply += 4.0 * r * nrhs * es;
       }
@@ -1815,7 +1844,7 @@ void estimate_bytes(const Symbolic& s, const mf_opts& o, int nrhs, int restart, 
     }
     for (const TreeNode& t : f.pp_tree)
       if (t.left < 0) fac += (double)t.size * t.size * es;    // leaf inverses
-    fac += np * (rtop + w) * es + nf * rtop * es;             // G (X and the SMW columns), W
+    fac += np * (rtop + w) * es + nf * rtop * eb;             // G (X and the SMW columns), W
     apply += rtop * nrhs * es;
   }
   for (double v : lvl_scratch) scratch = std::max(scratch, v);

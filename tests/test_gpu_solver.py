@@ -177,3 +177,37 @@ def test_kernel_timing_reports_work(gpu_lib):
     f.gmres(_to_dev(b), _to_dev(np.zeros_like(b)), tol=1e-10)
     torch.cuda.synchronize()
     assert [s["name"] for s in mfh.prof_stop()] == ["spmv_kernel"]
+
+
+@pytest.mark.parametrize("name,maker,leaf,eps", [("q1_3d_16_leaf32", lambda: q1_grid(16, 3), 32, 1e-3),
+                                                 ("grf_3d_14_leaf32", None, 32, 1e-3)])
+def test_bf16_bases_reach_oracle_solution(gpu_lib, name, maker, leaf, eps):
+    """U, V, W rounded to bfloat16 and stored in bfloat16: ranks close to the
+    FP32 factor's (a front's own compression is unchanged; its parents see
+    updates built from rounded bases), smaller persistent factor, and FP64
+    GMRES still reaches the exact solution."""
+    mfh = gpu_lib
+    from mfinputs import grf_squared_exponential
+    if maker is None:
+        g = grf_squared_exponential((15, 15, 15), corr_len=0.1, variance=1.0, seed=4)
+        p = q1_grid(14, 3, k_elem=np.exp(g))
+    else:
+        p = maker()
+    print(f"case bf16 {name} n={p.A.n}", flush=True)
+    sym = mfh.Symbolic.from_csr(p.A, p.coords, leaf)
+    f32 = mfh.Factor(sym, p.A.vals, eps, method="hodlr", precision="fp32", n_c=0)
+    fbf = mfh.Factor(sym, p.A.vals, eps, method="hodlr", precision="fp32", n_c=0, uv_bf16=1)
+    r32, rbf = f32.ranks(), fbf.ranks()
+    assert r32.shape == rbf.shape and abs(int(rbf.sum()) - int(r32.sum())) <= 0.05 * r32.sum()
+    assert fbf.info()["persistent_bytes"] < f32.info()["persistent_bytes"]
+    b = rhs(p.A.n, 2, "normal", 8)
+    x = _to_dev(np.zeros_like(b))
+    infos = fbf.gmres(_to_dev(b), x, tol=1e-10)
+    assert all(i["converged"] for i in infos), infos
+    xg = _to_host(x)
+    S = p.A.to_scipy()
+    for k in range(b.shape[1]):
+        assert np.linalg.norm(b[:, k] - S @ xg[:, k]) <= 1e-10 * np.linalg.norm(b[:, k])
+    ref_sym = symbolic.analyze(p.A, p.coords, leaf)
+    xr = dense_mf.solve(dense_mf.factor(ref_sym, p.A.vals), b)
+    assert np.linalg.norm(xg - xr) <= 1e-8 * np.linalg.norm(xr)
