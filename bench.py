@@ -35,13 +35,47 @@ def _log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+KERNELS_SRC = os.path.join(ROOT, "paper_1410_2697_amd", "csrc", "kernels.hip")
+
+
+def kernels_sha1() -> str:
+    import hashlib
+    with open(KERNELS_SRC, "rb") as f:
+        return hashlib.sha1(f.read()).hexdigest()
+
+
+def measured_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of `kernel` from the rocprofv3 counter summary
+    committed under profiles/ (FETCH_SIZE + WRITE_SIZE per dispatch, each
+    scaled by the copy-kernel calibration stated there).  None when there is
+    no summary for this workload and kernel, or when the kernel source has
+    changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"pmc_traffic_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    sha, rows = None, {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("kernels.hip sha1:"):
+                sha = line.split(":", 1)[1].strip().strip("`")
+            cells = [c.strip().strip("`") for c in line.strip().strip("|").split("|")]
+            if len(cells) >= 4 and cells[0] and cells[0] != "kernel" and not cells[0].startswith("-"):
+                try:
+                    rows[cells[0]] = float(cells[3])
+                except ValueError:
+                    pass
+    if sha != kernels_sha1() or kernel not in rows:
+        return None
+    return rows[kernel]
+
+
 def kernel_bound(name: str):
     """Roofline that bounds a device kernel: MFMA contractions, register/LDS
     pivot and triangular kernels (vector ALU), streaming kernels (HBM)."""
     dt = "f32" if "<float" in name else "f64"
     if name.startswith("gemm_kernel"):
         return "mfma", dt
-    if name.startswith(("potrf_kernel", "skreg_kernel", "skelfac_kernel", "gj_kernel")):
+    if name.startswith(("potrf_kernel", "skreg_kernel", "skelfac_kernel", "gj_kernel", "phase2_coop_kernel")):
         return "alu", dt
     return "hbm", dt
 
@@ -59,7 +93,7 @@ def roofline(stat: dict) -> dict:
         peak = (MFMA_PEAK_TFLOPS if bound == "mfma" else ALU_PEAK_TFLOPS)[dt]
         unit = "TFLOP/s"
     return {"kernel": stat["name"], "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-            "frac": achieved / peak, "traffic": None, "launches": stat["launches"],
+            "frac": achieved / peak, "traffic": stat.get("traffic"), "launches": stat["launches"],
             "avg_launch_us": 1e6 * avg_s, ("bytes_per_launch" if bound == "hbm" else "flops_per_launch"): per}
 
 
@@ -105,7 +139,7 @@ def run_config(mfh, torch, w, method, precision, n_c, steps, warmup, latency_cal
         stats = mfh.prof_stop()
         kernels = breakdown(stats)
         dominant = max(stats, key=lambda s: s["seconds"])["name"] if stats else None
-        mfh.prof_start([dominant])           # timed region: events around that kernel only
+        mfh.prof_start([dominant])           # timed region: that kernel only
     phases = []
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -201,7 +235,19 @@ def main():
     ap.add_argument("--latency-calls", type=int, default=20)
     ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES three times (counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": 4 * n, "copies": 3, "kernels_sha1": kernels_sha1()}), flush=True)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
         sys.exit(2)
@@ -219,6 +265,7 @@ def main():
     _log(f"hodlr: {hod['value']:.1f} solves/s, factor {hod['factor_s']*1e3:.1f} ms, solve {hod['solve_s']*1e3:.1f} ms, "
          f"iters {max(hod['gmres_iters'])}")
     if hod["roofline"]:
+        hod["roofline"]["traffic"] = measured_traffic(w.name, hod["roofline"]["kernel"])
         r = hod["roofline"]
         _log(f"dominant kernel {r['kernel']}: {r['achieved']:.3f} {r['unit']} of {r['peak']} ({100*r['frac']:.2f}%), "
              f"avg {r['avg_launch_us']:.1f} us over {r['launches']} launches")

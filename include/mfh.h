@@ -282,13 +282,15 @@ void mf_server_destroy(mf_server_t* sv);
 /*
  * Kernel timing for roofline reports (process-wide, all handles).
  * mf_prof_start(names): from now on, every launch of the named device
- * kernels (comma-separated trace names such as "gemm_kernel<float>" or
- * "phase2_kernel<float>"; NULL or "" = all timed kernels) is bracketed by
- * two HIP events recorded on the stream it is launched on, and the host
- * adds up the launch's algorithmic work (flops; bytes that the operation
- * must move at least once).  mf_prof_stop waits for the recorded events,
- * writes one mf_kstat per kernel that ran (at most cap; *n = count) and
- * stops timing.  Timing adds two event records per timed launch.
+ * kernels (semicolon-separated trace names such as "gemm_kernel<float>" or
+ * "skreg_kernel<float, 3, 24, false, 512>"; NULL or "" = all timed kernels)
+ * is timed and the host adds up the launch's algorithmic work (flops; bytes
+ * that the operation must move at least once).  GEMM launches time
+ * themselves on the device's constant-rate clock (first workgroup start to
+ * last workgroup end); other kernels get start and end events stamped by the
+ * runtime at the kernel's own start and end.  mf_prof_stop waits for the
+ * work, writes one mf_kstat per kernel that ran (at most cap; *n = count)
+ * and stops timing.
  */
 typedef struct {
   char name[64];        /* device kernel name as it appears in a kernel trace */

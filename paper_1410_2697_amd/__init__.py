@@ -278,7 +278,7 @@ class Factor:
 def prof_start(names=None):
     """Time every launch of the named device kernels (None: all) with HIP
     events on their launch streams, adding up their algorithmic work."""
-    arg = None if not names else ",".join(names if not isinstance(names, str) else [names]).encode()
+    arg = None if not names else ";".join(names if not isinstance(names, str) else [names]).encode()
     _check(load().mf_prof_start(arg))
 
 

@@ -118,7 +118,8 @@ __device__ __forceinline__ T load_op(const T* p, size_t idx, bool bf16) {
 // LDS; the next step's operands are loaded into registers while the MFMAs
 // work on the current one.
 template <typename T>
-__global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc<T>* __restrict__ descs, int ndesc) {
+__global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc<T>* __restrict__ descs, int ndesc,
+                                                   unsigned long long* ts) {
   constexpr int BM = kTile, BN = kTile, BK = kGemmBK<T>, NQ = BK * 64 / 256;
   __shared__ T As[BK][BM + 1];
   __shared__ T Bs[BK][BN + 1];
@@ -134,6 +135,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc<T>* __restrict
   const int k = d.kdev ? *d.kdev : d.k;
   const bool split = d.ksplit > 1;
   if ((flags & GF_LOWER_C) && n0 >= m0 + BM) return;   // above the diagonal (never read back)
+  if (ts && tid == 0) atomicMin(ts, (unsigned long long)wall_clock64());   // self-timing (profiling only)
   int kb0 = 0, kend = k;
   if (flags & GF_A_LOWER) kend = min(kend, m0 + BM);
   if (flags & GF_B_UPPER) kend = min(kend, n0 + BN);
@@ -233,6 +235,10 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc<T>* __restrict
         }
       }
     }
+  }
+  if (ts) {
+    __syncthreads();
+    if (tid == 0) atomicMax(ts + 1, (unsigned long long)wall_clock64());
   }
 }
 
@@ -1124,7 +1130,8 @@ inline int grid_for(int64_t n, int block = 256, int cap = 8192) {
 template <typename T>
 void launch_gemm(const GemmDesc<T>* d, int ndesc, int tiles, hipStream_t st) {
   if (ndesc <= 0 || tiles <= 0) return;
-  MFH_LAUNCH(gemm_kernel<T>, dim3(tiles), dim3(256), 0, st, d, ndesc);
+  unsigned long long* ts = prof_take_slot();
+  MFH_LAUNCH(gemm_kernel<T>, dim3(tiles), dim3(256), 0, st, d, ndesc, ts);
 }
 template <typename T>
 void launch_gemm_reduce(const GemmDesc<T>* d, int ndesc, int tiles, hipStream_t st) {

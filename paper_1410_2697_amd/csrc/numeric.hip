@@ -1055,7 +1055,7 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
       launch_fill<float>(reinterpret_cast<float*>(bars), (int64_t)64 * p2c.size(), 0.0f, st);   // barrier counters
       const auto* dc = reinterpret_cast<const Phase2CoopDesc<T>*>(base + op2c);
       for (const CoopGroup& g : cgroups) {
-        const int id = prof_begin(pk<T>(PK_PHASE2C_F64), st, 0.0, 0.0);
+        const int id = prof_begin(pk<T>(g.slds ? PK_PHASE2CL_F64 : PK_PHASE2CG_F64), st, 0.0, 0.0);
         coop_ids.push_back(id);
         const hipError_t e = launch_phase2_coop<T>(dc + g.first, g.n, g.wgs, g.slds ? coop_lds : coop_lds_g, g.slds,
                                                    eps, dstat, kSpinLimit, st);

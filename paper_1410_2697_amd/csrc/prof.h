@@ -23,7 +23,8 @@ enum ProfKind : int {
   PK_SKREG_HAT_F64, PK_SKREG_HAT_F32,
   PK_SKELFAC_F64, PK_SKELFAC_F32,
   PK_PHASE2_F64, PK_PHASE2_F32,
-  PK_PHASE2C_F64, PK_PHASE2C_F32,
+  PK_PHASE2CL_F64, PK_PHASE2CL_F32,    // multi-workgroup phase 2, slices in LDS
+  PK_PHASE2CG_F64, PK_PHASE2CG_F32,    // multi-workgroup phase 2, in place
   PK_EXTADD_F64, PK_EXTADD_F32,
   PK_GJ,
   PK_SPMV,
@@ -44,6 +45,11 @@ const char* prof_name(int kind);
 int prof_begin(int kind, hipStream_t st, double flops, double bytes);
 void prof_end(int id, hipStream_t st);
 bool prof_take(hipEvent_t* start, hipEvent_t* stop);
+// GEMM launches time themselves (short kernels: events would add the launch
+// overhead): a pending GEMM record hands out a device slot of two counters,
+// the earliest workgroup start and the latest workgroup end on the device's
+// constant-rate wall clock (atomic min / max).  nullptr when nothing is pending.
+unsigned long long* prof_take_slot();
 // for a launch that cannot take events: record the start on the stream now
 void prof_stream_start(int id, hipStream_t st);
 
@@ -64,7 +70,7 @@ struct ProfTotal {
   int64_t launches;
   double seconds, flops, bytes;
 };
-// names: comma-separated kernel names to time; empty = every kind
+// names: semicolon-separated kernel names to time; empty = every kind
 void prof_start(const std::string& names);
 // waits for the recorded events, returns per-kind totals, stops timing
 std::vector<ProfTotal> prof_stop();

@@ -172,11 +172,15 @@ def test_kernel_timing_reports_work(gpu_lib):
         assert name in stats and stats[name]["launches"] > 0 and stats[name]["seconds"] > 0, name
     assert stats["gemm_kernel<float>"]["flops"] > 0
     assert stats["spmv_kernel"]["bytes"] >= 12.0 * p.A.nnz
-    # timing only the named kernel leaves the others untimed
+    # timing only the named kernels leaves the others untimed (names may hold commas)
     mfh.prof_start(["spmv_kernel"])
     f.gmres(_to_dev(b), _to_dev(np.zeros_like(b)), tol=1e-10)
     torch.cuda.synchronize()
     assert [s["name"] for s in mfh.prof_stop()] == ["spmv_kernel"]
+    mfh.prof_start(["potrf_kernel<float, 64, 256>", "gemm_kernel<float>"])
+    mfh.Factor(sym, p.A.vals, 1e-4, method="hodlr", precision="fp32", n_c=64)
+    torch.cuda.synchronize()
+    assert sorted(s["name"] for s in mfh.prof_stop()) == ["gemm_kernel<float>", "potrf_kernel<float, 64, 256>"]
 
 
 @pytest.mark.parametrize("name,maker,leaf,eps", [("q1_3d_16_leaf32", lambda: q1_grid(16, 3), 32, 1e-3),
