@@ -361,6 +361,20 @@ __device__ __forceinline__ u64 wave_max_u64(u64 v) {
   return v;
 }
 
+// block-wide max with one barrier: the wave maxima go to one of two LDS
+// buffers chosen by the caller's step parity, so the next step can write the
+// other buffer without waiting for this step's readers
+__device__ __forceinline__ u64 block_max_u64_db(u64 v, u64* sh, int par) {
+  v = wave_max_u64(v);
+  u64* buf = sh + 16 * par;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, nw = blockDim.x >> 6;
+  if (l == 0) buf[w] = v;
+  __syncthreads();
+  u64 r = buf[0];
+  for (int k = 1; k < nw; ++k) r = buf[k] > r ? buf[k] : r;
+  return r;
+}
+
 __device__ u64 block_max_u64(u64 v, u64* sh) {
   v = wave_max_u64(v);
   const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
@@ -380,7 +394,7 @@ __global__ __launch_bounds__(NT) void skreg_kernel(const SkRegDesc<T>* __restric
   constexpr int CG = NT / 64, MR = RI * 64, MC = CJ * CG;
   __shared__ T s_row[MC];
   __shared__ T s_col[MR];
-  __shared__ u64 s_red[16];
+  __shared__ u64 s_red[32];
   __shared__ char s_inI[FULL ? MR : 1];
   __shared__ char s_inJ[FULL ? MC : 1];
   __shared__ short s_rstep[FULL ? 1 : MR];
@@ -424,6 +438,12 @@ __global__ __launch_bounds__(NT) void skreg_kernel(const SkRegDesc<T>* __restric
   T u11 = 0;
   // empty BDLR sets without the adaptive phase: rank 0
   const bool run = !(FULL && phase == 2 && !adaptive);
+  // Each step: search the registers, block-wide max of the pivot keys (one
+  // barrier; the wave maxima alternate between two LDS buffers), the pivot
+  // row and column through LDS (one barrier), then the rank-1 update.  The
+  // next step's first LDS writes come after its own reduction barrier, so no
+  // barrier closes a step.
+  int par = 0;
   while (run) {
     const unsigned smask_r = (phase == 1 && FULL) ? (rl & inI) : rl;
     const unsigned smask_c = (phase == 1 && FULL) ? (cl & inJ) : cl;
@@ -440,8 +460,8 @@ __global__ __launch_bounds__(NT) void skreg_kernel(const SkRegDesc<T>* __restric
         if (q > bq) { bq = q; bj = j; bi = i; }
       }
     }
-    const u64 best = make_key(bq, (unsigned)((g + CG * bj) * M + lane + 64 * bi));
-    const u64 K = block_max_u64(best, s_red);
+    const u64 K = block_max_u64_db(make_key(bq, (unsigned)((g + CG * bj) * M + lane + 64 * bi)), s_red, par);
+    par ^= 1;
     bool stop = K == 0ull;
     int as = 0, bs = 0;
     T piv = 0;
@@ -474,7 +494,6 @@ __global__ __launch_bounds__(NT) void skreg_kernel(const SkRegDesc<T>* __restric
       if (FULL && phase == 1 && adaptive) {
         phase = 2;
         r1 = r;
-        __syncthreads();
         continue;
       }
       break;
@@ -503,9 +522,10 @@ __global__ __launch_bounds__(NT) void skreg_kernel(const SkRegDesc<T>* __restric
         for (int i = 0; i < RI; ++i) e[i][j] -= li[i] * uj;
       }
     } else {
-      // in-place LU of B_hat: live rows get l = e / piv in the pivot column
+      // in-place LU of B_hat: live rows other than the pivot row get
+      // l = e / piv in the pivot column and the update elsewhere
       T li[RI];
-      unsigned upd = 0;   // rows to update: live and not the pivot row
+      unsigned upd = 0;
 #pragma unroll
       for (int i = 0; i < RI; ++i) {
         const int a = lane + 64 * i;
@@ -529,7 +549,6 @@ __global__ __launch_bounds__(NT) void skreg_kernel(const SkRegDesc<T>* __restric
     if (lane == (as & 63)) rl &= ~(1u << (as >> 6));
     if (g == (bs % CG)) cl &= ~(1u << (bs / CG));
     ++r;
-    __syncthreads();
   }
   if (r1 < 0) r1 = r;
   if (t == 0) {
