@@ -336,16 +336,18 @@ __global__ __launch_bounds__(NT) void potrf_kernel(const PotrfDesc<T>* __restric
 }
 
 // ------------------------------------------ register-resident skeleton ----
-// Pivot key: |v| truncated to 20 mantissa bits in the high word, the
-// complement of the column-major index (col * rows + row) in the low word, so
-// the largest key is the largest truncated magnitude with the lowest column,
-// then the lowest row.  A zero magnitude never wins (key 0 = no candidate).
+// Pivot key: |v| truncated in the high word (FP64: 20 mantissa bits; FP32:
+// 16, which leaves room for a position inside one 32-bit word in the
+// register kernel below), the complement of the element's position in the
+// low word, ordered by column, then row, so the largest key is the largest
+// truncated magnitude with the lowest column, then the lowest row.  A zero
+// magnitude never wins (key 0 = no candidate).
 typedef unsigned long long u64;
 
 __device__ __forceinline__ unsigned qmag(double v) {
   return (unsigned)(__double_as_longlong(fabs(v)) >> 32);
 }
-__device__ __forceinline__ unsigned qmag(float v) { return (unsigned)__float_as_uint(fabsf(v)) >> 3; }
+__device__ __forceinline__ unsigned qmag(float v) { return (unsigned)__float_as_uint(fabsf(v)) >> 7; }
 
 __device__ __forceinline__ u64 make_key(unsigned q, unsigned idx) {
   return q == 0u ? 0ull : (((u64)q) << 32) | (u64)(0xFFFFFFFFu - idx);
@@ -361,20 +363,6 @@ __device__ __forceinline__ u64 wave_max_u64(u64 v) {
   return v;
 }
 
-// block-wide max with one barrier: the wave maxima go to one of two LDS
-// buffers chosen by the caller's step parity, so the next step can write the
-// other buffer without waiting for this step's readers
-__device__ __forceinline__ u64 block_max_u64_db(u64 v, u64* sh, int par) {
-  v = wave_max_u64(v);
-  u64* buf = sh + 16 * par;
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, nw = blockDim.x >> 6;
-  if (l == 0) buf[w] = v;
-  __syncthreads();
-  u64 r = buf[0];
-  for (int k = 1; k < nw; ++k) r = buf[k] > r ? buf[k] : r;
-  return r;
-}
-
 __device__ u64 block_max_u64(u64 v, u64* sh) {
   v = wave_max_u64(v);
   const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
@@ -386,169 +374,276 @@ __device__ u64 block_max_u64(u64 v, u64* sh) {
   return r;
 }
 
+// store through the global address space: generic (flat) stores would also
+// hold up the wave's next wait for LDS results
+template <typename T>
+__device__ __forceinline__ void gstore(T* p, T v) {
+  *(__attribute__((address_space(1))) T*)p = v;
+}
+template <typename T>
+__device__ __forceinline__ T gload(const T* p) {
+  return *(const __attribute__((address_space(1))) T*)p;
+}
+
+// Wave-wide max / min with all 64 lanes active, returned in a scalar
+// register: DPP exchanges inside each row of 16 lanes (swap neighbours, swap
+// pairs, mirror in 8, mirror in 16), then the four row results are read out.
+template <bool MAX>
+__device__ __forceinline__ unsigned wave_ext_u32(unsigned v) {
+  auto pick = [](unsigned x, unsigned y) { return MAX ? (x > y ? x : y) : (x < y ? x : y); };
+  v = pick(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0xB1, 0xF, 0xF, false));
+  v = pick(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x4E, 0xF, 0xF, false));
+  v = pick(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x141, 0xF, 0xF, false));
+  v = pick(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x140, 0xF, 0xF, false));
+  const unsigned r0 = (unsigned)__builtin_amdgcn_readlane((int)v, 0);
+  const unsigned r1 = (unsigned)__builtin_amdgcn_readlane((int)v, 16);
+  const unsigned r2 = (unsigned)__builtin_amdgcn_readlane((int)v, 32);
+  const unsigned r3 = (unsigned)__builtin_amdgcn_readlane((int)v, 48);
+  return pick(pick(r0, r1), pick(r2, r3));
+}
+
+__device__ __forceinline__ float uniform(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ double uniform(double v) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(b & 0xFFFFFFFFll));
+  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)((unsigned long long)b >> 32));
+  return __longlong_as_double((long long)(((u64)hi << 32) | lo));
+}
+__device__ __forceinline__ unsigned uniform(unsigned v) { return (unsigned)__builtin_amdgcn_readfirstlane((int)v); }
+__device__ __forceinline__ u64 uniform(u64 v) {
+  return ((u64)uniform((unsigned)(v >> 32)) << 32) | uniform((unsigned)(v & 0xFFFFFFFFull));
+}
+
 // Thread t owns rows a = (t & 63) + 64 i (i < RI) and columns
-// b = (t >> 6) + CG j (j < CJ) of the block, CG = NT / 64 column groups.
+// b = (t >> 6) + CG j (j < CJ) of the block, CG = NT / 64 column groups, so
+// a column belongs to one wave and its liveness is wave-uniform.
+// Positions are (column << 16) | row.
 template <typename T, int RI, int CJ, bool FULL, int NT>
 __global__ __launch_bounds__(NT) void skreg_kernel(const SkRegDesc<T>* __restrict__ descs, double eps,
                                                      int adaptive, int* status) {
   constexpr int CG = NT / 64, MR = RI * 64, MC = CJ * CG;
-  __shared__ T s_row[MC];
+  static_assert(RI * CJ <= 128 && MR < 65536 && MC < 65536, "register block too large");
+  constexpr unsigned kMag = sizeof(T) == 4 ? 0x7FFFFF80u : 0x7FFFFFFFu;
+  __shared__ __align__(16) T s_row[CG][CJ];     // pivot row, by (column group, j)
   __shared__ T s_col[MR];
-  __shared__ u64 s_red[32];
+  __shared__ u64 s_red[2][CG];
   __shared__ char s_inI[FULL ? MR : 1];
   __shared__ char s_inJ[FULL ? MC : 1];
   __shared__ short s_rstep[FULL ? 1 : MR];
   __shared__ short s_cstep[FULL ? 1 : MC];
   const SkRegDesc<T> d = descs[blockIdx.x];
-  const int t = threadIdx.x, lane = t & 63, g = t >> 6;
+  const int t = threadIdx.x, lane = t & 63;
+  const int g = (int)uniform((unsigned)(t >> 6));
   const int M = FULL ? d.nr : d.nI, N = FULL ? d.nc : d.nJ;
   T e[RI][CJ];
   unsigned rl = 0, cl = 0, inI = 0, inJ = 0;
 #pragma unroll
-  for (int i = 0; i < RI; ++i) {
-    const int a = lane + 64 * i;
-    if (a < M) rl |= 1u << i;
+  for (int i = 0; i < RI; ++i)
+    if (lane + 64 * i < M) rl |= 1u << i;
+#pragma unroll
+  for (int j = 0; j < CJ; ++j)
+    if (g + CG * j < N) cl |= 1u << j;
+  cl = uniform(cl);
+  if (M > 0 && N > 0) {
+    // front offsets first, then every element load at once: indices past
+    // the block are clamped to its last row / column and the value dropped
+    int ro[RI];
+    size_t co[CJ];
+#pragma unroll
+    for (int i = 0; i < RI; ++i) {
+      const int a = min(lane + 64 * i, M - 1);
+      ro[i] = FULL ? d.r0 + a : gload(d.I + a);
+    }
 #pragma unroll
     for (int j = 0; j < CJ; ++j) {
-      const int b = g + CG * j;
-      if (i == 0 && b < N) cl |= 1u << j;
-      T v = 0;
-      if (a < M && b < N) v = FULL ? d.F[(d.r0 + a) + (size_t)(d.c0 + b) * d.ld] : d.F[d.I[a] + (size_t)d.J[b] * d.ld];
-      e[i][j] = v;
+      const int b = min(g + CG * j, N - 1);
+      co[j] = (size_t)(FULL ? d.c0 + b : gload(d.J + b)) * (size_t)d.ld;
     }
+#pragma unroll
+    for (int i = 0; i < RI; ++i)
+#pragma unroll
+      for (int j = 0; j < CJ; ++j) {
+        const T v = gload(d.F + ro[i] + co[j]);
+        e[i][j] = (((rl >> i) & 1u) && ((cl >> j) & 1u)) ? v : (T)0;
+      }
+  } else {
+#pragma unroll
+    for (int i = 0; i < RI; ++i)
+#pragma unroll
+      for (int j = 0; j < CJ; ++j) e[i][j] = 0;
   }
   if (FULL) {
-    for (int a = t; a < MR; a += blockDim.x) s_inI[a] = 0;
-    for (int b = t; b < MC; b += blockDim.x) s_inJ[b] = 0;
+    for (int a = t; a < MR; a += NT) s_inI[a] = 0;
+    for (int b = t; b < MC; b += NT) s_inJ[b] = 0;
     __syncthreads();
-    for (int k = t; k < d.nI; k += blockDim.x) s_inI[d.I[k] - d.r0] = 1;
-    for (int k = t; k < d.nJ; k += blockDim.x) s_inJ[d.J[k] - d.c0] = 1;
+    for (int k = t; k < d.nI; k += NT) s_inI[d.I[k] - d.r0] = 1;
+    for (int k = t; k < d.nJ; k += NT) s_inJ[d.J[k] - d.c0] = 1;
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < RI; ++i) if (s_inI[lane + 64 * i]) inI |= 1u << i;
 #pragma unroll
     for (int j = 0; j < CJ; ++j) if (s_inJ[g + CG * j]) inJ |= 1u << j;
+    inJ = uniform(inJ);
   } else {
-    for (int a = t; a < MR; a += blockDim.x) s_rstep[a] = -1;
-    for (int b = t; b < MC; b += blockDim.x) s_cstep[b] = -1;
+    for (int a = t; a < MR; a += NT) s_rstep[a] = -1;
+    for (int b = t; b < MC; b += NT) s_cstep[b] = -1;
   }
   const T stop_rel = (T)fmax(eps, (double)noise_rel<T>());
-  int phase = (FULL && !(d.nI > 0 && d.nJ > 0)) ? 2 : 1;
   int r = 0, r1 = -1;
   T u11 = 0;
-  // empty BDLR sets without the adaptive phase: rank 0
-  const bool run = !(FULL && phase == 2 && !adaptive);
-  // Each step: search the registers, block-wide max of the pivot keys (one
-  // barrier; the wave maxima alternate between two LDS buffers), the pivot
-  // row and column through LDS (one barrier), then the rank-1 update.  The
-  // next step's first LDS writes come after its own reduction barrier, so no
-  // barrier closes a step.
   int par = 0;
-  while (run) {
-    const unsigned smask_r = (phase == 1 && FULL) ? (rl & inI) : rl;
-    const unsigned smask_c = (phase == 1 && FULL) ? (cl & inJ) : cl;
-    // within a thread the index grows with (j, i) in that order, so the first
-    // strict maximum in this loop order is the thread's best key
-    unsigned bq = 0;
-    int bj = 0, bi = 0;
+  // Phase 1 searches I x J (whole-block mode) or all of B_hat; phase 2 (the
+  // adaptive phase) the whole residual block.  Empty BDLR sets start in
+  // phase 2, or stop at rank 0 without it.  Each pivot step: search the
+  // registers, block-wide max of the pivot keys (one barrier; the wave keys
+  // alternate between two LDS buffers), the pivot row and column through LDS
+  // (one barrier), then the rank-1 update.  The next step's first LDS writes
+  // come after its own reduction barrier, so no barrier closes a step.  The
+  // inner loop has a single latch, which keeps the register block in place.
+  const int last = FULL && adaptive ? 2 : 1;
+  int phase = (FULL && !(d.nI > 0 && d.nJ > 0)) ? 2 : 1;
+  bool capped = false;
+  for (; phase <= last && !capped; ++phase) {
+    const bool restricted = FULL && phase == 1;
+    for (;;) {
+      const unsigned rsel = restricted ? (rl & inI) : rl;
+      const unsigned csel = restricted ? (cl & inJ) : cl;
+      unsigned rm[RI];
 #pragma unroll
-    for (int j = 0; j < CJ; ++j) {
-      if (!((smask_c >> j) & 1u)) continue;
+      for (int i = 0; i < RI; ++i) rm[i] = ((rsel >> i) & 1u) ? kMag : 0u;
+      // thread-local best in (j, i) order, which is the position order; wave
+      // winner: largest magnitude, then earliest (j, i), then lowest lane
+      unsigned q, l, wl;
+      if constexpr (sizeof(T) == 4) {
+        // one word per element: magnitude bits 7..30, then 127 - (j RI + i)
+        unsigned bk = 0;
 #pragma unroll
-      for (int i = 0; i < RI; ++i) {
-        const unsigned q = ((smask_r >> i) & 1u) ? qmag(e[i][j]) : 0u;
-        if (q > bq) { bq = q; bj = j; bi = i; }
+        for (int j = 0; j < CJ; ++j) {
+          if (!((csel >> j) & 1u)) continue;
+#pragma unroll
+          for (int i = 0; i < RI; ++i) {
+            const unsigned w = (__float_as_uint(e[i][j]) & rm[i]) | (unsigned)(127 - (j * RI + i));
+            bk = w > bk ? w : bk;
+          }
+        }
+        const unsigned m = wave_ext_u32<true>(bk);
+        wl = (unsigned)(__ffsll((unsigned long long)__ballot(bk == m)) - 1);
+        q = m >> 7;
+        l = 127u - (m & 127u);
+      } else {
+        unsigned bq = 0, bl = 0;
+#pragma unroll
+        for (int j = 0; j < CJ; ++j) {
+          if (!((csel >> j) & 1u)) continue;
+#pragma unroll
+          for (int i = 0; i < RI; ++i) {
+            const unsigned x = (unsigned)((u64)__double_as_longlong(e[i][j]) >> 32) & rm[i];
+            if (x > bq) { bq = x; bl = (unsigned)(j * RI + i); }
+          }
+        }
+        q = wave_ext_u32<true>(bq);
+        const unsigned m = wave_ext_u32<false>(bq == q ? (bl << 6) | (unsigned)lane : 0xFFFFFFFFu);
+        l = m >> 6;
+        wl = m & 63u;
       }
-    }
-    const u64 K = block_max_u64_db(make_key(bq, (unsigned)((g + CG * bj) * M + lane + 64 * bi)), s_red, par);
-    par ^= 1;
-    bool stop = K == 0ull;
-    int as = 0, bs = 0;
-    T piv = 0;
-    if (!stop) {
-      const unsigned idx = 0xFFFFFFFFu - (unsigned)(K & 0xFFFFFFFFull);
-      as = (int)(idx % (unsigned)M);
-      bs = (int)(idx / (unsigned)M);
+      {
+        const unsigned jw = l / RI, iw = l - jw * RI;
+        const unsigned pos = (((unsigned)g + CG * jw) << 16) | (wl + 64u * iw);
+        if (lane == 0) s_red[par][g] = q ? (((u64)q) << 32) | (u64)(0xFFFFFFFFu - pos) : 0ull;
+      }
+      __syncthreads();
+      u64 K = s_red[par][0];
+#pragma unroll
+      for (int k = 1; k < CG; ++k) K = s_red[par][k] > K ? s_red[par][k] : K;
+      K = uniform(K);
+      par ^= 1;
+      if (K == 0ull) break;
+      const unsigned pos = 0xFFFFFFFFu - (unsigned)(K & 0xFFFFFFFFull);
+      const int as = (int)(pos & 0xFFFFu), bs = (int)(pos >> 16);
+      const int ia = as >> 6, gb = bs % CG, jb = bs / CG;
       if (lane == (as & 63)) {
 #pragma unroll
         for (int i = 0; i < RI; ++i)
-          if (i == (as >> 6)) {
+          if (i == ia) {
 #pragma unroll
-            for (int j = 0; j < CJ; ++j) s_row[g + CG * j] = e[i][j];
+            for (int j = 0; j < CJ; ++j) s_row[g][j] = (FULL || ((cl >> j) & 1u)) ? e[i][j] : (T)0;
           }
       }
-      if (g == (bs % CG)) {
+      if (g == gb) {
 #pragma unroll
         for (int j = 0; j < CJ; ++j)
-          if (j == (bs / CG)) {
+          if (j == jb) {
 #pragma unroll
             for (int i = 0; i < RI; ++i) s_col[lane + 64 * i] = e[i][j];
           }
       }
       __syncthreads();
-      piv = s_row[bs];
+      const T piv = uniform(s_row[gb][jb]);
       if (u11 == (T)0) u11 = fabs(piv);
-      stop = fabs(piv) < stop_rel * u11;
-    }
-    if (stop) {
-      if (FULL && phase == 1 && adaptive) {
-        phase = 2;
-        r1 = r;
-        continue;
+      if (fabs(piv) < stop_rel * u11) break;
+      if (r >= d.cap) {
+        if (t == 0) atomicOr(status, 2);
+        capped = true;
+        break;
       }
-      break;
-    }
-    if (r >= d.cap) {
-      if (t == 0) atomicOr(status, 2);
-      break;
-    }
-    if (t == 0) {
-      d.piv_r[r] = FULL ? d.r0 + as : d.I[as];
-      d.piv_c[r] = FULL ? d.c0 + bs : d.J[bs];
-    }
-    const T rpiv = (T)1 / piv;
-    if (FULL) {
-      T* Uc = d.U + (size_t)r * d.ldu;
-      T* Vc = d.V + (size_t)r * d.ldv;
-      for (int a = t; a < M; a += blockDim.x) Uc[a] = phase == 1 ? s_col[a] / piv : s_col[a];
-      for (int b = t; b < N; b += blockDim.x) Vc[b] = phase == 1 ? s_row[b] : s_row[b] / piv;
-      T li[RI];
+      const T rpiv = (T)1 / piv;
+      if (FULL) {
+        if (t == 0) {
+          gstore(d.piv_r + r, d.r0 + as);
+          gstore(d.piv_c + r, d.c0 + bs);
+        }
+        T* Uc = d.U + (size_t)r * d.ldu;
+        T* Vc = d.V + (size_t)r * d.ldv;
+        for (int a = t; a < M; a += NT) gstore(Uc + a, phase == 1 ? s_col[a] / piv : s_col[a]);
+        for (int b = t; b < N; b += NT)
+          gstore(Vc + b, phase == 1 ? s_row[b % CG][b / CG] : s_row[b % CG][b / CG] / piv);
+        T li[RI];
 #pragma unroll
-      for (int i = 0; i < RI; ++i) li[i] = s_col[lane + 64 * i] * rpiv;
+        for (int i = 0; i < RI; ++i) li[i] = s_col[lane + 64 * i] * rpiv;
 #pragma unroll
-      for (int j = 0; j < CJ; ++j) {
-        const T uj = s_row[g + CG * j];
+        for (int j = 0; j < CJ; ++j) {
+          const T uj = s_row[g][j];
 #pragma unroll
-        for (int i = 0; i < RI; ++i) e[i][j] -= li[i] * uj;
-      }
-    } else {
-      // in-place LU of B_hat: live rows other than the pivot row get
-      // l = e / piv in the pivot column and the update elsewhere
-      T li[RI];
-      unsigned upd = 0;
-#pragma unroll
-      for (int i = 0; i < RI; ++i) {
-        const int a = lane + 64 * i;
-        li[i] = s_col[a] * rpiv;
-        if (((rl >> i) & 1u) && a != as) upd |= 1u << i;
-      }
-#pragma unroll
-      for (int j = 0; j < CJ; ++j) {
-        const int b = g + CG * j;
-        const T uj = s_row[b];
-        const bool pc = b == bs, lc = ((cl >> j) & 1u) != 0;
+          for (int i = 0; i < RI; ++i) e[i][j] -= li[i] * uj;
+        }
+      } else {
+        // in-place LU of B_hat: live rows other than the pivot row take the
+        // update (the pivot row broadcast holds zeros in dead columns, and
+        // the other rows get a zero multiplier); the pivot column then
+        // stores the multipliers l = e / piv
+        T li[RI];
+        unsigned upd = 0;
 #pragma unroll
         for (int i = 0; i < RI; ++i) {
-          if (!((upd >> i) & 1u)) continue;
-          if (pc) e[i][j] = li[i];
-          else if (lc) e[i][j] -= li[i] * uj;
+          const int a = lane + 64 * i;
+          const bool u = ((rl >> i) & 1u) && a != as;
+          li[i] = u ? s_col[a] * rpiv : (T)0;
+          if (u) upd |= 1u << i;
         }
+#pragma unroll
+        for (int j = 0; j < CJ; ++j) {
+          const T uj = s_row[g][j];
+#pragma unroll
+          for (int i = 0; i < RI; ++i) e[i][j] -= li[i] * uj;
+        }
+        if (g == gb) {
+#pragma unroll
+          for (int j = 0; j < CJ; ++j)
+            if (j == jb) {
+#pragma unroll
+              for (int i = 0; i < RI; ++i)
+                if ((upd >> i) & 1u) e[i][j] = li[i];
+            }
+        }
+        if (t == 0) { s_rstep[as] = (short)r; s_cstep[bs] = (short)r; }
       }
-      if (t == 0) { s_rstep[as] = (short)r; s_cstep[bs] = (short)r; }
+      if (lane == (as & 63)) rl &= ~(1u << ia);
+      if (g == gb) cl &= ~(1u << jb);
+      ++r;
     }
-    if (lane == (as & 63)) rl &= ~(1u << (as >> 6));
-    if (g == (bs % CG)) cl &= ~(1u << (bs / CG));
-    ++r;
+    if (phase == 1 && !capped && last == 2) r1 = r;
   }
   if (r1 < 0) r1 = r;
   if (t == 0) {
@@ -558,6 +653,11 @@ __global__ __launch_bounds__(NT) void skreg_kernel(const SkRegDesc<T>* __restric
   }
   if (!FULL) {
     __syncthreads();
+    // pivot positions in the front, by step
+    for (int a = t; a < M; a += NT)
+      if (s_rstep[a] >= 0) d.piv_r[s_rstep[a]] = d.I[a];
+    for (int b = t; b < N; b += NT)
+      if (s_cstep[b] >= 0) d.piv_c[s_cstep[b]] = d.J[b];
 #pragma unroll
     for (int i = 0; i < RI; ++i) {
       const int a = lane + 64 * i;
@@ -1173,9 +1273,9 @@ template <typename T>
 void launch_skreg_full(const SkRegDesc<T>* d, int ndesc, double eps, int adaptive, int* status, hipStream_t st) {
   if (ndesc <= 0) return;
   if constexpr (sizeof(T) == 8)
-    MFH_LAUNCH((skreg_kernel<T, 2, 32, true, 512>), dim3(ndesc), dim3(512), 0, st, d, eps, adaptive, status);
+    MFH_LAUNCH((skreg_kernel<T, 2, 16, true, 1024>), dim3(ndesc), dim3(1024), 0, st, d, eps, adaptive, status);
   else
-    MFH_LAUNCH((skreg_kernel<T, 4, 32, true, 512>), dim3(ndesc), dim3(512), 0, st, d, eps, adaptive, status);
+    MFH_LAUNCH((skreg_kernel<T, 4, 16, true, 1024>), dim3(ndesc), dim3(1024), 0, st, d, eps, adaptive, status);
 }
 template <typename T>
 void launch_skreg_hat(const SkRegDesc<T>* d, int ndesc, double eps, int* status, hipStream_t st) {

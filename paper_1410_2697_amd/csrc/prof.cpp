@@ -13,7 +13,7 @@ const char* const kNames[PK_COUNT] = {
     "gemm_reduce_kernel<double>", "gemm_reduce_kernel<float>",
     "potrf_kernel<double, 64, 256>",  "potrf_kernel<float, 64, 256>",
     "potrf_kernel<double, 128, 512>", "potrf_kernel<float, 128, 512>",
-    "skreg_kernel<double, 2, 32, true, 512>", "skreg_kernel<float, 4, 32, true, 512>",
+    "skreg_kernel<double, 2, 16, true, 1024>", "skreg_kernel<float, 4, 16, true, 1024>",
     "skreg_kernel<double, 2, 8, false, 1024>", "skreg_kernel<float, 3, 24, false, 512>",
     "skelfac_kernel<double>",     "skelfac_kernel<float>",
     "phase2_kernel<double>",      "phase2_kernel<float>",
