@@ -227,6 +227,12 @@ template <typename T>
 constexpr int skreg_full_cols() { return 256; }
 template <typename T>
 constexpr int skreg_hat_max() { return sizeof(T) == 8 ? 128 : 192; }
+// skeleton factors: one 64-lane workgroup per 64 rows of C~ or of R~; LDS
+// holds the solved values (rmax x 64) and one column block of the factor
+constexpr int kSkelFacRows = 64;
+constexpr int kSkelFacBlock = 16;
+template <typename T>
+constexpr size_t skelfac_lds(int rmax) { return (size_t)rmax * (kSkelFacRows + kSkelFacBlock) * sizeof(T); }
 template <typename T>
 void launch_skelfac(const SkelFacDesc<T>* d, int ndesc, int wgs, int rmax, hipStream_t st);
 template <typename T>

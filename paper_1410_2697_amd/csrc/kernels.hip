@@ -676,37 +676,65 @@ __global__ __launch_bounds__(NT) void skreg_kernel(const SkRegDesc<T>* __restric
 }
 
 // ------------------------------------- skeleton factors C~ and R~^T -------
+// Each lane owns one row i of C~ (x U_r = B(i, J_r), U_r upper) or one
+// column a of R~^T (L_r y = B(I_r, a), L_r unit lower).  The solve runs over
+// column blocks of KB: the block's right-hand sides sit in registers, the
+// contributions of all earlier solved values (LDS, one per lane) are
+// subtracted with KB independent FMAs per value, then the triangular block
+// itself is solved in order.  The operations per entry are those of the
+// plain forward substitution, in the same order.
 template <typename T>
-__global__ __launch_bounds__(256) void skelfac_kernel(const SkelFacDesc<T>* __restrict__ descs, int ndesc) {
+__global__ __launch_bounds__(kSkelFacRows) void skelfac_kernel(const SkelFacDesc<T>* __restrict__ descs, int ndesc,
+                                                               int rmax) {
+  constexpr int KB = kSkelFacBlock, W = kSkelFacRows;
   extern __shared__ __align__(16) char smem[];
-  T* Ms = reinterpret_cast<T*>(smem);
+  T* X = reinterpret_cast<T*>(smem);              // rmax x W solved values
+  T* S = X + (size_t)rmax * W;                    // rmax x KB factor block
   int lo = 0, hi = ndesc - 1;
   while (lo < hi) { int mid = (lo + hi + 1) >> 1; if (descs[mid].wg0 <= (int)blockIdx.x) lo = mid; else hi = mid - 1; }
   const SkelFacDesc<T> d = descs[lo];
   const int r = *d.rank;
-  for (int idx = threadIdx.x; idx < r * r; idx += blockDim.x)
-    Ms[idx] = d.M[(idx % r) + (size_t)(idx / r) * d.ldm];
-  __syncthreads();
-  const int local = (int)blockIdx.x - d.wg0;
-  if (local < d.wgU) {
-    const int i = local * blockDim.x + threadIdx.x;
-    if (i >= d.nr) return;
-    const T* Frow = d.F + d.r0 + i;
-    T* U = d.U + i;
-    for (int s = 0; s < r; ++s) {       // x U_r = B(i, J_r)
-      T x = Frow[(size_t)d.piv_c[s] * d.ld];
-      for (int t = 0; t < s; ++t) x -= U[(size_t)t * d.ldu] * Ms[t + s * r];
-      U[(size_t)s * d.ldu] = x / Ms[s + s * r];
+  const int local = (int)blockIdx.x - d.wg0, lane = threadIdx.x;
+  const bool upart = local < d.wgU;
+  const int row = (upart ? local : local - d.wgU) * W + lane;
+  const bool valid = row < (upart ? d.nr : d.nc);
+  for (int k0 = 0; k0 < r; k0 += KB) {
+    const int nb = min(KB, r - k0), tn = k0 + nb;
+    __syncthreads();                              // earlier readers of S are done
+    for (int q = lane; q < tn * KB; q += W) {
+      const int t = q / KB, c = q - (q / KB) * KB;
+      T v = 0;
+      if (c < nb) v = upart ? d.M[t + (size_t)(k0 + c) * d.ldm] : d.M[(k0 + c) + (size_t)t * d.ldm];
+      S[q] = v;
     }
-  } else {
-    const int a = (local - d.wgU) * blockDim.x + threadIdx.x;
-    if (a >= d.nc) return;
-    const T* Fcol = d.F + (size_t)(d.c0 + a) * d.ld;
-    T* V = d.V + a;
-    for (int s = 0; s < r; ++s) {       // L_r y = B(I_r, a), unit diagonal
-      T y = Fcol[d.piv_r[s]];
-      for (int t = 0; t < s; ++t) y -= Ms[s + t * r] * V[(size_t)t * d.ldv];
-      V[(size_t)s * d.ldv] = y;
+    T acc[KB];
+#pragma unroll
+    for (int c = 0; c < KB; ++c) {
+      T v = 0;
+      if (valid && c < nb)
+        v = upart ? d.F[(d.r0 + row) + (size_t)d.piv_c[k0 + c] * d.ld]
+                  : d.F[d.piv_r[k0 + c] + (size_t)(d.c0 + row) * d.ld];
+      acc[c] = v;
+    }
+    __syncthreads();
+    for (int t = 0; t < k0; ++t) {
+      const T xt = X[(size_t)t * W + lane];
+      const T* st = S + t * KB;
+#pragma unroll
+      for (int c = 0; c < KB; ++c) acc[c] -= xt * st[c];
+    }
+#pragma unroll
+    for (int c = 0; c < KB; ++c) {
+      if (c < nb) {
+#pragma unroll
+        for (int cp = 0; cp < c; ++cp) acc[c] -= acc[cp] * S[(k0 + cp) * KB + c];
+        if (upart) acc[c] = acc[c] / S[(k0 + c) * KB + c];
+        X[(size_t)(k0 + c) * W + lane] = acc[c];
+        if (valid) {
+          if (upart) d.U[(size_t)(k0 + c) * d.ldu + row] = acc[c];
+          else d.V[(size_t)(k0 + c) * d.ldv + row] = acc[c];
+        }
+      }
     }
   }
 }
@@ -1288,7 +1316,7 @@ void launch_skreg_hat(const SkRegDesc<T>* d, int ndesc, double eps, int* status,
 template <typename T>
 void launch_skelfac(const SkelFacDesc<T>* d, int ndesc, int wgs, int rmax, hipStream_t st) {
   if (ndesc <= 0 || wgs <= 0) return;
-  MFH_LAUNCH(skelfac_kernel<T>, dim3(wgs), dim3(256), (size_t)rmax * rmax * sizeof(T), st, d, ndesc);
+  MFH_LAUNCH(skelfac_kernel<T>, dim3(wgs), dim3(kSkelFacRows), skelfac_lds<T>(rmax), st, d, ndesc, rmax);
 }
 template <typename T>
 void launch_phase2(const Phase2Desc<T>* d, int ndesc, int maxrc, double eps, int* status, hipStream_t st) {

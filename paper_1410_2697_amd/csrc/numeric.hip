@@ -981,9 +981,9 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
     f.F = fx.F; f.ld = fx.ld; f.r0 = B.r0; f.nr = B.nr; f.c0 = B.c0; f.nc = B.nc;
     f.piv_r = x.pr; f.piv_c = x.pc; f.M = x.M; f.ldm = std::max(x.kcap, 1); f.rank = x.rank1;
     f.U = x.U; f.ldu = B.nr; f.V = x.V; f.ldv = B.nc;
-    f.wgU = cdiv(B.nr, 256);
+    f.wgU = cdiv(B.nr, kSkelFacRows);
     f.wg0 = wgs;
-    wgs += f.wgU + cdiv(B.nc, 256);
+    wgs += f.wgU + cdiv(B.nc, kSkelFacRows);
     sf.push_back(f);
     if (adaptive) {
       // E = B - U V^T in place (k = phase-1 rank, read on the device)
@@ -1026,7 +1026,7 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
     ++g.n;
   }
   for (size_t i = 0; i < p2c.size(); ++i) p2c[i].bar = bars + 64 * i;
-  if ((size_t)rmax1 * rmax1 * sizeof(T) > (size_t)kLdsMax)
+  if (skelfac_lds<T>(rmax1) > (size_t)kLdsMax)
     throw Err{MF_EINVAL, "phase-1 rank bound too large for LDS: lower bdlr_cap"};
   if (maxrc > kLdsMax) throw Err{MF_EINVAL, "block too large for the phase-2 kernel"};
   const size_t okf = b.add(skf), okh = b.add(skh), osf = b.add(sf), op2 = b.add(p2), op2c = b.add(p2c);

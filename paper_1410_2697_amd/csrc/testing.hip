@@ -93,8 +93,8 @@ mf_status skel_t(void* F, int ld, int r0, int nr, int c0, int nc, const int* I, 
   fd.F = static_cast<T*>(F); fd.ld = ld; fd.r0 = r0; fd.nr = nr; fd.c0 = c0; fd.nc = nc;
   fd.piv_r = pr; fd.piv_c = pc; fd.M = M; fd.ldm = sd.ldm; fd.rank = rank1;
   fd.U = static_cast<T*>(U); fd.ldu = nr; fd.V = static_cast<T*>(V); fd.ldv = nc;
-  fd.wgU = (nr + 255) / 256; fd.wg0 = 0;
-  const int wgs = fd.wgU + (nc + 255) / 256;
+  fd.wgU = (nr + mfh::kSkelFacRows - 1) / mfh::kSkelFacRows; fd.wg0 = 0;
+  const int wgs = fd.wgU + (nc + mfh::kSkelFacRows - 1) / mfh::kSkelFacRows;
   mfh::GemmDesc<T> gdsc{};
   gdsc.A = fd.U; gdsc.lda = nr; gdsc.B = fd.V; gdsc.ldb = nc; gdsc.opB = 1;
   gdsc.C = static_cast<T*>(F) + r0 + (size_t)c0 * ld; gdsc.ldc = ld;
