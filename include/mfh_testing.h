@@ -48,6 +48,13 @@ mf_status mfh_test_skeleton(int32_t precision, void* F, int32_t ld, int32_t r0, 
                             int32_t nc, const int32_t* I, int32_t nI, const int32_t* J, int32_t nJ, double eps,
                             int32_t adaptive, int32_t cap, void* U, void* V, int32_t* rank_out);
 
+/* In-place inverse of the n x n float64 matrix A (column-major, leading
+ * dimension lda >= n, 1 <= n <= 1024) by Gauss-Jordan elimination with
+ * partial pivoting: the kernel the capacitance inverse M = (I - A B)^{-1}
+ * of the SMW factorization (Sec. 3) runs on.  *status_out receives the
+ * kernel's status word (4: a zero pivot column). */
+mf_status mfh_test_inverse(int32_t n, double* A, int32_t lda, int32_t* status_out);
+
 #ifdef __cplusplus
 }
 #endif

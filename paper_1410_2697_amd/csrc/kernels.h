@@ -261,7 +261,9 @@ template <typename S, typename D>
 void launch_copy(const CopyDesc<S, D>* d, int ndesc, int tiles, hipStream_t st);
 template <typename T>
 void launch_cap(const CapDesc<T>* d, int ndesc, hipStream_t st);
-void launch_gj_inverse(const InvDesc* d, int ndesc, int* status, hipStream_t st);
+// kernel variant (a prof.h kind) for matrices up to nmax
+int gj_kind(int nmax);
+void launch_gj_inverse(const InvDesc* d, int ndesc, int nmax, int* status, hipStream_t st);
 template <typename T>
 void launch_fill(T* p, int64_t n, T v, hipStream_t st);
 template <typename T>

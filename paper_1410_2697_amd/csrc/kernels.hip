@@ -282,59 +282,6 @@ __global__ void mfma_probe_kernel(int* rows, int* cols, int* assumed) {
   }
 }
 
-// ------------------------------------------------------- small Cholesky ----
-// Right-looking Cholesky of the lower triangle held in LDS, fused with the
-// inverse X = L^{-1}: after column j of L is final, row j of X is divided by
-// L(j, j) and X(i, 0:j+1) -= L(i, j) X(j, 0:j+1) for i > j (forward
-// substitution of L X = I, one rank-1 step per column).  X's strictly lower
-// part is stored transposed in the unused upper triangle of the same LDS
-// array (X(i, k) at S[k + i LD], k < i) and its diagonal in xd.
-template <typename T, int NMAX, int NT>
-__global__ __launch_bounds__(NT) void potrf_kernel(const PotrfDesc<T>* __restrict__ descs, int* status) {
-  constexpr int LD = NMAX + 1, NW = NT / 64;
-  __shared__ T S[NMAX * LD];
-  __shared__ T xd[NMAX];
-  const PotrfDesc<T> d = descs[blockIdx.x];
-  const int n = d.n, tid = threadIdx.x;
-  const bool inv = d.Inv != nullptr;
-  for (int j = tid >> 6; j < n; j += NW)
-    for (int i = tid & 63; i < n; i += 64) S[i + j * LD] = i >= j ? d.A[i + (size_t)j * d.lda] : (T)0;
-  __syncthreads();
-  for (int j = 0; j < n; ++j) {
-    T djj = S[j + j * LD];
-    const bool bad = !(djj > (T)0);
-    if (bad) djj = (T)1;
-    const T ljj = sqrt(djj);
-    const T rinv = (T)1 / ljj;
-    __syncthreads();   // every thread has read L(j, j) before it is overwritten
-    if (tid == 0) {
-      S[j + j * LD] = ljj;
-      xd[j] = rinv;
-      if (bad) atomicOr(status, 1);
-    }
-    for (int i = j + 1 + tid; i < n; i += NT) S[i + j * LD] *= rinv;      // column j of L
-    if (inv)
-      for (int k = tid; k < j; k += NT) S[k + j * LD] *= rinv;            // row j of X
-    __syncthreads();
-    // trailing update of A and the rank-1 step of X, 32-lane groups per column / row
-    for (int c = j + 1 + (tid >> 5); c < n; c += NT / 32) {
-      const T lc = S[c + j * LD];
-      for (int r = c + (tid & 31); r < n; r += 32) S[r + c * LD] -= S[r + j * LD] * lc;
-      if (inv) {
-        // X(c, k) -= L(c, j) X(j, k), k <= j   (X(c, k) at S[k + c LD])
-        for (int k = tid & 31; k <= j; k += 32) S[k + c * LD] -= lc * (k == j ? xd[j] : S[k + j * LD]);
-      }
-    }
-    __syncthreads();
-  }
-  for (int j = tid >> 6; j < n; j += NW)
-    for (int i = j + (tid & 63); i < n; i += 64) d.A[i + (size_t)j * d.lda] = S[i + j * LD];
-  if (!inv) return;
-  for (int j = tid >> 6; j < n; j += NW)
-    for (int i = tid & 63; i < n; i += 64)
-      d.Inv[i + (size_t)j * d.ldi] = i > j ? S[j + i * LD] : (i == j ? xd[i] : (T)0);
-}
-
 // ------------------------------------------ register-resident skeleton ----
 // Pivot key: |v| truncated in the high word (FP64: 20 mantissa bits; FP32:
 // 16, which leaves room for a position inside one 32-bit word in the
@@ -414,6 +361,116 @@ __device__ __forceinline__ double uniform(double v) {
 __device__ __forceinline__ unsigned uniform(unsigned v) { return (unsigned)__builtin_amdgcn_readfirstlane((int)v); }
 __device__ __forceinline__ u64 uniform(u64 v) {
   return ((u64)uniform((unsigned)(v >> 32)) << 32) | uniform((unsigned)(v & 0xFFFFFFFFull));
+}
+
+// ------------------------------------------------------- small Cholesky ----
+// Leaf Cholesky A = L L^T with X = L^{-1} built in the same sweep (forward
+// substitution of L X = I, one rank-1 step per column of L), the
+// whole n x n block (n <= NMAX) in registers.  Thread t owns rows
+// a = (t & 63) + 64 i and columns b = (t >> 6) + CG j, like the skeleton
+// kernel below.  Step j: column j of A and row j of X go to LDS (double
+// buffered, so one barrier per step); every thread scales them by
+// 1 / sqrt(A(j, j)), subtracts l l^T from its trailing entries and
+// l X(j, :) from its rows of X, and the owners store column j of L and
+// row j of X.  A non-positive pivot sets status bit 1 and continues with 1.
+template <typename T, int NMAX, int NT>
+__global__ __launch_bounds__(NT) void potrf_kernel(const PotrfDesc<T>* __restrict__ descs, int* status) {
+  constexpr int RI = NMAX / 64, CG = NT / 64, CJ = NMAX / CG;
+  static_assert(RI * 64 == NMAX && CJ * CG == NMAX, "square register block");
+  __shared__ T s_col[2][NMAX];
+  __shared__ __align__(16) T s_xr[2][CG][CJ];
+  const PotrfDesc<T> d = descs[blockIdx.x];
+  const int n = d.n, t = threadIdx.x, lane = t & 63;
+  const int g = (int)uniform((unsigned)(t >> 6));
+  const bool inv = d.Inv != nullptr;
+  T e[RI][CJ], x[RI][CJ];
+#pragma unroll
+  for (int i = 0; i < RI; ++i)
+#pragma unroll
+    for (int jj = 0; jj < CJ; ++jj) {
+      const int a = lane + 64 * i, b = g + CG * jj;
+      e[i][jj] = (a < n && b < n && a >= b) ? d.A[a + (size_t)b * d.lda] : (T)0;
+      x[i][jj] = (a == b) ? (T)1 : (T)0;
+    }
+  bool bad = false;
+  for (int j = 0; j < n; ++j) {
+    const int p = j & 1, gj = j % CG, jc = j / CG, lj = j & 63, ir = j >> 6;
+    if (g == gj) {
+#pragma unroll
+      for (int jj = 0; jj < CJ; ++jj)
+        if (jj == jc) {
+#pragma unroll
+          for (int i = 0; i < RI; ++i) s_col[p][lane + 64 * i] = e[i][jj];
+        }
+    }
+    if (inv && lane == lj) {
+#pragma unroll
+      for (int i = 0; i < RI; ++i)
+        if (i == ir) {
+#pragma unroll
+          for (int jj = 0; jj < CJ; ++jj) s_xr[p][g][jj] = x[i][jj];
+        }
+    }
+    __syncthreads();
+    T djj = uniform(s_col[p][j]);
+    if (!(djj > (T)0)) {
+      bad = true;
+      djj = (T)1;
+    }
+    const T ljj = sqrt(djj);
+    const T rinv = (T)1 / ljj;
+    T la[RI];
+#pragma unroll
+    for (int i = 0; i < RI; ++i) {
+      const int a = lane + 64 * i;
+      la[i] = a > j ? s_col[p][a] * rinv : (T)0;
+    }
+#pragma unroll
+    for (int jj = 0; jj < CJ; ++jj) {
+      const int b = g + CG * jj;
+      const T lb = b > j ? s_col[p][b] * rinv : (T)0;
+#pragma unroll
+      for (int i = 0; i < RI; ++i) e[i][jj] -= la[i] * lb;
+    }
+    if (g == gj) {
+#pragma unroll
+      for (int jj = 0; jj < CJ; ++jj)
+        if (jj == jc) {
+#pragma unroll
+          for (int i = 0; i < RI; ++i) {
+            const int a = lane + 64 * i;
+            if (a == j) e[i][jj] = ljj;
+            else if (a > j) e[i][jj] = la[i];
+          }
+        }
+    }
+    if (inv) {
+#pragma unroll
+      for (int jj = 0; jj < CJ; ++jj) {
+        const T xj = s_xr[p][g][jj] * rinv;
+#pragma unroll
+        for (int i = 0; i < RI; ++i) x[i][jj] -= la[i] * xj;
+      }
+      if (lane == lj) {
+#pragma unroll
+        for (int i = 0; i < RI; ++i)
+          if (i == ir) {
+#pragma unroll
+            for (int jj = 0; jj < CJ; ++jj) x[i][jj] = s_xr[p][g][jj] * rinv;
+          }
+      }
+    }
+  }
+  if (bad && t == 0) atomicOr(status, 1);
+#pragma unroll
+  for (int i = 0; i < RI; ++i)
+#pragma unroll
+    for (int jj = 0; jj < CJ; ++jj) {
+      const int a = lane + 64 * i, b = g + CG * jj;
+      if (a >= n || b >= n) continue;
+      if (a >= b) d.A[a + (size_t)b * d.lda] = e[i][jj];
+      if (inv) d.Inv[a + (size_t)b * d.ldi] = a >= b ? x[i][jj] : (T)0;
+    }
 }
 
 // Thread t owns rows a = (t & 63) + 64 i (i < RI) and columns
@@ -1051,8 +1108,9 @@ __global__ __launch_bounds__(256) void cap_kernel(const CapDesc<T>* __restrict__
 // rows k and p, turns column k into the k-th unit column while the inverse
 // builds up in its place, and the recorded row interchanges are undone as
 // column interchanges in reverse order at the end.  One workgroup per
-// matrix; a zero pivot column sets status bit 4.
-__global__ __launch_bounds__(1024) void gj_kernel(const InvDesc* __restrict__ descs, int* status) {
+// matrix; a zero pivot column sets status bit 4.  Used for n above the
+// register kernel's limit.
+__global__ __launch_bounds__(1024) void gj_wide_kernel(const InvDesc* __restrict__ descs, int* status) {
   __shared__ double f[kInvMax];
   __shared__ double rowk[kInvMax];
   __shared__ int perm[kInvMax];
@@ -1106,6 +1164,113 @@ __global__ __launch_bounds__(1024) void gj_kernel(const InvDesc* __restrict__ de
       }
     __syncthreads();
   }
+}
+
+// The same elimination with the whole matrix in registers (n <= RI * 64):
+// thread t owns rows a = (t & 63) + 64 i and columns b = (t >> 6) + CG j.
+// Rows are not moved.  Step k: the wave owning column k picks the pivot row
+// p among the rows not yet used (largest |A(i,k)|, lowest i on ties) and
+// puts column k in LDS (barrier); each wave puts its part of row p in LDS
+// (barrier); then row p becomes (A(p,:) with 1 at k) / A(p,k) and every other
+// row i becomes (A(i,:) with 0 at k) - A(i,k) row p.  With p_k the pivot row
+// of step k, the result B gives the inverse as inv(k, p_j) = B(p_k, j), which
+// is how it is written back.
+template <int RI, int CJ, int NT>
+__global__ __launch_bounds__(NT) void gj_kernel(const InvDesc* __restrict__ descs, int* status) {
+  constexpr int NMAX = RI * 64, CG = NT / 64;
+  static_assert(CJ * CG >= NMAX && RI * CJ <= 64, "register block");
+  __shared__ double s_col[2][NMAX];
+  __shared__ int s_piv[2];
+  __shared__ __align__(16) double s_row[CG][CJ];
+  __shared__ short s_rstep[NMAX], s_prow[CJ * CG];
+  const InvDesc d = descs[blockIdx.x];
+  const int n = d.n, t = threadIdx.x, lane = t & 63;
+  const int g = (int)uniform((unsigned)(t >> 6));
+  double e[RI][CJ];
+  unsigned rl = 0;
+#pragma unroll
+  for (int i = 0; i < RI; ++i) {
+    const int a = lane + 64 * i;
+    if (a < n) rl |= 1u << i;
+#pragma unroll
+    for (int j = 0; j < CJ; ++j) {
+      const int b = g + CG * j;
+      e[i][j] = (a < n && b < n) ? d.A[a + (size_t)b * d.ld] : 0.0;
+    }
+  }
+  bool singular = false;
+  for (int k = 0; k < n; ++k) {
+    const int p = k & 1, gk = k % CG, jk = k / CG;
+    if (g == gk) {
+      double cv[RI];
+#pragma unroll
+      for (int j = 0; j < CJ; ++j)
+        if (j == jk) {
+#pragma unroll
+          for (int i = 0; i < RI; ++i) cv[i] = e[i][j];
+        }
+      // thread best: largest magnitude among its live rows, lowest i first
+      u64 bk = 0;
+      unsigned bi = 0;
+#pragma unroll
+      for (int i = 0; i < RI; ++i) {
+        const u64 kv = ((rl >> i) & 1u) ? (u64)__double_as_longlong(fabs(cv[i])) + 1ull : 0ull;
+        if (kv > bk) { bk = kv; bi = (unsigned)i; }
+      }
+      const unsigned hi = wave_ext_u32<true>((unsigned)(bk >> 32));
+      const unsigned lo = wave_ext_u32<true>((unsigned)(bk >> 32) == hi ? (unsigned)(bk & 0xFFFFFFFFull) : 0u);
+      const u64 m = ((u64)hi << 32) | lo;
+      const unsigned w = wave_ext_u32<false>(bk == m ? (bi << 6) | (unsigned)lane : 0xFFFFFFFFu);
+#pragma unroll
+      for (int i = 0; i < RI; ++i) s_col[p][lane + 64 * i] = cv[i];
+      if (lane == 0) s_piv[p] = (int)((w & 63u) + 64u * (w >> 6));
+    }
+    __syncthreads();
+    const int pr = (int)uniform((unsigned)s_piv[p]);
+    const int ip = pr >> 6;
+    double piv = uniform(s_col[p][pr]);
+    if (!(fabs(piv) > 0.0)) {
+      singular = true;
+      piv = 1.0;
+    }
+    const double inv = 1.0 / piv;
+    if (lane == (pr & 63)) {
+#pragma unroll
+      for (int i = 0; i < RI; ++i)
+        if (i == ip) {
+#pragma unroll
+          for (int j = 0; j < CJ; ++j) s_row[g][j] = e[i][j];
+        }
+    }
+    if (t == 0) { s_rstep[pr] = (short)k; s_prow[k] = (short)pr; }
+    __syncthreads();
+    double f[RI];
+#pragma unroll
+    for (int i = 0; i < RI; ++i) f[i] = (lane + 64 * i) == pr ? 0.0 : s_col[p][lane + 64 * i];
+    const bool prow_lane = lane == (pr & 63);
+#pragma unroll
+    for (int j = 0; j < CJ; ++j) {
+      const bool colk = (g + CG * j) == k;
+      const double Rj = (colk ? 1.0 : s_row[g][j]) * inv;
+#pragma unroll
+      for (int i = 0; i < RI; ++i) e[i][j] = (colk ? 0.0 : e[i][j]) - f[i] * Rj;
+      if (prow_lane) {
+#pragma unroll
+        for (int i = 0; i < RI; ++i)
+          if (i == ip) e[i][j] = Rj;
+      }
+    }
+    if (prow_lane) rl &= ~(1u << ip);
+  }
+  if (singular && t == 0) atomicOr(status, 4);
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < RI; ++i)
+#pragma unroll
+    for (int j = 0; j < CJ; ++j) {
+      const int a = lane + 64 * i, b = g + CG * j;
+      if (a < n && b < n) d.A[s_rstep[a] + (size_t)s_prow[b] * d.ld] = e[i][j];
+    }
 }
 
 // --------------------------------------------------------- misc vectors ----
@@ -1383,9 +1548,17 @@ void launch_cap(const CapDesc<T>* d, int ndesc, hipStream_t st) {
   if (ndesc <= 0) return;
   MFH_LAUNCH(cap_kernel<T>, dim3(ndesc), dim3(256), 0, st, d);
 }
-void launch_gj_inverse(const InvDesc* d, int ndesc, int* status, hipStream_t st) {
+int gj_kind(int nmax) {
+  return nmax <= 64 ? PK_GJ64 : nmax <= 128 ? PK_GJ128 : nmax <= 192 ? PK_GJ192 : PK_GJWIDE;
+}
+void launch_gj_inverse(const InvDesc* d, int ndesc, int nmax, int* status, hipStream_t st) {
   if (ndesc <= 0) return;
-  MFH_LAUNCH(gj_kernel, dim3(ndesc), dim3(1024), 0, st, d, status);
+  switch (gj_kind(nmax)) {
+    case PK_GJ64: MFH_LAUNCH((gj_kernel<1, 16, 256>), dim3(ndesc), dim3(256), 0, st, d, status); break;
+    case PK_GJ128: MFH_LAUNCH((gj_kernel<2, 16, 512>), dim3(ndesc), dim3(512), 0, st, d, status); break;
+    case PK_GJ192: MFH_LAUNCH((gj_kernel<3, 12, 1024>), dim3(ndesc), dim3(1024), 0, st, d, status); break;
+    default: MFH_LAUNCH(gj_wide_kernel, dim3(ndesc), dim3(1024), 0, st, d, status); break;
+  }
 }
 template <typename T>
 void launch_fill(T* p, int64_t n, T v, hipStream_t st) {

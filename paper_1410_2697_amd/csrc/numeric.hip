@@ -1333,12 +1333,15 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
     gM.launch(base3, st);
     {
       double fl = 0, by = 0;     // in-place Gauss-Jordan: n steps of an n x n rank-1 update
+      int nmax = 0;
       for (const auto& d : invd) {
         fl += 2.0 * d.n * (double)d.n * d.n;
         by += 8.0 * 2.0 * d.n * (double)d.n;
+        nmax = std::max(nmax, d.n);
       }
-      const int id = prof_begin(PK_GJ, st, fl, by);
-      launch_gj_inverse(reinterpret_cast<const InvDesc*>(base3 + oinv), (int)invd.size(), d_status.as<int>(), st);
+      const int id = prof_begin(gj_kind(nmax), st, fl, by);
+      launch_gj_inverse(reinterpret_cast<const InvDesc*>(base3 + oinv), (int)invd.size(), nmax, d_status.as<int>(),
+                        st);
       prof_end(id, st);
     }
     gX1.launch(base3, st);

@@ -26,7 +26,7 @@ enum ProfKind : int {
   PK_PHASE2CL_F64, PK_PHASE2CL_F32,    // multi-workgroup phase 2, slices in LDS
   PK_PHASE2CG_F64, PK_PHASE2CG_F32,    // multi-workgroup phase 2, in place
   PK_EXTADD_F64, PK_EXTADD_F32,
-  PK_GJ,
+  PK_GJ64, PK_GJ128, PK_GJ192, PK_GJWIDE,   // capacitance inverse by matrix size
   PK_SPMV,
   PK_COUNT
 };

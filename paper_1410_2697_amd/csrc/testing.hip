@@ -204,6 +204,25 @@ mf_status mfh_test_potrf(int32_t precision, int32_t n, void* A, int32_t lda, voi
   return potrf_t<float>(n, A, lda, Inv, ldi, status_out);
 }
 
+mf_status mfh_test_inverse(int32_t n, double* A, int32_t lda, int32_t* status_out) {
+  if (n < 1 || n > mfh::kInvMax || lda < n || !A) return MF_EINVAL;
+  mfh::InvDesc d{};
+  d.A = A; d.n = n; d.ld = lda;
+  mfh::InvDesc* dd = nullptr;
+  int* st = nullptr;
+  mf_status s = hip_ok(hipMalloc(&dd, sizeof(d)));
+  if (s == MF_OK) s = hip_ok(hipMalloc(&st, sizeof(int)));
+  if (s != MF_OK) { hipFree(dd); return s; }
+  hipMemcpy(dd, &d, sizeof(d), hipMemcpyHostToDevice);
+  hipMemset(st, 0, sizeof(int));
+  mfh::launch_gj_inverse(dd, 1, n, st, nullptr);
+  s = hip_ok(hipDeviceSynchronize());
+  if (s == MF_OK && status_out) hipMemcpy(status_out, st, sizeof(int), hipMemcpyDeviceToHost);
+  hipFree(dd);
+  hipFree(st);
+  return s;
+}
+
 mf_status mfh_test_skeleton(int32_t precision, void* F, int32_t ld, int32_t r0, int32_t nr, int32_t c0, int32_t nc,
                             const int32_t* I, int32_t nI, const int32_t* J, int32_t nJ, double eps, int32_t adaptive,
                             int32_t cap, void* U, void* V, int32_t* rank_out) {

@@ -1,6 +1,6 @@
-"""Kernel-level parity on the GPU: grouped MFMA GEMM, LDS Cholesky + inverse,
-and the skeleton compression against plain float64 references / the
-oracle."""
+"""Kernel-level parity on the GPU: grouped MFMA GEMM, register Cholesky +
+inverse, the Gauss-Jordan inverse, and the skeleton compression against
+plain float64 references / the oracle."""
 import ctypes
 
 import numpy as np
@@ -97,7 +97,7 @@ def test_gemm(gpu_lib, prec, m, n, k, opA, opB, flags, kchunk):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("n", [1, 7, 64, 100, 128])
+@pytest.mark.parametrize("n", [1, 7, 63, 64, 65, 100, 127, 128])
 def test_potrf_inverse(gpu_lib, prec, n):
     import torch
     mfh = gpu_lib
@@ -118,6 +118,41 @@ def test_potrf_inverse(gpu_lib, prec, n):
     Inv = _host(dI, n)
     assert np.abs(np.triu(Inv, 1)).max() == 0.0
     assert np.abs(Inv @ Lref - np.eye(n)).max() <= tol * 10
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 63, 64, 65, 100, 128, 129, 191, 192, 193, 300])
+def test_gauss_jordan_inverse(gpu_lib, n):
+    """In-place inverse of M = I - A B (the capacitance matrix's shape) and of
+    a row-permuted I + A, whose large entries sit off the diagonal so the
+    steps must pivot: equal to numpy's inverse within the conditioning bound,
+    in every size class of the kernel (one register block per size up to
+    192, the streamed kernel above)."""
+    import torch
+    rng = np.random.default_rng(100 + n)
+    A = rng.standard_normal((n, n)) * 0.3 / np.sqrt(n)
+    B = rng.standard_normal((n, n)) * 0.3 / np.sqrt(n)
+    P = np.eye(n)[rng.permutation(n)]
+    for M in (np.eye(n) - A @ B, P @ (np.eye(n) + A)):
+        ld = n + 3
+        dM = _dev(M, ld, torch.float64)
+        status = ctypes.c_int32(-1)
+        assert gpu_lib.load().mfh_test_inverse(n, _p(dM), ld, ctypes.byref(status)) == 0
+        assert status.value == 0
+        X = _host(dM, n)
+        ref = np.linalg.inv(M)
+        kappa = np.linalg.cond(M)
+        assert np.abs(X - ref).max() <= 1e-14 * kappa * n * max(1.0, np.abs(ref).max())
+
+
+def test_gauss_jordan_flags_singular(gpu_lib):
+    import torch
+    n = 40
+    M = np.random.default_rng(3).standard_normal((n, n))
+    M[:, 5] = 0.0
+    dM = _dev(M, n, torch.float64)
+    status = ctypes.c_int32(0)
+    assert gpu_lib.load().mfh_test_inverse(n, _p(dM), n, ctypes.byref(status)) == 0
+    assert status.value & 4
 
 
 def test_potrf_flags_non_spd(gpu_lib):
