@@ -363,6 +363,13 @@ __device__ __forceinline__ u64 uniform(u64 v) {
   return ((u64)uniform((unsigned)(v >> 32)) << 32) | uniform((unsigned)(v & 0xFFFFFFFFull));
 }
 
+// One row of a register block as a vector: a wave-uniform index selects an
+// element with one indexed register move (no branch over the columns).
+template <typename T, int N>
+struct RegRow {
+  typedef T type __attribute__((ext_vector_type(N)));
+};
+
 // ------------------------------------------------------- small Cholesky ----
 // Leaf Cholesky A = L L^T with X = L^{-1} built in the same sweep (forward
 // substitution of L X = I, one rank-1 step per column of L), the
@@ -377,13 +384,15 @@ template <typename T, int NMAX, int NT>
 __global__ __launch_bounds__(NT) void potrf_kernel(const PotrfDesc<T>* __restrict__ descs, int* status) {
   constexpr int RI = NMAX / 64, CG = NT / 64, CJ = NMAX / CG;
   static_assert(RI * 64 == NMAX && CJ * CG == NMAX, "square register block");
+  typedef typename RegRow<T, CJ>::type row_t;
   __shared__ T s_col[2][NMAX];
   __shared__ __align__(16) T s_xr[2][CG][CJ];
+  __shared__ T s_rinv[NMAX];
   const PotrfDesc<T> d = descs[blockIdx.x];
   const int n = d.n, t = threadIdx.x, lane = t & 63;
   const int g = (int)uniform((unsigned)(t >> 6));
   const bool inv = d.Inv != nullptr;
-  T e[RI][CJ], x[RI][CJ];
+  row_t e[RI], x[RI];
 #pragma unroll
   for (int i = 0; i < RI; ++i)
 #pragma unroll
@@ -397,18 +406,16 @@ __global__ __launch_bounds__(NT) void potrf_kernel(const PotrfDesc<T>* __restric
     const int p = j & 1, gj = j % CG, jc = j / CG, lj = j & 63, ir = j >> 6;
     if (g == gj) {
 #pragma unroll
-      for (int jj = 0; jj < CJ; ++jj)
-        if (jj == jc) {
-#pragma unroll
-          for (int i = 0; i < RI; ++i) s_col[p][lane + 64 * i] = e[i][jj];
-        }
+      for (int i = 0; i < RI; ++i) s_col[p][lane + 64 * i] = e[i][jc];
     }
-    if (inv && lane == lj) {
+    if (inv) {
 #pragma unroll
       for (int i = 0; i < RI; ++i)
         if (i == ir) {
+          if (lane == lj) {
 #pragma unroll
-          for (int jj = 0; jj < CJ; ++jj) s_xr[p][g][jj] = x[i][jj];
+            for (int jj = 0; jj < CJ; ++jj) s_xr[p][g][jj] = x[i][jj];
+          }
         }
     }
     __syncthreads();
@@ -419,48 +426,42 @@ __global__ __launch_bounds__(NT) void potrf_kernel(const PotrfDesc<T>* __restric
     }
     const T ljj = sqrt(djj);
     const T rinv = (T)1 / ljj;
+    // loads first, then selects (a conditional load per column would
+    // serialise the LDS round trips)
     T la[RI];
 #pragma unroll
     for (int i = 0; i < RI; ++i) {
       const int a = lane + 64 * i;
-      la[i] = a > j ? s_col[p][a] * rinv : (T)0;
+      const T v = s_col[p][a];
+      la[i] = a > j ? v * rinv : (T)0;
     }
+    row_t lb;
 #pragma unroll
-    for (int jj = 0; jj < CJ; ++jj) {
-      const int b = g + CG * jj;
-      const T lb = b > j ? s_col[p][b] * rinv : (T)0;
+    for (int jj = 0; jj < CJ; ++jj) lb[jj] = s_col[p][g + CG * jj];
 #pragma unroll
-      for (int i = 0; i < RI; ++i) e[i][jj] -= la[i] * lb;
-    }
+    for (int jj = 0; jj < CJ; ++jj) lb[jj] = (g + CG * jj) > j ? lb[jj] * rinv : (T)0;
+#pragma unroll
+    for (int i = 0; i < RI; ++i) e[i] -= la[i] * lb;
     if (g == gj) {
 #pragma unroll
-      for (int jj = 0; jj < CJ; ++jj)
-        if (jj == jc) {
-#pragma unroll
-          for (int i = 0; i < RI; ++i) {
-            const int a = lane + 64 * i;
-            if (a == j) e[i][jj] = ljj;
-            else if (a > j) e[i][jj] = la[i];
-          }
-        }
+      for (int i = 0; i < RI; ++i) {
+        const int a = lane + 64 * i;
+        const T v = e[i][jc];
+        e[i][jc] = a == j ? ljj : (a > j ? la[i] : v);
+      }
     }
     if (inv) {
+      // row j of X is final once scaled by rinv; it stays unscaled in
+      // registers (no later step changes it) and is scaled at the end
+      row_t xj;
 #pragma unroll
-      for (int jj = 0; jj < CJ; ++jj) {
-        const T xj = s_xr[p][g][jj] * rinv;
+      for (int jj = 0; jj < CJ; ++jj) xj[jj] = s_xr[p][g][jj] * rinv;
 #pragma unroll
-        for (int i = 0; i < RI; ++i) x[i][jj] -= la[i] * xj;
-      }
-      if (lane == lj) {
-#pragma unroll
-        for (int i = 0; i < RI; ++i)
-          if (i == ir) {
-#pragma unroll
-            for (int jj = 0; jj < CJ; ++jj) x[i][jj] = s_xr[p][g][jj] * rinv;
-          }
-      }
+      for (int i = 0; i < RI; ++i) x[i] -= la[i] * xj;
+      if (t == 0) s_rinv[j] = rinv;
     }
   }
+  __syncthreads();
   if (bad && t == 0) atomicOr(status, 1);
 #pragma unroll
   for (int i = 0; i < RI; ++i)
@@ -469,7 +470,7 @@ __global__ __launch_bounds__(NT) void potrf_kernel(const PotrfDesc<T>* __restric
       const int a = lane + 64 * i, b = g + CG * jj;
       if (a >= n || b >= n) continue;
       if (a >= b) d.A[a + (size_t)b * d.lda] = e[i][jj];
-      if (inv) d.Inv[a + (size_t)b * d.ldi] = a >= b ? x[i][jj] : (T)0;
+      if (inv) d.Inv[a + (size_t)b * d.ldi] = a >= b ? x[i][jj] * s_rinv[a] : (T)0;
     }
 }
 
@@ -482,6 +483,7 @@ __global__ __launch_bounds__(NT) void skreg_kernel(const SkRegDesc<T>* __restric
                                                      int adaptive, int* status) {
   constexpr int CG = NT / 64, MR = RI * 64, MC = CJ * CG;
   static_assert(RI * CJ <= 128 && MR < 65536 && MC < 65536, "register block too large");
+  typedef typename RegRow<T, CJ>::type row_t;
   constexpr unsigned kMag = sizeof(T) == 4 ? 0x7FFFFF80u : 0x7FFFFFFFu;
   __shared__ __align__(16) T s_row[CG][CJ];     // pivot row, by (column group, j)
   __shared__ T s_col[MR];
@@ -494,7 +496,7 @@ __global__ __launch_bounds__(NT) void skreg_kernel(const SkRegDesc<T>* __restric
   const int t = threadIdx.x, lane = t & 63;
   const int g = (int)uniform((unsigned)(t >> 6));
   const int M = FULL ? d.nr : d.nI, N = FULL ? d.nc : d.nJ;
-  T e[RI][CJ];
+  row_t e[RI];
   unsigned rl = 0, cl = 0, inI = 0, inJ = 0;
 #pragma unroll
   for (int i = 0; i < RI; ++i)
@@ -620,21 +622,19 @@ __global__ __launch_bounds__(NT) void skreg_kernel(const SkRegDesc<T>* __restric
       const unsigned pos = 0xFFFFFFFFu - (unsigned)(K & 0xFFFFFFFFull);
       const int as = (int)(pos & 0xFFFFu), bs = (int)(pos >> 16);
       const int ia = as >> 6, gb = bs % CG, jb = bs / CG;
-      if (lane == (as & 63)) {
+      // row choice by a uniform branch, lane choice inside it: a select
+      // over whole rows would cost every wave RI x CJ moves
 #pragma unroll
-        for (int i = 0; i < RI; ++i)
-          if (i == ia) {
+      for (int i = 0; i < RI; ++i)
+        if (i == ia) {
+          if (lane == (as & 63)) {
 #pragma unroll
             for (int j = 0; j < CJ; ++j) s_row[g][j] = (FULL || ((cl >> j) & 1u)) ? e[i][j] : (T)0;
           }
-      }
+        }
       if (g == gb) {
 #pragma unroll
-        for (int j = 0; j < CJ; ++j)
-          if (j == jb) {
-#pragma unroll
-            for (int i = 0; i < RI; ++i) s_col[lane + 64 * i] = e[i][j];
-          }
+        for (int i = 0; i < RI; ++i) s_col[lane + 64 * i] = e[i][jb];
       }
       __syncthreads();
       const T piv = uniform(s_row[gb][jb]);
@@ -656,15 +656,11 @@ __global__ __launch_bounds__(NT) void skreg_kernel(const SkRegDesc<T>* __restric
         for (int a = t; a < M; a += NT) gstore(Uc + a, phase == 1 ? s_col[a] / piv : s_col[a]);
         for (int b = t; b < N; b += NT)
           gstore(Vc + b, phase == 1 ? s_row[b % CG][b / CG] : s_row[b % CG][b / CG] / piv);
-        T li[RI];
+        row_t u;
 #pragma unroll
-        for (int i = 0; i < RI; ++i) li[i] = s_col[lane + 64 * i] * rpiv;
+        for (int j = 0; j < CJ; ++j) u[j] = s_row[g][j];
 #pragma unroll
-        for (int j = 0; j < CJ; ++j) {
-          const T uj = s_row[g][j];
-#pragma unroll
-          for (int i = 0; i < RI; ++i) e[i][j] -= li[i] * uj;
-        }
+        for (int i = 0; i < RI; ++i) e[i] -= (s_col[lane + 64 * i] * rpiv) * u;
       } else {
         // in-place LU of B_hat: live rows other than the pivot row take the
         // update (the pivot row broadcast holds zeros in dead columns, and
@@ -676,23 +672,21 @@ __global__ __launch_bounds__(NT) void skreg_kernel(const SkRegDesc<T>* __restric
         for (int i = 0; i < RI; ++i) {
           const int a = lane + 64 * i;
           const bool u = ((rl >> i) & 1u) && a != as;
-          li[i] = u ? s_col[a] * rpiv : (T)0;
+          const T v = s_col[a];
+          li[i] = u ? v * rpiv : (T)0;
           if (u) upd |= 1u << i;
         }
+        row_t u;
 #pragma unroll
-        for (int j = 0; j < CJ; ++j) {
-          const T uj = s_row[g][j];
+        for (int j = 0; j < CJ; ++j) u[j] = s_row[g][j];
 #pragma unroll
-          for (int i = 0; i < RI; ++i) e[i][j] -= li[i] * uj;
-        }
+        for (int i = 0; i < RI; ++i) e[i] -= li[i] * u;
         if (g == gb) {
 #pragma unroll
-          for (int j = 0; j < CJ; ++j)
-            if (j == jb) {
-#pragma unroll
-              for (int i = 0; i < RI; ++i)
-                if ((upd >> i) & 1u) e[i][j] = li[i];
-            }
+          for (int i = 0; i < RI; ++i) {
+            const T v = e[i][jb];
+            e[i][jb] = ((upd >> i) & 1u) ? li[i] : v;
+          }
         }
         if (t == 0) { s_rstep[as] = (short)r; s_cstep[bs] = (short)r; }
       }
@@ -1179,6 +1173,7 @@ template <int RI, int CJ, int NT>
 __global__ __launch_bounds__(NT) void gj_kernel(const InvDesc* __restrict__ descs, int* status) {
   constexpr int NMAX = RI * 64, CG = NT / 64;
   static_assert(CJ * CG >= NMAX && RI * CJ <= 64, "register block");
+  typedef typename RegRow<double, CJ>::type row_t;
   __shared__ double s_col[2][NMAX];
   __shared__ int s_piv[2];
   __shared__ __align__(16) double s_row[CG][CJ];
@@ -1186,7 +1181,7 @@ __global__ __launch_bounds__(NT) void gj_kernel(const InvDesc* __restrict__ desc
   const InvDesc d = descs[blockIdx.x];
   const int n = d.n, t = threadIdx.x, lane = t & 63;
   const int g = (int)uniform((unsigned)(t >> 6));
-  double e[RI][CJ];
+  row_t e[RI];
   unsigned rl = 0;
 #pragma unroll
   for (int i = 0; i < RI; ++i) {
@@ -1204,11 +1199,7 @@ __global__ __launch_bounds__(NT) void gj_kernel(const InvDesc* __restrict__ desc
     if (g == gk) {
       double cv[RI];
 #pragma unroll
-      for (int j = 0; j < CJ; ++j)
-        if (j == jk) {
-#pragma unroll
-          for (int i = 0; i < RI; ++i) cv[i] = e[i][j];
-        }
+      for (int i = 0; i < RI; ++i) cv[i] = e[i][jk];
       // thread best: largest magnitude among its live rows, lowest i first
       u64 bk = 0;
       unsigned bi = 0;
@@ -1234,32 +1225,41 @@ __global__ __launch_bounds__(NT) void gj_kernel(const InvDesc* __restrict__ desc
       piv = 1.0;
     }
     const double inv = 1.0 / piv;
-    if (lane == (pr & 63)) {
+    const bool prow_lane = lane == (pr & 63);
 #pragma unroll
-      for (int i = 0; i < RI; ++i)
-        if (i == ip) {
+    for (int i = 0; i < RI; ++i)
+      if (i == ip) {
+        if (prow_lane) {
 #pragma unroll
           for (int j = 0; j < CJ; ++j) s_row[g][j] = e[i][j];
         }
-    }
+      }
     if (t == 0) { s_rstep[pr] = (short)k; s_prow[k] = (short)pr; }
     __syncthreads();
+    // R = (row p with 1 at k) / piv; f = column k with 0 at row p
+    row_t R;
+#pragma unroll
+    for (int j = 0; j < CJ; ++j) R[j] = s_row[g][j];
+    if (g == gk) R[jk] = 1.0;
+    R *= inv;
     double f[RI];
 #pragma unroll
-    for (int i = 0; i < RI; ++i) f[i] = (lane + 64 * i) == pr ? 0.0 : s_col[p][lane + 64 * i];
-    const bool prow_lane = lane == (pr & 63);
-#pragma unroll
-    for (int j = 0; j < CJ; ++j) {
-      const bool colk = (g + CG * j) == k;
-      const double Rj = (colk ? 1.0 : s_row[g][j]) * inv;
-#pragma unroll
-      for (int i = 0; i < RI; ++i) e[i][j] = (colk ? 0.0 : e[i][j]) - f[i] * Rj;
-      if (prow_lane) {
-#pragma unroll
-        for (int i = 0; i < RI; ++i)
-          if (i == ip) e[i][j] = Rj;
-      }
+    for (int i = 0; i < RI; ++i) {
+      const double v = s_col[p][lane + 64 * i];
+      f[i] = (lane + 64 * i) == pr ? 0.0 : v;
     }
+#pragma unroll
+    for (int i = 0; i < RI; ++i) e[i] -= f[i] * R;
+    if (g == gk) {
+      // column k: (0) - f R(k)
+#pragma unroll
+      for (int i = 0; i < RI; ++i) e[i][jk] = 0.0 - f[i] * R[jk];
+    }
+#pragma unroll
+    for (int i = 0; i < RI; ++i)
+      if (i == ip) {
+        if (prow_lane) e[i] = R;
+      }
     if (prow_lane) rl &= ~(1u << ip);
   }
   if (singular && t == 0) atomicOr(status, 4);
@@ -1556,7 +1556,7 @@ void launch_gj_inverse(const InvDesc* d, int ndesc, int nmax, int* status, hipSt
   switch (gj_kind(nmax)) {
     case PK_GJ64: MFH_LAUNCH((gj_kernel<1, 16, 256>), dim3(ndesc), dim3(256), 0, st, d, status); break;
     case PK_GJ128: MFH_LAUNCH((gj_kernel<2, 16, 512>), dim3(ndesc), dim3(512), 0, st, d, status); break;
-    case PK_GJ192: MFH_LAUNCH((gj_kernel<3, 12, 1024>), dim3(ndesc), dim3(1024), 0, st, d, status); break;
+    case PK_GJ192: MFH_LAUNCH((gj_kernel<3, 16, 768>), dim3(ndesc), dim3(768), 0, st, d, status); break;
     default: MFH_LAUNCH(gj_wide_kernel, dim3(ndesc), dim3(1024), 0, st, d, status); break;
   }
 }

@@ -20,7 +20,7 @@ const char* const kNames[PK_COUNT] = {
     "phase2_coop_kernel<double, true>", "phase2_coop_kernel<float, true>",
     "phase2_coop_kernel<double, false>", "phase2_coop_kernel<float, false>",
     "extadd_kernel<double>",      "extadd_kernel<float>",
-    "gj_kernel<1, 16, 256>", "gj_kernel<2, 16, 512>", "gj_kernel<3, 12, 1024>", "gj_wide_kernel",
+    "gj_kernel<1, 16, 256>", "gj_kernel<2, 16, 512>", "gj_kernel<3, 16, 768>", "gj_wide_kernel",
     "spmv_kernel",
 };
 
