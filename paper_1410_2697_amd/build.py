@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmfh.so")
-SOURCES = ["symbolic.cpp", "prof.cpp", "server.cpp", "api.cpp", "kernels.hip", "numeric.hip", "testing.hip"]
+SOURCES = ["hostpool.cpp", "symbolic.cpp", "prof.cpp", "server.cpp", "api.cpp", "kernels.hip", "numeric.hip", "testing.hip"]
 
 
 def hipcc() -> str:

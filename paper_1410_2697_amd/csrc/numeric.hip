@@ -27,6 +27,7 @@
 #include <mutex>
 #include <thread>
 
+#include "hostpool.h"
 #include "numeric.h"
 #include "prof.h"
 
@@ -463,7 +464,7 @@ class Numeric : public NumericBase {
   std::vector<int> bd_order;      // HODLR fronts, level by level
   std::vector<int> bd_left;       // fronts of each level still to do
   std::atomic<int> bd_next{0};
-  std::vector<std::thread> workers;
+  TaskGroup workers;                 // BDLR tasks on the host pool
   std::mutex mu;
   std::condition_variable cv;
   int lvb_ready = 0;
@@ -556,19 +557,21 @@ Numeric<T>::Numeric(const Symbolic& s, const double* vals, const mf_opts& o) {
     Numeric* self;
     ~Joiner() {
       self->cancel = true;
-      for (auto& t : self->workers)
-        if (t.joinable()) t.join();
+      self->workers.wait();
     }
   } joiner{this};
   if (hodlr && !bd_order.empty()) {
-    const int nthreads =
-        std::max(1, std::min<int>({(int)std::thread::hardware_concurrency(), 16, (int)bd_order.size()}));
-    for (int t = 0; t < nthreads; ++t)
-      workers.emplace_back([this, H]() {
+    const int ntasks = std::max(1, std::min<int>(max_workers(), (int)bd_order.size()));
+    workers.add(ntasks);
+    for (int t = 0; t < ntasks; ++t)
+      HostPool::get().submit([this, H]() {
         BdlrScratch w;
         for (;;) {
           const int i = bd_next.fetch_add(1);
-          if (i >= (int)bd_order.size() || cancel) return;
+          if (i >= (int)bd_order.size() || cancel) {
+            workers.done();
+            return;
+          }
           const int p = bd_order[i];
           const int h = sym->fronts[p].height;
           bool ok = true;

@@ -10,8 +10,10 @@
 // R' = R \ Sep.  Empty L or Sep -> leaf.  Postorder numbering: L subtree,
 // R' subtree, Sep.  Leaves and separators are numbered in kd order.
 #include "symbolic.h"
+#include "hostpool.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <limits>
 #include <numeric>
@@ -21,37 +23,31 @@
 namespace mfh {
 namespace {
 
-// Runs f(begin, end, worker) over [0, n) split into contiguous chunks, on up
-// to 16 host threads (one when the range is small).
-template <typename F>
-void parallel_for(int n, int min_chunk, F&& f) {
-  const int hw = std::max(1u, std::thread::hardware_concurrency());
-  const int nt = std::max(1, std::min({hw, 16, n / std::max(1, min_chunk)}));
-  if (nt <= 1) {
-    if (n > 0) f(0, n, 0);
-    return;
+
+
+// Output of one subtree of the dissection: its vertices in postorder and its
+// tree nodes (indices local to this output).
+struct NDOut {
+  struct TNode { int start, size; std::vector<int> kids; };
+  std::vector<int> perm;
+  std::vector<TNode> tree;
+  // appends a subtree's output; returns the subtree root's new index
+  int append(NDOut& o, int root) {
+    const int tb = (int)tree.size(), pb = (int)perm.size();
+    perm.insert(perm.end(), o.perm.begin(), o.perm.end());
+    for (auto& t : o.tree) {
+      for (int& k : t.kids) k += tb;
+      tree.push_back({t.start + pb, t.size, std::move(t.kids)});
+    }
+    return root + tb;
   }
-  std::vector<std::thread> th;
-  th.reserve(nt - 1);
-  const int ch = (n + nt - 1) / nt;
-  for (int t = 1; t < nt; ++t) {
-    const int b = t * ch, e = std::min(n, b + ch);
-    if (b < e) th.emplace_back([&f, b, e, t]() { f(b, e, t); });
-  }
-  f(0, std::min(n, ch), 0);
-  for (auto& x : th) x.join();
-}
-int max_workers() { return std::max(1, std::min<int>((int)std::thread::hardware_concurrency(), 16)); }
+};
 
 struct NDCtx {
   int n, dim, leaf;
   const int32_t* rowptr;
   const int32_t* colind;
   const double* coords;
-  std::vector<int> perm;
-  struct TNode { int start, size; std::vector<int> kids; };
-  std::vector<TNode> tree;
-  std::vector<char> inL;
 
   double co(int v, int a) const { return coords[(int64_t)v * dim + a]; }
 
@@ -90,22 +86,24 @@ struct NDCtx {
     kd_order(std::vector<int>(ids.begin() + m, ids.end()), out);
   }
 
-  int make_leaf(const std::vector<int>& S) {
-    int start = (int)perm.size();
-    kd_order(S, perm);
-    tree.push_back({start, (int)S.size(), {}});
-    return (int)tree.size() - 1;
+  int make_leaf(const std::vector<int>& S, NDOut& out) const {
+    int start = (int)out.perm.size();
+    kd_order(S, out.perm);
+    out.tree.push_back({start, (int)S.size(), {}});
+    return (int)out.tree.size() - 1;
   }
 
-  int rec(const std::vector<int>& S) {
-    if ((int)S.size() <= leaf) return make_leaf(S);
+  // Large sets near the root run their two halves as two host tasks (each
+  // with its own marker array); the merged output equals the sequential one.
+  int rec(const std::vector<int>& S, NDOut& out, std::vector<char>& inL, int spawn) const {
+    if ((int)S.size() <= leaf) return make_leaf(S, out);
     int ax = extent_axis(S);
     std::vector<int> srt(S);
     select_by_axis(srt, S.size() / 2, ax);
     double c = co(srt[S.size() / 2], ax);
     std::vector<int> L, R;
     for (int v : S) (co(v, ax) < c ? L : R).push_back(v);
-    if (L.empty()) return make_leaf(S);
+    if (L.empty()) return make_leaf(S, out);
     for (int v : L) inL[v] = 1;
     std::vector<int> Sep, Rp;
     for (int v : R) {
@@ -115,14 +113,30 @@ struct NDCtx {
       (hit ? Sep : Rp).push_back(v);
     }
     for (int v : L) inL[v] = 0;
-    if (Sep.empty()) return make_leaf(S);
+    if (Sep.empty()) return make_leaf(S, out);
     std::vector<int> kids;
-    kids.push_back(rec(L));
-    if (!Rp.empty()) kids.push_back(rec(Rp));
-    int start = (int)perm.size();
-    kd_order(Sep, perm);
-    tree.push_back({start, (int)Sep.size(), kids});
-    return (int)tree.size() - 1;
+    if (spawn > 0 && !Rp.empty() && (int)S.size() > 16 * leaf) {
+      NDOut oL, oR;
+      int rL = -1;
+      TaskGroup g;
+      g.add();
+      HostPool::get().submit([&]() {
+        std::vector<char> mark(n, 0);
+        rL = rec(L, oL, mark, spawn - 1);
+        g.done();
+      });
+      const int rR = rec(Rp, oR, inL, spawn - 1);
+      g.wait();
+      kids.push_back(out.append(oL, rL));
+      kids.push_back(out.append(oR, rR));
+    } else {
+      kids.push_back(rec(L, out, inL, 0));
+      if (!Rp.empty()) kids.push_back(rec(Rp, out, inL, 0));
+    }
+    int start = (int)out.perm.size();
+    kd_order(Sep, out.perm);
+    out.tree.push_back({start, (int)Sep.size(), kids});
+    return (int)out.tree.size() - 1;
   }
 };
 
@@ -153,29 +167,52 @@ void bisect_tree(int off, int size, int leaf, int kind, std::vector<TreeNode>& n
 std::string validate(int n, const int32_t* rowptr, const int32_t* colind) {
   if (n < 1) return "n must be >= 1";
   if (rowptr[0] != 0) return "rowptr[0] must be 0";
-  for (int i = 0; i < n; ++i) {
-    if (rowptr[i + 1] < rowptr[i]) return "rowptr not monotone";
-    bool diag = false;
-    for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
-      int j = colind[k];
-      if (j < 0 || j >= n) return "column index out of range";
-      if (k > rowptr[i] && colind[k - 1] >= j) return "columns not strictly increasing within a row";
-      if (j == i) diag = true;
-    }
-    if (!diag) return "missing diagonal entry in row " + std::to_string(i);
-  }
-  // symmetry: the transpose, built by counting sort (columns come out sorted
-  // within each row), must reproduce the pattern exactly
-  std::vector<int> tp(n + 1, 0), tc(rowptr[n]);
-  for (int k = 0; k < rowptr[n]; ++k) tp[colind[k] + 1]++;
-  for (int i = 0; i < n; ++i) tp[i + 1] += tp[i];
-  std::vector<int> fill(tp.begin(), tp.end() - 1);
   for (int i = 0; i < n; ++i)
-    for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) tc[fill[colind[k]]++] = i;
-  for (int i = 0; i <= n; ++i)
-    if (tp[i] != rowptr[i]) return "pattern is not symmetric";
-  for (int k = 0; k < rowptr[n]; ++k)
-    if (tc[k] != colind[k]) return "pattern is not symmetric";
+    if (rowptr[i + 1] < rowptr[i]) return "rowptr not monotone";
+  // per-row checks in parallel; the lowest failing row is reported
+  std::atomic<int> bad_row{n};
+  std::vector<int> code(max_workers(), 0);
+  std::vector<int> where(max_workers(), n);
+  parallel_for(n, 4096, [&](int r0, int r1, int t) {
+    for (int i = r0; i < r1 && i < bad_row.load(std::memory_order_relaxed); ++i) {
+      int c = 0;
+      bool diag = false;
+      for (int k = rowptr[i]; k < rowptr[i + 1] && c == 0; ++k) {
+        const int j = colind[k];
+        if (j < 0 || j >= n) c = 1;
+        else if (k > rowptr[i] && colind[k - 1] >= j) c = 2;
+        else if (j == i) diag = true;
+      }
+      if (c == 0 && !diag) c = 3;
+      if (c != 0) {
+        code[t] = c;
+        where[t] = i;
+        int cur = bad_row.load();
+        while (i < cur && !bad_row.compare_exchange_weak(cur, i)) {}
+        return;
+      }
+    }
+  });
+  int first = n, fc = 0;
+  for (size_t t = 0; t < code.size(); ++t)
+    if (code[t] != 0 && where[t] < first) { first = where[t]; fc = code[t]; }
+  if (fc == 1) return "column index out of range";
+  if (fc == 2) return "columns not strictly increasing within a row";
+  if (fc == 3) return "missing diagonal entry in row " + std::to_string(first);
+  // symmetry: every entry (i, j) has its mirror (j, i); rows are sorted, so
+  // a binary search in row j finds it (rows checked in parallel)
+  std::atomic<bool> asym{false};
+  parallel_for(n, 4096, [&](int r0, int r1, int) {
+    for (int i = r0; i < r1 && !asym.load(std::memory_order_relaxed); ++i)
+      for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+        const int j = colind[k];
+        if (!std::binary_search(colind + rowptr[j], colind + rowptr[j + 1], i)) {
+          asym.store(true, std::memory_order_relaxed);
+          break;
+        }
+      }
+  });
+  if (asym.load()) return "pattern is not symmetric";
   return "";
 }
 
@@ -191,14 +228,23 @@ std::string analyze(int n, const int32_t* rowptr, const int32_t* colind, const d
   s.n = n; s.leaf = leaf; s.dim = dim;
   s.nnz = rowptr[n];
   s.rowptr.assign(rowptr, rowptr + n + 1);
-  s.colind.assign(colind, colind + s.nnz);
+  s.colind.resize(s.nnz);
+  parallel_for(n, 4096, [&](int r0, int r1, int) {
+    std::copy(colind + rowptr[r0], colind + rowptr[r1], s.colind.begin() + rowptr[r0]);
+  });
 
-  NDCtx ctx{n, dim, leaf, rowptr, colind, coords, {}, {}, std::vector<char>(n, 0)};
-  ctx.perm.reserve(n);
-  std::vector<int> all(n);
-  std::iota(all.begin(), all.end(), 0);
-  ctx.rec(all);
-  s.perm = std::move(ctx.perm);
+  NDCtx ctx{n, dim, leaf, rowptr, colind, coords};
+  NDOut nd;
+  nd.perm.reserve(n);
+  {
+    std::vector<int> all(n);
+    std::iota(all.begin(), all.end(), 0);
+    std::vector<char> inL(n, 0);
+    int spawn = 0;
+    for (int w = max_workers(); w > 1; w >>= 1) ++spawn;    // up to 2^spawn subtrees at once
+    ctx.rec(all, nd, inL, spawn);
+  }
+  s.perm = std::move(nd.perm);
   s.iperm.assign(n, 0);
   for (int i = 0; i < n; ++i) s.iperm[s.perm[i]] = i;
 
@@ -206,7 +252,7 @@ std::string analyze(int n, const int32_t* rowptr, const int32_t* colind, const d
   s.prow.assign(n + 1, 0);
   for (int r = 0; r < n; ++r) s.prow[s.iperm[r] + 1] = rowptr[r + 1] - rowptr[r];
   for (int i = 0; i < n; ++i) s.prow[i + 1] += s.prow[i];
-  s.pcol.assign(s.nnz, 0);
+  s.pcol.resize(s.nnz);             // every entry is written below
   parallel_for(n, 2048, [&](int r0, int r1, int) {
     for (int r = r0; r < r1; ++r) {
       const int nr = s.iperm[r];
@@ -216,13 +262,13 @@ std::string analyze(int n, const int32_t* rowptr, const int32_t* colind, const d
     }
   });
 
-  const int nfr = (int)ctx.tree.size();
+  const int nfr = (int)nd.tree.size();
   s.fronts.resize(nfr);
   for (int p = 0; p < nfr; ++p) {
     Front& f = s.fronts[p];
-    f.start = ctx.tree[p].start;
-    f.npiv = ctx.tree[p].size;
-    f.children = ctx.tree[p].kids;
+    f.start = nd.tree[p].start;
+    f.npiv = nd.tree[p].size;
+    f.children = nd.tree[p].kids;
     for (int c : f.children) s.fronts[c].parent = p;
   }
   std::vector<int> owner(n);
@@ -327,15 +373,22 @@ std::string analyze(int n, const int32_t* rowptr, const int32_t* colind, const d
       for (int r = r0; r < r1; ++r) {
         int64_t o = off[r];
         const int i = s.iperm[r];
+        // a row's entries fall in few fronts: the last front's row position
+        // is reused instead of searching its update set again
+        int lp = -1, lrow = 0;
         for (int k = rowptr[r]; k < rowptr[r + 1]; ++k) {
           const int j = s.iperm[colind[k]];
           if (i < j) continue;
           const int p = owner[j];
           const Front& f = s.fronts[p];
+          if (p != lp) {
+            lp = p;
+            lrow = i < f.start + f.npiv
+                       ? i - f.start
+                       : f.npiv + (int)(std::lower_bound(f.upd.begin(), f.upd.end(), i) - f.upd.begin());
+          }
           s.asm_front[o] = p;
-          s.asm_row[o] = i < f.start + f.npiv
-                             ? i - f.start
-                             : f.npiv + (int)(std::lower_bound(f.upd.begin(), f.upd.end(), i) - f.upd.begin());
+          s.asm_row[o] = lrow;
           s.asm_col[o] = j - f.start;
           s.asm_src[o] = k;
           ++o;

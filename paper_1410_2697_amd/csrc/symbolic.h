@@ -2,9 +2,31 @@
 #pragma once
 #include <cstdint>
 #include <string>
+#include <memory>
+#include <utility>
 #include <vector>
 
 namespace mfh {
+
+// Allocator whose resize() leaves new elements of trivial types unwritten:
+// large index arrays are then first written by the worker threads that fill
+// them, instead of being zeroed by one thread beforehand.
+template <typename T>
+struct NoInitAlloc : std::allocator<T> {
+  template <typename U>
+  struct rebind { using other = NoInitAlloc<U>; };
+  NoInitAlloc() = default;
+  template <typename U>
+  NoInitAlloc(const NoInitAlloc<U>&) noexcept {}
+  template <typename U, typename... A>
+  void construct(U* p, A&&... a) {
+    if constexpr (sizeof...(A) == 0) ::new ((void*)p) U;
+    else ::new ((void*)p) U(std::forward<A>(a)...);
+  }
+};
+template <typename T>
+using bigvec = std::vector<T, NoInitAlloc<T>>;
+
 
 struct Block {            // lower off-diagonal block of a front, in front positions
   int kind;               // 0 top (F_fp), 1 pp, 2 ff
@@ -36,13 +58,13 @@ struct Front {
 struct Symbolic {
   int n = 0, leaf = 0, dim = 0;
   int64_t nnz = 0;
-  std::vector<int> rowptr, colind;  // copy of A's pattern (original order)
+  bigvec<int> rowptr, colind;       // copy of A's pattern (original order)
   std::vector<int> perm, iperm;     // perm[new] = old
-  std::vector<int> prow, pcol;      // pattern of P A P^T (CSR, sorted)
+  bigvec<int> prow, pcol;           // pattern of P A P^T (CSR, sorted)
   std::vector<Front> fronts;        // postorder
   std::vector<std::vector<int>> levels;  // by height
   // assembly of lower entries of P A P^T
-  std::vector<int> asm_front, asm_row, asm_col, asm_src;
+  bigvec<int> asm_front, asm_row, asm_col, asm_src;
   // BDLR cache
   int bdlr_depth = -2, bdlr_cap = -1;
   std::vector<int> bdlr_I, bdlr_Iptr, bdlr_J, bdlr_Jptr;   // over all blocks in front order
