@@ -130,8 +130,7 @@ struct Phase2CoopDesc {
   T* U;
   T* V;
   int* rank;
-  unsigned* bar;                 // barrier counter, zero before the launch
-  unsigned long long* keys;      // 2 x nwg
+  unsigned long long* keys;      // 2 x nwg tagged key slots, all 1 << 63 before the launch
   T* cand;                       // 2 x nwg x nr
   int ld, r0, nr, c0, nc, ldu, ldv, cap;
   int wg0, nwg, wcols;

@@ -866,26 +866,6 @@ __global__ __launch_bounds__(1024) void phase2_kernel(const Phase2Desc<T>* __res
 // arrives on the counter and polls it (bounded).  No cache-wide writeback or
 // invalidation is needed, so the slices stay in the caches.  Returns false
 // when the poll limit was reached.
-__device__ bool block_group_barrier(unsigned* bar, unsigned target, int spin_limit, int* status, int* s_ok) {
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int ok = 1;
-    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    int spins = 0;
-    while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      __builtin_amdgcn_s_sleep(1);
-      if (++spins > spin_limit) {
-        atomicOr(status, 8);
-        ok = 0;
-        break;
-      }
-    }
-    *s_ok = ok;
-  }
-  __syncthreads();
-  return *s_ok != 0;
-}
 template <typename T>
 __device__ __forceinline__ void publish(T* p, T v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -895,16 +875,36 @@ __device__ __forceinline__ T fetch(const T* p) {
   return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Block-wide maximum of a 64-bit key (every thread active), uniform result,
+// one barrier: the wave maxima go to half `par` of sh (2 x 16 entries);
+// consecutive calls alternate halves.
+__device__ __forceinline__ u64 block_max_key(u64 v, u64* sh, int par) {
+  const unsigned hi = wave_ext_u32<true>((unsigned)(v >> 32));
+  const unsigned lo = wave_ext_u32<true>((unsigned)(v >> 32) == hi ? (unsigned)(v & 0xFFFFFFFFull) : 0u);
+  if ((threadIdx.x & 63) == 0) sh[par * 16 + (threadIdx.x >> 6)] = ((u64)hi << 32) | lo;
+  __syncthreads();
+  u64 r = sh[par * 16];
+  for (int k = 1; k < (int)(blockDim.x >> 6); ++k) r = sh[par * 16 + k] > r ? sh[par * 16 + k] : r;
+  return uniform(r);
+}
+
+// Multi-workgroup phase 2.  Workgroup j owns a slice of wcols columns.  Each
+// step it applies the previous pivot's rank-1 update to its slice, finds its
+// best key, publishes that key's column, then the key in its slot.  A slot
+// holds the key with a tag in bit 63 that flips every second step (slots and
+// columns alternate between two buffers by step parity), so a workgroup
+// knows every other workgroup has published once all slots of the step's
+// buffer carry the step's tag: the polling of the slots is the barrier, and
+// it brings the keys along.  Then all pick the same pivot and read its column.
 // SLICE_LDS: the workgroup's columns are copied to LDS once (the front keeps
 // the phase-1 residual); otherwise they are updated in place in the front.
 template <typename T, bool SLICE_LDS>
 __global__ __launch_bounds__(256) void phase2_coop_kernel(const Phase2CoopDesc<T>* __restrict__ descs, int ndesc,
                                                           double eps, int* status, int spin_limit) {
   extern __shared__ __align__(16) char smem[];
-  __shared__ u64 s_red[16];
-  __shared__ u64 s_key;
-  __shared__ T s_piv;
-  __shared__ int s_ok;
+  __shared__ u64 s_red[32];
+  __shared__ u64 s_pk[2][4];
+  __shared__ int s_pok[2][4];
   int lo = 0, hi = ndesc - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -945,12 +945,13 @@ __global__ __launch_bounds__(256) void phase2_coop_kernel(const Phase2CoopDesc<T
   __syncthreads();
   double u11 = *d.u11;
   const double stop_rel = fmax(eps, (double)noise_rel<T>());
+  constexpr u64 kTag = 1ull << 63;
   int r = r1;
-  unsigned arrivals = 0;
-  int par = 0;           // parity of the buffers written this step
+  int step = 0, rpar = 0, ppar = 0;
   bool pending = false;
-  int a = 0;
-  for (;;) {
+  for (;; ++step) {
+    const int par = step & 1;
+    const u64 tag = ((step >> 1) & 1) ? kTag : 0ull;
     // update with the pending pivot (if any) and search own columns
     u64 best = 0;
     for (int c = wave; c < w; c += nwave) {
@@ -970,52 +971,73 @@ __global__ __launch_bounds__(256) void phase2_coop_kernel(const Phase2CoopDesc<T
         }
       }
     }
-    best = block_max_u64(best, s_red);
-    // publish the best key and its column
+    best = block_max_key(best, s_red, rpar);
+    rpar ^= 1;
+    // publish the best key's column, then (after every thread's stores are
+    // done) the tagged key
     if (best != 0ull) {
       const unsigned idx = 0xFFFFFFFFu - (unsigned)(best & 0xFFFFFFFFull);
       const int bc = (int)(idx / (unsigned)nr) - cb0;
       T* cd = d.cand + ((size_t)par * nwg + j) * nr;
       for (int i = tid; i < nr; i += nt) publish(cd + i, Es[i + (size_t)bc * les]);
     }
-    if (tid == 0) publish(d.keys + (size_t)par * nwg + j, (unsigned long long)best);
-    arrivals += (unsigned)nwg;
-    if (!block_group_barrier(d.bar, arrivals, spin_limit, status, &s_ok)) break;
-    // every workgroup picks the same pivot from the published keys
-    {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (tid == 0) publish(d.keys + (size_t)par * nwg + j, (unsigned long long)(best | tag));
+    // wait for every slot of this buffer to carry this step's tag
+    u64 K = 0;
+    bool met = false;
+    for (int spins = 0;; ++spins) {
       u64 kq = 0;
+      bool ok = true;
       for (int q = tid; q < nwg; q += nt) {
         const u64 k = fetch(d.keys + (size_t)par * nwg + q);
-        kq = k > kq ? k : kq;
+        if ((k & kTag) != tag) ok = false;
+        const u64 kv = k & ~kTag;
+        kq = kv > kq ? kv : kq;
       }
-      const u64 Kall = block_max_u64(kq, s_red);
-      if (tid == 0) {
-        s_key = Kall;
-        T pv = (T)0;
-        if (Kall != 0ull) {
-          const unsigned idx = 0xFFFFFFFFu - (unsigned)(Kall & 0xFFFFFFFFull);
-          const int y = (int)(idx / (unsigned)nr) / d.wcols;
-          pv = fetch(d.cand + ((size_t)par * nwg + y) * nr + (int)(idx % (unsigned)nr));
-        }
-        s_piv = pv;
+      const unsigned khi = wave_ext_u32<true>((unsigned)(kq >> 32));
+      const unsigned klo = wave_ext_u32<true>((unsigned)(kq >> 32) == khi ? (unsigned)(kq & 0xFFFFFFFFull) : 0u);
+      const bool wok = __ballot(!ok) == 0ull;
+      if (lane == 0) {
+        s_pk[ppar][wave] = ((u64)khi << 32) | klo;
+        s_pok[ppar][wave] = wok ? 1 : 0;
       }
       __syncthreads();
+      bool all = true;
+      u64 km = 0;
+      for (int q = 0; q < nwave; ++q) {
+        all = all && s_pok[ppar][q] != 0;
+        km = s_pk[ppar][q] > km ? s_pk[ppar][q] : km;
+      }
+      ppar ^= 1;
+      if (all) {
+        K = uniform(km);
+        met = true;
+        break;
+      }
+      if (spins >= spin_limit) break;
+      __builtin_amdgcn_s_sleep(1);
     }
-    const u64 K = s_key;
+    if (!met) {
+      if (tid == 0) atomicOr(status, 8);
+      break;
+    }
     if (K == 0ull) break;
     const unsigned idx = 0xFFFFFFFFu - (unsigned)(K & 0xFFFFFFFFull);
-    a = (int)(idx % (unsigned)nr);
+    const int a = (int)(idx % (unsigned)nr);
     const int b = (int)(idx / (unsigned)nr);
-    const T piv = s_piv;
+    const int y = b / d.wcols;
+    const T* cy = d.cand + ((size_t)par * nwg + y) * nr;
+    for (int i = tid; i < nr; i += nt) u[i] = fetch(cy + i);
+    __syncthreads();
+    const T piv = u[a];
     if (u11 == 0.0) u11 = fabs((double)piv);
     if (fabs((double)piv) < stop_rel * u11) break;
     if (r >= d.cap) {
       if (tid == 0 && j == 0) atomicOr(status, 2);
       break;
     }
-    const int y = b / d.wcols;
-    const T* cy = d.cand + ((size_t)par * nwg + y) * nr;
-    for (int i = tid; i < nr; i += nt) u[i] = fetch(cy + i);
     for (int c = tid; c < w; c += nt) vloc[c] = Es[a + (size_t)c * les] / piv;
     __syncthreads();
     {   // this workgroup's share of U(:, r), and V(own columns, r)
@@ -1029,7 +1051,6 @@ __global__ __launch_bounds__(256) void phase2_coop_kernel(const Phase2CoopDesc<T
     }
     ++r;
     pending = true;
-    par ^= 1;
     __syncthreads();
   }
   if (tid == 0 && j == 0) *d.rank = r;
@@ -1649,5 +1670,6 @@ template void launch_copy<double, double>(const CopyDesc<double, double>*, int, 
 template void launch_copy<float, double>(const CopyDesc<float, double>*, int, int, hipStream_t);
 template void launch_copy<double, float>(const CopyDesc<double, float>*, int, int, hipStream_t);
 template void launch_fill<int>(int*, int64_t, int, hipStream_t);
+template void launch_fill<unsigned long long>(unsigned long long*, int64_t, unsigned long long, hipStream_t);
 
 }  // namespace mfh

@@ -920,21 +920,25 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
   // ---- compression scratch (lives until the level's last launch)
   auto al = [](size_t v) { return (v + 255) & ~size_t(255); };
   size_t need = al(nb * sizeof(int)) * 2 + al(nb * sizeof(double));
-  int ncoop = 0;
+  int64_t nslots = 0;
   for (auto& x : br) {
     const Block& B = s.fronts[x.p].blocks[x.bi];
     if (x.nwg > 0) {
-      ++ncoop;
-      need += al((size_t)2 * x.nwg * sizeof(unsigned long long)) + al((size_t)2 * x.nwg * B.nr * sizeof(T));
+      nslots += 2 * x.nwg;
+      need += al((size_t)2 * x.nwg * B.nr * sizeof(T));
     }
     need += 2 * al(std::max(x.capr, 1) * sizeof(int));
     if (!x.full) need += al((size_t)std::max(x.kcap * x.kcap, 1) * sizeof(T));
     need += al((size_t)B.nr * x.capr * sizeof(T)) + al((size_t)B.nc * x.capr * sizeof(T));
   }
+  need += al((size_t)std::max<int64_t>(nslots, 1) * sizeof(unsigned long long));
   scrA.ensure(need, &ms, st);
   char* cur = static_cast<char*>(scrA.p);
   auto take = [&](size_t bytes) { char* r = cur; cur += al(bytes); return r; };
-  unsigned* bars = reinterpret_cast<unsigned*>(take((size_t)std::max(ncoop, 1) * 256));  // one 256-byte slot each
+  // every multi-workgroup block's tagged key slots, in one range
+  unsigned long long* slots =
+      reinterpret_cast<unsigned long long*>(take((size_t)std::max<int64_t>(nslots, 1) * sizeof(unsigned long long)));
+  int64_t slot_off = 0;
   int* rank1 = reinterpret_cast<int*>(take(nb * sizeof(int)));
   int* rankf = reinterpret_cast<int*>(take(nb * sizeof(int)));
   double* u11 = reinterpret_cast<double*>(take(nb * sizeof(double)));
@@ -950,7 +954,8 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
     x.rank = rankf + i;
     x.u11 = u11 + i;
     if (x.nwg > 0) {
-      x.keys = reinterpret_cast<unsigned long long*>(take((size_t)2 * x.nwg * sizeof(unsigned long long)));
+      x.keys = slots + slot_off;
+      slot_off += 2 * x.nwg;
       x.cand = reinterpret_cast<T*>(take((size_t)2 * x.nwg * B.nr * sizeof(T)));
     }
   }
@@ -1028,7 +1033,6 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
     g.wgs += p2c[i].nwg;
     ++g.n;
   }
-  for (size_t i = 0; i < p2c.size(); ++i) p2c[i].bar = bars + 64 * i;
   if (skelfac_lds<T>(rmax1) > (size_t)kLdsMax)
     throw Err{MF_EINVAL, "phase-1 rank bound too large for LDS: lower bdlr_cap"};
   if (maxrc > kLdsMax) throw Err{MF_EINVAL, "block too large for the phase-2 kernel"};
@@ -1055,7 +1059,7 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
     launch_phase2<T>(reinterpret_cast<const Phase2Desc<T>*>(base + op2), (int)p2.size(), maxrc, eps, dstat, st);
     prof_end(id_2, st);
     if (!p2c.empty()) {
-      launch_fill<float>(reinterpret_cast<float*>(bars), (int64_t)64 * p2c.size(), 0.0f, st);   // barrier counters
+      launch_fill<unsigned long long>(slots, nslots, 1ull << 63, st);   // no slot carries step 0's tag
       const auto* dc = reinterpret_cast<const Phase2CoopDesc<T>*>(base + op2c);
       for (const CoopGroup& g : cgroups) {
         const int id = prof_begin(pk<T>(g.slds ? PK_PHASE2CL_F64 : PK_PHASE2CG_F64), st, 0.0, 0.0);

@@ -128,16 +128,16 @@ mf_status skel_t(void* F, int ld, int r0, int nr, int c0, int nc, const int* I, 
       const size_t lds = slds ? (size_t)mfh::kPhase2CoopLds : mfh::phase2_coop_lds<T>(nr, wc, false);
       if (nwg > mfh::phase2_coop_capacity<T>(lds, slds)) nwg = 0;
       if (nwg > 0) {
-        char* cs = nullptr;   // barrier counter, keys, candidate columns
+        char* cs = nullptr;   // tagged key slots, candidate columns
         const size_t kb = 256 + (size_t)2 * nwg * 8, cb = (size_t)2 * nwg * nr * sizeof(T);
         s = hip_ok(hipMalloc(&cs, kb + cb));
         if (s == MF_OK) {
-          hipMemset(cs, 0, 256);
+          mfh::launch_fill<unsigned long long>(reinterpret_cast<unsigned long long*>(cs + 256), 2 * nwg, 1ull << 63,
+                                               nullptr);
           mfh::Phase2CoopDesc<T> qd{};
           qd.F = pd.F; qd.ld = ld; qd.r0 = r0; qd.nr = nr; qd.c0 = c0; qd.nc = nc;
           qd.piv_r = pr; qd.piv_c = pc; qd.rank1 = rank1; qd.u11 = u11; qd.U = pd.U; qd.ldu = nr; qd.V = pd.V;
           qd.ldv = nc; qd.cap = cap; qd.rank = rank;
-          qd.bar = reinterpret_cast<unsigned*>(cs);
           qd.keys = reinterpret_cast<unsigned long long*>(cs + 256);
           qd.cand = reinterpret_cast<T*>(cs + kb);
           qd.wg0 = 0; qd.nwg = nwg; qd.wcols = (nc + nwg - 1) / nwg;
