@@ -114,6 +114,9 @@ struct Phase2Desc {
   int ld, r0, nr, c0, nc, ldu, ldv, cap;
 };
 
+// rows of a block the multi-workgroup phase 2 takes (one bit per row and lane)
+constexpr int kPhase2CoopMaxRows = 4096;
+
 // Phase 2 spread over workgroups: workgroup j of a block keeps the residual
 // columns [j*wcols, min(nc, (j+1)*wcols)) in LDS for the whole pivot loop.
 // After each step every workgroup publishes its best pivot key and the

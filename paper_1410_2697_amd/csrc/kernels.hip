@@ -943,6 +943,10 @@ __global__ __launch_bounds__(256) void phase2_coop_kernel(const Phase2CoopDesc<T
     if (cc >= 0 && cc < w) lc[cc] = 0;
   }
   __syncthreads();
+  // live rows of this lane (rows lane + 64 k; nr <= kPhase2CoopMaxRows) as bits
+  u64 lmask = 0;
+  for (int k = 0; k < 64 && lane + 64 * k < nr; ++k)
+    if (lr[lane + 64 * k]) lmask |= 1ull << k;
   double u11 = *d.u11;
   const double stop_rel = fmax(eps, (double)noise_rel<T>());
   constexpr u64 kTag = 1ull << 63;
@@ -952,25 +956,49 @@ __global__ __launch_bounds__(256) void phase2_coop_kernel(const Phase2CoopDesc<T
   for (;; ++step) {
     const int par = step & 1;
     const u64 tag = ((step >> 1) & 1) ? kTag : 0ull;
-    // update with the pending pivot (if any) and search own columns
-    u64 best = 0;
+    // update with the pending pivot (if any) and search own columns, rows in
+    // groups of four independent load / update / store chains; the thread's
+    // best is (truncated magnitude, position), visited in ascending position
+    unsigned bq = 0, bidx = 0;
+    auto consider = [&](T x, int i, unsigned base) {
+      const unsigned q = ((lmask >> (i >> 6)) & 1ull) ? qmag(x) : 0u;
+      if (q > bq) { bq = q; bidx = base + (unsigned)i; }
+    };
     for (int c = wave; c < w; c += nwave) {
       const T v = pending ? vloc[c] : (T)0;
       const bool cc = lc[c] != 0;
       T* col = Es + (size_t)c * les;
       const unsigned base = (unsigned)(cb0 + c) * (unsigned)nr;
-      for (int i = lane; i < nr; i += 64) {
+      int i = lane;
+      for (; i + 192 < nr; i += 256) {
+        T x0 = col[i], x1 = col[i + 64], x2 = col[i + 128], x3 = col[i + 192];
+        if (pending) {
+          x0 -= u[i] * v;
+          x1 -= u[i + 64] * v;
+          x2 -= u[i + 128] * v;
+          x3 -= u[i + 192] * v;
+          col[i] = x0;
+          col[i + 64] = x1;
+          col[i + 128] = x2;
+          col[i + 192] = x3;
+        }
+        if (cc) {
+          consider(x0, i, base);
+          consider(x1, i + 64, base);
+          consider(x2, i + 128, base);
+          consider(x3, i + 192, base);
+        }
+      }
+      for (; i < nr; i += 64) {
         T x = col[i];
         if (pending) {
           x -= u[i] * v;
           col[i] = x;
         }
-        if (cc && lr[i]) {
-          const u64 k = make_key(qmag(x), base + (unsigned)i);
-          best = k > best ? k : best;
-        }
+        if (cc) consider(x, i, base);
       }
     }
+    u64 best = make_key(bq, bidx);
     best = block_max_key(best, s_red, rpar);
     rpar ^= 1;
     // publish the best key's column, then (after every thread's stores are
@@ -1049,6 +1077,7 @@ __global__ __launch_bounds__(256) void phase2_coop_kernel(const Phase2CoopDesc<T
       lr[a] = 0;
       if (b >= cb0 && b < cb0 + w) lc[b - cb0] = 0;
     }
+    if (lane == (a & 63)) lmask &= ~(1ull << (a >> 6));
     ++r;
     pending = true;
     __syncthreads();

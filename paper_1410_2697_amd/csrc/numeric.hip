@@ -890,7 +890,7 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
       x.kcap = std::min(x.nI, x.nJ);
       x.capr = std::max(std::min({B.nr, B.nc, opts.rank_cap}), x.kcap);
       x.full = B.nr <= skreg_full_rows<T>() && B.nc <= skreg_full_cols<T>();
-      if (!x.full && adaptive) {
+      if (!x.full && adaptive && B.nr <= kPhase2CoopMaxRows) {
         // phase 2 over several workgroups: column slices in LDS when they fit
         // the resident workgroups, else updated in place (about 64K entries each)
         const int wc = phase2_coop_wcols<T>(B.nr);

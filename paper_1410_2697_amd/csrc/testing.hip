@@ -124,7 +124,7 @@ mf_status skel_t(void* F, int ld, int r0, int nr, int c0, int nc, const int* I, 
       // 1: slices in LDS; 3: slices updated in place; 2: one workgroup
       const bool slds = adaptive == 1;
       int wc = adaptive == 1 ? mfh::phase2_coop_wcols<T>(nr) : (adaptive == 3 ? 4 : 0);
-      int nwg = wc > 0 ? (nc + wc - 1) / wc : 0;
+      int nwg = wc > 0 && nr <= mfh::kPhase2CoopMaxRows ? (nc + wc - 1) / wc : 0;
       const size_t lds = slds ? (size_t)mfh::kPhase2CoopLds : mfh::phase2_coop_lds<T>(nr, wc, false);
       if (nwg > mfh::phase2_coop_capacity<T>(lds, slds)) nwg = 0;
       if (nwg > 0) {
