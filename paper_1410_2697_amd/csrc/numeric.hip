@@ -452,6 +452,13 @@ class Numeric : public NumericBase {
   DevBuf split;                   // split-K partial sums of the factor's GEMM batches
   std::vector<int64_t> relmap_off;
   std::vector<int64_t> asm_lvl_off;
+  // host sources of the map uploads, kept until the factorization has synchronised
+  bigvec<int64_t> asm_hd;
+  bigvec<int> asm_hs, relmap_h;
+  // second stream for the whole-block skeleton kernels, which run beside
+  // the phase-1 / factor / phase-2 chain of the larger blocks of a level
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   struct LevelBdlr {              // BDLR sets of one level's HODLR blocks
     std::vector<int> I, Iptr, J, Jptr;
     std::map<int, int> first;     // front -> index of its first block in this level
@@ -500,7 +507,11 @@ class Numeric : public NumericBase {
     Numeric* self;
     ~SyncGuard() {
       if (!self->constructed) (void)hipStreamSynchronize(self->st);
+      if (self->side) (void)hipStreamSynchronize(self->side);
       self->wait_streams();
+      if (self->ev_fork) (void)hipEventDestroy(self->ev_fork);
+      if (self->ev_join) (void)hipEventDestroy(self->ev_join);
+      if (self->side) (void)hipStreamDestroy(self->side);
     }
   } sync_guard{this};
 };
@@ -536,6 +547,11 @@ Numeric<T>::Numeric(const Symbolic& s, const double* vals, const mf_opts& o) {
     const Front& f = s.fronts[p];
     fn[p].dense = !hodlr || f.n() < o.n_c;
     fn[p].ld = f.n();
+  }
+  if (hodlr) {
+    HIPCHK(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
   }
 
   // BDLR sets are host graph work: worker threads take the HODLR fronts in
@@ -605,39 +621,55 @@ Numeric<T>::Numeric(const Symbolic& s, const double* vals, const mf_opts& o) {
   for (int h = 0; h < H; ++h)
     for (int p : s.levels[h]) fn[p].F = wsT + reg_off[h] + front_elem_off[p];
 
-  // ---- assembly map by level, relative maps
+  // ---- assembly map by level (counted and placed per chunk on the host
+  // workers, keeping each level's entries in their original order), relative maps
   {
-    std::vector<std::vector<int64_t>> dest(H);
-    std::vector<std::vector<int>> src(H);
-    for (size_t e = 0; e < s.asm_src.size(); ++e) {
-      const int p = s.asm_front[e];
-      const int h = s.fronts[p].height;
-      dest[h].push_back((fn[p].F - wsT) + s.asm_row[e] + (int64_t)s.asm_col[e] * fn[p].ld);
-      src[h].push_back(s.asm_src[e]);
-    }
+    const int ne = (int)s.asm_src.size();
+    const int W = max_workers();
+    std::vector<int64_t> cnt((size_t)W * H, 0);
+    parallel_for(ne, 32768, [&](int b, int e, int c) {
+      int64_t* cc = cnt.data() + (size_t)c * H;
+      for (int q = b; q < e; ++q) ++cc[s.fronts[s.asm_front[q]].height];
+    });
     asm_lvl_off.assign(H + 1, 0);
-    std::vector<int64_t> hd;
-    std::vector<int> hs;
+    std::vector<int64_t> pos((size_t)W * H);
+    int64_t tot = 0;
     for (int h = 0; h < H; ++h) {
-      asm_lvl_off[h] = (int64_t)hd.size();
-      hd.insert(hd.end(), dest[h].begin(), dest[h].end());
-      hs.insert(hs.end(), src[h].begin(), src[h].end());
+      asm_lvl_off[h] = tot;
+      for (int c = 0; c < W; ++c) {
+        pos[(size_t)c * H + h] = tot;
+        tot += cnt[(size_t)c * H + h];
+      }
     }
-    asm_lvl_off[H] = (int64_t)hd.size();
-    d_asm_dest.alloc(hd.size() * sizeof(int64_t), &ms);
-    d_asm_src.alloc(hs.size() * sizeof(int), &ms);
-    HIPCHK(hipMemcpyAsync(d_asm_dest.p, hd.data(), hd.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(d_asm_src.p, hs.data(), hs.size() * sizeof(int), hipMemcpyHostToDevice, st));
-    HIPCHK(hipStreamSynchronize(st));     // host vectors go out of scope
-    std::vector<int> rm;
+    asm_lvl_off[H] = tot;
+    asm_hd.resize(tot);
+    asm_hs.resize(tot);
+    parallel_for(ne, 32768, [&](int b, int e, int c) {
+      int64_t* pp = pos.data() + (size_t)c * H;
+      for (int q = b; q < e; ++q) {
+        const int p = s.asm_front[q];
+        const int64_t o = pp[s.fronts[p].height]++;
+        asm_hd[o] = (fn[p].F - wsT) + s.asm_row[q] + (int64_t)s.asm_col[q] * fn[p].ld;
+        asm_hs[o] = s.asm_src[q];
+      }
+    });
+    d_asm_dest.alloc(std::max<int64_t>(tot, 1) * sizeof(int64_t), &ms);
+    d_asm_src.alloc(std::max<int64_t>(tot, 1) * sizeof(int), &ms);
+    HIPCHK(hipMemcpyAsync(d_asm_dest.p, asm_hd.data(), tot * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d_asm_src.p, asm_hs.data(), tot * sizeof(int), hipMemcpyHostToDevice, st));
     relmap_off.assign(nfr, 0);
+    int64_t nrm = 0;
     for (int p = 0; p < nfr; ++p) {
-      relmap_off[p] = (int64_t)rm.size();
-      rm.insert(rm.end(), s.fronts[p].relmap.begin(), s.fronts[p].relmap.end());
+      relmap_off[p] = nrm;
+      nrm += (int64_t)s.fronts[p].relmap.size();
     }
-    d_relmap.alloc(std::max<size_t>(rm.size(), 1) * sizeof(int), &ms);
-    HIPCHK(hipMemcpyAsync(d_relmap.p, rm.data(), rm.size() * sizeof(int), hipMemcpyHostToDevice, st));
-    HIPCHK(hipStreamSynchronize(st));
+    relmap_h.resize(nrm);
+    parallel_for(nfr, 64, [&](int b, int e, int) {
+      for (int p = b; p < e; ++p)
+        std::copy(s.fronts[p].relmap.begin(), s.fronts[p].relmap.end(), relmap_h.begin() + relmap_off[p]);
+    });
+    d_relmap.alloc(std::max<int64_t>(nrm, 1) * sizeof(int), &ms);
+    HIPCHK(hipMemcpyAsync(d_relmap.p, relmap_h.data(), nrm * sizeof(int), hipMemcpyHostToDevice, st));
   }
   ranks.assign(s.nblocks, -1);
 
@@ -692,6 +724,9 @@ Numeric<T>::Numeric(const Symbolic& s, const double* vals, const mf_opts& o) {
   split.release();
   d_asm_dest.release();
   d_asm_src.release();
+  asm_hd = {};
+  asm_hs = {};
+  relmap_h = {};
   dp.ar.chunks.clear();
   dp.ar.off = 0;
   dp.keep.clear();
@@ -1041,10 +1076,19 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
   const char* base = dp.upload(b, st);
   int* dstat = d_status.as<int>();
   // timing records; their work is added once the ranks are back on the host
-  const int id_f = skf.empty() ? -1 : prof_begin(pk<T>(PK_SKREG_FULL_F64), st, 0.0, 0.0);
+  // whole-block blocks on the side stream while the larger blocks' chain
+  // runs here; joined before the ranks are read back
+  const bool fork = side && !skf.empty() && !skh.empty();
+  hipStream_t fst = fork ? side : st;
+  if (fork) {
+    HIPCHK(hipEventRecord(ev_fork, st));
+    HIPCHK(hipStreamWaitEvent(side, ev_fork, 0));
+  }
+  const int id_f = skf.empty() ? -1 : prof_begin(pk<T>(PK_SKREG_FULL_F64), fst, 0.0, 0.0);
   launch_skreg_full<T>(reinterpret_cast<const SkRegDesc<T>*>(base + okf), (int)skf.size(), eps, adaptive ? 1 : 0,
-                       dstat, st);
-  prof_end(id_f, st);
+                       dstat, fst);
+  prof_end(id_f, fst);
+  if (fork) HIPCHK(hipEventRecord(ev_join, side));
   const int id_h = skh.empty() ? -1 : prof_begin(pk<T>(PK_SKREG_HAT_F64), st, 0.0, 0.0);
   launch_skreg_hat<T>(reinterpret_cast<const SkRegDesc<T>*>(base + okh), (int)skh.size(), eps, dstat, st);
   prof_end(id_h, st);
@@ -1071,6 +1115,7 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
       }
     }
   }
+  if (fork) HIPCHK(hipStreamWaitEvent(st, ev_join, 0));
   // ---- the one synchronisation of the level: ranks to the host
   std::vector<int> hr(nb), h1(nb);
   int status = 0;
