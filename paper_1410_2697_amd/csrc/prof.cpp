@@ -74,6 +74,8 @@ Rec* find(State& s, int id) {
 
 const char* prof_name(int kind) { return (kind >= 0 && kind < PK_COUNT) ? kNames[kind] : "?"; }
 
+bool prof_selected(int kind) { return ((S().mask.load(std::memory_order_relaxed) >> kind) & 1) != 0; }
+
 int prof_begin(int kind, hipStream_t st, double flops, double bytes) {
   State& s = S();
   if (!((s.mask.load(std::memory_order_relaxed) >> kind) & 1)) return -1;

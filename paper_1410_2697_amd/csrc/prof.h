@@ -35,6 +35,8 @@ template <typename T>
 constexpr int pk(int f64_kind) { return sizeof(T) == 4 ? f64_kind + 1 : f64_kind; }
 
 const char* prof_name(int kind);
+// true while a timing session selects this kernel kind
+bool prof_selected(int kind);
 
 // id >= 0 when the launch is timed; -1 otherwise (all calls then do nothing).
 // A timed record hands its two events to the next kernel launched by this
