@@ -75,6 +75,8 @@ def kernel_bound(name: str):
     dt = "f32" if "<float" in name else "f64"
     if name.startswith("gemm_kernel"):
         return "mfma", dt
+    if name.startswith("gemm_narrow_kernel"):   # right-hand-side blocks: streams the factor
+        return "hbm", dt
     if name.startswith(("potrf_kernel", "skreg_kernel", "skelfac_kernel", "gj_kernel", "gj_wide_kernel", "phase2_coop_kernel")):
         return "alu", dt
     return "hbm", dt

@@ -10,6 +10,7 @@
 namespace mfh {
 
 constexpr int kTile = 64;            // GEMM output tile (rows and columns)
+constexpr int kTileNarrow = 16;   // output tile width for right-hand-side blocks
 template <typename T>
 constexpr int kGemmBK = sizeof(T) == 4 ? 64 : 32;   // GEMM k step (LDS-staged)
 constexpr int kGemmSplitAlign = 64;  // split-K ranges are multiples of this (and of every k step)
@@ -210,7 +211,9 @@ struct VecGatherDesc {    // t(0:nf, :) = xn(upd, :)
 template <typename T>
 void launch_mfma_probe(int* rows, int* cols, int* assumed, hipStream_t st);
 template <typename T>
-void launch_gemm(const GemmDesc<T>* d, int ndesc, int tiles, hipStream_t st);
+// tn = kTile: 64 x 64 output tiles; tn = kTileNarrow: 64 x 16 tiles, for
+// problems of at most 16 columns (tiles_n of the descriptors counts tn-wide tiles)
+void launch_gemm(const GemmDesc<T>* d, int ndesc, int tiles, hipStream_t st, int tn = kTile);
 // reduction of split-K partial sums: d lists only split problems, with
 // tile0/tiles_m describing this launch's 64 x 64 output tiles
 template <typename T>

@@ -117,10 +117,14 @@ __device__ __forceinline__ T load_op(const T* p, size_t idx, bool bf16) {
 // 2x2 MFMA 16x16x4 tiles.  K advances in steps of kGemmBK<T> staged through
 // LDS; the next step's operands are loaded into registers while the MFMAs
 // work on the current one.
-template <typename T>
-__global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc<T>* __restrict__ descs, int ndesc,
-                                                   unsigned long long* ts) {
-  constexpr int BM = kTile, BN = kTile, BK = kGemmBK<T>, NQ = BK * 64 / 256;
+// BN = 64: 64 x 64 output tiles, the four waves in a 2 x 2 grid of 32 x 32
+// (2 x 2 MFMA tiles each).  BN = 16 (right-hand-side blocks of at most 16
+// columns): 64 x 16 tiles, each wave one 16 x 16 MFMA tile, so no MFMA work
+// is spent on empty columns.
+template <typename T, int BN>
+__device__ __forceinline__ void gemm_tile(const GemmDesc<T>* __restrict__ descs, int ndesc, unsigned long long* ts) {
+  constexpr int BM = kTile, BK = kGemmBK<T>, NQ = BK * 64 / 256, NQB = BK * BN / 256;
+  constexpr bool NARROW = BN == 16;
   __shared__ T As[BK][BM + 1];
   __shared__ T Bs[BK][BN + 1];
   typedef typename Mfma<T>::v4 v4;
@@ -152,11 +156,11 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc<T>* __restrict
   const bool abf = (flags & GF_A_BF16) != 0, bbf = (flags & GF_B_BF16) != 0;
   v4 acc00 = {0, 0, 0, 0}, acc01 = {0, 0, 0, 0}, acc10 = {0, 0, 0, 0}, acc11 = {0, 0, 0, 0};
   const int wave = tid >> 6, lane = tid & 63;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int wm = NARROW ? wave * 16 : (wave >> 1) * 32, wn = NARROW ? 0 : (wave & 1) * 32;
   const int li = lane & 15, lk = lane >> 4;
   // per-thread load coordinates: (row of the tile, k offset) for each of NQ loads
   // op N: row = tid & 63, k = (tid >> 6) + 4q;   op T: k = tid % BK, row = tid / BK + (256 / BK) q
-  T ra[NQ], rb[NQ];
+  T ra[NQ], rb[NQB];
   auto load = [&](int kb) {
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
@@ -169,10 +173,10 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc<T>* __restrict
                   : (T)0;
     }
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
+    for (int q = 0; q < NQB; ++q) {
       int j, kk;
       if (opB == 0) { kk = tid % BK; j = tid / BK + (256 / BK) * q; }
-      else { j = tid & 63; kk = (tid >> 6) + 4 * q; }
+      else { j = tid % BN; kk = tid / BN + (256 / BN) * q; }
       const int gj = n0 + j, gk = kb + kk;
       rb[q] = (gj < n && gk < kend)
                   ? load_op(B, opB == 0 ? gk + (size_t)gj * ldb : gj + (size_t)gk * ldb, bbf)
@@ -188,10 +192,10 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc<T>* __restrict
       As[kk][i] = ra[q];
     }
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
+    for (int q = 0; q < NQB; ++q) {
       int j, kk;
       if (opB == 0) { kk = tid % BK; j = tid / BK + (256 / BK) * q; }
-      else { j = tid & 63; kk = (tid >> 6) + 4 * q; }
+      else { j = tid % BN; kk = tid / BN + (256 / BN) * q; }
       Bs[kk][j] = rb[q];
     }
   };
@@ -203,12 +207,16 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc<T>* __restrict
 #pragma unroll
     for (int k4 = 0; k4 < BK / 4; ++k4) {
       const int kq = k4 * 4 + lk;
-      const T a0 = As[kq][wm + li], a1 = As[kq][wm + 16 + li];
-      const T b0 = Bs[kq][wn + li], b1 = Bs[kq][wn + 16 + li];
-      acc00 = Mfma<T>::run(a0, b0, acc00);
-      acc01 = Mfma<T>::run(a0, b1, acc01);
-      acc10 = Mfma<T>::run(a1, b0, acc10);
-      acc11 = Mfma<T>::run(a1, b1, acc11);
+      if constexpr (NARROW) {
+        acc00 = Mfma<T>::run(As[kq][wm + li], Bs[kq][li], acc00);
+      } else {
+        const T a0 = As[kq][wm + li], a1 = As[kq][wm + 16 + li];
+        const T b0 = Bs[kq][wn + li], b1 = Bs[kq][wn + 16 + li];
+        acc00 = Mfma<T>::run(a0, b0, acc00);
+        acc01 = Mfma<T>::run(a0, b1, acc01);
+        acc10 = Mfma<T>::run(a1, b0, acc10);
+        acc11 = Mfma<T>::run(a1, b1, acc11);
+      }
     }
     __syncthreads();
   }
@@ -217,7 +225,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc<T>* __restrict
   const int ldc = split ? m : d.ldc;
   const v4* accs[4] = {&acc00, &acc01, &acc10, &acc11};
 #pragma unroll
-  for (int ab = 0; ab < 4; ++ab) {
+  for (int ab = 0; ab < (NARROW ? 1 : 4); ++ab) {
     const int a = ab >> 1, b = ab & 1;
     const v4 acc = *accs[ab];
     const int col = n0 + wn + b * 16 + li;
@@ -240,6 +248,17 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc<T>* __restrict
     __syncthreads();
     if (tid == 0) atomicMax(ts + 1, (unsigned long long)wall_clock64());
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc<T>* __restrict__ descs, int ndesc,
+                                                   unsigned long long* ts) {
+  gemm_tile<T, kTile>(descs, ndesc, ts);
+}
+template <typename T>
+__global__ __launch_bounds__(256) void gemm_narrow_kernel(const GemmDesc<T>* __restrict__ descs, int ndesc,
+                                                          unsigned long long* ts) {
+  gemm_tile<T, kTileNarrow>(descs, ndesc, ts);
 }
 
 template <typename T>
@@ -1490,10 +1509,11 @@ inline int grid_for(int64_t n, int block = 256, int cap = 8192) {
 
 // ------------------------------------------------------------ launchers ----
 template <typename T>
-void launch_gemm(const GemmDesc<T>* d, int ndesc, int tiles, hipStream_t st) {
+void launch_gemm(const GemmDesc<T>* d, int ndesc, int tiles, hipStream_t st, int tn) {
   if (ndesc <= 0 || tiles <= 0) return;
   unsigned long long* ts = prof_take_slot();
-  MFH_LAUNCH(gemm_kernel<T>, dim3(tiles), dim3(256), 0, st, d, ndesc, ts);
+  if (tn == kTileNarrow) MFH_LAUNCH(gemm_narrow_kernel<T>, dim3(tiles), dim3(256), 0, st, d, ndesc, ts);
+  else MFH_LAUNCH(gemm_kernel<T>, dim3(tiles), dim3(256), 0, st, d, ndesc, ts);
 }
 template <typename T>
 void launch_gemm_reduce(const GemmDesc<T>* d, int ndesc, int tiles, hipStream_t st) {
@@ -1669,7 +1689,7 @@ void launch_axpby(const double* a, const double* b, double* c, double alpha, dou
 }
 
 #define MFH_INST(T)                                                                              \
-  template void launch_gemm<T>(const GemmDesc<T>*, int, int, hipStream_t);                       \
+  template void launch_gemm<T>(const GemmDesc<T>*, int, int, hipStream_t, int);                  \
   template void launch_gemm_reduce<T>(const GemmDesc<T>*, int, int, hipStream_t);                \
   template void launch_potrf<T>(const PotrfDesc<T>*, int, int, int*, hipStream_t);               \
   template void launch_skreg_full<T>(const SkRegDesc<T>*, int, double, int, int*, hipStream_t);  \

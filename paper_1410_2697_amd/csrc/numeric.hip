@@ -183,12 +183,13 @@ constexpr size_t kSplitPlanBytes = size_t(4) << 20;
 // assigns tile0/tiles_m/tiles_n/ksplit; returns total tiles; `red` receives
 // the reduction descriptors of split problems (tile0 over output tiles)
 template <typename T>
-int finalize_gemm(std::vector<GemmDesc<T>>& v, T* part, size_t cap, std::vector<GemmDesc<T>>& red, int& rtiles) {
+int finalize_gemm(std::vector<GemmDesc<T>>& v, T* part, size_t cap, std::vector<GemmDesc<T>>& red, int& rtiles,
+                  int tn = kTile) {
   red.clear();
   rtiles = 0;
   int base = 0;
   for (const auto& d : v)
-    if (d.m > 0 && d.n > 0) base += cdiv(d.m, kTile) * cdiv(d.n, kTile);
+    if (d.m > 0 && d.n > 0) base += cdiv(d.m, kTile) * cdiv(d.n, tn);
   const int want = (part && base > 0 && 2 * base <= kSplitTarget) ? kSplitTarget / base : 1;
   size_t used = 0;
   int t = 0;
@@ -197,7 +198,7 @@ int finalize_gemm(std::vector<GemmDesc<T>>& v, T* part, size_t cap, std::vector<
   for (auto& d : v) {
     if (d.m <= 0 || d.n <= 0) continue;
     d.tiles_m = cdiv(d.m, kTile);
-    d.tiles_n = cdiv(d.n, kTile);
+    d.tiles_n = cdiv(d.n, tn);
     d.ksplit = 1;
     d.kchunk = 0;
     d.part = nullptr;
@@ -216,10 +217,11 @@ int finalize_gemm(std::vector<GemmDesc<T>>& v, T* part, size_t cap, std::vector<
     d.tile0 = t;
     t += d.tiles_m * d.tiles_n * d.ksplit;
     out.push_back(d);
-    if (d.ksplit > 1) {
+    if (d.ksplit > 1) {          // the reduction always walks 64 x 64 tiles
       GemmDesc<T> r = d;
+      r.tiles_n = cdiv(d.n, kTile);
       r.tile0 = rtiles;
-      rtiles += d.tiles_m * d.tiles_n;
+      rtiles += r.tiles_m * r.tiles_n;
       red.push_back(r);
     }
   }
@@ -307,13 +309,17 @@ struct GemmBatch {
   std::vector<GemmDesc<T>> v, red;
   size_t off = 0, roff = 0;
   int tiles = 0, n = 0, rtiles = 0, rn = 0;
+  int tn = kTile;                            // output tile width: kTileNarrow when every n <= 16
   double flops = 0, bytes = 0, rbytes = 0;   // work of the descriptors with a host-known k
   mutable int pid = -1;                      // timing record of the last launch
   // split: split-K partial-sum area (reused by every batch of a stream)
   void stage(Blob& b, const DevBuf* split = nullptr) {
     T* part = split ? static_cast<T*>(split->p) : nullptr;
     const size_t cap = split ? split->bytes / sizeof(T) : 0;
-    tiles = finalize_gemm(v, part, cap, red, rtiles);
+    tn = kTileNarrow;
+    for (const auto& d : v)
+      if (d.n > kTileNarrow) tn = kTile;
+    tiles = finalize_gemm(v, part, cap, red, rtiles, tn);
     n = (int)v.size();
     off = b.add(v);
     rn = (int)red.size();
@@ -329,8 +335,8 @@ struct GemmBatch {
   }
   void launch(const char* base, hipStream_t st) const {
     if (n) {
-      pid = prof_begin(pk<T>(PK_GEMM_F64), st, flops, bytes);
-      launch_gemm<T>(reinterpret_cast<const GemmDesc<T>*>(base + off), n, tiles, st);
+      pid = prof_begin(pk<T>(tn == kTileNarrow ? PK_GEMMN_F64 : PK_GEMM_F64), st, flops, bytes);
+      launch_gemm<T>(reinterpret_cast<const GemmDesc<T>*>(base + off), n, tiles, st, tn);
       prof_end(pid, st);
     }
     if (rn) {
@@ -488,6 +494,7 @@ class Numeric : public NumericBase {
     size_t off;
     int n, tiles;
     double flops = 0, bytes = 0;
+    int tn = kTile;           // gemm: output tile width
   };
   struct Plan {
     int nrhs = 0;
@@ -1514,7 +1521,7 @@ typename Numeric<T>::Plan* Numeric<T>::get_plan(int nrhs) {
   pl->split.alloc(kSplitPlanBytes, &ms);
   auto rec_gemm = [&](GemmBatch<T>& g) {
     g.stage(b, &pl->split);
-    if (g.n) pl->recs.push_back({0, g.off, g.n, g.tiles, g.flops, g.bytes});
+    if (g.n) pl->recs.push_back({0, g.off, g.n, g.tiles, g.flops, g.bytes, g.tn});
     if (g.rn) pl->recs.push_back({4, g.roff, g.rn, g.rtiles, 0.0, g.rbytes});
   };
   auto rec_copy = [&](CopyBatch<T, T>& c) {
@@ -1672,7 +1679,7 @@ void Numeric<T>::apply(int nrhs, const double* r, double* z, hipStream_t stream)
   // a recorded apply cannot time its launches: launch directly while its
   // GEMM kernels are being timed
   bool replay = opts.apply_graph && !pl->no_graph && !prof_selected(pk<T>(PK_GEMM_F64)) &&
-                !prof_selected(pk<T>(PK_GEMM_REDUCE_F64));
+                !prof_selected(pk<T>(PK_GEMMN_F64)) && !prof_selected(pk<T>(PK_GEMM_REDUCE_F64));
   if (replay && !pl->exec) {
     // record the step sequence once on a stream of this handle; the plan's
     // buffers and descriptors stay put, so the graph stays valid with it
@@ -1706,8 +1713,9 @@ void Numeric<T>::launch_recs(const Plan& plan, hipStream_t stream) {
     const char* base = pl->desc + rc.off;
     switch (rc.kind) {
       case 0: {
-        const int id = prof_begin(pk<T>(PK_GEMM_F64), stream, rc.flops, rc.bytes);
-        launch_gemm<T>(reinterpret_cast<const GemmDesc<T>*>(base), rc.n, rc.tiles, stream);
+        const int id = prof_begin(pk<T>(rc.tn == kTileNarrow ? PK_GEMMN_F64 : PK_GEMM_F64), stream, rc.flops,
+                                  rc.bytes);
+        launch_gemm<T>(reinterpret_cast<const GemmDesc<T>*>(base), rc.n, rc.tiles, stream, rc.tn);
         prof_end(id, stream);
         break;
       }

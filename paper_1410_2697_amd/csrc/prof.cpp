@@ -10,6 +10,7 @@ namespace {
 
 const char* const kNames[PK_COUNT] = {
     "gemm_kernel<double>",        "gemm_kernel<float>",
+    "gemm_narrow_kernel<double>", "gemm_narrow_kernel<float>",
     "gemm_reduce_kernel<double>", "gemm_reduce_kernel<float>",
     "potrf_kernel<double, 64, 256>",  "potrf_kernel<float, 64, 256>",
     "potrf_kernel<double, 128, 512>", "potrf_kernel<float, 128, 512>",
@@ -45,7 +46,9 @@ struct State {
   int slot_dev = -1;
   int slots_used = 0;
 };
-bool self_timed(int kind) { return kind == PK_GEMM_F64 || kind == PK_GEMM_F32; }
+bool self_timed(int kind) {
+  return kind == PK_GEMM_F64 || kind == PK_GEMM_F32 || kind == PK_GEMMN_F64 || kind == PK_GEMMN_F32;
+}
 State& S() {
   static State s;
   return s;

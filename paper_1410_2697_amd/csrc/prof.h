@@ -16,6 +16,7 @@ namespace mfh {
 // float32 instantiations are separate kinds, float64 first.
 enum ProfKind : int {
   PK_GEMM_F64, PK_GEMM_F32,
+  PK_GEMMN_F64, PK_GEMMN_F32,          // 64 x 16 tiles (right-hand-side blocks)
   PK_GEMM_REDUCE_F64, PK_GEMM_REDUCE_F32,
   PK_POTRF64_F64, PK_POTRF64_F32,      // leaf size <= 64
   PK_POTRF128_F64, PK_POTRF128_F32,

@@ -21,8 +21,10 @@ mf_status gemm_t(int m, int n, int k, const void* A, int lda, int opA, const voi
   d.A = static_cast<const T*>(A); d.B = static_cast<const T*>(B); d.C = static_cast<T*>(C);
   d.m = m; d.n = n; d.k = k; d.lda = lda; d.ldb = ldb; d.ldc = ldc; d.opA = opA; d.opB = opB;
   d.flags = flags; d.alpha = alpha; d.beta = beta;
+  // at most 16 columns: the 64 x 16 tile variant (the reduction walks 64 x 64 tiles)
+  const int tn = n <= mfh::kTileNarrow ? mfh::kTileNarrow : mfh::kTile;
   d.tiles_m = (m + mfh::kTile - 1) / mfh::kTile;
-  d.tiles_n = (n + mfh::kTile - 1) / mfh::kTile;
+  d.tiles_n = (n + tn - 1) / tn;
   d.tile0 = 0;
   d.ksplit = 1;
   if (kchunk > 0 && k > 0) {
@@ -32,15 +34,18 @@ mf_status gemm_t(int m, int n, int k, const void* A, int lda, int opA, const voi
   const int otiles = d.tiles_m * d.tiles_n;
   if (otiles == 0) return MF_OK;
   mfh::GemmDesc<T>* dd = nullptr;
-  mf_status s = hip_ok(hipMalloc(&dd, sizeof(d)));
+  mf_status s = hip_ok(hipMalloc(&dd, 2 * sizeof(d)));
   if (s != MF_OK) return s;
   if (d.ksplit > 1) {
     s = hip_ok(hipMalloc(&d.part, (size_t)d.ksplit * m * n * sizeof(T)));
     if (s != MF_OK) { hipFree(dd); return s; }
   }
+  mfh::GemmDesc<T> r = d;
+  r.tiles_n = (n + mfh::kTile - 1) / mfh::kTile;
   hipMemcpy(dd, &d, sizeof(d), hipMemcpyHostToDevice);
-  mfh::launch_gemm<T>(dd, 1, otiles * d.ksplit, nullptr);
-  if (d.ksplit > 1) mfh::launch_gemm_reduce<T>(dd, 1, otiles, nullptr);
+  hipMemcpy(dd + 1, &r, sizeof(r), hipMemcpyHostToDevice);
+  mfh::launch_gemm<T>(dd, 1, otiles * d.ksplit, nullptr, tn);
+  if (d.ksplit > 1) mfh::launch_gemm_reduce<T>(dd + 1, 1, r.tiles_m * r.tiles_n, nullptr);
   s = hip_ok(hipDeviceSynchronize());
   hipFree(dd);
   if (d.part) hipFree(d.part);
