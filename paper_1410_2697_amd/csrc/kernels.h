@@ -116,7 +116,7 @@ struct Phase2Desc {
 };
 
 // rows of a block the multi-workgroup phase 2 takes (one bit per row and lane)
-constexpr int kPhase2CoopMaxRows = 4096;
+constexpr int kPhase2CoopMaxRows = 8192;
 
 // Phase 2 spread over workgroups: workgroup j of a block keeps the residual
 // columns [j*wcols, min(nc, (j+1)*wcols)) in LDS for the whole pivot loop.

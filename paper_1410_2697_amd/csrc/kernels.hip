@@ -962,10 +962,14 @@ __global__ __launch_bounds__(256) void phase2_coop_kernel(const Phase2CoopDesc<T
     if (cc >= 0 && cc < w) lc[cc] = 0;
   }
   __syncthreads();
-  // live rows of this lane (rows lane + 64 k; nr <= kPhase2CoopMaxRows) as bits
-  u64 lmask = 0;
-  for (int k = 0; k < 64 && lane + 64 * k < nr; ++k)
-    if (lr[lane + 64 * k]) lmask |= 1ull << k;
+  // live rows of this lane (rows lane + 64 k; nr <= kPhase2CoopMaxRows) as
+  // bits, k < 64 in lmask0 and the rest in lmask1
+  u64 lmask0 = 0, lmask1 = 0;
+  for (int k = 0; k < 128 && lane + 64 * k < nr; ++k)
+    if (lr[lane + 64 * k]) {
+      if (k < 64) lmask0 |= 1ull << k;
+      else lmask1 |= 1ull << (k - 64);
+    }
   double u11 = *d.u11;
   const double stop_rel = fmax(eps, (double)noise_rel<T>());
   constexpr u64 kTag = 1ull << 63;
@@ -980,7 +984,8 @@ __global__ __launch_bounds__(256) void phase2_coop_kernel(const Phase2CoopDesc<T
     // best is (truncated magnitude, position), visited in ascending position
     unsigned bq = 0, bidx = 0;
     auto consider = [&](T x, int i, unsigned base) {
-      const unsigned q = ((lmask >> (i >> 6)) & 1ull) ? qmag(x) : 0u;
+      const int k = i >> 6;
+      const unsigned q = (((k < 64 ? lmask0 : lmask1) >> (k & 63)) & 1ull) ? qmag(x) : 0u;
       if (q > bq) { bq = q; bidx = base + (unsigned)i; }
     };
     for (int c = wave; c < w; c += nwave) {
@@ -1096,7 +1101,11 @@ __global__ __launch_bounds__(256) void phase2_coop_kernel(const Phase2CoopDesc<T
       lr[a] = 0;
       if (b >= cb0 && b < cb0 + w) lc[b - cb0] = 0;
     }
-    if (lane == (a & 63)) lmask &= ~(1ull << (a >> 6));
+    if (lane == (a & 63)) {
+      const int k = a >> 6;
+      if (k < 64) lmask0 &= ~(1ull << k);
+      else lmask1 &= ~(1ull << (k - 64));
+    }
     ++r;
     pending = true;
     __syncthreads();

@@ -223,7 +223,7 @@ def test_skeleton_fp64_matches_oracle(gpu_lib, adaptive, nr, nc, nI, nJ, eps):
 
 @pytest.mark.parametrize("adaptive", [1, 2, 3])
 @pytest.mark.parametrize("nr,nc,nI,nJ", [(200, 150, 40, 40), (600, 300, 120, 100), (256, 256, 16, 16),
-                                         (1100, 700, 150, 150)])
+                                         (1100, 700, 150, 150), (4300, 160, 64, 64)])
 def test_skeleton_fp32_error_bound(gpu_lib, adaptive, nr, nc, nI, nJ):
     """FP32 whole-block and large-block paths: the adaptive skeleton meets the
     max-norm contract (up to float32 rounding of the residual)."""
