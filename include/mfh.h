@@ -71,10 +71,12 @@ typedef struct {
                            basis W) to bfloat16 right after compression and keep them in
                            bfloat16; the factorisation and the apply both use the rounded
                            values, so the preconditioner is that of the rounded matrix     */
-  int32_t apply_graph;  /* 1 (default): the preconditioner apply (Sec. 4.1.3) records its
-                           kernel sequence once per right-hand-side count as a HIP graph
-                           and replays it; 0: each kernel is launched on every apply.
-                           While mf_prof_start times the GEMM kernels the apply
+  int32_t apply_graph;  /* k >= 1 (default 4): the k-th preconditioner apply (Sec. 4.1.3)
+                           with a given right-hand-side count records its kernel sequence
+                           as a HIP graph, and it and every later apply with that count
+                           replay it; earlier applies launch each kernel (recording costs
+                           about as much as a few applies).  0: never record.  At most
+                           2^20.  While mf_prof_start times the GEMM kernels the apply
                            launches them directly.                                         */
   int32_t reserved0;    /* must be 0 */
   double eps;           /* low-rank tolerance (Sec. 2.2: stop when |u_r+1,r+1/u_11| < eps) */

@@ -68,7 +68,7 @@ mf_status mf_opts_default(mf_opts* o) {
   o->bdlr_cap = 0;
   o->adaptive = 1;
   o->rank_cap = 512;
-  o->apply_graph = 1;
+  o->apply_graph = 4;
   o->eps = 1e-4;
   o->stream = nullptr;
   return MF_OK;
@@ -186,8 +186,8 @@ mf_status mf_factor(const mf_symbolic_t* sh, const double* vals, double eps, int
   if (o.uv_bf16 && o.method != MF_METHOD_HODLR) return fail(MF_EINVAL, "uv_bf16 needs MF_METHOD_HODLR");
   if (o.precision != MF_FP64 && o.precision != MF_FP32) return fail(MF_EINVAL, "unknown precision");
   if (!(eps >= 0.0) || eps >= 1.0) return fail(MF_EINVAL, "eps must be in [0, 1)");
-  if ((o.apply_graph != 0 && o.apply_graph != 1) || o.reserved0 != 0)
-    return fail(MF_EINVAL, "apply_graph must be 0 or 1 and reserved0 0");
+  if (o.apply_graph < 0 || o.apply_graph > (1 << 20) || o.reserved0 != 0)
+    return fail(MF_EINVAL, "apply_graph must be in [0, 2^20] and reserved0 0");
   if (leaf != 0 && leaf != sh->s.leaf) return fail(MF_EINVAL, "leaf must be 0 or the analysis leaf size");
   if (o.method == MF_METHOD_HODLR) {
     if (sh->s.leaf > 128) return fail(MF_EINVAL, "HODLR leaves are limited to 128");

@@ -271,6 +271,9 @@ int gj_kind(int nmax);
 void launch_gj_inverse(const InvDesc* d, int ndesc, int nmax, int* status, hipStream_t st);
 template <typename T>
 void launch_fill(T* p, int64_t n, T v, hipStream_t st);
+// out[0..na+nb] = a[0..na), b[0..nb), *c; out may be pinned host memory
+// (its device address)
+void launch_readback(const int* a, int na, const int* b, int nb, const int* c, int* out, hipStream_t st);
 template <typename T>
 void launch_assemble(T* base, const int64_t* dest, const int* src, const double* vals, int64_t cnt,
                      hipStream_t st);

@@ -378,6 +378,16 @@ __device__ __forceinline__ double uniform(double v) {
   return __longlong_as_double((long long)(((u64)hi << 32) | lo));
 }
 __device__ __forceinline__ unsigned uniform(unsigned v) { return (unsigned)__builtin_amdgcn_readfirstlane((int)v); }
+// value of v in lane l (l wave-uniform), in a scalar register
+__device__ __forceinline__ float lane_value(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b & 0xFFFFFFFFll), l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)((unsigned long long)b >> 32), l);
+  return __longlong_as_double((long long)(((u64)hi << 32) | lo));
+}
 __device__ __forceinline__ u64 uniform(u64 v) {
   return ((u64)uniform((unsigned)(v >> 32)) << 32) | uniform((unsigned)(v & 0xFFFFFFFFull));
 }
@@ -504,8 +514,8 @@ __global__ __launch_bounds__(NT) void skreg_kernel(const SkRegDesc<T>* __restric
   static_assert(RI * CJ <= 128 && MR < 65536 && MC < 65536, "register block too large");
   typedef typename RegRow<T, CJ>::type row_t;
   constexpr unsigned kMag = sizeof(T) == 4 ? 0x7FFFFF80u : 0x7FFFFFFFu;
-  __shared__ __align__(16) T s_row[CG][CJ];     // pivot row, by (column group, j)
-  __shared__ T s_col[MR];
+  __shared__ T s_cc[2][CG][MR];                 // candidate column of each wave
+  __shared__ __align__(16) T s_wrow[FULL ? CG : 1][CJ];   // pivot row, per wave
   __shared__ u64 s_red[2][CG];
   __shared__ char s_inI[FULL ? MR : 1];
   __shared__ char s_inJ[FULL ? MC : 1];
@@ -515,7 +525,10 @@ __global__ __launch_bounds__(NT) void skreg_kernel(const SkRegDesc<T>* __restric
   const int t = threadIdx.x, lane = t & 63;
   const int g = (int)uniform((unsigned)(t >> 6));
   const int M = FULL ? d.nr : d.nI, N = FULL ? d.nc : d.nJ;
-  row_t e[RI];
+  // B_hat mode: a pivot column is zeroed in e once its step is done (so the
+  // search and the update need no column mask) and kept in m: the
+  // multipliers in rows that were live, the U entries in the others
+  row_t e[RI], m[FULL ? 1 : RI];
   unsigned rl = 0, cl = 0, inI = 0, inJ = 0;
 #pragma unroll
   for (int i = 0; i < RI; ++i)
@@ -575,11 +588,14 @@ __global__ __launch_bounds__(NT) void skreg_kernel(const SkRegDesc<T>* __restric
   // Phase 1 searches I x J (whole-block mode) or all of B_hat; phase 2 (the
   // adaptive phase) the whole residual block.  Empty BDLR sets start in
   // phase 2, or stop at rank 0 without it.  Each pivot step: search the
-  // registers, block-wide max of the pivot keys (one barrier; the wave keys
-  // alternate between two LDS buffers), the pivot row and column through LDS
-  // (one barrier), then the rank-1 update.  The next step's first LDS writes
-  // come after its own reduction barrier, so no barrier closes a step.  The
-  // inner loop has a single latch, which keeps the register block in place.
+  // registers; every wave writes its best key and the column holding it to
+  // LDS (two buffers, alternating by step); one barrier; every wave takes the
+  // block-wide max key, reads the pivot column from the winner's buffer and
+  // the pivot row of its own columns from the lane that holds it; then the
+  // rank-1 update.  A buffer is written again two steps later, after a
+  // barrier that every reader of it has passed, so one barrier per step
+  // suffices.  The inner loop has a single latch, which keeps the register
+  // block in place.
   const int last = FULL && adaptive ? 2 : 1;
   int phase = (FULL && !(d.nI > 0 && d.nJ > 0)) ? 2 : 1;
   bool capped = false;
@@ -599,7 +615,7 @@ __global__ __launch_bounds__(NT) void skreg_kernel(const SkRegDesc<T>* __restric
         unsigned bk = 0;
 #pragma unroll
         for (int j = 0; j < CJ; ++j) {
-          if (!((csel >> j) & 1u)) continue;
+          if (FULL && !((csel >> j) & 1u)) continue;
 #pragma unroll
           for (int i = 0; i < RI; ++i) {
             const unsigned w = (__float_as_uint(e[i][j]) & rm[i]) | (unsigned)(127 - (j * RI + i));
@@ -614,7 +630,7 @@ __global__ __launch_bounds__(NT) void skreg_kernel(const SkRegDesc<T>* __restric
         unsigned bq = 0, bl = 0;
 #pragma unroll
         for (int j = 0; j < CJ; ++j) {
-          if (!((csel >> j) & 1u)) continue;
+          if (FULL && !((csel >> j) & 1u)) continue;
 #pragma unroll
           for (int i = 0; i < RI; ++i) {
             const unsigned x = (unsigned)((u64)__double_as_longlong(e[i][j]) >> 32) & rm[i];
@@ -626,37 +642,33 @@ __global__ __launch_bounds__(NT) void skreg_kernel(const SkRegDesc<T>* __restric
         l = m >> 6;
         wl = m & 63u;
       }
-      {
-        const unsigned jw = l / RI, iw = l - jw * RI;
+      // the wave's candidate (its best element) goes to LDS with the column
+      // that holds it, so the winner's column is there after the one barrier
+      const unsigned jw = l / RI, iw = l - jw * RI;
+      const int cur = par;
+      par ^= 1;
+      if (q) {
+#pragma unroll
+        for (int i = 0; i < RI; ++i) s_cc[cur][g][lane + 64 * i] = e[i][jw];
+      }
+      if (lane == 0) {
         const unsigned pos = (((unsigned)g + CG * jw) << 16) | (wl + 64u * iw);
-        if (lane == 0) s_red[par][g] = q ? (((u64)q) << 32) | (u64)(0xFFFFFFFFu - pos) : 0ull;
+        s_red[cur][g] = q ? (((u64)q) << 32) | (u64)(0xFFFFFFFFu - pos) : 0ull;
       }
       __syncthreads();
-      u64 K = s_red[par][0];
+      u64 K = s_red[cur][0];
 #pragma unroll
-      for (int k = 1; k < CG; ++k) K = s_red[par][k] > K ? s_red[par][k] : K;
+      for (int k = 1; k < CG; ++k) K = s_red[cur][k] > K ? s_red[cur][k] : K;
       K = uniform(K);
-      par ^= 1;
       if (K == 0ull) break;
       const unsigned pos = 0xFFFFFFFFu - (unsigned)(K & 0xFFFFFFFFull);
       const int as = (int)(pos & 0xFFFFu), bs = (int)(pos >> 16);
-      const int ia = as >> 6, gb = bs % CG, jb = bs / CG;
-      // row choice by a uniform branch, lane choice inside it: a select
-      // over whole rows would cost every wave RI x CJ moves
+      const int ia = as >> 6, la = as & 63, gb = bs % CG, jb = bs / CG;
+      const T* cc = s_cc[cur][gb];
+      const T piv = uniform(cc[as]);
+      T c[RI];
 #pragma unroll
-      for (int i = 0; i < RI; ++i)
-        if (i == ia) {
-          if (lane == (as & 63)) {
-#pragma unroll
-            for (int j = 0; j < CJ; ++j) s_row[g][j] = (FULL || ((cl >> j) & 1u)) ? e[i][j] : (T)0;
-          }
-        }
-      if (g == gb) {
-#pragma unroll
-        for (int i = 0; i < RI; ++i) s_col[lane + 64 * i] = e[i][jb];
-      }
-      __syncthreads();
-      const T piv = uniform(s_row[gb][jb]);
+      for (int i = 0; i < RI; ++i) c[i] = cc[lane + 64 * i];
       if (u11 == (T)0) u11 = fabs(piv);
       if (fabs(piv) < stop_rel * u11) break;
       if (r >= d.cap) {
@@ -665,51 +677,87 @@ __global__ __launch_bounds__(NT) void skreg_kernel(const SkRegDesc<T>* __restric
         break;
       }
       const T rpiv = (T)1 / piv;
+      if (FULL && t == 0) {
+        gstore(d.piv_r + r, d.r0 + as);
+        gstore(d.piv_c + r, d.c0 + bs);
+      }
       if (FULL) {
-        if (t == 0) {
-          gstore(d.piv_r + r, d.r0 + as);
-          gstore(d.piv_c + r, d.c0 + bs);
-        }
         T* Uc = d.U + (size_t)r * d.ldu;
-        T* Vc = d.V + (size_t)r * d.ldv;
-        for (int a = t; a < M; a += NT) gstore(Uc + a, phase == 1 ? s_col[a] / piv : s_col[a]);
-        for (int b = t; b < N; b += NT)
-          gstore(Vc + b, phase == 1 ? s_row[b % CG][b / CG] : s_row[b % CG][b / CG] / piv);
-        row_t u;
+        for (int a = t; a < M; a += NT) gstore(Uc + a, phase == 1 ? cc[a] / piv : cc[a]);
+      }
+      // multipliers: whole-block mode updates every row (the pivot row and
+      // column become zero up to rounding); the LU of B_hat updates live rows
+      // other than the pivot row, then moves its pivot column to m (the
+      // multipliers l = e / piv in the rows that were live) and zeroes it
+      T li[RI];
+      unsigned upd = 0;
 #pragma unroll
-        for (int j = 0; j < CJ; ++j) u[j] = s_row[g][j];
+      for (int i = 0; i < RI; ++i) {
+        const bool w = FULL || (((rl >> i) & 1u) && lane + 64 * i != as);
+        li[i] = w ? c[i] * rpiv : (T)0;
+        if (w) upd |= 1u << i;
+      }
+      if constexpr (FULL) {
+        // whole-block mode is bound by the vector ALU, so the pivot row of
+        // the wave's columns goes through a per-wave LDS row: written by the
+        // lane that holds it and read back by the same wave (LDS operations
+        // of a wave complete in order, so no barrier)
 #pragma unroll
-        for (int i = 0; i < RI; ++i) e[i] -= (s_col[lane + 64 * i] * rpiv) * u;
-      } else {
-        // in-place LU of B_hat: live rows other than the pivot row take the
-        // update (the pivot row broadcast holds zeros in dead columns, and
-        // the other rows get a zero multiplier); the pivot column then
-        // stores the multipliers l = e / piv
-        T li[RI];
-        unsigned upd = 0;
+        for (int i0 = 0; i0 < RI; ++i0)
+          if (i0 == ia) {
+            if (lane == la) {
 #pragma unroll
-        for (int i = 0; i < RI; ++i) {
-          const int a = lane + 64 * i;
-          const bool u = ((rl >> i) & 1u) && a != as;
-          const T v = s_col[a];
-          li[i] = u ? v * rpiv : (T)0;
-          if (u) upd |= 1u << i;
+              for (int j = 0; j < CJ; ++j) s_wrow[g][j] = e[i0][j];
+            }
+          }
+        __builtin_amdgcn_wave_barrier();
+        // lane j stores the wave's column g + CG j (zero in dead columns,
+        // which hold rounding residue)
+        if (lane < CJ && g + CG * lane < N) {
+          const T vv = ((cl >> lane) & 1u) ? s_wrow[g][lane] : (T)0;
+          gstore(d.V + (size_t)r * d.ldv + g + CG * lane, phase == 1 ? vv : vv / piv);
         }
-        row_t u;
+        // the update in two halves of the row, which keeps FP64 blocks
+        // within the register budget of 1024 threads
+        constexpr int CH = CJ / 2;
 #pragma unroll
-        for (int j = 0; j < CJ; ++j) u[j] = s_row[g][j];
+        for (int h = 0; h < 2; ++h) {
+          T u[CH];
 #pragma unroll
-        for (int i = 0; i < RI; ++i) e[i] -= li[i] * u;
+          for (int j = 0; j < CH; ++j) u[j] = s_wrow[g][h * CH + j];
+#pragma unroll
+          for (int i = 0; i < RI; ++i)
+#pragma unroll
+            for (int j = 0; j < CH; ++j) e[i][h * CH + j] -= li[i] * u[j];
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      } else {
+        // B_hat mode is bound by the latency of a step: the pivot row of the
+        // wave's columns is read from the lane that holds it into scalar
+        // registers, the code repeated per register row so the row index is
+        // static.  Dead columns are zero, so they take no update.
+#pragma unroll
+        for (int i0 = 0; i0 < RI; ++i0)
+          if (i0 == ia) {
+            row_t u;
+#pragma unroll
+            for (int j = 0; j < CJ; ++j) u[j] = lane_value(e[i0][j], la);
+#pragma unroll
+            for (int i = 0; i < RI; ++i) e[i] -= li[i] * u;
+          }
+      }
+      if (!FULL) {
         if (g == gb) {
 #pragma unroll
           for (int i = 0; i < RI; ++i) {
             const T v = e[i][jb];
-            e[i][jb] = ((upd >> i) & 1u) ? li[i] : v;
+            m[i][jb] = ((upd >> i) & 1u) ? li[i] : v;
+            e[i][jb] = (T)0;
           }
         }
         if (t == 0) { s_rstep[as] = (short)r; s_cstep[bs] = (short)r; }
       }
-      if (lane == (as & 63)) rl &= ~(1u << ia);
+      if (lane == la) rl &= ~(1u << ia);
       if (g == gb) cl &= ~(1u << jb);
       ++r;
     }
@@ -739,7 +787,7 @@ __global__ __launch_bounds__(NT) void skreg_kernel(const SkRegDesc<T>* __restric
         const int b = g + CG * j;
         if (b >= N) continue;
         const int c = s_cstep[b];
-        if (c >= 0) d.M[s + (size_t)c * d.ldm] = e[i][j];
+        if (c >= 0) d.M[s + (size_t)c * d.ldm] = m[i][j];
       }
     }
   }
@@ -1358,6 +1406,16 @@ __global__ void fill_kernel(T* p, int64_t n, T v) {
     p[i] = v;
 }
 
+// The host's view of a level: a[0..na), b[0..nb) and *c, in that order, written
+// straight into pinned host memory (one launch in place of three copies).
+__global__ void readback_kernel(const int* __restrict__ a, int na, const int* __restrict__ b, int nb,
+                                const int* __restrict__ c, int* out) {
+  const int n = na + nb + 1;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    out[i] = i < na ? a[i] : (i < na + nb ? b[i - na] : *c);
+  __threadfence_system();
+}
+
 template <typename T>
 __global__ void assemble_kernel(T* base, const int64_t* __restrict__ dest, const int* __restrict__ src,
                                 const double* __restrict__ vals, int64_t cnt) {
@@ -1643,6 +1701,10 @@ template <typename T>
 void launch_fill(T* p, int64_t n, T v, hipStream_t st) {
   if (n <= 0) return;
   MFH_LAUNCH(fill_kernel<T>, dim3(grid_for(n)), dim3(256), 0, st, p, n, v);
+}
+void launch_readback(const int* a, int na, const int* b, int nb, const int* c, int* out, hipStream_t st) {
+  const int n = na + nb + 1;
+  MFH_LAUNCH(readback_kernel, dim3((n + 255) / 256), dim3(256), 0, st, a, na, b, nb, c, out);
 }
 template <typename T>
 void launch_assemble(T* base, const int64_t* dest, const int* src, const double* vals, int64_t cnt, hipStream_t st) {

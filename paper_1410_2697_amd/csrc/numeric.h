@@ -39,6 +39,9 @@ struct DevBuf {
   void release();
   void alloc(size_t b, MemStats* m);        // throws Err on failure
   void ensure(size_t b, MemStats* m, hipStream_t st);   // grows (synchronising) when needed
+  // grows without synchronising: the old block moves to `retired`, whose
+  // owner releases it after the stream work that may use it has finished
+  void grow(size_t b, MemStats* m, std::vector<std::unique_ptr<DevBuf>>& retired);
   template <typename T> T* as() const { return static_cast<T*>(p); }
 };
 

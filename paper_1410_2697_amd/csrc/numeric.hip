@@ -122,6 +122,22 @@ void DevBuf::ensure(size_t b, MemStats* m, hipStream_t st) {
   alloc(std::max(b, bytes + bytes / 2), m);
 }
 
+void DevBuf::grow(size_t b, MemStats* m, std::vector<std::unique_ptr<DevBuf>>& retired) {
+  if (p && b <= bytes) return;
+  const size_t want = std::max(b, bytes + bytes / 2);
+  if (p) {
+    auto old = std::make_unique<DevBuf>();
+    old->p = p;
+    old->bytes = bytes;
+    old->ms = ms;
+    old->dev = dev;
+    p = nullptr;
+    bytes = 0;
+    retired.push_back(std::move(old));
+  }
+  alloc(want, m);
+}
+
 void* Arena::alloc(size_t bytes) {
   bytes = (bytes + 255) & ~size_t(255);
   if (chunks.empty() || off + bytes > chunks.back()->bytes) {
@@ -142,18 +158,124 @@ namespace {
 
 inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 
-// Uploads descriptor blobs; device memory and host copies live until the
-// pool is destroyed, so no upload can race with a pending reader.
+// Pinned host staging.  A copy from pageable host memory is not queued: it
+// returns only once the stream has reached it, so each descriptor upload or
+// rank read-back would leave the device idle while the host plans the next
+// launches.  Copies to and from pinned memory are queued.  Chunks come from
+// a process-wide free list; an owner gives its chunks back only once its
+// streams are done with them.
+class PinnedPool {
+ public:
+  struct Chunk {
+    char* p = nullptr;
+    size_t bytes = 0;
+  };
+  static Chunk get(size_t bytes) {
+    {
+      std::lock_guard<std::mutex> g(mu());
+      std::vector<Chunk>& fl = list();
+      for (size_t i = 0; i < fl.size(); ++i)
+        if (fl[i].bytes >= bytes) {
+          const Chunk c = fl[i];
+          fl.erase(fl.begin() + (std::ptrdiff_t)i);
+          return c;
+        }
+    }
+    Chunk c;
+    c.bytes = std::max(bytes, kMinChunk);
+    void* p = nullptr;
+    if (hipHostMalloc(&p, c.bytes, hipHostMallocPortable) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      throw Err{MF_ENOMEM, "pinned host allocation of " + std::to_string(c.bytes) + " bytes failed"};
+    }
+    c.p = static_cast<char*>(p);
+    return c;
+  }
+  static void put(const Chunk& c) {
+    if (!c.p) return;
+    std::lock_guard<std::mutex> g(mu());
+    std::vector<Chunk>& fl = list();
+    size_t held = 0;
+    for (const Chunk& x : fl) held += x.bytes;
+    if (held + c.bytes > kMaxHeld) {
+      (void)hipHostFree(c.p);
+      return;
+    }
+    fl.push_back(c);
+  }
+
+ private:
+  static constexpr size_t kMinChunk = (size_t)1 << 20, kMaxHeld = (size_t)64 << 20;
+  static std::mutex& mu() {
+    static std::mutex m;
+    return m;
+  }
+  // never destroyed: chunks still listed at exit go with the process
+  static std::vector<Chunk>& list() {
+    static std::vector<Chunk>* l = new std::vector<Chunk>();
+    return *l;
+  }
+};
+
+// One pinned chunk for a function's small transfers, given back once the
+// stream has finished (also when the function throws).
+struct PinnedScratch {
+  PinnedPool::Chunk c;
+  hipStream_t st;
+  PinnedScratch(size_t bytes, hipStream_t s) : c(PinnedPool::get(bytes)), st(s) {}
+  PinnedScratch(const PinnedScratch&) = delete;
+  PinnedScratch& operator=(const PinnedScratch&) = delete;
+  ~PinnedScratch() {
+    (void)hipStreamSynchronize(st);
+    PinnedPool::put(c);
+  }
+  template <typename D>
+  D* as(size_t off_bytes) { return reinterpret_cast<D*>(c.p + off_bytes); }
+};
+
+// Uploads descriptor blobs through pinned staging.  The device copies live
+// until the pool is destroyed; its owner has synchronised the streams that
+// read them (and the staged copies) by then.
 struct DescPool {
   Arena ar;
-  std::vector<std::vector<char>> keep;
+  std::vector<PinnedPool::Chunk> stage;
+  size_t off = 0;
+  DescPool() = default;
+  DescPool(const DescPool&) = delete;
+  DescPool& operator=(const DescPool&) = delete;
+  ~DescPool() { release_staging(); }
+  // the streams that copied from the staging chunks have finished
+  void release_staging() {
+    for (const PinnedPool::Chunk& c : stage) PinnedPool::put(c);
+    stage.clear();
+    off = 0;
+  }
   char* upload(Blob& b, hipStream_t st) {
     if (b.h.empty()) return nullptr;
-    void* d = ar.alloc(b.h.size());
-    keep.push_back(std::move(b.h));
+    const size_t n = b.h.size();
+    void* d = ar.alloc(n);
+    if (stage.empty() || off + n > stage.back().bytes) {
+      stage.push_back(PinnedPool::get(n));
+      off = 0;
+    }
+    char* h = stage.back().p + off;
+    off = (off + n + 255) & ~size_t(255);
+    memcpy(h, b.h.data(), n);
     b.h = std::vector<char>();
-    HIPCHK(hipMemcpyAsync(d, keep.back().data(), keep.back().size(), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d, h, n, hipMemcpyHostToDevice, st));
     return static_cast<char*>(d);
+  }
+  // pinned host space for n bytes of read-back, valid until the pool goes
+  template <typename D>
+  D* host(size_t n) {
+    const size_t bytes = n * sizeof(D);
+    if (stage.empty() || off + bytes > stage.back().bytes) {
+      stage.push_back(PinnedPool::get(bytes));
+      off = 0;
+    }
+    D* h = reinterpret_cast<D*>(stage.back().p + off);
+    off = (off + bytes + 255) & ~size_t(255);
+    return h;
   }
 };
 
@@ -455,6 +577,9 @@ class Numeric : public NumericBase {
     return bf16 ? reinterpret_cast<T*>(arena.alloc_n<unsigned short>(n)) : arena.alloc_n<T>(n);
   }
   DevBuf ws, scrA, scrB, d_asm_dest, d_asm_src, d_relmap;
+  // blocks replaced by a growing scratch buffer, released at the next
+  // synchronisation (the level's rank read-back, the end of the factor)
+  std::vector<std::unique_ptr<DevBuf>> retired;
   DevBuf split;                   // split-K partial sums of the factor's GEMM batches
   std::vector<int64_t> relmap_off;
   std::vector<int64_t> asm_lvl_off;
@@ -503,6 +628,7 @@ class Numeric : public NumericBase {
     DescPool dp;
     std::vector<Rec> recs;
     T* xn = nullptr;
+    int uses = 0;                    // applies with this right-hand-side count so far
     hipGraphExec_t exec = nullptr;   // the recs recorded once (apply_graph)
     bool no_graph = false;           // recording failed: launch directly
     ~Plan() {
@@ -727,11 +853,13 @@ Numeric<T>::Numeric(const Symbolic& s, const double* vals, const mf_opts& o) {
     dense_level(D);
     hodlr_level(Hf, h);
   }
+  int* hstat = dp.host<int>(1);
+  HIPCHK(hipMemcpyAsync(hstat, d_status.p, sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(st));
-  int status = 0;
-  HIPCHK(hipMemcpy(&status, d_status.p, sizeof(int), hipMemcpyDeviceToHost));
+  const int status = *hstat;
   info.status_bits = status;
+  retired.clear();
   // release transient storage (the apply has its own workspaces and descriptors)
   ws.release();
   scrA.release();
@@ -744,7 +872,7 @@ Numeric<T>::Numeric(const Symbolic& s, const double* vals, const mf_opts& o) {
   relmap_h = {};
   dp.ar.chunks.clear();
   dp.ar.off = 0;
-  dp.keep.clear();
+  dp.release_staging();
   lvb.clear();
   fbd.clear();
   info.persistent_bytes = arena.used;
@@ -834,7 +962,7 @@ void Numeric<T>::dense_level(const std::vector<int>& D) {
     }
     tmax = std::max(tmax, need);
   }
-  scrB.ensure(std::max<int64_t>(tmax, 1) * sizeof(T), &ms, st);
+  scrB.grow(std::max<int64_t>(tmax, 1) * sizeof(T), &ms, retired);
   for (int sz = kNB; sz < maxnp; sz *= 2) {
     Dbl dd;
     T* tp = scrB.as<T>();
@@ -982,7 +1110,7 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
     need += al((size_t)B.nr * x.capr * sizeof(T)) + al((size_t)B.nc * x.capr * sizeof(T));
   }
   need += al((size_t)std::max<int64_t>(nslots, 1) * sizeof(unsigned long long));
-  scrA.ensure(need, &ms, st);
+  scrA.grow(need, &ms, retired);
   char* cur = static_cast<char*>(scrA.p);
   auto take = [&](size_t bytes) { char* r = cur; cur += al(bytes); return r; };
   // every multi-workgroup block's tagged key slots, in one range
@@ -1131,14 +1259,16 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
     }
   }
   if (fork) HIPCHK(hipStreamWaitEvent(st, ev_join, 0));
-  // ---- the one synchronisation of the level: ranks to the host
-  std::vector<int> hr(nb), h1(nb);
-  int status = 0;
-  HIPCHK(hipMemcpyAsync(hr.data(), rankf, nb * sizeof(int), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipMemcpyAsync(h1.data(), rank1, nb * sizeof(int), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipMemcpyAsync(&status, d_status.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  // ---- the one synchronisation of the level: ranks to the host (pinned)
+  int* hb = dp.host<int>(2 * (size_t)nb + 1);
+  int* hb_dev = nullptr;
+  HIPCHK(hipHostGetDevicePointer(reinterpret_cast<void**>(&hb_dev), hb, 0));
+  launch_readback(rankf, nb, rank1, nb, d_status.as<int>(), hb_dev, st);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(st));
+  const std::vector<int> hr(hb, hb + nb), h1(hb + nb, hb + 2 * nb);
+  const int status = hb[2 * nb];
+  retired.clear();
   if (status & 2) throw Err{MF_ECAPACITY, "a block rank exceeded rank_cap"};
   if (status & 8) throw Err{MF_EHIP, "phase-2 workgroups did not meet at their barrier"};
   for (int i = 0; i < nb; ++i) ranks[br[i].gb] = hr[i];
@@ -1286,7 +1416,7 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
     }
   }
   // leaf solves on G:  G_leaf <- L^{-T} L^{-1} G_leaf
-  scrB.ensure(std::max<int64_t>(t1_tot, 1) * sizeof(T), &ms, st);
+  scrB.grow(std::max<int64_t>(t1_tot, 1) * sizeof(T), &ms, retired);
   {
     T* tp = scrB.as<T>();
     for (int p : Hs) {
@@ -1333,7 +1463,7 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
       }
     }
     if (nodes.empty()) continue;
-    scrB.ensure(nP + nK + nPa + nQ, &ms, st);
+    scrB.grow(nP + nK + nPa + nQ, &ms, retired);
     char* cb = static_cast<char*>(scrB.p);
     auto tk = [&](size_t bytes) { char* r = cb; cb += al(bytes); return r; };
     Blob b3;
@@ -1429,7 +1559,7 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
       need2 += al((size_t)f.npiv * r * 8) * 2 + al((size_t)f.nf() * r * 8) * 2 + al((size_t)r * r * 8) +
                al((size_t)f.nf() * r * sizeof(T));
     }
-    scrB.ensure(std::max<size_t>(need2, 256), &ms, st);
+    scrB.grow(std::max<size_t>(need2, 256), &ms, retired);
     char* cb = static_cast<char*>(scrB.p);
     auto tk = [&](size_t bytes) { char* r = cb; cb += al(bytes); return r; };
     Blob b4;
@@ -1676,9 +1806,13 @@ void Numeric<T>::apply(int nrhs, const double* r, double* z, hipStream_t stream)
   st = keep;
   const int N = sym->n;
   launch_perm_in<T>(r, pl->xn, d_perm.as<int>(), N, nrhs, stream);
-  // a recorded apply cannot time its launches: launch directly while its
-  // GEMM kernels are being timed
-  bool replay = opts.apply_graph && !pl->no_graph && !prof_selected(pk<T>(PK_GEMM_F64)) &&
+  // the apply_graph-th apply with this count records the graph (recording
+  // costs about as much as a few direct applies); a recorded apply cannot
+  // time its launches, so it launches directly while its GEMM kernels are
+  // being timed
+  ++pl->uses;
+  bool replay = opts.apply_graph > 0 && pl->uses >= opts.apply_graph && !pl->no_graph &&
+                !prof_selected(pk<T>(PK_GEMM_F64)) &&
                 !prof_selected(pk<T>(PK_GEMMN_F64)) && !prof_selected(pk<T>(PK_GEMM_REDUCE_F64));
   if (replay && !pl->exec) {
     // record the step sequence once on a stream of this handle; the plan's
@@ -1791,14 +1925,21 @@ void NumericBase::gmres(int nrhs, const double* b, double* x, double tol, const 
   double* ydev = nr2 + nrhs;              // m x nrhs
   double* part = g_partial.as<double>();
 
-  std::vector<double> hs((size_t)2 * (m + 1) * nrhs + nrhs);
+  // host sides of the small transfers in pinned memory, so they are queued
+  // copies; every one is followed by a synchronisation before the host
+  // touches the buffer again
+  const size_t nhs = (size_t)2 * (m + 1) * nrhs + nrhs, nys = (size_t)m * nrhs;
+  PinnedScratch pin((nhs + nrhs + nys) * sizeof(double), st);
+  double* hs = pin.as<double>(0);
+  double* nrm2_h = hs + nhs;
+  double* ybuf_h = nrm2_h + nrhs;
   auto read_small = [&](int count) {
-    HIPCHK(hipMemcpyAsync(hs.data(), sm, count * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(hs, sm, count * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
   };
   // ||b||
   launch_mdot(b, 0, 1, b, N, nrhs, part, nr2, 0, st);
-  HIPCHK(hipMemcpyAsync(hs.data(), nr2, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(hs, nr2, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   std::vector<double> bnorm(nrhs), beta(nrhs);
   for (int k = 0; k < nrhs; ++k) bnorm[k] = std::sqrt(hs[k]);
@@ -1821,7 +1962,8 @@ void NumericBase::gmres(int nrhs, const double* b, double* x, double tol, const 
     if (!any) break;
     std::vector<char> act(nrhs);
     for (int k = 0; k < nrhs; ++k) act[k] = !conv[k] && iters[k] < maxit;
-    HIPCHK(hipMemcpyAsync(nr2, nrm2.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
+    std::copy(nrm2.begin(), nrm2.end(), nrm2_h);
+    HIPCHK(hipMemcpyAsync(nr2, nrm2_h, nrhs * sizeof(double), hipMemcpyHostToDevice, st));
     launch_scale_cols(r, V, nr2, N, nrhs, st);
     std::fill(H.begin(), H.end(), 0.0);
     std::fill(g.begin(), g.end(), 0.0);
@@ -1887,12 +2029,13 @@ void NumericBase::gmres(int nrhs, const double* b, double* x, double tol, const 
         ybuf[i * nrhs + k] = d != 0.0 ? sacc / d : 0.0;
       }
     }
-    HIPCHK(hipMemcpyAsync(ydev, ybuf.data(), (size_t)jend * nrhs * sizeof(double), hipMemcpyHostToDevice, st));
+    std::copy(ybuf.begin(), ybuf.begin() + (std::ptrdiff_t)jend * nrhs, ybuf_h);
+    HIPCHK(hipMemcpyAsync(ydev, ybuf_h, (size_t)jend * nrhs * sizeof(double), hipMemcpyHostToDevice, st));
     launch_xupdate(Z, vs, jend, ydev, x, N, nrhs, st);
     spmv(nrhs, x, w, 1.0, 0.0, st);
     launch_axpby(b, w, r, 1.0, -1.0, vs, st);
     launch_mdot(r, 0, 1, r, N, nrhs, part, nr2, 0, st);
-    HIPCHK(hipMemcpyAsync(hs.data(), nr2, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(hs, nr2, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     for (int k = 0; k < nrhs; ++k) beta[k] = std::sqrt(hs[k]);
   }

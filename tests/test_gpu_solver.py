@@ -222,8 +222,9 @@ def test_apply_graph_replays_equal_direct_launches(gpu_lib, method, prec):
     """The recorded apply (one HIP graph per right-hand-side count, replayed)
     gives the same bits as launching every step: on each replay, with direct
     launches of another handle and host work in between, for two
-    right-hand-side counts; GMRES through the replayed apply takes the same
-    iterations to the same solution."""
+    right-hand-side counts, recorded on the first apply of a count or on a
+    later one (apply_graph = 3); GMRES through the replayed apply takes the
+    same iterations to the same solution."""
     import torch
     mfh = gpu_lib
     p = q1_grid(14, 3)
@@ -233,16 +234,20 @@ def test_apply_graph_replays_equal_direct_launches(gpu_lib, method, prec):
     eps = 1e-4 if method == "hodlr" else 0.0
     kw = dict(method=method, precision=prec, n_c=64)
     fg = mfh.Factor(sym, p.A.vals, eps, apply_graph=1, **kw)
+    fg3 = mfh.Factor(sym, p.A.vals, eps, apply_graph=3, **kw)
     fd = mfh.Factor(sym, p.A.vals, eps, apply_graph=0, **kw)
     gen = torch.Generator(device="cuda").manual_seed(5)
-    for nrhs in (3, 3, 1, 3, 1, 1):
+    for nrhs in (3, 3, 1, 3, 1, 1, 3, 1, 3):
         r = torch.randn((nrhs, n), dtype=torch.float64, device="cuda", generator=gen)
         zg = torch.zeros_like(r)
+        zg3 = torch.zeros_like(r)
         zd = torch.zeros_like(r)
         fd.apply(r, zd)
         fg.apply(r, zg)
+        fg3.apply(r, zg3)
         torch.cuda.synchronize()
         assert torch.equal(zg, zd)
+        assert torch.equal(zg3, zd)
         _ = (r * 2.0).sum().item()          # other work and a host synchronisation between replays
     b = torch.tensor(rhs(n, 2, "normal", 3).T.copy(), dtype=torch.float64, device="cuda")
     xg, xd = torch.zeros_like(b), torch.zeros_like(b)
