@@ -136,11 +136,14 @@ mf_status mf_symbolic_export(const mf_symbolic_t* sh, int32_t what, int32_t* buf
         else v.insert(v.end(), f.relmap.begin(), f.relmap.end());
       }
       return export_vec(v, buf, cap, len);
-    case MF_EXP_ASM:
-      for (size_t e = 0; e < s.asm_src.size(); ++e) {
-        v.push_back(s.asm_front[e]); v.push_back(s.asm_row[e]); v.push_back(s.asm_col[e]); v.push_back(s.asm_src[e]);
+    case MF_EXP_ASM: {
+      mfh::bigvec<int> af, ar, ac, as;
+      mfh::assembly_map(s, af, ar, ac, as);
+      for (size_t e = 0; e < as.size(); ++e) {
+        v.push_back(af[e]); v.push_back(ar[e]); v.push_back(ac[e]); v.push_back(as[e]);
       }
       return export_vec(v, buf, cap, len);
+    }
     case MF_EXP_BLOCKS:
       for (size_t p = 0; p < s.fronts.size(); ++p)
         for (auto& b : s.fronts[p].blocks) {

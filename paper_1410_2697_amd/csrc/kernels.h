@@ -274,9 +274,19 @@ void launch_fill(T* p, int64_t n, T v, hipStream_t st);
 // out[0..na+nb] = a[0..na), b[0..nb), *c; out may be pinned host memory
 // (its device address)
 void launch_readback(const int* a, int na, const int* b, int nb, const int* c, int* out, hipStream_t st);
+// One front for the assembly of A's entries (F_bar_p, Eq. fbar): element
+// offset of its buffer in the workspace, pivot range, leading dimension,
+// height, and its update set upd[upd0 .. upd0 + nupd), sorted.
+struct AsmFront {
+  int64_t off;
+  int start, npiv, ld, height, upd0, nupd;
+};
+// A's lower entries whose column lies in a front of height h, placed in that
+// front's buffer (ws + off).  rowptr/colind/vals: A in CSR (original order);
+// iperm: new index of each original index; owner: front of each new index.
 template <typename T>
-void launch_assemble(T* base, const int64_t* dest, const int* src, const double* vals, int64_t cnt,
-                     hipStream_t st);
+void launch_assemble(T* ws, const int* rowptr, const int* colind, const double* vals, const int* iperm,
+                     const int* owner, const AsmFront* fr, const int* upd, int n, int h, hipStream_t st);
 template <typename T>
 void launch_vec_asm(const VecAsmDesc<T>* d, int ndesc, int nrhs, hipStream_t st);
 template <typename T>

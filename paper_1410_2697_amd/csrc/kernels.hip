@@ -1416,11 +1416,39 @@ __global__ void readback_kernel(const int* __restrict__ a, int na, const int* __
   __threadfence_system();
 }
 
+// A's entries of one level's fronts (F_bar_p, Eq. fbar): a thread walks one
+// row r of A; each lower entry (i = iperm[r] >= j = iperm[colind[k]]) whose
+// column's front p has height h goes to row i - start of p inside its pivot
+// block, else to npiv + (the position of i in p's sorted update set), and
+// column j - start.  Every entry is written once.
 template <typename T>
-__global__ void assemble_kernel(T* base, const int64_t* __restrict__ dest, const int* __restrict__ src,
-                                const double* __restrict__ vals, int64_t cnt) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x)
-    base[dest[i]] = (T)vals[src[i]];
+__global__ void assemble_kernel(T* __restrict__ ws, const int* __restrict__ rowptr, const int* __restrict__ colind,
+                                const double* __restrict__ vals, const int* __restrict__ iperm,
+                                const int* __restrict__ owner, const AsmFront* __restrict__ fr,
+                                const int* __restrict__ upd, int n, int h) {
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+    const int i = iperm[r];
+    const int k1 = rowptr[r + 1];
+    for (int k = rowptr[r]; k < k1; ++k) {
+      const int j = iperm[colind[k]];
+      if (i < j) continue;
+      const AsmFront f = fr[owner[j]];
+      if (f.height != h) continue;
+      int row;
+      if (i < f.start + f.npiv) {
+        row = i - f.start;
+      } else {
+        int lo = 0, hi = f.nupd;                  // first position with upd >= i
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (upd[f.upd0 + mid] < i) lo = mid + 1;
+          else hi = mid;
+        }
+        row = f.npiv + lo;
+      }
+      ws[f.off + row + (int64_t)(j - f.start) * f.ld] = (T)vals[k];
+    }
+  }
 }
 
 // one workgroup per (front, right-hand side)
@@ -1707,9 +1735,11 @@ void launch_readback(const int* a, int na, const int* b, int nb, const int* c, i
   MFH_LAUNCH(readback_kernel, dim3((n + 255) / 256), dim3(256), 0, st, a, na, b, nb, c, out);
 }
 template <typename T>
-void launch_assemble(T* base, const int64_t* dest, const int* src, const double* vals, int64_t cnt, hipStream_t st) {
-  if (cnt <= 0) return;
-  MFH_LAUNCH(assemble_kernel<T>, dim3(grid_for(cnt)), dim3(256), 0, st, base, dest, src, vals, cnt);
+void launch_assemble(T* ws, const int* rowptr, const int* colind, const double* vals, const int* iperm,
+                     const int* owner, const AsmFront* fr, const int* upd, int n, int h, hipStream_t st) {
+  if (n <= 0) return;
+  MFH_LAUNCH(assemble_kernel<T>, dim3((n + 255) / 256), dim3(256), 0, st, ws, rowptr, colind, vals, iperm, owner, fr,
+             upd, n, h);
 }
 template <typename T>
 void launch_vec_asm(const VecAsmDesc<T>* d, int ndesc, int nrhs, hipStream_t st) {
@@ -1775,8 +1805,8 @@ void launch_axpby(const double* a, const double* b, double* c, double alpha, dou
   template void launch_extadd<T>(const ExtAddDesc<T>*, int, int, hipStream_t);                   \
   template void launch_cap<T>(const CapDesc<T>*, int, hipStream_t);                              \
   template void launch_fill<T>(T*, int64_t, T, hipStream_t);                                     \
-  template void launch_assemble<T>(T*, const int64_t*, const int*, const double*, int64_t,       \
-                                   hipStream_t);                                                 \
+  template void launch_assemble<T>(T*, const int*, const int*, const double*, const int*,        \
+                                   const int*, const AsmFront*, const int*, int, int, hipStream_t); \
   template void launch_vec_asm<T>(const VecAsmDesc<T>*, int, int, hipStream_t);                  \
   template void launch_vec_gather<T>(const VecGatherDesc<T>*, int, const T*, int, int,           \
                                      hipStream_t);                                               \

@@ -576,16 +576,12 @@ class Numeric : public NumericBase {
   T* base_alloc(int64_t n, bool bf16) {
     return bf16 ? reinterpret_cast<T*>(arena.alloc_n<unsigned short>(n)) : arena.alloc_n<T>(n);
   }
-  DevBuf ws, scrA, scrB, d_asm_dest, d_asm_src, d_relmap;
+  DevBuf ws, scrA, scrB, d_owner, d_asmfr, d_upd, d_relmap;
   // blocks replaced by a growing scratch buffer, released at the next
   // synchronisation (the level's rank read-back, the end of the factor)
   std::vector<std::unique_ptr<DevBuf>> retired;
   DevBuf split;                   // split-K partial sums of the factor's GEMM batches
   std::vector<int64_t> relmap_off;
-  std::vector<int64_t> asm_lvl_off;
-  // host sources of the map uploads, kept until the factorization has synchronised
-  bigvec<int64_t> asm_hd;
-  bigvec<int> asm_hs, relmap_h;
   // second stream for the whole-block skeleton kernels, which run beside
   // the phase-1 / factor / phase-2 chain of the larger blocks of a level
   hipStream_t side = nullptr;
@@ -762,55 +758,47 @@ Numeric<T>::Numeric(const Symbolic& s, const double* vals, const mf_opts& o) {
   for (int h = 0; h < H; ++h)
     for (int p : s.levels[h]) fn[p].F = wsT + reg_off[h] + front_elem_off[p];
 
-  // ---- assembly map by level (counted and placed per chunk on the host
-  // workers, keeping each level's entries in their original order), relative maps
+  // ---- assembly tables (A's entries are placed level by level on the
+  // device: front of each index, the fronts' buffers and update sets) and the
+  // relative maps, staged through pinned memory
   {
-    const int ne = (int)s.asm_src.size();
-    const int W = max_workers();
-    std::vector<int64_t> cnt((size_t)W * H, 0);
-    parallel_for(ne, 32768, [&](int b, int e, int c) {
-      int64_t* cc = cnt.data() + (size_t)c * H;
-      for (int q = b; q < e; ++q) ++cc[s.fronts[s.asm_front[q]].height];
-    });
-    asm_lvl_off.assign(H + 1, 0);
-    std::vector<int64_t> pos((size_t)W * H);
-    int64_t tot = 0;
-    for (int h = 0; h < H; ++h) {
-      asm_lvl_off[h] = tot;
-      for (int c = 0; c < W; ++c) {
-        pos[(size_t)c * H + h] = tot;
-        tot += cnt[(size_t)c * H + h];
-      }
-    }
-    asm_lvl_off[H] = tot;
-    asm_hd.resize(tot);
-    asm_hs.resize(tot);
-    parallel_for(ne, 32768, [&](int b, int e, int c) {
-      int64_t* pp = pos.data() + (size_t)c * H;
-      for (int q = b; q < e; ++q) {
-        const int p = s.asm_front[q];
-        const int64_t o = pp[s.fronts[p].height]++;
-        asm_hd[o] = (fn[p].F - wsT) + s.asm_row[q] + (int64_t)s.asm_col[q] * fn[p].ld;
-        asm_hs[o] = s.asm_src[q];
-      }
-    });
-    d_asm_dest.alloc(std::max<int64_t>(tot, 1) * sizeof(int64_t), &ms);
-    d_asm_src.alloc(std::max<int64_t>(tot, 1) * sizeof(int), &ms);
-    HIPCHK(hipMemcpyAsync(d_asm_dest.p, asm_hd.data(), tot * sizeof(int64_t), hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(d_asm_src.p, asm_hs.data(), tot * sizeof(int), hipMemcpyHostToDevice, st));
+    int* owner_h = dp.host<int>((size_t)std::max(n, 1));
+    AsmFront* fr_h = dp.host<AsmFront>((size_t)std::max(nfr, 1));
+    std::vector<int64_t> upd_off(nfr + 1, 0);
     relmap_off.assign(nfr, 0);
     int64_t nrm = 0;
     for (int p = 0; p < nfr; ++p) {
+      const Front& f = s.fronts[p];
+      fr_h[p] = AsmFront{(int64_t)(fn[p].F - wsT), f.start, f.npiv, fn[p].ld, f.height, (int)upd_off[p],
+                         (int)f.upd.size()};
+      upd_off[p + 1] = upd_off[p] + (int64_t)f.upd.size();
       relmap_off[p] = nrm;
-      nrm += (int64_t)s.fronts[p].relmap.size();
+      nrm += (int64_t)f.relmap.size();
     }
-    relmap_h.resize(nrm);
+    const int64_t nupd = upd_off[nfr];
+    int* upd_h = dp.host<int>((size_t)std::max<int64_t>(nupd, 1));
+    int* relmap_h = dp.host<int>((size_t)std::max<int64_t>(nrm, 1));
     parallel_for(nfr, 64, [&](int b, int e, int) {
-      for (int p = b; p < e; ++p)
-        std::copy(s.fronts[p].relmap.begin(), s.fronts[p].relmap.end(), relmap_h.begin() + relmap_off[p]);
+      for (int p = b; p < e; ++p) {
+        const Front& f = s.fronts[p];
+        for (int i = 0; i < f.npiv; ++i) owner_h[f.start + i] = p;
+        std::copy(f.upd.begin(), f.upd.end(), upd_h + upd_off[p]);
+        std::copy(f.relmap.begin(), f.relmap.end(), relmap_h + relmap_off[p]);
+      }
     });
-    d_relmap.alloc(std::max<int64_t>(nrm, 1) * sizeof(int), &ms);
-    HIPCHK(hipMemcpyAsync(d_relmap.p, relmap_h.data(), nrm * sizeof(int), hipMemcpyHostToDevice, st));
+    {
+      int64_t covered = 0;                  // the fronts' pivot ranges tile 0..n-1
+      for (int p = 0; p < nfr; ++p) covered += s.fronts[p].npiv;
+      if (covered != n) throw Err{MF_EINVAL, "symbolic analysis: fronts do not cover every index"};
+    }
+    d_owner.alloc((size_t)std::max(n, 1) * sizeof(int), &ms);
+    d_asmfr.alloc((size_t)std::max(nfr, 1) * sizeof(AsmFront), &ms);
+    d_upd.alloc((size_t)std::max<int64_t>(nupd, 1) * sizeof(int), &ms);
+    d_relmap.alloc((size_t)std::max<int64_t>(nrm, 1) * sizeof(int), &ms);
+    HIPCHK(hipMemcpyAsync(d_owner.p, owner_h, (size_t)n * sizeof(int), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d_asmfr.p, fr_h, (size_t)nfr * sizeof(AsmFront), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d_upd.p, upd_h, (size_t)nupd * sizeof(int), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d_relmap.p, relmap_h, (size_t)nrm * sizeof(int), hipMemcpyHostToDevice, st));
   }
   ranks.assign(s.nblocks, -1);
 
@@ -818,8 +806,8 @@ Numeric<T>::Numeric(const Symbolic& s, const double* vals, const mf_opts& o) {
   for (int h = 0; h < H; ++h) {
     const auto& L = s.levels[h];
     launch_fill<T>(wsT + reg_off[h], reg_elems[h], (T)0, st);
-    launch_assemble<T>(wsT, d_asm_dest.as<int64_t>() + asm_lvl_off[h], d_asm_src.as<int>() + asm_lvl_off[h],
-                       d_vals.as<double>(), asm_lvl_off[h + 1] - asm_lvl_off[h], st);
+    launch_assemble<T>(wsT, d_rowptr.as<int>(), d_colind.as<int>(), d_vals.as<double>(), d_iperm.as<int>(),
+                       d_owner.as<int>(), d_asmfr.as<AsmFront>(), d_upd.as<int>(), n, h, st);
     for (int slot = 0; slot < 2; ++slot) {
       std::vector<ExtAddDesc<T>> ev;
       int tiles = 0;
@@ -865,11 +853,9 @@ Numeric<T>::Numeric(const Symbolic& s, const double* vals, const mf_opts& o) {
   scrA.release();
   scrB.release();
   split.release();
-  d_asm_dest.release();
-  d_asm_src.release();
-  asm_hd = {};
-  asm_hs = {};
-  relmap_h = {};
+  d_owner.release();
+  d_asmfr.release();
+  d_upd.release();
   dp.ar.chunks.clear();
   dp.ar.off = 0;
   dp.release_staging();

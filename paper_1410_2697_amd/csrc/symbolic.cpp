@@ -271,10 +271,6 @@ std::string analyze(int n, const int32_t* rowptr, const int32_t* colind, const d
     f.children = nd.tree[p].kids;
     for (int c : f.children) s.fronts[c].parent = p;
   }
-  std::vector<int> owner(n);
-  for (int p = 0; p < nfr; ++p)
-    for (int i = 0; i < s.fronts[p].npiv; ++i) owner[s.fronts[p].start + i] = p;
-
   for (int p = 0; p < nfr; ++p) {     // children come first in postorder
     Front& f = s.fronts[p];
     int h = 0;
@@ -350,9 +346,22 @@ std::string analyze(int n, const int32_t* rowptr, const int32_t* colind, const d
   }
   s.block_base[nfr] = nb;
   s.nblocks = nb;
-  // assembly map: lower entries in CSR order.  Rows are split over workers:
-  // one pass counts each row's lower entries, a second writes them at their
-  // offsets.
+  return "";
+}
+
+// Assembly map of A's lower entries (F_bar_p, Eq. fbar), in CSR order: the
+// front, the row and column inside it, and the entry's index in A.  Rows are
+// split over workers: one pass counts each row's lower entries, a second
+// writes them at their offsets.  (The factorisation places the entries on
+// the device from the same rule; this host form is for inspection.)
+void assembly_map(const Symbolic& s, bigvec<int>& asm_front, bigvec<int>& asm_row, bigvec<int>& asm_col,
+                  bigvec<int>& asm_src) {
+  const int n = s.n;
+  const int* rowptr = s.rowptr.data();
+  const int* colind = s.colind.data();
+  std::vector<int> owner(n);
+  for (int p = 0; p < (int)s.fronts.size(); ++p)
+    for (int i = 0; i < s.fronts[p].npiv; ++i) owner[s.fronts[p].start + i] = p;
   {
     std::vector<int64_t> off(n + 1, 0);
     parallel_for(n, 2048, [&](int r0, int r1, int) {
@@ -365,10 +374,10 @@ std::string analyze(int n, const int32_t* rowptr, const int32_t* colind, const d
     });
     for (int r = 0; r < n; ++r) off[r + 1] += off[r];
     const size_t tot = (size_t)off[n];
-    s.asm_front.resize(tot);
-    s.asm_row.resize(tot);
-    s.asm_col.resize(tot);
-    s.asm_src.resize(tot);
+    asm_front.resize(tot);
+    asm_row.resize(tot);
+    asm_col.resize(tot);
+    asm_src.resize(tot);
     parallel_for(n, 2048, [&](int r0, int r1, int) {
       for (int r = r0; r < r1; ++r) {
         int64_t o = off[r];
@@ -387,16 +396,15 @@ std::string analyze(int n, const int32_t* rowptr, const int32_t* colind, const d
                        ? i - f.start
                        : f.npiv + (int)(std::lower_bound(f.upd.begin(), f.upd.end(), i) - f.upd.begin());
           }
-          s.asm_front[o] = p;
-          s.asm_row[o] = lrow;
-          s.asm_col[o] = j - f.start;
-          s.asm_src[o] = k;
+          asm_front[o] = p;
+          asm_row[o] = lrow;
+          asm_col[o] = j - f.start;
+          asm_src[o] = k;
           ++o;
         }
       }
     });
   }
-  return "";
 }
 
 // BDLR sets (Sec. 2.2): interaction graph = A restricted to the front's

@@ -63,14 +63,16 @@ struct Symbolic {
   bigvec<int> prow, pcol;           // pattern of P A P^T (CSR, sorted)
   std::vector<Front> fronts;        // postorder
   std::vector<std::vector<int>> levels;  // by height
-  // assembly of lower entries of P A P^T
-  bigvec<int> asm_front, asm_row, asm_col, asm_src;
   // BDLR cache
   int bdlr_depth = -2, bdlr_cap = -1;
   std::vector<int> bdlr_I, bdlr_Iptr, bdlr_J, bdlr_Jptr;   // over all blocks in front order
   std::vector<int> block_base;      // first global block id of each front
   int nblocks = 0;
 };
+
+// Assembly map of A's lower entries into the fronts (F_bar_p, Eq. fbar), in
+// CSR order: front, row and column inside it, index of the entry in A.
+void assembly_map(const Symbolic& s, bigvec<int>& front, bigvec<int>& row, bigvec<int>& col, bigvec<int>& src);
 
 // Returns "" on success or an error message.
 std::string analyze(int n, const int32_t* rowptr, const int32_t* colind, const double* coords,
