@@ -281,12 +281,16 @@ struct AsmFront {
   int64_t off;
   int start, npiv, ld, height, upd0, nupd;
 };
-// A's lower entries whose column lies in a front of height h, placed in that
-// front's buffer (ws + off).  rowptr/colind/vals: A in CSR (original order);
-// iperm: new index of each original index; owner: front of each new index.
+// Destination of each entry k of A: dest[k] (element offset in the
+// workspace) and lvl[k] (height of the front, -1 for upper entries).
+// rowptr/colind: A's pattern (original order); iperm: new index of each
+// original index; owner: front of each new index.
+void launch_asm_map(const int* rowptr, const int* colind, const int* iperm, const int* owner, const AsmFront* fr,
+                    const int* upd, int n, int64_t* dest, signed char* lvl, hipStream_t st);
+// ws[dest[k]] = vals[k] for every entry with lvl[k] == h
 template <typename T>
-void launch_assemble(T* ws, const int* rowptr, const int* colind, const double* vals, const int* iperm,
-                     const int* owner, const AsmFront* fr, const int* upd, int n, int h, hipStream_t st);
+void launch_assemble(T* ws, const int64_t* dest, const signed char* lvl, const double* vals, int64_t nnz, int h,
+                     hipStream_t st);
 template <typename T>
 void launch_vec_asm(const VecAsmDesc<T>* d, int ndesc, int nrhs, hipStream_t st);
 template <typename T>

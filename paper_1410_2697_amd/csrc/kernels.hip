@@ -1416,24 +1416,26 @@ __global__ void readback_kernel(const int* __restrict__ a, int na, const int* __
   __threadfence_system();
 }
 
-// A's entries of one level's fronts (F_bar_p, Eq. fbar): a thread walks one
-// row r of A; each lower entry (i = iperm[r] >= j = iperm[colind[k]]) whose
-// column's front p has height h goes to row i - start of p inside its pivot
-// block, else to npiv + (the position of i in p's sorted update set), and
-// column j - start.  Every entry is written once.
-template <typename T>
-__global__ void assemble_kernel(T* __restrict__ ws, const int* __restrict__ rowptr, const int* __restrict__ colind,
-                                const double* __restrict__ vals, const int* __restrict__ iperm,
-                                const int* __restrict__ owner, const AsmFront* __restrict__ fr,
-                                const int* __restrict__ upd, int n, int h) {
+// Where A's entries go (F_bar_p, Eq. fbar), once per factorisation: a thread
+// walks one row r of A; each lower entry k (i = iperm[r] >= j =
+// iperm[colind[k]]) goes to the buffer of j's front p, row i - start inside
+// its pivot block, else npiv + (the position of i in p's sorted update set),
+// column j - start: dest[k] is that element's offset in the workspace and
+// lvl[k] the height of p; upper entries get lvl[k] = -1.
+__global__ void asm_map_kernel(const int* __restrict__ rowptr, const int* __restrict__ colind,
+                               const int* __restrict__ iperm, const int* __restrict__ owner,
+                               const AsmFront* __restrict__ fr, const int* __restrict__ upd, int n,
+                               int64_t* __restrict__ dest, signed char* __restrict__ lvl) {
   for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
     const int i = iperm[r];
     const int k1 = rowptr[r + 1];
     for (int k = rowptr[r]; k < k1; ++k) {
       const int j = iperm[colind[k]];
-      if (i < j) continue;
+      if (i < j) {
+        lvl[k] = -1;
+        continue;
+      }
       const AsmFront f = fr[owner[j]];
-      if (f.height != h) continue;
       int row;
       if (i < f.start + f.npiv) {
         row = i - f.start;
@@ -1446,12 +1448,21 @@ __global__ void assemble_kernel(T* __restrict__ ws, const int* __restrict__ rowp
         }
         row = f.npiv + lo;
       }
-      ws[f.off + row + (int64_t)(j - f.start) * f.ld] = (T)vals[k];
+      dest[k] = f.off + row + (int64_t)(j - f.start) * f.ld;
+      lvl[k] = (signed char)f.height;
     }
   }
 }
 
-// one workgroup per (front, right-hand side)
+// A's entries of the fronts of height h, placed where dest says
+template <typename T>
+__global__ void assemble_kernel(T* __restrict__ ws, const int64_t* __restrict__ dest,
+                                const signed char* __restrict__ lvl, const double* __restrict__ vals, int64_t nnz,
+                                int h) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nnz; k += (int64_t)gridDim.x * blockDim.x)
+    if (lvl[k] == h) ws[dest[k]] = (T)vals[k];
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void vec_asm_kernel(const VecAsmDesc<T>* __restrict__ descs, int nrhs) {
   const VecAsmDesc<T> d = descs[blockIdx.x];
@@ -1730,16 +1741,21 @@ void launch_fill(T* p, int64_t n, T v, hipStream_t st) {
   if (n <= 0) return;
   MFH_LAUNCH(fill_kernel<T>, dim3(grid_for(n)), dim3(256), 0, st, p, n, v);
 }
+void launch_asm_map(const int* rowptr, const int* colind, const int* iperm, const int* owner, const AsmFront* fr,
+                    const int* upd, int n, int64_t* dest, signed char* lvl, hipStream_t st) {
+  if (n <= 0) return;
+  MFH_LAUNCH(asm_map_kernel, dim3((n + 255) / 256), dim3(256), 0, st, rowptr, colind, iperm, owner, fr, upd, n, dest,
+             lvl);
+}
 void launch_readback(const int* a, int na, const int* b, int nb, const int* c, int* out, hipStream_t st) {
   const int n = na + nb + 1;
   MFH_LAUNCH(readback_kernel, dim3((n + 255) / 256), dim3(256), 0, st, a, na, b, nb, c, out);
 }
 template <typename T>
-void launch_assemble(T* ws, const int* rowptr, const int* colind, const double* vals, const int* iperm,
-                     const int* owner, const AsmFront* fr, const int* upd, int n, int h, hipStream_t st) {
-  if (n <= 0) return;
-  MFH_LAUNCH(assemble_kernel<T>, dim3((n + 255) / 256), dim3(256), 0, st, ws, rowptr, colind, vals, iperm, owner, fr,
-             upd, n, h);
+void launch_assemble(T* ws, const int64_t* dest, const signed char* lvl, const double* vals, int64_t nnz, int h,
+                     hipStream_t st) {
+  if (nnz <= 0) return;
+  MFH_LAUNCH(assemble_kernel<T>, dim3(grid_for(nnz)), dim3(256), 0, st, ws, dest, lvl, vals, nnz, h);
 }
 template <typename T>
 void launch_vec_asm(const VecAsmDesc<T>* d, int ndesc, int nrhs, hipStream_t st) {
@@ -1805,8 +1821,8 @@ void launch_axpby(const double* a, const double* b, double* c, double alpha, dou
   template void launch_extadd<T>(const ExtAddDesc<T>*, int, int, hipStream_t);                   \
   template void launch_cap<T>(const CapDesc<T>*, int, hipStream_t);                              \
   template void launch_fill<T>(T*, int64_t, T, hipStream_t);                                     \
-  template void launch_assemble<T>(T*, const int*, const int*, const double*, const int*,        \
-                                   const int*, const AsmFront*, const int*, int, int, hipStream_t); \
+  template void launch_assemble<T>(T*, const int64_t*, const signed char*, const double*, int64_t, int, \
+                                   hipStream_t);                                                 \
   template void launch_vec_asm<T>(const VecAsmDesc<T>*, int, int, hipStream_t);                  \
   template void launch_vec_gather<T>(const VecGatherDesc<T>*, int, const T*, int, int,           \
                                      hipStream_t);                                               \

@@ -576,7 +576,7 @@ class Numeric : public NumericBase {
   T* base_alloc(int64_t n, bool bf16) {
     return bf16 ? reinterpret_cast<T*>(arena.alloc_n<unsigned short>(n)) : arena.alloc_n<T>(n);
   }
-  DevBuf ws, scrA, scrB, d_owner, d_asmfr, d_upd, d_relmap;
+  DevBuf ws, scrA, scrB, d_owner, d_asmfr, d_upd, d_adest, d_alvl, d_relmap;
   // blocks replaced by a growing scratch buffer, released at the next
   // synchronisation (the level's rank read-back, the end of the factor)
   std::vector<std::unique_ptr<DevBuf>> retired;
@@ -799,6 +799,12 @@ Numeric<T>::Numeric(const Symbolic& s, const double* vals, const mf_opts& o) {
     HIPCHK(hipMemcpyAsync(d_asmfr.p, fr_h, (size_t)nfr * sizeof(AsmFront), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(d_upd.p, upd_h, (size_t)nupd * sizeof(int), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(d_relmap.p, relmap_h, (size_t)nrm * sizeof(int), hipMemcpyHostToDevice, st));
+    if (H > 127) throw Err{MF_EINVAL, "elimination tree deeper than 127 levels"};
+    d_adest.alloc((size_t)std::max<int64_t>(s.nnz, 1) * sizeof(int64_t), &ms);
+    d_alvl.alloc((size_t)std::max<int64_t>(s.nnz, 1), &ms);
+    launch_asm_map(d_rowptr.as<int>(), d_colind.as<int>(), d_iperm.as<int>(), d_owner.as<int>(),
+                   d_asmfr.as<AsmFront>(), d_upd.as<int>(), n, d_adest.as<int64_t>(),
+                   d_alvl.as<signed char>(), st);
   }
   ranks.assign(s.nblocks, -1);
 
@@ -806,8 +812,7 @@ Numeric<T>::Numeric(const Symbolic& s, const double* vals, const mf_opts& o) {
   for (int h = 0; h < H; ++h) {
     const auto& L = s.levels[h];
     launch_fill<T>(wsT + reg_off[h], reg_elems[h], (T)0, st);
-    launch_assemble<T>(wsT, d_rowptr.as<int>(), d_colind.as<int>(), d_vals.as<double>(), d_iperm.as<int>(),
-                       d_owner.as<int>(), d_asmfr.as<AsmFront>(), d_upd.as<int>(), n, h, st);
+    launch_assemble<T>(wsT, d_adest.as<int64_t>(), d_alvl.as<signed char>(), d_vals.as<double>(), s.nnz, h, st);
     for (int slot = 0; slot < 2; ++slot) {
       std::vector<ExtAddDesc<T>> ev;
       int tiles = 0;
@@ -856,6 +861,8 @@ Numeric<T>::Numeric(const Symbolic& s, const double* vals, const mf_opts& o) {
   d_owner.release();
   d_asmfr.release();
   d_upd.release();
+  d_adest.release();
+  d_alvl.release();
   dp.ar.chunks.clear();
   dp.ar.off = 0;
   dp.release_staging();
