@@ -251,6 +251,8 @@ void launch_phase2(const Phase2Desc<T>* d, int ndesc, int maxrc, double eps, int
 // for completion (synchronous); a barrier wait longer than spin_limit polls
 // sets status bit 8 and ends the loop.  Returns the launch or wait error.
 constexpr int kPhase2CoopLds = 64 * 1024;
+// fewest columns per workgroup the host gives a multi-workgroup block
+constexpr int kCoopMinCols = 4;
 template <typename T>
 int phase2_coop_wcols(int nr);
 template <typename T>

@@ -1050,6 +1050,21 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
   const int coop_capacity = phase2_coop_capacity<T>(coop_lds, true);
   const int coop_capacity_g = phase2_coop_capacity<T>(coop_lds_g, false);
   std::vector<BR> br;
+  // Columns per workgroup for the slice mode: as few as spread the level's
+  // multi-workgroup blocks over the resident workgroups of one launch (a
+  // step's update and search then run on more compute units), never more
+  // than fit a workgroup's LDS.
+  int wc_target = 1;
+  {
+    int64_t cols = 0;
+    for (int p : Hs)
+      for (const Block& B : s.fronts[p].blocks) {
+        const bool full = B.nr <= skreg_full_rows<T>() && B.nc <= skreg_full_cols<T>();
+        if (!full && adaptive && B.nr <= kPhase2CoopMaxRows && phase2_coop_wcols<T>(B.nr) > 0) cols += B.nc;
+      }
+    const int64_t slots = std::max<int64_t>(1, (int64_t)coop_capacity * 7 / 8);
+    wc_target = (int)std::max<int64_t>(kCoopMinCols, (cols + slots - 1) / slots);
+  }
   for (int p : Hs) {
     const Front& f = s.fronts[p];
     for (int bi = 0; bi < (int)f.blocks.size(); ++bi) {
@@ -1064,7 +1079,7 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
       if (!x.full && adaptive && B.nr <= kPhase2CoopMaxRows) {
         // phase 2 over several workgroups: column slices in LDS when they fit
         // the resident workgroups, else updated in place (about 64K entries each)
-        const int wc = phase2_coop_wcols<T>(B.nr);
+        const int wc = std::min(phase2_coop_wcols<T>(B.nr), wc_target);
         const int nl = wc > 0 ? cdiv(B.nc, wc) : 0;
         if (nl > 0 && nl <= coop_capacity) {
           x.nwg = nl;
