@@ -251,8 +251,11 @@ void launch_phase2(const Phase2Desc<T>* d, int ndesc, int maxrc, double eps, int
 // for completion (synchronous); a barrier wait longer than spin_limit polls
 // sets status bit 8 and ends the loop.  Returns the launch or wait error.
 constexpr int kPhase2CoopLds = 64 * 1024;
-// fewest columns per workgroup the host gives a multi-workgroup block
-constexpr int kCoopMinCols = 4;
+// threads of a multi-workgroup phase-2 workgroup (more waves make the
+// per-step barriers slower than they make the update faster), and the
+// fewest columns per workgroup the host gives a block (one per wave)
+constexpr int kCoopThreads = 256;
+constexpr int kCoopMinCols = kCoopThreads / 64;
 template <typename T>
 int phase2_coop_wcols(int nr);
 template <typename T>

@@ -966,12 +966,12 @@ __device__ __forceinline__ u64 block_max_key(u64 v, u64* sh, int par) {
 // SLICE_LDS: the workgroup's columns are copied to LDS once (the front keeps
 // the phase-1 residual); otherwise they are updated in place in the front.
 template <typename T, bool SLICE_LDS>
-__global__ __launch_bounds__(256) void phase2_coop_kernel(const Phase2CoopDesc<T>* __restrict__ descs, int ndesc,
+__global__ __launch_bounds__(kCoopThreads) void phase2_coop_kernel(const Phase2CoopDesc<T>* __restrict__ descs, int ndesc,
                                                           double eps, int* status, int spin_limit) {
   extern __shared__ __align__(16) char smem[];
   __shared__ u64 s_red[32];
-  __shared__ u64 s_pk[2][4];
-  __shared__ int s_pok[2][4];
+  __shared__ u64 s_pk[2][1];
+  __shared__ int s_pok[2][1];
   int lo = 0, hi = ndesc - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -1084,41 +1084,41 @@ __global__ __launch_bounds__(256) void phase2_coop_kernel(const Phase2CoopDesc<T
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (tid == 0) publish(d.keys + (size_t)par * nwg + j, (unsigned long long)(best | tag));
-    // wait for every slot of this buffer to carry this step's tag
-    u64 K = 0;
-    bool met = false;
-    for (int spins = 0;; ++spins) {
-      u64 kq = 0;
-      bool ok = true;
-      for (int q = tid; q < nwg; q += nt) {
-        const u64 k = fetch(d.keys + (size_t)par * nwg + q);
-        if ((k & kTag) != tag) ok = false;
-        const u64 kv = k & ~kTag;
-        kq = kv > kq ? kv : kq;
-      }
-      const unsigned khi = wave_ext_u32<true>((unsigned)(kq >> 32));
-      const unsigned klo = wave_ext_u32<true>((unsigned)(kq >> 32) == khi ? (unsigned)(kq & 0xFFFFFFFFull) : 0u);
-      const bool wok = __ballot(!ok) == 0ull;
-      if (lane == 0) {
-        s_pk[ppar][wave] = ((u64)khi << 32) | klo;
-        s_pok[ppar][wave] = wok ? 1 : 0;
-      }
-      __syncthreads();
-      bool all = true;
+    // wait for every slot of this buffer to carry this step's tag: wave 0
+    // polls (no barrier inside the loop; its exit is wave-uniform), then one
+    // barrier hands the key to the other waves
+    if (wave == 0) {
       u64 km = 0;
-      for (int q = 0; q < nwave; ++q) {
-        all = all && s_pok[ppar][q] != 0;
-        km = s_pk[ppar][q] > km ? s_pk[ppar][q] : km;
+      int ok_all = 0;
+      for (int spins = 0;; ++spins) {
+        u64 kq = 0;
+        bool ok = true;
+        for (int q = lane; q < nwg; q += 64) {
+          const u64 k = fetch(d.keys + (size_t)par * nwg + q);
+          if ((k & kTag) != tag) ok = false;
+          const u64 kv = k & ~kTag;
+          kq = kv > kq ? kv : kq;
+        }
+        if (__ballot(!ok) == 0ull) {
+          const unsigned khi = wave_ext_u32<true>((unsigned)(kq >> 32));
+          const unsigned klo =
+              wave_ext_u32<true>((unsigned)(kq >> 32) == khi ? (unsigned)(kq & 0xFFFFFFFFull) : 0u);
+          km = ((u64)khi << 32) | klo;
+          ok_all = 1;
+          break;
+        }
+        if (spins >= spin_limit) break;
+        __builtin_amdgcn_s_sleep(1);
       }
-      ppar ^= 1;
-      if (all) {
-        K = uniform(km);
-        met = true;
-        break;
+      if (lane == 0) {
+        s_pk[ppar][0] = km;
+        s_pok[ppar][0] = ok_all;
       }
-      if (spins >= spin_limit) break;
-      __builtin_amdgcn_s_sleep(1);
     }
+    __syncthreads();
+    const bool met = s_pok[ppar][0] != 0;
+    const u64 K = uniform(s_pk[ppar][0]);
+    ppar ^= 1;
     if (!met) {
       if (tid == 0) atomicOr(status, 8);
       break;
@@ -1683,7 +1683,7 @@ int phase2_coop_capacity(size_t lds, bool slice_lds) {
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
   const void* k = slice_lds ? reinterpret_cast<const void*>(phase2_coop_kernel<T, true>)
                             : reinterpret_cast<const void*>(phase2_coop_kernel<T, false>);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, 256, lds) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, kCoopThreads, lds) != hipSuccess) return 0;
   return per * cus;
 }
 // One multi-workgroup phase-2 launch runs at a time in the process, and the
@@ -1702,9 +1702,11 @@ hipError_t launch_phase2_coop(const Phase2CoopDesc<T>* d, int ndesc, int wgs, si
   if (ndesc <= 0 || wgs <= 0) return hipSuccess;
   std::lock_guard<std::mutex> g(phase2_coop_mutex());
   if (slice_lds)
-    MFH_LAUNCH((phase2_coop_kernel<T, true>), dim3(wgs), dim3(256), lds, st, d, ndesc, eps, status, spin_limit);
+    MFH_LAUNCH((phase2_coop_kernel<T, true>), dim3(wgs), dim3(kCoopThreads), lds, st, d, ndesc, eps, status,
+               spin_limit);
   else
-    MFH_LAUNCH((phase2_coop_kernel<T, false>), dim3(wgs), dim3(256), lds, st, d, ndesc, eps, status, spin_limit);
+    MFH_LAUNCH((phase2_coop_kernel<T, false>), dim3(wgs), dim3(kCoopThreads), lds, st, d, ndesc, eps, status,
+               spin_limit);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return hipStreamSynchronize(st);
