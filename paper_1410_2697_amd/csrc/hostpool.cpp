@@ -30,7 +30,9 @@ void TaskGroup::wait() {
 }
 
 HostPool& HostPool::get() {
-  static HostPool pool(std::max(0, std::min<int>((int)std::thread::hardware_concurrency(), 16) - 1));
+  // at least one worker: the factorization's level loop waits for BDLR
+  // tasks without running them itself
+  static HostPool pool(std::max(1, std::min<int>((int)std::thread::hardware_concurrency(), 16) - 1));
   return pool;
 }
 

@@ -7,8 +7,10 @@
 #include <condition_variable>
 #include <deque>
 #include <functional>
+#include <memory>
 #include <mutex>
 #include <thread>
+#include <type_traits>
 #include <vector>
 
 namespace mfh {
@@ -49,7 +51,10 @@ class HostPool {
 
 // Runs f(begin, end, chunk) over [0, n) in up to width() contiguous chunks
 // (one when n < 2 min_chunk); chunk indices are distinct, so per-chunk
-// scratch indexed by them is never shared.
+// scratch indexed by them is never shared.  The caller takes chunks too, so
+// every chunk has been claimed when its own loop ends; it then waits only for
+// chunks other threads are running, never runs unrelated queued tasks (which
+// may be long), and helper tasks that start late find no chunk left.
 template <typename F>
 void parallel_for(int n, int min_chunk, F&& f) {
   HostPool& pool = HostPool::get();
@@ -58,25 +63,27 @@ void parallel_for(int n, int min_chunk, F&& f) {
     if (n > 0) f(0, n, 0);
     return;
   }
+  struct State {
+    std::atomic<int> next{0}, done{0};
+  };
+  auto state = std::make_shared<State>();
   const int ch = (n + nt - 1) / nt;
-  std::atomic<int> next{0};
-  auto body = [&]() {
+  // claims and runs chunks; f is only touched while a chunk is unfinished,
+  // which keeps the caller (and f) waiting below
+  using Fn = typename std::remove_reference<F>::type;
+  Fn* fp = &f;
+  auto run = [n, nt, ch, fp](State* s) {
     for (;;) {
-      const int c = next.fetch_add(1);
+      const int c = s->next.fetch_add(1);
       if (c >= nt) return;
       const int b = c * ch, e = std::min(n, b + ch);
-      if (b < e) f(b, e, c);
+      if (b < e) (*fp)(b, e, c);
+      s->done.fetch_add(1, std::memory_order_release);
     }
   };
-  TaskGroup g;
-  g.add(nt - 1);
-  for (int t = 1; t < nt; ++t)
-    pool.submit([&]() {
-      body();
-      g.done();
-    });
-  body();
-  g.wait();
+  for (int t = 1; t < nt; ++t) pool.submit([state, run]() { run(state.get()); });
+  run(state.get());
+  while (state->done.load(std::memory_order_acquire) < nt) std::this_thread::yield();
 }
 
 // threads the host-side loops use at most
