@@ -13,6 +13,7 @@
 #include "hostpool.h"
 
 #include <algorithm>
+#include <utility>
 #include <atomic>
 #include <cstring>
 #include <limits>
@@ -51,26 +52,43 @@ struct NDCtx {
 
   double co(int v, int a) const { return coords[(int64_t)v * dim + a]; }
 
+  // axis of largest coordinate extent over ids (one pass for all axes)
   int extent_axis(const std::vector<int>& ids) const {
+    double mn[3], mx[3];
+    for (int a = 0; a < dim; ++a) {
+      mn[a] = std::numeric_limits<double>::infinity();
+      mx[a] = -mn[a];
+    }
+    for (int v : ids)
+      for (int a = 0; a < dim; ++a) {
+        const double c = co(v, a);
+        mn[a] = std::min(mn[a], c);
+        mx[a] = std::max(mx[a], c);
+      }
     int best = 0;
     double bext = -1.0;
     for (int a = 0; a < dim; ++a) {
-      double mn = std::numeric_limits<double>::infinity(), mx = -mn;
-      for (int v : ids) { double c = co(v, a); mn = std::min(mn, c); mx = std::max(mx, c); }
-      double ext = mx - mn;
+      const double ext = mx[a] - mn[a];
       if (a == 0 || ext > bext) { bext = ext; best = a; }   // first maximum wins
     }
     return best;
   }
 
   // places the element of rank m in (coordinate, id) order at ids[m], smaller
-  // ones before it, larger ones after (the order inside each part is free)
+  // ones before it, larger ones after (the order inside each part is free);
+  // the selection runs on (coordinate, id) pairs held contiguously
   void select_by_axis(std::vector<int>& ids, size_t m, int ax) const {
-    std::nth_element(ids.begin(), ids.begin() + m, ids.end(), [&](int x, int y) {
-      double cx = co(x, ax), cy = co(y, ax);
-      if (cx != cy) return cx < cy;
-      return x < y;
-    });
+    std::vector<std::pair<double, int>> key(ids.size());
+    for (size_t i = 0; i < ids.size(); ++i) key[i] = {co(ids[i], ax), ids[i]};
+    std::nth_element(key.begin(), key.begin() + (std::ptrdiff_t)m, key.end());
+    for (size_t i = 0; i < ids.size(); ++i) ids[i] = key[i].second;
+  }
+  // coordinate of the element of rank m in (coordinate, id) order
+  double median_coord(const std::vector<int>& ids, size_t m, int ax) const {
+    std::vector<std::pair<double, int>> key(ids.size());
+    for (size_t i = 0; i < ids.size(); ++i) key[i] = {co(ids[i], ax), ids[i]};
+    std::nth_element(key.begin(), key.begin() + (std::ptrdiff_t)m, key.end());
+    return key[m].first;
   }
 
   void kd_order(std::vector<int> ids, std::vector<int>& out) const {
@@ -98,9 +116,7 @@ struct NDCtx {
   int rec(const std::vector<int>& S, NDOut& out, std::vector<char>& inL, int spawn) const {
     if ((int)S.size() <= leaf) return make_leaf(S, out);
     int ax = extent_axis(S);
-    std::vector<int> srt(S);
-    select_by_axis(srt, S.size() / 2, ax);
-    double c = co(srt[S.size() / 2], ax);
+    const double c = median_coord(S, S.size() / 2, ax);
     std::vector<int> L, R;
     for (int v : S) (co(v, ax) < c ? L : R).push_back(v);
     if (L.empty()) return make_leaf(S, out);
@@ -173,7 +189,7 @@ std::string validate(int n, const int32_t* rowptr, const int32_t* colind) {
   std::atomic<int> bad_row{n};
   std::vector<int> code(max_workers(), 0);
   std::vector<int> where(max_workers(), n);
-  parallel_for(n, 4096, [&](int r0, int r1, int t) {
+  parallel_for(n, 1024, [&](int r0, int r1, int t) {
     for (int i = r0; i < r1 && i < bad_row.load(std::memory_order_relaxed); ++i) {
       int c = 0;
       bool diag = false;
@@ -202,7 +218,7 @@ std::string validate(int n, const int32_t* rowptr, const int32_t* colind) {
   // symmetry: every entry (i, j) has its mirror (j, i); rows are sorted, so
   // a binary search in row j finds it (rows checked in parallel)
   std::atomic<bool> asym{false};
-  parallel_for(n, 4096, [&](int r0, int r1, int) {
+  parallel_for(n, 1024, [&](int r0, int r1, int) {
     for (int i = r0; i < r1 && !asym.load(std::memory_order_relaxed); ++i)
       for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
         const int j = colind[k];
@@ -253,7 +269,7 @@ std::string analyze(int n, const int32_t* rowptr, const int32_t* colind, const d
   for (int r = 0; r < n; ++r) s.prow[s.iperm[r] + 1] = rowptr[r + 1] - rowptr[r];
   for (int i = 0; i < n; ++i) s.prow[i + 1] += s.prow[i];
   s.pcol.resize(s.nnz);             // every entry is written below
-  parallel_for(n, 2048, [&](int r0, int r1, int) {
+  parallel_for(n, 1024, [&](int r0, int r1, int) {
     for (int r = r0; r < r1; ++r) {
       const int nr = s.iperm[r];
       int o = s.prow[nr];
