@@ -1465,7 +1465,7 @@ __global__ void assemble_kernel(T* __restrict__ ws, const int64_t* __restrict__ 
 
 template <typename T>
 __global__ __launch_bounds__(256) void vec_asm_kernel(const VecAsmDesc<T>* __restrict__ descs, int nrhs) {
-  const VecAsmDesc<T> d = descs[blockIdx.x];
+  const VecAsmDesc<T>& d = descs[blockIdx.x];   // read in place (a copy indexed by child would sit in scratch)
   const int tid = threadIdx.x, nt = blockDim.x, k = blockIdx.y;
   T* t = d.t + (size_t)k * d.ldt;
   const T* x = d.xs + (size_t)k * d.ldx;
@@ -1541,32 +1541,46 @@ __global__ __launch_bounds__(256) void spmv_kernel(const int* __restrict__ rowpt
 
 constexpr int kMdotMax = 64;
 // partial[(chunk * nrhs + k) * nv + i] = sum over the chunk of X_i(:,k) .* w(:,k)
+// partial dot products of vectors i0 .. i0 + 7 (blockIdx.z = group) with w,
+// right-hand side k, over one chunk of rows; accumulators in registers
+constexpr int kMdotGroup = 8;
 __global__ __launch_bounds__(256) void mdot_partial_kernel(const double* X, int64_t xstride, int nv, const double* w,
                                                            int n, int nrhs, double* partial) {
   __shared__ double red[16];
-  const int chunk = blockIdx.x, k = blockIdx.y;
+  const int chunk = blockIdx.x, k = blockIdx.y, i0 = blockIdx.z * kMdotGroup;
+  const int m = min(kMdotGroup, nv - i0);
   const int per = (n + gridDim.x - 1) / gridDim.x;
   const int lo = chunk * per, hi = min(n, lo + per);
-  double acc[kMdotMax];
-  for (int i = 0; i < nv; ++i) acc[i] = 0.0;
+  double acc[kMdotGroup];
+#pragma unroll
+  for (int i = 0; i < kMdotGroup; ++i) acc[i] = 0.0;
   const double* wk = w + (size_t)k * n;
+  const double* Xk = X + (size_t)i0 * xstride + (size_t)k * n;
   for (int row = lo + threadIdx.x; row < hi; row += blockDim.x) {
     const double wv = wk[row];
-    for (int i = 0; i < nv; ++i) acc[i] += X[i * xstride + (size_t)k * n + row] * wv;
+#pragma unroll
+    for (int i = 0; i < kMdotGroup; ++i)
+      if (i < m) acc[i] += Xk[i * xstride + row] * wv;
   }
-  for (int i = 0; i < nv; ++i) {
-    const double s = block_sum(acc[i], red);
-    if (threadIdx.x == 0) partial[((size_t)chunk * nrhs + k) * nv + i] = s;
-  }
+#pragma unroll
+  for (int i = 0; i < kMdotGroup; ++i)
+    if (i < m) {                                      // m is uniform: every thread reaches the barriers
+      const double s = block_sum(acc[i], red);
+      if (threadIdx.x == 0) partial[((size_t)chunk * nrhs + k) * nv + i0 + i] = s;
+    }
 }
 
-__global__ void mdot_reduce_kernel(const double* partial, int nchunk, int nv, int nrhs, double* out, int accumulate) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;   // idx = i * nrhs + k
-  if (idx >= nv * nrhs) return;
+// one wave per output idx = i * nrhs + k: lanes load the chunk partials
+// (one load each for up to 64 chunks), then a butterfly sum in a fixed order
+__global__ __launch_bounds__(256) void mdot_reduce_kernel(const double* partial, int nchunk, int nv, int nrhs,
+                                                          double* out, int accumulate) {
+  const int idx = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6), lane = threadIdx.x & 63;
+  if (idx >= nv * nrhs) return;                             // whole waves
   const int i = idx / nrhs, k = idx % nrhs;
   double s = 0.0;
-  for (int c = 0; c < nchunk; ++c) s += partial[((size_t)c * nrhs + k) * nv + i];
-  out[idx] = accumulate ? out[idx] + s : s;
+  for (int c = lane; c < nchunk; c += 64) s += partial[((size_t)c * nrhs + k) * nv + i];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if (lane == 0) out[idx] = accumulate ? out[idx] + s : s;
 }
 
 __global__ void maxpy_kernel(const double* X, int64_t xstride, int nv, const double* coef, double* w, int n, int nrhs,
@@ -1786,9 +1800,10 @@ void launch_spmv(const int* rowptr, const int* colind, const double* vals, const
 void launch_mdot(const double* X, int64_t xstride, int nv, const double* w, int n, int nrhs, double* partial,
                  double* out, int accumulate, hipStream_t st) {
   const int nchunk = 64;
-  MFH_LAUNCH(mdot_partial_kernel, dim3(nchunk, nrhs), dim3(256), 0, st, X, xstride, nv, w, n, nrhs, partial);
-  MFH_LAUNCH(mdot_reduce_kernel, dim3((nv * nrhs + 255) / 256), dim3(256), 0, st, partial, nchunk, nv, nrhs,
-                     out, accumulate);
+  MFH_LAUNCH(mdot_partial_kernel, dim3(nchunk, nrhs, (nv + kMdotGroup - 1) / kMdotGroup), dim3(256), 0, st, X,
+             xstride, nv, w, n, nrhs, partial);
+  MFH_LAUNCH(mdot_reduce_kernel, dim3((nv * nrhs + 3) / 4), dim3(256), 0, st, partial, nchunk, nv, nrhs, out,
+             accumulate);
 }
 void launch_maxpy(const double* X, int64_t xstride, int nv, const double* coef, double* w, int n, int nrhs,
                   double sign, hipStream_t st) {
