@@ -232,12 +232,17 @@ template <typename T>
 constexpr int skreg_full_cols() { return 256; }
 template <typename T>
 constexpr int skreg_hat_max() { return sizeof(T) == 8 ? 128 : 192; }
-// skeleton factors: one 64-lane workgroup per 64 rows of C~ or of R~; LDS
-// holds the solved values (rmax x 64) and one column block of the factor
+// skeleton factors: one workgroup of kSkelFacThreads per 64 rows of C~ or of
+// R~ (its waves share each row's update sums); LDS holds the solved values
+// (rmax x 64), one column block of the factor and the waves' partial sums
 constexpr int kSkelFacRows = 64;
 constexpr int kSkelFacBlock = 16;
+constexpr int kSkelFacThreads = 256;
 template <typename T>
-constexpr size_t skelfac_lds(int rmax) { return (size_t)rmax * (kSkelFacRows + kSkelFacBlock) * sizeof(T); }
+constexpr size_t skelfac_lds(int rmax) {
+  return ((size_t)rmax * (kSkelFacRows + kSkelFacBlock) +
+          (size_t)(kSkelFacThreads / 64 - 1) * kSkelFacBlock * kSkelFacRows) * sizeof(T);
+}
 template <typename T>
 void launch_skelfac(const SkelFacDesc<T>* d, int ndesc, int wgs, int rmax, hipStream_t st);
 template <typename T>

@@ -794,32 +794,34 @@ __global__ __launch_bounds__(NT) void skreg_kernel(const SkRegDesc<T>* __restric
 }
 
 // ------------------------------------- skeleton factors C~ and R~^T -------
-// Each lane owns one row i of C~ (x U_r = B(i, J_r), U_r upper) or one
-// column a of R~^T (L_r y = B(I_r, a), L_r unit lower).  The solve runs over
-// column blocks of KB: the block's right-hand sides sit in registers, the
-// contributions of all earlier solved values (LDS, one per lane) are
-// subtracted with KB independent FMAs per value, then the triangular block
-// itself is solved in order.  The operations per entry are those of the
-// plain forward substitution, in the same order.
+// Each row position (lane) owns one row i of C~ (x U_r = B(i, J_r), U_r
+// upper) or one column a of R~^T (L_r y = B(I_r, a), L_r unit lower).  The
+// solve runs over column blocks of KB: the contributions of all earlier
+// solved values (LDS) to the block's right-hand sides are split over the
+// workgroup's waves by solved index (wave w takes t = w, w + NW, ...), each
+// with KB independent FMAs per value; wave 0 adds the other waves' partial
+// sums to the right-hand sides and solves the triangular block itself in
+// order.
 template <typename T>
-__global__ __launch_bounds__(kSkelFacRows) void skelfac_kernel(const SkelFacDesc<T>* __restrict__ descs, int ndesc,
-                                                               int rmax) {
-  constexpr int KB = kSkelFacBlock, W = kSkelFacRows;
+__global__ __launch_bounds__(kSkelFacThreads) void skelfac_kernel(const SkelFacDesc<T>* __restrict__ descs,
+                                                                  int ndesc, int rmax) {
+  constexpr int KB = kSkelFacBlock, W = kSkelFacRows, NW = kSkelFacThreads / 64;
   extern __shared__ __align__(16) char smem[];
   T* X = reinterpret_cast<T*>(smem);              // rmax x W solved values
   T* S = X + (size_t)rmax * W;                    // rmax x KB factor block
+  T* P = S + (size_t)rmax * KB;                   // (NW - 1) x KB x W partial sums
   int lo = 0, hi = ndesc - 1;
   while (lo < hi) { int mid = (lo + hi + 1) >> 1; if (descs[mid].wg0 <= (int)blockIdx.x) lo = mid; else hi = mid - 1; }
   const SkelFacDesc<T> d = descs[lo];
   const int r = *d.rank;
-  const int local = (int)blockIdx.x - d.wg0, lane = threadIdx.x;
+  const int local = (int)blockIdx.x - d.wg0, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const bool upart = local < d.wgU;
   const int row = (upart ? local : local - d.wgU) * W + lane;
   const bool valid = row < (upart ? d.nr : d.nc);
   for (int k0 = 0; k0 < r; k0 += KB) {
     const int nb = min(KB, r - k0), tn = k0 + nb;
-    __syncthreads();                              // earlier readers of S are done
-    for (int q = lane; q < tn * KB; q += W) {
+    __syncthreads();                              // earlier readers of S and P are done
+    for (int q = threadIdx.x; q < tn * KB; q += kSkelFacThreads) {
       const int t = q / KB, c = q - (q / KB) * KB;
       T v = 0;
       if (c < nb) v = upart ? d.M[t + (size_t)(k0 + c) * d.ldm] : d.M[(k0 + c) + (size_t)t * d.ldm];
@@ -829,28 +831,39 @@ __global__ __launch_bounds__(kSkelFacRows) void skelfac_kernel(const SkelFacDesc
 #pragma unroll
     for (int c = 0; c < KB; ++c) {
       T v = 0;
-      if (valid && c < nb)
+      if (wave == 0 && valid && c < nb)
         v = upart ? d.F[(d.r0 + row) + (size_t)d.piv_c[k0 + c] * d.ld]
                   : d.F[d.piv_r[k0 + c] + (size_t)(d.c0 + row) * d.ld];
       acc[c] = v;
     }
     __syncthreads();
-    for (int t = 0; t < k0; ++t) {
+    for (int t = wave; t < k0; t += NW) {
       const T xt = X[(size_t)t * W + lane];
       const T* st = S + t * KB;
 #pragma unroll
       for (int c = 0; c < KB; ++c) acc[c] -= xt * st[c];
     }
+    if (wave > 0) {
 #pragma unroll
-    for (int c = 0; c < KB; ++c) {
-      if (c < nb) {
+      for (int c = 0; c < KB; ++c) P[((size_t)(wave - 1) * KB + c) * W + lane] = acc[c];
+    }
+    __syncthreads();
+    if (wave == 0) {
 #pragma unroll
-        for (int cp = 0; cp < c; ++cp) acc[c] -= acc[cp] * S[(k0 + cp) * KB + c];
-        if (upart) acc[c] = acc[c] / S[(k0 + c) * KB + c];
-        X[(size_t)(k0 + c) * W + lane] = acc[c];
-        if (valid) {
-          if (upart) d.U[(size_t)(k0 + c) * d.ldu + row] = acc[c];
-          else d.V[(size_t)(k0 + c) * d.ldv + row] = acc[c];
+      for (int w2 = 0; w2 < NW - 1; ++w2)
+#pragma unroll
+        for (int c = 0; c < KB; ++c) acc[c] += P[((size_t)w2 * KB + c) * W + lane];
+#pragma unroll
+      for (int c = 0; c < KB; ++c) {
+        if (c < nb) {
+#pragma unroll
+          for (int cp = 0; cp < c; ++cp) acc[c] -= acc[cp] * S[(k0 + cp) * KB + c];
+          if (upart) acc[c] = acc[c] / S[(k0 + c) * KB + c];
+          X[(size_t)(k0 + c) * W + lane] = acc[c];
+          if (valid) {
+            if (upart) d.U[(size_t)(k0 + c) * d.ldu + row] = acc[c];
+            else d.V[(size_t)(k0 + c) * d.ldv + row] = acc[c];
+          }
         }
       }
     }
@@ -1671,7 +1684,7 @@ void launch_skreg_hat(const SkRegDesc<T>* d, int ndesc, double eps, int* status,
 template <typename T>
 void launch_skelfac(const SkelFacDesc<T>* d, int ndesc, int wgs, int rmax, hipStream_t st) {
   if (ndesc <= 0 || wgs <= 0) return;
-  MFH_LAUNCH(skelfac_kernel<T>, dim3(wgs), dim3(kSkelFacRows), skelfac_lds<T>(rmax), st, d, ndesc, rmax);
+  MFH_LAUNCH(skelfac_kernel<T>, dim3(wgs), dim3(kSkelFacThreads), skelfac_lds<T>(rmax), st, d, ndesc, rmax);
 }
 template <typename T>
 void launch_phase2(const Phase2Desc<T>* d, int ndesc, int maxrc, double eps, int* status, hipStream_t st) {
