@@ -231,7 +231,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="poisson3d_q1_32")
     ap.add_argument("--n-c", type=int, default=512)
     ap.add_argument("--latency-calls", type=int, default=20)

@@ -714,9 +714,11 @@ Numeric<T>::Numeric(const Symbolic& s, const double* vals, const mf_opts& o) {
     }
   } joiner{this};
   if (hodlr && !bd_order.empty()) {
-    // one task per worker thread: none stays queued, where a thread that
-    // helps while it waits could pick it up and be held by it
-    const int ntasks = std::max(1, std::min<int>(max_workers() - 1, (int)bd_order.size()));
+    // at most one task per worker thread (none stays queued, where a thread
+    // that helps while it waits could pick it up and be held by it), and two
+    // threads' worth of CPU left to this thread and the runtime, which plan
+    // and launch the levels meanwhile
+    const int ntasks = std::max(1, std::min<int>(max_workers() - 3, (int)bd_order.size()));
     workers.add(ntasks);
     for (int t = 0; t < ntasks; ++t)
       HostPool::get().submit([this, H]() {
