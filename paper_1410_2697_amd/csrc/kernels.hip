@@ -516,7 +516,7 @@ __global__ __launch_bounds__(NT) void skreg_kernel(const SkRegDesc<T>* __restric
   constexpr unsigned kMag = sizeof(T) == 4 ? 0x7FFFFF80u : 0x7FFFFFFFu;
   __shared__ T s_cc[2][CG][MR];                 // candidate column of each wave
   __shared__ __align__(16) T s_wrow[FULL ? CG : 1][CJ];   // pivot row, per wave
-  __shared__ u64 s_red[2][CG];
+  __shared__ u64 s_key[3];                      // block-wide max key of a step (three in turn)
   __shared__ char s_inI[FULL ? MR : 1];
   __shared__ char s_inJ[FULL ? MC : 1];
   __shared__ short s_rstep[FULL ? 1 : MR];
@@ -581,6 +581,9 @@ __global__ __launch_bounds__(NT) void skreg_kernel(const SkRegDesc<T>* __restric
     for (int a = t; a < MR; a += NT) s_rstep[a] = -1;
     for (int b = t; b < MC; b += NT) s_cstep[b] = -1;
   }
+  if (t < 3) s_key[t] = 0ull;
+  __syncthreads();
+  int kb = 0;
   const T stop_rel = (T)fmax(eps, (double)noise_rel<T>());
   int r = 0, r1 = -1;
   T u11 = 0;
@@ -651,15 +654,16 @@ __global__ __launch_bounds__(NT) void skreg_kernel(const SkRegDesc<T>* __restric
 #pragma unroll
         for (int i = 0; i < RI; ++i) s_cc[cur][g][lane + 64 * i] = e[i][jw];
       }
-      if (lane == 0) {
+      // the block-wide maximum forms in LDS (atomic max); the slot of the
+      // next step was last read two barriers ago and is cleared now
+      if (lane == 0 && q) {
         const unsigned pos = (((unsigned)g + CG * jw) << 16) | (wl + 64u * iw);
-        s_red[cur][g] = q ? (((u64)q) << 32) | (u64)(0xFFFFFFFFu - pos) : 0ull;
+        atomicMax(&s_key[kb], (((u64)q) << 32) | (u64)(0xFFFFFFFFu - pos));
       }
+      if (t == 0) s_key[kb == 2 ? 0 : kb + 1] = 0ull;
       __syncthreads();
-      u64 K = s_red[cur][0];
-#pragma unroll
-      for (int k = 1; k < CG; ++k) K = s_red[cur][k] > K ? s_red[cur][k] : K;
-      K = uniform(K);
+      u64 K = uniform(s_key[kb]);
+      kb = kb == 2 ? 0 : kb + 1;
       if (K == 0ull) break;
       const unsigned pos = 0xFFFFFFFFu - (unsigned)(K & 0xFFFFFFFFull);
       const int as = (int)(pos & 0xFFFFu), bs = (int)(pos >> 16);
