@@ -960,16 +960,17 @@ __device__ __forceinline__ T fetch(const T* p) {
 }
 
 // Block-wide maximum of a 64-bit key (every thread active), uniform result,
-// one barrier: the wave maxima go to half `par` of sh (2 x 16 entries);
-// consecutive calls alternate halves.
-__device__ __forceinline__ u64 block_max_key(u64 v, u64* sh, int par) {
+// one barrier: the wave maxima meet in slot sh[slot] by LDS atomic max
+// (slots 0..2 zero before the first call, used in turn by consecutive calls;
+// the next slot, last read two calls ago, is cleared here).
+__device__ __forceinline__ u64 block_max_key(u64 v, u64* sh, int slot) {
   const unsigned hi = wave_ext_u32<true>((unsigned)(v >> 32));
   const unsigned lo = wave_ext_u32<true>((unsigned)(v >> 32) == hi ? (unsigned)(v & 0xFFFFFFFFull) : 0u);
-  if ((threadIdx.x & 63) == 0) sh[par * 16 + (threadIdx.x >> 6)] = ((u64)hi << 32) | lo;
+  const u64 w = ((u64)hi << 32) | lo;
+  if ((threadIdx.x & 63) == 0 && w != 0ull) atomicMax(&sh[slot], w);
+  if (threadIdx.x == 0) sh[slot == 2 ? 0 : slot + 1] = 0ull;
   __syncthreads();
-  u64 r = sh[par * 16];
-  for (int k = 1; k < (int)(blockDim.x >> 6); ++k) r = sh[par * 16 + k] > r ? sh[par * 16 + k] : r;
-  return uniform(r);
+  return uniform(sh[slot]);
 }
 
 // Multi-workgroup phase 2.  Workgroup j owns a slice of wcols columns.  Each
@@ -1017,6 +1018,7 @@ __global__ __launch_bounds__(kCoopThreads) void phase2_coop_kernel(const Phase2C
   T* vloc = u + nr;                                // own entries of the new V column
   char* lr = reinterpret_cast<char*>(vloc + d.wcols);
   char* lc = lr + nr;
+  if (tid < 3) s_red[tid] = 0ull;
   for (int i = tid; i < nr; i += nt) lr[i] = 1;
   for (int c = tid; c < w; c += nt) lc[c] = 1;
   __syncthreads();
@@ -1089,7 +1091,7 @@ __global__ __launch_bounds__(kCoopThreads) void phase2_coop_kernel(const Phase2C
     }
     u64 best = make_key(bq, bidx);
     best = block_max_key(best, s_red, rpar);
-    rpar ^= 1;
+    rpar = rpar == 2 ? 0 : rpar + 1;
     // publish the best key's column, then (after every thread's stores are
     // done) the tagged key
     if (best != 0ull) {
