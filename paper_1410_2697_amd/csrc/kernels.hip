@@ -73,6 +73,24 @@ __device__ __forceinline__ int find_desc(const D* d, int n, int key) {
   }
   return lo;
 }
+// The same search by a whole workgroup (every thread calls it): each thread
+// probes one descriptor, so a round is one parallel load instead of a chain
+// of dependent ones; the probes at or below key form a prefix, counted by
+// one barrier.  More than blockDim.x descriptors take a coarse round first.
+template <typename D>
+__device__ __forceinline__ int find_desc_wg(const D* d, int n, int key) {
+  const int t = threadIdx.x, nt = blockDim.x;
+  int lo = 0, hi = n;                       // d[lo].tile0 <= key; the answer is in [lo, hi)
+  while (hi - lo > nt) {
+    const int step = (hi - lo + nt - 1) / nt;
+    const int i = lo + t * step;
+    const int c = __syncthreads_count(i < hi && d[i].tile0 <= key);
+    lo += (c - 1) * step;
+    hi = min(hi, lo + step);
+  }
+  const int c = __syncthreads_count(lo + t < hi && d[lo + t].tile0 <= key);
+  return lo + c - 1;
+}
 
 // 16x16x4 MFMA: lane l supplies A(l%16, l/16) and B(l/16, l%16); its four
 // accumulator values hold D(row(l/16, v), l%16), v = 0..3.  The row map
@@ -129,7 +147,7 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc<T>* __restrict__ descs,
   __shared__ T Bs[BK][BN + 1];
   typedef typename Mfma<T>::v4 v4;
   const int tid = threadIdx.x;
-  const int di = find_desc(descs, ndesc, (int)blockIdx.x);
+  const int di = find_desc_wg(descs, ndesc, (int)blockIdx.x);
   const GemmDesc<T>& d = descs[di];
   const int lt = (int)blockIdx.x - d.tile0;
   const int tm = lt % d.tiles_m, rest = lt / d.tiles_m;
@@ -263,7 +281,7 @@ __global__ __launch_bounds__(256) void gemm_narrow_kernel(const GemmDesc<T>* __r
 
 template <typename T>
 __global__ __launch_bounds__(256) void gemm_reduce_kernel(const GemmDesc<T>* __restrict__ descs, int ndesc) {
-  const int di = find_desc(descs, ndesc, (int)blockIdx.x);
+  const int di = find_desc_wg(descs, ndesc, (int)blockIdx.x);
   const GemmDesc<T>& d = descs[di];
   const int lt = (int)blockIdx.x - d.tile0;
   const int m0 = (lt % d.tiles_m) * kTile, n0 = (lt / d.tiles_m) * kTile;
@@ -1183,7 +1201,7 @@ __global__ __launch_bounds__(kCoopThreads) void phase2_coop_kernel(const Phase2C
 // ----------------------------------------------------------- extend-add ----
 template <typename T>
 __global__ __launch_bounds__(256) void extadd_kernel(const ExtAddDesc<T>* __restrict__ descs, int ndesc) {
-  const int di = find_desc(descs, ndesc, (int)blockIdx.x);
+  const int di = find_desc_wg(descs, ndesc, (int)blockIdx.x);
   const ExtAddDesc<T>& d = descs[di];
   const int lt = (int)blockIdx.x - d.tile0;
   const int tr = lt % d.tiles_r, tc = lt / d.tiles_r;
@@ -1201,7 +1219,7 @@ __global__ __launch_bounds__(256) void extadd_kernel(const ExtAddDesc<T>* __rest
 // ----------------------------------------------------------------- copy ----
 template <typename S, typename D>
 __global__ __launch_bounds__(256) void copy_kernel(const CopyDesc<S, D>* __restrict__ descs, int ndesc) {
-  const int di = find_desc(descs, ndesc, (int)blockIdx.x);
+  const int di = find_desc_wg(descs, ndesc, (int)blockIdx.x);
   const CopyDesc<S, D>& d = descs[di];
   const int lt = (int)blockIdx.x - d.tile0;
   const int tr = lt % d.tiles_r, tc = lt / d.tiles_r;
