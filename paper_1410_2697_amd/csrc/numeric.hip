@@ -1718,8 +1718,10 @@ typename Numeric<T>::Plan* Numeric<T>::get_plan(int nrhs) {
       size_t o = b.add(va);
       pl->recs.push_back({2, o, (int)va.size(), 0});
     }
+    // u2 (after u1) and lf1 (after the copy zc) touch different memory, so
+    // they share one launch
+    lf1.v.insert(lf1.v.end(), u2.v.begin(), u2.v.end());
     rec_gemm(u1);
-    rec_gemm(u2);
     rec_copy(zc);
     rec_gemm(lf1);
     rec_gemm(lf2);
