@@ -1755,11 +1755,21 @@ typename Numeric<T>::Plan* Numeric<T>::get_plan(int nrhs) {
       rec_gemm(g3);
     }
   }
-  // downward pass
+  // downward pass.  Every HODLR front's z is final after the upward pass:
+  // one launch copies them all into x, where the downward corrections then
+  // accumulate directly
+  {
+    CopyBatch<T, T> zx;
+    for (int p = 0; p < nfr; ++p) {
+      const Front& f = s.fronts[p];
+      if (fn[p].dense || f.npiv == 0) continue;
+      zx.v.push_back(cd<T, T>(wk + z_off[p], f.npiv, pl->xn + f.start, N, f.npiv, nrhs));
+    }
+    rec_copy(zx);
+  }
   for (int h = H - 1; h >= 0; --h) {
     std::vector<VecGatherDesc<T>> vg;
     GemmBatch<T> d1, d2;
-    CopyBatch<T, T> xo;
     for (int p : s.levels[h]) {
       const Front& f = s.fronts[p];
       const FN& x = fn[p];
@@ -1779,9 +1789,8 @@ typename Numeric<T>::Plan* Numeric<T>::get_plan(int nrhs) {
         T* hb = wk + h_off[p];
         if (x.r_top > 0) {
           d1.v.push_back(gd<T>(x.W, nf, 1, t + np, nh, 0, hb, x.r_top, x.r_top, nrhs, nf, 1.0, 0.0, bff));
-          d2.v.push_back(gd<T>(x.G, np, 0, hb, x.r_top, 0, z, np, np, nrhs, x.r_top, -1.0, 1.0));
+          d2.v.push_back(gd<T>(x.G, np, 0, hb, x.r_top, 0, pl->xn + f.start, N, np, nrhs, x.r_top, -1.0, 1.0));
         }
-        xo.v.push_back(cd<T, T>(z, np, pl->xn + f.start, N, np, nrhs));
       }
     }
     // the gather needs each front's I_p^f on the device
@@ -1803,7 +1812,6 @@ typename Numeric<T>::Plan* Numeric<T>::get_plan(int nrhs) {
     }
     rec_gemm(d1);
     rec_gemm(d2);
-    rec_copy(xo);
   }
   pl->desc = pl->dp.upload(b, st);
   HIPCHK(hipStreamSynchronize(st));
