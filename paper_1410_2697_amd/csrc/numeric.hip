@@ -1644,7 +1644,10 @@ typename Numeric<T>::Plan* Numeric<T>::get_plan(int nrhs) {
   for (int p = 0; p < nfr; ++p) {
     const Front& f = s.fronts[p];
     t_off[p] = tot; tot += (int64_t)f.n() * nrhs;
-    z_off[p] = tot; tot += (int64_t)f.npiv * nrhs;
+    // a HODLR front's z is its t's pivot rows (read by X^T t before the
+    // leaf solves change them in place); a dense front's z is separate
+    if (fn[p].dense) { z_off[p] = tot; tot += (int64_t)f.npiv * nrhs; }
+    else z_off[p] = t_off[p];
     if (!fn[p].dense) {
       h_off[p] = tot; tot += (int64_t)std::max(fn[p].r_top, 1) * nrhs;
       q_off[p].assign(f.pp_tree.size(), 0);
@@ -1675,7 +1678,6 @@ typename Numeric<T>::Plan* Numeric<T>::get_plan(int nrhs) {
   for (int h = 0; h < H; ++h) {
     std::vector<VecAsmDesc<T>> va;
     GemmBatch<T> u1, u2, lf1, lf2;
-    CopyBatch<T, T> zc;
     int Lmax = 0;
     for (int p : s.levels[h]) {
       const Front& f = s.fronts[p];
@@ -1702,14 +1704,13 @@ typename Numeric<T>::Plan* Numeric<T>::get_plan(int nrhs) {
           u1.v.push_back(gd<T>(x.G, np, 1, t, nh, 0, hb, x.r_top, x.r_top, nrhs, np, 1.0, 0.0));   // X^T t_p
           u2.v.push_back(gd<T>(x.W, nf, 0, hb, x.r_top, 0, t + np, nh, nf, nrhs, x.r_top, -1.0, 1.0, bff));
         }
-        zc.v.push_back(cd<T, T>(t, nh, z, np, np, nrhs));
         for (size_t i = 0; i < f.pp_tree.size(); ++i) {
           const TreeNode& tn = f.pp_tree[i];
           if (tn.left >= 0) { Lmax = std::max(Lmax, tn.level + 1); continue; }
           T* T1 = wk + l_off[p][i];
-          lf1.v.push_back(gd<T>(x.leafInv[i], tn.size, 0, z + tn.off, np, 0, T1, tn.size, tn.size, nrhs, tn.size, 1.0,
+          lf1.v.push_back(gd<T>(x.leafInv[i], tn.size, 0, z + tn.off, nh, 0, T1, tn.size, tn.size, nrhs, tn.size, 1.0,
                                 0.0, GF_A_LOWER));
-          lf2.v.push_back(gd<T>(x.leafInv[i], tn.size, 1, T1, tn.size, 0, z + tn.off, np, tn.size, nrhs, tn.size, 1.0,
+          lf2.v.push_back(gd<T>(x.leafInv[i], tn.size, 1, T1, tn.size, 0, z + tn.off, nh, tn.size, nrhs, tn.size, 1.0,
                                 0.0, GF_A_UPPER));
         }
       }
@@ -1718,11 +1719,10 @@ typename Numeric<T>::Plan* Numeric<T>::get_plan(int nrhs) {
       size_t o = b.add(va);
       pl->recs.push_back({2, o, (int)va.size(), 0});
     }
-    // u2 (after u1) and lf1 (after the copy zc) touch different memory, so
-    // they share one launch
+    // u2 (rows np.. of t, after u1) and lf1 (reads the pivot rows of t,
+    // after u1 has read them) touch different memory, so they share a launch
     lf1.v.insert(lf1.v.end(), u2.v.begin(), u2.v.end());
     rec_gemm(u1);
-    rec_copy(zc);
     rec_gemm(lf1);
     rec_gemm(lf2);
     for (int l = Lmax - 1; l >= 0; --l) {
@@ -1732,7 +1732,7 @@ typename Numeric<T>::Plan* Numeric<T>::get_plan(int nrhs) {
         const Front& f = s.fronts[p];
         const FN& x = fn[p];
         T* z = wk + z_off[p];
-        const int np = f.npiv;
+        const int np = f.npiv, zl = f.n();
         for (size_t i = 0; i < f.pp_tree.size(); ++i) {
           const TreeNode& t = f.pp_tree[i];
           if (t.left < 0 || t.level != l || x.nodeR[i] == 0) continue;
@@ -1741,12 +1741,12 @@ typename Numeric<T>::Plan* Numeric<T>::get_plan(int nrhs) {
           const int r = x.nodeR[i], n2 = 2 * r, c = x.col[l];
           T* q = wk + q_off[p][i];
           T* q2 = q + (int64_t)n2 * nrhs;
-          g1.v.push_back(gd<T>(x.nodeV[i], a.size, 1, z + a.off, np, 0, q, n2, r, nrhs, a.size, 1.0, 0.0, bff));
-          g1.v.push_back(gd<T>(x.nodeU[i], be.size, 1, z + be.off, np, 0, q + r, n2, r, nrhs, be.size, 1.0, 0.0, bff));
+          g1.v.push_back(gd<T>(x.nodeV[i], a.size, 1, z + a.off, zl, 0, q, n2, r, nrhs, a.size, 1.0, 0.0, bff));
+          g1.v.push_back(gd<T>(x.nodeU[i], be.size, 1, z + be.off, zl, 0, q + r, n2, r, nrhs, be.size, 1.0, 0.0, bff));
           g2.v.push_back(gd<T>(x.nodeK[i], n2, 0, q, n2, 0, q2, n2, n2, nrhs, n2, 1.0, 0.0));
-          g3.v.push_back(gd<T>(x.G + a.off + (int64_t)c * np, np, 0, q2, n2, 0, z + a.off, np, a.size, nrhs, r, -1.0,
+          g3.v.push_back(gd<T>(x.G + a.off + (int64_t)c * np, np, 0, q2, n2, 0, z + a.off, zl, a.size, nrhs, r, -1.0,
                                1.0));
-          g3.v.push_back(gd<T>(x.G + be.off + (int64_t)c * np, np, 0, q2 + r, n2, 0, z + be.off, np, be.size, nrhs, r,
+          g3.v.push_back(gd<T>(x.G + be.off + (int64_t)c * np, np, 0, q2 + r, n2, 0, z + be.off, zl, be.size, nrhs, r,
                                -1.0, 1.0));
         }
       }
@@ -1763,7 +1763,7 @@ typename Numeric<T>::Plan* Numeric<T>::get_plan(int nrhs) {
     for (int p = 0; p < nfr; ++p) {
       const Front& f = s.fronts[p];
       if (fn[p].dense || f.npiv == 0) continue;
-      zx.v.push_back(cd<T, T>(wk + z_off[p], f.npiv, pl->xn + f.start, N, f.npiv, nrhs));
+      zx.v.push_back(cd<T, T>(wk + z_off[p], f.n(), pl->xn + f.start, N, f.npiv, nrhs));
     }
     rec_copy(zx);
   }
