@@ -255,7 +255,7 @@ void launch_phase2(const Phase2Desc<T>* d, int ndesc, int maxrc, double eps, int
 // exceed it).  Launches are serialised process-wide and the launcher waits
 // for completion (synchronous); a barrier wait longer than spin_limit polls
 // sets status bit 8 and ends the loop.  Returns the launch or wait error.
-constexpr int kPhase2CoopLds = 64 * 1024;
+constexpr int kPhase2CoopLds = 78 * 1024;   // two workgroups fill a CU's 160 KB of LDS
 // threads of a multi-workgroup phase-2 workgroup (more waves make the
 // per-step barriers slower than they make the update faster), and the
 // fewest columns per workgroup the host gives a block (one per wave)
