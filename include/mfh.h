@@ -76,8 +76,9 @@ typedef struct {
                            as a HIP graph, and it and every later apply with that count
                            replay it; earlier applies launch each kernel (recording costs
                            about as much as a few applies).  0: never record.  At most
-                           2^20.  While mf_prof_start times the GEMM kernels the apply
-                           launches them directly.                                         */
+                           2^20.  A timing session (mf_prof_start) times the direct
+                           applies' launches; the graph is recorded untimed, so its
+                           replays run as they would without the session.             */
   int32_t reserved0;    /* must be 0 */
   double eps;           /* low-rank tolerance (Sec. 2.2: stop when |u_r+1,r+1/u_11| < eps) */
   void* stream;         /* hipStream_t, borrowed; NULL = null stream                      */

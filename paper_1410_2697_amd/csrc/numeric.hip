@@ -1207,9 +1207,12 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
     }
   }
   // multi-workgroup launches: consecutive groups of blocks of one slice mode
-  // whose workgroups can all be resident (descriptors ordered by mode)
+  // whose workgroups can all be resident.  Descriptors are ordered by mode,
+  // then by size, largest first: a launch lasts as long as its slowest block,
+  // so blocks of like size share launches.
   std::stable_sort(p2c.begin(), p2c.end(), [](const Phase2CoopDesc<T>& a, const Phase2CoopDesc<T>& b) {
-    return a.slice_lds > b.slice_lds;
+    if (a.slice_lds != b.slice_lds) return a.slice_lds > b.slice_lds;
+    return (int64_t)a.nr * a.nc > (int64_t)b.nr * b.nc;
   });
   struct CoopGroup { size_t first; int n, wgs; bool slds; };
   std::vector<CoopGroup> cgroups;
@@ -1829,13 +1832,12 @@ void Numeric<T>::apply(int nrhs, const double* r, double* z, hipStream_t stream)
   const int N = sym->n;
   launch_perm_in<T>(r, pl->xn, d_perm.as<int>(), N, nrhs, stream);
   // the apply_graph-th apply with this count records the graph (recording
-  // costs about as much as a few direct applies); a recorded apply cannot
-  // time its launches, so it launches directly while its GEMM kernels are
-  // being timed
+  // costs about as much as a few direct applies).  Its nodes are recorded
+  // untimed: while a timing session runs, only the direct applies (and the
+  // factorization's launches) are timed, and the replays run as they would
+  // without it.
   ++pl->uses;
-  bool replay = opts.apply_graph > 0 && pl->uses >= opts.apply_graph && !pl->no_graph &&
-                !prof_selected(pk<T>(PK_GEMM_F64)) &&
-                !prof_selected(pk<T>(PK_GEMMN_F64)) && !prof_selected(pk<T>(PK_GEMM_REDUCE_F64));
+  bool replay = opts.apply_graph > 0 && pl->uses >= opts.apply_graph && !pl->no_graph;
   if (replay && !pl->exec) {
     // record the step sequence once on a stream of this handle; the plan's
     // buffers and descriptors stay put, so the graph stays valid with it
@@ -1843,7 +1845,9 @@ void Numeric<T>::apply(int nrhs, const double* r, double* z, hipStream_t stream)
     bool ok = cap || hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) == hipSuccess;
     ok = ok && hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
     if (ok) {
+      prof_suspend(true);
       launch_recs(*pl, cap);
+      prof_suspend(false);
       ok = hipStreamEndCapture(cap, &g) == hipSuccess && g;
       ok = ok && hipGraphInstantiate(&pl->exec, g, nullptr, nullptr, 0) == hipSuccess;
       if (g) (void)hipGraphDestroy(g);

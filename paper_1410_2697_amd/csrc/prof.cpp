@@ -35,6 +35,7 @@ struct Rec {
 };
 constexpr int kSlots = 1 << 16;
 thread_local int t_pending = -1;   // record whose events the next MFH_LAUNCH takes
+thread_local bool t_suspended = false;
 
 struct State {
   std::mutex mu;
@@ -78,10 +79,11 @@ Rec* find(State& s, int id) {
 const char* prof_name(int kind) { return (kind >= 0 && kind < PK_COUNT) ? kNames[kind] : "?"; }
 
 bool prof_selected(int kind) { return ((S().mask.load(std::memory_order_relaxed) >> kind) & 1) != 0; }
+void prof_suspend(bool on) { t_suspended = on; }
 
 int prof_begin(int kind, hipStream_t st, double flops, double bytes) {
   State& s = S();
-  if (!((s.mask.load(std::memory_order_relaxed) >> kind) & 1)) return -1;
+  if (t_suspended || !((s.mask.load(std::memory_order_relaxed) >> kind) & 1)) return -1;
   std::lock_guard<std::mutex> g(s.mu);
   if (s.recs.size() >= (size_t(1) << kIdxBits)) return -1;
   Rec r{kind, take(s), take(s), flops, bytes, 0, -1};

@@ -38,6 +38,9 @@ constexpr int pk(int f64_kind) { return sizeof(T) == 4 ? f64_kind + 1 : f64_kind
 const char* prof_name(int kind);
 // true while a timing session selects this kernel kind
 bool prof_selected(int kind);
+// while set on this thread, no launch is timed (used while a HIP graph is
+// recorded: its nodes are replayed untimed)
+void prof_suspend(bool on);
 
 // id >= 0 when the launch is timed; -1 otherwise (all calls then do nothing).
 // A timed record hands its two events to the next kernel launched by this
