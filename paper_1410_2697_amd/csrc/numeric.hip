@@ -233,6 +233,69 @@ struct PinnedScratch {
   D* as(size_t off_bytes) { return reinterpret_cast<D*>(c.p + off_bytes); }
 };
 
+// Streams and events of finished factorizations, kept per device for the
+// next ones: creating a stream costs about a tenth of a millisecond.  An
+// owner returns them only after synchronising them.
+class HipObjPool {
+ public:
+  static hipStream_t stream(int dev) {
+    {
+      std::lock_guard<std::mutex> g(mu());
+      auto& v = streams()[dev];
+      if (!v.empty()) {
+        hipStream_t s = v.back();
+        v.pop_back();
+        return s;
+      }
+    }
+    hipStream_t s = nullptr;
+    HIPCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    return s;
+  }
+  static hipEvent_t event(int dev) {
+    {
+      std::lock_guard<std::mutex> g(mu());
+      auto& v = events()[dev];
+      if (!v.empty()) {
+        hipEvent_t e = v.back();
+        v.pop_back();
+        return e;
+      }
+    }
+    hipEvent_t e = nullptr;
+    HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    return e;
+  }
+  static void put(int dev, hipStream_t s) {
+    if (!s) return;
+    std::lock_guard<std::mutex> g(mu());
+    if (streams()[dev].size() < kKeep) streams()[dev].push_back(s);
+    else (void)hipStreamDestroy(s);
+  }
+  static void put(int dev, hipEvent_t e) {
+    if (!e) return;
+    std::lock_guard<std::mutex> g(mu());
+    if (events()[dev].size() < 2 * kKeep) events()[dev].push_back(e);
+    else (void)hipEventDestroy(e);
+  }
+
+ private:
+  static constexpr size_t kKeep = 16;
+  static std::mutex& mu() {
+    static std::mutex m;
+    return m;
+  }
+  // never destroyed: what is listed at exit goes with the process
+  static std::map<int, std::vector<hipStream_t>>& streams() {
+    static auto* m = new std::map<int, std::vector<hipStream_t>>();
+    return *m;
+  }
+  static std::map<int, std::vector<hipEvent_t>>& events() {
+    static auto* m = new std::map<int, std::vector<hipEvent_t>>();
+    return *m;
+  }
+};
+
 // Uploads descriptor blobs through pinned staging.  The device copies live
 // until the pool is destroyed; its owner has synchronised the streams that
 // read them (and the staged copies) by then.
@@ -645,10 +708,11 @@ class Numeric : public NumericBase {
       if (!self->constructed) (void)hipStreamSynchronize(self->st);
       if (self->side) (void)hipStreamSynchronize(self->side);
       self->wait_streams();
-      if (self->ev_fork) (void)hipEventDestroy(self->ev_fork);
-      if (self->ev_join) (void)hipEventDestroy(self->ev_join);
-      if (self->side) (void)hipStreamDestroy(self->side);
-      if (self->cap) (void)hipStreamDestroy(self->cap);
+      if (self->cap) (void)hipStreamSynchronize(self->cap);
+      HipObjPool::put(self->device, self->ev_fork);
+      HipObjPool::put(self->device, self->ev_join);
+      HipObjPool::put(self->device, self->side);
+      HipObjPool::put(self->device, self->cap);
     }
   } sync_guard{this};
 };
@@ -686,9 +750,9 @@ Numeric<T>::Numeric(const Symbolic& s, const double* vals, const mf_opts& o) {
     fn[p].ld = f.n();
   }
   if (hodlr) {
-    HIPCHK(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
-    HIPCHK(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
-    HIPCHK(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
+    side = HipObjPool::stream(device);
+    ev_fork = HipObjPool::event(device);
+    ev_join = HipObjPool::event(device);
   }
 
   // BDLR sets are host graph work: worker threads take the HODLR fronts in
