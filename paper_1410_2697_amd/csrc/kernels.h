@@ -252,8 +252,8 @@ void launch_phase2(const Phase2Desc<T>* d, int ndesc, int maxrc, double eps, int
 // does); phase2_coop_lds: dynamic LDS bytes of a workgroup, with the slice in
 // LDS or (slice_lds false) updated in place in the front; phase2_coop_capacity:
 // workgroups that can be resident at once with that LDS (a launch must not
-// exceed it).  Launches are serialised process-wide and the launcher waits
-// for completion (synchronous); a barrier wait longer than spin_limit polls
+// exceed it).  A launch waits on the host for the device's previous one
+// unless both are on one stream; a barrier wait longer than spin_limit polls
 // sets status bit 8 and ends the loop.  Returns the launch or wait error.
 constexpr int kPhase2CoopLds = 78 * 1024;   // two workgroups fill a CU's 160 KB of LDS
 // threads of a multi-workgroup phase-2 workgroup (more waves make the

@@ -1,5 +1,7 @@
 // Device kernels for gfx950 (CDNA4, wave64).  See kernels.h for the
 // descriptor of each launch.
+#include <map>
+#include <tuple>
 #include "kernels.h"
 #include "prof.h"
 
@@ -1731,36 +1733,67 @@ template <typename T>
 int phase2_coop_capacity(size_t lds, bool slice_lds) {
   int dev = 0, cus = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
+  // the answer depends only on (device, mode, LDS): asked once, then kept
+  static std::mutex mu;
+  static std::map<std::tuple<int, bool, size_t>, int> known;
+  const auto key = std::make_tuple(dev, slice_lds, lds);
+  {
+    std::lock_guard<std::mutex> g(mu);
+    const auto it = known.find(key);
+    if (it != known.end()) return it->second;
+  }
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
   const void* k = slice_lds ? reinterpret_cast<const void*>(phase2_coop_kernel<T, true>)
                             : reinterpret_cast<const void*>(phase2_coop_kernel<T, false>);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, kCoopThreads, lds) != hipSuccess) return 0;
+  std::lock_guard<std::mutex> g(mu);
+  known[key] = per * cus;
   return per * cus;
 }
-// One multi-workgroup phase-2 launch runs at a time in the process, and the
-// launcher waits for it: two spin-barrier launches on different streams could
-// otherwise each hold resources the other's missing workgroups need.  The
-// grid never exceeds the resident capacity, so on its own a launch always
-// gets all its workgroups resident once other streams' (finite) kernels
-// drain; the bounded barrier poll turns any stall into status bit 8.
-std::mutex& phase2_coop_mutex() {
-  static std::mutex m;
-  return m;
-}
+// One multi-workgroup phase-2 launch runs at a time on a device: two
+// spin-barrier launches on different streams could otherwise each hold
+// resources the other's missing workgroups need.  Before a launch the host
+// waits for the device's previous one unless both are on one stream (which
+// orders them already).  The grid never exceeds the resident capacity, so on
+// its own a launch always gets all its workgroups resident once other
+// streams' (finite) kernels drain; the bounded barrier poll turns any stall
+// into status bit 8.
 template <typename T>
 hipError_t launch_phase2_coop(const Phase2CoopDesc<T>* d, int ndesc, int wgs, size_t lds, bool slice_lds,
                               double eps, int* status, int spin_limit, hipStream_t st) {
   if (ndesc <= 0 || wgs <= 0) return hipSuccess;
-  std::lock_guard<std::mutex> g(phase2_coop_mutex());
+  struct Last {
+    hipEvent_t ev = nullptr;
+    hipStream_t st = nullptr;
+    bool pending = false;
+  };
+  static std::mutex mu;
+  static std::map<int, Last> last;   // by device
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> g(mu);
+  Last& L = last[dev];
+  if (!L.ev) {
+    e = hipEventCreateWithFlags(&L.ev, hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+  }
+  if (L.pending && L.st != st) {
+    e = hipEventSynchronize(L.ev);
+    if (e != hipSuccess) return e;
+  }
   if (slice_lds)
     MFH_LAUNCH((phase2_coop_kernel<T, true>), dim3(wgs), dim3(kCoopThreads), lds, st, d, ndesc, eps, status,
                spin_limit);
   else
     MFH_LAUNCH((phase2_coop_kernel<T, false>), dim3(wgs), dim3(kCoopThreads), lds, st, d, ndesc, eps, status,
                spin_limit);
-  const hipError_t e = hipGetLastError();
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return hipStreamSynchronize(st);
+  e = hipEventRecord(L.ev, st);
+  L.st = st;
+  L.pending = e == hipSuccess;
+  return e;
 }
 template <typename T>
 void launch_extadd(const ExtAddDesc<T>* d, int ndesc, int tiles, hipStream_t st) {
