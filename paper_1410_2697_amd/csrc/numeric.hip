@@ -205,7 +205,7 @@ class PinnedPool {
   }
 
  private:
-  static constexpr size_t kMinChunk = (size_t)1 << 20, kMaxHeld = (size_t)64 << 20;
+  static constexpr size_t kMinChunk = (size_t)1 << 20, kMaxHeld = (size_t)256 << 20;
   static std::mutex& mu() {
     static std::mutex m;
     return m;
@@ -736,11 +736,29 @@ Numeric<T>::Numeric(const Symbolic& s, const double* vals, const mf_opts& o) {
   d_perm.alloc(n * sizeof(int), &ms);
   d_iperm.alloc(n * sizeof(int), &ms);
   d_status.alloc(sizeof(int), &ms);
-  HIPCHK(hipMemcpyAsync(d_rowptr.p, s.rowptr.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(d_colind.p, s.colind.data(), s.nnz * sizeof(int), hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(d_vals.p, vals, s.nnz * sizeof(double), hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(d_perm.p, s.perm.data(), n * sizeof(int), hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(d_iperm.p, s.iperm.data(), n * sizeof(int), hipMemcpyHostToDevice, st));
+  {
+    // A's pattern, values and the permutation go through pinned staging
+    // (filled by the host threads), so the copies are queued and the host
+    // goes on planning while they run
+    struct Up { void* dst; const void* src; size_t bytes; };
+    const Up ups[5] = {{d_rowptr.p, s.rowptr.data(), (size_t)(n + 1) * sizeof(int)},
+                       {d_colind.p, s.colind.data(), (size_t)s.nnz * sizeof(int)},
+                       {d_vals.p, vals, (size_t)s.nnz * sizeof(double)},
+                       {d_perm.p, s.perm.data(), (size_t)n * sizeof(int)},
+                       {d_iperm.p, s.iperm.data(), (size_t)n * sizeof(int)}};
+    for (const Up& u : ups) {
+      char* h = dp.host<char>(u.bytes);
+      const size_t ch = 1 << 20;
+      const int nch = (int)((u.bytes + ch - 1) / ch);
+      parallel_for(nch, 1, [&](int b, int e, int) {
+        for (int c = b; c < e; ++c) {
+          const size_t o = (size_t)c * ch;
+          memcpy(h + o, static_cast<const char*>(u.src) + o, std::min(ch, u.bytes - o));
+        }
+      });
+      HIPCHK(hipMemcpyAsync(u.dst, h, u.bytes, hipMemcpyHostToDevice, st));
+    }
+  }
   launch_fill<int>(d_status.as<int>(), 1, 0, st);
 
   fn.resize(nfr);
