@@ -1549,20 +1549,24 @@ __global__ void perm_out_kernel(const T* xn, double* z, const int* iperm, int N,
 }
 
 // ------------------------------------------------------- Krylov / SpMV ----
-// one thread per row, all right-hand sides: A's row is read once
+constexpr int kSpmvLanes = 8;   // lanes per matrix row (rows of 3D stencils hold 7 to 27 entries)
+// kSpmvLanes lanes per row, all right-hand sides: the lanes of a row read
+// its entries in consecutive pairs of (column, value), so a row's entries come
+// in one pass, and combine their partial sums with shuffles
 __global__ __launch_bounds__(256) void spmv_kernel(const int* __restrict__ rowptr, const int* __restrict__ colind,
                                                    const double* __restrict__ vals, const double* __restrict__ x,
                                                    double* y, int n, int nrhs, double alpha, double beta) {
-  constexpr int KB = 16;
-  const int row = blockIdx.x * blockDim.x + threadIdx.x;
-  if (row >= n) return;
+  constexpr int KB = 16, G = kSpmvLanes;
+  const int row = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G);
+  const int g = threadIdx.x % G;
+  if (row >= n) return;                    // whole groups leave together (G divides the wave)
   const int j0 = rowptr[row], j1 = rowptr[row + 1];
   for (int k0 = 0; k0 < nrhs; k0 += KB) {
     const int kb = min(KB, nrhs - k0);
     double acc[KB];
 #pragma unroll
     for (int q = 0; q < KB; ++q) acc[q] = 0.0;
-    for (int j = j0; j < j1; ++j) {
+    for (int j = j0 + g; j < j1; j += G) {
       const double v = vals[j];
       const double* xc = x + colind[j] + (size_t)k0 * n;
 #pragma unroll
@@ -1571,7 +1575,11 @@ __global__ __launch_bounds__(256) void spmv_kernel(const int* __restrict__ rowpt
     }
 #pragma unroll
     for (int q = 0; q < KB; ++q)
-      if (q < kb) {
+      if (q < kb)
+        for (int o = G / 2; o > 0; o >>= 1) acc[q] += __shfl_xor(acc[q], o, G);
+#pragma unroll
+    for (int q = 0; q < KB; ++q)
+      if (q < kb && q % G == g) {
         double* yo = y + (size_t)(k0 + q) * n + row;
         *yo = beta == 0.0 ? alpha * acc[q] : alpha * acc[q] + beta * *yo;
       }
@@ -1864,8 +1872,8 @@ void launch_perm_out(const T* xn, double* z, const int* iperm, int N, int nrhs, 
 
 void launch_spmv(const int* rowptr, const int* colind, const double* vals, const double* x, double* y, int n,
                  int nrhs, double alpha, double beta, hipStream_t st) {
-  MFH_LAUNCH(spmv_kernel, dim3((n + 255) / 256), dim3(256), 0, st, rowptr, colind, vals, x, y, n, nrhs,
-                     alpha, beta);
+  MFH_LAUNCH(spmv_kernel, dim3((int)(((int64_t)n * kSpmvLanes + 255) / 256)), dim3(256), 0, st, rowptr, colind,
+             vals, x, y, n, nrhs, alpha, beta);
 }
 void launch_mdot(const double* X, int64_t xstride, int nv, const double* w, int n, int nrhs, double* partial,
                  double* out, int accumulate, hipStream_t st) {

@@ -361,9 +361,10 @@ GemmDesc<T> gd(const T* A, int lda, int opA, const T* B, int ldb, int opB, T* C,
 // problem takes its own region), followed by a fixed-order reduction.
 constexpr int kSpinLimit = 1 << 20;   // barrier polls before a phase-2 workgroup gives up
 constexpr int kSplitTarget = 512;   // workgroups wanted per launch (two per CU)
+constexpr int kSplitTargetNarrow = 1024;   // the same for right-hand-side tiles (four resident per CU)
 constexpr int kSplitChunk = 128;    // smallest k range of one split
 constexpr size_t kSplitFactorBytes = size_t(16) << 20;
-constexpr size_t kSplitPlanBytes = size_t(4) << 20;
+constexpr size_t kSplitPlanBytes = size_t(16) << 20;
 
 // assigns tile0/tiles_m/tiles_n/ksplit; returns total tiles; `red` receives
 // the reduction descriptors of split problems (tile0 over output tiles)
@@ -375,7 +376,8 @@ int finalize_gemm(std::vector<GemmDesc<T>>& v, T* part, size_t cap, std::vector<
   int base = 0;
   for (const auto& d : v)
     if (d.m > 0 && d.n > 0) base += cdiv(d.m, kTile) * cdiv(d.n, tn);
-  const int want = (part && base > 0 && 2 * base <= kSplitTarget) ? kSplitTarget / base : 1;
+  const int target = tn == kTileNarrow ? kSplitTargetNarrow : kSplitTarget;
+  const int want = (part && base > 0 && 2 * base <= target) ? target / base : 1;
   size_t used = 0;
   int t = 0;
   std::vector<GemmDesc<T>> out;
