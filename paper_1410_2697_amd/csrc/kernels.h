@@ -315,6 +315,10 @@ void launch_perm_out(const T* xn, double* z, const int* iperm, int N, int nrhs, 
 void launch_spmv(const int* rowptr, const int* colind, const double* vals, const double* x,
                  double* y, int n, int nrhs, double alpha, double beta, hipStream_t st);
 // dots[i*nrhs + k] (+)= <X_i(:,k), w(:,k)> for i < nv; X_i = X + i*ld*nrhs...
+// `partial` holds mdot_chunks(nrhs) * nv * nrhs doubles: the row range is cut
+// into that many chunks per right-hand side (more for few right-hand sides,
+// so that one launch still spreads over the whole chip)
+inline int mdot_chunks(int nrhs) { return nrhs >= 16 ? 64 : nrhs >= 2 ? 1024 / nrhs : 512; }
 void launch_mdot(const double* X, int64_t xstride, int nv, const double* w, int n, int nrhs,
                  double* partial, double* out, int accumulate, hipStream_t st);
 void launch_maxpy(const double* X, int64_t xstride, int nv, const double* coef, double* w, int n,

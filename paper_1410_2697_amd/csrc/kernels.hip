@@ -1550,9 +1550,9 @@ __global__ void perm_out_kernel(const T* xn, double* z, const int* iperm, int N,
 
 // ------------------------------------------------------- Krylov / SpMV ----
 constexpr int kSpmvLanes = 8;   // lanes per matrix row (rows of 3D stencils hold 7 to 27 entries)
-// kSpmvLanes lanes per row, all right-hand sides: the lanes of a row read
-// its entries in consecutive pairs of (column, value), so a row's entries come
-// in one pass, and combine their partial sums with shuffles
+// kSpmvLanes lanes per row, all right-hand sides: lane g of a row takes its
+// entries g, g + kSpmvLanes, ..., so neighbouring lanes read neighbouring
+// entries, and the lanes of the row combine their partial sums with shuffles
 __global__ __launch_bounds__(256) void spmv_kernel(const int* __restrict__ rowptr, const int* __restrict__ colind,
                                                    const double* __restrict__ vals, const double* __restrict__ x,
                                                    double* y, int n, int nrhs, double alpha, double beta) {
@@ -1877,7 +1877,7 @@ void launch_spmv(const int* rowptr, const int* colind, const double* vals, const
 }
 void launch_mdot(const double* X, int64_t xstride, int nv, const double* w, int n, int nrhs, double* partial,
                  double* out, int accumulate, hipStream_t st) {
-  const int nchunk = 64;
+  const int nchunk = mdot_chunks(nrhs);
   MFH_LAUNCH(mdot_partial_kernel, dim3(nchunk, nrhs, (nv + kMdotGroup - 1) / kMdotGroup), dim3(256), 0, st, X,
              xstride, nv, w, n, nrhs, partial);
   MFH_LAUNCH(mdot_reduce_kernel, dim3((nv * nrhs + 3) / 4), dim3(256), 0, st, partial, nchunk, nv, nrhs, out,

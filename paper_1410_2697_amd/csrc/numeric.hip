@@ -2023,7 +2023,7 @@ void NumericBase::gmres(int nrhs, const double* b, double* x, double tol, const 
   g_r.ensure((size_t)vs * 8, &ms, st);
   const int nsmall = 3 * (m + 2) * nrhs + 4 * nrhs;
   g_small.ensure((size_t)nsmall * 8, &ms, st);
-  g_partial.ensure((size_t)64 * (m + 2) * nrhs * 8, &ms, st);
+  g_partial.ensure((size_t)mdot_chunks(nrhs) * (m + 2) * nrhs * 8, &ms, st);
   double* V = g_V.as<double>();
   double* Z = g_Z.as<double>();
   double* w = g_w.as<double>();
