@@ -1502,18 +1502,50 @@ __global__ void assemble_kernel(T* __restrict__ ws, const int64_t* __restrict__ 
     if (lvl[k] == h) ws[dest[k]] = (T)vals[k];
 }
 
+constexpr int kVecBatch = 8;   // entries per thread per round in the apply's vector gathers
+
 template <typename T>
 __global__ __launch_bounds__(256) void vec_asm_kernel(const VecAsmDesc<T>* __restrict__ descs, int nrhs) {
   const VecAsmDesc<T>& d = descs[blockIdx.x];   // read in place (a copy indexed by child would sit in scratch)
   const int tid = threadIdx.x, nt = blockDim.x, k = blockIdx.y;
   T* t = d.t + (size_t)k * d.ldt;
   const T* x = d.xs + (size_t)k * d.ldx;
-  for (int i = tid; i < d.nhat; i += nt) t[i] = i < d.npiv ? x[i] : (T)0;
+  // kVecBatch entries per thread at a time: their loads are all issued
+  // before the first store, so one workgroup keeps many reads in flight
+  const int nhat = d.nhat, npiv = d.npiv;
+  for (int i0 = tid; i0 < nhat; i0 += nt * kVecBatch) {
+    T v[kVecBatch];
+#pragma unroll
+    for (int u = 0; u < kVecBatch; ++u) {
+      const int i = i0 + u * nt;
+      v[u] = i < npiv ? x[i] : (T)0;
+    }
+#pragma unroll
+    for (int u = 0; u < kVecBatch; ++u)
+      if (i0 + u * nt < nhat) t[i0 + u * nt] = v[u];
+  }
   __syncthreads();
   for (int c = 0; c < d.nchild; ++c) {   // children in order: no two threads touch one entry
     const T* ct = d.ct[c] + d.cnp[c] + (size_t)k * d.cld[c];
     const int* rel = d.crel[c];
-    for (int a = tid; a < d.cnf[c]; a += nt) t[rel[a]] += ct[a];
+    const int cnf = d.cnf[c];
+    for (int a0 = tid; a0 < cnf; a0 += nt * kVecBatch) {
+      int r[kVecBatch];
+      T v[kVecBatch];
+#pragma unroll
+      for (int u = 0; u < kVecBatch; ++u) {
+        const int a = a0 + u * nt;
+        r[u] = a < cnf ? rel[a] : -1;
+        v[u] = a < cnf ? ct[a] : (T)0;
+      }
+      // a child's relative map is one-to-one, so these entries are distinct
+#pragma unroll
+      for (int u = 0; u < kVecBatch; ++u)
+        if (r[u] >= 0) v[u] += t[r[u]];
+#pragma unroll
+      for (int u = 0; u < kVecBatch; ++u)
+        if (r[u] >= 0) t[r[u]] = v[u];
+    }
     __syncthreads();
   }
 }
@@ -1522,10 +1554,20 @@ template <typename T>
 __global__ __launch_bounds__(256) void vec_gather_kernel(const VecGatherDesc<T>* __restrict__ descs, const T* xn,
                                                          int N, int nrhs) {
   const VecGatherDesc<T> d = descs[blockIdx.x];
-  const int k = blockIdx.y;
+  const int k = blockIdx.y, nt = blockDim.x;
   T* t = d.t + (size_t)k * d.ldt;
   const T* x = xn + (size_t)k * N;
-  for (int a = threadIdx.x; a < d.nf; a += blockDim.x) t[a] = x[d.upd[a]];
+  for (int a0 = threadIdx.x; a0 < d.nf; a0 += nt * kVecBatch) {
+    int r[kVecBatch];
+    T v[kVecBatch];
+#pragma unroll
+    for (int u = 0; u < kVecBatch; ++u) r[u] = a0 + u * nt < d.nf ? d.upd[a0 + u * nt] : -1;
+#pragma unroll
+    for (int u = 0; u < kVecBatch; ++u) v[u] = r[u] >= 0 ? x[r[u]] : (T)0;
+#pragma unroll
+    for (int u = 0; u < kVecBatch; ++u)
+      if (r[u] >= 0) t[a0 + u * nt] = v[u];
+  }
 }
 
 template <typename T>
