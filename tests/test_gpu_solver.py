@@ -43,6 +43,31 @@ def test_dense_fp64_apply_matches_oracle(gpu_lib, name, maker, leaf):
     assert info["dense_fronts"] == ref_sym.nfronts and info["status_bits"] == 0
 
 
+@pytest.mark.parametrize("name,maker,leaf", SMALL)
+@pytest.mark.parametrize("nrhs", [1, 3, 17])
+def test_spmv_matches_csr_product(gpu_lib, name, maker, leaf, nrhs):
+    """mf_spmv against the float64 CSR product.  Rows hold 9 (2D), about 15
+    (Kuhn) and 27 (3D) entries, so the lanes that share a row take one to
+    four rounds, and 17 right-hand sides cross the kernel's 16-column block.
+    y starts as NaN: y = A x must not read it."""
+    import torch
+    mfh = gpu_lib
+    p = maker()
+    print(f"case {name} nrhs={nrhs}", flush=True)
+    sym = mfh.Symbolic.from_csr(p.A, p.coords, leaf)
+    f = mfh.Factor(sym, p.A.vals, 0.0, method="dense", precision="fp64")
+    x = rhs(p.A.n, nrhs, "normal", 3 + nrhs)
+    y = _to_dev(np.full_like(x, np.nan))
+    f.spmv(_to_dev(x), y)
+    torch.cuda.synchronize()
+    A = p.A.to_scipy()
+    ref = A @ x
+    bound = 64 * np.finfo(np.float64).eps * (abs(A) @ np.abs(x))
+    yg = _to_host(y)
+    assert yg.shape == ref.shape
+    assert np.all(np.abs(yg - ref) <= bound)
+
+
 @pytest.mark.parametrize("name,maker,leaf", SMALL[:2])
 def test_dense_gmres_one_iteration(gpu_lib, name, maker, leaf):
     mfh = gpu_lib
