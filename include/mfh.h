@@ -41,7 +41,7 @@ typedef enum {
   MF_OK = 0,
   MF_EINVAL = 1,      /* malformed argument (CSR, sizes, options)            */
   MF_ENOMEM = 2,      /* device or host allocation failed                    */
-  MF_EBUDGET = 3,     /* estimated bytes exceed the caller's budget          */
+  MF_EBUDGET = 3,     /* a request's estimated bytes exceed the whole device  */
   MF_ENOTSPD = 4,     /* a Cholesky pivot was not positive                   */
   MF_ENOCONV = 5,     /* GMRES hit maxit before reaching tol                 */
   MF_ECAPACITY = 6,   /* a block rank exceeded the configured rank capacity  */
@@ -66,12 +66,13 @@ typedef struct {
                         /* the pivot kernel takes (128 float64, 192 float32)                */
   int32_t adaptive;     /* 1: continue complete pivoting over the whole block until the
                            pivot-ratio rule holds there (max-norm error < eps*|u_11|)     */
-  int32_t rank_cap;     /* capacity per block rank; exceeding it -> MF_ECAPACITY            */
+  int32_t rank_cap;     /* capacity per block rank (a block's capacity is the larger of this
+                           and its phase-1 bound min(|I|, |J|)); exceeding it -> MF_ECAPACITY */
   int32_t uv_bf16;      /* HODLR + FP32 only: round the compressed bases U, V (and the F_fp
                            basis W) to bfloat16 right after compression and keep them in
                            bfloat16; the factorisation and the apply both use the rounded
                            values, so the preconditioner is that of the rounded matrix     */
-  int32_t apply_graph;  /* k >= 1 (default 4): the k-th preconditioner apply (Sec. 4.1.3)
+  int32_t apply_graph;  /* k >= 1 (default 4): the k-th preconditioner apply (Sec. 4.1.2)
                            with a given right-hand-side count records its kernel sequence
                            as a HIP graph, and it and every later apply with that count
                            replay it; earlier applies launch each kernel (recording costs
@@ -239,7 +240,10 @@ mf_status mf_estimate_bytes(const mf_symbolic_t* sym, const mf_opts* opts, int32
  *    request's estimated peak fits the memory budget next to the requests
  *    running and the factors kept resident; their factorisations and solves
  *    overlap on the device.  A request larger than the whole budget runs
- *    when nothing else holds memory.  Resident factors that no request is
+ *    when nothing else holds memory; one whose estimate exceeds the device's
+ *    total memory is refused at submit with MF_EBUDGET.  A factor serves one
+ *    solve at a time: a resolve waits while another solve of the same factor
+ *    runs, and requests queued behind it may start first.  Resident factors that no request is
  *    using are dropped, least recently used first, when memory is needed.
  *  - With keep_factors, a request's factor stays on the device after its
  *    solve; mf_server_resolve queues another solve with it (repeated

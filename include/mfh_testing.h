@@ -51,9 +51,17 @@ mf_status mfh_test_skeleton(int32_t precision, void* F, int32_t ld, int32_t r0, 
 /* In-place inverse of the n x n float64 matrix A (column-major, leading
  * dimension lda >= n, 1 <= n <= 1024) by Gauss-Jordan elimination with
  * partial pivoting: the kernel the capacitance inverse M = (I - A B)^{-1}
- * of the SMW factorization (Sec. 3) runs on.  *status_out receives the
+ * of the SMW factorization (Sec. 2.1) runs on.  *status_out receives the
  * kernel's status word (4: a zero pivot column). */
 mf_status mfh_test_inverse(int32_t n, double* A, int32_t lda, int32_t* status_out);
+
+/* Barrier wait of the multi-workgroup phase 2 (Sec. 2.2 compression spread
+ * over workgroups) for every later factorisation in the process, in ticks
+ * of the device's constant-rate clock: 0 restores the default (two
+ * seconds); a negative value makes every workgroup give up at its first
+ * barrier, so mf_factor must end with MF_EHIP while every kernel exits
+ * normally.  Host only; takes effect at the next phase-2 launch. */
+mf_status mfh_test_phase2_wait(int64_t ticks);
 
 #ifdef __cplusplus
 }

@@ -54,13 +54,11 @@ class DenseFactor:
     chol: list       # cho_factor of F_pp per front
     Fpp_L: list      # lower Cholesky factor of F_pp
     Ffp: list        # F_fp per front (n_f x n_p)
-    flops: float
 
 
 def factor(sym: Symbolic, vals: np.ndarray) -> DenseFactor:
     upd = [None] * sym.nfronts
     chol, Ls, Ffp = [], [], []
-    flops = 0.0
     for p, f in enumerate(sym.fronts):
         F = front_bar(sym, vals, p)
         for c in f.children:
@@ -77,8 +75,7 @@ def factor(sym: Symbolic, vals: np.ndarray) -> DenseFactor:
         if f.nf > 0:
             # U_p = F_ff - F_fp F_pp^{-1} F_pf   (Eq. update)
             upd[p] = F[npv:, npv:] - Ffp_p @ sla.cho_solve(cf, Fpf)
-        flops += npv ** 3 / 3 + npv ** 2 * f.nf + npv * f.nf ** 2
-    return DenseFactor(sym, chol, Ls, Ffp, flops)
+    return DenseFactor(sym, chol, Ls, Ffp)
 
 
 def global_L(fac: DenseFactor) -> np.ndarray:
@@ -124,12 +121,3 @@ def solve(fac: DenseFactor, b: np.ndarray) -> np.ndarray:
     x = np.empty_like(xn)
     x[sym.perm] = xn
     return x[:, 0] if squeeze else x
-
-
-def factor_bytes(fac: DenseFactor, itemsize: int = 8) -> int:
-    """Persistent bytes of the dense factor: lower triangle of each L_pp plus
-    the full n_f x n_p coupling block."""
-    tot = 0
-    for f in fac.sym.fronts:
-        tot += f.npiv * (f.npiv + 1) // 2 + f.nf * f.npiv
-    return tot * itemsize

@@ -316,10 +316,3 @@ def blocks(h: HNode) -> list:
         q = nxt
     return out
 
-
-def nbytes(h: HNode, itemsize: int = 8) -> int:
-    """Bytes of the HODLR data (leaves' lower triangles, U, V)."""
-    if h.is_leaf:
-        return h.size * (h.size + 1) // 2 * itemsize
-    return (nbytes(h.left, itemsize) + nbytes(h.right, itemsize)
-            + (h.lr.U.size + h.lr.V.size) * itemsize)

@@ -183,17 +183,3 @@ def solve(fac: HodlrFactor, b: np.ndarray) -> np.ndarray:
     x = np.empty_like(xn)
     x[sym.perm] = xn
     return x[:, 0] if squeeze else x
-
-
-def factor_bytes(fac: HodlrFactor, itemsize: int = 8) -> int:
-    """Persistent bytes (dense fronts: lower L_pp + F_fp; HODLR fronts:
-    leaves, U, V of F_pp, plus W and X)."""
-    tot = 0
-    for f, ff in zip(fac.sym.fronts, fac.fronts):
-        if ff.dense:
-            tot += (f.npiv * (f.npiv + 1) // 2 + f.nf * f.npiv) * itemsize
-        else:
-            tot += hodlr.nbytes(ff.Hpp, itemsize)
-            if ff.W is not None:
-                tot += (ff.W.size + ff.X.size) * itemsize
-    return tot

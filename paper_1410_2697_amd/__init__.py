@@ -118,6 +118,7 @@ SIGNATURES = [
     ("mfh_test_skeleton", _I32, [_I32, _P, _I32, _I32, _I32, _I32, _I32, _P, _I32, _P, _I32, _D, _I32, _I32,
                                  _P, _P, ctypes.POINTER(_I32)]),
     ("mfh_test_inverse", _I32, [_I32, _P, _I32, ctypes.POINTER(_I32)]),
+    ("mfh_test_phase2_wait", _I32, [_I64]),
 ]
 
 

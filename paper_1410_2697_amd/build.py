@@ -1,6 +1,8 @@
 """Build the HIP library ``libmfh.so`` in-tree for gfx950.
 
 Usage: python -m paper_1410_2697_amd.build   (or build() from Python).
+Each source is compiled to an object under ``_build/`` (in parallel), then
+linked; every call compiles every source again.
 """
 from __future__ import annotations
 
@@ -8,11 +10,18 @@ import os
 import shutil
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmfh.so")
-SOURCES = ["hostpool.cpp", "symbolic.cpp", "prof.cpp", "server.cpp", "api.cpp", "kernels.hip", "numeric.hip", "testing.hip"]
+OBJ = os.path.join(os.path.dirname(HERE), "_build")
+SOURCES = ["hostpool.cpp", "symbolic.cpp", "prof.cpp", "server.cpp", "api.cpp", "kernels.hip", "numeric.hip",
+           "testing.hip", "apply_dag.hip"]
+FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+         # packed FP32 instructions are kept out of the generated code
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-Wno-unused-command-line-argument"]
 
 
 def hipcc() -> str:
@@ -22,18 +31,33 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False) -> str:
-    cmd = [hipcc(), "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
-           # packed FP32 instructions are kept out of the generated code
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-Wno-unused-command-line-argument",
-           "-o", LIB + ".tmp"] + [os.path.join(CSRC, s) for s in SOURCES]
-    if verbose:
-        print(" ".join(cmd), flush=True)
+def _run(cmd):
     r = subprocess.run(cmd, capture_output=True, text=True)
     err = "\n".join(l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l)
-    if r.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + err)
+    return r.returncode, err
+
+
+def build(verbose: bool = False) -> str:
+    os.makedirs(OBJ, exist_ok=True)
+    cc = hipcc()
+    srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+    jobs = []
+    for s in srcs:
+        o = os.path.join(OBJ, s + ".o")
+        jobs.append((o, [cc] + FLAGS + ["-c", "-o", o, os.path.join(CSRC, s)]))
+    if verbose:
+        for _, c in jobs:
+            print(" ".join(c), flush=True)
+    workers = max(1, min(len(jobs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))
+    with ThreadPoolExecutor(workers) as ex:
+        res = list(ex.map(lambda j: _run(j[1]), jobs))
+    errs = [e for (rc, e) in res if rc != 0]
+    if errs:
+        raise RuntimeError("hipcc failed:\n" + "\n".join(errs))
+    link = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp"] + [o for o, _ in jobs]
+    rc, err = _run(link)
+    if rc != 0:
+        raise RuntimeError("link failed:\n" + err)
     os.replace(LIB + ".tmp", LIB)
     return LIB
 

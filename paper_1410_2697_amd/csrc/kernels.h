@@ -253,8 +253,10 @@ void launch_phase2(const Phase2Desc<T>* d, int ndesc, int maxrc, double eps, int
 // LDS or (slice_lds false) updated in place in the front; phase2_coop_capacity:
 // workgroups that can be resident at once with that LDS (a launch must not
 // exceed it).  A launch waits on the host for the device's previous one
-// unless both are on one stream; a barrier wait longer than spin_limit polls
-// sets status bit 8 and ends the loop.  Returns the launch or wait error.
+// unless both are on one stream; a barrier wait longer than wait_ticks
+// ticks of the device's constant-rate clock sets status bit 8 and ends the
+// loop (wait_ticks < 0: every workgroup gives up at its first barrier, a
+// test hook).  Returns the launch or wait error.
 constexpr int kPhase2CoopLds = 78 * 1024;   // two workgroups fill a CU's 160 KB of LDS
 // threads of a multi-workgroup phase-2 workgroup (more waves make the
 // per-step barriers slower than they make the update faster), and the
@@ -269,7 +271,7 @@ template <typename T>
 int phase2_coop_capacity(size_t lds, bool slice_lds);
 template <typename T>
 hipError_t launch_phase2_coop(const Phase2CoopDesc<T>* d, int ndesc, int wgs, size_t lds, bool slice_lds,
-                              double eps, int* status, int spin_limit, hipStream_t st);
+                              double eps, int* status, long long wait_ticks, hipStream_t st);
 template <typename T>
 void launch_extadd(const ExtAddDesc<T>* d, int ndesc, int tiles, hipStream_t st);
 template <typename S, typename D>

@@ -1005,7 +1005,7 @@ __device__ __forceinline__ u64 block_max_key(u64 v, u64* sh, int slot) {
 // the phase-1 residual); otherwise they are updated in place in the front.
 template <typename T, bool SLICE_LDS>
 __global__ __launch_bounds__(kCoopThreads) void phase2_coop_kernel(const Phase2CoopDesc<T>* __restrict__ descs, int ndesc,
-                                                          double eps, int* status, int spin_limit) {
+                                                          double eps, int* status, long long wait_ticks) {
   extern __shared__ __align__(16) char smem[];
   __shared__ u64 s_red[32];
   __shared__ u64 s_pk[2][1];
@@ -1129,7 +1129,9 @@ __global__ __launch_bounds__(kCoopThreads) void phase2_coop_kernel(const Phase2C
     if (wave == 0) {
       u64 km = 0;
       int ok_all = 0;
-      for (int spins = 0;; ++spins) {
+      const long long t_wait = wall_clock64();
+      for (;;) {
+        if (wait_ticks < 0) break;   // host-forced give-up (test hook): no poll at all
         u64 kq = 0;
         bool ok = true;
         for (int q = lane; q < nwg; q += 64) {
@@ -1146,7 +1148,7 @@ __global__ __launch_bounds__(kCoopThreads) void phase2_coop_kernel(const Phase2C
           ok_all = 1;
           break;
         }
-        if (spins >= spin_limit) break;
+        if ((long long)wall_clock64() - t_wait > wait_ticks) break;
         __builtin_amdgcn_s_sleep(1);
       }
       if (lane == 0) {
@@ -1810,7 +1812,7 @@ int phase2_coop_capacity(size_t lds, bool slice_lds) {
 // into status bit 8.
 template <typename T>
 hipError_t launch_phase2_coop(const Phase2CoopDesc<T>* d, int ndesc, int wgs, size_t lds, bool slice_lds,
-                              double eps, int* status, int spin_limit, hipStream_t st) {
+                              double eps, int* status, long long wait_ticks, hipStream_t st) {
   if (ndesc <= 0 || wgs <= 0) return hipSuccess;
   struct Last {
     hipEvent_t ev = nullptr;
@@ -1834,10 +1836,10 @@ hipError_t launch_phase2_coop(const Phase2CoopDesc<T>* d, int ndesc, int wgs, si
   }
   if (slice_lds)
     MFH_LAUNCH((phase2_coop_kernel<T, true>), dim3(wgs), dim3(kCoopThreads), lds, st, d, ndesc, eps, status,
-               spin_limit);
+               wait_ticks);
   else
     MFH_LAUNCH((phase2_coop_kernel<T, false>), dim3(wgs), dim3(kCoopThreads), lds, st, d, ndesc, eps, status,
-               spin_limit);
+               wait_ticks);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   e = hipEventRecord(L.ev, st);
@@ -1953,7 +1955,7 @@ void launch_axpby(const double* a, const double* b, double* c, double alpha, dou
   template int phase2_coop_wcols<T>(int);                                                         \
   template size_t phase2_coop_lds<T>(int, int, bool);                                             \
   template int phase2_coop_capacity<T>(size_t, bool);                                             \
-  template hipError_t launch_phase2_coop<T>(const Phase2CoopDesc<T>*, int, int, size_t, bool, double, int*, int, \
+  template hipError_t launch_phase2_coop<T>(const Phase2CoopDesc<T>*, int, int, size_t, bool, double, int*, long long, \
                                             hipStream_t);                                         \
   template void launch_extadd<T>(const ExtAddDesc<T>*, int, int, hipStream_t);                   \
   template void launch_cap<T>(const CapDesc<T>*, int, hipStream_t);                              \

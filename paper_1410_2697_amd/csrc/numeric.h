@@ -102,6 +102,12 @@ class NumericBase {
 };
 
 std::unique_ptr<NumericBase> make_numeric(const Symbolic& s, const double* vals, const mf_opts& o);
+// Barrier wait of the multi-workgroup phase 2, in ticks of the device's
+// constant-rate clock: 0 restores the default (two seconds), < 0 makes every
+// workgroup give up at its first barrier (test hook for the error path).
+void set_phase2_wait_ticks(long long ticks);
+// message of the MF_EHIP a phase-2 barrier give-up ends the factorisation with
+constexpr const char* kPhase2WaitMsg = "phase-2 workgroups did not meet at their barrier";
 int64_t workspace_plan(const Symbolic& s, std::vector<int64_t>& reg_off, std::vector<int64_t>& reg_elems,
                        std::vector<int64_t>& front_elem_off);
 void estimate_bytes(const Symbolic& s, const mf_opts& o, int nrhs, int restart, int64_t& persistent,

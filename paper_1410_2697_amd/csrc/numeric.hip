@@ -359,7 +359,7 @@ GemmDesc<T> gd(const T* A, int lda, int opA, const T* B, int ldb, int opB, T* C,
 // chip, its deep products (k >= 2 * kSplitChunk) get several workgroups
 // along k, writing partial sums into `part` (capacity `cap` elements; each
 // problem takes its own region), followed by a fixed-order reduction.
-constexpr int kSpinLimit = 1 << 20;   // barrier polls before a phase-2 workgroup gives up
+constexpr double kPhase2WaitSeconds = 2.0;   // a phase-2 barrier wait this long gives up (status bit 8)
 constexpr int kSplitTarget = 512;   // workgroups wanted per launch (two per CU)
 constexpr int kSplitTargetNarrow = 1024;   // the same for right-hand-side tiles (four resident per CU)
 constexpr int kSplitChunk = 128;    // smallest k range of one split
@@ -605,6 +605,21 @@ namespace {
 
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+std::atomic<long long> g_phase2_wait_override{0};
+
+// Ticks of the device's constant-rate clock a phase-2 workgroup waits at a
+// barrier before it gives up; a test override (set_phase2_wait_ticks) wins.
+long long phase2_wait_ticks(int dev) {
+  const long long o = g_phase2_wait_override.load();
+  if (o != 0) return o;
+  int khz = 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0) {
+    (void)hipGetLastError();
+    khz = 100000;   // 100 MHz, the constant clock of CDNA parts
+  }
+  return (long long)(kPhase2WaitSeconds * 1000.0 * khz);
 }
 
 constexpr int kNB = 64;          // dense panel width
@@ -1338,6 +1353,7 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
   launch_skelfac<T>(reinterpret_cast<const SkelFacDesc<T>*>(base + osf), (int)sf.size(), wgs, rmax1, st);
   prof_end(id_s, st);
   int id_2 = -1;
+  bool fork_joined = false;
   std::vector<int> coop_ids;
   if (adaptive) {
     resid.launch(base, st);
@@ -1345,19 +1361,27 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
     launch_phase2<T>(reinterpret_cast<const Phase2Desc<T>*>(base + op2), (int)p2.size(), maxrc, eps, dstat, st);
     prof_end(id_2, st);
     if (!p2c.empty()) {
+      // The multi-workgroup launches need all their workgroups resident at
+      // once: the side stream's whole-block kernels (1024-thread, register
+      // heavy) finish before them rather than compete for compute units.
+      if (fork) {
+        HIPCHK(hipStreamWaitEvent(st, ev_join, 0));
+        fork_joined = true;
+      }
+      const long long wait_ticks = phase2_wait_ticks(device);
       launch_fill<unsigned long long>(slots, nslots, 1ull << 63, st);   // no slot carries step 0's tag
       const auto* dc = reinterpret_cast<const Phase2CoopDesc<T>*>(base + op2c);
       for (const CoopGroup& g : cgroups) {
         const int id = prof_begin(pk<T>(g.slds ? PK_PHASE2CL_F64 : PK_PHASE2CG_F64), st, 0.0, 0.0);
         coop_ids.push_back(id);
         const hipError_t e = launch_phase2_coop<T>(dc + g.first, g.n, g.wgs, g.slds ? coop_lds : coop_lds_g, g.slds,
-                                                   eps, dstat, kSpinLimit, st);
+                                                   eps, dstat, wait_ticks, st);
         prof_end(id, st);
         if (e != hipSuccess) throw Err{MF_EHIP, std::string("phase-2 launch: ") + hipGetErrorString(e)};
       }
     }
   }
-  if (fork) HIPCHK(hipStreamWaitEvent(st, ev_join, 0));
+  if (fork && !fork_joined) HIPCHK(hipStreamWaitEvent(st, ev_join, 0));
   // ---- the one synchronisation of the level: ranks to the host (pinned)
   int* hb = dp.host<int>(2 * (size_t)nb + 1);
   int* hb_dev = nullptr;
@@ -1369,7 +1393,7 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
   const int status = hb[2 * nb];
   retired.clear();
   if (status & 2) throw Err{MF_ECAPACITY, "a block rank exceeded rank_cap"};
-  if (status & 8) throw Err{MF_EHIP, "phase-2 workgroups did not meet at their barrier"};
+  if (status & 8) throw Err{MF_EHIP, kPhase2WaitMsg};
   for (int i = 0; i < nb; ++i) ranks[br[i].gb] = hr[i];
   // work of the rank-dependent launches: each pivot step of the whole-block
   // kernels updates the block once; the phase-1 kernel on B_hat reads it once
@@ -2208,6 +2232,8 @@ void estimate_bytes(const Symbolic& s, const mf_opts& o, int nrhs, int restart, 
   persistent = (int64_t)(fac + csr + apply + gm + kSplitPlanBytes);
   peak = (int64_t)(ws + fac + csr + scratch + fixed + 16.0 * s.nnz);
 }
+
+void set_phase2_wait_ticks(long long ticks) { g_phase2_wait_override.store(ticks); }
 
 std::unique_ptr<NumericBase> make_numeric(const Symbolic& s, const double* vals, const mf_opts& o) {
   if (o.precision == MF_FP64) return std::make_unique<Numeric<double>>(s, vals, o);

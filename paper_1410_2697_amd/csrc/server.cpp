@@ -23,15 +23,14 @@ Server::Server(const mf_server_opts& o) : o_(o) {
     (void)hipGetLastError();
     throw Err{MF_ESTATE, "no HIP device is visible"};
   }
-  budget_ = o_.mem_budget;
-  if (budget_ <= 0) {
-    size_t fr = 0, tot = 0;
-    if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
-      (void)hipGetLastError();
-      throw Err{MF_EHIP, "hipMemGetInfo failed"};
-    }
-    budget_ = (int64_t)(0.8 * (double)fr);
+  size_t fr = 0, tot = 0;
+  if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+    (void)hipGetLastError();
+    throw Err{MF_EHIP, "hipMemGetInfo failed"};
   }
+  device_total_ = (int64_t)tot;
+  budget_ = o_.mem_budget;
+  if (budget_ <= 0) budget_ = (int64_t)(0.8 * (double)fr);
   for (int i = 0; i < o_.slots; ++i) workers_.emplace_back([this]() { worker(); });
 }
 
@@ -75,6 +74,10 @@ int64_t Server::submit(int n, const int32_t* rowptr, const int32_t* colind, cons
   estimate_bytes(*r->sym, o_.factor, nrhs, o_.gmres.restart, pers, peak);
   r->est = std::max(peak, pers);
   r->info.est_bytes = r->est;
+  // a request larger than the whole device can never run, not even alone
+  if (r->est > device_total_)
+    throw Err{MF_EBUDGET, "estimated device bytes " + std::to_string(r->est) + " exceed the device's " +
+                              std::to_string(device_total_)};
   std::lock_guard<std::mutex> g(mu_);
   if (stop_) throw Err{MF_ESTATE, "server stopped"};
   r->id = next_id_++;
@@ -110,6 +113,23 @@ int64_t Server::resolve(int64_t factor_ticket, int nrhs, const double* b) {
   return id;
 }
 
+// A factor handle serves one solve at a time (its GMRES workspaces and apply
+// plans are shared by every solve on it), so a resolve waits while another
+// resolve of the same factor runs; requests behind it may go first.  Memory
+// admission keeps arrival order: the first request that does not fit stops
+// the scan.
+std::deque<int64_t>::iterator Server::pick_locked(std::vector<std::unique_ptr<Factor>>& evicted) {
+  for (auto it = queue_.begin(); it != queue_.end(); ++it) {
+    Req& r = *reqs_[*it];
+    if (r.resolve) {
+      auto f = factors_.find(r.factor_id);
+      if (f != factors_.end() && f->second->busy) continue;
+    }
+    return admit_locked(r, evicted) ? it : queue_.end();
+  }
+  return queue_.end();
+}
+
 bool Server::admit_locked(Req& r, std::vector<std::unique_ptr<Factor>>& evicted) {
   for (;;) {
     if (in_use_ + r.est <= budget_) return true;
@@ -139,14 +159,17 @@ void Server::worker() {
     Req* r = nullptr;
     {
       std::unique_lock<std::mutex> lk(mu_);
+      auto pick = queue_.end();
       for (;;) {
         if (stop_) break;
-        if (!queue_.empty() && admit_locked(*reqs_[queue_.front()], evicted)) break;
+        pick = pick_locked(evicted);
+        if (pick != queue_.end()) break;
         cv_work_.wait(lk);
       }
       if (stop_) break;
-      r = reqs_[queue_.front()].get();
-      queue_.pop_front();
+      r = reqs_[*pick].get();
+      queue_.erase(pick);
+      if (r->resolve) factors_.at(r->factor_id)->busy = true;
       r->state = 1;
       r->info.t_queue = now() - r->t_submit;
       in_use_ += r->est;
@@ -183,7 +206,17 @@ void Server::run(Req& r, hipStream_t st, DevBuf& db, DevBuf& dx) {
       own = std::make_unique<Factor>();
       own->n = r.n;
       own->sym = std::move(r.sym);
-      own->num = make_numeric(*own->sym, r.vals.data(), fo);
+      // A multi-workgroup phase-2 launch needs its workgroups resident at
+      // once; should another slot's kernels hold the compute units past the
+      // barrier wait, the factorisation gives up cleanly and runs once more.
+      for (int attempt = 0;; ++attempt) {
+        try {
+          own->num = make_numeric(*own->sym, r.vals.data(), fo);
+          break;
+        } catch (const Err& e) {
+          if (attempt > 0 || e.code != MF_EHIP || e.msg.rfind(kPhase2WaitMsg, 0) != 0) throw;
+        }
+      }
       r.info.t_factor = now() - t0;
       r.info.peak_bytes = own->num->ms.peak;
       r.vals.clear();
@@ -234,6 +267,7 @@ void Server::run(Req& r, hipStream_t st, DevBuf& db, DevBuf& dx) {
       if (it != factors_.end()) {
         Factor& rf = *it->second;
         --rf.users;
+        rf.busy = false;
         rf.last_use = ++clock_;
         in_use_ += f ? (f->num->ms.current - rf.bytes) : 0;   // a new nrhs may add workspaces
         rf.bytes = f ? f->num->ms.current : rf.bytes;

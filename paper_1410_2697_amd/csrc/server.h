@@ -37,6 +37,7 @@ class Server {
     int n = 0;
     int64_t bytes = 0;      // accounted while resident
     int users = 0;          // queued or running resolves
+    bool busy = false;      // a resolve is running on it (one solve per factor at a time)
     uint64_t last_use = 0;
     bool released = false;
   };
@@ -57,7 +58,10 @@ class Server {
 
   void worker();
   void run(Req& r, hipStream_t st, DevBuf& db, DevBuf& dx);
-  // admission of the queue head (lock held); evicted factors are moved out
+  // next admissible queued request (lock held), or queue_.end(): requests
+  // are taken in arrival order, except that a resolve whose factor is busy
+  // with another solve is passed over; evicted factors are moved out
+  std::deque<int64_t>::iterator pick_locked(std::vector<std::unique_ptr<Factor>>& evicted);
   bool admit_locked(Req& r, std::vector<std::unique_ptr<Factor>>& evicted);
   int64_t solve_bytes(int n, int nrhs) const;
 
@@ -68,7 +72,7 @@ class Server {
   std::deque<int64_t> queue_;
   std::map<int64_t, std::unique_ptr<Req>> reqs_;
   std::map<int64_t, std::unique_ptr<Factor>> factors_;
-  int64_t next_id_ = 1, in_use_ = 0, budget_ = 0;
+  int64_t next_id_ = 1, in_use_ = 0, budget_ = 0, device_total_ = 0;
   uint64_t clock_ = 0;
   int running_ = 0;
   bool stop_ = false;

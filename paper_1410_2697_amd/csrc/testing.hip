@@ -4,6 +4,7 @@
 
 #include "../../include/mfh_testing.h"
 #include "kernels.h"
+#include "numeric.h"
 
 namespace {
 thread_local std::string t_err;
@@ -148,7 +149,7 @@ mf_status skel_t(void* F, int ld, int r0, int nr, int c0, int nc, const int* I, 
           qd.wg0 = 0; qd.nwg = nwg; qd.wcols = (nc + nwg - 1) / nwg;
           hipMemcpy(dd + 3072, &qd, sizeof(qd), hipMemcpyHostToDevice);
           s = hip_ok(mfh::launch_phase2_coop<T>(reinterpret_cast<mfh::Phase2CoopDesc<T>*>(dd + 3072), 1, nwg, lds,
-                                                slds, eps, status, 1 << 20, nullptr));
+                                                slds, eps, status, 200000000LL, nullptr));
           if (s == MF_OK) s = hip_ok(hipDeviceSynchronize());
           hipFree(cs);
         }
@@ -241,3 +242,8 @@ mf_status mfh_test_skeleton(int32_t precision, void* F, int32_t ld, int32_t r0, 
 }
 
 }  // extern "C"
+
+extern "C" mf_status mfh_test_phase2_wait(int64_t ticks) {
+  mfh::set_phase2_wait_ticks((long long)ticks);
+  return MF_OK;
+}

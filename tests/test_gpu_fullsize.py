@@ -2,9 +2,9 @@
 times: 2D Q1 Poisson 64^2 (FP64, eps 1e-6), 3D Kuhn-P1 48^3 cells (FP32,
 eps 1e-4, 8 RHS) and 3D GRF diffusion 64^3 (FP32 with BF16 bases, eps 1e-3).
 Checks: the true FP64 residual of every right-hand side, and the solution
-against the float64 oracle where the oracle finishes in seconds to a minute
-(sampled columns), else against the GPU dense-front FP64 solve within the
-forward-error bound kappa * residual."""
+against the float64 oracle's conventional multifrontal solve to 1e-8
+(computed in the test where the oracle finishes in seconds to a minute,
+stored in tests/golden by an oracle-only script for 64^3)."""
 import numpy as np
 import pytest
 
@@ -56,8 +56,8 @@ def test_poisson2d_64_fp64_ranks_and_solution_match_oracle(gpu_lib):
 
 def test_kuhn_p1_48_fp32_reaches_oracle_solution(gpu_lib):
     """Kuhn-P1 tetrahedra on 48^3 cells (N = 110592), eps 1e-4, FP32 factors,
-    8 RHS: true residual <= 1e-10 for every column; two sampled columns
-    against the oracle's exact multifrontal solve to 1e-8."""
+    8 RHS: true residual <= 1e-10 for every column; every column within
+    1e-8 (relative, per column) of the oracle's exact multifrontal solve."""
     mfh = gpu_lib
     w = make_workload("p1kuhn_48")
     p = w.problem
@@ -71,21 +71,30 @@ def test_kuhn_p1_48_fp32_reaches_oracle_solution(gpu_lib):
     xg = _to_host(x)
     assert _relres(p.A.to_scipy(), w.b, xg).max() <= w.tol
     ref_sym = symbolic.analyze(p.A, p.coords, w.leaf)
-    cols = [0, 7]
-    xr = dense_mf.solve(dense_mf.factor(ref_sym, p.A.vals), w.b[:, cols])
-    assert np.linalg.norm(xg[:, cols] - xr) <= 1e-8 * np.linalg.norm(xr)
+    xr = dense_mf.solve(dense_mf.factor(ref_sym, p.A.vals), w.b)
+    err = np.linalg.norm(xg - xr, axis=0) / np.linalg.norm(xr, axis=0)
+    print("relative error per column", err.max(), flush=True)
+    assert err.max() <= 1e-8
 
 
-def test_grf_diffusion_64_bf16_against_dense(gpu_lib):
-    """k = exp(GRF) on 64^3 nodes (N = 262144), eps 1e-3, BF16 bases: true
-    residual <= 1e-10; the HODLR solution agrees with the GPU dense-front
-    FP64 solve (itself checked against the oracle on smaller grids) within
-    kappa * (residual of both), kappa bounded by the coefficient contrast
-    times the constant-coefficient bound 4 (n+1)^2 / pi^2."""
+def test_grf_diffusion_64_bf16_matches_stored_oracle_solution(gpu_lib):
+    """k = exp(GRF) on 64^3 nodes (N = 262144), eps 1e-3, FP32 factors with
+    BF16 bases, GMRES tolerance 1e-10: true residual <= 1e-10, and the whole
+    solution vector within 1e-8 (relative 2-norm) of the oracle's float64
+    conventional multifrontal solve.  The oracle solve takes minutes of CPU
+    time at this size, so it is stored in tests/golden by
+    tests/golden/make_golden.py (oracle only), with a fingerprint of the
+    inputs that must match the workload generated here."""
+    import os
     mfh = gpu_lib
     w = make_workload("diffusion3d_grf_64")
     p = w.problem
     print(f"case {w.name} n={p.A.n}", flush=True)
+    here = os.path.dirname(os.path.abspath(__file__))
+    g = np.load(os.path.join(here, "golden", "diffusion3d_grf_64_x.npz"))
+    fp = np.array([p.A.n, p.A.nnz, np.sum(p.A.vals), np.sum(np.abs(p.A.vals)), np.sum(w.b), np.sum(np.abs(w.b))])
+    assert np.allclose(g["fingerprint"], fp, rtol=1e-12, atol=0), "stored oracle solution is for other inputs"
+    xr = g["x"]
     sym = mfh.Symbolic.from_csr(p.A, p.coords, w.leaf)
     fh = mfh.Factor(sym, p.A.vals, w.eps, method="hodlr", precision="fp32", n_c=512, uv_bf16=1)
     xh = _to_dev(np.zeros_like(w.b))
@@ -93,20 +102,7 @@ def test_grf_diffusion_64_bf16_against_dense(gpu_lib):
     print("iters", [i["iters"] for i in ih], fh.info(), flush=True)
     assert all(i["converged"] for i in ih)
     xhg = _to_host(xh)
-    A = p.A.to_scipy()
-    rh = _relres(A, w.b, xhg).max()
-    assert rh <= w.tol
-    fd = mfh.Factor(sym, p.A.vals, 0.0, method="dense", precision="fp64")
-    xd = _to_dev(np.zeros_like(w.b))
-    fd.gmres(_to_dev(w.b), xd, tol=w.tol)
-    xdg = _to_host(xd)
-    rd = _relres(A, w.b, xdg).max()
-    assert rd <= 1e-13
-    # coefficient contrast of this field, times the Q1 Laplacian condition bound
-    from mfinputs import grf_squared_exponential
-    n = w.params["grid"]
-    g = grf_squared_exponential((n + 1,) * 3, corr_len=0.1, variance=1.0, seed=0)
-    kappa = float(np.exp(g.max() - g.min())) * 4.0 * (n + 1) ** 2 / np.pi ** 2
-    diff = np.linalg.norm(xhg - xdg) / np.linalg.norm(xdg)
-    print(f"kappa bound {kappa:.3e} diff {diff:.3e}", flush=True)
-    assert diff <= kappa * (rh + rd)
+    assert _relres(p.A.to_scipy(), w.b, xhg).max() <= w.tol
+    err = np.linalg.norm(xhg - xr) / np.linalg.norm(xr)
+    print(f"relative error against the oracle {err:.3e}", flush=True)
+    assert err <= 1e-8

@@ -1,11 +1,13 @@
 """Serving through the C ABI: requests factored and solved concurrently on
-one device give the same results as alone, memory admission holds, resident
-factors serve repeated right-hand sides, and the byte estimate bounds the
+one device give the same results as alone and match the oracle's solve to
+1e-8, memory admission holds, resident factors serve repeated right-hand
+sides (one solve per factor at a time), and the byte estimate bounds the
 measured factorisation peak."""
 import numpy as np
 import pytest
 
 from mfinputs import serving_request, q1_grid, rhs
+from oracle import symbolic, dense_mf
 
 pytestmark = pytest.mark.gpu
 
@@ -18,11 +20,24 @@ def _requests():
     return [serving_request(side, seed, nrhs=2) for side, seed in MIX]
 
 
-def _check_solution(w, x):
+def _oracle_solve(w, b=None, leaf=32):
+    """The oracle's float64 conventional multifrontal solve of the request."""
+    p = w.problem
+    ref = symbolic.analyze(p.A, p.coords, leaf)
+    return dense_mf.solve(dense_mf.factor(ref, p.A.vals), w.b if b is None else b)
+
+
+def _check_solution(w, x, b=None):
+    """True residual <= tol and every column within 1e-8 (relative) of the
+    oracle's solve."""
+    b = w.b if b is None else b
     A = w.problem.A.to_scipy()
-    r = w.b - A @ x
-    rel = np.linalg.norm(r, axis=0) / np.linalg.norm(w.b, axis=0)
+    r = b - A @ x
+    rel = np.linalg.norm(r, axis=0) / np.linalg.norm(b, axis=0)
     assert rel.max() <= 1e-10 * 1.01, rel
+    xr = _oracle_solve(w, b)
+    err = np.linalg.norm(x - xr, axis=0) / np.linalg.norm(xr, axis=0)
+    assert err.max() <= 1e-8, err
 
 
 def test_same_alone_and_in_the_mix(gpu_lib):
@@ -79,13 +94,47 @@ def test_resident_factor_serves_new_right_hand_sides(gpu_lib):
     t2 = sv.resolve(t, b2)
     x2, info2 = sv.wait(t2)
     assert info2["t_factor"] == 0.0 and info2["status"] == 0
-    A = w.problem.A.to_scipy()
-    rel = np.linalg.norm(b2 - A @ x2, axis=0) / np.linalg.norm(b2, axis=0)
-    assert rel.max() <= 1e-10 * 1.01
+    _check_solution(w, x2, b2)
     sv.release(t)
     assert sv.memory()["in_use"] == 0
     with pytest.raises(mfh.MfError):
         sv.resolve(t, b2)
+    sv.close()
+
+
+def test_concurrent_resolves_of_one_factor(gpu_lib):
+    """Three resolves of one resident factor submitted back to back on a
+    server with three slots (one solve per factor at a time: the server
+    runs them one after another while other requests may pass them), each
+    x equal to the same right-hand side solved alone, and to the oracle."""
+    mfh = gpu_lib
+    w = serving_request(12, 21, nrhs=1)
+    other = serving_request(10, 22, nrhs=2)
+    bs = [rhs(w.problem.A.n, k + 1, "normal", 100 + k) for k in range(3)]
+    print("case resolves: 3 resolves of one factor, 3 slots", flush=True)
+    sv = mfh.Server(slots=1, keep_factors=True, **KW)
+    t = sv.submit(w.problem.A, w.problem.coords, w.b)
+    sv.wait(t)
+    alone = []
+    for b in bs:
+        x, info = sv.wait(sv.resolve(t, b))
+        assert info["status"] == 0
+        alone.append(x)
+    sv.close()
+    sv = mfh.Server(slots=3, keep_factors=True, **KW)
+    t = sv.submit(w.problem.A, w.problem.coords, w.b)
+    sv.wait(t)
+    tickets = [sv.resolve(t, b) for b in bs]
+    to = sv.submit(other.problem.A, other.problem.coords, other.b)
+    for b, tk, xa in zip(bs, tickets, alone):
+        x, info = sv.wait(tk)
+        assert info["status"] == 0
+        _check_solution(w, x, b)
+        assert np.abs(x - xa).max() <= 1e-12 * np.abs(xa).max()
+    xo, info = sv.wait(to)
+    assert info["status"] == 0
+    _check_solution(other, xo)
+    sv.release(t)
     sv.close()
 
 

@@ -148,7 +148,9 @@ def test_hodlr_fp32_gmres_reaches_oracle_solution(gpu_lib, name, maker, leaf, ep
 
 
 def test_full_size_poisson3d_32_sixteen_rhs(gpu_lib):
-    """3D Q1 Poisson 32^3, FP32 HODLR factor, eps 1e-4, leaf 128, 16 RHS."""
+    """3D Q1 Poisson 32^3, FP32 HODLR factor, eps 1e-4, leaf 128, 16 RHS:
+    true residual <= 1e-10 and every column within 1e-8 (relative, per
+    column) of the oracle's exact multifrontal solve."""
     mfh = gpu_lib
     w = make_workload("poisson3d_q1_32")
     p = w.problem
@@ -162,11 +164,12 @@ def test_full_size_poisson3d_32_sixteen_rhs(gpu_lib):
     S = p.A.to_scipy()
     res = np.linalg.norm(w.b - S @ xg, axis=0) / np.linalg.norm(w.b, axis=0)
     assert res.max() <= 1e-10
-    # sampled columns against the oracle's exact multifrontal solve
+    # every column against the oracle's exact multifrontal solve
     ref_sym = symbolic.analyze(p.A, p.coords, w.leaf)
-    cols = [0, 15]
-    xr = dense_mf.solve(dense_mf.factor(ref_sym, p.A.vals), w.b[:, cols])
-    assert np.linalg.norm(xg[:, cols] - xr) <= 1e-8 * np.linalg.norm(xr)
+    xr = dense_mf.solve(dense_mf.factor(ref_sym, p.A.vals), w.b)
+    err = np.linalg.norm(xg - xr, axis=0) / np.linalg.norm(xr, axis=0)
+    print("relative error per column", err.max(), flush=True)
+    assert err.max() <= 1e-8
 
 
 def test_not_spd_reports_error(gpu_lib):

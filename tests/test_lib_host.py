@@ -48,6 +48,11 @@ CASES = [
 @pytest.mark.parametrize("name,maker,leaf", CASES)
 def test_symbolic_bit_exact(name, maker, leaf):
     p = maker()
+    _assert_symbolic_equal(p, leaf)
+
+
+def _assert_symbolic_equal(p, leaf):
+    """Every exported array of mf_analyze equals the oracle's analysis."""
     ref = symbolic.analyze(p.A, p.coords, leaf)
     s = mfh.Symbolic.from_csr(p.A, p.coords, leaf)
     assert np.array_equal(s.export(mfh.MF_EXP_PERM), ref.perm)
@@ -89,6 +94,20 @@ def test_bdlr_sets_bit_exact(name, maker, leaf, depth, cap):
             assert np.array_equal(J[Jp[g]:Jp[g + 1]], rj)
             g += 1
     assert g == Ip.shape[0] - 1
+
+
+@pytest.mark.parametrize("name", ["q1_3d_64_leaf128", "p1kuhn_48_leaf128"])
+def test_symbolic_bit_exact_full_size(name):
+    """The analyses of the largest workloads, in full: the 64^3 Q1 grid (the
+    pattern and coordinates of the 64^3 diffusion workload; its coefficient
+    field changes only values) and the jittered Kuhn-P1 mesh of 48^3 cells
+    with the generator's own seed."""
+    if name.startswith("q1"):
+        p = q1_grid(64, 3)
+    else:
+        from mfinputs import make_workload
+        p = make_workload("p1kuhn_48").problem
+    _assert_symbolic_equal(p, 128)
 
 
 def test_symbolic_full_size_3d_32():
