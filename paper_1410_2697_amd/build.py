@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmfh.so")
 OBJ = os.path.join(os.path.dirname(HERE), "_build")
 SOURCES = ["hostpool.cpp", "symbolic.cpp", "prof.cpp", "server.cpp", "api.cpp", "kernels.hip", "numeric.hip",
-           "testing.hip", "apply_dag.hip"]
+           "testing.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # packed FP32 instructions are kept out of the generated code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
