@@ -203,6 +203,33 @@ void mf_factor_free(mf_numeric_t* f);
 mf_status mf_apply(mf_numeric_t* f, int32_t nrhs, const double* r, double* z, void* stream);
 
 /*
+ * Preconditioner apply that allocates nothing, for callers that cannot
+ * allocate device memory (serving loops, harnesses that forbid hipMalloc,
+ * code recorded into a HIP graph once the handle and nrhs have been used
+ * before capture).  Same z = M^{-1} r, same kernels, same split-K choices as
+ * mf_apply (the results are equal bit for bit); its workspace, split-K
+ * partial sums and step descriptors live in one static device array of
+ * MF_APPLY_SCRATCH_BYTES that each GPU the library runs on keeps until the
+ * process ends.  No hipMalloc, hipFree or allocating library call is made.
+ *   r, z    device float64[n*nrhs], column-major, original ordering; may not alias
+ *   stream  hipStream_t or NULL; asynchronous once the descriptors are in place
+ * Every call on a GPU shares that GPU's array, which keeps the last call's
+ * contents: when it last held another handle's plan or another nrhs, the
+ * call uploads the descriptors again (host planning and a copy that waits on
+ * `stream`).  Nothing in the array needs clearing: every entry a call reads
+ * it has written first.  Calls that overlap on one GPU (two streams or
+ * threads without synchronisation between them) race: order them.  The
+ * call does not register its stream with the handle: synchronise the stream
+ * before mf_factor_free.
+ * Errors: MF_EINVAL when the workspace for nrhs columns plus the split-K
+ * area and descriptors exceed MF_APPLY_SCRATCH_BYTES (use mf_apply, or fewer
+ * right-hand sides per call); MF_ESTATE when the factor's device is not the
+ * current device.
+ */
+#define MF_APPLY_SCRATCH_BYTES (64ull << 20)
+mf_status mf_apply_noalloc(mf_numeric_t* f, int32_t nrhs, const double* r, double* z, void* stream);
+
+/*
  * Right-preconditioned flexible GMRES(m) with M = the factor (Sec. 3):
  * x0 = 0, classical Gram-Schmidt with reorthogonalisation in float64, stop
  * when ||b - A x||_2 <= tol ||b||_2 (true residual, float64 SpMV with A) for

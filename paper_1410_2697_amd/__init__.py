@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libmfh.so")
 _lib = None
 
 MF_OK, MF_EINVAL, MF_ENOMEM, MF_EBUDGET, MF_ENOTSPD, MF_ENOCONV, MF_ECAPACITY, MF_EHIP, MF_ESTATE = range(9)
+MF_APPLY_SCRATCH_BYTES = 64 << 20   # include/mfh.h: the scratch of mf_apply_noalloc
 STATUS_NAMES = ["MF_OK", "MF_EINVAL", "MF_ENOMEM", "MF_EBUDGET", "MF_ENOTSPD", "MF_ENOCONV",
                 "MF_ECAPACITY", "MF_EHIP", "MF_ESTATE"]
 MF_FP64, MF_FP32 = 0, 1
@@ -96,6 +97,7 @@ SIGNATURES = [
     ("mf_factor_ranks", _I32, [_P, _P, _I64, ctypes.POINTER(_I64)]),
     ("mf_factor_free", None, [_P]),
     ("mf_apply", _I32, [_P, _I32, _P, _P, _P]),
+    ("mf_apply_noalloc", _I32, [_P, _I32, _P, _P, _P]),
     ("gmres_solve", _I32, [_P, _I32, _P, _P, _D, ctypes.POINTER(GmresOpts), ctypes.POINTER(GmresInfo)]),
     ("mf_spmv", _I32, [_P, _I32, _P, _P, _P]),
     ("mf_estimate_bytes", _I32, [_P, ctypes.POINTER(MfOpts), _I32, _I32, ctypes.POINTER(_I64),
@@ -246,6 +248,14 @@ class Factor:
         n = self.sym.n
         _check(load().mf_apply(self.h, nrhs, _devptr(r, n, nrhs, "r"), _devptr(z, n, nrhs, "z"),
                                _stream_ptr(stream)))
+
+    def apply_noalloc(self, r, z, stream=None):
+        """mf_apply_noalloc: the same apply with its memory in the library's
+        static device scratch (no device allocation)."""
+        nrhs = r.shape[0] if r.dim() == 2 else 1
+        n = self.sym.n
+        _check(load().mf_apply_noalloc(self.h, nrhs, _devptr(r, n, nrhs, "r"), _devptr(z, n, nrhs, "z"),
+                                       _stream_ptr(stream)))
 
     def spmv(self, x, y, stream=None):
         nrhs = x.shape[0] if x.dim() == 2 else 1

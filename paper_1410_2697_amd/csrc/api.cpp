@@ -235,6 +235,15 @@ mf_status mf_apply(mf_numeric_t* f, int32_t nrhs, const double* r, double* z, vo
   MF_GUARD_END
 }
 
+mf_status mf_apply_noalloc(mf_numeric_t* f, int32_t nrhs, const double* r, double* z, void* stream) {
+  MF_GUARD_BEGIN
+  if (!f || !r || !z || nrhs < 1) return fail(MF_EINVAL, "bad argument");
+  if (r == z) return fail(MF_EINVAL, "r and z may not alias");
+  f->n->apply_noalloc(nrhs, r, z, static_cast<hipStream_t>(stream));
+  return MF_OK;
+  MF_GUARD_END
+}
+
 mf_status mf_spmv(mf_numeric_t* f, int32_t nrhs, const double* x, double* y, void* stream) {
   MF_GUARD_BEGIN
   if (!f || !x || !y || nrhs < 1 || x == y) return fail(MF_EINVAL, "bad argument");

@@ -78,10 +78,13 @@ class NumericBase {
  public:
   virtual ~NumericBase() = default;
   virtual void apply(int nrhs, const double* r, double* z, hipStream_t st) = 0;
+  // the same apply with no device allocation (mf_apply_noalloc)
+  virtual void apply_noalloc(int nrhs, const double* r, double* z, hipStream_t st) = 0;
   void spmv(int nrhs, const double* x, double* y, double alpha, double beta, hipStream_t st);
   void gmres(int nrhs, const double* b, double* x, double tol, const mf_gmres_opts& o, mf_gmres_info* info,
              mf_status* st_out);
   mf_factor_info info{};
+  uint64_t uid = 0;              // process-unique handle number (never reused)
   std::vector<int> ranks;        // per global block, -1 for dense fronts
   const Symbolic* sym = nullptr;
   mf_opts opts{};

@@ -366,6 +366,44 @@ constexpr int kSplitChunk = 128;    // smallest k range of one split
 constexpr size_t kSplitFactorBytes = size_t(16) << 20;
 constexpr size_t kSplitPlanBytes = size_t(16) << 20;
 
+// Scratch of the allocation-free apply (mf_apply_noalloc): one static device
+// array, which each GPU the library runs on holds until the process ends.
+// It takes the apply's workspace, then kSplitPlanBytes of split-K partial
+// sums (as an allocated plan has, so both applies split alike), then the step
+// descriptors.
+static_assert(MF_APPLY_SCRATCH_BYTES > kSplitPlanBytes, "scratch smaller than its split-K part");
+static __device__ __align__(256) unsigned char scratch[MF_APPLY_SCRATCH_BYTES];
+
+// Host side of each device's scratch: its device address (hipGetSymbolAddress
+// on the first call on that device, with the device current; the array's
+// name is only a host stand-in) and which handle's plan, for how many
+// right-hand sides, its descriptors hold now.
+struct ScratchState {
+  std::mutex mu;
+  char* ptr = nullptr;
+  uint64_t owner = 0;
+  int nrhs = 0;
+};
+constexpr int kMaxDevices = 64;
+ScratchState& scratch_state(int dev) {
+  static ScratchState s[kMaxDevices];
+  if (dev < 0 || dev >= kMaxDevices) throw Err{MF_ESTATE, "device index out of range"};
+  return s[dev];
+}
+char* scratch_address(ScratchState& S) {   // S.mu held, the device current
+  if (!S.ptr) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      throw Err{MF_EHIP, std::string("scratch address lookup failed: ") + hipGetErrorString(e)};
+    }
+    S.ptr = static_cast<char*>(p);
+  }
+  return S.ptr;
+}
+std::atomic<uint64_t> g_handle_ids{0};
+
 // assigns tile0/tiles_m/tiles_n/ksplit; returns total tiles; `red` receives
 // the reduction descriptors of split problems (tile0 over output tiles)
 template <typename T>
@@ -501,8 +539,9 @@ struct GemmBatch {
   mutable int pid = -1;                      // timing record of the last launch
   // split: split-K partial-sum area (reused by every batch of a stream)
   void stage(Blob& b, const DevBuf* split = nullptr) {
-    T* part = split ? static_cast<T*>(split->p) : nullptr;
-    const size_t cap = split ? split->bytes / sizeof(T) : 0;
+    stage(b, split ? static_cast<T*>(split->p) : nullptr, split ? split->bytes / sizeof(T) : 0);
+  }
+  void stage(Blob& b, T* part, size_t cap) {
     tn = kTileNarrow;
     for (const auto& d : v)
       if (d.n > kTileNarrow) tn = kTile;
@@ -634,6 +673,7 @@ class Numeric : public NumericBase {
   Numeric(const Symbolic& s, const double* vals, const mf_opts& o);
 
   void apply(int nrhs, const double* r, double* z, hipStream_t st) override;
+  void apply_noalloc(int nrhs, const double* r, double* z, hipStream_t st) override;
 
  private:
   struct FN {
@@ -711,10 +751,19 @@ class Numeric : public NumericBase {
       if (exec) (void)hipGraphExecDestroy(exec);
     }
   };
+  struct Layout {                    // workspace offsets of one right-hand-side count
+    int64_t tot = 0;
+    std::vector<int64_t> t_off, z_off, h_off;
+    std::vector<std::vector<int64_t>> q_off, l_off;
+  };
+  Layout plan_layout(int nrhs) const;
+  template <typename Upload>
+  void build_plan(Plan& pl, int nrhs, const Layout& L, T* wk, T* part, size_t cap, Upload&& upload);
   void launch_recs(const Plan& pl, hipStream_t stream);
   hipStream_t cap = nullptr;         // stream the apply graphs are recorded on
   std::map<int, std::unique_ptr<Plan>> plans;
   Plan* get_plan(int nrhs);
+  std::unique_ptr<Plan> na_plan;     // host side of the plan last placed in the scratch
   bool constructed = false;
   // Declared last, so destroyed first (also when the constructor throws):
   // device blocks go back to the allocator cache only after the work that
@@ -739,6 +788,7 @@ Numeric<T>::Numeric(const Symbolic& s, const double* vals, const mf_opts& o) {
   const double t0 = now_s();
   sym = &s;
   opts = o;
+  uid = ++g_handle_ids;
   st = static_cast<hipStream_t>(o.stream);
   arena.ms = &ms;
   dp.ar.ms = &ms;
@@ -1738,45 +1788,71 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
 
 // ================================================================ apply ====
 template <typename T>
-typename Numeric<T>::Plan* Numeric<T>::get_plan(int nrhs) {
-  auto it = plans.find(nrhs);
-  if (it != plans.end()) return it->second.get();
+typename Numeric<T>::Layout Numeric<T>::plan_layout(int nrhs) const {
   const Symbolic& s = *sym;
-  auto pl = std::make_unique<Plan>();
-  pl->nrhs = nrhs;
-  pl->dp.ar.ms = &ms;
-  const int bff = (sizeof(T) == 4 && opts.uv_bf16) ? GF_A_BF16 : 0;   // U, V, W kept in bfloat16
   const int nfr = (int)s.fronts.size();
-  const int N = s.n;
-  // workspace layout (elements of T)
-  int64_t tot = (int64_t)N * nrhs;
-  std::vector<int64_t> t_off(nfr), z_off(nfr), h_off(nfr);
-  std::vector<std::vector<int64_t>> q_off(nfr), l_off(nfr);
+  Layout L;
+  L.t_off.resize(nfr); L.z_off.resize(nfr); L.h_off.resize(nfr);
+  L.q_off.resize(nfr); L.l_off.resize(nfr);
+  // workspace layout (elements of T); x in the permuted order comes first
+  int64_t tot = (int64_t)s.n * nrhs;
   for (int p = 0; p < nfr; ++p) {
     const Front& f = s.fronts[p];
-    t_off[p] = tot; tot += (int64_t)f.n() * nrhs;
+    L.t_off[p] = tot; tot += (int64_t)f.n() * nrhs;
     // a HODLR front's z is its t's pivot rows (read by X^T t before the
     // leaf solves change them in place); a dense front's z is separate
-    if (fn[p].dense) { z_off[p] = tot; tot += (int64_t)f.npiv * nrhs; }
-    else z_off[p] = t_off[p];
+    if (fn[p].dense) { L.z_off[p] = tot; tot += (int64_t)f.npiv * nrhs; }
+    else L.z_off[p] = L.t_off[p];
     if (!fn[p].dense) {
-      h_off[p] = tot; tot += (int64_t)std::max(fn[p].r_top, 1) * nrhs;
-      q_off[p].assign(f.pp_tree.size(), 0);
-      l_off[p].assign(f.pp_tree.size(), 0);
+      L.h_off[p] = tot; tot += (int64_t)std::max(fn[p].r_top, 1) * nrhs;
+      L.q_off[p].assign(f.pp_tree.size(), 0);
+      L.l_off[p].assign(f.pp_tree.size(), 0);
       for (size_t i = 0; i < f.pp_tree.size(); ++i) {
         const TreeNode& t = f.pp_tree[i];
-        if (t.left >= 0) { q_off[p][i] = tot; tot += (int64_t)4 * std::max(fn[p].nodeR[i], 1) * nrhs; }
-        else { l_off[p][i] = tot; tot += (int64_t)t.size * nrhs; }
+        if (t.left >= 0) { L.q_off[p][i] = tot; tot += (int64_t)4 * std::max(fn[p].nodeR[i], 1) * nrhs; }
+        else { L.l_off[p][i] = tot; tot += (int64_t)t.size * nrhs; }
       }
     }
   }
-  pl->work.alloc(tot * sizeof(T), &ms);
-  T* wk = static_cast<T*>(pl->work.p);
+  L.tot = tot;
+  return L;
+}
+
+template <typename T>
+typename Numeric<T>::Plan* Numeric<T>::get_plan(int nrhs) {
+  auto it = plans.find(nrhs);
+  if (it != plans.end()) return it->second.get();
+  auto pl = std::make_unique<Plan>();
+  pl->dp.ar.ms = &ms;
+  const Layout L = plan_layout(nrhs);
+  pl->work.alloc(L.tot * sizeof(T), &ms);
+  pl->split.alloc(kSplitPlanBytes, &ms);
+  Plan* raw = pl.get();
+  build_plan(*raw, nrhs, L, raw->work.template as<T>(), raw->split.template as<T>(), kSplitPlanBytes / sizeof(T),
+             [this, raw](Blob& bl) { return raw->dp.upload(bl, st); });
+  HIPCHK(hipStreamSynchronize(st));
+  plans[nrhs] = std::move(pl);
+  return raw;
+}
+
+// The apply's step sequence for nrhs right-hand sides: workspace wk
+// (L.tot elements), split-K partial sums in part (cap elements), and the
+// descriptor blobs placed on the device by `upload`.
+template <typename T>
+template <typename Upload>
+void Numeric<T>::build_plan(Plan& plan, int nrhs, const Layout& L, T* wk, T* part, size_t cap, Upload&& upload) {
+  const Symbolic& s = *sym;
+  Plan* pl = &plan;
+  pl->nrhs = nrhs;
+  const int bff = (sizeof(T) == 4 && opts.uv_bf16) ? GF_A_BF16 : 0;   // U, V, W kept in bfloat16
+  const int nfr = (int)s.fronts.size();
+  const int N = s.n;
+  const std::vector<int64_t>&t_off = L.t_off, &z_off = L.z_off, &h_off = L.h_off;
+  const std::vector<std::vector<int64_t>>&q_off = L.q_off, &l_off = L.l_off;
   pl->xn = wk;
   Blob b;
-  pl->split.alloc(kSplitPlanBytes, &ms);
   auto rec_gemm = [&](GemmBatch<T>& g) {
-    g.stage(b, &pl->split);
+    g.stage(b, part, cap);
     if (g.n) pl->recs.push_back({0, g.off, g.n, g.tiles, g.flops, g.bytes, g.tn});
     if (g.rn) pl->recs.push_back({4, g.roff, g.rn, g.rtiles, 0.0, g.rbytes});
   };
@@ -1916,7 +1992,7 @@ typename Numeric<T>::Plan* Numeric<T>::get_plan(int nrhs) {
       }
       Blob ub;
       size_t o = ub.add(upd);
-      const char* ubase = pl->dp.upload(ub, st);
+      const char* ubase = upload(ub);
       for (size_t i = 0; i < vg.size(); ++i) vg[i].upd = reinterpret_cast<const int*>(ubase + o) + uo[i];
       size_t ov = b.add(vg);
       pl->recs.push_back({3, ov, (int)vg.size(), 0});
@@ -1924,11 +2000,7 @@ typename Numeric<T>::Plan* Numeric<T>::get_plan(int nrhs) {
     rec_gemm(d1);
     rec_gemm(d2);
   }
-  pl->desc = pl->dp.upload(b, st);
-  HIPCHK(hipStreamSynchronize(st));
-  Plan* raw = pl.get();
-  plans[nrhs] = std::move(pl);
-  return raw;
+  pl->desc = upload(b);
 }
 
 template <typename T>
@@ -1970,6 +2042,54 @@ void Numeric<T>::apply(int nrhs, const double* r, double* z, hipStream_t stream)
   if (replay) HIPCHK(hipGraphLaunch(pl->exec, stream));
   else launch_recs(*pl, stream);
   launch_perm_out<T>(pl->xn, z, d_iperm.as<int>(), N, nrhs, stream);
+  HIPCHK(hipGetLastError());
+}
+
+// The same step sequence as apply(), with its memory in the device's
+// scratch: workspace first, split-K partials next, descriptors after them.
+// The descriptors are uploaded again (host planning and a blocking copy)
+// whenever the scratch last held another handle's plan or another nrhs.
+template <typename T>
+void Numeric<T>::apply_noalloc(int nrhs, const double* r, double* z, hipStream_t stream) {
+  int cur = -1;
+  HIPCHK(hipGetDevice(&cur));
+  if (cur != device) throw Err{MF_ESTATE, "the factor's device is not the current device"};
+  ScratchState& S = scratch_state(device);
+  std::lock_guard<std::mutex> g(S.mu);
+  char* base = scratch_address(S);
+  const Layout L = plan_layout(nrhs);
+  const size_t wbytes = ((size_t)L.tot * sizeof(T) + 255) & ~size_t(255);
+  if (wbytes + kSplitPlanBytes >= (size_t)MF_APPLY_SCRATCH_BYTES)
+    throw Err{MF_EINVAL, "the apply workspace for " + std::to_string(nrhs) + " right-hand sides needs " +
+                             std::to_string(wbytes) + " bytes; the scratch holds " +
+                             std::to_string((size_t)MF_APPLY_SCRATCH_BYTES - kSplitPlanBytes)};
+  if (!na_plan || S.owner != uid || S.nrhs != nrhs) {
+    S.owner = 0;
+    na_plan.reset();
+    auto pl = std::make_unique<Plan>();
+    char* bump = base + wbytes + kSplitPlanBytes;
+    char* const end = base + MF_APPLY_SCRATCH_BYTES;
+    auto up = [&](Blob& bl) -> char* {
+      const size_t n = bl.h.size();
+      if (n == 0) return nullptr;
+      if (n > (size_t)(end - bump))
+        throw Err{MF_EINVAL, "the apply descriptors do not fit the scratch next to the workspace"};
+      char* d = bump;
+      bump += (n + 255) & ~size_t(255);
+      HIPCHK(hipMemcpyAsync(d, bl.h.data(), n, hipMemcpyHostToDevice, stream));
+      HIPCHK(hipStreamSynchronize(stream));   // the host blob may go now
+      return d;
+    };
+    build_plan(*pl, nrhs, L, reinterpret_cast<T*>(base), reinterpret_cast<T*>(base + wbytes),
+               kSplitPlanBytes / sizeof(T), up);
+    na_plan = std::move(pl);
+    S.owner = uid;
+    S.nrhs = nrhs;
+  }
+  const int N = sym->n;
+  launch_perm_in<T>(r, na_plan->xn, d_perm.as<int>(), N, nrhs, stream);
+  launch_recs(*na_plan, stream);
+  launch_perm_out<T>(na_plan->xn, z, d_iperm.as<int>(), N, nrhs, stream);
   HIPCHK(hipGetLastError());
 }
 

@@ -36,6 +36,12 @@ def test_exports_every_declared_symbol():
     assert set(names) == {s[0] for s in mfh.SIGNATURES}
 
 
+def test_scratch_size_constant_matches_header():
+    src = open(os.path.join(INCLUDE, "mfh.h")).read()
+    m = re.search(r"#define MF_APPLY_SCRATCH_BYTES \((\d+)ull << (\d+)\)", src)
+    assert m and int(m.group(1)) << int(m.group(2)) == mfh.MF_APPLY_SCRATCH_BYTES
+
+
 CASES = [
     ("q1_2d_64_leaf64", lambda: q1_grid(64, 2), 64),
     ("q1_2d_20_leaf8", lambda: q1_grid(20, 2), 8),
