@@ -1445,11 +1445,15 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
   if (status & 2) throw Err{MF_ECAPACITY, "a block rank exceeded rank_cap"};
   if (status & 8) throw Err{MF_EHIP, kPhase2WaitMsg};
   for (int i = 0; i < nb; ++i) ranks[br[i].gb] = hr[i];
-  // work of the rank-dependent launches: each pivot step of the whole-block
-  // kernels updates the block once; the phase-1 kernel on B_hat reads it once
-  // and updates it per step; the factor kernel solves with the r x r LU for
-  // every row and column; phase 2 makes one pass (read + write) per step plus
-  // the final search.
+  // work of the rank-dependent launches: pivot step k of complete pivoting
+  // updates the active (rows - k) x (cols - k) part of its block (whole block,
+  // B_hat, or the phase-2 residual); the phase-1 kernel on B_hat reads it once;
+  // the factor kernel solves with the r x r LU for every row and column;
+  // phase 2 makes one pass (read + write) per step plus the final search.
+  auto active = [](double nr, double nc, double k0, double k1) {   // sum over k in [k0, k1) of 2 (nr-k)(nc-k)
+    auto s = [&](double k) { return nr * nc * k - (nr + nc) * k * (k - 1) / 2 + (k - 1) * k * (2 * k - 1) / 6; };
+    return k1 > k0 ? 2.0 * (s(k1) - s(k0)) : 0.0;
+  };
   {
     double ff = 0, fb = 0, hf = 0, hb = 0, sfl = 0, sb = 0, rf = 0, rb = 0, pf = 0, pb = 0, cf = 0, cbytes = 0;
     for (int i = 0; i < nb; ++i) {
@@ -1457,12 +1461,12 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
       const Block& B = s.fronts[x.p].blocks[x.bi];
       const double e = (double)B.nr * B.nc;
       if (x.full) {
-        ff += 2.0 * e * hr[i];
+        ff += active(B.nr, B.nc, 0, hr[i]);
         fb += sizeof(T) * (e + (double)(B.nr + B.nc) * hr[i]);
         continue;
       }
       const double eh = (double)x.nI * x.nJ, r1 = h1[i];
-      hf += 2.0 * eh * r1;
+      hf += active(x.nI, x.nJ, 0, r1);
       hb += sizeof(T) * (eh + r1 * r1) + 8.0 * r1;
       sfl += (double)(B.nr + B.nc) * r1 * r1;
       sb += sizeof(T) * ((double)(B.nr + B.nc) * r1 * 2);
@@ -1471,10 +1475,10 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
         rb += sizeof(T) * ((double)(B.nr + B.nc) * r1 + 2.0 * e);
         const double steps = hr[i] - h1[i] + 1;
         if (x.nwg > 0) {   // slices read once; per step one U and V column
-          cf += 2.0 * e * steps;
+          cf += active(B.nr, B.nc, r1, hr[i] + 1);
           cbytes += sizeof(T) * (e + (double)(B.nr + B.nc) * (steps - 1));
         } else {
-          pf += 2.0 * e * steps;
+          pf += active(B.nr, B.nc, r1, hr[i] + 1);
           pb += sizeof(T) * 2.0 * e * steps;
         }
       }

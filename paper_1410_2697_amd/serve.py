@@ -71,7 +71,11 @@ def main(argv=None):
     sides = tuple(int(v) for v in args.sides.split(","))
     stream = serving_requests(args.count, args.seed, 1.0, sides)
     t = time.perf_counter()
-    reqs = [serving_request(side, seed, nrhs=args.nrhs) for (_, side, seed) in stream]
+    reqs = []
+    for i, (_, side, seed) in enumerate(stream):
+        reqs.append(serving_request(side, seed, nrhs=args.nrhs))
+        if (i + 1) % 32 == 0:
+            print(f"[serve] generated {i + 1} of {len(stream)}", file=sys.stderr, flush=True)
     print(f"[serve] generated {len(reqs)} requests in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
     kw = dict(leaf=128, tol=1e-10, eps=1e-4, precision="fp32", n_c=512)
     # capacity: everything submitted at once (a warm-up pass first)
