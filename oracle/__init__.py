@@ -19,6 +19,8 @@ hodlr      HODLR matrices (Sec. 2.1, Eq. HODLR2): BDLR / SVD compression
 hodlr_mf   HODLR-accelerated multifrontal factor and solve (Sec. 4.2,
            Eq. update_HODLR, Eq. HODLR_EA_Expand, Eq. update_HODLR_Parent).
 gmres      right-preconditioned flexible GMRES(m) (Sec. 3).
+pcg        preconditioned conjugate gradients, flexible beta (Sec. 3: the
+           preconditioner serves any Krylov solver, CG among them).
 
 Parity status: every function is pinned by the tests under tests/ (see the
 pin list in each module's docstring).  Iteration counts and the particular
