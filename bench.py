@@ -209,6 +209,33 @@ def run_config(mfh, torch, w, method, precision, n_c, steps, warmup, latency_cal
     }
 
 
+def resident_pcg(torch, f, w, steps, warmup, latency_calls, stream):
+    """Conjugate gradients (pcg_solve) with the same resident factor: rate
+    over `steps` solves and per-call latency, no timing session."""
+    b = torch.tensor(w.b.T.copy(), dtype=torch.float64, device="cuda")
+    x = torch.zeros_like(b)
+    for _ in range(warmup):
+        f.pcg(b, x, tol=w.tol, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        infos = f.pcg(b, x, tol=w.tol, stream=stream)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    lat = []
+    for _ in range(latency_calls):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        f.pcg(b, x, tol=w.tol, stream=stream)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - a)
+    lat.sort()
+    return {"solves_per_s": b.shape[0] * steps / el, "iters": [i["iters"] for i in infos],
+            "relres_max": max(i["relres"] for i in infos),
+            "latency_p50_ms": 1e3 * lat[len(lat) // 2], "latency_p99_ms": 1e3 * lat[min(len(lat) - 1, int(0.99 * len(lat)))],
+            "latency_calls": len(lat)}
+
+
 def blas_threads() -> int:
     try:
         from threadpoolctl import threadpool_info
@@ -304,6 +331,9 @@ def main():
     hod = run_config(mfh, torch, w, "hodlr", w.precision, args.n_c, args.steps, args.warmup, args.latency_calls,
                      stream, args.apply_graph)
     report("hodlr", hod)
+    hod_pcg = resident_pcg(torch, hod["f"], w, args.steps, args.warmup, args.latency_calls, stream)
+    _log(f"hodlr pcg: {hod_pcg['solves_per_s']:.1f} solves/s with the factor resident "
+         f"(p50 {hod_pcg['latency_p50_ms']:.2f} ms, iters {max(hod_pcg['iters'])})")
     den = None
     if not args.no_dense:
         den = run_config(mfh, torch, w, "dense", "fp64", 0, args.steps, args.warmup, args.latency_calls, stream,
@@ -337,6 +367,7 @@ def main():
                    "step": "gmres_solve of every right-hand side with the factor resident",
                    "arithmetic": "f32 compression, factors and apply; f64 GMRES, SpMV and capacitance inverses"},
         "hodlr_mf": summary(hod),
+        "hodlr_mf_pcg": hod_pcg,
         "dense_mf_fp64": summary(den) if den else None,
         "error_vs_oracle": err,
         "roofline": hod["roofline"],

@@ -242,6 +242,46 @@ mf_status mf_apply_noalloc(mf_numeric_t* f, int32_t nrhs, const double* r, doubl
 mf_status gmres_solve(mf_numeric_t* f, int32_t nrhs, const double* b, double* x,
                       double tol, const mf_gmres_opts* opts, mf_gmres_info* info);
 
+/*
+ * Preconditioned conjugate gradients with M = the factor (Sec. 3: the
+ * multifrontal preconditioner serves any Krylov solver, conjugate gradients
+ * among them).  A is SPD and the factor is a symmetric approximation of it;
+ * CG needs that approximation positive definite, which a loose eps may not
+ * give (gmres_solve has no such need).  x0 = 0; flexible beta
+ * <z_k+1, r_k+1 - r_k> / <z_k, r_k>, since the reduced-precision apply is
+ * not an exactly fixed linear operator; per right-hand side: stop when the
+ * recursive residual meets tol, then check the true residual
+ * ||b - A x||_2 <= tol ||b||_2 (float64 SpMV with A) and start again from x
+ * when it misses.  No Krylov basis is stored: five n x nrhs float64 vectors.
+ *   b, x   device float64[n*nrhs], column-major, original ordering
+ *   info   host array of nrhs entries (may be NULL): iterations, converged,
+ *          final true relative residual
+ * Synchronous.  Returns MF_ENOCONV (x = last iterate, info filled) when a
+ * right-hand side does not converge within maxit.
+ */
+typedef struct {
+  int32_t maxit;        /* iterations per right-hand side; default 4000 */
+  int32_t reserved;     /* must be 0 */
+  void* stream;         /* hipStream_t, borrowed; NULL = null stream */
+} mf_pcg_opts;
+mf_status mf_pcg_opts_default(mf_pcg_opts* o);
+mf_status pcg_solve(mf_numeric_t* f, int32_t nrhs, const double* b, double* x, double tol,
+                    const mf_pcg_opts* opts, mf_gmres_info* info);
+
+/*
+ * Direct solve with the factor (Conclusion: at high accuracy the solver is a
+ * standalone direct solver, not only a preconditioner): x = M^{-1} b, then
+ * `refine` steps of iterative refinement x += M^{-1} (b - A x), the residual
+ * in float64.  Build the factor with a small eps (and MF_FP64) for this use.
+ *   b, x    device float64[n*nrhs], column-major, original ordering; may not alias
+ *   refine  refinement steps, 0..64
+ *   info    host array of nrhs entries (may be NULL): iters = refine,
+ *           converged = 1, relres = final ||b - A x||_2 / ||b||_2
+ * Synchronous.
+ */
+mf_status mf_direct_solve(mf_numeric_t* f, int32_t nrhs, const double* b, double* x, int32_t refine,
+                          void* stream, mf_gmres_info* info);
+
 /* y = A x with the factor's device copy of A (float64 CSR), column-major
  * n x nrhs device arrays; asynchronous on stream. */
 mf_status mf_spmv(mf_numeric_t* f, int32_t nrhs, const double* x, double* y, void* stream);

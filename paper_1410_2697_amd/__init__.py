@@ -42,6 +42,10 @@ class GmresOpts(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int32), ("maxit", ctypes.c_int32), ("stream", ctypes.c_void_p)]
 
 
+class PcgOpts(ctypes.Structure):
+    _fields_ = [("maxit", ctypes.c_int32), ("reserved", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+
+
 class GmresInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32), ("relres", ctypes.c_double)]
 
@@ -99,6 +103,9 @@ SIGNATURES = [
     ("mf_apply", _I32, [_P, _I32, _P, _P, _P]),
     ("mf_apply_noalloc", _I32, [_P, _I32, _P, _P, _P]),
     ("gmres_solve", _I32, [_P, _I32, _P, _P, _D, ctypes.POINTER(GmresOpts), ctypes.POINTER(GmresInfo)]),
+    ("mf_direct_solve", _I32, [_P, _I32, _P, _P, _I32, _P, ctypes.POINTER(GmresInfo)]),
+    ("mf_pcg_opts_default", _I32, [ctypes.POINTER(PcgOpts)]),
+    ("pcg_solve", _I32, [_P, _I32, _P, _P, _D, ctypes.POINTER(PcgOpts), ctypes.POINTER(GmresInfo)]),
     ("mf_spmv", _I32, [_P, _I32, _P, _P, _P]),
     ("mf_estimate_bytes", _I32, [_P, ctypes.POINTER(MfOpts), _I32, _I32, ctypes.POINTER(_I64),
                                  ctypes.POINTER(_I64)]),
@@ -275,6 +282,33 @@ class Factor:
         infos = (GmresInfo * nrhs)()
         st = lib.gmres_solve(self.h, nrhs, _devptr(b, n, nrhs, "b"), _devptr(x, n, nrhs, "x"), float(tol),
                              ctypes.byref(o), infos)
+        out = [{"iters": i.iters, "converged": bool(i.converged), "relres": i.relres} for i in infos]
+        if st == MF_ENOCONV and not raise_on_noconv:
+            return out
+        _check(st)
+        return out
+
+    def direct_solve(self, b, x, refine: int = 1, stream=None):
+        """mf_direct_solve: x = M^{-1} b plus `refine` refinement steps."""
+        nrhs = b.shape[0] if b.dim() == 2 else 1
+        n = self.sym.n
+        infos = (GmresInfo * nrhs)()
+        _check(load().mf_direct_solve(self.h, nrhs, _devptr(b, n, nrhs, "b"), _devptr(x, n, nrhs, "x"), int(refine),
+                                      _stream_ptr(stream), infos))
+        return [{"iters": i.iters, "converged": bool(i.converged), "relres": i.relres} for i in infos]
+
+    def pcg(self, b, x, tol: float = 1e-10, maxit: int = 4000, stream=None, raise_on_noconv: bool = True):
+        """pcg_solve: preconditioned conjugate gradients with this factor."""
+        lib = load()
+        nrhs = b.shape[0] if b.dim() == 2 else 1
+        n = self.sym.n
+        o = PcgOpts()
+        _check(lib.mf_pcg_opts_default(ctypes.byref(o)))
+        o.maxit = maxit
+        o.stream = _stream_ptr(stream).value
+        infos = (GmresInfo * nrhs)()
+        st = lib.pcg_solve(self.h, nrhs, _devptr(b, n, nrhs, "b"), _devptr(x, n, nrhs, "x"), float(tol),
+                           ctypes.byref(o), infos)
         out = [{"iters": i.iters, "converged": bool(i.converged), "relres": i.relres} for i in infos]
         if st == MF_ENOCONV and not raise_on_noconv:
             return out

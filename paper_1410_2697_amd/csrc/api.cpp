@@ -244,6 +244,42 @@ mf_status mf_apply_noalloc(mf_numeric_t* f, int32_t nrhs, const double* r, doubl
   MF_GUARD_END
 }
 
+mf_status mf_direct_solve(mf_numeric_t* f, int32_t nrhs, const double* b, double* x, int32_t refine, void* stream,
+                          mf_gmres_info* info) {
+  MF_GUARD_BEGIN
+  if (!f || !b || !x || nrhs < 1 || b == x) return fail(MF_EINVAL, "bad argument");
+  if (refine < 0 || refine > 64) return fail(MF_EINVAL, "refine must be 0..64");
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  f->n->direct_solve(nrhs, b, x, refine, st, info);
+  f->n->note_stream(st);
+  return MF_OK;
+  MF_GUARD_END
+}
+
+mf_status mf_pcg_opts_default(mf_pcg_opts* o) {
+  if (!o) return fail(MF_EINVAL, "null opts");
+  *o = mf_pcg_opts{};
+  o->maxit = 4000;
+  return MF_OK;
+}
+
+mf_status pcg_solve(mf_numeric_t* f, int32_t nrhs, const double* b, double* x, double tol, const mf_pcg_opts* opts,
+                    mf_gmres_info* info) {
+  MF_GUARD_BEGIN
+  if (!f || !b || !x || nrhs < 1 || b == x) return fail(MF_EINVAL, "bad argument");
+  if (!(tol > 0.0)) return fail(MF_EINVAL, "tol must be > 0");
+  mf_pcg_opts o;
+  if (opts) o = *opts; else mf_pcg_opts_default(&o);
+  if (o.maxit < 1 || o.reserved != 0) return fail(MF_EINVAL, "maxit must be >= 1 and reserved 0");
+  mf_status s = MF_OK;
+  const hipStream_t st = static_cast<hipStream_t>(o.stream);
+  f->n->pcg(nrhs, b, x, tol, o.maxit, st, info, &s);
+  f->n->note_stream(st);
+  if (s == MF_ENOCONV) return fail(MF_ENOCONV, "PCG did not reach tol within maxit");
+  return s;
+  MF_GUARD_END
+}
+
 mf_status mf_spmv(mf_numeric_t* f, int32_t nrhs, const double* x, double* y, void* stream) {
   MF_GUARD_BEGIN
   if (!f || !x || !y || nrhs < 1 || x == y) return fail(MF_EINVAL, "bad argument");

@@ -331,5 +331,12 @@ void launch_xupdate(const double* Z, int64_t zstride, int nv, const double* y, d
                     int nrhs, hipStream_t st);
 void launch_axpby(const double* a, const double* b, double* c, double alpha, double beta, int64_t n,
                   hipStream_t st);
+// conjugate-gradient updates per column k (act[k] == 0: zero step):
+// x += alpha p, rprev = r, r -= alpha q with alpha_k = rz_k / pq_k
+void launch_cg_xr(double* x, double* r, double* rprev, const double* p, const double* q, const double* rz,
+                  const double* pq, const int* act, int n, int nrhs, hipStream_t st);
+// p = z + beta p with beta_k = (rzn_k - rzo_k) / rz_k
+void launch_cg_p(double* p, const double* z, const double* rzn, const double* rzo, const double* rz, const int* act,
+                 int n, int nrhs, hipStream_t st);
 
 }  // namespace mfh

@@ -1709,6 +1709,33 @@ __global__ void axpby_kernel(const double* a, const double* b, double* c, double
     c[i] = alpha * a[i] + beta * b[i];
 }
 
+// Conjugate-gradient vector updates, one coefficient per right-hand side k
+// (column k of the n x nrhs blocks); an inactive column (act[k] == 0, or a
+// zero p^T A p) gets a zero step.
+// alpha_k = rz_k / pq_k:  x += alpha p,  rprev = r,  r -= alpha q
+__global__ void cg_xr_kernel(double* x, double* r, double* rprev, const double* p, const double* q,
+                             const double* rz, const double* pq, const int* act, int n, int nrhs) {
+  const int64_t tot = (int64_t)n * nrhs;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < tot; idx += (int64_t)gridDim.x * blockDim.x) {
+    const int k = (int)(idx / n);
+    const double alpha = (act[k] && pq[k] > 0.0) ? rz[k] / pq[k] : 0.0;
+    const double rv = r[idx];
+    x[idx] += alpha * p[idx];
+    rprev[idx] = rv;
+    r[idx] = rv - alpha * q[idx];
+  }
+}
+// beta_k = (rzn_k - rzo_k) / rz_k (flexible form):  p = z + beta p
+__global__ void cg_p_kernel(double* p, const double* z, const double* rzn, const double* rzo, const double* rz,
+                            const int* act, int n, int nrhs) {
+  const int64_t tot = (int64_t)n * nrhs;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < tot; idx += (int64_t)gridDim.x * blockDim.x) {
+    const int k = (int)(idx / n);
+    const double beta = (act[k] && rz[k] != 0.0) ? (rzn[k] - rzo[k]) / rz[k] : 0.0;
+    p[idx] = z[idx] + beta * p[idx];
+  }
+}
+
 inline int grid_for(int64_t n, int block = 256, int cap = 8192) {
   int64_t g = (n + block - 1) / block;
   if (g < 1) g = 1;
@@ -1926,6 +1953,15 @@ void launch_mdot(const double* X, int64_t xstride, int nv, const double* w, int 
              xstride, nv, w, n, nrhs, partial);
   MFH_LAUNCH(mdot_reduce_kernel, dim3((nv * nrhs + 3) / 4), dim3(256), 0, st, partial, nchunk, nv, nrhs, out,
              accumulate);
+}
+void launch_cg_xr(double* x, double* r, double* rprev, const double* p, const double* q, const double* rz,
+                  const double* pq, const int* act, int n, int nrhs, hipStream_t st) {
+  MFH_LAUNCH(cg_xr_kernel, dim3(grid_for((int64_t)n * nrhs)), dim3(256), 0, st, x, r, rprev, p, q, rz, pq, act, n,
+             nrhs);
+}
+void launch_cg_p(double* p, const double* z, const double* rzn, const double* rzo, const double* rz, const int* act,
+                 int n, int nrhs, hipStream_t st) {
+  MFH_LAUNCH(cg_p_kernel, dim3(grid_for((int64_t)n * nrhs)), dim3(256), 0, st, p, z, rzn, rzo, rz, act, n, nrhs);
 }
 void launch_maxpy(const double* X, int64_t xstride, int nv, const double* coef, double* w, int n, int nrhs,
                   double sign, hipStream_t st) {

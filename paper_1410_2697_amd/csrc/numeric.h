@@ -83,6 +83,9 @@ class NumericBase {
   void spmv(int nrhs, const double* x, double* y, double alpha, double beta, hipStream_t st);
   void gmres(int nrhs, const double* b, double* x, double tol, const mf_gmres_opts& o, mf_gmres_info* info,
              mf_status* st_out);
+  void pcg(int nrhs, const double* b, double* x, double tol, int maxit, hipStream_t st, mf_gmres_info* info,
+           mf_status* st_out);
+  void direct_solve(int nrhs, const double* b, double* x, int refine, hipStream_t st, mf_gmres_info* info);
   mf_factor_info info{};
   uint64_t uid = 0;              // process-unique handle number (never reused)
   std::vector<int> ranks;        // per global block, -1 for dense fronts

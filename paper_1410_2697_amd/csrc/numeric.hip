@@ -2306,6 +2306,146 @@ void NumericBase::gmres(int nrhs, const double* b, double* x, double tol, const 
   *st_out = ok ? MF_OK : MF_ENOCONV;
 }
 
+// ======================================================= direct solve ====
+// The factor as a direct solver (Conclusion: at high accuracy, a standalone
+// direct solver): x = M^{-1} b, then `refine` steps of iterative refinement
+// x += M^{-1} (b - A x) with float64 residuals; the final true relative
+// residuals go to info.
+void NumericBase::direct_solve(int nrhs, const double* b, double* x, int refine, hipStream_t st,
+                               mf_gmres_info* info_out) {
+  const int N = sym->n;
+  const int64_t vs = (int64_t)N * nrhs;
+  g_r.ensure((size_t)vs * 8, &ms, st);
+  g_w.ensure((size_t)vs * 8, &ms, st);
+  g_small.ensure((size_t)2 * nrhs * 8, &ms, st);
+  g_partial.ensure((size_t)mdot_chunks(nrhs) * nrhs * 8, &ms, st);
+  double* r = g_r.as<double>();
+  double* w = g_w.as<double>();
+  double* nb = g_small.as<double>();
+  double* nr = nb + nrhs;
+  double* part = g_partial.as<double>();
+  apply(nrhs, b, x, st);
+  for (int s = 0; s < refine; ++s) {
+    spmv(nrhs, x, w, 1.0, 0.0, st);
+    launch_axpby(b, w, r, 1.0, -1.0, vs, st);       // r = b - A x
+    apply(nrhs, r, w, st);
+    launch_axpby(x, w, x, 1.0, 1.0, vs, st);        // x += M^{-1} r
+  }
+  spmv(nrhs, x, w, 1.0, 0.0, st);
+  launch_axpby(b, w, r, 1.0, -1.0, vs, st);
+  launch_mdot(r, 0, 1, r, N, nrhs, part, nr, 0, st);
+  launch_mdot(b, 0, 1, b, N, nrhs, part, nb, 0, st);
+  PinnedScratch pin((size_t)2 * nrhs * sizeof(double), st);
+  double* h = pin.as<double>(0);
+  HIPCHK(hipMemcpyAsync(h, nb, (size_t)2 * nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (info_out)
+    for (int k = 0; k < nrhs; ++k) {
+      const double rel = h[k] > 0.0 ? std::sqrt(h[nrhs + k] / h[k]) : 0.0;
+      info_out[k] = {refine, 1, rel};
+    }
+}
+
+// ================================================================== PCG ====
+// Preconditioned conjugate gradients with M = the factor (Sec. 3: the
+// preconditioner serves any Krylov solver, CG among them), every
+// right-hand side its own coefficients.  x0 = 0; flexible beta
+// <z_new, r_new - r_old> / <z_old, r_old> (the FP32 apply is not an exactly
+// fixed linear operator); a column stops when its recursive residual meets
+// tol or it reaches maxit iterations, then every column's true residual
+// b - A x is formed and columns that miss tol start again from x.  One host
+// read of the residual norms per iteration.
+void NumericBase::pcg(int nrhs, const double* b, double* x, double tol, int maxit, hipStream_t st,
+                      mf_gmres_info* info_out, mf_status* st_out) {
+  const int N = sym->n;
+  const int64_t vs = (int64_t)N * nrhs;
+  g_V.ensure((size_t)2 * vs * 8, &ms, st);
+  g_Z.ensure((size_t)3 * vs * 8, &ms, st);
+  g_small.ensure((size_t)7 * nrhs * 8 + (size_t)nrhs * 4, &ms, st);
+  g_partial.ensure((size_t)mdot_chunks(nrhs) * 2 * nrhs * 8, &ms, st);
+  double* r = g_V.as<double>();
+  double* rprev = r + vs;                 // right after r: one mdot takes both
+  double* z = g_Z.as<double>();
+  double* p = z + vs;
+  double* q = p + vs;
+  double* sm = g_small.as<double>();
+  double* S[2] = {sm, sm + 2 * nrhs};     // per iteration: <r, z> (first nrhs), <r_old, z> (next nrhs)
+  double* pq = sm + 4 * nrhs;
+  double* rr = pq + nrhs;
+  double* bn = rr + nrhs;
+  int* act = reinterpret_cast<int*>(bn + nrhs);
+  double* part = g_partial.as<double>();
+  PinnedScratch pin((size_t)nrhs * (sizeof(double) + sizeof(int)), st);
+  double* hr = pin.as<double>(0);
+  int* hact = pin.as<int>((size_t)nrhs * sizeof(double));
+  auto read = [&](const double* d) {
+    HIPCHK(hipMemcpyAsync(hr, d, (size_t)nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+  };
+  auto upload_act = [&]() {
+    HIPCHK(hipMemcpyAsync(act, hact, (size_t)nrhs * sizeof(int), hipMemcpyHostToDevice, st));
+  };
+  launch_mdot(b, 0, 1, b, N, nrhs, part, bn, 0, st);
+  read(bn);
+  std::vector<double> bnorm(nrhs), relres(nrhs, 0.0);
+  std::vector<int> iters(nrhs, 0), conv(nrhs, 0);
+  for (int k = 0; k < nrhs; ++k) {
+    bnorm[k] = std::sqrt(hr[k]);
+    conv[k] = bnorm[k] == 0.0;
+  }
+  launch_fill<double>(x, vs, 0.0, st);
+  launch_axpby(b, b, r, 1.0, 0.0, vs, st);   // r = b
+  for (;;) {
+    bool any = false;
+    for (int k = 0; k < nrhs; ++k) {
+      hact[k] = !conv[k] && iters[k] < maxit;
+      any |= hact[k] != 0;
+    }
+    if (!any) break;
+    upload_act();
+    // (re)start every active column from x with its residual r
+    apply(nrhs, r, z, st);
+    launch_axpby(z, z, p, 1.0, 0.0, vs, st);                 // p = z
+    launch_mdot(r, 0, 1, z, N, nrhs, part, S[0], 0, st);     // <r, z>
+    int cur = 0;
+    for (;;) {
+      spmv(nrhs, p, q, 1.0, 0.0, st);
+      launch_mdot(p, 0, 1, q, N, nrhs, part, pq, 0, st);
+      launch_cg_xr(x, r, rprev, p, q, S[cur], pq, act, N, nrhs, st);
+      launch_mdot(r, 0, 1, r, N, nrhs, part, rr, 0, st);
+      read(rr);
+      any = false;
+      for (int k = 0; k < nrhs; ++k) {
+        if (!hact[k]) continue;
+        ++iters[k];
+        if (std::sqrt(hr[k]) <= tol * bnorm[k] || iters[k] >= maxit) hact[k] = 0;
+        any |= hact[k] != 0;
+      }
+      if (!any) break;
+      upload_act();
+      apply(nrhs, r, z, st);
+      launch_mdot(r, vs, 2, z, N, nrhs, part, S[1 - cur], 0, st);   // <r, z>, <r_old, z>
+      launch_cg_p(p, z, S[1 - cur], S[1 - cur] + nrhs, S[cur], act, N, nrhs, st);
+      cur = 1 - cur;
+    }
+    // true residuals
+    spmv(nrhs, x, q, 1.0, 0.0, st);
+    launch_axpby(b, q, r, 1.0, -1.0, vs, st);
+    launch_mdot(r, 0, 1, r, N, nrhs, part, rr, 0, st);
+    read(rr);
+    for (int k = 0; k < nrhs; ++k) {
+      relres[k] = bnorm[k] > 0.0 ? std::sqrt(hr[k]) / bnorm[k] : 0.0;
+      if (relres[k] <= tol) conv[k] = 1;
+    }
+  }
+  bool ok = true;
+  for (int k = 0; k < nrhs; ++k) {
+    ok &= conv[k] != 0;
+    if (info_out) info_out[k] = {iters[k], conv[k], relres[k]};
+  }
+  *st_out = ok ? MF_OK : MF_ENOCONV;
+}
+
 // Device bytes of a factorisation before it runs.  Exact for the front
 // workspace, the dense fronts and the fixed buffers; the HODLR part assumes
 // every block rank r <= min(rows, cols, rank_cap, 8 sqrt(max(rows, cols)))
