@@ -365,10 +365,10 @@ void mf_server_destroy(mf_server_t* sv);
  * kernels (semicolon-separated trace names such as "gemm_kernel<float>" or
  * "skreg_kernel<float, 3, 24, false, 512>"; NULL or "" = all timed kernels)
  * is timed and the host adds up the launch's algorithmic work (flops; bytes
- * that the operation must move at least once).  GEMM launches time
- * themselves on the device's constant-rate clock (first workgroup start to
- * last workgroup end); other kernels get start and end events stamped by the
- * runtime at the kernel's own start and end.  mf_prof_stop waits for the
+ * that the operation must move at least once).  Each timed launch gets start
+ * and end events stamped by the runtime at the kernel's own start and end
+ * (the dispatch interval a kernel trace reports); the events cost launch
+ * throughput, so time throughput outside a session.  mf_prof_stop waits for the
  * work, writes one mf_kstat per kernel that ran (at most cap; *n = count)
  * and stops timing.
  */

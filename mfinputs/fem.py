@@ -14,6 +14,9 @@ Problem families
 * ``p1_kuhn_cube`` P1 tetrahedra: every cube of a uniform grid split into 6
                    Kuhn tetrahedra along the (0,0,0)-(1,1,1) diagonal, interior
                    nodes jittered, Dirichlet on the faces x=0, y=0, z=0.
+* ``q1_elasticity`` vector problem (3 unknowns per node): isotropic linear
+                   elasticity (Navier-Cauchy) with trilinear hexahedra,
+                   clamped on every face.
 
 The sparsity *pattern* is the element-connectivity pattern: explicit zeros
 (e.g. the face couplings of the 3D Q1 Laplacian, which cancel exactly) are
@@ -183,6 +186,111 @@ def q1_dirichlet_lift(n: int, dim: int, g, k_elem: np.ndarray | None = None):
     b_I = b_all[interior]
     g_I = g(coord[interior] * h)
     return b_I, g_I
+
+
+def isotropic_elasticity_matrix(E: float, nu: float) -> np.ndarray:
+    """Voigt stress-strain matrix D (order xx, yy, zz, yz, xz, xy, engineering
+    shear strains) of isotropic linear elasticity: Lame lambda and mu."""
+    lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu))
+    mu = E / (2.0 * (1.0 + nu))
+    D = np.zeros((6, 6))
+    D[:3, :3] = lam
+    D[np.arange(3), np.arange(3)] = lam + 2.0 * mu
+    D[np.arange(3, 6), np.arange(3, 6)] = mu
+    return D
+
+
+def q1_elasticity_element_stiffness(h: float, E: float = 1.0, nu: float = 0.3) -> np.ndarray:
+    """Stiffness (24 x 24) of one trilinear hexahedron (a cube of side h) for
+    the Navier-Cauchy equation (isotropic linear elasticity): the integral
+    of B^T D B by 2 x 2 x 2 Gauss points (exact for this element).  Local
+    node l = bit_x + 2 bit_y + 4 bit_z; degree of freedom 3 l + c for the
+    displacement component c."""
+    D = isotropic_elasticity_matrix(E, nu)
+    g = (np.array([-1.0, 1.0]) / np.sqrt(3.0) + 1.0) * (h / 2.0)   # Gauss points on [0, h]
+    w = (h / 2.0) ** 3
+    bits = np.array([[(l >> a) & 1 for a in range(3)] for l in range(8)])
+    Ke = np.zeros((24, 24))
+    for x in g:
+        for y in g:
+            for z in g:
+                p = np.array([x, y, z]) / h
+                f = np.where(bits == 1, p, 1.0 - p)             # 1D factors per node and axis
+                df = np.where(bits == 1, 1.0, -1.0) / h
+                grad = np.zeros((8, 3))
+                for a in range(3):
+                    others = [b for b in range(3) if b != a]
+                    grad[:, a] = df[:, a] * f[:, others[0]] * f[:, others[1]]
+                B = np.zeros((6, 24))
+                for l in range(8):
+                    gx, gy, gz = grad[l]
+                    c = 3 * l
+                    B[0, c] = gx
+                    B[1, c + 1] = gy
+                    B[2, c + 2] = gz
+                    B[3, c + 1], B[3, c + 2] = gz, gy
+                    B[4, c], B[4, c + 2] = gz, gx
+                    B[5, c], B[5, c + 1] = gy, gx
+                Ke += w * B.T @ D @ B
+    return Ke
+
+
+def _elasticity_assemble(n: int, E: float, nu: float, keep_all: bool):
+    """Element loop of q1_elasticity on the grid with n interior nodes per
+    axis: returns (rows, cols, vals, node ids) over all (n+2)^3 grid nodes
+    (keep_all) or over the interior unknowns only."""
+    m, ne, h = n + 2, n + 1, 1.0 / (n + 1)
+    Ke = q1_elasticity_element_stiffness(h, E, nu)
+    grids = np.meshgrid(*[np.arange(ne)] * 3, indexing="ij")
+    origin = np.stack([gg.ravel() for gg in grids], axis=1)
+    offs = np.array([[(l >> a) & 1 for a in range(3)] for l in range(8)])
+    nodes = origin[:, None, :] + offs[None, :, :]                    # [nel, 8, 3]
+    if keep_all:
+        nid = nodes[:, :, 0] + m * (nodes[:, :, 1] + m * nodes[:, :, 2])
+    else:
+        inside = np.all((nodes >= 1) & (nodes <= n), axis=2)
+        idx = nodes - 1
+        nid = np.where(inside, idx[:, :, 0] + n * (idx[:, :, 1] + n * idx[:, :, 2]), -1)
+    dof = (3 * nid[:, :, None] + np.arange(3)[None, None, :]).reshape(nid.shape[0], 24)
+    dof[np.repeat(nid, 3, axis=1) < 0] = -1
+    ii = np.repeat(np.arange(24), 24)
+    jj = np.tile(np.arange(24), 24)
+    R, C = dof[:, ii], dof[:, jj]
+    keep = (R >= 0) & (C >= 0)
+    return R[keep], C[keep], np.broadcast_to(Ke[ii, jj], R.shape)[keep], h
+
+
+def q1_elasticity(n: int, E: float = 1.0, nu: float = 0.3, name: str = "elasticity_q1") -> Problem:
+    """Linear elasticity (Navier-Cauchy, isotropic) with trilinear hexahedra
+    on the unit cube, n interior nodes per axis (h = 1/(n+1)), displacement
+    clamped on every face: 3 unknowns per interior node, N = 3 n^3, node-major
+    (unknown 3 i + c is component c at node i = x + n y + n^2 z).  Each
+    unknown carries its node's integer grid coordinates."""
+    R, C, V, h = _elasticity_assemble(n, E, nu, keep_all=False)
+    N = 3 * n ** 3
+    A = _coo_to_csr(N, R, C, V)
+    ids = np.arange(n ** 3)
+    node = np.stack([ids % n, (ids // n) % n, ids // (n * n)], axis=1).astype(np.float64)
+    coords = np.repeat(node, 3, axis=0)
+    return Problem(name, A, coords, 3, {"n": n, "h": h, "kind": "elasticity_q1", "E": E, "nu": nu})
+
+
+def q1_elasticity_lift(n: int, G: np.ndarray, E: float = 1.0, nu: float = 0.3):
+    """Manufactured problem for q1_elasticity(n): boundary displacements
+    u(x) = G x (any 3 x 3 G: a constant-strain field) lifted into the interior
+    right-hand side b_I = -A_IB u_B.  Returns (b_I, u_I).  Constant stress has
+    zero divergence, and trilinear elements contain linear fields, so the
+    discrete solution equals u_I at the nodes."""
+    m = n + 2
+    R, C, V, h = _elasticity_assemble(n, E, nu, keep_all=True)
+    S = _coo_to_csr(3 * m ** 3, R, C, V).to_scipy()
+    ids = np.arange(m ** 3)
+    pos = np.stack([ids % m, (ids // m) % m, ids // (m * m)], axis=1) * h
+    u = (pos @ np.asarray(G, dtype=np.float64).T).ravel()           # node-major, 3 components
+    interior = np.repeat(np.all((pos > 0.5 * h) & (pos < 1.0 - 0.5 * h), axis=1), 3)
+    ub = np.where(interior, 0.0, u)
+    b_all = -(S @ ub)
+    return b_all[interior], u[interior]
 
 
 def grf_squared_exponential(shape, corr_len: float, variance: float, seed: int) -> np.ndarray:

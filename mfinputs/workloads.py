@@ -1,5 +1,6 @@
 """Named synthetic workloads.  Each stands in for the paper's (unavailable)
-elasticity matrices with a scalar elliptic FEM problem of a stated shape.
+elasticity matrices with an elliptic FEM problem of a stated shape: scalar
+(Poisson, diffusion) or vector (linear elasticity, 3 unknowns per node).
 
 Parameters per workload: the mesh, the leaf size (one value for the
 nested-dissection leaf and the HODLR leaf), the low-rank tolerance eps, the
@@ -11,7 +12,7 @@ import dataclasses
 
 import numpy as np
 
-from .fem import Problem, q1_grid, p1_kuhn_cube, rhs, grf_squared_exponential, lognormal_elements
+from .fem import Problem, q1_grid, p1_kuhn_cube, q1_elasticity, rhs, grf_squared_exponential, lognormal_elements
 
 
 @dataclasses.dataclass
@@ -56,6 +57,18 @@ def _p1kuhn(cells=48, seed=0, nrhs=8):
                     params={"cells": cells, "nrhs": nrhs, "jitter": 0.2})
 
 
+def _elasticity3d_q1(n=32, seed=0, nrhs=4):
+    """Isotropic linear elasticity (E = 1, nu = 0.3) on a structured cube,
+    3 unknowns per node: 32^3 nodes give N = 98,304, the size of the paper's
+    smallest structured FETI-local matrix (about 100K unknowns)."""
+    p = q1_elasticity(n, name=f"elasticity3d_q1_{n}")
+    b = rhs(p.A.n, nrhs, "normal", seed)
+    # three unknowns per node triple the separator ranks; eps 1e-2, one of the
+    # tolerances the paper uses on its elasticity matrices (1e-1 and 1e-2)
+    return Workload(p.name, p, b, leaf=128, eps=1e-2, precision="fp32", tol=1e-10,
+                    params={"grid": n, "dim": 3, "dof_per_node": 3, "nrhs": nrhs, "E": 1.0, "nu": 0.3})
+
+
 def serving_request(side: int, seed: int, nrhs: int = 4) -> Workload:
     k = lognormal_elements((side + 1,) * 3, 0.5, seed)
     p = q1_grid(side, 3, k_elem=k, name=f"serve_{side}_{seed}")
@@ -80,6 +93,7 @@ WORKLOADS = {
     "poisson3d_q1_32": _poisson3d_q1,
     "diffusion3d_grf_64": _diffusion3d_grf,
     "p1kuhn_48": _p1kuhn,
+    "elasticity3d_q1_32": _elasticity3d_q1,
 }
 
 

@@ -142,7 +142,7 @@ __device__ __forceinline__ T load_op(const T* p, size_t idx, bool bf16) {
 // columns): 64 x 16 tiles, each wave one 16 x 16 MFMA tile, so no MFMA work
 // is spent on empty columns.
 template <typename T, int BN>
-__device__ __forceinline__ void gemm_tile(const GemmDesc<T>* __restrict__ descs, int ndesc, unsigned long long* ts) {
+__device__ __forceinline__ void gemm_tile(const GemmDesc<T>* __restrict__ descs, int ndesc) {
   constexpr int BM = kTile, BK = kGemmBK<T>, NQ = BK * 64 / 256, NQB = BK * BN / 256;
   constexpr bool NARROW = BN == 16;
   __shared__ T As[BK][BM + 1];
@@ -159,7 +159,6 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc<T>* __restrict__ descs,
   const int k = d.kdev ? *d.kdev : d.k;
   const bool split = d.ksplit > 1;
   if ((flags & GF_LOWER_C) && n0 >= m0 + BM) return;   // above the diagonal (never read back)
-  if (ts && tid == 0) atomicMin(ts, (unsigned long long)wall_clock64());   // self-timing (profiling only)
   int kb0 = 0, kend = k;
   if (flags & GF_A_LOWER) kend = min(kend, m0 + BM);
   if (flags & GF_B_UPPER) kend = min(kend, n0 + BN);
@@ -264,21 +263,15 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc<T>* __restrict__ descs,
       }
     }
   }
-  if (ts) {
-    __syncthreads();
-    if (tid == 0) atomicMax(ts + 1, (unsigned long long)wall_clock64());
-  }
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc<T>* __restrict__ descs, int ndesc,
-                                                   unsigned long long* ts) {
-  gemm_tile<T, kTile>(descs, ndesc, ts);
+__global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc<T>* __restrict__ descs, int ndesc) {
+  gemm_tile<T, kTile>(descs, ndesc);
 }
 template <typename T>
-__global__ __launch_bounds__(256) void gemm_narrow_kernel(const GemmDesc<T>* __restrict__ descs, int ndesc,
-                                                          unsigned long long* ts) {
-  gemm_tile<T, kTileNarrow>(descs, ndesc, ts);
+__global__ __launch_bounds__(256) void gemm_narrow_kernel(const GemmDesc<T>* __restrict__ descs, int ndesc) {
+  gemm_tile<T, kTileNarrow>(descs, ndesc);
 }
 
 template <typename T>
@@ -1749,9 +1742,8 @@ inline int grid_for(int64_t n, int block = 256, int cap = 8192) {
 template <typename T>
 void launch_gemm(const GemmDesc<T>* d, int ndesc, int tiles, hipStream_t st, int tn) {
   if (ndesc <= 0 || tiles <= 0) return;
-  unsigned long long* ts = prof_take_slot();
-  if (tn == kTileNarrow) MFH_LAUNCH(gemm_narrow_kernel<T>, dim3(tiles), dim3(256), 0, st, d, ndesc, ts);
-  else MFH_LAUNCH(gemm_kernel<T>, dim3(tiles), dim3(256), 0, st, d, ndesc, ts);
+  if (tn == kTileNarrow) MFH_LAUNCH(gemm_narrow_kernel<T>, dim3(tiles), dim3(256), 0, st, d, ndesc);
+  else MFH_LAUNCH(gemm_kernel<T>, dim3(tiles), dim3(256), 0, st, d, ndesc);
 }
 template <typename T>
 void launch_gemm_reduce(const GemmDesc<T>* d, int ndesc, int tiles, hipStream_t st) {

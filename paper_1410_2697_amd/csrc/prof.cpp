@@ -29,11 +29,8 @@ struct Rec {
   int kind;
   hipEvent_t a, b;
   double flops, bytes;
-  int state;        // 0 waiting for a launch, 1 events taken by a launch, 2 recorded here, 3 dropped,
-                    // 4 timed by the kernel itself in device slot `slot`
-  int slot;
+  int state;        // 0 waiting for a launch, 1 events taken by a launch, 2 recorded here, 3 dropped
 };
-constexpr int kSlots = 1 << 16;
 thread_local int t_pending = -1;   // record whose events the next MFH_LAUNCH takes
 thread_local bool t_suspended = false;
 
@@ -43,13 +40,7 @@ struct State {
   int session = 0;
   std::vector<Rec> recs;
   std::vector<hipEvent_t> pool;
-  unsigned long long* slots = nullptr;   // device: kSlots x {min start, max end}
-  int slot_dev = -1;
-  int slots_used = 0;
 };
-bool self_timed(int kind) {
-  return kind == PK_GEMM_F64 || kind == PK_GEMM_F32 || kind == PK_GEMMN_F64 || kind == PK_GEMMN_F32;
-}
 State& S() {
   static State s;
   return s;
@@ -86,7 +77,7 @@ int prof_begin(int kind, hipStream_t st, double flops, double bytes) {
   if (t_suspended || !((s.mask.load(std::memory_order_relaxed) >> kind) & 1)) return -1;
   std::lock_guard<std::mutex> g(s.mu);
   if (s.recs.size() >= (size_t(1) << kIdxBits)) return -1;
-  Rec r{kind, take(s), take(s), flops, bytes, 0, -1};
+  Rec r{kind, take(s), take(s), flops, bytes, 0};
   (void)st;
   if (!r.a || !r.b) {
     if (r.a) s.pool.push_back(r.a);
@@ -96,22 +87,6 @@ int prof_begin(int kind, hipStream_t st, double flops, double bytes) {
   s.recs.push_back(r);
   t_pending = (int)(s.recs.size() - 1);
   return ((s.session & 0x3F) << kIdxBits) | t_pending;
-}
-
-unsigned long long* prof_take_slot() {
-  if (t_pending < 0) return nullptr;
-  State& s = S();
-  std::lock_guard<std::mutex> g(s.mu);
-  const int i = t_pending;
-  if (i >= (int)s.recs.size() || s.recs[i].state != 0 || !self_timed(s.recs[i].kind) || !s.slots ||
-      s.slots_used >= kSlots)
-    return nullptr;
-  int dev = -1;
-  if (hipGetDevice(&dev) != hipSuccess || dev != s.slot_dev) return nullptr;
-  t_pending = -1;
-  s.recs[i].state = 4;
-  s.recs[i].slot = s.slots_used++;
-  return s.slots + 2 * (size_t)s.recs[i].slot;
 }
 
 bool prof_take(hipEvent_t* start, hipEvent_t* stop) {
@@ -178,30 +153,6 @@ void prof_start(const std::string& names) {
   }
   s.recs.clear();
   t_pending = -1;
-  // device slots for self-timed kernels, reset to {max, 0}
-  int dev = -1;
-  if (hipGetDevice(&dev) == hipSuccess) {
-    if (s.slots && s.slot_dev != dev) s.slots = nullptr;   // other device: keep the old block, allocate anew
-    if (!s.slots) {
-      void* p = nullptr;
-      if (hipMalloc(&p, sizeof(unsigned long long) * 2 * kSlots) == hipSuccess) {
-        s.slots = static_cast<unsigned long long*>(p);
-        s.slot_dev = dev;
-      } else {
-        (void)hipGetLastError();
-      }
-    }
-    if (s.slots) {
-      std::vector<unsigned long long> init(2 * kSlots, 0ull);
-      for (int i = 0; i < kSlots; ++i) init[2 * i] = ~0ull;
-      if (hipMemcpy(s.slots, init.data(), init.size() * sizeof(unsigned long long), hipMemcpyHostToDevice) !=
-          hipSuccess) {
-        (void)hipGetLastError();
-        s.slots = nullptr;
-      }
-    }
-  }
-  s.slots_used = 0;
   ++s.session;
   s.mask.store(m);
 }
@@ -212,31 +163,11 @@ std::vector<ProfTotal> prof_stop() {
   s.mask.store(0);
   std::vector<ProfTotal> t(PK_COUNT);
   for (int k = 0; k < PK_COUNT; ++k) t[k] = ProfTotal{k, 0, 0.0, 0.0, 0.0};
-  std::vector<unsigned long long> sl;
-  double tick = 0.0;   // seconds per wall-clock count
-  if (s.slots && s.slots_used > 0) {
-    int khz = 0;
-    if (hipDeviceSynchronize() == hipSuccess &&
-        hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, s.slot_dev) == hipSuccess && khz > 0) {
-      sl.resize(2 * (size_t)s.slots_used);
-      if (hipMemcpy(sl.data(), s.slots, sl.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost) !=
-          hipSuccess) {
-        sl.clear();
-        (void)hipGetLastError();
-      }
-      tick = 1.0 / (1e3 * khz);
-    } else {
-      (void)hipGetLastError();
-    }
-  }
   for (Rec& r : s.recs) {
     float ms = 0.f;
     double sec = -1.0;
-    if (r.state == 4) {
-      if (!sl.empty() && sl[2 * r.slot + 1] >= sl[2 * r.slot] && sl[2 * r.slot] != ~0ull)
-        sec = tick * (double)(sl[2 * r.slot + 1] - sl[2 * r.slot]);
-    } else if ((r.state == 1 || r.state == 2) && hipEventSynchronize(r.b) == hipSuccess &&
-               hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+    if ((r.state == 1 || r.state == 2) && hipEventSynchronize(r.b) == hipSuccess &&
+        hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
       sec = 1e-3 * ms;
     }
     if (sec >= 0.0) {

@@ -51,11 +51,6 @@ void prof_suspend(bool on);
 int prof_begin(int kind, hipStream_t st, double flops, double bytes);
 void prof_end(int id, hipStream_t st);
 bool prof_take(hipEvent_t* start, hipEvent_t* stop);
-// GEMM launches time themselves (short kernels: events would add the launch
-// overhead): a pending GEMM record hands out a device slot of two counters,
-// the earliest workgroup start and the latest workgroup end on the device's
-// constant-rate wall clock (atomic min / max).  nullptr when nothing is pending.
-unsigned long long* prof_take_slot();
 // for a launch that cannot take events: record the start on the stream now
 void prof_stream_start(int id, hipStream_t st);
 

@@ -98,3 +98,66 @@ def test_rhs_and_grf_seeded():
     assert np.array_equal(a, b) and a.shape == (100, 3)
     g = grf_squared_exponential((33, 33, 33), 0.1, 1.0, 0)
     assert abs(g.mean()) < 0.3 and 0.5 < g.var() < 1.5
+
+
+# ---- vector elasticity (3 unknowns per node)
+def _rigid_modes(h):
+    """Six rigid-body displacement fields of the unit element's 8 nodes."""
+    from mfinputs.fem import q1_elasticity_element_stiffness  # noqa: F401
+    pos = np.array([[(l >> a) & 1 for a in range(3)] for l in range(8)], dtype=float) * h
+    modes = []
+    for c in range(3):
+        u = np.zeros((8, 3)); u[:, c] = 1.0
+        modes.append(u.ravel())
+    for w in np.eye(3):
+        modes.append(np.cross(w, pos).ravel())          # infinitesimal rotation w x x
+    return np.array(modes).T
+
+
+def test_elasticity_element_stiffness_rigid_modes_and_rank():
+    from mfinputs.fem import q1_elasticity_element_stiffness
+    h = 0.25
+    K = q1_elasticity_element_stiffness(h, 2.0, 0.3)
+    assert np.abs(K - K.T).max() <= 1e-14 * np.abs(K).max()
+    ev = np.linalg.eigvalsh(K)
+    assert ev.min() >= -1e-12 * ev.max()
+    assert np.sum(ev < 1e-10 * ev.max()) == 6          # exactly the rigid-body modes
+    R = _rigid_modes(h)
+    assert np.abs(K @ R).max() <= 1e-12 * np.abs(K).max()
+
+
+def test_elasticity_element_energy_closed_forms():
+    """Uniform uniaxial strain eps: energy u^T K u = (lambda + 2 mu) eps^2 h^3;
+    uniform shear u_x = g y: u^T K u = mu g^2 h^3."""
+    from mfinputs.fem import q1_elasticity_element_stiffness
+    E, nu, h = 3.0, 0.25, 0.5
+    lam, mu = E * nu / ((1 + nu) * (1 - 2 * nu)), E / (2 * (1 + nu))
+    K = q1_elasticity_element_stiffness(h, E, nu)
+    pos = np.array([[(l >> a) & 1 for a in range(3)] for l in range(8)], dtype=float) * h
+    u = np.zeros((8, 3)); u[:, 0] = 0.01 * pos[:, 0]
+    assert np.isclose(u.ravel() @ K @ u.ravel(), (lam + 2 * mu) * 0.01 ** 2 * h ** 3, rtol=1e-12)
+    u = np.zeros((8, 3)); u[:, 0] = 0.02 * pos[:, 1]
+    assert np.isclose(u.ravel() @ K @ u.ravel(), mu * 0.02 ** 2 * h ** 3, rtol=1e-12)
+
+
+def test_elasticity_patch_test_reproduces_linear_fields():
+    """Boundary displacements u = G x lifted into the right-hand side: the
+    discrete solution is G x at every interior node (constant stress is in
+    equilibrium; trilinear elements contain linear fields)."""
+    from mfinputs.fem import q1_elasticity, q1_elasticity_lift
+    G = np.array([[0.1, -0.2, 0.05], [0.3, 0.02, -0.1], [-0.04, 0.15, 0.2]])
+    p = q1_elasticity(5)
+    b, u = q1_elasticity_lift(5, G)
+    x = np.linalg.solve(p.A.to_dense(), b)
+    assert np.abs(x - u).max() <= 1e-12 * np.abs(u).max()
+
+
+def test_elasticity_matrix_structure():
+    from mfinputs.fem import q1_elasticity
+    p = q1_elasticity(4)
+    assert p.A.n == 3 * 4 ** 3
+    counts = np.diff(p.A.rowptr)
+    assert counts.max() == 81 and counts.min() == 3 * 8    # 27 or 8 neighbouring nodes (corner), 3 each
+    D = p.A.to_dense()
+    assert np.allclose(D, D.T, atol=1e-15) and np.linalg.eigvalsh(D).min() > 0
+    assert np.array_equal(p.coords[0::3], p.coords[1::3]) and np.array_equal(p.coords[0::3], p.coords[2::3])

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import paper_1410_2697_amd as mfh
-from mfinputs import q1_grid, p1_kuhn_cube
+from mfinputs import q1_grid, p1_kuhn_cube, q1_elasticity
 from oracle import symbolic
 
 INCLUDE = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include")
@@ -48,6 +48,7 @@ CASES = [
     ("q1_3d_16_leaf128", lambda: q1_grid(16, 3), 128),
     ("q1_3d_11_leaf24", lambda: q1_grid(11, 3), 24),
     ("p1kuhn_9_leaf40", lambda: p1_kuhn_cube(9, 0.2, 7), 40),
+    ("elasticity_7_leaf60", lambda: q1_elasticity(7), 60),
 ]
 
 

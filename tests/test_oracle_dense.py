@@ -2,7 +2,7 @@
 import numpy as np
 import pytest
 
-from mfinputs import q1_grid, p1_kuhn_cube, rhs
+from mfinputs import q1_grid, p1_kuhn_cube, q1_elasticity, q1_elasticity_lift, rhs
 from mfinputs.fem import q1_dirichlet_lift
 from oracle import symbolic, dense_mf
 
@@ -12,6 +12,7 @@ from oracle import symbolic, dense_mf
     (lambda: q1_grid(6, 3), 16),
     (lambda: q1_grid(5, 3, k_elem=np.exp(np.random.default_rng(0).standard_normal((6, 6, 6)))), 10),
     (lambda: p1_kuhn_cube(5, 0.2, 1), 12),
+    (lambda: q1_elasticity(4), 24),                    # 3 unknowns per node
 ])
 def test_factor_is_the_cholesky_factor(maker, leaf):
     """The Cholesky factor of an SPD matrix is unique, so the multifrontal L
@@ -60,3 +61,15 @@ def test_multilinear_boundary_data_reproduced(dim):
     sym = symbolic.analyze(p.A, p.coords, 8)
     x = dense_mf.solve(dense_mf.factor(sym, p.A.vals), b)
     assert np.abs(x - gI).max() < 1e-12
+
+
+def test_elasticity_patch_test_through_the_multifrontal_solve():
+    """The constant-strain patch test of the vector problem, solved by the
+    oracle's multifrontal factorisation (3 unknowns per node, the nested
+    dissection sees repeated node coordinates)."""
+    G = np.array([[0.2, 0.1, -0.3], [0.0, -0.1, 0.05], [0.4, 0.2, 0.1]])
+    p = q1_elasticity(6)
+    b, u = q1_elasticity_lift(6, G)
+    sym = symbolic.analyze(p.A, p.coords, 48)
+    x = dense_mf.solve(dense_mf.factor(sym, p.A.vals), b)
+    assert np.abs(x - u).max() <= 1e-12 * np.abs(u).max()
