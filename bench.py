@@ -294,7 +294,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="poisson3d_q1_32")
-    ap.add_argument("--n-c", type=int, default=512)
+    ap.add_argument("--n-c", type=int, default=None, help="dense/HODLR front threshold (default: the "
+                    "workload's, else 512)")
     ap.add_argument("--latency-calls", type=int, default=100)
     ap.add_argument("--apply-graph", type=int, default=0,
                     help="record the apply as a HIP graph from its k-th use (0: launch each step, so that the "
@@ -325,6 +326,8 @@ def main():
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     w = make_workload(args.workload)
+    if args.n_c is None:
+        args.n_c = int(w.params.get("n_c", 512))
     _log(f"workload {w.name} n={w.problem.A.n} nnz={w.problem.A.nnz} nrhs={w.b.shape[1]}")
     def report(tag, r):
         e = r["end_to_end"]

@@ -31,7 +31,7 @@ def _poisson2d_q1(n=64, seed=0):
     p = q1_grid(n, 2, name=f"poisson2d_q1_{n}")
     b = rhs(p.A.n, 1, "uniform", seed)
     return Workload(p.name, p, b, leaf=64, eps=1e-6, precision="fp64", tol=1e-10,
-                    params={"grid": n, "dim": 2, "nrhs": 1})
+                    params={"grid": n, "dim": 2, "nrhs": 1, "n_c": 0})    # every front HODLR
 
 
 def _poisson3d_q1(n=32, seed=0, nrhs=16):
