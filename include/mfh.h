@@ -80,7 +80,13 @@ typedef struct {
                            2^20.  A timing session (mf_prof_start) times the direct
                            applies' launches; the graph is recorded untimed, so its
                            replays run as they would without the session.             */
-  int32_t reserved0;    /* must be 0 */
+  int32_t sampled;      /* HODLR only, 1: the sampled extend-add of Sec. 4.2.1 (Eq. HODLR_EA_Expand):
+                           compressed fronts are never staged densely; only the BDLR rows
+                           and columns of each block and the diagonal leaves are formed, from
+                           A's entries, dense children's updates and compressed children's
+                           F_ff^HODLR - Wt W^T, and compression uses those samples alone, so
+                           it needs adaptive = 0 (the paper's scheme).  0: every front is
+                           staged densely and children's updates are scatter-added whole   */
   double eps;           /* low-rank tolerance (Sec. 2.2: stop when |u_r+1,r+1/u_11| < eps) */
   void* stream;         /* hipStream_t, borrowed; NULL = null stream                      */
 } mf_opts;

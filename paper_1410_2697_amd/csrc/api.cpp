@@ -189,8 +189,11 @@ mf_status mf_factor(const mf_symbolic_t* sh, const double* vals, double eps, int
   if (o.uv_bf16 && o.method != MF_METHOD_HODLR) return fail(MF_EINVAL, "uv_bf16 needs MF_METHOD_HODLR");
   if (o.precision != MF_FP64 && o.precision != MF_FP32) return fail(MF_EINVAL, "unknown precision");
   if (!(eps >= 0.0) || eps >= 1.0) return fail(MF_EINVAL, "eps must be in [0, 1)");
-  if (o.apply_graph < 0 || o.apply_graph > (1 << 20) || o.reserved0 != 0)
-    return fail(MF_EINVAL, "apply_graph must be in [0, 2^20] and reserved0 0");
+  if (o.apply_graph < 0 || o.apply_graph > (1 << 20)) return fail(MF_EINVAL, "apply_graph must be in [0, 2^20]");
+  if (o.sampled != 0 && o.sampled != 1) return fail(MF_EINVAL, "sampled must be 0 or 1");
+  if (o.sampled && (o.method != MF_METHOD_HODLR || o.adaptive))
+    return fail(MF_EINVAL, "the sampled extend-add forms only the BDLR rows and columns: it needs "
+                           "MF_METHOD_HODLR and adaptive 0");
   if (leaf != 0 && leaf != sh->s.leaf) return fail(MF_EINVAL, "leaf must be 0 or the analysis leaf size");
   if (o.method == MF_METHOD_HODLR) {
     if (sh->s.leaf > 128) return fail(MF_EINVAL, "HODLR leaves are limited to 128");

@@ -85,10 +85,15 @@ struct SkRegDesc {
 };
 
 // C~ = B(:, J_r) U_r^{-1} (rows of U) and R~^T = (L_r^{-1} B(I_r, :))^T
-// (rows of V) for a block B = F(r0 : r0+nr, c0 : c0+nc).
+// (rows of V) for a block B = F(r0 : r0+nr, c0 : c0+nc).  The pivot
+// columns are read from F (ld), the pivot rows from FR (ldr): the same front
+// when it is staged densely, else the block's column and row samples (then
+// r0 = c0 = 0 and the pivots index the samples).
 template <typename T>
 struct SkelFacDesc {
   const T* F;
+  const T* FR;
+  int ldr, pad;
   const int* piv_r;
   const int* piv_c;
   const T* M;
@@ -206,6 +211,63 @@ struct VecGatherDesc {    // t(0:nf, :) = xn(upd, :)
   int nf, ldt;
 };
 
+// ---- sampled extend-add (Sec. 4.2.1, Eq. HODLR_EA_Expand, Fig. HODLR_EA) ----
+// A HODLR front is not staged densely: only the entries its compression and
+// factorisation read are formed, each as F_bar_p (A's entries in the pivot
+// rows and columns) plus every child's update at the mapped position.
+//
+// Node of a HODLR child's F_ff^HODLR cluster tree: positions in the child's
+// update set; an internal node holds its lower off-diagonal block (rows in
+// the right child, columns in the left) as U V^T, a leaf its dense block.
+struct FfNode {
+  int off, size, left, right;   // left < 0: leaf
+  int rank;
+  const void* U;    // internal: right.size x rank (ld right.size); leaf: size x size (ld size)
+  const void* V;    // internal: left.size x rank (ld left.size)
+};
+// A child's update U_c (nf x nf, symmetric) as a parent's gather sees it:
+// dense staging (lower triangle at rows / columns npc..), or compressed,
+// U_c = F_ff^HODLR - Wt W^T with Wt = W S (Eq. update_HODLR).
+template <typename T>
+struct ChildUpd {
+  const int* inv;   // parent position -> index in the child's update set (-1: none)
+  int dense;
+  const T* F;       // dense child
+  int ld, npc;
+  const FfNode* nodes;   // compressed child: ff cluster tree, root first
+  const T* W;       // nf x rtop (bfloat16 bit patterns when wbf)
+  const T* Wt;      // nf x rtop
+  int nf, rtop, wbf;
+};
+template <typename T>
+struct GatherFront {
+  int start, npiv, nhat;
+  const int* upd;   // I_p^f as new indices
+  int nchild;
+  ChildUpd<T> ch[2];
+};
+// out(r, c) = F_p(rows[r], cols[c]), r < nr, c < nc (front positions; a null
+// list is the range r0.. / c0..); one workgroup per 256 entries from tile0
+template <typename T>
+struct GatherDesc {
+  const int* rows;
+  const int* cols;
+  T* out;
+  int r0, c0, nr, nc, ldo;
+  int front;
+  int tile0;
+};
+// dense parent, compressed child: parent(relmap[a], relmap[b]) += U_c(a, b)
+// for a >= b (lower triangle; one workgroup per 64 x 64 tile)
+template <typename T>
+struct ExtAddCDesc {
+  ChildUpd<T> c;
+  T* parent;
+  const int* relmap;
+  int ldp, nfc;
+  int tile0, tiles_r;
+};
+
 // ---- launchers (all asynchronous on `st`; descriptor arrays are device) ----
 // MFMA accumulator layout probe (one wave, 64 x 4 entries per output)
 template <typename T>
@@ -274,6 +336,13 @@ hipError_t launch_phase2_coop(const Phase2CoopDesc<T>* d, int ndesc, int wgs, si
                               double eps, int* status, long long wait_ticks, hipStream_t st);
 template <typename T>
 void launch_extadd(const ExtAddDesc<T>* d, int ndesc, int tiles, hipStream_t st);
+// sampled extend-add: every GatherDesc entry; rowptr/colind/vals are A in
+// the original order and perm maps new indices to original ones
+template <typename T>
+void launch_gather(const GatherDesc<T>* d, int ndesc, int tiles, const GatherFront<T>* fronts, const int* rowptr,
+                   const int* colind, const double* vals, const int* perm, hipStream_t st);
+template <typename T>
+void launch_extadd_c(const ExtAddCDesc<T>* d, int ndesc, int tiles, hipStream_t st);
 template <typename S, typename D>
 void launch_copy(const CopyDesc<S, D>* d, int ndesc, int tiles, hipStream_t st);
 template <typename T>

@@ -850,7 +850,7 @@ __global__ __launch_bounds__(kSkelFacThreads) void skelfac_kernel(const SkelFacD
       T v = 0;
       if (wave == 0 && valid && c < nb)
         v = upart ? d.F[(d.r0 + row) + (size_t)d.piv_c[k0 + c] * d.ld]
-                  : d.F[d.piv_r[k0 + c] + (size_t)(d.c0 + row) * d.ld];
+                  : d.FR[d.piv_r[k0 + c] + (size_t)(d.c0 + row) * d.ldr];
       acc[c] = v;
     }
     __syncthreads();
@@ -1214,6 +1214,88 @@ __global__ __launch_bounds__(256) void extadd_kernel(const ExtAddDesc<T>* __rest
 }
 
 // ----------------------------------------------------------------- copy ----
+// ----------------------------------------------- sampled extend-add -------
+// Entry (a, b) of a child's update (symmetric, so any order of a and b).
+template <typename T>
+__device__ T child_update(const ChildUpd<T>& c, int a, int b) {
+  if (c.dense) {
+    const int i = max(a, b), j = min(a, b);
+    return c.F[(c.npc + i) + (size_t)(c.npc + j) * c.ld];
+  }
+  T v = 0;
+  int nd = 0;
+  for (;;) {   // the cluster-tree node where a and b part, or their leaf
+    const FfNode n = c.nodes[nd];
+    if (n.left < 0) {
+      v = static_cast<const T*>(n.U)[(a - n.off) + (size_t)(b - n.off) * n.size];
+      break;
+    }
+    const FfNode l = c.nodes[n.left], r = c.nodes[n.right];
+    const bool al = a < l.off + l.size, bl = b < l.off + l.size;
+    if (al == bl) {
+      nd = al ? n.left : n.right;
+      continue;
+    }
+    const int ri = (al ? b : a) - r.off, ci = (al ? a : b) - l.off;   // row in the right child, column in the left
+    const T* U = static_cast<const T*>(n.U);
+    const T* V = static_cast<const T*>(n.V);
+    for (int k = 0; k < n.rank; ++k) v += U[ri + (size_t)k * r.size] * V[ci + (size_t)k * l.size];
+    break;
+  }
+  T s = 0;
+  for (int k = 0; k < c.rtop; ++k) s += c.Wt[a + (size_t)k * c.nf] * load_op(c.W, b + (size_t)k * c.nf, c.wbf != 0);
+  return v - s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void gather_kernel(const GatherDesc<T>* __restrict__ descs, int ndesc,
+                                                     const GatherFront<T>* __restrict__ fronts,
+                                                     const int* __restrict__ rowptr, const int* __restrict__ colind,
+                                                     const double* __restrict__ vals, const int* __restrict__ perm) {
+  const int di = find_desc_wg(descs, ndesc, (int)blockIdx.x);
+  const GatherDesc<T>& d = descs[di];
+  const int64_t e = (int64_t)((int)blockIdx.x - d.tile0) * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)d.nr * d.nc) return;
+  const int rr = (int)(e % d.nr), cc = (int)(e / d.nr);
+  const int i = d.rows ? d.rows[rr] : d.r0 + rr;
+  const int j = d.cols ? d.cols[cc] : d.c0 + cc;
+  const GatherFront<T>& f = fronts[d.front];
+  T v = 0;
+  if (i < f.npiv || j < f.npiv) {   // F_bar_p: A's entries in the pivot rows and columns
+    const int gi = i < f.npiv ? f.start + i : f.upd[i - f.npiv];
+    const int gj = j < f.npiv ? f.start + j : f.upd[j - f.npiv];
+    const int row = perm[gi], col = perm[gj];
+    int lo = rowptr[row], hi = rowptr[row + 1];
+    const int end = hi;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (colind[mid] < col) lo = mid + 1;
+      else hi = mid;
+    }
+    if (lo < end && colind[lo] == col) v = (T)vals[lo];
+  }
+  for (int c = 0; c < f.nchild; ++c) {
+    const ChildUpd<T>& u = f.ch[c];
+    const int a = u.inv[i], b = u.inv[j];
+    if (a >= 0 && b >= 0) v += child_update(u, a, b);
+  }
+  d.out[rr + (size_t)cc * d.ldo] = v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void extadd_c_kernel(const ExtAddCDesc<T>* __restrict__ descs, int ndesc) {
+  const int di = find_desc_wg(descs, ndesc, (int)blockIdx.x);
+  const ExtAddCDesc<T>& d = descs[di];
+  const int lt = (int)blockIdx.x - d.tile0;
+  const int tr = lt % d.tiles_r, tc = lt / d.tiles_r;
+  if (tc > tr) return;
+  for (int e = threadIdx.x; e < kTile * kTile; e += blockDim.x) {
+    const int a = tr * kTile + (e & 63), b = tc * kTile + (e >> 6);
+    if (a < d.nfc && b < d.nfc && a >= b)   // relmap increases: (a, b) lands in the parent's lower triangle
+      d.parent[d.relmap[a] + (size_t)d.relmap[b] * d.ldp] += child_update(d.c, a, b);
+  }
+}
+
 template <typename S, typename D>
 __global__ __launch_bounds__(256) void copy_kernel(const CopyDesc<S, D>* __restrict__ descs, int ndesc) {
   const int di = find_desc_wg(descs, ndesc, (int)blockIdx.x);
@@ -1867,6 +1949,17 @@ hipError_t launch_phase2_coop(const Phase2CoopDesc<T>* d, int ndesc, int wgs, si
   return e;
 }
 template <typename T>
+void launch_gather(const GatherDesc<T>* d, int ndesc, int tiles, const GatherFront<T>* fronts, const int* rowptr,
+                   const int* colind, const double* vals, const int* perm, hipStream_t st) {
+  if (ndesc <= 0 || tiles <= 0) return;
+  MFH_LAUNCH(gather_kernel<T>, dim3(tiles), dim3(256), 0, st, d, ndesc, fronts, rowptr, colind, vals, perm);
+}
+template <typename T>
+void launch_extadd_c(const ExtAddCDesc<T>* d, int ndesc, int tiles, hipStream_t st) {
+  if (ndesc <= 0 || tiles <= 0) return;
+  MFH_LAUNCH(extadd_c_kernel<T>, dim3(tiles), dim3(256), 0, st, d, ndesc);
+}
+template <typename T>
 void launch_extadd(const ExtAddDesc<T>* d, int ndesc, int tiles, hipStream_t st) {
   if (ndesc <= 0 || tiles <= 0) return;
   MFH_LAUNCH(extadd_kernel<T>, dim3(tiles), dim3(256), 0, st, d, ndesc);
@@ -1986,6 +2079,9 @@ void launch_axpby(const double* a, const double* b, double* c, double alpha, dou
   template hipError_t launch_phase2_coop<T>(const Phase2CoopDesc<T>*, int, int, size_t, bool, double, int*, long long, \
                                             hipStream_t);                                         \
   template void launch_extadd<T>(const ExtAddDesc<T>*, int, int, hipStream_t);                   \
+  template void launch_extadd_c<T>(const ExtAddCDesc<T>*, int, int, hipStream_t);                 \
+  template void launch_gather<T>(const GatherDesc<T>*, int, int, const GatherFront<T>*, const int*, \
+                                 const int*, const double*, const int*, hipStream_t);              \
   template void launch_cap<T>(const CapDesc<T>*, int, hipStream_t);                              \
   template void launch_fill<T>(T*, int64_t, T, hipStream_t);                                     \
   template void launch_assemble<T>(T*, const int64_t*, const signed char*, const double*, int64_t, int, \

@@ -114,8 +114,12 @@ std::unique_ptr<NumericBase> make_numeric(const Symbolic& s, const double* vals,
 void set_phase2_wait_ticks(long long ticks);
 // message of the MF_EHIP a phase-2 barrier give-up ends the factorisation with
 constexpr const char* kPhase2WaitMsg = "phase-2 workgroups did not meet at their barrier";
+// Front workspace plan (elements): the staged fronts of one level share a
+// region that lives until the level of its last parent is done; regions are
+// placed first fit over offsets.  `staged` (null: every front) marks the
+// fronts that take dense staging.  Returns the peak.
 int64_t workspace_plan(const Symbolic& s, std::vector<int64_t>& reg_off, std::vector<int64_t>& reg_elems,
-                       std::vector<int64_t>& front_elem_off);
+                       std::vector<int64_t>& front_elem_off, const std::vector<char>* staged = nullptr);
 void estimate_bytes(const Symbolic& s, const mf_opts& o, int nrhs, int restart, int64_t& persistent,
                     int64_t& peak);
 

@@ -603,11 +603,8 @@ void timed_potrf(const PotrfDesc<T>* d, const std::vector<PotrfDesc<T>>& hv, int
 
 }  // namespace
 
-// Front workspace plan (elements): the fronts of one level share a region;
-// a region lives until the level of its last parent is done; regions are
-// placed first fit over offsets.  Returns the peak.
 int64_t workspace_plan(const Symbolic& s, std::vector<int64_t>& reg_off, std::vector<int64_t>& reg_elems,
-                       std::vector<int64_t>& front_elem_off) {
+                       std::vector<int64_t>& front_elem_off, const std::vector<char>* staged) {
   const int H = (int)s.levels.size();
   reg_off.assign(H, 0);
   reg_elems.assign(H, 0);
@@ -620,6 +617,7 @@ int64_t workspace_plan(const Symbolic& s, std::vector<int64_t>& reg_off, std::ve
     int end = h;
     for (int p : s.levels[h]) {
       front_elem_off[p] = tot;
+      if (staged && !(*staged)[p]) continue;   // never staged densely
       const int64_t nn = s.fronts[p].n();
       tot += (nn * nn + 63) & ~int64_t(63);
       const int par = s.fronts[p].parent;
@@ -688,9 +686,40 @@ class Numeric : public NumericBase {
     T* W = nullptr;           // HODLR: nf x r_top
     std::vector<T*> nodeU, nodeV, nodeK, leafInv;   // per pp-tree node
     std::vector<int> nodeR;   // rank per pp-tree node (internal)
+    // sampled extend-add: the compressed update a parent gathers from
+    const FfNode* ffnodes = nullptr;   // device: F_ff^HODLR cluster tree
+    T* Wt = nullptr;                    // W S (nf x r_top)
   };
   std::vector<FN> fn;
   Arena arena;
+  // sampled extend-add (Sec. 4.2.1): compressed fronts are not staged.  What
+  // a parent reads of a compressed child (its F_ff^HODLR tree and W S) is
+  // kept per child until the parent's level has been launched.
+  bool sampled = false;
+  std::vector<std::vector<std::unique_ptr<DevBuf>>> keep;   // by front
+  std::vector<int64_t> upd_off_;       // each front's I_p^f in d_upd
+  DevBuf scrS;                         // the level's gathered samples and pp leaf blocks
+  T* keep_alloc(int p, int64_t n) {
+    keep[p].push_back(std::make_unique<DevBuf>());
+    keep[p].back()->alloc((size_t)std::max<int64_t>(n, 1) * sizeof(T), &ms);
+    return keep[p].back()->template as<T>();
+  }
+  // a child's update as its parent's gather or extend-add reads it
+  ChildUpd<T> child_upd(int c, const int* inv) const {
+    const Front& fc = sym->fronts[c];
+    ChildUpd<T> u{};
+    u.inv = inv;
+    u.nf = fc.nf();
+    if (fn[c].F) {
+      u.dense = 1;
+      u.F = fn[c].F; u.ld = fn[c].ld; u.npc = fc.npiv;
+    } else {
+      u.nodes = fn[c].ffnodes;
+      u.W = fn[c].W; u.Wt = fn[c].Wt; u.rtop = fn[c].r_top;
+      u.wbf = (sizeof(T) == 4 && opts.uv_bf16) ? 1 : 0;
+    }
+    return u;
+  }
   DescPool dp;
   // n entries of a compressed basis: T, or bfloat16 (2 bytes each) when rounded
   T* base_alloc(int64_t n, bool bf16) {
@@ -796,6 +825,9 @@ Numeric<T>::Numeric(const Symbolic& s, const double* vals, const mf_opts& o) {
   const int n = s.n;
   const int nfr = (int)s.fronts.size();
   const bool hodlr = o.method == MF_METHOD_HODLR;
+  sampled = hodlr && o.sampled != 0;
+  if (sampled && o.adaptive != 0)
+    throw Err{MF_EINVAL, "sampled extend-add needs adaptive = 0 (the whole-block phase reads every entry)"};
 
   d_rowptr.alloc((n + 1) * sizeof(int), &ms);
   d_colind.alloc(s.nnz * sizeof(int), &ms);
@@ -829,6 +861,7 @@ Numeric<T>::Numeric(const Symbolic& s, const double* vals, const mf_opts& o) {
   launch_fill<int>(d_status.as<int>(), 1, 0, st);
 
   fn.resize(nfr);
+  keep.resize(nfr);
   for (int p = 0; p < nfr; ++p) {
     const Front& f = s.fronts[p];
     fn[p].dense = !hodlr || f.n() < o.n_c;
@@ -902,14 +935,18 @@ Numeric<T>::Numeric(const Symbolic& s, const double* vals, const mf_opts& o) {
   std::vector<int64_t> reg_off(H), reg_elems(H);
   std::vector<int64_t> front_elem_off(nfr);
   {
-    const int64_t peak = workspace_plan(s, reg_off, reg_elems, front_elem_off);
+    std::vector<char> staged(nfr, 1);
+    if (sampled)
+      for (int p = 0; p < nfr; ++p) staged[p] = fn[p].dense;   // compressed fronts: samples only
+    const int64_t peak = workspace_plan(s, reg_off, reg_elems, front_elem_off, &staged);
     ws.alloc(std::max<int64_t>(peak, 1) * sizeof(T), &ms);
     split.alloc(kSplitFactorBytes, &ms);
     info.workspace_bytes = peak * (int64_t)sizeof(T);
   }
   wsT = ws.as<T>();
   for (int h = 0; h < H; ++h)
-    for (int p : s.levels[h]) fn[p].F = wsT + reg_off[h] + front_elem_off[p];
+    for (int p : s.levels[h])
+      fn[p].F = (sampled && !fn[p].dense) ? nullptr : wsT + reg_off[h] + front_elem_off[p];
 
   // ---- assembly tables (A's entries are placed level by level on the
   // device: front of each index, the fronts' buffers and update sets) and the
@@ -922,13 +959,16 @@ Numeric<T>::Numeric(const Symbolic& s, const double* vals, const mf_opts& o) {
     int64_t nrm = 0;
     for (int p = 0; p < nfr; ++p) {
       const Front& f = s.fronts[p];
-      fr_h[p] = AsmFront{(int64_t)(fn[p].F - wsT), f.start, f.npiv, fn[p].ld, f.height, (int)upd_off[p],
-                         (int)f.upd.size()};
+      // a front that is never staged reads A's entries itself (height -1: not assembled)
+      const bool st_p = fn[p].F != nullptr;
+      fr_h[p] = AsmFront{st_p ? (int64_t)(fn[p].F - wsT) : 0, f.start, f.npiv, fn[p].ld, st_p ? f.height : -1,
+                         (int)upd_off[p], (int)f.upd.size()};
       upd_off[p + 1] = upd_off[p] + (int64_t)f.upd.size();
       relmap_off[p] = nrm;
       nrm += (int64_t)f.relmap.size();
     }
     const int64_t nupd = upd_off[nfr];
+    upd_off_ = upd_off;
     int* upd_h = dp.host<int>((size_t)std::max<int64_t>(nupd, 1));
     int* relmap_h = dp.host<int>((size_t)std::max<int64_t>(nrm, 1));
     parallel_for(nfr, 64, [&](int b, int e, int) {
@@ -968,13 +1008,25 @@ Numeric<T>::Numeric(const Symbolic& s, const double* vals, const mf_opts& o) {
     launch_assemble<T>(wsT, d_adest.as<int64_t>(), d_alvl.as<signed char>(), d_vals.as<double>(), s.nnz, h, st);
     for (int slot = 0; slot < 2; ++slot) {
       std::vector<ExtAddDesc<T>> ev;
-      int tiles = 0;
+      std::vector<ExtAddCDesc<T>> evc;   // compressed child into a staged parent
+      int tiles = 0, tiles_c = 0;
       for (int p : L) {
         const Front& f = s.fronts[p];
         if ((int)f.children.size() <= slot) continue;
         const int c = f.children[slot];
         const Front& fc = s.fronts[c];
-        if (fc.nf() == 0) continue;
+        if (fc.nf() == 0 || !fn[p].F) continue;   // an unstaged parent gathers its children itself
+        if (!fn[c].F) {
+          ExtAddCDesc<T> d{};
+          d.c = child_upd(c, nullptr);
+          d.parent = fn[p].F; d.relmap = d_relmap.as<int>() + relmap_off[c];
+          d.ldp = fn[p].ld; d.nfc = fc.nf();
+          d.tiles_r = cdiv(fc.nf(), kTile);
+          d.tile0 = tiles_c;
+          tiles_c += d.tiles_r * d.tiles_r;
+          evc.push_back(d);
+          continue;
+        }
         ExtAddDesc<T> d{};
         d.child = fn[c].F; d.parent = fn[p].F; d.relmap = d_relmap.as<int>() + relmap_off[c];
         d.ldc = fn[c].ld; d.npc = fc.npiv; d.nfc = fc.nf(); d.ldp = fn[p].ld;
@@ -993,11 +1045,25 @@ Numeric<T>::Numeric(const Symbolic& s, const double* vals, const mf_opts& o) {
         launch_extadd<T>(reinterpret_cast<const ExtAddDesc<T>*>(base + off), (int)ev.size(), tiles, st);
         prof_end(id, st);
       }
+      if (!evc.empty()) {
+        Blob b;
+        size_t off = b.add(evc);
+        char* base = dp.upload(b, st);
+        launch_extadd_c<T>(reinterpret_cast<const ExtAddCDesc<T>*>(base + off), (int)evc.size(), tiles_c, st);
+      }
     }
     std::vector<int> D, Hf;
     for (int p : L) (fn[p].dense ? D : Hf).push_back(p);
     dense_level(D);
     hodlr_level(Hf, h);
+    // the children's kept updates have been read by this level's launches;
+    // released at the next synchronisation
+    if (sampled)
+      for (int p : L)
+        for (int c : s.fronts[p].children) {
+          for (auto& kb : keep[c]) retired.push_back(std::move(kb));
+          keep[c].clear();
+        }
   }
   int* hstat = dp.host<int>(1);
   HIPCHK(hipMemcpyAsync(hstat, d_status.p, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -1010,6 +1076,8 @@ Numeric<T>::Numeric(const Symbolic& s, const double* vals, const mf_opts& o) {
   ws.release();
   scrA.release();
   scrB.release();
+  scrS.release();
+  keep.clear();
   split.release();
   d_owner.release();
   d_asmfr.release();
@@ -1298,6 +1366,146 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
       x.cand = reinterpret_cast<T*>(take((size_t)2 * x.nwg * B.nr * sizeof(T)));
     }
   }
+  // ---- sampled extend-add (Sec. 4.2.1): the level's fronts are never
+  // assembled.  What the compression reads of a block (the whole block when
+  // it fits the register kernel, else B(I,J), B(:,J) and B(I,:)) and the
+  // diagonal leaf blocks of both cluster trees are gathered from A and the
+  // children's updates.
+  struct Smp { const T* F; const T* C; const T* R; const int* I; const int* J; int ld; };
+  std::vector<Smp> smp;
+  std::map<int, std::vector<T*>> ppleaf, ffleaf;   // front -> leaf block per tree node
+  if (sampled) {
+    size_t tneed = 0;
+    for (auto& x : br) {
+      const Block& B = s.fronts[x.p].blocks[x.bi];
+      tneed += x.full ? al((size_t)B.nr * B.nc * sizeof(T))
+                      : al((size_t)x.nI * x.nJ * sizeof(T)) + al((size_t)B.nr * x.nJ * sizeof(T)) +
+                            al((size_t)x.nI * B.nc * sizeof(T));
+    }
+    for (int p : Hs)
+      for (const TreeNode& t : s.fronts[p].pp_tree)
+        if (t.left < 0) tneed += al((size_t)t.size * t.size * sizeof(T));
+    scrS.grow(std::max<size_t>(tneed, 256), &ms, retired);
+    char* sc = static_cast<char*>(scrS.p);
+    auto stake = [&](size_t elems) { T* r = reinterpret_cast<T*>(sc); sc += al(elems * sizeof(T)); return r; };
+    // index lists: block-local I and J (whole-block mode), 0, 1, 2, ... (the
+    // sample buffers), and each child's map from parent positions to its update set
+    std::vector<int> loc;
+    std::vector<size_t> locI(nb, 0), locJ(nb, 0);
+    int iota_n = 1;
+    for (int i = 0; i < nb; ++i) {
+      const BR& x = br[i];
+      const Block& B = s.fronts[x.p].blocks[x.bi];
+      if (!x.full) {
+        iota_n = std::max({iota_n, x.nI, x.nJ});
+        continue;
+      }
+      locI[i] = loc.size();
+      for (int k = bIptr[x.lk]; k < bIptr[x.lk + 1]; ++k) loc.push_back(lb.I[k] - B.r0);
+      locJ[i] = loc.size();
+      for (int k = bJptr[x.lk]; k < bJptr[x.lk + 1]; ++k) loc.push_back(lb.J[k] - B.c0);
+    }
+    const size_t iota0 = loc.size();
+    for (int k = 0; k < iota_n; ++k) loc.push_back(k);
+    std::vector<int> inv;
+    std::map<int, size_t> inv_off;
+    for (int p : Hs) {
+      const Front& f = s.fronts[p];
+      if (f.children.size() > 2) throw Err{MF_EINVAL, "a front with more than two children"};
+      for (int c : f.children) {
+        const Front& fc = s.fronts[c];
+        if (fc.nf() == 0) continue;
+        const size_t o = inv.size();
+        inv_off[c] = o;
+        inv.resize(o + f.n(), -1);
+        for (int a = 0; a < fc.nf(); ++a) inv[o + fc.relmap[a]] = a;
+      }
+    }
+    Blob bi;
+    const size_t oloc = bi.add(loc), oinv = bi.add(inv);
+    const char* ib = dp.upload(bi, st);
+    const int* dloc = reinterpret_cast<const int*>(ib + oloc);
+    const int* dinv = reinterpret_cast<const int*>(ib + oinv);
+    std::vector<GatherFront<T>> gf;
+    std::map<int, int> gfi;
+    for (int p : Hs) {
+      const Front& f = s.fronts[p];
+      GatherFront<T> g{};
+      g.start = f.start; g.npiv = f.npiv; g.nhat = f.n();
+      g.upd = d_upd.as<int>() + upd_off_[p];
+      for (int c : f.children)
+        if (s.fronts[c].nf() > 0) g.ch[g.nchild++] = child_upd(c, dinv + inv_off.at(c));
+      gfi[p] = (int)gf.size();
+      gf.push_back(g);
+    }
+    std::vector<GatherDesc<T>> gdv;
+    int64_t gtiles = 0;
+    auto gat = [&](int p, const int* rows, int r0, int nr, const int* cols, int c0, int nc, T* out, int ldo) {
+      if (nr <= 0 || nc <= 0) return;
+      GatherDesc<T> d{};
+      d.rows = rows; d.cols = cols; d.out = out;
+      d.r0 = r0; d.c0 = c0; d.nr = nr; d.nc = nc; d.ldo = ldo;
+      d.front = gfi.at(p);
+      d.tile0 = (int)gtiles;
+      gtiles += ((int64_t)nr * nc + 255) / 256;
+      gdv.push_back(d);
+    };
+    smp.resize(nb);
+    for (int i = 0; i < nb; ++i) {
+      const BR& x = br[i];
+      const Block& B = s.fronts[x.p].blocks[x.bi];
+      if (x.full) {
+        T* R = stake((size_t)B.nr * B.nc);
+        gat(x.p, nullptr, B.r0, B.nr, nullptr, B.c0, B.nc, R, B.nr);
+        smp[i] = Smp{R, nullptr, nullptr, dloc + locI[i], dloc + locJ[i], B.nr};
+        continue;
+      }
+      const int* Ib = dI + bIptr[x.lk];
+      const int* Jb = dJ + bJptr[x.lk];
+      T* Bh = stake((size_t)x.nI * x.nJ);
+      T* C = stake((size_t)B.nr * x.nJ);
+      T* R = stake((size_t)x.nI * B.nc);
+      gat(x.p, Ib, 0, x.nI, Jb, 0, x.nJ, Bh, std::max(x.nI, 1));
+      gat(x.p, nullptr, B.r0, B.nr, Jb, 0, x.nJ, C, B.nr);
+      gat(x.p, Ib, 0, x.nI, nullptr, B.c0, B.nc, R, std::max(x.nI, 1));
+      smp[i] = Smp{Bh, C, R, dloc + iota0, dloc + iota0, std::max(x.nI, 1)};
+    }
+    for (int p : Hs) {
+      const Front& f = s.fronts[p];
+      auto& pl = ppleaf[p];
+      pl.assign(f.pp_tree.size(), nullptr);
+      for (size_t k = 0; k < f.pp_tree.size(); ++k) {
+        const TreeNode& t = f.pp_tree[k];
+        if (t.left >= 0) continue;
+        pl[k] = stake((size_t)t.size * t.size);
+        gat(p, nullptr, t.off, t.size, nullptr, t.off, t.size, pl[k], t.size);
+      }
+      // F_ff^HODLR's leaf blocks are kept whole: they are the parent's to read
+      int64_t fl_tot = 0;
+      for (const TreeNode& t : f.ff_tree)
+        if (t.left < 0) fl_tot += (int64_t)t.size * t.size;
+      auto& fl = ffleaf[p];
+      fl.assign(f.ff_tree.size(), nullptr);
+      if (fl_tot == 0) continue;
+      T* kp = keep_alloc(p, fl_tot);
+      for (size_t k = 0; k < f.ff_tree.size(); ++k) {
+        const TreeNode& t = f.ff_tree[k];
+        if (t.left >= 0) continue;
+        fl[k] = kp;
+        kp += (int64_t)t.size * t.size;
+        gat(p, nullptr, t.off, t.size, nullptr, t.off, t.size, fl[k], t.size);
+      }
+    }
+    if (gtiles > INT32_MAX) throw Err{MF_EINVAL, "level too large for one gather launch"};
+    if (!gdv.empty()) {
+      Blob bg;
+      const size_t ogf = bg.add(gf), ogd = bg.add(gdv);
+      const char* gb = dp.upload(bg, st);
+      launch_gather<T>(reinterpret_cast<const GatherDesc<T>*>(gb + ogd), (int)gdv.size(), (int)gtiles,
+                       reinterpret_cast<const GatherFront<T>*>(gb + ogf), d_rowptr.as<int>(), d_colind.as<int>(),
+                       d_vals.as<double>(), d_perm.as<int>(), st);
+    }
+  }
   Blob b;
   std::vector<SkRegDesc<T>> skf, skh;
   std::vector<SkelFacDesc<T>> sf;
@@ -1312,6 +1520,11 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
     d.F = fx.F; d.ld = fx.ld; d.r0 = B.r0; d.nr = B.nr; d.c0 = B.c0; d.nc = B.nc;
     d.I = dI + bIptr[x.lk]; d.nI = x.nI;
     d.J = dJ + bJptr[x.lk]; d.nJ = x.nJ;
+    const Smp* sm = sampled ? &smp[&x - br.data()] : nullptr;
+    if (sm) {   // the whole block, or B_hat with I and J numbered 0, 1, ...
+      d.F = sm->F; d.ld = sm->ld; d.r0 = 0; d.c0 = 0;
+      d.I = sm->I; d.J = sm->J;
+    }
     d.piv_r = x.pr; d.piv_c = x.pc;
     d.rank1 = x.rank1; d.rank = x.rank; d.u11 = x.u11; d.cap = x.capr;
     if (x.full) {
@@ -1325,7 +1538,11 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
     skh.push_back(d);
     rmax1 = std::max(rmax1, x.kcap);
     SkelFacDesc<T> f{};
-    f.F = fx.F; f.ld = fx.ld; f.r0 = B.r0; f.nr = B.nr; f.c0 = B.c0; f.nc = B.nc;
+    f.F = fx.F; f.ld = fx.ld; f.FR = fx.F; f.ldr = fx.ld; f.r0 = B.r0; f.nr = B.nr; f.c0 = B.c0; f.nc = B.nc;
+    if (sm) {   // B(:, J) and B(I, :); pivots index the lists I and J
+      f.F = sm->C; f.ld = B.nr; f.r0 = 0;
+      f.FR = sm->R; f.ldr = sm->ld; f.c0 = 0;
+    }
     f.piv_r = x.pr; f.piv_c = x.pc; f.M = x.M; f.ldm = std::max(x.kcap, 1); f.rank = x.rank1;
     f.U = x.U; f.ldu = B.nr; f.V = x.V; f.ldv = B.nc;
     f.wgU = cdiv(B.nr, kSkelFacRows);
@@ -1570,7 +1787,9 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
       if (t.left < 0) {
         x.leafInv[i] = arena.alloc_n<T>((int64_t)t.size * t.size);
         PotrfDesc<T> d{};
-        d.A = x.F + t.off + (int64_t)t.off * x.ld; d.lda = x.ld; d.n = t.size;
+        if (sampled) { d.A = ppleaf.at(p)[i]; d.lda = t.size; }
+        else { d.A = x.F + t.off + (int64_t)t.off * x.ld; d.lda = x.ld; }
+        d.n = t.size;
         d.Inv = x.leafInv[i]; d.ldi = t.size;
         leaves.push_back(d);
         continue;
@@ -1748,8 +1967,9 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
       const Front& f = s.fronts[p];
       FN& x = fn[p];
       const int npv = f.npiv, nf = f.nf();
-      // F_ff off-diagonal blocks <- U V^T (compressed form, written densely for the parent)
-      for (int bi = 0; bi < (int)f.blocks.size(); ++bi) {
+      // F_ff off-diagonal blocks <- U V^T (compressed form, written densely for
+      // the parent; a sampled front keeps U and V instead)
+      for (int bi = 0; bi < (int)f.blocks.size() && !sampled; ++bi) {
         const Block& B = f.blocks[bi];
         if (B.kind != 2) continue;
         const BR& bb = br[bidx[{p, bi}]];
@@ -1765,13 +1985,15 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
       double* Wt64 = reinterpret_cast<double*>(tk((size_t)nf * r * 8));
       double* S64 = reinterpret_cast<double*>(tk((size_t)r * r * 8));
       T* Wt = reinterpret_cast<T*>(tk((size_t)nf * r * sizeof(T)));
+      if (sampled) x.Wt = Wt = keep_alloc(p, (int64_t)nf * r);
       c64.v.push_back(cd<T, double>(tb.V, npv, V64, npv, npv, r));
       c64.v.push_back(cd<T, double>(x.G, npv, X64, npv, npv, r));
       c64.v.push_back(cd<T, double>(tb.U, nf, W64, nf, nf, r));
       gS.v.push_back(gd<double>(V64, npv, 1, X64, npv, 0, S64, r, r, r, npv, 1.0, 0.0));       // S = V^T X
       gWt.v.push_back(gd<double>(W64, nf, 0, S64, r, 0, Wt64, nf, nf, r, r, 1.0, 0.0));        // W S
       cW.v.push_back(cd<double, T>(Wt64, nf, Wt, nf, nf, r));
-      gup.v.push_back(gd<T>(Wt, nf, 0, tb.U, nf, 1, x.F + npv + (int64_t)npv * x.ld, x.ld, nf, nf, r, -1.0, 1.0,
+      if (!sampled)
+        gup.v.push_back(gd<T>(Wt, nf, 0, tb.U, nf, 1, x.F + npv + (int64_t)npv * x.ld, x.ld, nf, nf, r, -1.0, 1.0,
                             GF_LOWER_C));
     }
     c64.stage(b4);
@@ -1788,6 +2010,51 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
     gff.launch(base4, st);
     gup.launch(base4, st);
   }
+  if (!sampled) return;
+  // ---- what the parents read of a sampled front: F_ff^HODLR as its cluster
+  // tree (leaf blocks gathered above, each internal node's U and V), root first
+  Blob b5;
+  CopyBatch<T, T> kc;
+  std::vector<FfNode> nodes;
+  std::vector<std::pair<int, size_t>> first;
+  for (int p : Hs) {
+    const Front& f = s.fronts[p];
+    if (f.ff_tree.empty()) continue;
+    int64_t tot = 0;
+    for (const TreeNode& t : f.ff_tree)
+      if (t.left >= 0) tot += (int64_t)t.size * hr[bidx.at({p, t.block})];
+    T* kp = tot > 0 ? keep_alloc(p, tot) : nullptr;
+    first.push_back({p, nodes.size()});
+    for (size_t k = 0; k < f.ff_tree.size(); ++k) {
+      const TreeNode& t = f.ff_tree[k];
+      FfNode nd{};
+      nd.off = t.off - f.npiv; nd.size = t.size; nd.left = t.left; nd.right = t.right;
+      if (t.left < 0) {
+        nd.U = ffleaf.at(p)[k];
+      } else {
+        const BR& bb = br[bidx.at({p, t.block})];
+        const int r = hr[bidx.at({p, t.block})];
+        const TreeNode& a = f.ff_tree[t.left];
+        const TreeNode& be = f.ff_tree[t.right];
+        nd.rank = r;
+        if (r > 0) {   // U: rows in the right child; V: rows in the left child
+          T* U = kp;
+          T* V = kp + (int64_t)be.size * r;
+          kp += (int64_t)t.size * r;
+          kc.v.push_back(cd<T, T>(bb.U, be.size, U, be.size, be.size, r));
+          kc.v.push_back(cd<T, T>(bb.V, a.size, V, a.size, a.size, r));
+          nd.U = U;
+          nd.V = V;
+        }
+      }
+      nodes.push_back(nd);
+    }
+  }
+  const size_t on = b5.add(nodes);
+  kc.stage(b5);
+  const char* base5 = dp.upload(b5, st);
+  kc.launch(base5, st);
+  for (auto& w : first) fn[w.first].ffnodes = reinterpret_cast<const FfNode*>(base5 + on) + w.second;
 }
 
 // ================================================================ apply ====
@@ -2457,8 +2724,15 @@ void estimate_bytes(const Symbolic& s, const mf_opts& o, int nrhs, int restart, 
   const double es = o.precision == MF_FP64 ? 8.0 : 4.0;
   const double eb = (o.precision == MF_FP32 && o.uv_bf16) ? 2.0 : es;   // stored bases U, V, W
   const bool hodlr = o.method == MF_METHOD_HODLR;
+  const bool sampled = hodlr && o.sampled != 0;
   std::vector<int64_t> ro, re, fo;
-  const double ws = (double)workspace_plan(s, ro, re, fo) * es;
+  std::vector<char> staged(s.fronts.size(), 1);
+  if (sampled)
+    for (size_t p = 0; p < s.fronts.size(); ++p) staged[p] = s.fronts[p].n() < o.n_c;
+  const double ws = (double)workspace_plan(s, ro, re, fo, &staged) * es;
+  // sampled: a level's gathered samples, and the compressed updates kept for
+  // the parents (ff leaf blocks, ff bases, W S) while the next level runs
+  std::vector<double> lvl_samples(s.levels.size(), 0.0), lvl_kept(s.levels.size(), 0.0);
   const double csr = 12.0 * s.nnz + 4.0 * (s.n + 1) + 8.0 * s.n;
   double fac = 0, scratch = 0, apply = 0;
   std::vector<double> lvl_scratch(s.levels.size(), 0.0);
@@ -2484,17 +2758,34 @@ void estimate_bytes(const Symbolic& s, const mf_opts& o, int nrhs, int restart, 
         apply += 4.0 * r * nrhs * es;
       }
       lvl_scratch[f.height] += (B.nr + B.nc) * std::min((double)o.rank_cap, (double)std::min(B.nr, B.nc)) * es;
+      if (sampled) {
+        const double cap = o.bdlr_cap > 0 ? o.bdlr_cap : (es == 8.0 ? 128.0 : 192.0);   // BDLR set bound
+        const double nI = std::min((double)B.nr, cap), nJ = std::min((double)B.nc, cap);
+        const bool full = B.nr <= 256 && B.nc <= 256;
+        lvl_samples[f.height] += (full ? (double)B.nr * B.nc : B.nr * nJ + nI * B.nc + nI * nJ) * es;
+        if (B.kind == 2) lvl_kept[f.height] += (B.nr + B.nc) * r * es;
+        if (B.kind == 0) lvl_kept[f.height] += B.nr * r * es;
+      }
     }
     for (const TreeNode& t : f.pp_tree)
-      if (t.left < 0) fac += (double)t.size * t.size * es;    // leaf inverses
+      if (t.left < 0) {
+        fac += (double)t.size * t.size * es;                  // leaf inverses
+        if (sampled) lvl_samples[f.height] += (double)t.size * t.size * es;
+      }
+    if (sampled)
+      for (const TreeNode& t : f.ff_tree)
+        if (t.left < 0) lvl_kept[f.height] += (double)t.size * t.size * es;
     fac += np * (rtop + w) * es + nf * rtop * eb;             // G (X and the SMW columns), W
     apply += rtop * nrhs * es;
   }
   for (double v : lvl_scratch) scratch = std::max(scratch, v);
+  double samples = 0;
+  for (size_t h = 0; h < s.levels.size(); ++h)
+    samples = std::max(samples, lvl_samples[h] + lvl_kept[h] + (h > 0 ? lvl_kept[h - 1] : 0.0));
   const double gm = 8.0 * s.n * nrhs * (2.0 * restart + 3.0);
   const double fixed = (double)kSplitFactorBytes + (64 << 20);   // split-K partials, one descriptor chunk
   persistent = (int64_t)(fac + csr + apply + gm + kSplitPlanBytes);
-  peak = (int64_t)(ws + fac + csr + scratch + fixed + 16.0 * s.nnz);
+  peak = (int64_t)(ws + fac + csr + scratch + samples + fixed + 16.0 * s.nnz);
 }
 
 void set_phase2_wait_ticks(long long ticks) { g_phase2_wait_override.store(ticks); }

@@ -96,7 +96,7 @@ mf_status skel_t(void* F, int ld, int r0, int nr, int c0, int nc, const int* I, 
   sd.U = static_cast<T*>(U); sd.ldu = nr; sd.V = static_cast<T*>(V); sd.ldv = nc;
   sd.M = M; sd.ldm = kcap > 0 ? kcap : 1;
   mfh::SkelFacDesc<T> fd{};
-  fd.F = static_cast<T*>(F); fd.ld = ld; fd.r0 = r0; fd.nr = nr; fd.c0 = c0; fd.nc = nc;
+  fd.F = static_cast<T*>(F); fd.ld = ld; fd.FR = fd.F; fd.ldr = ld; fd.r0 = r0; fd.nr = nr; fd.c0 = c0; fd.nc = nc;
   fd.piv_r = pr; fd.piv_c = pc; fd.M = M; fd.ldm = sd.ldm; fd.rank = rank1;
   fd.U = static_cast<T*>(U); fd.ldu = nr; fd.V = static_cast<T*>(V); fd.ldv = nc;
   fd.wgU = (nr + mfh::kSkelFacRows - 1) / mfh::kSkelFacRows; fd.wg0 = 0;

@@ -205,3 +205,20 @@ def test_estimate_bytes_dense_part_is_exact():
     assert delta >= 8 * n * 63 and delta < 8 * n * 63 + 8 * sum(f.n + f.npiv for f in ref.fronts) + 1
     eh = mfh.estimate_bytes(sym, nrhs=1, restart=30, method="hodlr", precision="fp32", n_c=64)
     assert 0 < eh["persistent_bytes"] and 0 < eh["peak_bytes"]
+
+
+def test_estimate_bytes_sampled_drops_compressed_fronts():
+    """Sampled extend-add: the compressed fronts leave the front workspace, so
+    the estimated peak falls, while the persistent factor is the same."""
+    import paper_1410_2697_amd as mfh
+    from mfinputs import q1_grid
+    p = q1_grid(24, 3)
+    sym = mfh.Symbolic.from_csr(p.A, p.coords, 64)
+    kw = dict(nrhs=1, restart=30, method="hodlr", precision="fp32", n_c=0, adaptive=0)
+    ea = mfh.estimate_bytes(sym, sampled=0, **kw)
+    es = mfh.estimate_bytes(sym, sampled=1, **kw)
+    assert es["persistent_bytes"] == ea["persistent_bytes"]
+    assert es["peak_bytes"] < ea["peak_bytes"]
+    ref = symbolic.analyze(p.A, p.coords, 64)
+    largest_front = max(f.n * f.n for f in ref.fronts) * 4
+    assert ea["peak_bytes"] - es["peak_bytes"] > largest_front / 2
