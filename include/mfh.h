@@ -116,7 +116,8 @@ typedef struct {
   int32_t rank_max;
   int32_t dense_fronts;       /* fronts factored densely                                             */
   int32_t hodlr_fronts;
-  int32_t status_bits;        /* device status word (1: non-positive pivot, 2: rank capacity)        */
+  int32_t status_bits;        /* device status word (1: non-positive pivot, 2: rank capacity,
+                                 4: singular capacitance, 16: non-finite block entry)                */
   double factor_seconds;      /* wall time of mf_factor (host clock, synchronised)                   */
   int64_t resident_bytes;     /* device bytes the handle holds now: factor, copy of A, apply and
                                  GMRES workspaces                                                    */

@@ -43,7 +43,8 @@ mf_status mfh_test_potrf(int32_t precision, int32_t n, void* A, int32_t lda, voi
  * than one workgroup's registers and a column slice fits LDS; 2 = as 1 but
  * with one workgroup streaming the block; 3 = as 1 with workgroups of at
  * most 4 columns updating the block in place.  The block of F may be
- * overwritten by a residual.  *rank_out receives the final rank. */
+ * overwritten by a residual.  *rank_out receives the final rank.  Returns
+ * MF_ENOTSPD when a chosen pivot is not finite (the kernels stop there). */
 mf_status mfh_test_skeleton(int32_t precision, void* F, int32_t ld, int32_t r0, int32_t nr, int32_t c0,
                             int32_t nc, const int32_t* I, int32_t nI, const int32_t* J, int32_t nJ, double eps,
                             int32_t adaptive, int32_t cap, void* U, void* V, int32_t* rank_out);

@@ -6,6 +6,7 @@
 #include "prof.h"
 
 #include <climits>
+#include <limits>
 #include <mutex>
 
 namespace mfh {
@@ -539,8 +540,10 @@ __global__ __launch_bounds__(NT) void skreg_kernel(const SkRegDesc<T>* __restric
   const int g = (int)uniform((unsigned)(t >> 6));
   const int M = FULL ? d.nr : d.nI, N = FULL ? d.nc : d.nJ;
   // B_hat mode: a pivot column is zeroed in e once its step is done (so the
-  // search and the update need no column mask) and kept in m: the
-  // multipliers in rows that were live, the U entries in the others
+  // update leaves it alone) and kept in m: the multipliers in rows that were
+  // live, the U entries in the others.  The search still masks finished
+  // columns: a multiplier that is not finite turns a zeroed entry into NaN
+  // (NaN times 0), and such a column must not be chosen twice.
   row_t e[RI], m[FULL ? 1 : RI];
   unsigned rl = 0, cl = 0, inI = 0, inJ = 0;
 #pragma unroll
@@ -631,7 +634,7 @@ __global__ __launch_bounds__(NT) void skreg_kernel(const SkRegDesc<T>* __restric
         unsigned bk = 0;
 #pragma unroll
         for (int j = 0; j < CJ; ++j) {
-          if (FULL && !((csel >> j) & 1u)) continue;
+          if (!((csel >> j) & 1u)) continue;
 #pragma unroll
           for (int i = 0; i < RI; ++i) {
             const unsigned w = (__float_as_uint(e[i][j]) & rm[i]) | (unsigned)(127 - (j * RI + i));
@@ -646,7 +649,7 @@ __global__ __launch_bounds__(NT) void skreg_kernel(const SkRegDesc<T>* __restric
         unsigned bq = 0, bl = 0;
 #pragma unroll
         for (int j = 0; j < CJ; ++j) {
-          if (FULL && !((csel >> j) & 1u)) continue;
+          if (!((csel >> j) & 1u)) continue;
 #pragma unroll
           for (int i = 0; i < RI; ++i) {
             const unsigned x = (unsigned)((u64)__double_as_longlong(e[i][j]) >> 32) & rm[i];
@@ -686,6 +689,11 @@ __global__ __launch_bounds__(NT) void skreg_kernel(const SkRegDesc<T>* __restric
       T c[RI];
 #pragma unroll
       for (int i = 0; i < RI; ++i) c[i] = cc[lane + 64 * i];
+      if (!(fabs(piv) <= std::numeric_limits<T>::max())) {   // Inf or NaN: the front broke down
+        if (t == 0) atomicOr(status, 16);
+        capped = true;
+        break;
+      }
       if (u11 == (T)0) u11 = fabs(piv);
       if (fabs(piv) < stop_rel * u11) break;
       if (r >= d.cap) {
@@ -936,6 +944,10 @@ __global__ __launch_bounds__(1024) void phase2_kernel(const Phase2Desc<T>* __res
     const unsigned idx = 0xFFFFFFFFu - (unsigned)(K & 0xFFFFFFFFull);
     const int as = (int)(idx % (unsigned)nr), bs = (int)(idx / (unsigned)nr);
     const T piv = E[as + (size_t)bs * ld];
+    if (!(fabs((double)piv) <= (double)std::numeric_limits<T>::max())) {
+      if (tid == 0) atomicOr(status, 16);
+      break;
+    }
     if (u11 == 0.0) u11 = fabs((double)piv);
     if (fabs((double)piv) < stop_rel * u11) break;
     if (r >= d.cap) {
@@ -1166,6 +1178,10 @@ __global__ __launch_bounds__(kCoopThreads) void phase2_coop_kernel(const Phase2C
     for (int i = tid; i < nr; i += nt) u[i] = fetch(cy + i);
     __syncthreads();
     const T piv = u[a];
+    if (!(fabs((double)piv) <= (double)std::numeric_limits<T>::max())) {   // the same in every workgroup
+      if (tid == 0 && j == 0) atomicOr(status, 16);
+      break;
+    }
     if (u11 == 0.0) u11 = fabs((double)piv);
     if (fabs((double)piv) < stop_rel * u11) break;
     if (r >= d.cap) {

@@ -646,6 +646,13 @@ double now_s() {
 
 std::atomic<long long> g_phase2_wait_override{0};
 
+// Message for the breakdown bits of the device status word.
+const char* breakdown_msg(int status) {
+  if (status & 1) return "non-positive pivot in a Cholesky factorisation";
+  if (status & 4) return "singular SMW capacitance matrix";
+  return "a block to compress holds a value that is not finite (the factorisation broke down)";
+}
+
 // Ticks of the device's constant-rate clock a phase-2 workgroup waits at a
 // barrier before it gives up; a test override (set_phase2_wait_ticks) wins.
 long long phase2_wait_ticks(int dev) {
@@ -1105,8 +1112,7 @@ Numeric<T>::Numeric(const Symbolic& s, const double* vals, const mf_opts& o) {
   info.factor_seconds = now_s() - t0;
   note_stream(st);
   constructed = true;
-  if (status & 1) throw Err{MF_ENOTSPD, "non-positive pivot in a Cholesky factorisation"};
-  if (status & 4) throw Err{MF_ENOTSPD, "singular SMW capacitance matrix"};
+  if (status & (1 | 4 | 16)) throw Err{MF_ENOTSPD, breakdown_msg(status)};
   if (status & 2) throw Err{MF_ECAPACITY, "a block rank exceeded rank_cap"};
 }
 
@@ -1661,6 +1667,10 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
   retired.clear();
   if (status & 2) throw Err{MF_ECAPACITY, "a block rank exceeded rank_cap"};
   if (status & 8) throw Err{MF_EHIP, kPhase2WaitMsg};
+  // a breakdown below this level (non-positive pivot, singular capacitance,
+  // non-finite block entries) ends the factorisation here: what the levels
+  // above would compute from it is meaningless
+  if (status & (1 | 4 | 16)) throw Err{MF_ENOTSPD, breakdown_msg(status)};
   for (int i = 0; i < nb; ++i) ranks[br[i].gb] = hr[i];
   // work of the rank-dependent launches: pivot step k of complete pivoting
   // updates the active (rows - k) x (cols - k) part of its block (whole block,

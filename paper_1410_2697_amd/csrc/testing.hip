@@ -171,6 +171,10 @@ mf_status skel_t(void* F, int ld, int r0, int nr, int c0, int nc, const int* I, 
     t_err = "phase-2 workgroups did not meet at their barrier";
     return MF_EHIP;
   }
+  if (s == MF_OK && (stat & 16)) {
+    t_err = "a pivot was not finite";
+    return MF_ENOTSPD;
+  }
   return s;
 }
 }  // namespace

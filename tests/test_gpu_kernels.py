@@ -239,9 +239,9 @@ def test_skeleton_fp32_error_bound(gpu_lib, adaptive, nr, nc, nI, nJ):
     dV = torch.zeros((cap, nc), dtype=torch.float32, device="cuda")
     rank = ctypes.c_int32(-1)
     eps = 1e-4
-    st = gpu_lib.load().mfh_test_skeleton(1, _p(dF), ld, 0, nr, 0, nc, _p(torch.tensor(I, device="cuda")), nI,
-                                          _p(torch.tensor(J, device="cuda")), nJ, eps, adaptive, cap, _p(dU), _p(dV),
-                                          ctypes.byref(rank))
+    dIa, dJa = torch.tensor(I, device="cuda"), torch.tensor(J, device="cuda")   # held: the kernel reads them
+    st = gpu_lib.load().mfh_test_skeleton(1, _p(dF), ld, 0, nr, 0, nc, _p(dIa), nI, _p(dJa), nJ, eps, adaptive, cap,
+                                          _p(dU), _p(dV), ctypes.byref(rank))
     assert st == 0
     r = rank.value
     U = dU.double().cpu().numpy()[:r].T
@@ -250,3 +250,39 @@ def test_skeleton_fp32_error_bound(gpu_lib, adaptive, nr, nc, nI, nJ):
     assert np.abs(E).max() <= (eps + 1e-5) * np.abs(B).max()
     ref = hodlr.skeleton(B, I.astype(np.int64), J.astype(np.int64), eps)
     assert abs(r - ref.rank) <= max(2, ref.rank // 10)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("adaptive", [0, 1])
+@pytest.mark.parametrize("nr,nc,nI,nJ", [(300, 40, 64, 40), (120, 90, 30, 30)])
+@pytest.mark.parametrize("kind", ["nan", "overflow"])
+def test_skeleton_stops_at_nonfinite_pivot(gpu_lib, precision, adaptive, nr, nc, nI, nJ, kind):
+    """A block that holds a NaN, or whose elimination overflows, ends the
+    compression with MF_ENOTSPD at a rank within min(|I|, |J|): the pivot
+    search masks finished columns, so a column that became NaN (a non-finite
+    multiplier times its zeroed entries) is never chosen twice.  300 x 40 in
+    FP32 is the B_hat kernel, 120 x 90 the whole-block kernel."""
+    import torch
+    dt = torch.float64 if precision == 0 else torch.float32
+    big = 1e308 if precision == 0 else 3e38
+    B = _kernel_matrix(nr, nc, 3 + nr, 0.3)
+    rng = np.random.default_rng(5)
+    I = np.sort(rng.choice(nr, nI, replace=False)).astype(np.int32)
+    J = np.sort(rng.choice(nc, nJ, replace=False)).astype(np.int32)
+    if kind == "nan":
+        B[I[2], J[3]] = np.nan
+    else:   # first pivot big; eliminating it doubles a big entry of the next row past the largest finite value
+        B[I[0], J[0]], B[I[0], J[1]] = big, big
+        B[I[1], J[0]], B[I[1], J[1]] = -big, big
+    print(f"case nonfinite {kind} prec={precision} adaptive={adaptive} {nr}x{nc}", flush=True)
+    ld = nr + 4
+    dF = _dev(B, ld, dt)
+    cap = min(nr, nc)
+    dU = torch.zeros((cap, nr), dtype=dt, device="cuda")
+    dV = torch.zeros((cap, nc), dtype=dt, device="cuda")
+    rank = ctypes.c_int32(-1)
+    dIa, dJa = torch.tensor(I, device="cuda"), torch.tensor(J, device="cuda")   # held: the kernel reads them
+    st = gpu_lib.load().mfh_test_skeleton(precision, _p(dF), ld, 0, nr, 0, nc, _p(dIa), nI, _p(dJa), nJ, 1e-4,
+                                          adaptive, cap, _p(dU), _p(dV), ctypes.byref(rank))
+    assert st == gpu_lib.MF_ENOTSPD
+    assert 0 <= rank.value <= (min(nI, nJ) if not adaptive else cap)
