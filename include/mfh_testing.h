@@ -28,6 +28,13 @@ mf_status mfh_test_gemm(int32_t precision, int32_t m, int32_t n, int32_t k, cons
                         int32_t opA, const void* B, int32_t ldb, int32_t opB, void* C, int32_t ldc,
                         double alpha, double beta, int32_t flags, int32_t kchunk);
 
+/* The same product with op(B) = B(brow, :): row kk of B is row brow[kk]
+ * (device int32[k]) of the ldb-strided array B, the row map the apply
+ * reads x(I_p^f) through. */
+mf_status mfh_test_gemm_rows(int32_t precision, int32_t m, int32_t n, int32_t k, const void* A, int32_t lda,
+                             int32_t opA, const void* B, int32_t ldb, const int32_t* brow, void* C, int32_t ldc,
+                             double alpha, double beta, int32_t kchunk);
+
 /* In-place Cholesky of the n x n lower triangle of A (n <= 128) and the
  * explicit inverse of the factor into Inv (full square, zeros above).
  * *status_out receives the kernel's status word (1: non-positive pivot). */

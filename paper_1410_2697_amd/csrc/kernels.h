@@ -33,6 +33,8 @@ enum GemmFlags : int {
 // s sums k in [s*kchunk, (s+1)*kchunk)
 // into part + s*m*n (m x n, ld m); a reduction launch then forms
 // C = alpha * sum_s part_s + beta * C in a fixed order (deterministic).
+// brow != nullptr (op(B) = B only): row kk of B is row brow[kk] of the
+// array B (a gather through an index map, e.g. x(I_p^f)).
 template <typename T>
 struct GemmDesc {
   const T* A;
@@ -40,6 +42,7 @@ struct GemmDesc {
   T* C;
   const int* kdev;
   T* part;
+  const int* brow;
   int m, n, k;
   int lda, ldb, ldc;
   int opA, opB;      // 0: N, 1: T
@@ -204,12 +207,6 @@ struct VecAsmDesc {
   int cnp[2], cnf[2], cld[2];
 };
 
-template <typename T>
-struct VecGatherDesc {    // t(0:nf, :) = xn(upd, :)
-  T* t;
-  const int* upd;
-  int nf, ldt;
-};
 
 // ---- sampled extend-add (Sec. 4.2.1, Eq. HODLR_EA_Expand, Fig. HODLR_EA) ----
 // A HODLR front is not staged densely: only the entries its compression and
@@ -374,9 +371,6 @@ void launch_assemble(T* ws, const int64_t* dest, const signed char* lvl, const d
                      hipStream_t st);
 template <typename T>
 void launch_vec_asm(const VecAsmDesc<T>* d, int ndesc, int nrhs, hipStream_t st);
-template <typename T>
-void launch_vec_gather(const VecGatherDesc<T>* d, int ndesc, const T* xn, int N, int nrhs,
-                       hipStream_t st);
 template <typename T>
 void launch_perm_in(const double* r, T* xn, const int* perm, int N, int nrhs, hipStream_t st);
 template <typename T>

@@ -143,16 +143,18 @@ __device__ __forceinline__ T load_op(const T* p, size_t idx, bool bf16) {
 // columns): 64 x 16 tiles, each wave one 16 x 16 MFMA tile, so no MFMA work
 // is spent on empty columns.
 template <typename T, int BN>
-__device__ __forceinline__ void gemm_tile(const GemmDesc<T>* __restrict__ descs, int ndesc) {
+struct GemmLds {
+  T As[kGemmBK<T>][kTile + 1];
+  T Bs[kGemmBK<T>][BN + 1];
+};
+template <typename T, int BN, bool ROWS>
+__device__ __forceinline__ void gemm_tile_body(const GemmDesc<T>& d, int lt, GemmLds<T, BN>& L) {
   constexpr int BM = kTile, BK = kGemmBK<T>, NQ = BK * 64 / 256, NQB = BK * BN / 256;
   constexpr bool NARROW = BN == 16;
-  __shared__ T As[BK][BM + 1];
-  __shared__ T Bs[BK][BN + 1];
+  auto& As = L.As;
+  auto& Bs = L.Bs;
   typedef typename Mfma<T>::v4 v4;
   const int tid = threadIdx.x;
-  const int di = find_desc_wg(descs, ndesc, (int)blockIdx.x);
-  const GemmDesc<T>& d = descs[di];
-  const int lt = (int)blockIdx.x - d.tile0;
   const int tm = lt % d.tiles_m, rest = lt / d.tiles_m;
   const int tn = rest % d.tiles_n, ks = rest / d.tiles_n;
   const int m0 = tm * BM, n0 = tn * BN;
@@ -172,6 +174,7 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc<T>* __restrict__ descs,
   }
   const T* __restrict__ A = d.A;
   const T* __restrict__ B = d.B;
+  const int* __restrict__ brow = d.brow;
   const int lda = d.lda, ldb = d.ldb, opA = d.opA, opB = d.opB;
   const bool abf = (flags & GF_A_BF16) != 0, bbf = (flags & GF_B_BF16) != 0;
   v4 acc00 = {0, 0, 0, 0}, acc01 = {0, 0, 0, 0}, acc10 = {0, 0, 0, 0}, acc11 = {0, 0, 0, 0};
@@ -198,9 +201,10 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc<T>* __restrict__ descs,
       if (opB == 0) { kk = tid % BK; j = tid / BK + (256 / BK) * q; }
       else { j = tid % BN; kk = tid / BN + (256 / BN) * q; }
       const int gj = n0 + j, gk = kb + kk;
-      rb[q] = (gj < n && gk < kend)
-                  ? load_op(B, opB == 0 ? gk + (size_t)gj * ldb : gj + (size_t)gk * ldb, bbf)
-                  : (T)0;
+      const bool ok = gj < n && gk < kend;
+      int bk = gk;
+      if constexpr (ROWS) bk = ok ? brow[gk] : 0;   // opB == 0 when rows are mapped
+      rb[q] = ok ? load_op(B, opB == 0 ? bk + (size_t)gj * ldb : gj + (size_t)gk * ldb, bbf) : (T)0;
     }
   };
   auto stash = [&]() {
@@ -266,6 +270,16 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc<T>* __restrict__ descs,
   }
 }
 
+template <typename T, int BN>
+__device__ __forceinline__ void gemm_tile(const GemmDesc<T>* __restrict__ descs, int ndesc) {
+  const int di = find_desc_wg(descs, ndesc, (int)blockIdx.x);
+  const GemmDesc<T>& d = descs[di];
+  const int lt = (int)blockIdx.x - d.tile0;
+  __shared__ GemmLds<T, BN> L;   // one LDS block for both bodies
+  if (d.brow) gemm_tile_body<T, BN, true>(d, lt, L);
+  else gemm_tile_body<T, BN, false>(d, lt, L);
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc<T>* __restrict__ descs, int ndesc) {
   gemm_tile<T, kTile>(descs, ndesc);
@@ -290,7 +304,13 @@ __global__ __launch_bounds__(256) void gemm_reduce_kernel(const GemmDesc<T>* __r
     if (row >= m || col >= n || (lower && row < col)) continue;
     const T* p = d.part + row + (size_t)col * m;
     T s = 0;
-    for (int q = 0; q < S; ++q) s += p[q * mn];
+    for (int q0 = 0; q0 < S; q0 += 8) {   // eight slices' loads in flight at once, summed in slice order
+      T v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = q0 + u < S ? p[(size_t)(q0 + u) * mn] : (T)0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += v[u];
+    }
     T* c = d.C + row + (size_t)col * d.ldc;
     T val = alpha * s;
     if (beta != (T)0) val += beta * *c;
@@ -1643,25 +1663,6 @@ __global__ __launch_bounds__(256) void vec_asm_kernel(const VecAsmDesc<T>* __res
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void vec_gather_kernel(const VecGatherDesc<T>* __restrict__ descs, const T* xn,
-                                                         int N, int nrhs) {
-  const VecGatherDesc<T> d = descs[blockIdx.x];
-  const int k = blockIdx.y, nt = blockDim.x;
-  T* t = d.t + (size_t)k * d.ldt;
-  const T* x = xn + (size_t)k * N;
-  for (int a0 = threadIdx.x; a0 < d.nf; a0 += nt * kVecBatch) {
-    int r[kVecBatch];
-    T v[kVecBatch];
-#pragma unroll
-    for (int u = 0; u < kVecBatch; ++u) r[u] = a0 + u * nt < d.nf ? d.upd[a0 + u * nt] : -1;
-#pragma unroll
-    for (int u = 0; u < kVecBatch; ++u) v[u] = r[u] >= 0 ? x[r[u]] : (T)0;
-#pragma unroll
-    for (int u = 0; u < kVecBatch; ++u)
-      if (r[u] >= 0) t[a0 + u * nt] = v[u];
-  }
-}
 
 template <typename T>
 __global__ void perm_in_kernel(const double* r, T* xn, const int* perm, int N, int nrhs) {
@@ -2029,11 +2030,6 @@ void launch_vec_asm(const VecAsmDesc<T>* d, int ndesc, int nrhs, hipStream_t st)
   MFH_LAUNCH(vec_asm_kernel<T>, dim3(ndesc, nrhs), dim3(256), 0, st, d, nrhs);
 }
 template <typename T>
-void launch_vec_gather(const VecGatherDesc<T>* d, int ndesc, const T* xn, int N, int nrhs, hipStream_t st) {
-  if (ndesc <= 0) return;
-  MFH_LAUNCH(vec_gather_kernel<T>, dim3(ndesc, nrhs), dim3(256), 0, st, d, xn, N, nrhs);
-}
-template <typename T>
 void launch_perm_in(const double* r, T* xn, const int* perm, int N, int nrhs, hipStream_t st) {
   MFH_LAUNCH(perm_in_kernel<T>, dim3(grid_for((int64_t)N * nrhs)), dim3(256), 0, st, r, xn, perm, N, nrhs);
 }
@@ -2103,8 +2099,6 @@ void launch_axpby(const double* a, const double* b, double* c, double alpha, dou
   template void launch_assemble<T>(T*, const int64_t*, const signed char*, const double*, int64_t, int, \
                                    hipStream_t);                                                 \
   template void launch_vec_asm<T>(const VecAsmDesc<T>*, int, int, hipStream_t);                  \
-  template void launch_vec_gather<T>(const VecGatherDesc<T>*, int, const T*, int, int,           \
-                                     hipStream_t);                                               \
   template void launch_perm_in<T>(const double*, T*, const int*, int, int, hipStream_t);         \
   template void launch_perm_out<T>(const T*, double*, const int*, int, int, hipStream_t);
 

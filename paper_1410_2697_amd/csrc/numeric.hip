@@ -767,7 +767,7 @@ class Numeric : public NumericBase {
   void hodlr_level(const std::vector<int>& H, int h);
 
   struct Rec {
-    int kind;                 // 0 gemm T, 1 copy TT, 2 vec_asm, 3 vec_gather, 4 split-K reduction
+    int kind;                 // 0 gemm T, 1 copy TT, 2 vec_asm, 4 split-K reduction
     size_t off;
     int n, tiles;
     double flops = 0, bytes = 0;
@@ -2236,47 +2236,47 @@ void Numeric<T>::build_plan(Plan& plan, int nrhs, const Layout& L, T* wk, T* par
     rec_copy(zx);
   }
   for (int h = H - 1; h >= 0; --h) {
-    std::vector<VecGatherDesc<T>> vg;
+    // t_f = x(I_p^f) is read by the first product through the front's
+    // update set (a row map on its B operand), so it is never formed
+    std::map<int, const int*> upd_dev;
+    {
+      std::vector<int> upd;
+      std::vector<std::pair<int, int64_t>> uo;
+      for (int p : s.levels[h]) {
+        const Front& f = s.fronts[p];
+        if (f.nf() == 0) continue;
+        uo.push_back({p, (int64_t)upd.size()});
+        upd.insert(upd.end(), f.upd.begin(), f.upd.end());
+      }
+      if (!upd.empty()) {
+        Blob ub;
+        const size_t o = ub.add(upd);
+        const char* ubase = upload(ub);
+        for (auto& q : uo) upd_dev[q.first] = reinterpret_cast<const int*>(ubase + o) + q.second;
+      }
+    }
     GemmBatch<T> d1, d2;
     for (int p : s.levels[h]) {
       const Front& f = s.fronts[p];
       const FN& x = fn[p];
-      const int np = f.npiv, nf = f.nf(), nh = f.n();
-      T* t = wk + t_off[p];
+      const int np = f.npiv, nf = f.nf();
       T* z = wk + z_off[p];
-      if (nf > 0) {
-        VecGatherDesc<T> g{};
-        g.t = t + np; g.upd = d_relmap.as<int>();   // placeholder, replaced below
-        g.nf = nf; g.ldt = nh;
-        vg.push_back(g);
-      }
       if (x.dense) {
-        if (nf > 0) d1.v.push_back(gd<T>(x.Lfp, nf, 1, t + np, nh, 0, z, np, np, nrhs, nf, -1.0, 1.0));
+        if (nf > 0) {
+          auto g = gd<T>(x.Lfp, nf, 1, pl->xn, N, 0, z, np, np, nrhs, nf, -1.0, 1.0);
+          g.brow = upd_dev.at(p);
+          d1.v.push_back(g);
+        }
         d2.v.push_back(gd<T>(x.Linv, np, 1, z, np, 0, pl->xn + f.start, N, np, nrhs, np, 1.0, 0.0, GF_A_UPPER));
       } else {
         T* hb = wk + h_off[p];
         if (x.r_top > 0) {
-          d1.v.push_back(gd<T>(x.W, nf, 1, t + np, nh, 0, hb, x.r_top, x.r_top, nrhs, nf, 1.0, 0.0, bff));
+          auto g = gd<T>(x.W, nf, 1, pl->xn, N, 0, hb, x.r_top, x.r_top, nrhs, nf, 1.0, 0.0, bff);
+          g.brow = upd_dev.at(p);
+          d1.v.push_back(g);
           d2.v.push_back(gd<T>(x.G, np, 0, hb, x.r_top, 0, pl->xn + f.start, N, np, nrhs, x.r_top, -1.0, 1.0));
         }
       }
-    }
-    // the gather needs each front's I_p^f on the device
-    if (!vg.empty()) {
-      std::vector<int> upd;
-      std::vector<int64_t> uo;
-      for (int p : s.levels[h]) {
-        const Front& f = s.fronts[p];
-        if (f.nf() == 0) continue;
-        uo.push_back((int64_t)upd.size());
-        upd.insert(upd.end(), f.upd.begin(), f.upd.end());
-      }
-      Blob ub;
-      size_t o = ub.add(upd);
-      const char* ubase = upload(ub);
-      for (size_t i = 0; i < vg.size(); ++i) vg[i].upd = reinterpret_cast<const int*>(ubase + o) + uo[i];
-      size_t ov = b.add(vg);
-      pl->recs.push_back({3, ov, (int)vg.size(), 0});
     }
     rec_gemm(d1);
     rec_gemm(d2);
@@ -2396,8 +2396,6 @@ void Numeric<T>::launch_recs(const Plan& plan, hipStream_t stream) {
       }
       case 1: launch_copy<T, T>(reinterpret_cast<const CopyDesc<T, T>*>(base), rc.n, rc.tiles, stream); break;
       case 2: launch_vec_asm<T>(reinterpret_cast<const VecAsmDesc<T>*>(base), rc.n, nrhs, stream); break;
-      case 3: launch_vec_gather<T>(reinterpret_cast<const VecGatherDesc<T>*>(base), rc.n, pl->xn, N, nrhs, stream);
-        break;
     }
   }
 }

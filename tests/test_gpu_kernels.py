@@ -51,6 +51,10 @@ GEMM_CASES = [
     (100, 16, 1000, 1, 0, 0, 128), (130, 130, 300, 0, 1, 1, 64), (96, 20, 200, 0, 0, 2, 64),
     (96, 20, 200, 1, 0, 4, 64), (50, 70, 170, 0, 1, 16, 64), (70, 50, 333, 1, 1, 8, 128), (7, 9, 20, 0, 0, 0, 64),
     (65, 33, 129, 1, 1, 0, 0), (200, 130, 31, 0, 0, 1, 0), (64, 64, 200, 0, 1, 16, 0),
+    # 64 x 16 tiles (n <= 16): k shared by four waves, several steps loaded at once
+    (96, 16, 200, 0, 0, 2, 0), (96, 16, 200, 1, 0, 4, 0), (96, 16, 200, 1, 0, 4, 64), (50, 16, 170, 0, 1, 16, 64),
+    (50, 9, 70, 0, 0, 8, 0), (300, 16, 2000, 1, 0, 0, 0), (1000, 16, 37, 0, 0, 0, 0), (129, 16, 129, 0, 1, 1, 0),
+    (70, 13, 3000, 0, 1, 0, 1536), (17, 3, 5, 1, 1, 0, 0), (64, 16, 4096, 0, 0, 0, 0),
 ]
 
 
@@ -286,3 +290,67 @@ def test_skeleton_stops_at_nonfinite_pivot(gpu_lib, precision, adaptive, nr, nc,
                                           adaptive, cap, _p(dU), _p(dV), ctypes.byref(rank))
     assert st == gpu_lib.MF_ENOTSPD
     assert 0 <= rank.value <= (min(nI, nJ) if not adaptive else cap)
+
+
+@pytest.mark.parametrize("n", [16, 40])
+@pytest.mark.parametrize("bf", [32, 64, 96])
+@pytest.mark.parametrize("opA,opB", [(0, 0), (1, 1)])
+def test_gemm_bf16_operands(gpu_lib, n, bf, opA, opB):
+    """FP32 GEMM with A and/or B held as bfloat16 bit patterns (flags 32 / 64):
+    the 64 x 16 kernel (n = 16) and the 64 x 64 kernel (n = 40) against a
+    float64 product of the same bfloat16 values."""
+    import torch
+    m, k = 150, 333
+    rng = np.random.default_rng(bf + n + opA)
+    Aop = rng.standard_normal((m, k))
+    Bop = rng.standard_normal((k, n))
+    A = Aop.T.copy() if opA else Aop
+    B = Bop.T.copy() if opB else Bop
+    lda, ldb, ldc = A.shape[0] + 3, B.shape[0] + 1, m + 5
+
+    def dev(X, ld, as_bf16):
+        rows, cols = X.shape
+        buf = np.zeros((cols, ld))
+        buf[:, :rows] = X.T
+        if as_bf16:
+            return torch.tensor(buf, dtype=torch.bfloat16, device="cuda")
+        return torch.tensor(buf, dtype=torch.float32, device="cuda")
+
+    dA, dB = dev(A, lda, bool(bf & 32)), dev(B, ldb, bool(bf & 64))
+    dC = _dev(np.zeros((m, n)), ldc, torch.float32)
+    st = gpu_lib.load().mfh_test_gemm(1, m, n, k, _p(dA), lda, opA, _p(dB), ldb, opB, _p(dC), ldc, 1.0, 0.0, bf, 0)
+    assert st == 0
+    Ar = dA.double().cpu().numpy()[:, :A.shape[0]].T
+    Br = dB.double().cpu().numpy()[:, :B.shape[0]].T
+    ref = (Ar.T if opA else Ar) @ (Br.T if opB else Br)
+    out = _host(dC, m)
+    assert np.abs(out - ref).max() <= 2e-5 * np.sqrt(k) * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("m,n,k,opA,kchunk", [(90, 16, 300, 1, 0), (90, 16, 300, 1, 128), (40, 5, 77, 0, 0),
+                                              (130, 40, 200, 1, 64)])
+def test_gemm_row_map(gpu_lib, prec, m, n, k, opA, kchunk):
+    """op(B) = B(brow, :) through a row map (the apply's read of x(I_p^f)):
+    equal to the product with the gathered rows."""
+    import torch
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    rng = np.random.default_rng(m + n + k)
+    nb = 3 * k + 11
+    Bfull = rng.standard_normal((nb, n))
+    rows = np.sort(rng.choice(nb, k, replace=False)).astype(np.int32)
+    Aop = rng.standard_normal((m, k))
+    A = Aop.T.copy() if opA else Aop
+    C0 = rng.standard_normal((m, n))
+    lda, ldb, ldc = A.shape[0] + 2, nb, m + 1
+    dA, dB, dC = _dev(A, lda, dt), _dev(Bfull, ldb, dt), _dev(C0, ldc, dt)
+    drows = torch.tensor(rows, device="cuda")
+    st = gpu_lib.load().mfh_test_gemm_rows(0 if prec == "fp64" else 1, m, n, k, _p(dA), lda, opA, _p(dB), ldb,
+                                           _p(drows), _p(dC), ldc, -1.0, 1.0, kchunk)
+    assert st == 0
+    cast = np.float32 if prec == "fp32" else np.float64
+    Ar = A.astype(cast).astype(np.float64)
+    Br = Bfull.astype(cast).astype(np.float64)[rows]
+    ref = C0.astype(cast).astype(np.float64) - (Ar.T if opA else Ar) @ Br
+    tol = 1e-13 if prec == "fp64" else 2e-5
+    assert np.abs(_host(dC, m) - ref).max() <= tol * np.sqrt(k) * max(1.0, np.abs(ref).max())
