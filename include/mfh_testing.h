@@ -63,6 +63,19 @@ mf_status mfh_test_skeleton(int32_t precision, void* F, int32_t ld, int32_t r0, 
  * kernel's status word (4: a zero pivot column). */
 mf_status mfh_test_inverse(int32_t n, double* A, int32_t lda, int32_t* status_out);
 
+/* Truncation error of every compressed block (Sec. 2.2: the pivot-ratio
+ * rule at eps).  While on, factorisations with assembled fronts keep a
+ * float64 copy of each block before compression and, once its rank is
+ * known, measure max|B| and max|B - U V^T| in float64 with the bases as
+ * computed (before any bfloat16 rounding).  Debug cost: one float64 copy of
+ * a level's blocks and a device synchronisation per level. */
+mf_status mfh_test_record_block_errors(int32_t on);
+/* The recorded errors of a factor, 6 doubles per block in level order:
+ * front, block (index in the front's block list), rank, max|B|, |u_11|
+ * (the first pivot), max|B - U V^T|.  *count receives the number of blocks;
+ * at most cap are written. */
+mf_status mfh_test_block_errors(const mf_numeric_t* f, double* out, int64_t cap, int64_t* count);
+
 /* Barrier wait of the multi-workgroup phase 2 (Sec. 2.2 compression spread
  * over workgroups) for every later factorisation in the process, in ticks
  * of the device's constant-rate clock: 0 restores the default (two

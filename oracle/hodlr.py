@@ -58,11 +58,14 @@ def _stop(piv: float, eps: float, u11: float) -> bool:
     return abs(piv) < max(eps, NOISE_REL) * u11
 
 
-def _pick_pivot(W: np.ndarray, live_r: np.ndarray, live_c: np.ndarray):
-    """(row, col) of the complete-pivoting choice among live entries, or None
-    when every live entry is zero."""
+def _pick_pivot(W: np.ndarray, live_r: np.ndarray, live_c: np.ndarray, mask: np.ndarray = None):
+    """(row, col) of the complete-pivoting choice among live entries (and
+    within ``mask`` when given), or None when every such entry is zero."""
     q = np.abs(W).view(np.int64) & ~np.int64(0xFFFFFFFF)   # |v| truncated to 20 mantissa bits
-    q = np.where(live_r[:, None] & live_c[None, :], q, -1)
+    ok = live_r[:, None] & live_c[None, :]
+    if mask is not None:
+        ok = ok & mask
+    q = np.where(ok, q, -1)
     qmax = q.max() if q.size else -1
     if qmax <= 0:
         return None
@@ -128,7 +131,7 @@ def complete_pivot_lu(Bh: np.ndarray, eps: float):
 
 
 def skeleton(B: np.ndarray, I: np.ndarray, J: np.ndarray, eps: float,
-             adaptive: bool = True) -> LowRank:
+             adaptive=True) -> LowRank:
     """BDLR pseudo-skeleton of block B from row set I and column set J
     (block-local indices), Eq. Bhat.
 
@@ -143,7 +146,15 @@ def skeleton(B: np.ndarray, I: np.ndarray, J: np.ndarray, eps: float,
     column E(:, j) to C~ and row E(i, :) / E(i, j) to R~.  At exit
     max|B - C~ R~| < eps |u_11| / (1 - 2^-20) <= eps max|B| / (1 - 2^-20).
     u_11 is the first pivot taken (from B_hat, or from B when phase 1 takes
-    none)."""
+    none).
+
+    ``adaptive="cross"`` runs phase 2 on the sampled cross only: the pivot
+    is the largest live residual entry in the BDLR rows I or columns J
+    (E(I, :) and E(:, J), the entries a front that is never assembled
+    forms), and the stopping rule holds there; each pivot still appends the
+    whole residual column and row, so a sampled front fetches one row and
+    one column of B per extra pivot.  With I and J covering the block this
+    is the whole-block phase 2."""
     m, n = B.shape
     Ct = np.zeros((m, 0))
     Rt = np.zeros((0, n))
@@ -167,9 +178,16 @@ def skeleton(B: np.ndarray, I: np.ndarray, J: np.ndarray, eps: float,
         live_c = np.ones(n, dtype=bool)
         live_r[Ir] = False
         live_c[Jr] = False
+        mask = None
+        if adaptive == "cross":
+            in_i = np.zeros(m, dtype=bool)
+            in_j = np.zeros(n, dtype=bool)
+            in_i[I] = True
+            in_j[J] = True
+            mask = in_i[:, None] | in_j[None, :]
         cols_add, rows_add, ir_add, jc_add = [], [], [], []
         while live_r.any() and live_c.any():
-            pick = _pick_pivot(E, live_r, live_c)
+            pick = _pick_pivot(E, live_r, live_c, mask)
             if pick is None:
                 break
             i, j = pick

@@ -46,7 +46,7 @@ class Options:
     cap: int = 192         # BDLR set size cap
     n_c: int = 0           # fronts with n_p + n_f < n_c stay dense
     compress: str = "skeleton"   # "skeleton" (BDLR, Sec. 2.2) or "svd"
-    adaptive: bool = True  # continue complete pivoting on the full block (phase 2)
+    adaptive: object = True  # phase 2: True whole block, "cross" the sampled rows and columns, False none
     record_errors: bool = False
 
 

@@ -129,6 +129,8 @@ SIGNATURES = [
                                  _P, _P, ctypes.POINTER(_I32)]),
     ("mfh_test_inverse", _I32, [_I32, _P, _I32, ctypes.POINTER(_I32)]),
     ("mfh_test_phase2_wait", _I32, [_I64]),
+    ("mfh_test_record_block_errors", _I32, [_I32]),
+    ("mfh_test_block_errors", _I32, [_P, _P, _I64, ctypes.POINTER(_I64)]),
 ]
 
 

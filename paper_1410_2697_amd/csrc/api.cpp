@@ -9,6 +9,7 @@
 #include <string>
 
 #include "../../include/mfh.h"
+#include "../../include/mfh_testing.h"
 #include "numeric.h"
 #include "prof.h"
 #include "server.h"
@@ -305,6 +306,20 @@ mf_status gmres_solve(mf_numeric_t* f, int32_t nrhs, const double* b, double* x,
   f->n->note_stream(static_cast<hipStream_t>(o.stream));
   if (s == MF_ENOCONV) return fail(MF_ENOCONV, "GMRES did not reach tol within maxit");
   return s;
+  MF_GUARD_END
+}
+
+mf_status mfh_test_block_errors(const mf_numeric_t* f, double* out, int64_t cap, int64_t* count) {
+  MF_GUARD_BEGIN
+  if (!f || !count || cap < 0 || (cap > 0 && !out)) return fail(MF_EINVAL, "bad argument");
+  const auto& e = f->n->block_errors;
+  *count = (int64_t)e.size();
+  for (int64_t i = 0; i < std::min<int64_t>(cap, (int64_t)e.size()); ++i) {
+    double* o = out + 6 * i;
+    o[0] = e[i].front; o[1] = e[i].block; o[2] = e[i].rank;
+    o[3] = e[i].bmax; o[4] = e[i].u11; o[5] = e[i].emax;
+  }
+  return MF_OK;
   MF_GUARD_END
 }
 

@@ -349,6 +349,13 @@ int gj_kind(int nmax);
 void launch_gj_inverse(const InvDesc* d, int ndesc, int nmax, int* status, hipStream_t st);
 template <typename T>
 void launch_fill(T* p, int64_t n, T v, hipStream_t st);
+// out[i] = max |p_i(r, c)| over the rows x cols matrix p_i (ld), one
+// workgroup per matrix
+struct MaxAbsDesc {
+  const double* p;
+  int rows, cols, ld, pad;
+};
+void launch_maxabs(const MaxAbsDesc* d, int ndesc, double* out, hipStream_t st);
 // out[0..na+nb] = a[0..na), b[0..nb), *c; out may be pinned host memory
 // (its device address)
 void launch_readback(const int* a, int na, const int* b, int nb, const int* c, int* out, hipStream_t st);

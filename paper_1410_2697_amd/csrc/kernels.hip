@@ -2003,6 +2003,23 @@ void launch_gj_inverse(const InvDesc* d, int ndesc, int nmax, int* status, hipSt
     default: MFH_LAUNCH(gj_wide_kernel, dim3(ndesc), dim3(1024), 0, st, d, status); break;
   }
 }
+__global__ __launch_bounds__(256) void maxabs_kernel(const MaxAbsDesc* __restrict__ descs, double* out) {
+  __shared__ double red[kWave];
+  const MaxAbsDesc d = descs[blockIdx.x];
+  const int64_t tot = (int64_t)d.rows * d.cols;
+  double mx = 0.0;
+  for (int64_t e = threadIdx.x; e < tot; e += blockDim.x) {
+    const int r = (int)(e % d.rows), c = (int)(e / d.rows);
+    const double v = fabs(d.p[r + (size_t)c * d.ld]);
+    mx = fmax(mx, v != v ? (double)INFINITY : v);   // a NaN is reported as infinity
+  }
+  mx = block_max(mx, red);
+  if (threadIdx.x == 0) out[blockIdx.x] = mx;
+}
+void launch_maxabs(const MaxAbsDesc* d, int ndesc, double* out, hipStream_t st) {
+  if (ndesc <= 0) return;
+  MFH_LAUNCH(maxabs_kernel, dim3(ndesc), dim3(256), 0, st, d, out);
+}
 template <typename T>
 void launch_fill(T* p, int64_t n, T v, hipStream_t st) {
   if (n <= 0) return;

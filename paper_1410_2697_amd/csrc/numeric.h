@@ -87,6 +87,11 @@ class NumericBase {
            mf_status* st_out);
   void direct_solve(int nrhs, const double* b, double* x, int refine, hipStream_t st, mf_gmres_info* info);
   mf_factor_info info{};
+  // per compressed block, when recording is on (set_record_block_errors):
+  // front, block, rank, max|B|, |u_11|, max|B - U V^T| (float64, before any
+  // bfloat16 rounding of the bases)
+  struct BlockErr { int front, block, rank; double bmax, u11, emax; };
+  std::vector<BlockErr> block_errors;
   uint64_t uid = 0;              // process-unique handle number (never reused)
   std::vector<int> ranks;        // per global block, -1 for dense fronts
   const Symbolic* sym = nullptr;
@@ -112,6 +117,10 @@ std::unique_ptr<NumericBase> make_numeric(const Symbolic& s, const double* vals,
 // constant-rate clock: 0 restores the default (two seconds), < 0 makes every
 // workgroup give up at its first barrier (test hook for the error path).
 void set_phase2_wait_ticks(long long ticks);
+// Test hook: factorisations started while on keep a float64 copy of every
+// block before compression and record its truncation error (block_errors);
+// assembled fronts only (a sampled front never forms its blocks).
+void set_record_block_errors(bool on);
 // message of the MF_EHIP a phase-2 barrier give-up ends the factorisation with
 constexpr const char* kPhase2WaitMsg = "phase-2 workgroups did not meet at their barrier";
 // Front workspace plan (elements): the staged fronts of one level share a

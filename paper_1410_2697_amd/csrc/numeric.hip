@@ -645,6 +645,7 @@ double now_s() {
 }
 
 std::atomic<long long> g_phase2_wait_override{0};
+std::atomic<bool> g_record_block_errors{false};
 
 // Message for the breakdown bits of the device status word.
 const char* breakdown_msg(int status) {
@@ -1605,6 +1606,30 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
   resid.stage(b, &split);
   const char* base = dp.upload(b, st);
   int* dstat = d_status.as<int>();
+  // test hook: every block in float64 before compression changes the front
+  const bool rec = g_record_block_errors.load() && !sampled;
+  DevBuf dbgB;
+  std::vector<int64_t> dbg_off(nb, 0);
+  if (rec) {
+    int64_t tot = 0;
+    for (int i = 0; i < nb; ++i) {
+      const Block& B = s.fronts[br[i].p].blocks[br[i].bi];
+      dbg_off[i] = tot;
+      tot += (int64_t)B.nr * B.nc;
+    }
+    dbgB.alloc((size_t)std::max<int64_t>(tot, 1) * sizeof(double), &ms);
+    CopyBatch<T, double> cb;
+    for (int i = 0; i < nb; ++i) {
+      const Block& B = s.fronts[br[i].p].blocks[br[i].bi];
+      const FN& fx = fn[br[i].p];
+      cb.v.push_back(cd<T, double>(fx.F + B.r0 + (int64_t)B.c0 * fx.ld, fx.ld, dbgB.as<double>() + dbg_off[i], B.nr,
+                                   B.nr, B.nc));
+    }
+    Blob bd;
+    cb.stage(bd);
+    const char* bdb = dp.upload(bd, st);
+    cb.launch(bdb, st);
+  }
   // timing records; their work is added once the ranks are back on the host
   // whole-block blocks on the side stream while the larger blocks' chain
   // runs here; joined before the ranks are read back
@@ -1724,6 +1749,47 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
     }
   }
 
+  if (rec) {   // max|B| and max|B - U V^T| in float64, with the bases as computed (before any rounding)
+    int64_t uv = 0;
+    for (int i = 0; i < nb; ++i) {
+      const Block& B = s.fronts[br[i].p].blocks[br[i].bi];
+      uv += (int64_t)(B.nr + B.nc) * hr[i];
+    }
+    DevBuf dUV, dmax;
+    dUV.alloc((size_t)std::max<int64_t>(uv, 1) * sizeof(double), &ms);
+    dmax.alloc((size_t)2 * nb * sizeof(double), &ms);
+    CopyBatch<T, double> cu;
+    GemmBatch<double> ge;
+    std::vector<MaxAbsDesc> md;
+    double* up = dUV.as<double>();
+    for (int i = 0; i < nb; ++i) {
+      const Block& B = s.fronts[br[i].p].blocks[br[i].bi];
+      double* bd = dbgB.as<double>() + dbg_off[i];
+      md.push_back(MaxAbsDesc{bd, B.nr, B.nc, B.nr, 0});
+      const int r = hr[i];
+      if (r == 0) continue;
+      cu.v.push_back(cd<T, double>(br[i].U, B.nr, up, B.nr, B.nr, r));
+      cu.v.push_back(cd<T, double>(br[i].V, B.nc, up + (int64_t)B.nr * r, B.nc, B.nc, r));
+      ge.v.push_back(gd<double>(up, B.nr, 0, up + (int64_t)B.nr * r, B.nc, 1, bd, B.nr, B.nr, B.nc, r, -1.0, 1.0));
+      up += (int64_t)(B.nr + B.nc) * r;
+    }
+    Blob b6;
+    const size_t om = b6.add(md);
+    cu.stage(b6);
+    ge.stage(b6, &split);
+    const char* base6 = dp.upload(b6, st);
+    const MaxAbsDesc* dmd = reinterpret_cast<const MaxAbsDesc*>(base6 + om);
+    launch_maxabs(dmd, nb, dmax.as<double>(), st);
+    cu.launch(base6, st);
+    ge.launch(base6, st);
+    launch_maxabs(dmd, nb, dmax.as<double>() + nb, st);
+    double* hm = dp.host<double>((size_t)3 * nb);
+    HIPCHK(hipMemcpyAsync(hm, dmax.p, (size_t)2 * nb * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(hm + 2 * nb, u11, (size_t)nb * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int i = 0; i < nb; ++i)
+      block_errors.push_back(BlockErr{br[i].p, br[i].bi, hr[i], hm[i], hm[2 * nb + i], hm[nb + i]});
+  }
   const bool uvbf = sizeof(T) == 4 && opts.uv_bf16 != 0;
   if (uvbf) {   // bases rounded to bfloat16 once; everything below uses the rounded values
     CopyBatch<T, T> rnd;
@@ -2797,6 +2863,7 @@ void estimate_bytes(const Symbolic& s, const mf_opts& o, int nrhs, int restart, 
 }
 
 void set_phase2_wait_ticks(long long ticks) { g_phase2_wait_override.store(ticks); }
+void set_record_block_errors(bool on) { g_record_block_errors.store(on); }
 
 std::unique_ptr<NumericBase> make_numeric(const Symbolic& s, const double* vals, const mf_opts& o) {
   if (o.precision == MF_FP64) return std::make_unique<Numeric<double>>(s, vals, o);

@@ -256,6 +256,11 @@ mf_status mfh_test_skeleton(int32_t precision, void* F, int32_t ld, int32_t r0, 
 
 }  // extern "C"
 
+extern "C" mf_status mfh_test_record_block_errors(int32_t on) {
+  mfh::set_record_block_errors(on != 0);
+  return MF_OK;
+}
+
 extern "C" mf_status mfh_test_phase2_wait(int64_t ticks) {
   mfh::set_phase2_wait_ticks((long long)ticks);
   return MF_OK;

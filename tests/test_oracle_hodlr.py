@@ -112,3 +112,44 @@ def test_smw_solve_equals_dense(n, leaf, rank):
         assert np.abs(y - yr).max() < 1e-10 * np.abs(yr).max()
         # ranks were found exactly
         assert all(lr.rank == rank for lr in hodlr.blocks(H))
+
+
+def test_skeleton_cross_meets_bound_on_the_cross():
+    """Phase 2 on the sampled cross: every residual entry in the BDLR rows
+    and columns meets the pivot-ratio rule, the rank lies between the
+    one-phase and the whole-block ones, and the factors are the residual
+    columns and rows of the pivots (U V^T reproduces B on them)."""
+    B = _kernel_block(90, 70, 7, gap=0.15)
+    rng = np.random.default_rng(3)
+    I = np.sort(rng.choice(90, 6, replace=False))
+    J = np.sort(rng.choice(70, 5, replace=False))
+    eps = 1e-7
+    lr0 = hodlr.skeleton(B, I, J, eps, adaptive=False)
+    lrc = hodlr.skeleton(B, I, J, eps, adaptive="cross")
+    lrw = hodlr.skeleton(B, I, J, eps, adaptive=True)
+    assert lr0.rank < lrc.rank <= lrw.rank
+    E = B - lrc.U @ lrc.V.T
+    u11 = np.abs(B[np.ix_(I, J)]).max()
+    bound = eps * u11 / (1 - hodlr.TIE_REL) * (1 + 1e-9)
+    assert np.abs(E[I, :]).max() < bound and np.abs(E[:, J]).max() < bound
+    # the pivots' rows and columns are reproduced (to rounding)
+    assert np.abs(E[lrc.piv_rows, :]).max() < 1e-12 * np.abs(B).max()
+    assert np.abs(E[:, lrc.piv_cols]).max() < 1e-12 * np.abs(B).max()
+    # outside the cross the error is not bounded by the rule (it is what the
+    # cross does not see), but it is no larger than the one-phase error
+    assert np.abs(E).max() <= np.abs(B - lr0.U @ lr0.V.T).max() * (1 + 1e-9)
+
+
+def test_skeleton_cross_with_full_sets_is_whole_block():
+    B = _kernel_block(40, 33, 11, gap=0.3)
+    I = np.arange(40)[::3]
+    J = np.arange(33)
+    lrc = hodlr.skeleton(B, np.arange(40), J, 1e-9, adaptive="cross")
+    lrw = hodlr.skeleton(B, np.arange(40), J, 1e-9, adaptive=True)
+    assert lrc.rank == lrw.rank
+    assert np.array_equal(lrc.piv_rows, lrw.piv_rows) and np.array_equal(lrc.piv_cols, lrw.piv_cols)
+    assert np.abs(lrc.U @ lrc.V.T - lrw.U @ lrw.V.T).max() == 0.0
+    # all columns sampled: the cross is the whole block even with few rows
+    lrc2 = hodlr.skeleton(B, I, J, 1e-9, adaptive="cross")
+    lrw2 = hodlr.skeleton(B, I, J, 1e-9, adaptive=True)
+    assert lrc2.rank == lrw2.rank and np.array_equal(lrc2.piv_cols, lrw2.piv_cols)
