@@ -189,6 +189,29 @@ def run_config(mfh, torch, w, method, precision, n_c, steps, warmup, latency_cal
         torch.cuda.synchronize()
         lat.append(time.perf_counter() - a)
     lat.sort()
+    # the preconditioner apply alone (the hot loop of every iteration):
+    # wall time per apply, and the algorithmic bytes its timed kernels move
+    # (factor blocks plus right-hand-side blocks) per apply
+    z = torch.zeros_like(b)
+    for _ in range(5):
+        f.apply(b, z, stream=stream)
+    torch.cuda.synchronize()
+    na = 50
+    a0 = time.perf_counter()
+    for _ in range(na):
+        f.apply(b, z, stream=stream)
+    torch.cuda.synchronize()
+    apply_s = (time.perf_counter() - a0) / na
+    mfh.prof_start()
+    for _ in range(5):
+        f.apply(b, z, stream=stream)
+    torch.cuda.synchronize()
+    ast = mfh.prof_stop()
+    abytes = sum(s["bytes"] for s in ast) / 5
+    apply_roof = {"us_per_apply": 1e6 * apply_s, "bytes_per_apply": abytes,
+                  "achieved": abytes / apply_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                  "frac": abytes / apply_s / 1e9 / HBM_PEAK_GBS,
+                  "timed_launches_per_apply": sum(s["launches"] for s in ast) / 5}
     info = f.info()
     n = len(phases)
     q = lambda frac: 1e3 * lat[min(len(lat) - 1, int(frac * len(lat)))] if lat else None
@@ -213,6 +236,7 @@ def run_config(mfh, torch, w, method, precision, n_c, steps, warmup, latency_cal
         "kernels_step": kernels,
         "kernels_solve": solve_kernels,
         "roofline": roof,
+        "apply_roofline": apply_roof,
         "x": x,
         "f": f,
     }

@@ -64,8 +64,13 @@ typedef struct {
   int32_t bdlr_depth;   /* BDLR depth d (Sec. 2.2, Table 1 "d"); < 0: every row/column    */
   int32_t bdlr_cap;     /* at most this many BDLR rows (and columns) per block; 0: the most */
                         /* the pivot kernel takes (128 float64, 192 float32)                */
-  int32_t adaptive;     /* 1: continue complete pivoting over the whole block until the
-                           pivot-ratio rule holds there (max-norm error < eps*|u_11|)     */
+  int32_t adaptive;     /* phase 2 of the skeleton (Sec. 2.2), after the pivoting on B(I, J):
+                           0: none (the paper's scheme);
+                           1: complete pivoting continues over the whole block until the
+                              pivot-ratio rule holds there (max-norm error < eps*|u_11|);
+                           2 (sampled = 1 only): it continues over the sampled cross, the
+                              residual rows I and columns J, until the rule holds there;
+                              each extra pivot forms one more row and column of the front */
   int32_t rank_cap;     /* capacity per block rank (a block's capacity is the larger of this
                            and its phase-1 bound min(|I|, |J|)); exceeding it -> MF_ECAPACITY */
   int32_t uv_bf16;      /* HODLR + FP32 only: round the compressed bases U, V (and the F_fp
@@ -85,7 +90,7 @@ typedef struct {
                            and columns of each block and the diagonal leaves are formed, from
                            A's entries, dense children's updates and compressed children's
                            F_ff^HODLR - Wt W^T, and compression uses those samples alone, so
-                           it needs adaptive = 0 (the paper's scheme).  0: every front is
+                           it needs adaptive 0 (the paper's scheme) or 2.  0: every front is
                            staged densely and children's updates are scatter-added whole   */
   double eps;           /* low-rank tolerance (Sec. 2.2: stop when |u_r+1,r+1/u_11| < eps) */
   void* stream;         /* hipStream_t, borrowed; NULL = null stream                      */

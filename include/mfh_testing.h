@@ -28,12 +28,14 @@ mf_status mfh_test_gemm(int32_t precision, int32_t m, int32_t n, int32_t k, cons
                         int32_t opA, const void* B, int32_t ldb, int32_t opB, void* C, int32_t ldc,
                         double alpha, double beta, int32_t flags, int32_t kchunk);
 
-/* The same product with op(B) = B(brow, :): row kk of B is row brow[kk]
- * (device int32[k]) of the ldb-strided array B, the row map the apply
- * reads x(I_p^f) through. */
+/* The same product with row maps on the stored arrays (device int32, or
+ * NULL): stored row s of A is read as row arow[s] (rows of op(A) when
+ * opA == 0, its columns when opA == 1), likewise brow for B.  The apply
+ * reads x(I_p^f) through brow; the sampled skeleton reads the sampled rows
+ * of its bases through them. */
 mf_status mfh_test_gemm_rows(int32_t precision, int32_t m, int32_t n, int32_t k, const void* A, int32_t lda,
-                             int32_t opA, const void* B, int32_t ldb, const int32_t* brow, void* C, int32_t ldc,
-                             double alpha, double beta, int32_t kchunk);
+                             int32_t opA, const int32_t* arow, const void* B, int32_t ldb, int32_t opB,
+                             const int32_t* brow, void* C, int32_t ldc, double alpha, double beta, int32_t kchunk);
 
 /* In-place Cholesky of the n x n lower triangle of A (n <= 128) and the
  * explicit inverse of the factor into Inv (full square, zeros above).

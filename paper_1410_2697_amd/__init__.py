@@ -123,7 +123,8 @@ SIGNATURES = [
     # include/mfh_testing.h
     ("mfh_test_mfma_layout", _I32, [_I32, _P, _P, _P]),
     ("mfh_test_gemm", _I32, [_I32, _I32, _I32, _I32, _P, _I32, _I32, _P, _I32, _I32, _P, _I32, _D, _D, _I32, _I32]),
-    ("mfh_test_gemm_rows", _I32, [_I32, _I32, _I32, _I32, _P, _I32, _I32, _P, _I32, _P, _P, _I32, _D, _D, _I32]),
+    ("mfh_test_gemm_rows", _I32, [_I32, _I32, _I32, _I32, _P, _I32, _I32, _P, _P, _I32, _I32, _P, _P, _I32, _D, _D,
+                                  _I32]),
     ("mfh_test_potrf", _I32, [_I32, _I32, _P, _I32, _P, _I32, ctypes.POINTER(_I32)]),
     ("mfh_test_skeleton", _I32, [_I32, _P, _I32, _I32, _I32, _I32, _I32, _P, _I32, _P, _I32, _D, _I32, _I32,
                                  _P, _P, ctypes.POINTER(_I32)]),

@@ -192,9 +192,11 @@ mf_status mf_factor(const mf_symbolic_t* sh, const double* vals, double eps, int
   if (!(eps >= 0.0) || eps >= 1.0) return fail(MF_EINVAL, "eps must be in [0, 1)");
   if (o.apply_graph < 0 || o.apply_graph > (1 << 20)) return fail(MF_EINVAL, "apply_graph must be in [0, 2^20]");
   if (o.sampled != 0 && o.sampled != 1) return fail(MF_EINVAL, "sampled must be 0 or 1");
-  if (o.sampled && (o.method != MF_METHOD_HODLR || o.adaptive))
+  if (o.adaptive < 0 || o.adaptive > 2) return fail(MF_EINVAL, "adaptive must be 0, 1 or 2");
+  if (o.sampled && (o.method != MF_METHOD_HODLR || o.adaptive == 1))
     return fail(MF_EINVAL, "the sampled extend-add forms only the BDLR rows and columns: it needs "
-                           "MF_METHOD_HODLR and adaptive 0");
+                           "MF_METHOD_HODLR and adaptive 0 or 2");
+  if (o.adaptive == 2 && !o.sampled) return fail(MF_EINVAL, "adaptive 2 (the sampled cross) needs sampled = 1");
   if (leaf != 0 && leaf != sh->s.leaf) return fail(MF_EINVAL, "leaf must be 0 or the analysis leaf size");
   if (o.method == MF_METHOD_HODLR) {
     if (sh->s.leaf > 128) return fail(MF_EINVAL, "HODLR leaves are limited to 128");

@@ -33,8 +33,10 @@ enum GemmFlags : int {
 // s sums k in [s*kchunk, (s+1)*kchunk)
 // into part + s*m*n (m x n, ld m); a reduction launch then forms
 // C = alpha * sum_s part_s + beta * C in a fixed order (deterministic).
-// brow != nullptr (op(B) = B only): row kk of B is row brow[kk] of the
-// array B (a gather through an index map, e.g. x(I_p^f)).
+// Row maps (nullptr: none): a stored row index s of the array A (B) is
+// read as row arow[s] (brow[s]); the stored rows are the rows of op(A) when
+// opA == 0, its columns when opA == 1 (the same for B).  They gather
+// through an index map, e.g. x(I_p^f), or the sampled rows of a basis.
 template <typename T>
 struct GemmDesc {
   const T* A;
@@ -42,6 +44,7 @@ struct GemmDesc {
   T* C;
   const int* kdev;
   T* part;
+  const int* arow;
   const int* brow;
   int m, n, k;
   int lda, ldb, ldc;
@@ -265,6 +268,33 @@ struct ExtAddCDesc {
   int tile0, tiles_r;
 };
 
+// Phase 2 on the sampled cross of a block of a front that is never assembled
+// (skeleton adaptive mode 2; one workgroup of kCrossThreads per block):
+// complete pivoting over the live residual entries in the BDLR rows I and
+// columns J until the pivot-ratio rule holds there.  A pivot (i, j) appends
+// the residual column E(:, j) to U and the residual row E(i, :) / E(i, j) to
+// V; a column outside J or a row outside I is formed from the front's
+// entries (front_value) minus U V^T.  EJ and EI hold E(:, J) and E(I, :)
+// (set to B(:, J) - U V(J, :)^T and B(I, :) - U(I, :) V^T before the
+// launch) and take every pivot's rank-1 update.
+template <typename T>
+struct CrossDesc {
+  T* EJ;                 // nr x nJ, ld nr
+  T* EI;                 // nI x nc, ld nI
+  const int* Il;         // block-local rows of I, ascending
+  const int* Jl;         // block-local columns of J, ascending
+  const int* piv_r;      // phase-1 pivots, as indices into Il and Jl
+  const int* piv_c;
+  const int* rank1;      // phase-1 rank
+  const double* u11;     // |first phase-1 pivot| (0: none)
+  T* U;                  // nr x cap, ld nr (phase-1 columns first)
+  T* V;                  // nc x cap, ld nc
+  int* rank;             // final rank
+  const GatherFront<T>* front;
+  int r0, c0, nr, nc, nI, nJ, cap, pad;
+};
+constexpr int kCrossThreads = 1024;
+
 // ---- launchers (all asynchronous on `st`; descriptor arrays are device) ----
 // MFMA accumulator layout probe (one wave, 64 x 4 entries per output)
 template <typename T>
@@ -340,6 +370,10 @@ void launch_gather(const GatherDesc<T>* d, int ndesc, int tiles, const GatherFro
                    const int* colind, const double* vals, const int* perm, hipStream_t st);
 template <typename T>
 void launch_extadd_c(const ExtAddCDesc<T>* d, int ndesc, int tiles, hipStream_t st);
+// status bits: 2 capacity, 16 non-finite pivot; LDS nr + nc bytes of the largest block
+template <typename T>
+void launch_cross(const CrossDesc<T>* d, int ndesc, int maxrc, double eps, const int* rowptr, const int* colind,
+                  const double* vals, const int* perm, int* status, hipStream_t st);
 template <typename S, typename D>
 void launch_copy(const CopyDesc<S, D>* d, int ndesc, int tiles, hipStream_t st);
 template <typename T>

@@ -174,6 +174,7 @@ __device__ __forceinline__ void gemm_tile_body(const GemmDesc<T>& d, int lt, Gem
   }
   const T* __restrict__ A = d.A;
   const T* __restrict__ B = d.B;
+  const int* __restrict__ arow = d.arow;
   const int* __restrict__ brow = d.brow;
   const int lda = d.lda, ldb = d.ldb, opA = d.opA, opB = d.opB;
   const bool abf = (flags & GF_A_BF16) != 0, bbf = (flags & GF_B_BF16) != 0;
@@ -191,9 +192,10 @@ __device__ __forceinline__ void gemm_tile_body(const GemmDesc<T>& d, int lt, Gem
       if (opA == 0) { i = tid & 63; kk = (tid >> 6) + 4 * q; }
       else { kk = tid % BK; i = tid / BK + (256 / BK) * q; }
       const int gi = m0 + i, gk = kb + kk;
-      ra[q] = (gi < m && gk < kend)
-                  ? load_op(A, opA == 0 ? gi + (size_t)gk * lda : gk + (size_t)gi * lda, abf)
-                  : (T)0;
+      const bool ok = gi < m && gk < kend;
+      int sr = opA == 0 ? gi : gk;   // stored row
+      if constexpr (ROWS) sr = (ok && arow) ? arow[sr] : sr;
+      ra[q] = ok ? load_op(A, opA == 0 ? sr + (size_t)gk * lda : sr + (size_t)gi * lda, abf) : (T)0;
     }
 #pragma unroll
     for (int q = 0; q < NQB; ++q) {
@@ -202,9 +204,9 @@ __device__ __forceinline__ void gemm_tile_body(const GemmDesc<T>& d, int lt, Gem
       else { j = tid % BN; kk = tid / BN + (256 / BN) * q; }
       const int gj = n0 + j, gk = kb + kk;
       const bool ok = gj < n && gk < kend;
-      int bk = gk;
-      if constexpr (ROWS) bk = ok ? brow[gk] : 0;   // opB == 0 when rows are mapped
-      rb[q] = ok ? load_op(B, opB == 0 ? bk + (size_t)gj * ldb : gj + (size_t)gk * ldb, bbf) : (T)0;
+      int sr = opB == 0 ? gk : gj;   // stored row
+      if constexpr (ROWS) sr = (ok && brow) ? brow[sr] : sr;
+      rb[q] = ok ? load_op(B, opB == 0 ? sr + (size_t)gj * ldb : sr + (size_t)gk * ldb, bbf) : (T)0;
     }
   };
   auto stash = [&]() {
@@ -276,7 +278,7 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc<T>* __restrict__ descs,
   const GemmDesc<T>& d = descs[di];
   const int lt = (int)blockIdx.x - d.tile0;
   __shared__ GemmLds<T, BN> L;   // one LDS block for both bodies
-  if (d.brow) gemm_tile_body<T, BN, true>(d, lt, L);
+  if (d.arow || d.brow) gemm_tile_body<T, BN, true>(d, lt, L);
   else gemm_tile_body<T, BN, false>(d, lt, L);
 }
 
@@ -640,12 +642,18 @@ __global__ __launch_bounds__(NT) void skreg_kernel(const SkRegDesc<T>* __restric
   bool capped = false;
   for (; phase <= last && !capped; ++phase) {
     const bool restricted = FULL && phase == 1;
+    // adaptive 2: phase 2 searches the sampled cross only, rows I in every
+    // column and every row in the columns J
+    const bool cross = FULL && phase == 2 && adaptive == 2;
     for (;;) {
       const unsigned rsel = restricted ? (rl & inI) : rl;
       const unsigned csel = restricted ? (cl & inJ) : cl;
-      unsigned rm[RI];
+      unsigned rm[RI], rmi[RI];
 #pragma unroll
-      for (int i = 0; i < RI; ++i) rm[i] = ((rsel >> i) & 1u) ? kMag : 0u;
+      for (int i = 0; i < RI; ++i) {
+        rm[i] = ((rsel >> i) & 1u) ? kMag : 0u;
+        rmi[i] = cross ? (((rsel & inI) >> i) & 1u ? kMag : 0u) : rm[i];
+      }
       // thread-local best in (j, i) order, which is the position order; wave
       // winner: largest magnitude, then earliest (j, i), then lowest lane
       unsigned q, l, wl;
@@ -655,9 +663,10 @@ __global__ __launch_bounds__(NT) void skreg_kernel(const SkRegDesc<T>* __restric
 #pragma unroll
         for (int j = 0; j < CJ; ++j) {
           if (!((csel >> j) & 1u)) continue;
+          const bool cj = ((inJ >> j) & 1u) != 0;
 #pragma unroll
           for (int i = 0; i < RI; ++i) {
-            const unsigned w = (__float_as_uint(e[i][j]) & rm[i]) | (unsigned)(127 - (j * RI + i));
+            const unsigned w = (__float_as_uint(e[i][j]) & (cj ? rm[i] : rmi[i])) | (unsigned)(127 - (j * RI + i));
             bk = w > bk ? w : bk;
           }
         }
@@ -670,9 +679,10 @@ __global__ __launch_bounds__(NT) void skreg_kernel(const SkRegDesc<T>* __restric
 #pragma unroll
         for (int j = 0; j < CJ; ++j) {
           if (!((csel >> j) & 1u)) continue;
+          const bool cj = ((inJ >> j) & 1u) != 0;
 #pragma unroll
           for (int i = 0; i < RI; ++i) {
-            const unsigned x = (unsigned)((u64)__double_as_longlong(e[i][j]) >> 32) & rm[i];
+            const unsigned x = (unsigned)((u64)__double_as_longlong(e[i][j]) >> 32) & (cj ? rm[i] : rmi[i]);
             if (x > bq) { bq = x; bl = (unsigned)(j * RI + i); }
           }
         }
@@ -1283,19 +1293,13 @@ __device__ T child_update(const ChildUpd<T>& c, int a, int b) {
   return v - s;
 }
 
+// Entry (i, j) of a front that is never assembled (front positions):
+// F_bar_p's entry (A's, when i or j is a pivot position) plus every child's
+// update at the mapped position.
 template <typename T>
-__global__ __launch_bounds__(256) void gather_kernel(const GatherDesc<T>* __restrict__ descs, int ndesc,
-                                                     const GatherFront<T>* __restrict__ fronts,
-                                                     const int* __restrict__ rowptr, const int* __restrict__ colind,
-                                                     const double* __restrict__ vals, const int* __restrict__ perm) {
-  const int di = find_desc_wg(descs, ndesc, (int)blockIdx.x);
-  const GatherDesc<T>& d = descs[di];
-  const int64_t e = (int64_t)((int)blockIdx.x - d.tile0) * blockDim.x + threadIdx.x;
-  if (e >= (int64_t)d.nr * d.nc) return;
-  const int rr = (int)(e % d.nr), cc = (int)(e / d.nr);
-  const int i = d.rows ? d.rows[rr] : d.r0 + rr;
-  const int j = d.cols ? d.cols[cc] : d.c0 + cc;
-  const GatherFront<T>& f = fronts[d.front];
+__device__ T front_value(const GatherFront<T>& f, int i, int j, const int* __restrict__ rowptr,
+                         const int* __restrict__ colind, const double* __restrict__ vals,
+                         const int* __restrict__ perm) {
   T v = 0;
   if (i < f.npiv || j < f.npiv) {   // F_bar_p: A's entries in the pivot rows and columns
     const int gi = i < f.npiv ? f.start + i : f.upd[i - f.npiv];
@@ -1315,7 +1319,158 @@ __global__ __launch_bounds__(256) void gather_kernel(const GatherDesc<T>* __rest
     const int a = u.inv[i], b = u.inv[j];
     if (a >= 0 && b >= 0) v += child_update(u, a, b);
   }
-  d.out[rr + (size_t)cc * d.ldo] = v;
+  return v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void gather_kernel(const GatherDesc<T>* __restrict__ descs, int ndesc,
+                                                     const GatherFront<T>* __restrict__ fronts,
+                                                     const int* __restrict__ rowptr, const int* __restrict__ colind,
+                                                     const double* __restrict__ vals, const int* __restrict__ perm) {
+  const int di = find_desc_wg(descs, ndesc, (int)blockIdx.x);
+  const GatherDesc<T>& d = descs[di];
+  const int64_t e = (int64_t)((int)blockIdx.x - d.tile0) * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)d.nr * d.nc) return;
+  const int rr = (int)(e % d.nr), cc = (int)(e / d.nr);
+  const int i = d.rows ? d.rows[rr] : d.r0 + rr;
+  const int j = d.cols ? d.cols[cc] : d.c0 + cc;
+  d.out[rr + (size_t)cc * d.ldo] = front_value(fronts[d.front], i, j, rowptr, colind, vals, perm);
+}
+
+// index of v in the ascending list a[0 .. n), or -1
+__device__ __forceinline__ int find_sorted(const int* __restrict__ a, int n, int v) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (a[mid] < v) lo = mid + 1;
+    else hi = mid;
+  }
+  return (lo < n && a[lo] == v) ? lo : -1;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kCrossThreads) void cross_kernel(const CrossDesc<T>* __restrict__ descs, double eps,
+                                                              const int* __restrict__ rowptr,
+                                                              const int* __restrict__ colind,
+                                                              const double* __restrict__ vals,
+                                                              const int* __restrict__ perm, int* status) {
+  extern __shared__ __align__(16) char smem[];
+  __shared__ u64 s_red[16];
+  __shared__ T s_piv;
+  __shared__ int s_ci, s_ri;
+  const CrossDesc<T> d = descs[blockIdx.x];
+  const int nr = d.nr, nc = d.nc, nI = d.nI, nJ = d.nJ, tid = threadIdx.x, nt = blockDim.x;
+  char* lr = smem;        // live rows / columns (not yet a pivot's)
+  char* lc = smem + nr;
+  const int r1 = *d.rank1;
+  for (int a = tid; a < nr; a += nt) lr[a] = 1;
+  for (int b = tid; b < nc; b += nt) lc[b] = 1;
+  __syncthreads();
+  for (int s = tid; s < r1; s += nt) {
+    lr[d.Il[d.piv_r[s]]] = 0;
+    lc[d.Jl[d.piv_c[s]]] = 0;
+  }
+  __syncthreads();
+  T* __restrict__ EJ = d.EJ;
+  T* __restrict__ EI = d.EI;
+  const int64_t nej = (int64_t)nr * nJ, nei = (int64_t)nI * nc;
+  const double stop_rel = fmax(eps, (double)noise_rel<T>());
+  double u11 = *d.u11;
+  int r = r1;
+  // largest live residual entry of the cross (position order on ties); each
+  // later search runs in the same pass as the previous pivot's update
+  u64 best = 0;
+  for (int64_t e = tid; e < nej; e += nt) {
+    const int i = (int)(e % nr), j = d.Jl[e / nr];
+    if (lr[i] && lc[j]) {
+      const u64 k = make_key(qmag(EJ[e]), (unsigned)(j * nr + i));
+      best = k > best ? k : best;
+    }
+  }
+  for (int64_t e = tid; e < nei; e += nt) {
+    const int i = d.Il[e % nI], j = (int)(e / nI);
+    if (lr[i] && lc[j]) {
+      const u64 k = make_key(qmag(EI[e]), (unsigned)(j * nr + i));
+      best = k > best ? k : best;
+    }
+  }
+  for (;;) {
+    const u64 K = block_max_u64(best, s_red);
+    if (K == 0ull) break;
+    const unsigned idx = 0xFFFFFFFFu - (unsigned)(K & 0xFFFFFFFFull);
+    const int is = (int)(idx % (unsigned)nr), js = (int)(idx / (unsigned)nr);
+    if (tid == 0) {
+      const int ci = find_sorted(d.Jl, nJ, js), ri = find_sorted(d.Il, nI, is);
+      s_ci = ci;
+      s_ri = ri;
+      // every key came from E(:, J) or E(I, :), so one of the two is found
+      s_piv = ci >= 0 ? EJ[is + (size_t)ci * nr] : (ri >= 0 ? EI[ri + (size_t)js * nI] : (T)0);
+    }
+    __syncthreads();
+    const int ci = s_ci, ri = s_ri;
+    if (ci < 0 && ri < 0) break;
+    const T piv = s_piv;
+    if (!(fabs((double)piv) <= (double)std::numeric_limits<T>::max())) {
+      if (tid == 0) atomicOr(status, 16);
+      break;
+    }
+    if (u11 == 0.0) u11 = fabs((double)piv);
+    if (fabs((double)piv) < stop_rel * u11) break;
+    if (r >= d.cap) {
+      if (tid == 0) atomicOr(status, 2);
+      break;
+    }
+    T* Uc = d.U + (size_t)r * nr;
+    T* Vc = d.V + (size_t)r * nc;
+    // residual column js into U(:, r), residual row is / piv into V(:, r)
+    for (int i = tid; i < nr; i += nt) {
+      T v;
+      if (ci >= 0) {
+        v = EJ[i + (size_t)ci * nr];
+      } else {
+        v = front_value(*d.front, d.r0 + i, d.c0 + js, rowptr, colind, vals, perm);
+        for (int k = 0; k < r; ++k) v -= d.U[i + (size_t)k * nr] * d.V[js + (size_t)k * nc];
+      }
+      Uc[i] = v;
+    }
+    for (int j = tid; j < nc; j += nt) {
+      T v;
+      if (ri >= 0) {
+        v = EI[ri + (size_t)j * nI];
+      } else {
+        v = front_value(*d.front, d.r0 + is, d.c0 + j, rowptr, colind, vals, perm);
+        for (int k = 0; k < r; ++k) v -= d.U[is + (size_t)k * nr] * d.V[j + (size_t)k * nc];
+      }
+      Vc[j] = v / piv;
+    }
+    if (tid == 0) {
+      lr[is] = 0;
+      lc[js] = 0;
+    }
+    ++r;
+    __syncthreads();
+    // the cross takes the rank-1 update, and the next search reads the new values
+    best = 0;
+    for (int64_t e = tid; e < nej; e += nt) {
+      const int i = (int)(e % nr), j = d.Jl[e / nr];
+      const T v = EJ[e] - Uc[i] * Vc[j];
+      EJ[e] = v;
+      if (lr[i] && lc[j]) {
+        const u64 k = make_key(qmag(v), (unsigned)(j * nr + i));
+        best = k > best ? k : best;
+      }
+    }
+    for (int64_t e = tid; e < nei; e += nt) {
+      const int i = d.Il[e % nI], j = (int)(e / nI);
+      const T v = EI[e] - Uc[i] * Vc[j];
+      EI[e] = v;
+      if (lr[i] && lc[j]) {
+        const u64 k = make_key(qmag(v), (unsigned)(j * nr + i));
+        best = k > best ? k : best;
+      }
+    }
+  }
+  if (tid == 0) *d.rank = r;
 }
 
 template <typename T>
@@ -1972,6 +2127,13 @@ void launch_gather(const GatherDesc<T>* d, int ndesc, int tiles, const GatherFro
   MFH_LAUNCH(gather_kernel<T>, dim3(tiles), dim3(256), 0, st, d, ndesc, fronts, rowptr, colind, vals, perm);
 }
 template <typename T>
+void launch_cross(const CrossDesc<T>* d, int ndesc, int maxrc, double eps, const int* rowptr, const int* colind,
+                  const double* vals, const int* perm, int* status, hipStream_t st) {
+  if (ndesc <= 0) return;
+  MFH_LAUNCH(cross_kernel<T>, dim3(ndesc), dim3(kCrossThreads), (size_t)maxrc, st, d, eps, rowptr, colind, vals, perm,
+             status);
+}
+template <typename T>
 void launch_extadd_c(const ExtAddCDesc<T>* d, int ndesc, int tiles, hipStream_t st) {
   if (ndesc <= 0 || tiles <= 0) return;
   MFH_LAUNCH(extadd_c_kernel<T>, dim3(tiles), dim3(256), 0, st, d, ndesc);
@@ -2109,6 +2271,8 @@ void launch_axpby(const double* a, const double* b, double* c, double alpha, dou
                                             hipStream_t);                                         \
   template void launch_extadd<T>(const ExtAddDesc<T>*, int, int, hipStream_t);                   \
   template void launch_extadd_c<T>(const ExtAddCDesc<T>*, int, int, hipStream_t);                 \
+  template void launch_cross<T>(const CrossDesc<T>*, int, int, double, const int*, const int*, const double*, \
+                                const int*, int*, hipStream_t);                                   \
   template void launch_gather<T>(const GatherDesc<T>*, int, int, const GatherFront<T>*, const int*, \
                                  const int*, const double*, const int*, hipStream_t);              \
   template void launch_cap<T>(const CapDesc<T>*, int, hipStream_t);                              \

@@ -834,8 +834,9 @@ Numeric<T>::Numeric(const Symbolic& s, const double* vals, const mf_opts& o) {
   const int nfr = (int)s.fronts.size();
   const bool hodlr = o.method == MF_METHOD_HODLR;
   sampled = hodlr && o.sampled != 0;
-  if (sampled && o.adaptive != 0)
-    throw Err{MF_EINVAL, "sampled extend-add needs adaptive = 0 (the whole-block phase reads every entry)"};
+  if (sampled && o.adaptive == 1)
+    throw Err{MF_EINVAL, "sampled extend-add needs adaptive 0 or 2 (the whole-block phase reads every entry)"};
+  if (!sampled && o.adaptive == 2) throw Err{MF_EINVAL, "adaptive 2 (the sampled cross) needs sampled = 1"};
 
   d_rowptr.alloc((n + 1) * sizeof(int), &ms);
   d_colind.alloc(s.nnz * sizeof(int), &ms);
@@ -1231,7 +1232,8 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
   if (Hs.empty()) return;
   const Symbolic& s = *sym;
   const double eps = opts.eps;
-  const bool adaptive = opts.adaptive != 0;
+  const bool adaptive = opts.adaptive == 1;   // phase 2 over the whole block
+  const bool cross = opts.adaptive == 2;      // phase 2 over the sampled cross (sampled fronts)
   {
     std::unique_lock<std::mutex> lk(mu);
     cv.wait(lk, [&] { return lvb_ready > h; });
@@ -1378,8 +1380,12 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
   // it fits the register kernel, else B(I,J), B(:,J) and B(I,:)) and the
   // diagonal leaf blocks of both cluster trees are gathered from A and the
   // children's updates.
-  struct Smp { const T* F; const T* C; const T* R; const int* I; const int* J; int ld; };
+  // F, ld: what the pivot kernel reads; C = B(:, J), R = B(I, :) (B_hat
+  // blocks; they become the cross residuals); Il, Jl: block-local I and J
+  struct Smp { const T* F; T* C; T* R; const int* I; const int* J; int ld; const int* Il; const int* Jl; };
   std::vector<Smp> smp;
+  const GatherFront<T>* dgf = nullptr;   // this level's fronts for the gathers (device)
+  std::map<int, int> gfi;                // front -> index in dgf
   std::map<int, std::vector<T*>> ppleaf, ffleaf;   // front -> leaf block per tree node
   if (sampled) {
     size_t tneed = 0;
@@ -1403,10 +1409,7 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
     for (int i = 0; i < nb; ++i) {
       const BR& x = br[i];
       const Block& B = s.fronts[x.p].blocks[x.bi];
-      if (!x.full) {
-        iota_n = std::max({iota_n, x.nI, x.nJ});
-        continue;
-      }
+      if (!x.full) iota_n = std::max({iota_n, x.nI, x.nJ});
       locI[i] = loc.size();
       for (int k = bIptr[x.lk]; k < bIptr[x.lk + 1]; ++k) loc.push_back(lb.I[k] - B.r0);
       locJ[i] = loc.size();
@@ -1434,7 +1437,6 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
     const int* dloc = reinterpret_cast<const int*>(ib + oloc);
     const int* dinv = reinterpret_cast<const int*>(ib + oinv);
     std::vector<GatherFront<T>> gf;
-    std::map<int, int> gfi;
     for (int p : Hs) {
       const Front& f = s.fronts[p];
       GatherFront<T> g{};
@@ -1464,7 +1466,7 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
       if (x.full) {
         T* R = stake((size_t)B.nr * B.nc);
         gat(x.p, nullptr, B.r0, B.nr, nullptr, B.c0, B.nc, R, B.nr);
-        smp[i] = Smp{R, nullptr, nullptr, dloc + locI[i], dloc + locJ[i], B.nr};
+        smp[i] = Smp{R, nullptr, nullptr, dloc + locI[i], dloc + locJ[i], B.nr, dloc + locI[i], dloc + locJ[i]};
         continue;
       }
       const int* Ib = dI + bIptr[x.lk];
@@ -1475,7 +1477,7 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
       gat(x.p, Ib, 0, x.nI, Jb, 0, x.nJ, Bh, std::max(x.nI, 1));
       gat(x.p, nullptr, B.r0, B.nr, Jb, 0, x.nJ, C, B.nr);
       gat(x.p, Ib, 0, x.nI, nullptr, B.c0, B.nc, R, std::max(x.nI, 1));
-      smp[i] = Smp{Bh, C, R, dloc + iota0, dloc + iota0, std::max(x.nI, 1)};
+      smp[i] = Smp{Bh, C, R, dloc + iota0, dloc + iota0, std::max(x.nI, 1), dloc + locI[i], dloc + locJ[i]};
     }
     for (int p : Hs) {
       const Front& f = s.fronts[p];
@@ -1508,9 +1510,9 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
       Blob bg;
       const size_t ogf = bg.add(gf), ogd = bg.add(gdv);
       const char* gb = dp.upload(bg, st);
-      launch_gather<T>(reinterpret_cast<const GatherDesc<T>*>(gb + ogd), (int)gdv.size(), (int)gtiles,
-                       reinterpret_cast<const GatherFront<T>*>(gb + ogf), d_rowptr.as<int>(), d_colind.as<int>(),
-                       d_vals.as<double>(), d_perm.as<int>(), st);
+      dgf = reinterpret_cast<const GatherFront<T>*>(gb + ogf);
+      launch_gather<T>(reinterpret_cast<const GatherDesc<T>*>(gb + ogd), (int)gdv.size(), (int)gtiles, dgf,
+                       d_rowptr.as<int>(), d_colind.as<int>(), d_vals.as<double>(), d_perm.as<int>(), st);
     }
   }
   Blob b;
@@ -1640,7 +1642,7 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
     HIPCHK(hipStreamWaitEvent(side, ev_fork, 0));
   }
   const int id_f = skf.empty() ? -1 : prof_begin(pk<T>(PK_SKREG_FULL_F64), fst, 0.0, 0.0);
-  launch_skreg_full<T>(reinterpret_cast<const SkRegDesc<T>*>(base + okf), (int)skf.size(), eps, adaptive ? 1 : 0,
+  launch_skreg_full<T>(reinterpret_cast<const SkRegDesc<T>*>(base + okf), (int)skf.size(), eps, opts.adaptive,
                        dstat, fst);
   prof_end(id_f, fst);
   if (fork) HIPCHK(hipEventRecord(ev_join, side));
@@ -1653,6 +1655,48 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
   int id_2 = -1;
   bool fork_joined = false;
   std::vector<int> coop_ids;
+  if (cross) {
+    // phase 2 on the sampled cross of every B_hat block: the samples become
+    // the residuals E(:, J) = B(:, J) - U V(J, :)^T and E(I, :) =
+    // B(I, :) - U(I, :) V^T (k = phase-1 rank, read on the device), then one
+    // workgroup per block pivots on them
+    GemmBatch<T> xres;
+    std::vector<CrossDesc<T>> xd;
+    int maxrc = 1;
+    for (int i = 0; i < nb; ++i) {
+      const BR& x = br[i];
+      if (x.full) continue;
+      const Block& B = s.fronts[x.p].blocks[x.bi];
+      const Smp& m = smp[i];
+      if (x.nJ > 0) {
+        auto g = gd<T>(x.U, B.nr, 0, x.V, B.nc, 1, m.C, B.nr, B.nr, x.nJ, x.kcap, -1.0, 1.0, 0, x.rank1);
+        g.brow = m.Jl;
+        xres.v.push_back(g);
+      }
+      if (x.nI > 0) {
+        auto g = gd<T>(x.U, B.nr, 0, x.V, B.nc, 1, m.R, x.nI, x.nI, B.nc, x.kcap, -1.0, 1.0, 0, x.rank1);
+        g.arow = m.Il;
+        xres.v.push_back(g);
+      }
+      CrossDesc<T> c{};
+      c.EJ = m.C; c.EI = m.R; c.Il = m.Il; c.Jl = m.Jl;
+      c.piv_r = x.pr; c.piv_c = x.pc; c.rank1 = x.rank1; c.u11 = x.u11;
+      c.U = x.U; c.V = x.V; c.rank = x.rank; c.front = dgf + gfi.at(x.p);
+      c.r0 = B.r0; c.c0 = B.c0; c.nr = B.nr; c.nc = B.nc; c.nI = x.nI; c.nJ = x.nJ; c.cap = x.capr;
+      xd.push_back(c);
+      maxrc = std::max(maxrc, B.nr + B.nc);
+    }
+    if (!xd.empty()) {
+      if (maxrc > kLdsMax) throw Err{MF_EINVAL, "block too large for the cross kernel"};
+      Blob bx;
+      const size_t ox = bx.add(xd);
+      xres.stage(bx, &split);
+      const char* bxb = dp.upload(bx, st);
+      xres.launch(bxb, st);
+      launch_cross<T>(reinterpret_cast<const CrossDesc<T>*>(bxb + ox), (int)xd.size(), maxrc, eps,
+                      d_rowptr.as<int>(), d_colind.as<int>(), d_vals.as<double>(), d_perm.as<int>(), dstat, st);
+    }
+  }
   if (adaptive) {
     resid.launch(base, st);
     id_2 = p2.empty() ? -1 : prof_begin(pk<T>(PK_PHASE2_F64), st, 0.0, 0.0);

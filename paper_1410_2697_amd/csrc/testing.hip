@@ -17,9 +17,11 @@ mf_status hip_ok(hipError_t e) {
 
 template <typename T>
 mf_status gemm_t(int m, int n, int k, const void* A, int lda, int opA, const void* B, int ldb, int opB, void* C,
-                 int ldc, double alpha, double beta, int flags, int kchunk, const int* brow = nullptr) {
+                 int ldc, double alpha, double beta, int flags, int kchunk, const int* arow = nullptr,
+                 const int* brow = nullptr) {
   mfh::GemmDesc<T> d{};
-  d.A = static_cast<const T*>(A); d.B = static_cast<const T*>(B); d.C = static_cast<T*>(C); d.brow = brow;
+  d.A = static_cast<const T*>(A); d.B = static_cast<const T*>(B); d.C = static_cast<T*>(C);
+  d.arow = arow; d.brow = brow;
   d.m = m; d.n = n; d.k = k; d.lda = lda; d.ldb = ldb; d.ldc = ldc; d.opA = opA; d.opB = opB;
   d.flags = flags; d.alpha = alpha; d.beta = beta;
   // at most 16 columns: the 64 x 16 tile variant (the reduction walks 64 x 64 tiles)
@@ -208,12 +210,12 @@ mf_status mfh_test_gemm(int32_t precision, int32_t m, int32_t n, int32_t k, cons
 }
 
 mf_status mfh_test_gemm_rows(int32_t precision, int32_t m, int32_t n, int32_t k, const void* A, int32_t lda,
-                             int32_t opA, const void* B, int32_t ldb, const int32_t* brow, void* C, int32_t ldc,
-                             double alpha, double beta, int32_t kchunk) {
-  if (m < 0 || n < 0 || k < 0 || !C || !brow || kchunk < 0 || kchunk % mfh::kGemmSplitAlign != 0) return MF_EINVAL;
+                             int32_t opA, const int32_t* arow, const void* B, int32_t ldb, int32_t opB,
+                             const int32_t* brow, void* C, int32_t ldc, double alpha, double beta, int32_t kchunk) {
+  if (m < 0 || n < 0 || k < 0 || !C || kchunk < 0 || kchunk % mfh::kGemmSplitAlign != 0) return MF_EINVAL;
   if (precision == MF_FP64)
-    return gemm_t<double>(m, n, k, A, lda, opA, B, ldb, 0, C, ldc, alpha, beta, 0, kchunk, brow);
-  return gemm_t<float>(m, n, k, A, lda, opA, B, ldb, 0, C, ldc, alpha, beta, 0, kchunk, brow);
+    return gemm_t<double>(m, n, k, A, lda, opA, B, ldb, opB, C, ldc, alpha, beta, 0, kchunk, arow, brow);
+  return gemm_t<float>(m, n, k, A, lda, opA, B, ldb, opB, C, ldc, alpha, beta, 0, kchunk, arow, brow);
 }
 
 mf_status mfh_test_potrf(int32_t precision, int32_t n, void* A, int32_t lda, void* Inv, int32_t ldi,

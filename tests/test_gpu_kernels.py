@@ -328,29 +328,45 @@ def test_gemm_bf16_operands(gpu_lib, n, bf, opA, opB):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("m,n,k,opA,kchunk", [(90, 16, 300, 1, 0), (90, 16, 300, 1, 128), (40, 5, 77, 0, 0),
-                                              (130, 40, 200, 1, 64)])
-def test_gemm_row_map(gpu_lib, prec, m, n, k, opA, kchunk):
-    """op(B) = B(brow, :) through a row map (the apply's read of x(I_p^f)):
-    equal to the product with the gathered rows."""
+@pytest.mark.parametrize("m,n,k,opA,opB,amap,bmap,kchunk", [
+    (90, 16, 300, 1, 0, False, True, 0), (90, 16, 300, 1, 0, False, True, 128), (40, 5, 77, 0, 0, False, True, 0),
+    (130, 40, 200, 1, 0, False, True, 64), (70, 9, 50, 0, 1, True, False, 0), (70, 9, 50, 0, 1, False, True, 0),
+    (150, 100, 40, 0, 1, True, True, 0), (33, 16, 200, 1, 1, True, True, 128)])
+def test_gemm_row_map(gpu_lib, prec, m, n, k, opA, opB, amap, bmap, kchunk):
+    """Row maps on the stored A and B (the apply's read of x(I_p^f), the
+    sampled skeleton's read of its bases' sampled rows): equal to the product
+    of the gathered arrays."""
     import torch
     dt = torch.float64 if prec == "fp64" else torch.float32
-    rng = np.random.default_rng(m + n + k)
-    nb = 3 * k + 11
-    Bfull = rng.standard_normal((nb, n))
-    rows = np.sort(rng.choice(nb, k, replace=False)).astype(np.int32)
+    rng = np.random.default_rng(m + n + k + 7 * opB)
     Aop = rng.standard_normal((m, k))
-    A = Aop.T.copy() if opA else Aop
+    Bop = rng.standard_normal((k, n))
+    A = Aop.T.copy() if opA else Aop       # stored arrays (before the maps)
+    B = Bop.T.copy() if opB else Bop
+
+    def embed(X, use):
+        if not use:
+            return X, None
+        rows = X.shape[0]
+        big = rng.standard_normal((3 * rows + 5, X.shape[1]))
+        idx = np.sort(rng.choice(big.shape[0], rows, replace=False)).astype(np.int32)
+        big[idx] = X
+        return big, idx
+
+    As, ai = embed(A, amap)
+    Bs, bi = embed(B, bmap)
+    lda, ldb, ldc = As.shape[0] + 2, Bs.shape[0] + 1, m + 1
     C0 = rng.standard_normal((m, n))
-    lda, ldb, ldc = A.shape[0] + 2, nb, m + 1
-    dA, dB, dC = _dev(A, lda, dt), _dev(Bfull, ldb, dt), _dev(C0, ldc, dt)
-    drows = torch.tensor(rows, device="cuda")
-    st = gpu_lib.load().mfh_test_gemm_rows(0 if prec == "fp64" else 1, m, n, k, _p(dA), lda, opA, _p(dB), ldb,
-                                           _p(drows), _p(dC), ldc, -1.0, 1.0, kchunk)
+    dA, dB, dC = _dev(As, lda, dt), _dev(Bs, ldb, dt), _dev(C0, ldc, dt)
+    dai = torch.tensor(ai, device="cuda") if amap else None
+    dbi = torch.tensor(bi, device="cuda") if bmap else None
+    st = gpu_lib.load().mfh_test_gemm_rows(0 if prec == "fp64" else 1, m, n, k, _p(dA), lda, opA,
+                                           _p(dai) if amap else None, _p(dB), ldb, opB, _p(dbi) if bmap else None,
+                                           _p(dC), ldc, -1.0, 1.0, kchunk)
     assert st == 0
     cast = np.float32 if prec == "fp32" else np.float64
     Ar = A.astype(cast).astype(np.float64)
-    Br = Bfull.astype(cast).astype(np.float64)[rows]
-    ref = C0.astype(cast).astype(np.float64) - (Ar.T if opA else Ar) @ Br
+    Br = B.astype(cast).astype(np.float64)
+    ref = C0.astype(cast).astype(np.float64) - (Ar.T if opA else Ar) @ (Br.T if opB else Br)
     tol = 1e-13 if prec == "fp64" else 2e-5
     assert np.abs(_host(dC, m) - ref).max() <= tol * np.sqrt(k) * max(1.0, np.abs(ref).max())
