@@ -186,6 +186,15 @@ __device__ __forceinline__ void gemm_tile_body(const GemmDesc<T>& d, int lt, Gem
   // op N: row = tid & 63, k = (tid >> 6) + 4q;   op T: k = tid % BK, row = tid / BK + (256 / BK) q
   T ra[NQ], rb[NQB];
   auto load = [&](int kb) {
+    // A thread's loads of one operand all fall in one stored row (op N of A:
+    // row tid & 63; op T of A and op N of B: k = tid % BK; op T of B: column
+    // tid % BN), so a row map costs one index load per operand and k block,
+    // issued ahead of the data loads; clamped indices keep it in the map.
+    int amap = 0, bmap = 0;
+    if constexpr (ROWS) {
+      if (arow) amap = arow[opA == 0 ? min(m0 + (tid & 63), m - 1) : min(kb + tid % BK, kend - 1)];
+      if (brow) bmap = brow[opB == 0 ? min(kb + tid % BK, kend - 1) : min(n0 + tid % BN, n - 1)];
+    }
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       int i, kk;
@@ -194,7 +203,7 @@ __device__ __forceinline__ void gemm_tile_body(const GemmDesc<T>& d, int lt, Gem
       const int gi = m0 + i, gk = kb + kk;
       const bool ok = gi < m && gk < kend;
       int sr = opA == 0 ? gi : gk;   // stored row
-      if constexpr (ROWS) sr = (ok && arow) ? arow[sr] : sr;
+      if constexpr (ROWS) sr = arow ? amap : sr;
       ra[q] = ok ? load_op(A, opA == 0 ? sr + (size_t)gk * lda : sr + (size_t)gi * lda, abf) : (T)0;
     }
 #pragma unroll
@@ -205,7 +214,7 @@ __device__ __forceinline__ void gemm_tile_body(const GemmDesc<T>& d, int lt, Gem
       const int gj = n0 + j, gk = kb + kk;
       const bool ok = gj < n && gk < kend;
       int sr = opB == 0 ? gk : gj;   // stored row
-      if constexpr (ROWS) sr = (ok && brow) ? brow[sr] : sr;
+      if constexpr (ROWS) sr = brow ? bmap : sr;
       rb[q] = ok ? load_op(B, opB == 0 ? sr + (size_t)gj * ldb : sr + (size_t)gk * ldb, bbf) : (T)0;
     }
   };
