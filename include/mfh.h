@@ -156,6 +156,29 @@ mf_status mf_analyze(int32_t n, const int32_t* rowptr, const int32_t* colind,
 mf_status mf_symbolic_get_info(const mf_symbolic_t* s, mf_symbolic_info* info);
 
 /*
+ * Analysis of the block-diagonal matrix diag(A_1, ..., A_k) from the
+ * analyses of A_1, ..., A_k, for factoring independent systems together:
+ * the elimination forest is the disjoint union of the parts' trees and the
+ * fronts of every part at one height share an etree level, so one
+ * factorisation and one apply process all parts' fronts of a level in the
+ * same launches (Sec. 4.1: fronts of one level are independent).
+ *   parts    host array of `count` (>= 1) analysis handles, all with the
+ *            same leaf size and dimension; read only, still owned by the
+ *            caller (they may be freed after the call)
+ *   out      receives a new handle (free with mf_symbolic_free)
+ * Layout of the merged system: rows of part i follow those of parts
+ * 0..i-1 (offset n_0 + ... + n_{i-1}); its CSR pattern is the parts'
+ * patterns in that order, so its values for mf_factor are the parts' value
+ * arrays concatenated.  Fronts and blocks are numbered part by part (the
+ * exports and mf_factor_ranks list part 0's first).  The merged order and
+ * fronts are the parts' own, shifted: factoring the merged system gives
+ * every part the ranks it gets alone.
+ * Errors: MF_EINVAL for count < 1, a null handle, differing leaf size or
+ * dimension, or more than 2^31 - 1 unknowns or entries in total.
+ */
+mf_status mf_symbolic_merge(const mf_symbolic_t* const* parts, int32_t count, mf_symbolic_t** out);
+
+/*
  * Read-only export of the analysis, for bit-exact comparison.  `what`
  * selects an int32 array (codes below); if buf is NULL or cap is too small,
  * only *len is set.  BDLR sets (Sec. 2.2) need mf_symbolic_bdlr first.
@@ -324,6 +347,16 @@ mf_status mf_estimate_bytes(const mf_symbolic_t* sym, const mf_opts* opts, int32
  *    solve at a time: a resolve waits while another solve of the same factor
  *    runs, and requests queued behind it may start first.  Resident factors that no request is
  *    using are dropped, least recently used first, when memory is needed.
+ *  - With merge > 1 (and no keep_factors), a slot that admits a request
+ *    also takes the requests queued right behind it, in arrival order, up to
+ *    `merge` requests and 16 right-hand sides in all, while their summed
+ *    estimates (plus the merged solve's vectors) fit the budget.  It factors
+ *    them as one block-diagonal system (mf_symbolic_merge: fronts of every
+ *    request at one etree level share the level's launches) and solves them
+ *    with one GMRES call in which each request's right-hand sides are their
+ *    own columns, zero outside its rows: every column's iteration is the one
+ *    it has alone, and each request gets its own x, status and iteration
+ *    counts (the factor and solve times are the group's).
  *  - With keep_factors, a request's factor stays on the device after its
  *    solve; mf_server_resolve queues another solve with it (repeated
  *    right-hand sides) until mf_server_release.
@@ -341,7 +374,8 @@ typedef struct {
   mf_opts factor;         /* factorisation options (stream ignored)                           */
   mf_gmres_opts gmres;    /* GMRES options (stream ignored)                                   */
   int32_t keep_factors;   /* 1: keep each factor resident for mf_server_resolve               */
-  int32_t reserved;
+  int32_t merge;          /* 1..16: most queued requests a slot factors and solves together
+                             (1: one at a time; ignored with keep_factors)                   */
 } mf_server_opts;
 
 typedef struct {
@@ -356,6 +390,8 @@ typedef struct {
   int64_t est_bytes;      /* estimated peak used for admission                                 */
   int64_t peak_bytes;     /* peak device bytes of its factorisation                            */
   int64_t resident_bytes; /* device bytes its factor keeps (if resident)                       */
+  int32_t group_size;     /* requests factored and solved together with it (itself included)   */
+  int32_t reserved;
 } mf_request_info;
 
 mf_status mf_server_opts_default(mf_server_opts* o);

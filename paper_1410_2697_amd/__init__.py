@@ -65,14 +65,15 @@ class FactorInfo(ctypes.Structure):
 class ServerOpts(ctypes.Structure):
     _fields_ = [("slots", ctypes.c_int32), ("leaf", ctypes.c_int32), ("mem_budget", ctypes.c_int64),
                 ("tol", ctypes.c_double), ("factor", MfOpts), ("gmres", GmresOpts),
-                ("keep_factors", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("keep_factors", ctypes.c_int32), ("merge", ctypes.c_int32)]
 
 
 class RequestInfo(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iters_max", ctypes.c_int32), ("relres_max", ctypes.c_double),
                 ("t_queue", ctypes.c_double), ("t_analyze", ctypes.c_double), ("t_factor", ctypes.c_double),
                 ("t_solve", ctypes.c_double), ("t_total", ctypes.c_double), ("est_bytes", ctypes.c_int64),
-                ("peak_bytes", ctypes.c_int64), ("resident_bytes", ctypes.c_int64)]
+                ("peak_bytes", ctypes.c_int64), ("resident_bytes", ctypes.c_int64), ("group_size", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class KStat(ctypes.Structure):
@@ -92,6 +93,7 @@ SIGNATURES = [
     ("mf_opts_default", _I32, [ctypes.POINTER(MfOpts)]),
     ("mf_gmres_opts_default", _I32, [ctypes.POINTER(GmresOpts)]),
     ("mf_analyze", _I32, [_I32, _P, _P, _P, _I32, _I32, ctypes.POINTER(_P)]),
+    ("mf_symbolic_merge", _I32, [_P, _I32, ctypes.POINTER(_P)]),
     ("mf_symbolic_get_info", _I32, [_P, ctypes.POINTER(SymbolicInfo)]),
     ("mf_symbolic_export", _I32, [_P, _I32, _P, _I64, ctypes.POINTER(_I64)]),
     ("mf_symbolic_bdlr", _I32, [_P, _I32, _I32]),
@@ -191,6 +193,20 @@ class Symbolic:
     @classmethod
     def from_csr(cls, A, coords, leaf):
         return cls(A.n, A.rowptr, A.colind, coords, leaf)
+
+    @classmethod
+    def merge(cls, parts):
+        """mf_symbolic_merge: the analysis of diag(A_1, ..., A_k); factor it
+        with the parts' value arrays concatenated."""
+        lib = load()
+        arr = (ctypes.c_void_p * len(parts))(*[p.h for p in parts])
+        h = ctypes.c_void_p()
+        _check(lib.mf_symbolic_merge(arr, len(parts), ctypes.byref(h)))
+        self = cls.__new__(cls)
+        self.n = sum(p.n for p in parts)
+        self.leaf = parts[0].leaf
+        self.h = h
+        return self
 
     def info(self) -> dict:
         i = SymbolicInfo()
@@ -360,12 +376,13 @@ class Server:
     (n, nrhs).  Calls release the interpreter lock while they block."""
 
     def __init__(self, slots: int = 4, leaf: int = 128, mem_budget: int = 0, tol: float = 1e-10,
-                 keep_factors: bool = False, restart: int = 30, maxit: int = 4000, **factor_kw):
+                 keep_factors: bool = False, restart: int = 30, maxit: int = 4000, merge: int = 1, **factor_kw):
         lib = load()
         o = ServerOpts()
         _check(lib.mf_server_opts_default(ctypes.byref(o)))
         o.slots, o.leaf, o.mem_budget, o.tol = int(slots), int(leaf), int(mem_budget), float(tol)
         o.keep_factors = 1 if keep_factors else 0
+        o.merge = int(merge)
         o.factor = default_opts(**factor_kw)
         o.gmres.restart, o.gmres.maxit = int(restart), int(maxit)
         h = ctypes.c_void_p()

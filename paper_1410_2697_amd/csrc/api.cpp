@@ -97,6 +97,24 @@ mf_status mf_analyze(int32_t n, const int32_t* rowptr, const int32_t* colind, co
   MF_GUARD_END
 }
 
+mf_status mf_symbolic_merge(const mf_symbolic_t* const* parts, int32_t count, mf_symbolic_t** out) {
+  MF_GUARD_BEGIN
+  if (!out) return fail(MF_EINVAL, "null output handle");
+  *out = nullptr;
+  if (!parts || count < 1) return fail(MF_EINVAL, "no analyses to merge");
+  std::vector<const mfh::Symbolic*> v(count);
+  for (int i = 0; i < count; ++i) {
+    if (!parts[i]) return fail(MF_EINVAL, "null analysis handle");
+    v[i] = &parts[i]->s;
+  }
+  auto h = std::make_unique<mf_symbolic_s>();
+  std::string e = mfh::merge(v, h->s);
+  if (!e.empty()) return fail(MF_EINVAL, e);
+  *out = h.release();
+  return MF_OK;
+  MF_GUARD_END
+}
+
 mf_status mf_symbolic_get_info(const mf_symbolic_t* sh, mf_symbolic_info* info) {
   if (!sh || !info) return fail(MF_EINVAL, "null argument");
   const mfh::Symbolic& s = sh->s;
@@ -350,6 +368,7 @@ mf_status mf_server_opts_default(mf_server_opts* o) {
   mf_opts_default(&o->factor);
   mf_gmres_opts_default(&o->gmres);
   o->keep_factors = 0;
+  o->merge = 1;
   return MF_OK;
 }
 
@@ -371,6 +390,7 @@ mf_status mf_server_create(const mf_server_opts* o, mf_server_t** out) {
   if (!(fo.eps >= 0.0) || fo.eps >= 1.0) return fail(MF_EINVAL, "eps must be in [0, 1)");
   if (so.gmres.restart < 1 || so.gmres.restart > 60 || so.gmres.maxit < 1)
     return fail(MF_EINVAL, "restart must be 1..60, maxit >= 1");
+  if (so.merge < 1 || so.merge > 16) return fail(MF_EINVAL, "merge must be 1..16");
   mf_status g = gpu_present();
   if (g != MF_OK) return g;
   auto h = std::make_unique<mf_server_s>();

@@ -8,6 +8,8 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdint>
+#include <iterator>
 
 namespace mfh {
 namespace {
@@ -146,6 +148,32 @@ bool Server::admit_locked(Req& r, std::vector<std::unique_ptr<Factor>>& evicted)
   return running_ == 0;           // larger than the whole budget: run alone
 }
 
+// Requests that join an admitted submit request: the ones queued right
+// behind it, in arrival order, while each is a submit request, the group
+// stays within `merge` requests and kMergeCols right-hand sides, and the
+// summed estimates plus the merged solve's vectors fit the budget; the
+// first that does not qualify ends the group.
+int64_t Server::group_locked(std::deque<int64_t>::iterator it, std::vector<int64_t>& ids) {
+  constexpr int kMergeCols = 16;
+  const Req& h = *reqs_[*it];
+  ids.assign(1, *it);
+  int64_t est = h.est;
+  if (h.resolve || o_.keep_factors || o_.merge <= 1 || h.nrhs > kMergeCols) return est;
+  int64_t n = h.n;
+  int cols = h.nrhs;
+  for (auto q = std::next(it); q != queue_.end() && (int)ids.size() < o_.merge; ++q) {
+    const Req& r = *reqs_[*q];
+    if (r.resolve || cols + r.nrhs > kMergeCols || r.sym->leaf != h.sym->leaf || r.sym->dim != h.sym->dim) break;
+    const int64_t add = est + r.est + solve_bytes((int)std::min<int64_t>(n + r.n, INT32_MAX), cols + r.nrhs);
+    if (in_use_ + add > budget_) break;
+    ids.push_back(*q);
+    est += r.est;
+    n += r.n;
+    cols += r.nrhs;
+  }
+  return ids.size() > 1 ? est + solve_bytes((int)std::min<int64_t>(n, INT32_MAX), cols) : est;
+}
+
 void Server::worker() {
   (void)hipSetDevice(dev_);
   hipStream_t st = nullptr;
@@ -156,7 +184,8 @@ void Server::worker() {
   DevBuf db, dx;
   for (;;) {
     std::vector<std::unique_ptr<Factor>> evicted;
-    Req* r = nullptr;
+    std::vector<Req*> group;
+    int64_t charge = 0;
     {
       std::unique_lock<std::mutex> lk(mu_);
       auto pick = queue_.end();
@@ -167,22 +196,31 @@ void Server::worker() {
         cv_work_.wait(lk);
       }
       if (stop_) break;
-      r = reqs_[*pick].get();
-      queue_.erase(pick);
-      if (r->resolve) factors_.at(r->factor_id)->busy = true;
-      r->state = 1;
-      r->info.t_queue = now() - r->t_submit;
-      in_use_ += r->est;
+      std::vector<int64_t> ids;
+      charge = group_locked(pick, ids);
+      for (int64_t id : ids) {
+        Req* r = reqs_[id].get();
+        queue_.erase(std::find(queue_.begin(), queue_.end(), id));
+        if (r->resolve) factors_.at(r->factor_id)->busy = true;
+        r->state = 1;
+        r->info.t_queue = now() - r->t_submit;
+        r->info.group_size = (int32_t)ids.size();
+        group.push_back(r);
+      }
+      in_use_ += charge;
       ++running_;
     }
     evicted.clear();              // waits for their streams, outside the lock
-    run(*r, st, db, dx);
+    if (group.size() == 1) run(*group[0], st, db, dx);
+    else run_merged(group, st, db, dx);
     {
       std::lock_guard<std::mutex> g(mu_);
-      in_use_ -= r->est;
+      in_use_ -= charge;
       --running_;
-      r->state = 2;
-      r->info.t_total = now() - r->t_submit;
+      for (Req* r : group) {
+        r->state = 2;
+        r->info.t_total = now() - r->t_submit;
+      }
     }
     cv_done_.notify_all();
     cv_work_.notify_all();
@@ -286,6 +324,96 @@ void Server::run(Req& r, hipStream_t st, DevBuf& db, DevBuf& dx) {
   }
   drop.reset();
   own.reset();
+}
+
+void Server::run_merged(const std::vector<Req*>& rs, hipStream_t st, DevBuf& db, DevBuf& dx) {
+  const int k = (int)rs.size();
+  std::vector<int64_t> no(k + 1, 0);
+  std::vector<int> co(k + 1, 0);
+  for (int i = 0; i < k; ++i) {
+    no[i + 1] = no[i] + rs[i]->n;
+    co[i + 1] = co[i] + rs[i]->nrhs;
+  }
+  const int64_t N = no[k];
+  const int C = co[k];
+  Symbolic msym;                  // outlives the factor below, which refers to it
+  std::unique_ptr<NumericBase> num;
+  try {
+    const double t0 = now();
+    std::vector<const Symbolic*> parts;
+    size_t nv = 0;
+    for (Req* r : rs) {
+      parts.push_back(r->sym.get());
+      nv += r->vals.size();
+    }
+    const std::string e = merge(parts, msym);
+    if (!e.empty()) throw Err{MF_EINVAL, e};
+    std::vector<double> vals;
+    vals.reserve(nv);
+    for (Req* r : rs) vals.insert(vals.end(), r->vals.begin(), r->vals.end());
+    mf_opts fo = o_.factor;
+    fo.stream = st;
+    for (int attempt = 0;; ++attempt) {   // the same single retry as a request alone
+      try {
+        num = make_numeric(msym, vals.data(), fo);
+        break;
+      } catch (const Err& e2) {
+        if (attempt > 0 || e2.code != MF_EHIP || e2.msg.rfind(kPhase2WaitMsg, 0) != 0) throw;
+      }
+    }
+    const double t_factor = now() - t0;
+    // request i's right-hand sides in columns co[i].., zero outside its rows
+    const double t1 = now();
+    std::vector<double> B((size_t)N * C, 0.0);
+    for (int i = 0; i < k; ++i)
+      for (int c = 0; c < rs[i]->nrhs; ++c)
+        std::copy(rs[i]->b.begin() + (size_t)c * rs[i]->n, rs[i]->b.begin() + (size_t)(c + 1) * rs[i]->n,
+                  B.begin() + (size_t)(co[i] + c) * N + no[i]);
+    const size_t bytes = (size_t)N * C * sizeof(double);
+    db.ensure(bytes, nullptr, st);
+    dx.ensure(bytes, nullptr, st);
+    HIPCHK(hipMemcpyAsync(db.p, B.data(), bytes, hipMemcpyHostToDevice, st));
+    mf_gmres_opts go = o_.gmres;
+    go.stream = st;
+    std::vector<mf_gmres_info> gi(C);
+    mf_status s = MF_OK;
+    num->gmres(C, db.as<double>(), dx.as<double>(), o_.tol, go, gi.data(), &s);
+    HIPCHK(hipMemcpyAsync(B.data(), dx.p, bytes, hipMemcpyDeviceToHost, st));
+    num->note_stream(st);
+    HIPCHK(hipStreamSynchronize(st));
+    const double t_solve = now() - t1;
+    for (int i = 0; i < k; ++i) {
+      Req& r = *rs[i];
+      r.x.resize((size_t)r.n * r.nrhs);
+      bool conv = true;
+      for (int c = 0; c < r.nrhs; ++c) {
+        std::copy(B.begin() + (size_t)(co[i] + c) * N + no[i], B.begin() + (size_t)(co[i] + c) * N + no[i + 1],
+                  r.x.begin() + (size_t)c * r.n);
+        const mf_gmres_info& g = gi[co[i] + c];
+        r.info.iters_max = std::max(r.info.iters_max, g.iters);
+        r.info.relres_max = std::max(r.info.relres_max, g.relres);
+        conv &= g.converged != 0;
+      }
+      r.status = conv ? MF_OK : MF_ENOCONV;
+      if (!conv) r.err = "GMRES did not reach tol within maxit";
+      r.info.t_factor = t_factor;
+      r.info.t_solve = t_solve;
+      r.info.peak_bytes = num->ms.peak;
+    }
+  } catch (const Err& e) {
+    for (Req* r : rs) { r->status = e.code; r->err = e.msg; }
+  } catch (const std::bad_alloc&) {
+    for (Req* r : rs) { r->status = MF_ENOMEM; r->err = "host allocation failed"; }
+  } catch (const std::exception& e) {
+    for (Req* r : rs) { r->status = MF_EINVAL; r->err = e.what(); }
+  }
+  num.reset();
+  for (Req* r : rs) {
+    r->info.status = r->status;
+    r->vals.clear();
+    r->vals.shrink_to_fit();
+    r->sym.reset();
+  }
 }
 
 void Server::wait(int64_t ticket, double* x, mf_request_info* info) {

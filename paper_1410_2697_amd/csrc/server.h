@@ -58,6 +58,11 @@ class Server {
 
   void worker();
   void run(Req& r, hipStream_t st, DevBuf& db, DevBuf& dx);
+  // several submitted requests factored and solved as one block-diagonal system
+  void run_merged(const std::vector<Req*>& rs, hipStream_t st, DevBuf& db, DevBuf& dx);
+  // requests queued right behind the admitted head `it` that join its group
+  // (lock held); returns the group's device-byte charge
+  int64_t group_locked(std::deque<int64_t>::iterator it, std::vector<int64_t>& ids);
   // next admissible queued request (lock held), or queue_.end(): requests
   // are taken in arrival order, except that a resolve whose factor is busy
   // with another solve is passed over; evicted factors are moved out

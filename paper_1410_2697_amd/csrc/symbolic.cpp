@@ -365,6 +365,80 @@ std::string analyze(int n, const int32_t* rowptr, const int32_t* colind, const d
   return "";
 }
 
+// Analysis of the block-diagonal matrix diag(A_1, ..., A_k) from those of
+// its blocks.  The nested dissection of a block-diagonal matrix may keep
+// each block's own order: no entry couples two blocks, so the elimination
+// forest is the disjoint union of the blocks' trees, each front keeps its
+// frontal sets, relative maps and cluster trees, and only global indices
+// shift (rows of block i by n_1 + ... + n_{i-1}, fronts by the number of
+// fronts before it).  Levels are by height, so fronts of every block that
+// sit at one height share a level (Sec. 4.1: the fronts of one level are
+// independent).  BDLR caches are dropped: the factorisation forms its sets
+// per front.
+std::string merge(const std::vector<const Symbolic*>& parts, Symbolic& s) {
+  if (parts.empty()) return "no analyses to merge";
+  for (const Symbolic* q : parts) {
+    if (!q) return "null analysis";
+    if (q->leaf != parts[0]->leaf || q->dim != parts[0]->dim) return "analyses differ in leaf size or dimension";
+  }
+  int64_t n = 0, nnz = 0, nfr = 0, nb = 0;
+  int hmax = 0;
+  for (const Symbolic* q : parts) {
+    n += q->n;
+    nnz += q->nnz;
+    nfr += (int64_t)q->fronts.size();
+    nb += q->nblocks;
+    hmax = std::max(hmax, (int)q->levels.size());
+  }
+  if (n > std::numeric_limits<int32_t>::max() || nnz > std::numeric_limits<int32_t>::max())
+    return "merged analysis exceeds 32-bit indices";
+  s = Symbolic();
+  s.n = (int)n; s.leaf = parts[0]->leaf; s.dim = parts[0]->dim; s.nnz = nnz;
+  s.rowptr.resize(n + 1);
+  s.colind.resize(nnz);
+  s.prow.resize(n + 1);
+  s.pcol.resize(nnz);
+  s.perm.resize(n);
+  s.iperm.resize(n);
+  s.fronts.reserve(nfr);
+  s.levels.assign(hmax, {});
+  s.block_base.reserve(nfr + 1);
+  int no = 0, fo = 0, bo = 0;
+  int64_t eo = 0;
+  for (const Symbolic* q : parts) {
+    for (int r = 0; r < q->n; ++r) {
+      s.rowptr[no + r] = (int)(eo + q->rowptr[r]);
+      s.prow[no + r] = (int)(eo + q->prow[r]);
+      s.perm[no + r] = no + q->perm[r];
+      s.iperm[no + r] = no + q->iperm[r];
+    }
+    for (int64_t k = 0; k < q->nnz; ++k) {
+      s.colind[eo + k] = no + q->colind[k];
+      s.pcol[eo + k] = no + q->pcol[k];
+    }
+    for (const Front& f : q->fronts) {
+      Front g = f;
+      g.start += no;
+      for (int& v : g.upd) v += no;
+      if (g.parent >= 0) g.parent += fo;
+      for (int& c : g.children) c += fo;
+      s.fronts.push_back(std::move(g));
+    }
+    for (size_t h = 0; h < q->levels.size(); ++h)
+      for (int p : q->levels[h]) s.levels[h].push_back(fo + p);
+    for (size_t p = 0; p < q->fronts.size(); ++p) s.block_base.push_back(bo + q->block_base[p]);
+    no += q->n;
+    eo += q->nnz;
+    fo += (int)q->fronts.size();
+    bo += q->nblocks;
+  }
+  s.rowptr[n] = (int)nnz;
+  s.prow[n] = (int)nnz;
+  s.block_base.push_back(bo);
+  s.nblocks = bo;
+  return "";
+}
+
 // Assembly map of A's lower entries (F_bar_p, Eq. fbar), in CSR order: the
 // front, the row and column inside it, and the entry's index in A.  Rows are
 // split over workers: one pass counts each row's lower entries, a second

@@ -77,6 +77,9 @@ void assembly_map(const Symbolic& s, bigvec<int>& front, bigvec<int>& row, bigve
 // Returns "" on success or an error message.
 std::string analyze(int n, const int32_t* rowptr, const int32_t* colind, const double* coords,
                     int dim, int leaf, Symbolic& out);
+// Analysis of diag(A_1, ..., A_k) from the analyses of A_1, ..., A_k (equal
+// leaf size and dimension).  Returns "" on success or an error message.
+std::string merge(const std::vector<const Symbolic*>& parts, Symbolic& out);
 // Reusable buffers for BDLR set construction.
 struct BdlrScratch {
   std::vector<int> pos_of, adjp, adj, dist, frontier, nxt;

@@ -6,7 +6,7 @@ coefficients; grid sides are drawn uniformly from a set, arrivals are
 Poisson at a rate given as a fraction of the measured capacity.  All inputs
 are generated before the clock starts.  Prints one JSON line.
 
-    python -m paper_1410_2697_amd.serve --count 64 --slots 4 --rate-frac 0.8
+    python -m paper_1410_2697_amd.serve --count 64 --slots 4 --rate-frac 0.8 [--merge 4]
 """
 from __future__ import annotations
 
@@ -20,10 +20,10 @@ import time
 import numpy as np
 
 
-def _run(mfh, reqs, times, slots, mem_budget, kw):
+def _run(mfh, reqs, times, slots, mem_budget, kw, merge=1):
     """Submit request i at times[i] (seconds from start); returns per-request
     (latency, info) and the makespan."""
-    sv = mfh.Server(slots=slots, mem_budget=mem_budget, **kw)
+    sv = mfh.Server(slots=slots, mem_budget=mem_budget, merge=merge, **kw)
     tickets = [None] * len(reqs)
     submitted = threading.Event()
     t0 = time.perf_counter()
@@ -63,6 +63,7 @@ def main(argv=None):
     ap.add_argument("--rate-frac", type=float, default=0.8)
     ap.add_argument("--mem-budget", type=int, default=0)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--merge", type=int, default=1, help="most queued requests factored and solved together")
     args = ap.parse_args(argv)
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     import paper_1410_2697_amd as mfh
@@ -79,14 +80,14 @@ def main(argv=None):
     print(f"[serve] generated {len(reqs)} requests in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
     kw = dict(leaf=128, tol=1e-10, eps=1e-4, precision="fp32", n_c=512)
     # capacity: everything submitted at once (a warm-up pass first)
-    _run(mfh, reqs[: min(4, len(reqs))], [0.0] * min(4, len(reqs)), args.slots, args.mem_budget, kw)
-    out, span, peak_use, budget = _run(mfh, reqs, [0.0] * len(reqs), args.slots, args.mem_budget, kw)
+    _run(mfh, reqs[: min(4, len(reqs))], [0.0] * min(4, len(reqs)), args.slots, args.mem_budget, kw, args.merge)
+    out, span, peak_use, budget = _run(mfh, reqs, [0.0] * len(reqs), args.slots, args.mem_budget, kw, args.merge)
     capacity = len(reqs) / span
     print(f"[serve] capacity {capacity:.2f} requests/s ({span:.2f} s for {len(reqs)})", file=sys.stderr, flush=True)
     # Poisson arrivals at rate_frac x capacity
     rate = args.rate_frac * capacity
     gaps = np.array([a for (a, _, _) in serving_requests(args.count, args.seed, rate, sides)])
-    out2, span2, peak_use2, _ = _run(mfh, reqs, list(gaps), args.slots, args.mem_budget, kw)
+    out2, span2, peak_use2, _ = _run(mfh, reqs, list(gaps), args.slots, args.mem_budget, kw, args.merge)
     lat = np.sort([o[0] for o in out2])
     ok = [o[1]["status"] == 0 for o in out2]
     solves = sum(w.b.shape[1] for w in reqs)
@@ -98,7 +99,9 @@ def main(argv=None):
     worst = max(rel_residual(w, o[2]) for w, o in zip(reqs, out2))
     res = {
         "metric": "serving: requests/s and per-request latency (submit to solution)",
-        "requests": len(reqs), "sides": list(sides), "nrhs": args.nrhs, "slots": args.slots,
+        "requests": len(reqs), "sides": list(sides), "nrhs": args.nrhs, "slots": args.slots, "merge": args.merge,
+        "group_size_mean": float(np.mean([o[1]["group_size"] for o in out2])),
+        "capacity_group_size_mean": float(np.mean([o[1]["group_size"] for o in out])),
         "capacity_requests_per_s": capacity, "capacity_solves_per_s": solves / span,
         "arrival_rate_per_s": rate, "rate_frac": args.rate_frac,
         "throughput_requests_per_s": len(reqs) / span2, "throughput_solves_per_s": solves / span2,

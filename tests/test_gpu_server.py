@@ -151,3 +151,32 @@ def test_estimate_bounds_measured_peak(gpu_lib, n, leaf, method, prec):
     print(f"case estimate {n} {method} {prec}: est {est} peak {info['peak_bytes']}", flush=True)
     assert est["peak_bytes"] >= info["peak_bytes"]
     assert est["persistent_bytes"] >= info["resident_bytes"]
+
+
+def test_merged_requests_match_the_oracle(gpu_lib):
+    """merge = 4: requests queued behind a running one are factored and
+    solved together as one block-diagonal system; each still gets its own
+    x (within 1e-8 of the oracle), status and iteration counts."""
+    mfh = gpu_lib
+    first = serving_request(24, 11, nrhs=2)          # keeps the one slot busy while the rest queue
+    ws = [first] + _requests()
+    sv = mfh.Server(slots=1, merge=4, **KW)
+    print("case merged serving: 7 requests, 1 slot, merge 4", flush=True)
+    tickets = [sv.submit(w.problem.A, w.problem.coords, w.b) for w in ws]
+    groups = []
+    for w, t in zip(ws, tickets):
+        x, info = sv.wait(t)
+        assert info["status"] == 0 and info["iters_max"] >= 1
+        _check_solution(w, x)
+        groups.append(info["group_size"])
+    assert max(groups) > 1 and max(groups) <= 4, groups
+    assert sv.memory()["in_use"] == 0
+    sv.close()
+
+
+def test_merge_option_is_validated(gpu_lib):
+    mfh = gpu_lib
+    for bad in (0, 17):
+        with pytest.raises(mfh.MfError) as e:
+            mfh.Server(slots=1, merge=bad, **KW)
+        assert e.value.status == mfh.MF_EINVAL

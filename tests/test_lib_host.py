@@ -222,3 +222,75 @@ def test_estimate_bytes_sampled_drops_compressed_fronts():
     ref = symbolic.analyze(p.A, p.coords, 64)
     largest_front = max(f.n * f.n for f in ref.fronts) * 4
     assert ea["peak_bytes"] - es["peak_bytes"] > largest_front / 2
+
+
+def test_symbolic_merge_is_the_shifted_union():
+    """mf_symbolic_merge: the analysis of diag(A_1, A_2, A_3) is each part's
+    own analysis with rows, fronts, blocks and CSR entries shifted by the
+    parts before it; the levels are by height across parts."""
+    parts_in = [(q1_grid(10, 3), 32), (p1_kuhn_cube(5, 0.2, 3), 32), (q1_grid(12, 3), 32)]
+    parts = [mfh.Symbolic.from_csr(p.A, p.coords, leaf) for p, leaf in parts_in]
+    for s in parts:
+        s.bdlr(3, 48)
+    m = mfh.Symbolic.merge(parts)
+    m.bdlr(3, 48)
+    infos = [s.info() for s in parts]
+    mi = m.info()
+    assert mi["n"] == sum(i["n"] for i in infos) and mi["nnz"] == sum(i["nnz"] for i in infos)
+    assert mi["nfronts"] == sum(i["nfronts"] for i in infos)
+    assert mi["nlevels"] == max(i["nlevels"] for i in infos)
+    no = [0]; fo = [0]; eo = [0]; bo = [0]
+    for s, i in zip(parts, infos):
+        no.append(no[-1] + i["n"]); fo.append(fo[-1] + i["nfronts"]); eo.append(eo[-1] + i["nnz"])
+        bo.append(bo[-1] + s.export(mfh.MF_EXP_BLOCKS).size // 7)
+
+    def shifted(what, fn):
+        return np.concatenate([fn(s.export(what), k) for k, s in enumerate(parts)])
+
+    assert np.array_equal(m.export(mfh.MF_EXP_PERM), shifted(mfh.MF_EXP_PERM, lambda a, k: a + no[k]))
+
+    def fr(a, k):
+        a = a.reshape(-1, 6).copy()
+        a[:, 0] += no[k]
+        a[:, 3] = np.where(a[:, 3] >= 0, a[:, 3] + fo[k], -1)
+        return a.ravel()
+    assert np.array_equal(m.export(mfh.MF_EXP_FRONT), shifted(mfh.MF_EXP_FRONT, fr))
+    assert np.array_equal(m.export(mfh.MF_EXP_UPD), shifted(mfh.MF_EXP_UPD, lambda a, k: a + no[k]))
+    assert np.array_equal(m.export(mfh.MF_EXP_RELMAP), shifted(mfh.MF_EXP_RELMAP, lambda a, k: a))
+
+    def blk(a, k):
+        a = a.reshape(-1, 7).copy()
+        a[:, 0] += fo[k]
+        return a.ravel()
+    assert np.array_equal(m.export(mfh.MF_EXP_BLOCKS), shifted(mfh.MF_EXP_BLOCKS, blk))
+
+    def asm(a, k):
+        a = a.reshape(-1, 4).copy()
+        a[:, 0] += fo[k]
+        a[:, 3] += eo[k]
+        return a.ravel()
+    assert np.array_equal(m.export(mfh.MF_EXP_ASM), shifted(mfh.MF_EXP_ASM, asm))
+    for what in (mfh.MF_EXP_BDLR_I, mfh.MF_EXP_BDLR_J):   # front positions: unchanged
+        assert np.array_equal(m.export(what), shifted(what, lambda a, k: a))
+    # the fronts of one level come from every part whose tree reaches that height
+    fm = m.export(mfh.MF_EXP_FRONT).reshape(-1, 6)
+    for k in range(len(parts)):
+        assert fm[fo[k]:fo[k + 1], 4].max() == infos[k]["nlevels"] - 1
+        assert (fm[fo[k]:fo[k + 1], 3] == -1).sum() == 1          # one root per part
+
+
+def test_symbolic_merge_rejects_bad_parts():
+    a = mfh.Symbolic.from_csr(q1_grid(6, 3).A, q1_grid(6, 3).coords, 16)
+    b = mfh.Symbolic.from_csr(q1_grid(6, 3).A, q1_grid(6, 3).coords, 24)
+    c = mfh.Symbolic.from_csr(q1_grid(8, 2).A, q1_grid(8, 2).coords, 16)
+    for bad in ([a, b], [a, c]):
+        with pytest.raises(mfh.MfError) as e:
+            mfh.Symbolic.merge(bad)
+        assert e.value.status == mfh.MF_EINVAL
+    lib = mfh.load()
+    h = ctypes.c_void_p()
+    assert lib.mf_symbolic_merge(None, 0, ctypes.byref(h)) == mfh.MF_EINVAL
+    arr = (ctypes.c_void_p * 2)(a.h.value, None)
+    assert lib.mf_symbolic_merge(arr, 2, ctypes.byref(h)) == mfh.MF_EINVAL
+    m = mfh.Symbolic.merge([a])
+    assert np.array_equal(m.export(mfh.MF_EXP_ASM), a.export(mfh.MF_EXP_ASM))
