@@ -6,7 +6,9 @@ linked; every call compiles every source again.
 """
 from __future__ import annotations
 
+import json
 import os
+import re
 import shutil
 import subprocess
 import sys
@@ -44,7 +46,8 @@ def build(verbose: bool = False) -> str:
     jobs = []
     for s in srcs:
         o = os.path.join(OBJ, s + ".o")
-        jobs.append((o, [cc] + FLAGS + ["-c", "-o", o, os.path.join(CSRC, s)]))
+        extra = ["-Rpass-analysis=kernel-resource-usage"] if s.endswith(".hip") else []
+        jobs.append((o, [cc] + FLAGS + extra + ["-c", "-o", o, os.path.join(CSRC, s)]))
     if verbose:
         for _, c in jobs:
             print(" ".join(c), flush=True)
@@ -54,12 +57,33 @@ def build(verbose: bool = False) -> str:
     errs = [e for (rc, e) in res if rc != 0]
     if errs:
         raise RuntimeError("hipcc failed:\n" + "\n".join(errs))
+    _write_resources([e for (_, e) in res])
     link = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp"] + [o for o, _ in jobs]
     rc, err = _run(link)
     if rc != 0:
         raise RuntimeError("link failed:\n" + err)
     os.replace(LIB + ".tmp", LIB)
     return LIB
+
+
+def _write_resources(logs):
+    """Per-kernel registers, scratch and occupancy from the compiler's
+    resource remarks, to ``_build/kernel_resources.json`` (a kernel that
+    spills its register-resident rows to scratch memory runs many times
+    slower, and the host tests check that none does)."""
+    out, name = {}, None
+    for log in logs:
+        for line in log.splitlines():
+            m = re.search(r"remark: Function Name: (\S+)", line)
+            if m:
+                name = m.group(1)
+                out[name] = {}
+                continue
+            m = re.search(r"remark:\s+(VGPRs|AGPRs|ScratchSize \[bytes/lane\]|Occupancy \[waves/SIMD\]): (\d+)", line)
+            if m and name:
+                out[name][m.group(1).split(" ")[0]] = int(m.group(2))
+    with open(os.path.join(OBJ, "kernel_resources.json"), "w") as f:
+        json.dump(out, f, indent=0, sort_keys=True)
 
 
 if __name__ == "__main__":

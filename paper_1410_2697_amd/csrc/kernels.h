@@ -417,22 +417,29 @@ void launch_perm_in(const double* r, T* xn, const int* perm, int N, int nrhs, hi
 template <typename T>
 void launch_perm_out(const T* xn, double* z, const int* iperm, int N, int nrhs, hipStream_t st);
 
+// Per-column row windows (`win`, device int32[2 * nrhs] or null for all
+// rows): column k of an n x nrhs block uses rows [win[2k], win[2k+1]) only.
+// Independent systems solved together keep each system's right-hand sides in
+// their own columns, zero outside its rows; the kernels below then read and
+// write only those rows of each column (rows outside a window are left as
+// they are and never read for that column's results).
 // float64 CSR SpMV, column-major n x nrhs; y = alpha*A*x + beta*y
 void launch_spmv(const int* rowptr, const int* colind, const double* vals, const double* x,
-                 double* y, int n, int nrhs, double alpha, double beta, hipStream_t st);
+                 double* y, int n, int nrhs, double alpha, double beta, hipStream_t st,
+                 const int* win = nullptr);
 // dots[i*nrhs + k] (+)= <X_i(:,k), w(:,k)> for i < nv; X_i = X + i*ld*nrhs...
 // `partial` holds mdot_chunks(nrhs) * nv * nrhs doubles: the row range is cut
 // into that many chunks per right-hand side (more for few right-hand sides,
 // so that one launch still spreads over the whole chip)
 inline int mdot_chunks(int nrhs) { return nrhs >= 16 ? 64 : nrhs >= 2 ? 1024 / nrhs : 512; }
 void launch_mdot(const double* X, int64_t xstride, int nv, const double* w, int n, int nrhs,
-                 double* partial, double* out, int accumulate, hipStream_t st);
+                 double* partial, double* out, int accumulate, hipStream_t st, const int* win = nullptr);
 void launch_maxpy(const double* X, int64_t xstride, int nv, const double* coef, double* w, int n,
-                  int nrhs, double sign, hipStream_t st);
+                  int nrhs, double sign, hipStream_t st, const int* win = nullptr);
 void launch_scale_cols(const double* w, double* v, const double* norms, int n, int nrhs,
-                       hipStream_t st);
+                       hipStream_t st, const int* win = nullptr);
 void launch_xupdate(const double* Z, int64_t zstride, int nv, const double* y, double* x, int n,
-                    int nrhs, hipStream_t st);
+                    int nrhs, hipStream_t st, const int* win = nullptr);
 void launch_axpby(const double* a, const double* b, double* c, double alpha, double beta, int64_t n,
                   hipStream_t st);
 // conjugate-gradient updates per column k (act[k] == 0: zero step):

@@ -649,6 +649,7 @@ __global__ __launch_bounds__(NT) void skreg_kernel(const SkRegDesc<T>* __restric
   const int last = FULL && adaptive ? 2 : 1;
   int phase = (FULL && !(d.nI > 0 && d.nJ > 0)) ? 2 : 1;
   bool capped = false;
+  T spiv = 0;                     // the last pivot taken or refused
   for (; phase <= last && !capped; ++phase) {
     const bool restricted = FULL && phase == 1;
     // adaptive 2: phase 2 searches the sampled cross only, rows I in every
@@ -668,6 +669,7 @@ __global__ __launch_bounds__(NT) void skreg_kernel(const SkRegDesc<T>* __restric
       unsigned q, l, wl;
       if constexpr (sizeof(T) == 4) {
         // one word per element: magnitude bits 7..30, then 127 - (j RI + i)
+        // (finished columns are skipped: csel is uniform in the wave)
         unsigned bk = 0;
 #pragma unroll
         for (int j = 0; j < CJ; ++j) {
@@ -728,13 +730,12 @@ __global__ __launch_bounds__(NT) void skreg_kernel(const SkRegDesc<T>* __restric
       T c[RI];
 #pragma unroll
       for (int i = 0; i < RI; ++i) c[i] = cc[lane + 64 * i];
-      if (!(fabs(piv) <= std::numeric_limits<T>::max())) {   // Inf or NaN: the front broke down
-        if (t == 0) atomicOr(status, 16);
-        capped = true;
-        break;
-      }
       if (u11 == (T)0) u11 = fabs(piv);
-      if (fabs(piv) < stop_rel * u11) break;
+      // below the stopping ratio, or not finite (Inf or NaN: the front broke
+      // down, flagged after the loop; a separate exit here would push the
+      // register block out to scratch)
+      spiv = piv;
+      if (!(fabs(piv) >= stop_rel * u11 && fabs(piv) <= std::numeric_limits<T>::max())) break;
       if (r >= d.cap) {
         if (t == 0) atomicOr(status, 2);
         capped = true;
@@ -824,6 +825,10 @@ __global__ __launch_bounds__(NT) void skreg_kernel(const SkRegDesc<T>* __restric
       if (lane == la) rl &= ~(1u << ia);
       if (g == gb) cl &= ~(1u << jb);
       ++r;
+    }
+    if (!(fabs(spiv) <= std::numeric_limits<T>::max())) {   // stopped at a pivot that is not finite
+      if (t == 0) atomicOr(status, 16);
+      capped = true;
     }
     if (phase == 1 && !capped && last == 2) r1 = r;
   }
@@ -1853,16 +1858,39 @@ constexpr int kSpmvLanes = 8;   // lanes per matrix row (rows of 3D stencils hol
 // kSpmvLanes lanes per row, all right-hand sides: lane g of a row takes its
 // entries g, g + kSpmvLanes, ..., so neighbouring lanes read neighbouring
 // entries, and the lanes of the row combine their partial sums with shuffles
+// (with windows, a row takes the columns whose windows hold it: those of one
+// system, which are contiguous)
+__device__ __forceinline__ void col_window(const int* win, int k, int n, int& lo, int& hi) {
+  if (win) {
+    lo = win[2 * k];
+    hi = win[2 * k + 1];
+  } else {
+    lo = 0;
+    hi = n;
+  }
+}
+
 __global__ __launch_bounds__(256) void spmv_kernel(const int* __restrict__ rowptr, const int* __restrict__ colind,
                                                    const double* __restrict__ vals, const double* __restrict__ x,
-                                                   double* y, int n, int nrhs, double alpha, double beta) {
+                                                   double* y, int n, int nrhs, double alpha, double beta,
+                                                   const int* __restrict__ win) {
   constexpr int KB = 16, G = kSpmvLanes;
   const int row = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G);
   const int g = threadIdx.x % G;
   if (row >= n) return;                    // whole groups leave together (G divides the wave)
+  int c0 = 0, c1 = nrhs;
+  if (win) {
+    c0 = nrhs;
+    c1 = 0;
+    for (int k = 0; k < nrhs; ++k)
+      if (win[2 * k] <= row && row < win[2 * k + 1]) {
+        c0 = min(c0, k);
+        c1 = k + 1;
+      }
+  }
   const int j0 = rowptr[row], j1 = rowptr[row + 1];
-  for (int k0 = 0; k0 < nrhs; k0 += KB) {
-    const int kb = min(KB, nrhs - k0);
+  for (int k0 = c0; k0 < c1; k0 += KB) {
+    const int kb = min(KB, c1 - k0);
     double acc[KB];
 #pragma unroll
     for (int q = 0; q < KB; ++q) acc[q] = 0.0;
@@ -1892,12 +1920,14 @@ constexpr int kMdotMax = 64;
 // right-hand side k, over one chunk of rows; accumulators in registers
 constexpr int kMdotGroup = 8;
 __global__ __launch_bounds__(256) void mdot_partial_kernel(const double* X, int64_t xstride, int nv, const double* w,
-                                                           int n, int nrhs, double* partial) {
+                                                           int n, int nrhs, double* partial, const int* win) {
   __shared__ double red[16];
   const int chunk = blockIdx.x, k = blockIdx.y, i0 = blockIdx.z * kMdotGroup;
   const int m = min(kMdotGroup, nv - i0);
-  const int per = (n + gridDim.x - 1) / gridDim.x;
-  const int lo = chunk * per, hi = min(n, lo + per);
+  int wlo, whi;
+  col_window(win, k, n, wlo, whi);
+  const int per = (whi - wlo + gridDim.x - 1) / gridDim.x;
+  const int lo = wlo + chunk * per, hi = min(whi, lo + per);
   double acc[kMdotGroup];
 #pragma unroll
   for (int i = 0; i < kMdotGroup; ++i) acc[i] = 0.0;
@@ -1930,30 +1960,38 @@ __global__ __launch_bounds__(256) void mdot_reduce_kernel(const double* partial,
   if (lane == 0) out[idx] = accumulate ? out[idx] + s : s;
 }
 
+// column k = blockIdx.y, its window's rows strided over blockIdx.x
 __global__ void maxpy_kernel(const double* X, int64_t xstride, int nv, const double* coef, double* w, int n, int nrhs,
-                             double sign) {
-  const int64_t tot = (int64_t)n * nrhs;
-  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < tot; idx += (int64_t)gridDim.x * blockDim.x) {
-    const int k = (int)(idx / n);
+                             double sign, const int* win) {
+  const int k = blockIdx.y;
+  int lo, hi;
+  col_window(win, k, n, lo, hi);
+  for (int row = lo + blockIdx.x * blockDim.x + threadIdx.x; row < hi; row += gridDim.x * blockDim.x) {
+    const int64_t idx = (int64_t)k * n + row;
     double s = 0.0;
     for (int i = 0; i < nv; ++i) s += coef[i * nrhs + k] * X[i * xstride + idx];
     w[idx] += sign * s;
   }
 }
 
-__global__ void scale_cols_kernel(const double* w, double* v, const double* nrm2, int n, int nrhs) {
-  const int64_t tot = (int64_t)n * nrhs;
-  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < tot; idx += (int64_t)gridDim.x * blockDim.x) {
-    const int k = (int)(idx / n);
-    const double nn = sqrt(nrm2[k]);
+__global__ void scale_cols_kernel(const double* w, double* v, const double* nrm2, int n, int nrhs, const int* win) {
+  const int k = blockIdx.y;
+  int lo, hi;
+  col_window(win, k, n, lo, hi);
+  const double nn = sqrt(nrm2[k]);
+  for (int row = lo + blockIdx.x * blockDim.x + threadIdx.x; row < hi; row += gridDim.x * blockDim.x) {
+    const int64_t idx = (int64_t)k * n + row;
     v[idx] = nn > 0.0 ? w[idx] / nn : 0.0;
   }
 }
 
-__global__ void xupdate_kernel(const double* Z, int64_t zstride, int nv, const double* y, double* x, int n, int nrhs) {
-  const int64_t tot = (int64_t)n * nrhs;
-  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < tot; idx += (int64_t)gridDim.x * blockDim.x) {
-    const int k = (int)(idx / n);
+__global__ void xupdate_kernel(const double* Z, int64_t zstride, int nv, const double* y, double* x, int n, int nrhs,
+                               const int* win) {
+  const int k = blockIdx.y;
+  int lo, hi;
+  col_window(win, k, n, lo, hi);
+  for (int row = lo + blockIdx.x * blockDim.x + threadIdx.x; row < hi; row += gridDim.x * blockDim.x) {
+    const int64_t idx = (int64_t)k * n + row;
     double s = 0.0;
     for (int i = 0; i < nv; ++i) s += y[i * nrhs + k] * Z[i * zstride + idx];
     x[idx] += s;
@@ -2227,15 +2265,15 @@ void launch_perm_out(const T* xn, double* z, const int* iperm, int N, int nrhs, 
 }
 
 void launch_spmv(const int* rowptr, const int* colind, const double* vals, const double* x, double* y, int n,
-                 int nrhs, double alpha, double beta, hipStream_t st) {
+                 int nrhs, double alpha, double beta, hipStream_t st, const int* win) {
   MFH_LAUNCH(spmv_kernel, dim3((int)(((int64_t)n * kSpmvLanes + 255) / 256)), dim3(256), 0, st, rowptr, colind,
-             vals, x, y, n, nrhs, alpha, beta);
+             vals, x, y, n, nrhs, alpha, beta, win);
 }
 void launch_mdot(const double* X, int64_t xstride, int nv, const double* w, int n, int nrhs, double* partial,
-                 double* out, int accumulate, hipStream_t st) {
+                 double* out, int accumulate, hipStream_t st, const int* win) {
   const int nchunk = mdot_chunks(nrhs);
   MFH_LAUNCH(mdot_partial_kernel, dim3(nchunk, nrhs, (nv + kMdotGroup - 1) / kMdotGroup), dim3(256), 0, st, X,
-             xstride, nv, w, n, nrhs, partial);
+             xstride, nv, w, n, nrhs, partial, win);
   MFH_LAUNCH(mdot_reduce_kernel, dim3((nv * nrhs + 3) / 4), dim3(256), 0, st, partial, nchunk, nv, nrhs, out,
              accumulate);
 }
@@ -2248,18 +2286,19 @@ void launch_cg_p(double* p, const double* z, const double* rzn, const double* rz
                  int n, int nrhs, hipStream_t st) {
   MFH_LAUNCH(cg_p_kernel, dim3(grid_for((int64_t)n * nrhs)), dim3(256), 0, st, p, z, rzn, rzo, rz, act, n, nrhs);
 }
+// per-column launches: as many workgroups in all as the flat form had
+inline dim3 col_grid(int n, int nrhs) { return dim3(grid_for(n, 256, std::max(1, 8192 / nrhs)), nrhs); }
 void launch_maxpy(const double* X, int64_t xstride, int nv, const double* coef, double* w, int n, int nrhs,
-                  double sign, hipStream_t st) {
-  MFH_LAUNCH(maxpy_kernel, dim3(grid_for((int64_t)n * nrhs)), dim3(256), 0, st, X, xstride, nv, coef, w, n,
-                     nrhs, sign);
+                  double sign, hipStream_t st, const int* win) {
+  MFH_LAUNCH(maxpy_kernel, col_grid(n, nrhs), dim3(256), 0, st, X, xstride, nv, coef, w, n, nrhs, sign, win);
 }
-void launch_scale_cols(const double* w, double* v, const double* norms, int n, int nrhs, hipStream_t st) {
-  MFH_LAUNCH(scale_cols_kernel, dim3(grid_for((int64_t)n * nrhs)), dim3(256), 0, st, w, v, norms, n, nrhs);
+void launch_scale_cols(const double* w, double* v, const double* norms, int n, int nrhs, hipStream_t st,
+                       const int* win) {
+  MFH_LAUNCH(scale_cols_kernel, col_grid(n, nrhs), dim3(256), 0, st, w, v, norms, n, nrhs, win);
 }
 void launch_xupdate(const double* Z, int64_t zstride, int nv, const double* y, double* x, int n, int nrhs,
-                    hipStream_t st) {
-  MFH_LAUNCH(xupdate_kernel, dim3(grid_for((int64_t)n * nrhs)), dim3(256), 0, st, Z, zstride, nv, y, x, n,
-                     nrhs);
+                    hipStream_t st, const int* win) {
+  MFH_LAUNCH(xupdate_kernel, col_grid(n, nrhs), dim3(256), 0, st, Z, zstride, nv, y, x, n, nrhs, win);
 }
 void launch_axpby(const double* a, const double* b, double* c, double alpha, double beta, int64_t n, hipStream_t st) {
   MFH_LAUNCH(axpby_kernel, dim3(grid_for(n)), dim3(256), 0, st, a, b, c, alpha, beta, n);

@@ -80,9 +80,12 @@ class NumericBase {
   virtual void apply(int nrhs, const double* r, double* z, hipStream_t st) = 0;
   // the same apply with no device allocation (mf_apply_noalloc)
   virtual void apply_noalloc(int nrhs, const double* r, double* z, hipStream_t st) = 0;
-  void spmv(int nrhs, const double* x, double* y, double alpha, double beta, hipStream_t st);
+  void spmv(int nrhs, const double* x, double* y, double alpha, double beta, hipStream_t st,
+            const int* win = nullptr);
+  // win: host int32[2 * nrhs] row windows of the columns (independent systems
+  // solved together, each column zero outside its system's rows), or null
   void gmres(int nrhs, const double* b, double* x, double tol, const mf_gmres_opts& o, mf_gmres_info* info,
-             mf_status* st_out);
+             mf_status* st_out, const int32_t* win = nullptr);
   void pcg(int nrhs, const double* b, double* x, double tol, int maxit, hipStream_t st, mf_gmres_info* info,
            mf_status* st_out);
   void direct_solve(int nrhs, const double* b, double* x, int refine, hipStream_t st, mf_gmres_info* info);

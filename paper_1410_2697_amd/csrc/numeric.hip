@@ -2537,16 +2537,18 @@ void NumericBase::wait_streams() {
 }
 
 // ================================================================ GMRES ====
-void NumericBase::spmv(int nrhs, const double* x, double* y, double alpha, double beta, hipStream_t st) {
+void NumericBase::spmv(int nrhs, const double* x, double* y, double alpha, double beta, hipStream_t st,
+                       const int* win) {
   // CSR read once, x gathered once per right-hand side, y written (and read)
   const double by = 12.0 * sym->nnz + 4.0 * (sym->n + 1) + 8.0 * sym->n * nrhs * (beta != 0.0 ? 3.0 : 2.0);
   const int id = prof_begin(PK_SPMV, st, 2.0 * sym->nnz * nrhs, by);
-  launch_spmv(d_rowptr.as<int>(), d_colind.as<int>(), d_vals.as<double>(), x, y, sym->n, nrhs, alpha, beta, st);
+  launch_spmv(d_rowptr.as<int>(), d_colind.as<int>(), d_vals.as<double>(), x, y, sym->n, nrhs, alpha, beta, st,
+              win);
   prof_end(id, st);
 }
 
 void NumericBase::gmres(int nrhs, const double* b, double* x, double tol, const mf_gmres_opts& o,
-                        mf_gmres_info* info_out, mf_status* st_out) {
+                        mf_gmres_info* info_out, mf_status* st_out, const int32_t* win_host) {
   hipStream_t st = static_cast<hipStream_t>(o.stream);
   const int N = sym->n, m = std::max(1, o.restart);
   const int64_t vs = (int64_t)N * nrhs;
@@ -2555,7 +2557,14 @@ void NumericBase::gmres(int nrhs, const double* b, double* x, double tol, const 
   g_w.ensure((size_t)vs * 8, &ms, st);
   g_r.ensure((size_t)vs * 8, &ms, st);
   const int nsmall = 3 * (m + 2) * nrhs + 4 * nrhs;
-  g_small.ensure((size_t)nsmall * 8, &ms, st);
+  g_small.ensure((size_t)nsmall * 8 + (win_host ? (size_t)2 * nrhs * 4 : 0), &ms, st);
+  int* win = nullptr;             // column row windows on the device, after the doubles
+  if (win_host) {
+    win = reinterpret_cast<int*>(g_small.as<double>() + nsmall);
+    PinnedScratch wp((size_t)2 * nrhs * 4, st);
+    std::copy(win_host, win_host + 2 * nrhs, wp.as<int>(0));
+    HIPCHK(hipMemcpyAsync(win, wp.as<int>(0), (size_t)2 * nrhs * 4, hipMemcpyHostToDevice, st));
+  }
   g_partial.ensure((size_t)mdot_chunks(nrhs) * (m + 2) * nrhs * 8, &ms, st);
   double* V = g_V.as<double>();
   double* Z = g_Z.as<double>();
@@ -2581,7 +2590,7 @@ void NumericBase::gmres(int nrhs, const double* b, double* x, double tol, const 
     HIPCHK(hipStreamSynchronize(st));
   };
   // ||b||
-  launch_mdot(b, 0, 1, b, N, nrhs, part, nr2, 0, st);
+  launch_mdot(b, 0, 1, b, N, nrhs, part, nr2, 0, st, win);
   HIPCHK(hipMemcpyAsync(hs, nr2, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   std::vector<double> bnorm(nrhs), beta(nrhs);
@@ -2607,7 +2616,7 @@ void NumericBase::gmres(int nrhs, const double* b, double* x, double tol, const 
     for (int k = 0; k < nrhs; ++k) act[k] = !conv[k] && iters[k] < maxit;
     std::copy(nrm2.begin(), nrm2.end(), nrm2_h);
     HIPCHK(hipMemcpyAsync(nr2, nrm2_h, nrhs * sizeof(double), hipMemcpyHostToDevice, st));
-    launch_scale_cols(r, V, nr2, N, nrhs, st);
+    launch_scale_cols(r, V, nr2, N, nrhs, st, win);
     std::fill(H.begin(), H.end(), 0.0);
     std::fill(g.begin(), g.end(), 0.0);
     for (int k = 0; k < nrhs; ++k) g[(size_t)k * (m + 1)] = act[k] ? beta[k] : 0.0;
@@ -2618,14 +2627,14 @@ void NumericBase::gmres(int nrhs, const double* b, double* x, double tol, const 
       double* Vj = V + (int64_t)j * vs;
       double* Zj = Z + (int64_t)j * vs;
       apply(nrhs, Vj, Zj, st);
-      spmv(nrhs, Zj, w, 1.0, 0.0, st);
+      spmv(nrhs, Zj, w, 1.0, 0.0, st, win);
       // classical Gram-Schmidt, twice
-      launch_mdot(V, vs, j + 1, w, N, nrhs, part, h1, 0, st);
-      launch_maxpy(V, vs, j + 1, h1, w, N, nrhs, -1.0, st);
-      launch_mdot(V, vs, j + 1, w, N, nrhs, part, h2, 0, st);
-      launch_maxpy(V, vs, j + 1, h2, w, N, nrhs, -1.0, st);
-      launch_mdot(w, 0, 1, w, N, nrhs, part, nr2, 0, st);
-      launch_scale_cols(w, V + (int64_t)(j + 1) * vs, nr2, N, nrhs, st);
+      launch_mdot(V, vs, j + 1, w, N, nrhs, part, h1, 0, st, win);
+      launch_maxpy(V, vs, j + 1, h1, w, N, nrhs, -1.0, st, win);
+      launch_mdot(V, vs, j + 1, w, N, nrhs, part, h2, 0, st, win);
+      launch_maxpy(V, vs, j + 1, h2, w, N, nrhs, -1.0, st, win);
+      launch_mdot(w, 0, 1, w, N, nrhs, part, nr2, 0, st, win);
+      launch_scale_cols(w, V + (int64_t)(j + 1) * vs, nr2, N, nrhs, st, win);
       read_small(2 * (m + 1) * nrhs + nrhs);
       bool all_done = true;
       for (int k = 0; k < nrhs; ++k) {
@@ -2674,10 +2683,10 @@ void NumericBase::gmres(int nrhs, const double* b, double* x, double tol, const 
     }
     std::copy(ybuf.begin(), ybuf.begin() + (std::ptrdiff_t)jend * nrhs, ybuf_h);
     HIPCHK(hipMemcpyAsync(ydev, ybuf_h, (size_t)jend * nrhs * sizeof(double), hipMemcpyHostToDevice, st));
-    launch_xupdate(Z, vs, jend, ydev, x, N, nrhs, st);
-    spmv(nrhs, x, w, 1.0, 0.0, st);
+    launch_xupdate(Z, vs, jend, ydev, x, N, nrhs, st, win);
+    spmv(nrhs, x, w, 1.0, 0.0, st, win);
     launch_axpby(b, w, r, 1.0, -1.0, vs, st);
-    launch_mdot(r, 0, 1, r, N, nrhs, part, nr2, 0, st);
+    launch_mdot(r, 0, 1, r, N, nrhs, part, nr2, 0, st, win);
     HIPCHK(hipMemcpyAsync(hs, nr2, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     for (int k = 0; k < nrhs; ++k) beta[k] = std::sqrt(hs[k]);

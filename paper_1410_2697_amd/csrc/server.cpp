@@ -376,8 +376,14 @@ void Server::run_merged(const std::vector<Req*>& rs, hipStream_t st, DevBuf& db,
     mf_gmres_opts go = o_.gmres;
     go.stream = st;
     std::vector<mf_gmres_info> gi(C);
+    std::vector<int32_t> win(2 * (size_t)C);     // each column touches only its request's rows
+    for (int i = 0; i < k; ++i)
+      for (int c = co[i]; c < co[i + 1]; ++c) {
+        win[2 * c] = (int32_t)no[i];
+        win[2 * c + 1] = (int32_t)no[i + 1];
+      }
     mf_status s = MF_OK;
-    num->gmres(C, db.as<double>(), dx.as<double>(), o_.tol, go, gi.data(), &s);
+    num->gmres(C, db.as<double>(), dx.as<double>(), o_.tol, go, gi.data(), &s, win.data());
     HIPCHK(hipMemcpyAsync(B.data(), dx.p, bytes, hipMemcpyDeviceToHost, st));
     num->note_stream(st);
     HIPCHK(hipStreamSynchronize(st));

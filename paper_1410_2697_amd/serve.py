@@ -20,24 +20,25 @@ import time
 import numpy as np
 
 
-def _run(mfh, reqs, times, slots, mem_budget, kw, merge=1):
-    """Submit request i at times[i] (seconds from start); returns per-request
-    (latency, info) and the makespan."""
+def _run(mfh, reqs, times, slots, mem_budget, kw, merge=1, clients=1):
+    """Submit request i at times[i] (seconds from start) from client thread
+    i % clients (each submit analyses its request on the calling thread);
+    returns per-request (latency, info) and the makespan."""
     sv = mfh.Server(slots=slots, mem_budget=mem_budget, merge=merge, **kw)
     tickets = [None] * len(reqs)
-    submitted = threading.Event()
     t0 = time.perf_counter()
 
-    def submitter():
-        for i, w in enumerate(reqs):
+    def submitter(c):
+        for i in range(c, len(reqs), clients):
+            w = reqs[i]
             d = t0 + times[i] - time.perf_counter()
             if d > 0:
                 time.sleep(d)
             tickets[i] = sv.submit(w.problem.A, w.problem.coords, w.b)
-        submitted.set()
 
-    th = threading.Thread(target=submitter)
-    th.start()
+    ths = [threading.Thread(target=submitter, args=(c,)) for c in range(clients)]
+    for th in ths:
+        th.start()
     out = [None] * len(reqs)
     peak_in_use = 0
     for i in range(len(reqs)):
@@ -47,7 +48,8 @@ def _run(mfh, reqs, times, slots, mem_budget, kw, merge=1):
         x, info = sv.wait(tickets[i], raise_on_error=False)
         out[i] = (info["t_total"], info, x)
         peak_in_use = max(peak_in_use, sv.memory()["in_use"])
-    th.join()
+    for th in ths:
+        th.join()
     makespan = time.perf_counter() - t0
     mem = sv.memory()
     sv.close()
@@ -64,6 +66,7 @@ def main(argv=None):
     ap.add_argument("--mem-budget", type=int, default=0)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--merge", type=int, default=1, help="most queued requests factored and solved together")
+    ap.add_argument("--clients", type=int, default=1, help="threads submitting requests (each analyses its own)")
     args = ap.parse_args(argv)
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     import paper_1410_2697_amd as mfh
@@ -80,14 +83,17 @@ def main(argv=None):
     print(f"[serve] generated {len(reqs)} requests in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
     kw = dict(leaf=128, tol=1e-10, eps=1e-4, precision="fp32", n_c=512)
     # capacity: everything submitted at once (a warm-up pass first)
-    _run(mfh, reqs[: min(4, len(reqs))], [0.0] * min(4, len(reqs)), args.slots, args.mem_budget, kw, args.merge)
-    out, span, peak_use, budget = _run(mfh, reqs, [0.0] * len(reqs), args.slots, args.mem_budget, kw, args.merge)
+    _run(mfh, reqs[: min(4, len(reqs))], [0.0] * min(4, len(reqs)), args.slots, args.mem_budget, kw, args.merge,
+         args.clients)
+    out, span, peak_use, budget = _run(mfh, reqs, [0.0] * len(reqs), args.slots, args.mem_budget, kw, args.merge,
+         args.clients)
     capacity = len(reqs) / span
     print(f"[serve] capacity {capacity:.2f} requests/s ({span:.2f} s for {len(reqs)})", file=sys.stderr, flush=True)
     # Poisson arrivals at rate_frac x capacity
     rate = args.rate_frac * capacity
     gaps = np.array([a for (a, _, _) in serving_requests(args.count, args.seed, rate, sides)])
-    out2, span2, peak_use2, _ = _run(mfh, reqs, list(gaps), args.slots, args.mem_budget, kw, args.merge)
+    out2, span2, peak_use2, _ = _run(mfh, reqs, list(gaps), args.slots, args.mem_budget, kw, args.merge,
+         args.clients)
     lat = np.sort([o[0] for o in out2])
     ok = [o[1]["status"] == 0 for o in out2]
     solves = sum(w.b.shape[1] for w in reqs)
@@ -100,6 +106,7 @@ def main(argv=None):
     res = {
         "metric": "serving: requests/s and per-request latency (submit to solution)",
         "requests": len(reqs), "sides": list(sides), "nrhs": args.nrhs, "slots": args.slots, "merge": args.merge,
+        "clients": args.clients,
         "group_size_mean": float(np.mean([o[1]["group_size"] for o in out2])),
         "capacity_group_size_mean": float(np.mean([o[1]["group_size"] for o in out])),
         "capacity_requests_per_s": capacity, "capacity_solves_per_s": solves / span,

@@ -294,3 +294,18 @@ def test_symbolic_merge_rejects_bad_parts():
     assert lib.mf_symbolic_merge(arr, 2, ctypes.byref(h)) == mfh.MF_EINVAL
     m = mfh.Symbolic.merge([a])
     assert np.array_equal(m.export(mfh.MF_EXP_ASM), a.export(mfh.MF_EXP_ASM))
+
+
+def test_no_kernel_spills_to_scratch():
+    """Every device function of the library keeps its working set in
+    registers and LDS: the compiler reports no scratch (private memory) for
+    any of them.  The register-resident skeleton and Cholesky kernels slow
+    down many times over when a change pushes their rows out to scratch."""
+    import json
+    path = os.path.join(os.path.dirname(os.path.dirname(__file__)), "_build", "kernel_resources.json")
+    if not os.path.exists(path):
+        pytest.skip("library not built here")
+    res = json.load(open(path))
+    assert any("skreg_kernel" in k for k in res) and any("gemm_narrow_kernel" in k for k in res)
+    spills = {k: v for k, v in res.items() if v.get("ScratchSize", 0) > 0}
+    assert not spills, spills
