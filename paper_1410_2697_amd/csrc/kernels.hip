@@ -147,7 +147,10 @@ struct GemmLds {
   T As[kGemmBK<T>][kTile + 1];
   T Bs[kGemmBK<T>][BN + 1];
 };
-template <typename T, int BN, bool ROWS>
+// ROWS: 0 no row maps; 1 a row map on B only, op N (the apply's reads of
+// x(I_p^f)); 2 row maps on A and/or B in either op.  Each case is its own
+// body: the general one costs the others about a tenth of a launch.
+template <typename T, int BN, int ROWS>
 __device__ __forceinline__ void gemm_tile_body(const GemmDesc<T>& d, int lt, GemmLds<T, BN>& L) {
   constexpr int BM = kTile, BK = kGemmBK<T>, NQ = BK * 64 / 256, NQB = BK * BN / 256;
   constexpr bool NARROW = BN == 16;
@@ -191,7 +194,7 @@ __device__ __forceinline__ void gemm_tile_body(const GemmDesc<T>& d, int lt, Gem
     // tid % BN), so a row map costs one index load per operand and k block,
     // issued ahead of the data loads; clamped indices keep it in the map.
     int amap = 0, bmap = 0;
-    if constexpr (ROWS) {
+    if constexpr (ROWS == 2) {
       if (arow) amap = arow[opA == 0 ? min(m0 + (tid & 63), m - 1) : min(kb + tid % BK, kend - 1)];
       if (brow) bmap = brow[opB == 0 ? min(kb + tid % BK, kend - 1) : min(n0 + tid % BN, n - 1)];
     }
@@ -201,10 +204,16 @@ __device__ __forceinline__ void gemm_tile_body(const GemmDesc<T>& d, int lt, Gem
       if (opA == 0) { i = tid & 63; kk = (tid >> 6) + 4 * q; }
       else { kk = tid % BK; i = tid / BK + (256 / BK) * q; }
       const int gi = m0 + i, gk = kb + kk;
-      const bool ok = gi < m && gk < kend;
-      int sr = opA == 0 ? gi : gk;   // stored row
-      if constexpr (ROWS) sr = arow ? amap : sr;
-      ra[q] = ok ? load_op(A, opA == 0 ? sr + (size_t)gk * lda : sr + (size_t)gi * lda, abf) : (T)0;
+      if constexpr (ROWS == 2) {
+        const bool ok = gi < m && gk < kend;
+        int sr = opA == 0 ? gi : gk;   // stored row
+        sr = arow ? amap : sr;
+        ra[q] = ok ? load_op(A, opA == 0 ? sr + (size_t)gk * lda : sr + (size_t)gi * lda, abf) : (T)0;
+      } else {
+        ra[q] = (gi < m && gk < kend)
+                    ? load_op(A, opA == 0 ? gi + (size_t)gk * lda : gk + (size_t)gi * lda, abf)
+                    : (T)0;
+      }
     }
 #pragma unroll
     for (int q = 0; q < NQB; ++q) {
@@ -213,9 +222,15 @@ __device__ __forceinline__ void gemm_tile_body(const GemmDesc<T>& d, int lt, Gem
       else { j = tid % BN; kk = tid / BN + (256 / BN) * q; }
       const int gj = n0 + j, gk = kb + kk;
       const bool ok = gj < n && gk < kend;
-      int sr = opB == 0 ? gk : gj;   // stored row
-      if constexpr (ROWS) sr = brow ? bmap : sr;
-      rb[q] = ok ? load_op(B, opB == 0 ? sr + (size_t)gj * ldb : sr + (size_t)gk * ldb, bbf) : (T)0;
+      if constexpr (ROWS == 2) {
+        int sr = opB == 0 ? gk : gj;   // stored row
+        sr = brow ? bmap : sr;
+        rb[q] = ok ? load_op(B, opB == 0 ? sr + (size_t)gj * ldb : sr + (size_t)gk * ldb, bbf) : (T)0;
+      } else {
+        int bk = gk;
+        if constexpr (ROWS == 1) bk = ok ? brow[gk] : 0;   // op N when only B's rows are mapped
+        rb[q] = ok ? load_op(B, opB == 0 ? bk + (size_t)gj * ldb : gj + (size_t)gk * ldb, bbf) : (T)0;
+      }
     }
   };
   auto stash = [&]() {
@@ -286,9 +301,10 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc<T>* __restrict__ descs,
   const int di = find_desc_wg(descs, ndesc, (int)blockIdx.x);
   const GemmDesc<T>& d = descs[di];
   const int lt = (int)blockIdx.x - d.tile0;
-  __shared__ GemmLds<T, BN> L;   // one LDS block for both bodies
-  if (d.arow || d.brow) gemm_tile_body<T, BN, true>(d, lt, L);
-  else gemm_tile_body<T, BN, false>(d, lt, L);
+  __shared__ GemmLds<T, BN> L;   // one LDS block for every body
+  if (d.arow || (d.brow && d.opB != 0)) gemm_tile_body<T, BN, 2>(d, lt, L);
+  else if (d.brow) gemm_tile_body<T, BN, 1>(d, lt, L);
+  else gemm_tile_body<T, BN, 0>(d, lt, L);
 }
 
 template <typename T>
