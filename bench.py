@@ -77,7 +77,7 @@ def kernel_bound(name: str):
     """Roofline that bounds a device kernel: MFMA contractions, register/LDS
     pivot and triangular kernels (vector ALU), streaming kernels (HBM)."""
     dt = "f32" if "<float" in name else "f64"
-    if name.startswith("gemm_kernel"):
+    if name.startswith(("gemm_kernel", "potrf_blk_kernel")):   # blocked leaf Cholesky: trailing updates on MFMA
         return "mfma", dt
     if name.startswith("gemm_narrow_kernel"):   # right-hand-side blocks: streams the factor
         return "hbm", dt

@@ -564,6 +564,192 @@ __global__ __launch_bounds__(NT) void potrf_kernel(const PotrfDesc<T>* __restric
     }
 }
 
+// Blocked leaf Cholesky: the same A = L L^T and X = L^{-1} by 16-column
+// blocks, one 256-thread workgroup per matrix, A and X in LDS
+// (column-major, one element of padding per column).  For block k:
+//  - wave 0 factors the 16 x 16 diagonal block D in registers (lane r holds
+//    row r; the entries of the column being eliminated reach the other lanes
+//    by lane reads, so no barrier) and forms D^{-1} in the same sweep;
+//  - all waves, on 16 x 16 x 4 MFMA tiles: the panel below becomes
+//    L_ik = A_ik D^{-T}, row block k of X becomes D^{-1} X_k;
+//  - then the trailing lower blocks take A_ij -= L_ik L_jk^T and the later
+//    row blocks of X take X_i -= L_ik X_k (block forward substitution of
+//    L X = I).
+// Three barriers per block of 16 columns instead of one per column.  Rows
+// and columns beyond n are the identity.  A non-positive pivot sets status
+// bit 1 and continues with 1.
+constexpr int kPotrfNB = 16;
+// 1 / sqrt(v) for v > 0: the hardware estimate, then Newton steps
+// y <- y (3 - v y^2) / 2 (one for float32, three for float64, each about
+// doubling the correct bits of the estimate)
+__device__ __forceinline__ float rsqrt_nr(float v) {
+  const float y = __builtin_amdgcn_rsqf(v);
+  return y * (1.5f - 0.5f * v * y * y);
+}
+__device__ __forceinline__ double rsqrt_nr(double v) {
+  double y = __builtin_amdgcn_rsq(v);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) y = y * (1.5 - 0.5 * v * y * y);
+  return y;
+}
+template <typename T, int NMAX>
+constexpr size_t potrf_blk_lds() {
+  return sizeof(T) * (2 * (size_t)NMAX * (NMAX + 1) + kPotrfNB * (kPotrfNB + 1));
+}
+
+template <typename T, int NMAX>
+__global__ __launch_bounds__(256) void potrf_blk_kernel(const PotrfDesc<T>* __restrict__ descs, int* status) {
+  constexpr int NB = kPotrfNB, LD = NMAX + 1, DL = NB + 1;
+  typedef typename Mfma<T>::v4 v4;
+  extern __shared__ __align__(16) char smem[];
+  T* S = reinterpret_cast<T*>(smem);            // A, then L (lower part)
+  T* X = S + (size_t)NMAX * LD;                  // X = L^{-1}
+  T* Di = X + (size_t)NMAX * LD;                 // D^{-1} of the current block, ld DL
+  const PotrfDesc<T> d = descs[blockIdx.x];
+  const int n = d.n, t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int nbk = (n + NB - 1) / NB, np = nbk * NB;
+  const bool inv = d.Inv != nullptr;
+  // thread t takes rows t & 63 (+ 64) of columns t >> 6, + 4, ...: a batch
+  // of independent loads in flight before the LDS stores
+  {
+    constexpr int RB = NMAX / 64, CB = 8;
+    const int r0 = t & 63, cg = t >> 6;
+    for (int cb = 0; cb < np; cb += 4 * CB) {
+      T v[RB][CB];
+#pragma unroll
+      for (int i = 0; i < RB; ++i)
+#pragma unroll
+        for (int j = 0; j < CB; ++j) {
+          const int r = r0 + 64 * i, c = cb + cg + 4 * j;
+          v[i][j] = r == c ? (T)1 : (T)0;
+          if (r < n && c < n && r >= c) v[i][j] = d.A[r + (size_t)c * d.lda];
+          else if (r < n && c < n) v[i][j] = 0;
+        }
+#pragma unroll
+      for (int i = 0; i < RB; ++i)
+#pragma unroll
+        for (int j = 0; j < CB; ++j) {
+          const int r = r0 + 64 * i, c = cb + cg + 4 * j;
+          if (r < np && c < np) {
+            S[r + c * LD] = v[i][j];
+            X[r + c * LD] = r == c ? (T)1 : (T)0;
+          }
+        }
+    }
+  }
+  __syncthreads();
+  bool bad = false;
+  // C(16 x 16) = P(16 x 16) Q(16 x 16) on one wave: P(i, q) = p(i, q),
+  // Q(q, j) = qf(q, j) read from LDS; lane (li, lk) gets C(row(lk, v), li)
+  auto tile = [&](auto p, auto qf) {
+    v4 acc = {0, 0, 0, 0};
+#pragma unroll
+    for (int k4 = 0; k4 < NB / 4; ++k4) {
+      const int q = 4 * k4 + lk;
+      acc = Mfma<T>::run(p(li, q), qf(q, li), acc);
+    }
+    return acc;
+  };
+  for (int k = 0; k < nbk; ++k) {
+    const int k0 = k * NB;
+    if (wave == 0) {
+      T a[NB], x[NB];
+#pragma unroll
+      for (int c = 0; c < NB; ++c) {
+        a[c] = 0;
+        x[c] = lane == c ? (T)1 : (T)0;
+        if (lane < NB && c <= lane) a[c] = S[(k0 + lane) + (k0 + c) * LD];
+      }
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        T piv = lane_value(a[j], j);
+        if (!(piv > (T)0)) {
+          bad = true;
+          piv = (T)1;
+        }
+        const T rinv = rsqrt_nr(piv), ljj = piv * rinv;
+        const T l = lane > j ? a[j] * rinv : (T)0;   // column j of L below the pivot
+        a[j] = lane == j ? ljj : l;
+        T xj[NB];                                    // row j of D^{-1}, final once scaled
+#pragma unroll
+        for (int c = 0; c <= j; ++c) xj[c] = lane_value(x[c], j) * rinv;
+#pragma unroll
+        for (int c = j + 1; c < NB; ++c) {
+          const T lc = lane_value(l, c);
+          if (lane >= c) a[c] -= l * lc;
+        }
+#pragma unroll
+        for (int c = 0; c <= j; ++c) x[c] = lane == j ? xj[c] : x[c] - l * xj[c];
+      }
+      if (lane < NB) {
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+          if (c <= lane) S[(k0 + lane) + (k0 + c) * LD] = a[c];
+          Di[lane + c * DL] = x[c];
+        }
+      }
+    }
+    __syncthreads();
+    // panel L_ik = A_ik D^{-T} (i > k) and row block k of X: D^{-1} X_k
+    {
+      const int npan = nbk - 1 - k, ntile = npan + (inv ? k + 1 : 0);
+      for (int q = wave; q < ntile; q += 4) {
+        if (q < npan) {
+          const int r0 = (k + 1 + q) * NB;
+          const v4 c = tile([&](int i, int kk) { return S[(r0 + i) + (k0 + kk) * LD]; },
+                            [&](int kk, int j) { return Di[j + kk * DL]; });
+#pragma unroll
+          for (int v = 0; v < 4; ++v) S[(r0 + Mfma<T>::row(lk, v)) + (k0 + li) * LD] = c[v];
+        } else {
+          const int c0 = (q - npan) * NB;
+          const v4 c = tile([&](int i, int kk) { return Di[i + kk * DL]; },
+                            [&](int kk, int j) { return X[(k0 + kk) + (c0 + j) * LD]; });
+#pragma unroll
+          for (int v = 0; v < 4; ++v) X[(k0 + Mfma<T>::row(lk, v)) + (c0 + li) * LD] = c[v];
+        }
+      }
+    }
+    __syncthreads();
+    // trailing: A_ij -= L_ik L_jk^T (k < j <= i), X_i -= L_ik X_k (i > k)
+    {
+      const int m = nbk - 1 - k, ntri = m * (m + 1) / 2, ntile = ntri + (inv ? m * (k + 1) : 0);
+      for (int q = wave; q < ntile; q += 4) {
+        if (q < ntri) {
+          int ib = 0;
+          while ((ib + 1) * (ib + 2) / 2 <= q) ++ib;
+          const int jb = q - ib * (ib + 1) / 2;
+          const int r0 = (k + 1 + ib) * NB, c0 = (k + 1 + jb) * NB;
+          const v4 c = tile([&](int i, int kk) { return S[(r0 + i) + (k0 + kk) * LD]; },
+                            [&](int kk, int j) { return S[(c0 + j) + (k0 + kk) * LD]; });
+#pragma unroll
+          for (int v = 0; v < 4; ++v) S[(r0 + Mfma<T>::row(lk, v)) + (c0 + li) * LD] -= c[v];
+        } else {
+          const int qq = q - ntri, ib = qq / (k + 1), cb = qq % (k + 1);
+          const int r0 = (k + 1 + ib) * NB, c0 = cb * NB;
+          const v4 c = tile([&](int i, int kk) { return S[(r0 + i) + (k0 + kk) * LD]; },
+                            [&](int kk, int j) { return X[(k0 + kk) + (c0 + j) * LD]; });
+#pragma unroll
+          for (int v = 0; v < 4; ++v) X[(r0 + Mfma<T>::row(lk, v)) + (c0 + li) * LD] -= c[v];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (bad && t == 0) atomicOr(status, 1);
+  {
+    const int r0 = t & 63, cg = t >> 6;
+    for (int c = cg; c < n; c += 4)
+#pragma unroll
+      for (int i = 0; i < NMAX / 64; ++i) {
+        const int r = r0 + 64 * i;
+        if (r >= n) continue;
+        if (r >= c) d.A[r + (size_t)c * d.lda] = S[r + c * LD];
+        if (inv) d.Inv[r + (size_t)c * d.ldi] = r >= c ? X[r + c * LD] : (T)0;
+      }
+  }
+}
+
 // Thread t owns rows a = (t & 63) + 64 i (i < RI) and columns
 // b = (t >> 6) + CG j (j < CJ) of the block, CG = NT / 64 column groups, so
 // a column belongs to one wave and its liveness is wave-uniform.
@@ -2076,8 +2262,15 @@ template void launch_mfma_probe<double>(int*, int*, int*, hipStream_t);
 template <typename T>
 void launch_potrf(const PotrfDesc<T>* d, int ndesc, int nmax, int* status, hipStream_t st) {
   if (ndesc <= 0) return;
-  if (nmax <= 64) MFH_LAUNCH((potrf_kernel<T, 64, 256>), dim3(ndesc), dim3(256), 0, st, d, status);
-  else MFH_LAUNCH((potrf_kernel<T, 128, 512>), dim3(ndesc), dim3(512), 0, st, d, status);
+  // blocked MFMA form wherever A and X fit LDS together (all but float64
+  // blocks above 64), the register form otherwise
+  constexpr size_t lds64 = potrf_blk_lds<T, 64>(), lds128 = potrf_blk_lds<T, 128>();
+  if (nmax <= 64)
+    MFH_LAUNCH((potrf_blk_kernel<T, 64>), dim3(ndesc), dim3(256), lds64, st, d, status);
+  else if constexpr (sizeof(T) == 4)
+    MFH_LAUNCH((potrf_blk_kernel<T, 128>), dim3(ndesc), dim3(256), lds128, st, d, status);
+  else
+    MFH_LAUNCH((potrf_kernel<T, 128, 512>), dim3(ndesc), dim3(512), 0, st, d, status);
 }
 template <typename T>
 void launch_skreg_full(const SkRegDesc<T>* d, int ndesc, double eps, int adaptive, int* status, hipStream_t st) {

@@ -12,8 +12,8 @@ const char* const kNames[PK_COUNT] = {
     "gemm_kernel<double>",        "gemm_kernel<float>",
     "gemm_narrow_kernel<double>", "gemm_narrow_kernel<float>",
     "gemm_reduce_kernel<double>", "gemm_reduce_kernel<float>",
-    "potrf_kernel<double, 64, 256>",  "potrf_kernel<float, 64, 256>",
-    "potrf_kernel<double, 128, 512>", "potrf_kernel<float, 128, 512>",
+    "potrf_blk_kernel<double, 64>",   "potrf_blk_kernel<float, 64>",
+    "potrf_kernel<double, 128, 512>", "potrf_blk_kernel<float, 128>",
     "skreg_kernel<double, 2, 16, true, 1024>", "skreg_kernel<float, 4, 16, true, 1024>",
     "skreg_kernel<double, 2, 8, false, 1024>", "skreg_kernel<float, 3, 24, false, 512>",
     "skelfac_kernel<double>",     "skelfac_kernel<float>",

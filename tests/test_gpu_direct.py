@@ -46,7 +46,8 @@ def test_direct_hodlr_fp64_small_eps(gpu_lib, name, maker, leaf):
 
 def test_direct_fp32_factor_refines_to_tolerance(gpu_lib):
     """An FP32 HODLR factor at eps 1e-6 as a direct solver: each refinement
-    step shrinks the float64 residual, and a few steps reach 1e-10."""
+    step shrinks the float64 residual until it reaches float64 rounding
+    (below 1e-14 it only moves within rounding), and a few steps reach 1e-10."""
     mfh = gpu_lib
     p = q1_grid(14, 3)
     n = p.A.n
@@ -57,7 +58,7 @@ def test_direct_fp32_factor_refines_to_tolerance(gpu_lib):
     for s in range(5):
         x = _dev(np.zeros_like(b))
         res.append(max(i["relres"] for i in f.direct_solve(_dev(b), x, refine=s)))
-    assert all(r1 < r0 for r0, r1 in zip(res, res[1:])), res
+    assert all(r1 < r0 or r0 <= 1e-14 for r0, r1 in zip(res, res[1:])), res
     assert res[-1] <= 1e-10, res
     xs = np.linalg.solve(p.A.to_dense(), b)
     assert (np.linalg.norm(_host(x) - xs, axis=0) / np.linalg.norm(xs, axis=0)).max() <= 1e-8

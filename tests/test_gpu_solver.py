@@ -196,7 +196,7 @@ def test_kernel_timing_reports_work(gpu_lib):
     torch.cuda.synchronize()
     stats = {s["name"]: s for s in mfh.prof_stop()}
     print(sorted(stats), flush=True)
-    for name in ("gemm_kernel<float>", "spmv_kernel", "potrf_kernel<float, 64, 256>"):
+    for name in ("gemm_kernel<float>", "spmv_kernel", "potrf_blk_kernel<float, 64>"):
         assert name in stats and stats[name]["launches"] > 0 and stats[name]["seconds"] > 0, name
     assert stats["gemm_kernel<float>"]["flops"] > 0
     assert stats["spmv_kernel"]["bytes"] >= 12.0 * p.A.nnz
@@ -205,10 +205,10 @@ def test_kernel_timing_reports_work(gpu_lib):
     f.gmres(_to_dev(b), _to_dev(np.zeros_like(b)), tol=1e-10)
     torch.cuda.synchronize()
     assert [s["name"] for s in mfh.prof_stop()] == ["spmv_kernel"]
-    mfh.prof_start(["potrf_kernel<float, 64, 256>", "gemm_kernel<float>"])
+    mfh.prof_start(["potrf_blk_kernel<float, 64>", "gemm_kernel<float>"])
     mfh.Factor(sym, p.A.vals, 1e-4, method="hodlr", precision="fp32", n_c=64)
     torch.cuda.synchronize()
-    assert sorted(s["name"] for s in mfh.prof_stop()) == ["gemm_kernel<float>", "potrf_kernel<float, 64, 256>"]
+    assert sorted(s["name"] for s in mfh.prof_stop()) == ["gemm_kernel<float>", "potrf_blk_kernel<float, 64>"]
 
 
 @pytest.mark.parametrize("name,maker,leaf,eps", [("q1_3d_16_leaf32", lambda: q1_grid(16, 3), 32, 1e-3),
