@@ -575,9 +575,10 @@ __global__ __launch_bounds__(NT) void potrf_kernel(const PotrfDesc<T>* __restric
 //  - then the trailing lower blocks take A_ij -= L_ik L_jk^T and the later
 //    row blocks of X take X_i -= L_ik X_k (block forward substitution of
 //    L X = I).
-// Three barriers per block of 16 columns instead of one per column.  Rows
-// and columns beyond n are the identity.  A non-positive pivot sets status
-// bit 1 and continues with 1.
+// The next diagonal block is updated and factored by wave 0 while the other
+// waves finish the trailing update (look-ahead), so each block of 16 columns
+// costs two barriers instead of sixteen.  Rows and columns beyond n are the
+// identity.  A non-positive pivot sets status bit 1 and continues with 1.
 constexpr int kPotrfNB = 16;
 // 1 / sqrt(v) for v > 0: the hardware estimate, then Newton steps
 // y <- y (3 - v y^2) / 2 (one for float32, three for float64, each about
@@ -651,46 +652,52 @@ __global__ __launch_bounds__(256) void potrf_blk_kernel(const PotrfDesc<T>* __re
     }
     return acc;
   };
-  for (int k = 0; k < nbk; ++k) {
+  // wave 0: factor diagonal block k in registers, D^{-1} to Di
+  auto diag = [&](int k) {
     const int k0 = k * NB;
-    if (wave == 0) {
-      T a[NB], x[NB];
+    T a[NB], x[NB];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      a[c] = 0;
+      x[c] = lane == c ? (T)1 : (T)0;
+      if (lane < NB && c <= lane) a[c] = S[(k0 + lane) + (k0 + c) * LD];
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      T piv = lane_value(a[j], j);
+      if (!(piv > (T)0)) {
+        bad = true;
+        piv = (T)1;
+      }
+      const T rinv = rsqrt_nr(piv), ljj = piv * rinv;
+      const T l = lane > j ? a[j] * rinv : (T)0;   // column j of L below the pivot
+      a[j] = lane == j ? ljj : l;
+      T xj[NB];                                    // row j of D^{-1}, final once scaled
+#pragma unroll
+      for (int c = 0; c <= j; ++c) xj[c] = lane_value(x[c], j) * rinv;
+#pragma unroll
+      for (int c = j + 1; c < NB; ++c) {
+        const T lc = lane_value(l, c);
+        if (lane >= c) a[c] -= l * lc;
+      }
+#pragma unroll
+      for (int c = 0; c <= j; ++c) x[c] = lane == j ? xj[c] : x[c] - l * xj[c];
+    }
+    if (lane < NB) {
 #pragma unroll
       for (int c = 0; c < NB; ++c) {
-        a[c] = 0;
-        x[c] = lane == c ? (T)1 : (T)0;
-        if (lane < NB && c <= lane) a[c] = S[(k0 + lane) + (k0 + c) * LD];
-      }
-#pragma unroll
-      for (int j = 0; j < NB; ++j) {
-        T piv = lane_value(a[j], j);
-        if (!(piv > (T)0)) {
-          bad = true;
-          piv = (T)1;
-        }
-        const T rinv = rsqrt_nr(piv), ljj = piv * rinv;
-        const T l = lane > j ? a[j] * rinv : (T)0;   // column j of L below the pivot
-        a[j] = lane == j ? ljj : l;
-        T xj[NB];                                    // row j of D^{-1}, final once scaled
-#pragma unroll
-        for (int c = 0; c <= j; ++c) xj[c] = lane_value(x[c], j) * rinv;
-#pragma unroll
-        for (int c = j + 1; c < NB; ++c) {
-          const T lc = lane_value(l, c);
-          if (lane >= c) a[c] -= l * lc;
-        }
-#pragma unroll
-        for (int c = 0; c <= j; ++c) x[c] = lane == j ? xj[c] : x[c] - l * xj[c];
-      }
-      if (lane < NB) {
-#pragma unroll
-        for (int c = 0; c < NB; ++c) {
-          if (c <= lane) S[(k0 + lane) + (k0 + c) * LD] = a[c];
-          Di[lane + c * DL] = x[c];
-        }
+        if (c <= lane) S[(k0 + lane) + (k0 + c) * LD] = a[c];
+        Di[lane + c * DL] = x[c];
       }
     }
-    __syncthreads();
+  };
+  if (wave == 0) diag(0);
+  __syncthreads();
+  // look-ahead: in the trailing update of block k, wave 0 takes the next
+  // diagonal tile first and factors it while the other waves finish the
+  // remaining tiles, so the serial diagonal work overlaps the update
+  for (int k = 0; k < nbk; ++k) {
+    const int k0 = k * NB;
     // panel L_ik = A_ik D^{-T} (i > k) and row block k of X: D^{-1} X_k
     {
       const int npan = nbk - 1 - k, ntile = npan + (inv ? k + 1 : 0);
@@ -711,10 +718,11 @@ __global__ __launch_bounds__(256) void potrf_blk_kernel(const PotrfDesc<T>* __re
       }
     }
     __syncthreads();
-    // trailing: A_ij -= L_ik L_jk^T (k < j <= i), X_i -= L_ik X_k (i > k)
+    // trailing: A_ij -= L_ik L_jk^T (k < j <= i), X_i -= L_ik X_k (i > k);
+    // tile 0 is the next diagonal block (wave 0), the others go to waves 1-3
     {
       const int m = nbk - 1 - k, ntri = m * (m + 1) / 2, ntile = ntri + (inv ? m * (k + 1) : 0);
-      for (int q = wave; q < ntile; q += 4) {
+      auto trail = [&](int q) {
         if (q < ntri) {
           int ib = 0;
           while ((ib + 1) * (ib + 2) / 2 <= q) ++ib;
@@ -732,6 +740,14 @@ __global__ __launch_bounds__(256) void potrf_blk_kernel(const PotrfDesc<T>* __re
 #pragma unroll
           for (int v = 0; v < 4; ++v) X[(r0 + Mfma<T>::row(lk, v)) + (c0 + li) * LD] -= c[v];
         }
+      };
+      if (wave == 0) {
+        if (m > 0) {
+          trail(0);
+          diag(k + 1);   // LDS operations of one wave complete in order
+        }
+      } else {
+        for (int q = wave; q < ntile; q += 3) trail(q);
       }
     }
     __syncthreads();
