@@ -92,6 +92,13 @@ typedef struct {
                            F_ff^HODLR - Wt W^T, and compression uses those samples alone, so
                            it needs adaptive 0 (the paper's scheme) or 2.  0: every front is
                            staged densely and children's updates are scatter-added whole   */
+  int32_t apply_split_chunk;   /* launch shape of the apply's GEMMs (Sec. 4.1.2), tuned per
+                                  workload: the smallest k range one split-K workgroup sums, a
+                                  multiple of 64 in [64, 4096]; 0: 128                        */
+  int32_t apply_split_target;  /* workgroups one such launch aims for by splitting k, in
+                                  [1, 65536]; 0: 1024 for right-hand-side tiles (at most 16
+                                  right-hand sides), 512 for wider ones.  Both change only the
+                                  order of the partial sums                                   */
   double eps;           /* low-rank tolerance (Sec. 2.2: stop when |u_r+1,r+1/u_11| < eps) */
   void* stream;         /* hipStream_t, borrowed; NULL = null stream                      */
 } mf_opts;

@@ -35,7 +35,8 @@ class MfOpts(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int32), ("precision", ctypes.c_int32), ("n_c", ctypes.c_int32),
                 ("bdlr_depth", ctypes.c_int32), ("bdlr_cap", ctypes.c_int32), ("adaptive", ctypes.c_int32),
                 ("rank_cap", ctypes.c_int32), ("uv_bf16", ctypes.c_int32), ("apply_graph", ctypes.c_int32),
-                ("sampled", ctypes.c_int32), ("eps", ctypes.c_double), ("stream", ctypes.c_void_p)]
+                ("sampled", ctypes.c_int32), ("apply_split_chunk", ctypes.c_int32),
+                ("apply_split_target", ctypes.c_int32), ("eps", ctypes.c_double), ("stream", ctypes.c_void_p)]
 
 
 class GmresOpts(ctypes.Structure):

@@ -3,7 +3,10 @@ bucket, measure the low-rank tolerance eps, the dense/HODLR threshold n_c
 and the BDLR depth d on the GPU and keep the setting that minimises the
 solve time with the factor resident (the benchmark metric), and the one
 that minimises analysis + factorisation + solve.  Every setting must reach
-the 1e-10 residual.  Writes a JSON table that `tuned_options` reads.
+the 1e-10 residual.  Then, for the best setting that keeps compressed
+fronts, the launch shape of the apply's GEMMs (apply_split_chunk,
+apply_split_target: how far k is split over workgroups) is swept on the
+resident solve.  Writes a JSON table that `tuned_options` reads.
 
     python -m paper_1410_2697_amd.autotune [--out paper_1410_2697_amd/tuned.json]
 """
@@ -22,6 +25,8 @@ TABLE = os.path.join(HERE, "tuned.json")
 EPS = (1e-2, 1e-3, 1e-4, 1e-5)
 N_C = (256, 512, 1024, 2048, 4096)
 DEPTH = (-1, 3)
+# apply GEMM launch shapes: (smallest k range of a split, workgroups aimed for); (0, 0) is the default
+TILES = ((0, 0), (64, 512), (64, 1024), (128, 512), (128, 2048), (256, 1024), (256, 2048), (512, 1024))
 
 
 def size_bucket(n: int) -> str:
@@ -45,7 +50,12 @@ def tuned_options(cls: str, n: int, goal: str = "solve", table: str = TABLE):
     r = rows[key].get(goal)
     if r is None:
         return None
-    return {"eps": r["eps"], "n_c": r["n_c"], "depth": r["depth"]}
+    out = {"eps": r["eps"], "n_c": r["n_c"], "depth": r["depth"]}
+    tiles = rows[key].get("tiles")
+    if tiles and goal in ("solve_hodlr", "e2e_hodlr"):
+        out.update(apply_split_chunk=tiles["best"]["apply_split_chunk"],
+                   apply_split_target=tiles["best"]["apply_split_target"])
+    return out
 
 
 def main(argv=None):
@@ -87,6 +97,20 @@ def main(argv=None):
         if hod:    # the best settings that still compress some fronts
             entry["solve_hodlr"] = pick("solve_ms", hod)
             entry["e2e_hodlr"] = pick("e2e_ms", hod)
+            # launch shape of the apply's GEMMs for that setting (changes only rounding)
+            sh = entry["solve_hodlr"]
+            trials = []
+            for chunk, target in TILES:
+                r = measure(mfh, torch, p, 128, sh["eps"], n_c=sh["n_c"], depth=sh["depth"], nrhs=4, solves=5,
+                            maxit=400, apply_split_chunk=chunk, apply_split_target=target)
+                print(f"[autotune] {cls} n={r['n']}: tiles chunk={chunk} target={target} "
+                      f"solve {r['solve_ms']:.3f} ms", file=sys.stderr, flush=True)
+                if r["converged"]:
+                    trials.append({"apply_split_chunk": chunk, "apply_split_target": target,
+                                   "solve_ms": r["solve_ms"]})
+            if trials:
+                entry["tiles"] = {"default_solve_ms": trials[0]["solve_ms"] if trials[0]["apply_split_chunk"] == 0
+                                  else None, "best": min(trials, key=lambda t: t["solve_ms"]), "tried": trials}
         table.setdefault(cls, {})[size_bucket(p.A.n)] = entry
         print(json.dumps({cls: table[cls]}), flush=True)
     with open(args.out, "w") as f:

@@ -209,6 +209,10 @@ mf_status mf_factor(const mf_symbolic_t* sh, const double* vals, double eps, int
   if (o.precision != MF_FP64 && o.precision != MF_FP32) return fail(MF_EINVAL, "unknown precision");
   if (!(eps >= 0.0) || eps >= 1.0) return fail(MF_EINVAL, "eps must be in [0, 1)");
   if (o.apply_graph < 0 || o.apply_graph > (1 << 20)) return fail(MF_EINVAL, "apply_graph must be in [0, 2^20]");
+  if (o.apply_split_chunk != 0 && (o.apply_split_chunk < 64 || o.apply_split_chunk > 4096 || o.apply_split_chunk % 64))
+    return fail(MF_EINVAL, "apply_split_chunk must be 0 or a multiple of 64 in [64, 4096]");
+  if (o.apply_split_target < 0 || o.apply_split_target > 65536)
+    return fail(MF_EINVAL, "apply_split_target must be in [0, 65536]");
   if (o.sampled != 0 && o.sampled != 1) return fail(MF_EINVAL, "sampled must be 0 or 1");
   if (o.adaptive < 0 || o.adaptive > 2) return fail(MF_EINVAL, "adaptive must be 0, 1 or 2");
   if (o.sampled && (o.method != MF_METHOD_HODLR || o.adaptive == 1))
@@ -388,6 +392,10 @@ mf_status mf_server_create(const mf_server_opts* o, mf_server_t** out) {
       return fail(MF_EINVAL, "bdlr_cap or rank_cap out of range");
   }
   if (!(fo.eps >= 0.0) || fo.eps >= 1.0) return fail(MF_EINVAL, "eps must be in [0, 1)");
+  if (fo.apply_split_chunk != 0 && (fo.apply_split_chunk < 64 || fo.apply_split_chunk > 4096 || fo.apply_split_chunk % 64))
+    return fail(MF_EINVAL, "apply_split_chunk must be 0 or a multiple of 64 in [64, 4096]");
+  if (fo.apply_split_target < 0 || fo.apply_split_target > 65536)
+    return fail(MF_EINVAL, "apply_split_target must be in [0, 65536]");
   if (so.gmres.restart < 1 || so.gmres.restart > 60 || so.gmres.maxit < 1)
     return fail(MF_EINVAL, "restart must be 1..60, maxit >= 1");
   if (so.merge < 1 || so.merge > 16) return fail(MF_EINVAL, "merge must be 1..16");

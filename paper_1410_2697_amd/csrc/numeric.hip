@@ -408,13 +408,13 @@ std::atomic<uint64_t> g_handle_ids{0};
 // the reduction descriptors of split problems (tile0 over output tiles)
 template <typename T>
 int finalize_gemm(std::vector<GemmDesc<T>>& v, T* part, size_t cap, std::vector<GemmDesc<T>>& red, int& rtiles,
-                  int tn = kTile) {
+                  int tn = kTile, int chunk_min = kSplitChunk, int target_set = 0) {
   red.clear();
   rtiles = 0;
   int base = 0;
   for (const auto& d : v)
     if (d.m > 0 && d.n > 0) base += cdiv(d.m, kTile) * cdiv(d.n, tn);
-  const int target = tn == kTileNarrow ? kSplitTargetNarrow : kSplitTarget;
+  const int target = target_set > 0 ? target_set : tn == kTileNarrow ? kSplitTargetNarrow : kSplitTarget;
   const int want = (part && base > 0 && 2 * base <= target) ? target / base : 1;
   size_t used = 0;
   int t = 0;
@@ -427,8 +427,8 @@ int finalize_gemm(std::vector<GemmDesc<T>>& v, T* part, size_t cap, std::vector<
     d.ksplit = 1;
     d.kchunk = 0;
     d.part = nullptr;
-    if (want > 1 && !d.kdev && d.k >= 2 * kSplitChunk) {
-      int sp = std::min(want, d.k / kSplitChunk);
+    if (want > 1 && !d.kdev && d.k >= 2 * chunk_min) {
+      int sp = std::min(want, d.k / chunk_min);
       const int chunk = cdiv(cdiv(d.k, sp), kGemmSplitAlign) * kGemmSplitAlign;
       sp = cdiv(d.k, chunk);
       const size_t need = (size_t)sp * d.m * d.n;
@@ -541,11 +541,11 @@ struct GemmBatch {
   void stage(Blob& b, const DevBuf* split = nullptr) {
     stage(b, split ? static_cast<T*>(split->p) : nullptr, split ? split->bytes / sizeof(T) : 0);
   }
-  void stage(Blob& b, T* part, size_t cap) {
+  void stage(Blob& b, T* part, size_t cap, int chunk_min = kSplitChunk, int target = 0) {
     tn = kTileNarrow;
     for (const auto& d : v)
       if (d.n > kTileNarrow) tn = kTile;
-    tiles = finalize_gemm(v, part, cap, red, rtiles, tn);
+    tiles = finalize_gemm(v, part, cap, red, rtiles, tn, chunk_min, target);
     n = (int)v.size();
     off = b.add(v);
     rn = (int)red.size();
@@ -2242,8 +2242,9 @@ void Numeric<T>::build_plan(Plan& plan, int nrhs, const Layout& L, T* wk, T* par
   const std::vector<std::vector<int64_t>>&q_off = L.q_off, &l_off = L.l_off;
   pl->xn = wk;
   Blob b;
+  const int chunk_min = opts.apply_split_chunk > 0 ? opts.apply_split_chunk : kSplitChunk;
   auto rec_gemm = [&](GemmBatch<T>& g) {
-    g.stage(b, part, cap);
+    g.stage(b, part, cap, chunk_min, opts.apply_split_target);
     if (g.n) pl->recs.push_back({0, g.off, g.n, g.tiles, g.flops, g.bytes, g.tn});
     if (g.rn) pl->recs.push_back({4, g.roff, g.rn, g.rtiles, 0.0, g.rbytes});
   };

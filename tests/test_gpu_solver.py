@@ -283,3 +283,25 @@ def test_apply_graph_replays_equal_direct_launches(gpu_lib, method, prec):
     idd = fd.gmres(b, xd, tol=1e-10)
     assert [i["iters"] for i in ig] == [i["iters"] for i in idd]
     assert torch.equal(xg, xd)
+
+
+@pytest.mark.parametrize("method,n_c", [("hodlr", 64), ("dense", 0)])
+@pytest.mark.parametrize("chunk,target", [(64, 256), (256, 2048), (4096, 1)])
+def test_apply_split_shape_changes_only_rounding(gpu_lib, method, n_c, chunk, target):
+    """The apply's split-K launch shape (apply_split_chunk, apply_split_target)
+    only reorders partial sums: FP64 applies agree with the default shape to
+    1e-12, and the ranks are the same."""
+    mfh = gpu_lib
+    p = q1_grid(16, 3)
+    print(f"case split-shape {method} chunk={chunk} target={target}", flush=True)
+    sym = mfh.Symbolic.from_csr(p.A, p.coords, 32)
+    kw = dict(method=method, precision="fp64", n_c=n_c)
+    f0 = mfh.Factor(sym, p.A.vals, 1e-6, **kw)
+    f1 = mfh.Factor(sym, p.A.vals, 1e-6, apply_split_chunk=chunk, apply_split_target=target, **kw)
+    assert np.array_equal(f0.ranks(), f1.ranks())
+    b = rhs(p.A.n, 5, "normal", 17)
+    z0, z1 = _to_dev(np.zeros_like(b)), _to_dev(np.zeros_like(b))
+    f0.apply(_to_dev(b), z0)
+    f1.apply(_to_dev(b), z1)
+    z0, z1 = _to_host(z0), _to_host(z1)
+    assert np.abs(z1 - z0).max() <= 1e-12 * np.abs(z0).max()

@@ -168,7 +168,8 @@ def test_option_validation():
     lib = mfh.load()
     h = ctypes.c_void_p()
     for kw, eps in [({"precision": 7}, 1e-4), ({"method": 9}, 1e-4), ({}, -1.0), ({"bdlr_cap": -1}, 1e-4),
-                    ({"bdlr_cap": 500}, 1e-4)]:
+                    ({"bdlr_cap": 500}, 1e-4), ({"apply_split_chunk": 100}, 1e-4),
+                    ({"apply_split_chunk": 8192}, 1e-4), ({"apply_split_target": -1}, 1e-4)]:
         o = mfh.default_opts(**kw)
         st = lib.mf_factor(s.h, mfh._ptr(p.A.vals), eps, 0, ctypes.byref(o), ctypes.byref(h))
         assert st == mfh.MF_EINVAL, (kw, eps)
@@ -309,3 +310,26 @@ def test_no_kernel_spills_to_scratch():
     assert any("skreg_kernel" in k for k in res) and any("gemm_narrow_kernel" in k for k in res)
     spills = {k: v for k, v in res.items() if v.get("ScratchSize", 0) > 0}
     assert not spills, spills
+
+
+def test_tuned_options_reads_the_table(tmp_path):
+    """autotune.tuned_options: nearest size bucket, the goal's eps/n_c/d, and
+    for the settings that keep compressed fronts the tuned launch shape of
+    the apply's GEMMs."""
+    import json
+    from paper_1410_2697_amd import autotune
+    t = {"poisson3d": {"32768": {"solve": {"eps": 1e-3, "n_c": 4096, "depth": 3, "solve_ms": 1.0},
+                                 "solve_hodlr": {"eps": 1e-4, "n_c": 1024, "depth": 3, "solve_ms": 2.0},
+                                 "tiles": {"best": {"apply_split_chunk": 256, "apply_split_target": 2048,
+                                                    "solve_ms": 1.9}}},
+                       "262144": {"solve": {"eps": 1e-5, "n_c": 4096, "depth": -1, "solve_ms": 5.0}}}}
+    path = tmp_path / "t.json"
+    path.write_text(json.dumps(t))
+    assert autotune.tuned_options("poisson3d", 30000, "solve", str(path)) == {"eps": 1e-3, "n_c": 4096, "depth": 3}
+    assert autotune.tuned_options("poisson3d", 40000, "solve_hodlr", str(path)) == {
+        "eps": 1e-4, "n_c": 1024, "depth": 3, "apply_split_chunk": 256, "apply_split_target": 2048}
+    assert autotune.tuned_options("poisson3d", 250000, "solve", str(path))["eps"] == 1e-5
+    assert autotune.tuned_options("poisson3d", 250000, "solve_hodlr", str(path)) is None
+    assert autotune.tuned_options("p1kuhn", 1000, "solve", str(path)) is None
+    for cls in ("poisson3d", "p1kuhn", "elasticity3d"):      # the committed table
+        assert autotune.tuned_options(cls, 32768) is not None
