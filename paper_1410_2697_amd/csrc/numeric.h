@@ -42,6 +42,10 @@ struct DevBuf {
   // grows without synchronising: the old block moves to `retired`, whose
   // owner releases it after the stream work that may use it has finished
   void grow(size_t b, MemStats* m, std::vector<std::unique_ptr<DevBuf>>& retired);
+  // grows to exactly b bytes after synchronising the stream and releasing
+  // the old block and `retired`, so that the high-water mark never holds a
+  // dead block beside its successor (for the largest per-level scratch)
+  void regrow(size_t b, MemStats* m, hipStream_t st, std::vector<std::unique_ptr<DevBuf>>& retired);
   template <typename T> T* as() const { return static_cast<T*>(p); }
 };
 

@@ -122,6 +122,13 @@ void DevBuf::ensure(size_t b, MemStats* m, hipStream_t st) {
   alloc(std::max(b, bytes + bytes / 2), m);
 }
 
+void DevBuf::regrow(size_t b, MemStats* m, hipStream_t st, std::vector<std::unique_ptr<DevBuf>>& retired) {
+  if (p && b <= bytes) return;
+  HIPCHK(hipStreamSynchronize(st));   // no launch uses the old block or `retired` any more
+  retired.clear();
+  alloc(b, m);                        // releases the old block before allocating
+}
+
 void DevBuf::grow(size_t b, MemStats* m, std::vector<std::unique_ptr<DevBuf>>& retired) {
   if (p && b <= bytes) return;
   const size_t want = std::max(b, bytes + bytes / 2);
@@ -1348,7 +1355,7 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
     need += al((size_t)B.nr * x.capr * sizeof(T)) + al((size_t)B.nc * x.capr * sizeof(T));
   }
   need += al((size_t)std::max<int64_t>(nslots, 1) * sizeof(unsigned long long));
-  scrA.grow(need, &ms, retired);
+  scrA.regrow(need, &ms, st, retired);
   char* cur = static_cast<char*>(scrA.p);
   auto take = [&](size_t bytes) { char* r = cur; cur += al(bytes); return r; };
   // every multi-workgroup block's tagged key slots, in one range
@@ -1398,7 +1405,7 @@ void Numeric<T>::hodlr_level(const std::vector<int>& Hs, int h) {
     for (int p : Hs)
       for (const TreeNode& t : s.fronts[p].pp_tree)
         if (t.left < 0) tneed += al((size_t)t.size * t.size * sizeof(T));
-    scrS.grow(std::max<size_t>(tneed, 256), &ms, retired);
+    scrS.regrow(std::max<size_t>(tneed, 256), &ms, st, retired);
     char* sc = static_cast<char*>(scrS.p);
     auto stake = [&](size_t elems) { T* r = reinterpret_cast<T*>(sc); sc += al(elems * sizeof(T)); return r; };
     // index lists: block-local I and J (whole-block mode), 0, 1, 2, ... (the
