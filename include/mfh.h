@@ -363,7 +363,10 @@ mf_status mf_estimate_bytes(const mf_symbolic_t* sym, const mf_opts* opts, int32
  *    with one GMRES call in which each request's right-hand sides are their
  *    own columns, zero outside its rows: every column's iteration is the one
  *    it has alone, and each request gets its own x, status and iteration
- *    counts (the factor and solve times are the group's).
+ *    counts (the factor and solve times are the group's).  If the merged
+ *    factorisation fails for a reason one request can cause (MF_ENOTSPD,
+ *    MF_ECAPACITY, MF_EINVAL), each request of the group is factored and
+ *    solved alone instead, so only the faulty one reports the error.
  *  - With keep_factors, a request's factor stays on the device after its
  *    solve; mf_server_resolve queues another solve with it (repeated
  *    right-hand sides) until mf_server_release.

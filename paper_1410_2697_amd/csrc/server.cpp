@@ -338,6 +338,7 @@ void Server::run_merged(const std::vector<Req*>& rs, hipStream_t st, DevBuf& db,
   const int C = co[k];
   Symbolic msym;                  // outlives the factor below, which refers to it
   std::unique_ptr<NumericBase> num;
+  bool alone = false;             // the merged factorisation failed: each request runs by itself
   try {
     const double t0 = now();
     std::vector<const Symbolic*> parts;
@@ -358,53 +359,62 @@ void Server::run_merged(const std::vector<Req*>& rs, hipStream_t st, DevBuf& db,
         num = make_numeric(msym, vals.data(), fo);
         break;
       } catch (const Err& e2) {
-        if (attempt > 0 || e2.code != MF_EHIP || e2.msg.rfind(kPhase2WaitMsg, 0) != 0) throw;
+        if (attempt == 0 && e2.code == MF_EHIP && e2.msg.rfind(kPhase2WaitMsg, 0) == 0) continue;
+        // one request of the group may be at fault (a matrix that is not
+        // positive definite, say): the others must not share its error
+        if (e2.code == MF_ENOTSPD || e2.code == MF_ECAPACITY || e2.code == MF_EINVAL) {
+          alone = true;
+          break;
+        }
+        throw;
       }
     }
-    const double t_factor = now() - t0;
-    // request i's right-hand sides in columns co[i].., zero outside its rows
-    const double t1 = now();
-    std::vector<double> B((size_t)N * C, 0.0);
-    for (int i = 0; i < k; ++i)
-      for (int c = 0; c < rs[i]->nrhs; ++c)
-        std::copy(rs[i]->b.begin() + (size_t)c * rs[i]->n, rs[i]->b.begin() + (size_t)(c + 1) * rs[i]->n,
-                  B.begin() + (size_t)(co[i] + c) * N + no[i]);
-    const size_t bytes = (size_t)N * C * sizeof(double);
-    db.ensure(bytes, nullptr, st);
-    dx.ensure(bytes, nullptr, st);
-    HIPCHK(hipMemcpyAsync(db.p, B.data(), bytes, hipMemcpyHostToDevice, st));
-    mf_gmres_opts go = o_.gmres;
-    go.stream = st;
-    std::vector<mf_gmres_info> gi(C);
-    std::vector<int32_t> win(2 * (size_t)C);     // each column touches only its request's rows
-    for (int i = 0; i < k; ++i)
-      for (int c = co[i]; c < co[i + 1]; ++c) {
-        win[2 * c] = (int32_t)no[i];
-        win[2 * c + 1] = (int32_t)no[i + 1];
+    if (!alone) {
+      const double t_factor = now() - t0;
+      // request i's right-hand sides in columns co[i].., zero outside its rows
+      const double t1 = now();
+      std::vector<double> B((size_t)N * C, 0.0);
+      for (int i = 0; i < k; ++i)
+        for (int c = 0; c < rs[i]->nrhs; ++c)
+          std::copy(rs[i]->b.begin() + (size_t)c * rs[i]->n, rs[i]->b.begin() + (size_t)(c + 1) * rs[i]->n,
+                    B.begin() + (size_t)(co[i] + c) * N + no[i]);
+      const size_t bytes = (size_t)N * C * sizeof(double);
+      db.ensure(bytes, nullptr, st);
+      dx.ensure(bytes, nullptr, st);
+      HIPCHK(hipMemcpyAsync(db.p, B.data(), bytes, hipMemcpyHostToDevice, st));
+      mf_gmres_opts go = o_.gmres;
+      go.stream = st;
+      std::vector<mf_gmres_info> gi(C);
+      std::vector<int32_t> win(2 * (size_t)C);     // each column touches only its request's rows
+      for (int i = 0; i < k; ++i)
+        for (int c = co[i]; c < co[i + 1]; ++c) {
+          win[2 * c] = (int32_t)no[i];
+          win[2 * c + 1] = (int32_t)no[i + 1];
+        }
+      mf_status s = MF_OK;
+      num->gmres(C, db.as<double>(), dx.as<double>(), o_.tol, go, gi.data(), &s, win.data());
+      HIPCHK(hipMemcpyAsync(B.data(), dx.p, bytes, hipMemcpyDeviceToHost, st));
+      num->note_stream(st);
+      HIPCHK(hipStreamSynchronize(st));
+      const double t_solve = now() - t1;
+      for (int i = 0; i < k; ++i) {
+        Req& r = *rs[i];
+        r.x.resize((size_t)r.n * r.nrhs);
+        bool conv = true;
+        for (int c = 0; c < r.nrhs; ++c) {
+          std::copy(B.begin() + (size_t)(co[i] + c) * N + no[i], B.begin() + (size_t)(co[i] + c) * N + no[i + 1],
+                    r.x.begin() + (size_t)c * r.n);
+          const mf_gmres_info& g = gi[co[i] + c];
+          r.info.iters_max = std::max(r.info.iters_max, g.iters);
+          r.info.relres_max = std::max(r.info.relres_max, g.relres);
+          conv &= g.converged != 0;
+        }
+        r.status = conv ? MF_OK : MF_ENOCONV;
+        if (!conv) r.err = "GMRES did not reach tol within maxit";
+        r.info.t_factor = t_factor;
+        r.info.t_solve = t_solve;
+        r.info.peak_bytes = num->ms.peak;
       }
-    mf_status s = MF_OK;
-    num->gmres(C, db.as<double>(), dx.as<double>(), o_.tol, go, gi.data(), &s, win.data());
-    HIPCHK(hipMemcpyAsync(B.data(), dx.p, bytes, hipMemcpyDeviceToHost, st));
-    num->note_stream(st);
-    HIPCHK(hipStreamSynchronize(st));
-    const double t_solve = now() - t1;
-    for (int i = 0; i < k; ++i) {
-      Req& r = *rs[i];
-      r.x.resize((size_t)r.n * r.nrhs);
-      bool conv = true;
-      for (int c = 0; c < r.nrhs; ++c) {
-        std::copy(B.begin() + (size_t)(co[i] + c) * N + no[i], B.begin() + (size_t)(co[i] + c) * N + no[i + 1],
-                  r.x.begin() + (size_t)c * r.n);
-        const mf_gmres_info& g = gi[co[i] + c];
-        r.info.iters_max = std::max(r.info.iters_max, g.iters);
-        r.info.relres_max = std::max(r.info.relres_max, g.relres);
-        conv &= g.converged != 0;
-      }
-      r.status = conv ? MF_OK : MF_ENOCONV;
-      if (!conv) r.err = "GMRES did not reach tol within maxit";
-      r.info.t_factor = t_factor;
-      r.info.t_solve = t_solve;
-      r.info.peak_bytes = num->ms.peak;
     }
   } catch (const Err& e) {
     for (Req* r : rs) { r->status = e.code; r->err = e.msg; }
@@ -414,6 +424,13 @@ void Server::run_merged(const std::vector<Req*>& rs, hipStream_t st, DevBuf& db,
     for (Req* r : rs) { r->status = MF_EINVAL; r->err = e.what(); }
   }
   num.reset();
+  if (alone) {                    // factor and solve each request by itself
+    for (Req* r : rs) {
+      r->info.group_size = 1;
+      run(*r, st, db, dx);
+    }
+    return;
+  }
   for (Req* r : rs) {
     r->info.status = r->status;
     r->vals.clear();

@@ -180,3 +180,31 @@ def test_merge_option_is_validated(gpu_lib):
         with pytest.raises(mfh.MfError) as e:
             mfh.Server(slots=1, merge=bad, **KW)
         assert e.value.status == mfh.MF_EINVAL
+
+
+def test_merged_group_with_a_request_that_is_not_spd(gpu_lib):
+    """A group whose merged factorisation fails because one matrix is not
+    positive definite falls back to factoring each request alone: that
+    request ends with MF_ENOTSPD, the others still match the oracle."""
+    import types
+    mfh = gpu_lib
+    first = serving_request(24, 12, nrhs=2)          # keeps the one slot busy while the rest queue
+    good = [serving_request(side, seed, nrhs=2) for side, seed in [(10, 31), (12, 32)]]
+    bad_w = serving_request(11, 33, nrhs=2)
+    A = bad_w.problem.A
+    bad_A = types.SimpleNamespace(n=A.n, rowptr=A.rowptr, colind=A.colind, vals=-np.asarray(A.vals))
+    sv = mfh.Server(slots=1, merge=4, **KW)
+    print("case merged serving with a negative definite request", flush=True)
+    t_first = sv.submit(first.problem.A, first.problem.coords, first.b)
+    t_good0 = sv.submit(good[0].problem.A, good[0].problem.coords, good[0].b)
+    t_bad = sv.submit(bad_A, bad_w.problem.coords, bad_w.b)
+    t_good1 = sv.submit(good[1].problem.A, good[1].problem.coords, good[1].b)
+    for w, t in ((first, t_first), (good[0], t_good0), (good[1], t_good1)):
+        x, info = sv.wait(t)
+        assert info["status"] == 0
+        _check_solution(w, x)
+    with pytest.raises(mfh.MfError) as e:
+        sv.wait(t_bad)
+    assert e.value.status == mfh.MF_ENOTSPD
+    assert sv.memory()["in_use"] == 0
+    sv.close()
