@@ -652,43 +652,49 @@ __global__ __launch_bounds__(256) void potrf_blk_kernel(const PotrfDesc<T>* __re
     }
     return acc;
   };
-  // wave 0: factor diagonal block k in registers, D^{-1} to Di
+  // wave 0: factor diagonal block k in registers, D^{-1} to Di.  Lane
+  // r + 16 g holds row r, columns g, g + 4, g + 8, g + 12 of D and of D^{-1};
+  // a step reads the entries it needs from other lanes by shuffles
   auto diag = [&](int k) {
-    const int k0 = k * NB;
-    T a[NB], x[NB];
+    const int k0 = k * NB, r = lane & 15, g = lane >> 4;
+    T a[4], x[4];
 #pragma unroll
-    for (int c = 0; c < NB; ++c) {
-      a[c] = 0;
-      x[c] = lane == c ? (T)1 : (T)0;
-      if (lane < NB && c <= lane) a[c] = S[(k0 + lane) + (k0 + c) * LD];
+    for (int q = 0; q < 4; ++q) {
+      const int c = g + 4 * q;
+      a[q] = c <= r ? S[(k0 + r) + (k0 + c) * LD] : (T)0;
+      x[q] = r == c ? (T)1 : (T)0;
     }
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
-      T piv = lane_value(a[j], j);
+      const int gj = j & 3, qj = j >> 2;   // column j sits in lanes (., gj), register qj
+      T piv = lane_value(a[qj], j + 16 * gj);
       if (!(piv > (T)0)) {
         bad = true;
         piv = (T)1;
       }
+      const T colv = __shfl(a[qj], r + 16 * gj);        // D(r, j), unscaled
+      T lc[4], xj[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        lc[q] = __shfl(a[qj], (g + 4 * q) + 16 * gj);    // D(c, j) for this lane's columns c
+        xj[q] = __shfl(x[q], j + 16 * g);                // row j of D^{-1}, unscaled
+      }
       const T rinv = rsqrt_nr(piv), ljj = piv * rinv;
-      const T l = lane > j ? a[j] * rinv : (T)0;   // column j of L below the pivot
-      a[j] = lane == j ? ljj : l;
-      T xj[NB];                                    // row j of D^{-1}, final once scaled
+      const T l = r > j ? colv * rinv : (T)0;           // L(r, j)
+      if (g == gj) a[qj] = r == j ? ljj : l;
 #pragma unroll
-      for (int c = 0; c <= j; ++c) xj[c] = lane_value(x[c], j) * rinv;
-#pragma unroll
-      for (int c = j + 1; c < NB; ++c) {
-        const T lc = lane_value(l, c);
-        if (lane >= c) a[c] -= l * lc;
+      for (int q = 0; q < 4; ++q) {
+        const int c = g + 4 * q;
+        if (c > j && r >= c) a[q] -= l * (lc[q] * rinv);
+        const T xs = xj[q] * rinv;                       // row j of D^{-1} is final once scaled
+        x[q] = r == j ? xs : x[q] - l * xs;
       }
-#pragma unroll
-      for (int c = 0; c <= j; ++c) x[c] = lane == j ? xj[c] : x[c] - l * xj[c];
     }
-    if (lane < NB) {
 #pragma unroll
-      for (int c = 0; c < NB; ++c) {
-        if (c <= lane) S[(k0 + lane) + (k0 + c) * LD] = a[c];
-        Di[lane + c * DL] = x[c];
-      }
+    for (int q = 0; q < 4; ++q) {
+      const int c = g + 4 * q;
+      if (c <= r) S[(k0 + r) + (k0 + c) * LD] = a[q];
+      Di[r + c * DL] = x[q];
     }
   };
   if (wave == 0) diag(0);
