@@ -17,6 +17,7 @@
 #include <atomic>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <numeric>
 #include <thread>
 #include <tuple>
@@ -52,19 +53,47 @@ struct NDCtx {
 
   double co(int v, int a) const { return coords[(int64_t)v * dim + a]; }
 
-  // axis of largest coordinate extent over ids (one pass for all axes)
-  int extent_axis(const std::vector<int>& ids) const {
-    double mn[3], mx[3];
+  // coordinate range of ids along every axis (large sets: per-chunk ranges, combined)
+  void extents(const std::vector<int>& ids, double* mn, double* mx) const {
     for (int a = 0; a < dim; ++a) {
       mn[a] = std::numeric_limits<double>::infinity();
       mx[a] = -mn[a];
     }
-    for (int v : ids)
+    const int n_s = (int)ids.size();
+    if (n_s < kParallelSplit) {
+      for (int v : ids)
+        for (int a = 0; a < dim; ++a) {
+          const double c = co(v, a);
+          mn[a] = std::min(mn[a], c);
+          mx[a] = std::max(mx[a], c);
+        }
+      return;
+    }
+    std::mutex mu;
+    parallel_for(n_s, 4096, [&](int i0, int i1, int) {
+      double lo[3], hi[3];
       for (int a = 0; a < dim; ++a) {
-        const double c = co(v, a);
-        mn[a] = std::min(mn[a], c);
-        mx[a] = std::max(mx[a], c);
+        lo[a] = std::numeric_limits<double>::infinity();
+        hi[a] = -lo[a];
       }
+      for (int i = i0; i < i1; ++i)
+        for (int a = 0; a < dim; ++a) {
+          const double c = co(ids[i], a);
+          lo[a] = std::min(lo[a], c);
+          hi[a] = std::max(hi[a], c);
+        }
+      std::lock_guard<std::mutex> g(mu);
+      for (int a = 0; a < dim; ++a) {
+        mn[a] = std::min(mn[a], lo[a]);
+        mx[a] = std::max(mx[a], hi[a]);
+      }
+    });
+  }
+
+  // axis of largest coordinate extent over ids (one pass for all axes)
+  int extent_axis(const std::vector<int>& ids) const {
+    double mn[3], mx[3];
+    extents(ids, mn, mx);
     int best = 0;
     double bext = -1.0;
     for (int a = 0; a < dim; ++a) {
@@ -83,13 +112,82 @@ struct NDCtx {
     std::nth_element(key.begin(), key.begin() + (std::ptrdiff_t)m, key.end());
     for (size_t i = 0; i < ids.size(); ++i) ids[i] = key[i].second;
   }
-  // coordinate of the element of rank m in (coordinate, id) order
+  // coordinate of the element of rank m in (coordinate, id) order: the
+  // m-th smallest coordinate (ids only order equal coordinates)
   double median_coord(const std::vector<int>& ids, size_t m, int ax) const {
-    std::vector<std::pair<double, int>> key(ids.size());
-    for (size_t i = 0; i < ids.size(); ++i) key[i] = {co(ids[i], ax), ids[i]};
-    std::nth_element(key.begin(), key.begin() + (std::ptrdiff_t)m, key.end());
-    return key[m].first;
+    const int n_s = (int)ids.size();
+    if (n_s < kParallelMedian) {
+      std::vector<double> key(ids.size());
+      for (size_t i = 0; i < ids.size(); ++i) key[i] = co(ids[i], ax);
+      std::nth_element(key.begin(), key.begin() + (std::ptrdiff_t)m, key.end());
+      return key[m];
+    }
+    // large sets: a histogram of the coordinates over value bins (per
+    // chunk, summed) finds the bin holding rank m; the selection then runs
+    // on that bin's values alone.  The bin index is non-decreasing in the
+    // value, so every value of an earlier bin is smaller: the result is the
+    // exact m-th smallest coordinate.
+    double mn[3], mx[3];
+    extents(ids, mn, mx);
+    const double lo = mn[ax], hi = mx[ax];
+    if (!(hi > lo)) return lo;
+    constexpr int NBIN = 4096;
+    const double scale = NBIN / (hi - lo);
+    auto bin = [&](double x) { return std::min(NBIN - 1, std::max(0, (int)((x - lo) * scale))); };
+    const int nch = std::min(max_workers() * 4, n_s / 4096 + 1), per = (n_s + nch - 1) / nch;
+    std::vector<std::vector<int>> hist(nch, std::vector<int>(NBIN, 0));
+    parallel_for(nch, 1, [&](int c0, int c1, int) {
+      for (int c = c0; c < c1; ++c)
+        for (int i = c * per; i < std::min(n_s, (c + 1) * per); ++i) ++hist[c][bin(co(ids[i], ax))];
+    });
+    int64_t below = 0;
+    int b = 0;
+    for (;; ++b) {
+      int64_t cnt = 0;
+      for (int c = 0; c < nch; ++c) cnt += hist[c][b];
+      if (below + cnt > (int64_t)m || b == NBIN - 1) break;
+      below += cnt;
+    }
+    std::vector<std::vector<double>> part(nch);
+    parallel_for(nch, 1, [&](int c0, int c1, int) {
+      for (int c = c0; c < c1; ++c)
+        for (int i = c * per; i < std::min(n_s, (c + 1) * per); ++i) {
+          const double x = co(ids[i], ax);
+          if (bin(x) == b) part[c].push_back(x);
+        }
+    });
+    std::vector<double> key;
+    for (auto& v : part) key.insert(key.end(), v.begin(), v.end());
+    const size_t mm = m - (size_t)below;
+    std::nth_element(key.begin(), key.begin() + (std::ptrdiff_t)mm, key.end());
+    return key[mm];
   }
+  // S split by keep(v) into (yes, no), both in S's order; large sets in
+  // parallel chunks whose outputs are joined in chunk order
+  template <typename F>
+  void split(const std::vector<int>& S, F keep, std::vector<int>& yes, std::vector<int>& no) const {
+    const int n_s = (int)S.size();
+    if (n_s < kParallelSplit) {
+      for (int v : S) (keep(v) ? yes : no).push_back(v);
+      return;
+    }
+    const int nch = std::min(max_workers() * 4, n_s / 4096 + 1);
+    std::vector<std::vector<int>> cy(nch), cn(nch);
+    const int per = (n_s + nch - 1) / nch;
+    parallel_for(nch, 1, [&](int c0, int c1, int) {
+      for (int c = c0; c < c1; ++c)
+        for (int i = c * per; i < std::min(n_s, (c + 1) * per); ++i) {
+          const int v = S[i];
+          (keep(v) ? cy[c] : cn[c]).push_back(v);
+        }
+    });
+    for (int c = 0; c < nch; ++c) {
+      yes.insert(yes.end(), cy[c].begin(), cy[c].end());
+      no.insert(no.end(), cn[c].begin(), cn[c].end());
+    }
+  }
+  static constexpr int kParallelSplit = 32768;
+  static constexpr int kParallelMedian = 100000;
 
   void kd_order(std::vector<int> ids, std::vector<int>& out) const {
     if ((int)ids.size() <= leaf) {
@@ -118,16 +216,15 @@ struct NDCtx {
     int ax = extent_axis(S);
     const double c = median_coord(S, S.size() / 2, ax);
     std::vector<int> L, R;
-    for (int v : S) (co(v, ax) < c ? L : R).push_back(v);
+    split(S, [&](int v) { return co(v, ax) < c; }, L, R);
     if (L.empty()) return make_leaf(S, out);
     for (int v : L) inL[v] = 1;
     std::vector<int> Sep, Rp;
-    for (int v : R) {
-      bool hit = false;
+    split(R, [&](int v) {
       for (int k = rowptr[v]; k < rowptr[v + 1]; ++k)
-        if (inL[colind[k]]) { hit = true; break; }
-      (hit ? Sep : Rp).push_back(v);
-    }
+        if (inL[colind[k]]) return true;
+      return false;
+    }, Sep, Rp);
     for (int v : L) inL[v] = 0;
     if (Sep.empty()) return make_leaf(S, out);
     std::vector<int> kids;
@@ -215,20 +312,33 @@ std::string validate(int n, const int32_t* rowptr, const int32_t* colind) {
   if (fc == 1) return "column index out of range";
   if (fc == 2) return "columns not strictly increasing within a row";
   if (fc == 3) return "missing diagonal entry in row " + std::to_string(first);
-  // symmetry: every entry (i, j) has its mirror (j, i); rows are sorted, so
-  // a binary search in row j finds it (rows checked in parallel)
+  // symmetry: every entry (i, j) above the diagonal has its mirror (j, i)
+  // (rows are sorted: a binary search in row j, which starts at the mirror's
+  // position at or after the diagonal), and there are as many entries below
+  // the diagonal as above.  Distinct entries above have distinct mirrors, so
+  // equal counts make the mirroring a bijection: the pattern is symmetric.
   std::atomic<bool> asym{false};
+  std::atomic<int64_t> upper{0}, lower{0};
   parallel_for(n, 1024, [&](int r0, int r1, int) {
+    int64_t up = 0, lo = 0;
     for (int i = r0; i < r1 && !asym.load(std::memory_order_relaxed); ++i)
       for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
         const int j = colind[k];
+        if (j < i) {
+          ++lo;
+          continue;
+        }
+        if (j == i) continue;
+        ++up;
         if (!std::binary_search(colind + rowptr[j], colind + rowptr[j + 1], i)) {
           asym.store(true, std::memory_order_relaxed);
           break;
         }
       }
+    upper += up;
+    lower += lo;
   });
-  if (asym.load()) return "pattern is not symmetric";
+  if (asym.load() || upper.load() != lower.load()) return "pattern is not symmetric";
   return "";
 }
 
@@ -337,12 +447,19 @@ std::string analyze(int n, const int32_t* rowptr, const int32_t* colind, const d
     for (int p = b; p < e; ++p) {
       const Front& f = s.fronts[p];
       for (int c : f.children) {
+        // both update sets are ascending: one merge scan places the child's
+        // indices among the parent's pivots and update set
         Front& fc = s.fronts[c];
         fc.relmap.resize(fc.upd.size());
+        size_t q = 0;
         for (size_t a = 0; a < fc.upd.size(); ++a) {
-          int g = fc.upd[a];
-          if (g < f.start + f.npiv) fc.relmap[a] = g - f.start;
-          else fc.relmap[a] = f.npiv + (int)(std::lower_bound(f.upd.begin(), f.upd.end(), g) - f.upd.begin());
+          const int g = fc.upd[a];
+          if (g < f.start + f.npiv) {
+            fc.relmap[a] = g - f.start;
+          } else {
+            while (q < f.upd.size() && f.upd[q] < g) ++q;
+            fc.relmap[a] = f.npiv + (int)q;
+          }
         }
       }
     }
