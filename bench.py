@@ -340,7 +340,7 @@ def main():
         print(json.dumps({"copy_bytes": 4 * n, "copies": 3, "kernels_sha1": kernels_sha1()}), flush=True)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
+        print(json.dumps({"error": "bench.py measures one GPU only; run with --gpus 1"}))
         sys.exit(2)
     import torch
     import paper_1410_2697_amd as mfh
