@@ -208,3 +208,23 @@ def test_merged_group_with_a_request_that_is_not_spd(gpu_lib):
     assert e.value.status == mfh.MF_ENOTSPD
     assert sv.memory()["in_use"] == 0
     sv.close()
+
+
+def test_merged_groups_respect_the_column_limit(gpu_lib):
+    """Requests of 6 right-hand sides each: a group holds at most 16
+    columns, so at most two of them are factored together; every x still
+    matches the oracle."""
+    mfh = gpu_lib
+    first = serving_request(24, 13, nrhs=2)
+    ws = [serving_request(side, seed, nrhs=6) for side, seed in [(9, 41), (10, 42), (11, 43), (12, 44)]]
+    sv = mfh.Server(slots=1, merge=8, **KW)
+    print("case merged serving, 6 right-hand sides per request", flush=True)
+    tickets = [sv.submit(w.problem.A, w.problem.coords, w.b) for w in [first] + ws]
+    groups = []
+    for w, t in zip([first] + ws, tickets):
+        x, info = sv.wait(t)
+        assert info["status"] == 0
+        _check_solution(w, x)
+        groups.append(info["group_size"])
+    assert max(groups[1:]) <= 2, groups
+    sv.close()
