@@ -79,7 +79,7 @@ def kernel_bound(name: str):
     dt = "f32" if "<float" in name else "f64"
     if name.startswith(("gemm_kernel", "potrf_blk_kernel")):   # blocked leaf Cholesky: trailing updates on MFMA
         return "mfma", dt
-    if name.startswith("gemm_narrow_kernel"):   # right-hand-side blocks: streams the factor
+    if name.startswith(("gemm_narrow_kernel", "gemm_narrow_fold_kernel")):   # right-hand-side blocks: streams the factor
         return "hbm", dt
     if name.startswith(("potrf_kernel", "skreg_kernel", "skelfac_kernel", "gj_kernel", "gj_wide_kernel", "phase2_coop_kernel")):
         return "alu", dt

@@ -37,6 +37,21 @@ mf_status mfh_test_gemm_rows(int32_t precision, int32_t m, int32_t n, int32_t k,
                              int32_t opA, const int32_t* arow, const void* B, int32_t ldb, int32_t opB,
                              const int32_t* brow, void* C, int32_t ldc, double alpha, double beta, int32_t kchunk);
 
+/* C = alpha * op(A) * Bf + beta * C (n <= 16, slices[s] <= 8) where Bf
+ * is B as a product that folds a split-K reduction reads it: rows [0, bsplit) of Bf from
+ * source 0, rows [bsplit, k) from source 1.  Source s with slices[s] > 0
+ * gives Bf(i, j) = coef[2s] * sum_q part_s[i' + j*ld[s] + q*ld[s]*n]
+ * + coef[2s+1] * B(i, j), with i' the row inside the source and the slices
+ * summed in order q = 0, 1, ...; a source with slices[s] == 0 reads B.
+ * part0/part1 are device arrays of slices[s] * ld[s] * n elements (ld[s] at
+ * least the source's row count); slices, ld and coef are host arrays of 2,
+ * 2 and 4 entries.  kchunk as for mfh_test_gemm.  The apply reads the
+ * split outputs of h_p, q and z this way. */
+mf_status mfh_test_gemm_fold(int32_t precision, int32_t m, int32_t n, int32_t k, const void* A, int32_t lda,
+                             int32_t opA, const void* B, int32_t ldb, void* C, int32_t ldc, double alpha,
+                             double beta, int32_t kchunk, int32_t bsplit, const void* part0, const void* part1,
+                             const int32_t* slices, const int32_t* ld, const double* coef);
+
 /* In-place Cholesky of the n x n lower triangle of A (n <= 128) and the
  * explicit inverse of the factor into Inv (full square, zeros above).
  * *status_out receives the kernel's status word (1: non-positive pivot). */

@@ -128,6 +128,8 @@ SIGNATURES = [
     ("mfh_test_gemm", _I32, [_I32, _I32, _I32, _I32, _P, _I32, _I32, _P, _I32, _I32, _P, _I32, _D, _D, _I32, _I32]),
     ("mfh_test_gemm_rows", _I32, [_I32, _I32, _I32, _I32, _P, _I32, _I32, _P, _P, _I32, _I32, _P, _P, _I32, _D, _D,
                                   _I32]),
+    ("mfh_test_gemm_fold", _I32, [_I32, _I32, _I32, _I32, _P, _I32, _I32, _P, _I32, _P, _I32, _D, _D, _I32, _I32,
+                                  _P, _P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_D)]),
     ("mfh_test_potrf", _I32, [_I32, _I32, _P, _I32, _P, _I32, ctypes.POINTER(_I32)]),
     ("mfh_test_skeleton", _I32, [_I32, _P, _I32, _I32, _I32, _I32, _I32, _P, _I32, _P, _I32, _D, _I32, _I32,
                                  _P, _P, ctypes.POINTER(_I32)]),

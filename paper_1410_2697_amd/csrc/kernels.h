@@ -13,6 +13,7 @@ constexpr int kTile = 64;            // GEMM output tile (rows and columns)
 constexpr int kTileNarrow = 16;   // output tile width for right-hand-side blocks
 template <typename T>
 constexpr int kGemmBK = sizeof(T) == 4 ? 64 : 32;   // GEMM k step (LDS-staged)
+constexpr int kFoldSlices = 8;      // most partial slices a product reads in place of a reduction
 constexpr int kGemmSplitAlign = 64;  // split-K ranges are multiples of this (and of every k step)
 constexpr double kTieRel = 1.0 / 1048576.0;   // 2^-20: near-ties in complete pivoting
 
@@ -54,6 +55,23 @@ struct GemmDesc {
   int tiles_m, tiles_n;
   int ksplit, kchunk;
   double alpha, beta;
+};
+
+// Folded split K, one per GemmDesc of a launch_gemm_fold batch: B (op N, no
+// row maps, n <= kTileNarrow) is the output of earlier split products whose
+// reduction launch was left out.  Rows [0, split) of B come from source 0,
+// rows [split, k) from source 1.  A source with `slices` > 0 (at most
+// kFoldSlices) reads element (i, j) as
+//   alpha * sum_s part[i + j*ld + s*ld*n] + beta * B(i, j)
+// summed in slice order (the reduction's own order); a source with no
+// slices reads B itself, and a descriptor with no sliced source runs as
+// in launch_gemm.
+template <typename T>
+struct FoldDesc {
+  const T* part[2];
+  int slices[2], ld[2];
+  int split, pad;
+  double alpha[2], beta[2];
 };
 
 // In-place Cholesky of an n x n diagonal block (n <= 128) and, if Inv is
@@ -307,6 +325,9 @@ void launch_gemm(const GemmDesc<T>* d, int ndesc, int tiles, hipStream_t st, int
 // tile0/tiles_m describing this launch's 64 x 64 output tiles
 template <typename T>
 void launch_gemm_reduce(const GemmDesc<T>* d, int ndesc, int tiles, hipStream_t st);
+// 64 x 16 tiles with folded split-K sources for B (f[i] belongs to d[i])
+template <typename T>
+void launch_gemm_fold(const GemmDesc<T>* d, const FoldDesc<T>* f, int ndesc, int tiles, hipStream_t st);
 template <typename T>
 void launch_potrf(const PotrfDesc<T>* d, int ndesc, int nmax, int* status, hipStream_t st);
 // whole-block register skeleton: blocks up to skreg_full_rows<T>() x skreg_full_cols<T>()

@@ -132,6 +132,24 @@ __device__ __forceinline__ T load_op(const T* p, size_t idx, bool bf16) {
   }
   return p[idx];
 }
+// The GEMM's operand loads keep a bfloat16 element's raw bits (zero-extended)
+// in the register and widen it when the register is written to LDS: a
+// conversion right after the load would wait for that load before the next
+// one is issued.
+template <typename T>
+__device__ __forceinline__ T load_raw(const T* p, size_t idx, bool bf16) {
+  if constexpr (sizeof(T) == 4) {
+    if (bf16) return __uint_as_float((unsigned)reinterpret_cast<const unsigned short*>(p)[idx]);
+  }
+  return p[idx];
+}
+template <typename T>
+__device__ __forceinline__ T widen_raw(T v, bool bf16) {
+  if constexpr (sizeof(T) == 4) {
+    if (bf16) return __uint_as_float(__float_as_uint(v) << 16);
+  }
+  return v;
+}
 
 // ---------------------------------------------------------------- GEMM ----
 // 64x64 output tile per workgroup, 4 waves each owning a 32x32 quadrant as
@@ -148,10 +166,13 @@ struct GemmLds {
   T Bs[kGemmBK<T>][BN + 1];
 };
 // ROWS: 0 no row maps; 1 a row map on B only, op N (the apply's reads of
-// x(I_p^f)); 2 row maps on A and/or B in either op.  Each case is its own
-// body: the general one costs the others about a tenth of a launch.
+// x(I_p^f)); 2 row maps on A and/or B in either op; 3 B formed from the
+// partial slices of a split product whose reduction launch was folded into
+// this one (op N, no row maps; gemm_narrow_fold_kernel only).  Each case is its own body: the general one
+// costs the others about a tenth of a launch.
 template <typename T, int BN, int ROWS>
-__device__ __forceinline__ void gemm_tile_body(const GemmDesc<T>& d, int lt, GemmLds<T, BN>& L) {
+__device__ __forceinline__ void gemm_tile_body(const GemmDesc<T>& d, int lt, GemmLds<T, BN>& L,
+                                               const FoldDesc<T>* __restrict__ fd = nullptr) {
   constexpr int BM = kTile, BK = kGemmBK<T>, NQ = BK * 64 / 256, NQB = BK * BN / 256;
   constexpr bool NARROW = BN == 16;
   auto& As = L.As;
@@ -180,6 +201,16 @@ __device__ __forceinline__ void gemm_tile_body(const GemmDesc<T>& d, int lt, Gem
   const int* __restrict__ arow = d.arow;
   const int* __restrict__ brow = d.brow;
   const int lda = d.lda, ldb = d.ldb, opA = d.opA, opB = d.opB;
+  const int bsplit = ROWS == 3 ? fd->split : 0;
+  // the fold descriptor's fields, read once (uniform) and selected per thread
+  int fS0 = 0, fS1 = 0, fld0 = 0, fld1 = 0;
+  const T* __restrict__ fp0 = nullptr;
+  const T* __restrict__ fp1 = nullptr;
+  if constexpr (ROWS == 3) {
+    fS0 = fd->slices[0]; fS1 = fd->slices[1];
+    fld0 = fd->ld[0]; fld1 = fd->ld[1];
+    fp0 = fd->part[0]; fp1 = fd->part[1];
+  }
   const bool abf = (flags & GF_A_BF16) != 0, bbf = (flags & GF_B_BF16) != 0;
   v4 acc00 = {0, 0, 0, 0}, acc01 = {0, 0, 0, 0}, acc10 = {0, 0, 0, 0}, acc11 = {0, 0, 0, 0};
   const int wave = tid >> 6, lane = tid & 63;
@@ -188,6 +219,8 @@ __device__ __forceinline__ void gemm_tile_body(const GemmDesc<T>& d, int lt, Gem
   // per-thread load coordinates: (row of the tile, k offset) for each of NQ loads
   // op N: row = tid & 63, k = (tid >> 6) + 4q;   op T: k = tid % BK, row = tid / BK + (256 / BK) q
   T ra[NQ], rb[NQB];
+  T fw[ROWS == 3 ? NQB : 1][ROWS == 3 ? kFoldSlices : 1];   // folded partial slices
+  int fs[ROWS == 3 ? NQB : 1];                               // 0: B as read; 1 + source
   auto load = [&](int kb) {
     // A thread's loads of one operand all fall in one stored row (op N of A:
     // row tid & 63; op T of A and op N of B: k = tid % BK; op T of B: column
@@ -198,6 +231,7 @@ __device__ __forceinline__ void gemm_tile_body(const GemmDesc<T>& d, int lt, Gem
       if (arow) amap = arow[opA == 0 ? min(m0 + (tid & 63), m - 1) : min(kb + tid % BK, kend - 1)];
       if (brow) bmap = brow[opB == 0 ? min(kb + tid % BK, kend - 1) : min(n0 + tid % BN, n - 1)];
     }
+    if constexpr (ROWS == 1) bmap = brow[min(kb + tid % BK, kend - 1)];   // op N: row kb + tid % BK
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       int i, kk;
@@ -208,10 +242,10 @@ __device__ __forceinline__ void gemm_tile_body(const GemmDesc<T>& d, int lt, Gem
         const bool ok = gi < m && gk < kend;
         int sr = opA == 0 ? gi : gk;   // stored row
         sr = arow ? amap : sr;
-        ra[q] = ok ? load_op(A, opA == 0 ? sr + (size_t)gk * lda : sr + (size_t)gi * lda, abf) : (T)0;
+        ra[q] = ok ? load_raw(A, opA == 0 ? sr + (size_t)gk * lda : sr + (size_t)gi * lda, abf) : (T)0;
       } else {
         ra[q] = (gi < m && gk < kend)
-                    ? load_op(A, opA == 0 ? gi + (size_t)gk * lda : gk + (size_t)gi * lda, abf)
+                    ? load_raw(A, opA == 0 ? gi + (size_t)gk * lda : gk + (size_t)gi * lda, abf)
                     : (T)0;
       }
     }
@@ -222,14 +256,41 @@ __device__ __forceinline__ void gemm_tile_body(const GemmDesc<T>& d, int lt, Gem
       else { j = tid % BN; kk = tid / BN + (256 / BN) * q; }
       const int gj = n0 + j, gk = kb + kk;
       const bool ok = gj < n && gk < kend;
-      if constexpr (ROWS == 2) {
+      if constexpr (ROWS == 3) {
+        // op N: the element's partial slices (at most kFoldSlices) stay in
+        // registers until stash() sums them.  The loads are unconditional
+        // (slice indices clamped, an element outside the tile reads B[0])
+        // so that none waits for another.
+        int S = 0, src = 0;
+        size_t bi = 0, str = 0;
+        const T* __restrict__ p = B;
+        if (ok) {
+          src = gk >= bsplit ? 1 : 0;
+          S = src ? fS1 : fS0;
+          const int ld = src ? fld1 : fld0;
+          bi = gk + (size_t)gj * ldb;
+          if (S) {
+            p = (src ? fp1 : fp0) + (gk - (src ? bsplit : 0)) + (size_t)gj * ld;
+            str = (size_t)ld * n;
+          } else {
+            p = B + bi;
+          }
+        }
+        const int last = S > 0 ? S - 1 : 0;
+#pragma unroll
+        for (int u = 0; u < kFoldSlices; ++u) fw[q][u] = p[(size_t)min(u, last) * str];
+        rb[q] = B[bi];
+        // bit 0: inside the tile; bit 1: source; above: slices.  stash()
+        // drops slices beyond S and zeroes elements outside the tile.
+        fs[q] = ok ? (S << 2) | (src << 1) | 1 : 0;
+      } else if constexpr (ROWS == 2) {
         int sr = opB == 0 ? gk : gj;   // stored row
         sr = brow ? bmap : sr;
-        rb[q] = ok ? load_op(B, opB == 0 ? sr + (size_t)gj * ldb : sr + (size_t)gk * ldb, bbf) : (T)0;
+        rb[q] = ok ? load_raw(B, opB == 0 ? sr + (size_t)gj * ldb : sr + (size_t)gk * ldb, bbf) : (T)0;
       } else {
         int bk = gk;
-        if constexpr (ROWS == 1) bk = ok ? brow[gk] : 0;   // op N when only B's rows are mapped
-        rb[q] = ok ? load_op(B, opB == 0 ? bk + (size_t)gj * ldb : gj + (size_t)gk * ldb, bbf) : (T)0;
+        if constexpr (ROWS == 1) bk = bmap;   // op N when only B's rows are mapped (kk = tid % BK)
+        rb[q] = ok ? load_raw(B, opB == 0 ? bk + (size_t)gj * ldb : gj + (size_t)gk * ldb, bbf) : (T)0;
       }
     }
   };
@@ -239,14 +300,27 @@ __device__ __forceinline__ void gemm_tile_body(const GemmDesc<T>& d, int lt, Gem
       int i, kk;
       if (opA == 0) { i = tid & 63; kk = (tid >> 6) + 4 * q; }
       else { kk = tid % BK; i = tid / BK + (256 / BK) * q; }
-      As[kk][i] = ra[q];
+      As[kk][i] = widen_raw(ra[q], abf);
     }
 #pragma unroll
     for (int q = 0; q < NQB; ++q) {
       int j, kk;
       if (opB == 0) { kk = tid % BK; j = tid / BK + (256 / BK) * q; }
       else { j = tid % BN; kk = tid / BN + (256 / BN) * q; }
-      Bs[kk][j] = rb[q];
+      if constexpr (ROWS == 3) {
+        const int S = fs[q] >> 2, src = (fs[q] >> 1) & 1;
+        if (!(fs[q] & 1)) rb[q] = (T)0;   // outside the tile; inside with no slices: B as read
+        if (S) {   // the reduction's arithmetic, slices in order
+          T s = (T)0;
+#pragma unroll
+          for (int u = 0; u < kFoldSlices; ++u) s += u < S ? fw[q][u] : (T)0;
+          const T bb = (T)(src ? fd->beta[1] : fd->beta[0]);
+          T v = (T)(src ? fd->alpha[1] : fd->alpha[0]) * s;
+          if (bb != (T)0) v += bb * rb[q];
+          rb[q] = v;
+        }
+      }
+      Bs[kk][j] = ROWS == 3 ? rb[q] : widen_raw(rb[q], bbf);
     }
   };
   if (kb0 < kend) load(kb0);
@@ -279,6 +353,15 @@ __device__ __forceinline__ void gemm_tile_body(const GemmDesc<T>& d, int lt, Gem
     const int a = ab >> 1, b = ab & 1;
     const v4 acc = *accs[ab];
     const int col = n0 + wn + b * 16 + li;
+    // the four C values (beta != 0) are loaded before any is used, so that
+    // their loads are in flight together
+    T cv[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = m0 + wm + a * 16 + Mfma<T>::row(lk, v);
+      const bool rd = !split && beta != (T)0 && row < m && col < n && (!(flags & GF_LOWER_C) || row >= col);
+      cv[v] = rd ? C[row + (size_t)col * ldc] : (T)0;
+    }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int row = m0 + wm + a * 16 + Mfma<T>::row(lk, v);
@@ -288,7 +371,7 @@ __device__ __forceinline__ void gemm_tile_body(const GemmDesc<T>& d, int lt, Gem
           *c = acc[v];
         } else if (!(flags & GF_LOWER_C) || row >= col) {
           T val = alpha * acc[v];
-          if (beta != (T)0) val += beta * *c;
+          if (beta != (T)0) val += beta * cv[v];
           *c = val;
         }
       }
@@ -314,6 +397,22 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc<T>* __restrict
 template <typename T>
 __global__ __launch_bounds__(256) void gemm_narrow_kernel(const GemmDesc<T>* __restrict__ descs, int ndesc) {
   gemm_tile<T, kTileNarrow>(descs, ndesc);
+}
+
+// A batch of which some products read B from folded split-K partials; a
+// kernel of its own, so that the other launches keep their registers.
+template <typename T>
+__global__ __launch_bounds__(256) void gemm_narrow_fold_kernel(const GemmDesc<T>* __restrict__ descs,
+                                                               const FoldDesc<T>* __restrict__ folds, int ndesc) {
+  const int di = find_desc_wg(descs, ndesc, (int)blockIdx.x);
+  const GemmDesc<T>& d = descs[di];
+  const FoldDesc<T>* f = folds + di;
+  const int lt = (int)blockIdx.x - d.tile0;
+  __shared__ GemmLds<T, kTileNarrow> L;
+  if (f->slices[0] > 0 || f->slices[1] > 0) gemm_tile_body<T, kTileNarrow, 3>(d, lt, L, f);
+  else if (d.arow || (d.brow && d.opB != 0)) gemm_tile_body<T, kTileNarrow, 2>(d, lt, L);
+  else if (d.brow) gemm_tile_body<T, kTileNarrow, 1>(d, lt, L);
+  else gemm_tile_body<T, kTileNarrow, 0>(d, lt, L);
 }
 
 template <typename T>
@@ -2271,6 +2370,11 @@ void launch_gemm(const GemmDesc<T>* d, int ndesc, int tiles, hipStream_t st, int
   else MFH_LAUNCH(gemm_kernel<T>, dim3(tiles), dim3(256), 0, st, d, ndesc);
 }
 template <typename T>
+void launch_gemm_fold(const GemmDesc<T>* d, const FoldDesc<T>* f, int ndesc, int tiles, hipStream_t st) {
+  if (ndesc <= 0 || tiles <= 0) return;
+  MFH_LAUNCH(gemm_narrow_fold_kernel<T>, dim3(tiles), dim3(256), 0, st, d, f, ndesc);
+}
+template <typename T>
 void launch_gemm_reduce(const GemmDesc<T>* d, int ndesc, int tiles, hipStream_t st) {
   if (ndesc <= 0 || tiles <= 0) return;
   MFH_LAUNCH(gemm_reduce_kernel<T>, dim3(tiles), dim3(256), 0, st, d, ndesc);
@@ -2538,6 +2642,7 @@ void launch_axpby(const double* a, const double* b, double* c, double alpha, dou
 #define MFH_INST(T)                                                                              \
   template void launch_gemm<T>(const GemmDesc<T>*, int, int, hipStream_t, int);                  \
   template void launch_gemm_reduce<T>(const GemmDesc<T>*, int, int, hipStream_t);                \
+  template void launch_gemm_fold<T>(const GemmDesc<T>*, const FoldDesc<T>*, int, int, hipStream_t); \
   template void launch_potrf<T>(const PotrfDesc<T>*, int, int, int*, hipStream_t);               \
   template void launch_skreg_full<T>(const SkRegDesc<T>*, int, double, int, int*, hipStream_t);  \
   template void launch_skreg_hat<T>(const SkRegDesc<T>*, int, double, int*, hipStream_t);        \

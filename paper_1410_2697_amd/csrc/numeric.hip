@@ -26,6 +26,8 @@
 #include <map>
 #include <mutex>
 #include <thread>
+#include <unordered_map>
+#include <unordered_set>
 
 #include "hostpool.h"
 #include "numeric.h"
@@ -415,7 +417,7 @@ std::atomic<uint64_t> g_handle_ids{0};
 // the reduction descriptors of split problems (tile0 over output tiles)
 template <typename T>
 int finalize_gemm(std::vector<GemmDesc<T>>& v, T* part, size_t cap, std::vector<GemmDesc<T>>& red, int& rtiles,
-                  int tn = kTile, int chunk_min = kSplitChunk, int target_set = 0) {
+                  int tn = kTile, int chunk_min = kSplitChunk, int target_set = 0, size_t* used_out = nullptr) {
   red.clear();
   rtiles = 0;
   int base = 0;
@@ -458,6 +460,7 @@ int finalize_gemm(std::vector<GemmDesc<T>>& v, T* part, size_t cap, std::vector<
     }
   }
   v.swap(out);
+  if (used_out) *used_out = used;
   return t;
 }
 
@@ -542,6 +545,10 @@ struct GemmBatch {
   size_t off = 0, roff = 0;
   int tiles = 0, n = 0, rtiles = 0, rn = 0;
   int tn = kTile;                            // output tile width: kTileNarrow when every n <= 16
+  size_t pused = 0;                          // elements of the partial-sum area this batch writes
+  std::vector<FoldDesc<T>> fdesc;            // with nfold: B sources of each descriptor (at foff)
+  size_t foff = 0;
+  bool nfold = false;
   double flops = 0, bytes = 0, rbytes = 0;   // work of the descriptors with a host-known k
   mutable int pid = -1;                      // timing record of the last launch
   // split: split-K partial-sum area (reused by every batch of a stream)
@@ -552,22 +559,92 @@ struct GemmBatch {
     tn = kTileNarrow;
     for (const auto& d : v)
       if (d.n > kTileNarrow) tn = kTile;
-    tiles = finalize_gemm(v, part, cap, red, rtiles, tn, chunk_min, target);
+    tiles = finalize_gemm(v, part, cap, red, rtiles, tn, chunk_min, target, &pused);
     n = (int)v.size();
     off = b.add(v);
-    rn = (int)red.size();
-    if (rn) roff = b.add(red);
-    flops = bytes = rbytes = 0;
+    flops = bytes = 0;
     for (const auto& d : v)
       if (!d.kdev) {
         flops += gemm_flops(d, d.k);
         bytes += gemm_bytes(d, d.k);
       }
-    for (const auto& d : red)
+    stage_reductions(b);
+  }
+  void stage_reductions(Blob& b) {
+    rn = (int)red.size();
+    rtiles = 0;
+    rbytes = 0;
+    for (auto& d : red) {
+      d.tile0 = rtiles;
+      rtiles += d.tiles_m * d.tiles_n;
       rbytes += sizeof(T) * ((double)d.m * d.n * (d.ksplit + (d.beta != 0.0 ? 2 : 1)));
+    }
+    if (rn) roff = b.add(red);
+  }
+  // After this batch is staged: each descriptor whose B is in `foldable`
+  // (an output of the staged batch p that nothing reads afterwards) takes
+  // the partial slices of the split products of p that write it as its B
+  // sources.  The C arrays so folded are appended to `folded`; a descriptor
+  // whose B does not line up with p's outputs reads B as usual.
+  void resolve_folds(const GemmBatch& p, const std::unordered_set<const T*>& foldable, Blob& b,
+                     std::vector<const T*>& folded) {
+    nfold = false;
+    if (tn != kTileNarrow || foldable.empty()) return;   // only the 64 x 16 tile kernel folds
+    std::unordered_map<const T*, const GemmDesc<T>*> out;
+    for (const auto& q : p.v) out.emplace(q.C, &q);
+    auto find = [&](const T* c) -> const GemmDesc<T>* {
+      auto it = out.find(c);
+      return it == out.end() ? nullptr : it->second;
+    };
+    auto fits = [&](const GemmDesc<T>* q, const GemmDesc<T>& d) {
+      return q && q->ldc == d.ldb && q->n == d.n && !(q->flags & GF_LOWER_C) && q->ksplit <= kFoldSlices;
+    };
+    fdesc.assign(v.size(), FoldDesc<T>{});
+    for (size_t i = 0; i < v.size(); ++i) {
+      const GemmDesc<T>& d = v[i];
+      if (!foldable.count(d.B) || d.opB != 0 || d.arow || d.brow || d.kdev ||
+          (d.flags & (GF_B_LOWER | GF_B_UPPER | GF_B_BF16)))
+        continue;
+      const GemmDesc<T>* src[2] = {find(d.B), nullptr};
+      if (!fits(src[0], d) || src[0]->m > d.k) continue;
+      if (src[0]->m < d.k) {
+        src[1] = find(d.B + src[0]->m);
+        if (!fits(src[1], d) || src[0]->m + src[1]->m != d.k) continue;
+      }
+      FoldDesc<T>& f = fdesc[i];
+      f.split = src[0]->m;
+      for (int s = 0; s < 2; ++s) {
+        if (!src[s] || src[s]->ksplit <= 1) continue;
+        f.part[s] = src[s]->part;
+        f.slices[s] = src[s]->ksplit;
+        f.ld[s] = src[s]->m;
+        f.alpha[s] = src[s]->alpha;
+        f.beta[s] = src[s]->beta;
+        nfold = true;
+        folded.push_back(src[s]->C);
+      }
+    }
+    if (nfold) foff = b.add(fdesc);
+    else fdesc.clear();
+  }
+  // After resolve_folds: the reductions of the folded outputs are left out.
+  void drop_reductions(Blob& b, const std::vector<const T*>& folded) {
+    if (folded.empty() || red.empty()) return;
+    const std::unordered_set<const T*> gone(folded.begin(), folded.end());
+    std::vector<GemmDesc<T>> keep;
+    for (const auto& d : red)
+      if (!gone.count(d.C)) keep.push_back(d);
+    if (keep.size() == red.size()) return;
+    red.swap(keep);
+    stage_reductions(b);
   }
   void launch(const char* base, hipStream_t st) const {
-    if (n) {
+    if (n && nfold) {
+      pid = prof_begin(pk<T>(PK_GEMMNF_F64), st, flops, bytes);
+      launch_gemm_fold<T>(reinterpret_cast<const GemmDesc<T>*>(base + off),
+                          reinterpret_cast<const FoldDesc<T>*>(base + foff), n, tiles, st);
+      prof_end(pid, st);
+    } else if (n) {
       pid = prof_begin(pk<T>(tn == kTileNarrow ? PK_GEMMN_F64 : PK_GEMM_F64), st, flops, bytes);
       launch_gemm<T>(reinterpret_cast<const GemmDesc<T>*>(base + off), n, tiles, st, tn);
       prof_end(pid, st);
@@ -775,11 +852,12 @@ class Numeric : public NumericBase {
   void hodlr_level(const std::vector<int>& H, int h);
 
   struct Rec {
-    int kind;                 // 0 gemm T, 1 copy TT, 2 vec_asm, 4 split-K reduction
+    int kind;                 // 0 gemm T, 1 copy TT, 2 vec_asm, 4 split-K reduction, 5 gemm T with folded B
     size_t off;
     int n, tiles;
     double flops = 0, bytes = 0;
     int tn = kTile;           // gemm: output tile width
+    size_t off2 = 0;          // kind 5: the FoldDesc array
   };
   struct Plan {
     int nrhs = 0;
@@ -2250,10 +2328,37 @@ void Numeric<T>::build_plan(Plan& plan, int nrhs, const Layout& L, T* wk, T* par
   pl->xn = wk;
   Blob b;
   const int chunk_min = opts.apply_split_chunk > 0 ? opts.apply_split_chunk : kSplitChunk;
-  auto rec_gemm = [&](GemmBatch<T>& g) {
-    g.stage(b, part, cap, chunk_min, opts.apply_split_target);
-    if (g.n) pl->recs.push_back({0, g.off, g.n, g.tiles, g.flops, g.bytes, g.tn});
+  std::unordered_set<const T*> foldable;   // B arrays read by one product only, right after their writers
+  // the partial-sum area of a batch starts at `off` (past partials that it reads)
+  auto stage_gemm = [&](GemmBatch<T>& g, size_t off) {
+    g.stage(b, off < cap ? part + off : nullptr, off < cap ? cap - off : 0, chunk_min, opts.apply_split_target);
+  };
+  auto push_gemm = [&](GemmBatch<T>& g) {
+    if (g.n && g.nfold) pl->recs.push_back({5, g.off, g.n, g.tiles, g.flops, g.bytes, g.tn, g.foff});
+    else if (g.n) pl->recs.push_back({0, g.off, g.n, g.tiles, g.flops, g.bytes, g.tn});
     if (g.rn) pl->recs.push_back({4, g.roff, g.rn, g.rtiles, 0.0, g.rbytes});
+  };
+  auto rec_gemm = [&](GemmBatch<T>& g) {
+    stage_gemm(g, 0);
+    push_gemm(g);
+  };
+  // c runs right after p and its descriptors marked by fold_b read outputs of p
+  // that nothing reads later: those outputs' split-K partials are summed
+  // while c loads its B operand, and their reduction launch is left out
+  auto rec_pair = [&](GemmBatch<T>& p, GemmBatch<T>& c) {
+    stage_gemm(p, 0);
+    stage_gemm(c, p.pused);
+    std::vector<const T*> folded;
+    c.resolve_folds(p, foldable, b, folded);
+    p.drop_reductions(b, folded);
+    push_gemm(p);
+    push_gemm(c);
+  };
+  // marks a product whose B (u2: h_p, g2: q, d2: h_p or z) is written by
+  // the batch just before it and read by nothing after it
+  auto fold_b = [&](GemmDesc<T> g) {
+    foldable.insert(g.B);
+    return g;
   };
   auto rec_copy = [&](CopyBatch<T, T>& c) {
     c.stage(b);
@@ -2288,7 +2393,7 @@ void Numeric<T>::build_plan(Plan& plan, int nrhs, const Layout& L, T* wk, T* par
         T* hb = wk + h_off[p];
         if (x.r_top > 0) {
           u1.v.push_back(gd<T>(x.G, np, 1, t, nh, 0, hb, x.r_top, x.r_top, nrhs, np, 1.0, 0.0));   // X^T t_p
-          u2.v.push_back(gd<T>(x.W, nf, 0, hb, x.r_top, 0, t + np, nh, nf, nrhs, x.r_top, -1.0, 1.0, bff));
+          u2.v.push_back(fold_b(gd<T>(x.W, nf, 0, hb, x.r_top, 0, t + np, nh, nf, nrhs, x.r_top, -1.0, 1.0, bff)));
         }
         for (size_t i = 0; i < f.pp_tree.size(); ++i) {
           const TreeNode& tn = f.pp_tree[i];
@@ -2308,8 +2413,7 @@ void Numeric<T>::build_plan(Plan& plan, int nrhs, const Layout& L, T* wk, T* par
     // u2 (rows np.. of t, after u1) and lf1 (reads the pivot rows of t,
     // after u1 has read them) touch different memory, so they share a launch
     lf1.v.insert(lf1.v.end(), u2.v.begin(), u2.v.end());
-    rec_gemm(u1);
-    rec_gemm(lf1);
+    rec_pair(u1, lf1);
     rec_gemm(lf2);
     for (int l = Lmax - 1; l >= 0; --l) {
       GemmBatch<T> g1, g2, g3;
@@ -2329,15 +2433,14 @@ void Numeric<T>::build_plan(Plan& plan, int nrhs, const Layout& L, T* wk, T* par
           T* q2 = q + (int64_t)n2 * nrhs;
           g1.v.push_back(gd<T>(x.nodeV[i], a.size, 1, z + a.off, zl, 0, q, n2, r, nrhs, a.size, 1.0, 0.0, bff));
           g1.v.push_back(gd<T>(x.nodeU[i], be.size, 1, z + be.off, zl, 0, q + r, n2, r, nrhs, be.size, 1.0, 0.0, bff));
-          g2.v.push_back(gd<T>(x.nodeK[i], n2, 0, q, n2, 0, q2, n2, n2, nrhs, n2, 1.0, 0.0));
+          g2.v.push_back(fold_b(gd<T>(x.nodeK[i], n2, 0, q, n2, 0, q2, n2, n2, nrhs, n2, 1.0, 0.0)));
           g3.v.push_back(gd<T>(x.G + a.off + (int64_t)c * np, np, 0, q2, n2, 0, z + a.off, zl, a.size, nrhs, r, -1.0,
                                1.0));
           g3.v.push_back(gd<T>(x.G + be.off + (int64_t)c * np, np, 0, q2 + r, n2, 0, z + be.off, zl, be.size, nrhs, r,
                                -1.0, 1.0));
         }
       }
-      rec_gemm(g1);
-      rec_gemm(g2);
+      rec_pair(g1, g2);
       rec_gemm(g3);
     }
   }
@@ -2385,19 +2488,18 @@ void Numeric<T>::build_plan(Plan& plan, int nrhs, const Layout& L, T* wk, T* par
           g.brow = upd_dev.at(p);
           d1.v.push_back(g);
         }
-        d2.v.push_back(gd<T>(x.Linv, np, 1, z, np, 0, pl->xn + f.start, N, np, nrhs, np, 1.0, 0.0, GF_A_UPPER));
+        d2.v.push_back(fold_b(gd<T>(x.Linv, np, 1, z, np, 0, pl->xn + f.start, N, np, nrhs, np, 1.0, 0.0, GF_A_UPPER)));
       } else {
         T* hb = wk + h_off[p];
         if (x.r_top > 0) {
           auto g = gd<T>(x.W, nf, 1, pl->xn, N, 0, hb, x.r_top, x.r_top, nrhs, nf, 1.0, 0.0, bff);
           g.brow = upd_dev.at(p);
           d1.v.push_back(g);
-          d2.v.push_back(gd<T>(x.G, np, 0, hb, x.r_top, 0, pl->xn + f.start, N, np, nrhs, x.r_top, -1.0, 1.0));
+          d2.v.push_back(fold_b(gd<T>(x.G, np, 0, hb, x.r_top, 0, pl->xn + f.start, N, np, nrhs, x.r_top, -1.0, 1.0)));
         }
       }
     }
-    rec_gemm(d1);
-    rec_gemm(d2);
+    rec_pair(d1, d2);
   }
   pl->desc = upload(b);
 }
@@ -2503,6 +2605,13 @@ void Numeric<T>::launch_recs(const Plan& plan, hipStream_t stream) {
         const int id = prof_begin(pk<T>(rc.tn == kTileNarrow ? PK_GEMMN_F64 : PK_GEMM_F64), stream, rc.flops,
                                   rc.bytes);
         launch_gemm<T>(reinterpret_cast<const GemmDesc<T>*>(base), rc.n, rc.tiles, stream, rc.tn);
+        prof_end(id, stream);
+        break;
+      }
+      case 5: {
+        const int id = prof_begin(pk<T>(PK_GEMMNF_F64), stream, rc.flops, rc.bytes);
+        launch_gemm_fold<T>(reinterpret_cast<const GemmDesc<T>*>(base),
+                            reinterpret_cast<const FoldDesc<T>*>(pl->desc + rc.off2), rc.n, rc.tiles, stream);
         prof_end(id, stream);
         break;
       }

@@ -12,6 +12,7 @@ const char* const kNames[PK_COUNT] = {
     "gemm_kernel<double>",        "gemm_kernel<float>",
     "gemm_narrow_kernel<double>", "gemm_narrow_kernel<float>",
     "gemm_reduce_kernel<double>", "gemm_reduce_kernel<float>",
+    "gemm_narrow_fold_kernel<double>", "gemm_narrow_fold_kernel<float>",
     "potrf_blk_kernel<double, 64>",   "potrf_blk_kernel<float, 64>",
     "potrf_kernel<double, 128, 512>", "potrf_blk_kernel<float, 128>",
     "skreg_kernel<double, 2, 16, true, 1024>", "skreg_kernel<float, 4, 16, true, 1024>",

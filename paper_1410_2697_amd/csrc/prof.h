@@ -18,6 +18,7 @@ enum ProfKind : int {
   PK_GEMM_F64, PK_GEMM_F32,
   PK_GEMMN_F64, PK_GEMMN_F32,          // 64 x 16 tiles (right-hand-side blocks)
   PK_GEMM_REDUCE_F64, PK_GEMM_REDUCE_F32,
+  PK_GEMMNF_F64, PK_GEMMNF_F32,        // 64 x 16 tiles reading folded split-K partials
   PK_POTRF64_F64, PK_POTRF64_F32,      // leaf size <= 64
   PK_POTRF128_F64, PK_POTRF128_F32,
   PK_SKREG_FULL_F64, PK_SKREG_FULL_F32,

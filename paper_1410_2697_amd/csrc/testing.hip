@@ -1,5 +1,6 @@
 // Kernel-level test hooks (include/mfh_testing.h): one problem per call,
 // synchronous, on the null stream.
+#include <algorithm>
 #include <string>
 
 #include "../../include/mfh_testing.h"
@@ -18,7 +19,7 @@ mf_status hip_ok(hipError_t e) {
 template <typename T>
 mf_status gemm_t(int m, int n, int k, const void* A, int lda, int opA, const void* B, int ldb, int opB, void* C,
                  int ldc, double alpha, double beta, int flags, int kchunk, const int* arow = nullptr,
-                 const int* brow = nullptr) {
+                 const int* brow = nullptr, const mfh::FoldDesc<T>* fold = nullptr) {
   mfh::GemmDesc<T> d{};
   d.A = static_cast<const T*>(A); d.B = static_cast<const T*>(B); d.C = static_cast<T*>(C);
   d.arow = arow; d.brow = brow;
@@ -37,8 +38,9 @@ mf_status gemm_t(int m, int n, int k, const void* A, int lda, int opA, const voi
   const int otiles = d.tiles_m * d.tiles_n;
   if (otiles == 0) return MF_OK;
   mfh::GemmDesc<T>* dd = nullptr;
-  mf_status s = hip_ok(hipMalloc(&dd, 2 * sizeof(d)));
+  mf_status s = hip_ok(hipMalloc(&dd, 2 * sizeof(d) + sizeof(mfh::FoldDesc<T>)));
   if (s != MF_OK) return s;
+  auto* df = reinterpret_cast<mfh::FoldDesc<T>*>(dd + 2);
   if (d.ksplit > 1) {
     s = hip_ok(hipMalloc(&d.part, (size_t)d.ksplit * m * n * sizeof(T)));
     if (s != MF_OK) { hipFree(dd); return s; }
@@ -47,7 +49,12 @@ mf_status gemm_t(int m, int n, int k, const void* A, int lda, int opA, const voi
   r.tiles_n = (n + mfh::kTile - 1) / mfh::kTile;
   hipMemcpy(dd, &d, sizeof(d), hipMemcpyHostToDevice);
   hipMemcpy(dd + 1, &r, sizeof(r), hipMemcpyHostToDevice);
-  mfh::launch_gemm<T>(dd, 1, otiles * d.ksplit, nullptr, tn);
+  if (fold) {
+    hipMemcpy(df, fold, sizeof(*fold), hipMemcpyHostToDevice);
+    mfh::launch_gemm_fold<T>(dd, df, 1, otiles * d.ksplit, nullptr);
+  } else {
+    mfh::launch_gemm<T>(dd, 1, otiles * d.ksplit, nullptr, tn);
+  }
   if (d.ksplit > 1) mfh::launch_gemm_reduce<T>(dd + 1, 1, r.tiles_m * r.tiles_n, nullptr);
   s = hip_ok(hipDeviceSynchronize());
   hipFree(dd);
@@ -216,6 +223,35 @@ mf_status mfh_test_gemm_rows(int32_t precision, int32_t m, int32_t n, int32_t k,
   if (precision == MF_FP64)
     return gemm_t<double>(m, n, k, A, lda, opA, B, ldb, opB, C, ldc, alpha, beta, 0, kchunk, arow, brow);
   return gemm_t<float>(m, n, k, A, lda, opA, B, ldb, opB, C, ldc, alpha, beta, 0, kchunk, arow, brow);
+}
+
+mf_status mfh_test_gemm_fold(int32_t precision, int32_t m, int32_t n, int32_t k, const void* A, int32_t lda,
+                             int32_t opA, const void* B, int32_t ldb, void* C, int32_t ldc, double alpha,
+                             double beta, int32_t kchunk, int32_t bsplit, const void* part0, const void* part1,
+                             const int32_t* slices, const int32_t* ld, const double* coef) {
+  if (m < 0 || n < 0 || n > mfh::kTileNarrow || k < 0 || !C || kchunk < 0 || kchunk % mfh::kGemmSplitAlign != 0 ||
+      bsplit < 0 || bsplit > k || !slices || !ld || !coef)
+    return MF_EINVAL;
+  const void* parts[2] = {part0, part1};
+  const int rows[2] = {bsplit, k - bsplit};
+  for (int s = 0; s < 2; ++s)
+    if (slices[s] < 0 || slices[s] > mfh::kFoldSlices ||
+        (slices[s] > 0 && (!parts[s] || ld[s] < std::max(rows[s], 1))))
+      return MF_EINVAL;
+  auto run = [&](auto zero) -> mf_status {
+    using T = decltype(zero);
+    mfh::FoldDesc<T> f{};
+    f.split = bsplit;
+    for (int s = 0; s < 2; ++s) {
+      f.part[s] = slices[s] > 0 ? static_cast<const T*>(parts[s]) : nullptr;
+      f.slices[s] = slices[s];
+      f.ld[s] = ld[s];
+      f.alpha[s] = coef[2 * s];
+      f.beta[s] = coef[2 * s + 1];
+    }
+    return gemm_t<T>(m, n, k, A, lda, opA, B, ldb, 0, C, ldc, alpha, beta, 0, kchunk, nullptr, nullptr, &f);
+  };
+  return precision == MF_FP64 ? run(0.0) : run(0.0f);
 }
 
 mf_status mfh_test_potrf(int32_t precision, int32_t n, void* A, int32_t lda, void* Inv, int32_t ldi,

@@ -370,3 +370,81 @@ def test_gemm_row_map(gpu_lib, prec, m, n, k, opA, opB, amap, bmap, kchunk):
     ref = C0.astype(cast).astype(np.float64) - (Ar.T if opA else Ar) @ (Br.T if opB else Br)
     tol = 1e-13 if prec == "fp64" else 2e-5
     assert np.abs(_host(dC, m) - ref).max() <= tol * np.sqrt(k) * max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("m,n,k,opA,bsplit,s0,s1,beta0,kchunk", [
+    (96, 16, 200, 0, 200, 4, 0, 0.0, 0),       # u2 / d2 of a HODLR front: h_p from one split product
+    (130, 16, 333, 1, 333, 3, 0, 1.0, 0),      # d2 of a dense front: z - L_fp^T x_f, split, beta 1
+    (78, 16, 78, 0, 39, 2, 2, 0.0, 0),         # g2: q from two split products
+    (100, 7, 150, 0, 70, 0, 5, 0.0, 0),        # one source split, the other read as written
+    (64, 16, 1024, 1, 1024, 8, 0, 0.0, 256),   # eight slices, the consumer itself split
+    (113, 16, 1056, 0, 600, 6, 3, 1.0, 128),   # six and three slices, both split, consumer split
+    (17, 1, 5, 0, 2, 1, 8, 0.0, 0),            # ragged: one column, eight slices over three rows
+])
+def test_gemm_folded_partials(gpu_lib, prec, m, n, k, opA, bsplit, s0, s1, beta0, kchunk):
+    """A product whose B is the output of split-K products read straight from
+    their partial slices (the apply's reads of h_p, q and z without their
+    reduction launches): equal to the product with B formed as the
+    reduction forms it."""
+    import torch
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    cast = np.float32 if prec == "fp32" else np.float64
+    rng = np.random.default_rng(m * 7 + n + k + s0 + 3 * s1)
+    Aop = rng.standard_normal((m, k))
+    A = Aop.T.copy() if opA else Aop
+    B = rng.standard_normal((k, n))
+    rows = (bsplit, k - bsplit)
+    S = (s0, s1)
+    coef = (-1.0, beta0, 0.5, 0.0)
+    lds = (max(rows[0], 1) + 2, max(rows[1], 1) + 1)
+    parts, dparts = [], []
+    for s in range(2):
+        P = rng.standard_normal((S[s], lds[s], n)) if S[s] else None
+        parts.append(P)
+        if P is None:
+            dparts.append(None)
+            continue
+        # slice q holds element (i, j) at i + j*ld + q*ld*n
+        flat = np.transpose(P, (0, 2, 1)).reshape(-1)
+        dparts.append(torch.tensor(flat, dtype=dt, device="cuda"))
+    lda, ldb, ldc = A.shape[0] + 3, k + 2, m + 1
+    C0 = rng.standard_normal((m, n))
+    dA, dB, dC = _dev(A, lda, dt), _dev(B, ldb, dt), _dev(C0, ldc, dt)
+    sl = (ctypes.c_int32 * 2)(*S)
+    ld = (ctypes.c_int32 * 2)(*lds)
+    cf = (ctypes.c_double * 4)(*coef)
+    st = gpu_lib.load().mfh_test_gemm_fold(0 if prec == "fp64" else 1, m, n, k, _p(dA), lda, opA, _p(dB), ldb,
+                                           _p(dC), ldc, 0.75, -0.5, kchunk, bsplit,
+                                           _p(dparts[0]) if dparts[0] is not None else None,
+                                           _p(dparts[1]) if dparts[1] is not None else None, sl, ld, cf)
+    assert st == 0
+    Br = B.astype(cast).astype(np.float64)
+    Bf = Br.copy()
+    for s in range(2):
+        r0 = 0 if s == 0 else bsplit
+        if not S[s] or rows[s] == 0:
+            continue
+        tot = parts[s].astype(cast).astype(np.float64)[:, :rows[s], :].sum(axis=0)
+        Bf[r0:r0 + rows[s]] = coef[2 * s] * tot + coef[2 * s + 1] * Br[r0:r0 + rows[s]]
+    Ar = A.astype(cast).astype(np.float64)
+    ref = 0.75 * (Ar.T if opA else Ar) @ Bf - 0.5 * C0.astype(cast).astype(np.float64)
+    tol = 1e-13 if prec == "fp64" else 3e-5
+    assert np.abs(_host(dC, m) - ref).max() <= tol * np.sqrt(k * (1 + max(S))) * max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("bad", ["wide", "chunk", "bsplit", "ld", "noptr", "slices"])
+def test_gemm_folded_partials_rejects(gpu_lib, bad):
+    """Argument checks of the folded-partials hook (no launch is made)."""
+    import torch
+    d = torch.zeros(64 * 64, dtype=torch.float64, device="cuda")
+    n = 17 if bad == "wide" else 4
+    kchunk = 100 if bad == "chunk" else 0
+    bsplit = 9 if bad == "bsplit" else 4
+    sl = (ctypes.c_int32 * 2)(9 if bad == "slices" else 2, 0)
+    ld = (ctypes.c_int32 * 2)(3 if bad == "ld" else 4, 1)
+    cf = (ctypes.c_double * 4)(1.0, 0.0, 1.0, 0.0)
+    p0 = None if bad == "noptr" else _p(d)
+    st = gpu_lib.load().mfh_test_gemm_fold(0, 8, n, 8, _p(d), 8, 0, _p(d), 8, _p(d), 8, 1.0, 0.0, kchunk, bsplit,
+                                           p0, None, sl, ld, cf)
+    assert st == 1   # MF_EINVAL
