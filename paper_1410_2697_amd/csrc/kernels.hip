@@ -1830,10 +1830,26 @@ __global__ __launch_bounds__(256) void copy_kernel(const CopyDesc<S, D>* __restr
   const CopyDesc<S, D>& d = descs[di];
   const int lt = (int)blockIdx.x - d.tile0;
   const int tr = lt % d.tiles_r, tc = lt / d.tiles_r;
-  for (int e = threadIdx.x; e < kTile * kTile; e += blockDim.x) {
+  // 256 threads, PER entries each: every load of the tile is issued before
+  // the first store (a load used right away would wait before the next)
+  constexpr int PER = kTile * kTile / 256;
+  S sv[PER];
+  D dv[PER];
+  const bool acc = d.accumulate != 0;
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = (int)threadIdx.x + u * 256;
+    const int i = tr * kTile + (e & 63), j = tc * kTile + (e >> 6);
+    const bool in = i < d.rows && j < d.cols;
+    sv[u] = in ? d.src[i + (size_t)j * d.lds] : (S)0;
+    dv[u] = in && acc ? d.dst[i + (size_t)j * d.ldd] : (D)0;
+  }
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = (int)threadIdx.x + u * 256;
     const int i = tr * kTile + (e & 63), j = tc * kTile + (e >> 6);
     if (i < d.rows && j < d.cols) {
-      D v = (D)(d.alpha * (double)d.src[i + (size_t)j * d.lds]);
+      D v = (D)(d.alpha * (double)sv[u]);
       const size_t o = i + (size_t)j * d.ldd;
       if constexpr (sizeof(D) == 4) {
         if (d.bf16 == 2) {
@@ -1842,7 +1858,7 @@ __global__ __launch_bounds__(256) void copy_kernel(const CopyDesc<S, D>* __restr
         }
         if (d.bf16 == 1) v = bf16_to_float(float_to_bf16(v));
       }
-      if (d.accumulate) v += d.dst[o];
+      if (acc) v += dv[u];
       d.dst[o] = v;
     }
   }
@@ -2143,10 +2159,15 @@ __global__ __launch_bounds__(256) void vec_asm_kernel(const VecAsmDesc<T>* __res
         r[u] = a < cnf ? rel[a] : -1;
         v[u] = a < cnf ? ct[a] : (T)0;
       }
-      // a child's relative map is one-to-one, so these entries are distinct
+      // a child's relative map is one-to-one, so these entries are distinct.
+      // The parent entries are loaded unconditionally (entry 0 for the
+      // unused slots) so that their loads are in flight together.
+      T tv[kVecBatch];
+#pragma unroll
+      for (int u = 0; u < kVecBatch; ++u) tv[u] = t[r[u] >= 0 ? r[u] : 0];
 #pragma unroll
       for (int u = 0; u < kVecBatch; ++u)
-        if (r[u] >= 0) v[u] += t[r[u]];
+        if (r[u] >= 0) v[u] += tv[u];
 #pragma unroll
       for (int u = 0; u < kVecBatch; ++u)
         if (r[u] >= 0) t[r[u]] = v[u];
@@ -2198,6 +2219,7 @@ __global__ __launch_bounds__(256) void spmv_kernel(const int* __restrict__ rowpt
                                                    double* y, int n, int nrhs, double alpha, double beta,
                                                    const int* __restrict__ win) {
   constexpr int KB = 16, G = kSpmvLanes;
+  static_assert(KB % G == 0, "each lane writes KB / G columns");
   const int row = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G);
   const int g = threadIdx.x % G;
   if (row >= n) return;                    // whole groups leave together (G divides the wave)
@@ -2220,20 +2242,36 @@ __global__ __launch_bounds__(256) void spmv_kernel(const int* __restrict__ rowpt
     for (int j = j0 + g; j < j1; j += G) {
       const double v = vals[j];
       const double* xc = x + colind[j] + (size_t)k0 * n;
+      // all KB loads in flight at once: columns past kb re-read column
+      // kb - 1 and are dropped (a load used right away, under a branch,
+      // would wait before the next one is issued)
+      double xv[KB];
 #pragma unroll
-      for (int q = 0; q < KB; ++q)
-        if (q < kb) acc[q] += v * xc[(size_t)q * n];
+      for (int q = 0; q < KB; ++q) xv[q] = xc[(size_t)min(q, kb - 1) * n];
+#pragma unroll
+      for (int q = 0; q < KB; ++q) acc[q] += q < kb ? v * xv[q] : 0.0;
     }
 #pragma unroll
     for (int q = 0; q < KB; ++q)
       if (q < kb)
         for (int o = G / 2; o > 0; o >>= 1) acc[q] += __shfl_xor(acc[q], o, G);
+    // lane g writes columns g, g + G, ...: its sums are selected without
+    // branches and its y values (beta != 0) loaded before any is used
+    constexpr int H = KB / G;
+    double mine[H], yv[H];
 #pragma unroll
-    for (int q = 0; q < KB; ++q)
-      if (q < kb && q % G == g) {
-        double* yo = y + (size_t)(k0 + q) * n + row;
-        *yo = beta == 0.0 ? alpha * acc[q] : alpha * acc[q] + beta * *yo;
-      }
+    for (int h = 0; h < H; ++h) {
+      const int q = g + h * G;
+      mine[h] = 0.0;
+#pragma unroll
+      for (int qq = 0; qq < KB; ++qq) mine[h] = qq == q ? acc[qq] : mine[h];
+      yv[h] = beta == 0.0 ? 0.0 : y[(size_t)(k0 + min(q, kb - 1)) * n + row];
+    }
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+      const int q = g + h * G;
+      if (q < kb) y[(size_t)(k0 + q) * n + row] = beta == 0.0 ? alpha * mine[h] : alpha * mine[h] + beta * yv[h];
+    }
   }
 }
 
@@ -2258,9 +2296,13 @@ __global__ __launch_bounds__(256) void mdot_partial_kernel(const double* X, int6
   const double* Xk = X + (size_t)i0 * xstride + (size_t)k * n;
   for (int row = lo + threadIdx.x; row < hi; row += blockDim.x) {
     const double wv = wk[row];
+    // all kMdotGroup loads in flight together: vectors past m re-read
+    // vector m - 1 into sums that are never stored
+    double xv[kMdotGroup];
 #pragma unroll
-    for (int i = 0; i < kMdotGroup; ++i)
-      if (i < m) acc[i] += Xk[i * xstride + row] * wv;
+    for (int i = 0; i < kMdotGroup; ++i) xv[i] = Xk[min(i, m - 1) * xstride + row];
+#pragma unroll
+    for (int i = 0; i < kMdotGroup; ++i) acc[i] += xv[i] * wv;
   }
 #pragma unroll
   for (int i = 0; i < kMdotGroup; ++i)
@@ -2292,6 +2334,7 @@ __global__ void maxpy_kernel(const double* X, int64_t xstride, int nv, const dou
   for (int row = lo + blockIdx.x * blockDim.x + threadIdx.x; row < hi; row += gridDim.x * blockDim.x) {
     const int64_t idx = (int64_t)k * n + row;
     double s = 0.0;
+#pragma unroll 8
     for (int i = 0; i < nv; ++i) s += coef[i * nrhs + k] * X[i * xstride + idx];
     w[idx] += sign * s;
   }
@@ -2316,6 +2359,7 @@ __global__ void xupdate_kernel(const double* Z, int64_t zstride, int nv, const d
   for (int row = lo + blockIdx.x * blockDim.x + threadIdx.x; row < hi; row += gridDim.x * blockDim.x) {
     const int64_t idx = (int64_t)k * n + row;
     double s = 0.0;
+#pragma unroll 8
     for (int i = 0; i < nv; ++i) s += y[i * nrhs + k] * Z[i * zstride + idx];
     x[idx] += s;
   }
@@ -2489,6 +2533,7 @@ hipError_t launch_phase2_coop(const Phase2CoopDesc<T>* d, int ndesc, int wgs, si
     e = hipEventSynchronize(L.ev);
     if (e != hipSuccess) return e;
   }
+  (void)hipGetLastError();   // what follows reports this launch's error only
   if (slice_lds)
     MFH_LAUNCH((phase2_coop_kernel<T, true>), dim3(wgs), dim3(kCoopThreads), lds, st, d, ndesc, eps, status,
                wait_ticks);

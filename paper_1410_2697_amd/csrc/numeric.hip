@@ -277,6 +277,16 @@ class HipObjPool {
   }
   static void put(int dev, hipStream_t s) {
     if (!s) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
+      // not reusable: a later owner's events would land in an open capture
+      hipGraph_t gr = nullptr;
+      if (cs != hipStreamCaptureStatusNone && hipStreamEndCapture(s, &gr) == hipSuccess && gr)
+        (void)hipGraphDestroy(gr);
+      (void)hipStreamDestroy(s);
+      (void)hipGetLastError();
+      return;
+    }
     std::lock_guard<std::mutex> g(mu());
     if (streams()[dev].size() < kKeep) streams()[dev].push_back(s);
     else (void)hipStreamDestroy(s);
@@ -901,6 +911,7 @@ class Numeric : public NumericBase {
       HipObjPool::put(self->device, self->ev_join);
       HipObjPool::put(self->device, self->side);
       HipObjPool::put(self->device, self->cap);
+      (void)hipGetLastError();   // the calls above report nothing to later ones
     }
   } sync_guard{this};
 };
@@ -2527,7 +2538,15 @@ void Numeric<T>::apply(int nrhs, const double* r, double* z, hipStream_t stream)
     ok = ok && hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
     if (ok) {
       prof_suspend(true);
-      launch_recs(*pl, cap);
+      try {
+        launch_recs(*pl, cap);
+      } catch (...) {   // never leave the stream capturing
+        prof_suspend(false);
+        if (hipStreamEndCapture(cap, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        pl->no_graph = true;
+        throw;
+      }
       prof_suspend(false);
       ok = hipStreamEndCapture(cap, &g) == hipSuccess && g;
       ok = ok && hipGraphInstantiate(&pl->exec, g, nullptr, nullptr, 0) == hipSuccess;
@@ -2629,25 +2648,35 @@ void Numeric<T>::launch_recs(const Plan& plan, hipStream_t stream) {
 
 void NumericBase::note_stream(hipStream_t st) {
   std::lock_guard<std::mutex> g(ev_mu);
+  // a failed record is dropped here, not left for the next hipGetLastError
   for (auto& e : stream_events)
     if (e.first == st) {
-      (void)hipEventRecord(e.second, st);
+      if (hipEventRecord(e.second, st) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipStreamSynchronize(st);
+        (void)hipGetLastError();
+      }
       return;
     }
   hipEvent_t ev = nullptr;
   if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
     (void)hipGetLastError();
     (void)hipStreamSynchronize(st);
+    (void)hipGetLastError();
     return;
   }
-  (void)hipEventRecord(ev, st);
+  if (hipEventRecord(ev, st) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipStreamSynchronize(st);
+    (void)hipGetLastError();
+  }
   stream_events.push_back({st, ev});
 }
 
 void NumericBase::wait_streams() {
   std::lock_guard<std::mutex> g(ev_mu);
   for (auto& e : stream_events) {
-    (void)hipEventSynchronize(e.second);
+    if (hipEventSynchronize(e.second) != hipSuccess) (void)hipGetLastError();
     (void)hipEventDestroy(e.second);
   }
   stream_events.clear();
