@@ -258,30 +258,28 @@ __device__ __forceinline__ void gemm_tile_body(const GemmDesc<T>& d, int lt, Gem
       const bool ok = gj < n && gk < kend;
       if constexpr (ROWS == 3) {
         // op N: the element's partial slices (at most kFoldSlices) stay in
-        // registers until stash() sums them.  The loads are unconditional
-        // (slice indices clamped, an element outside the tile reads B[0])
-        // so that none waits for another.
+        // registers until stash() sums them.  Each lane of a column inside
+        // the tile issues kFoldSlices loads (slice indices clamped), so
+        // that none waits for another; columns outside load nothing.
         int S = 0, src = 0;
-        size_t bi = 0, str = 0;
-        const T* __restrict__ p = B;
-        if (ok) {
-          src = gk >= bsplit ? 1 : 0;
+        if (gj < n) {   // a column is shared by a whole wave (FP32) or half a wave (FP64)
+          // rows past kend (last k step) read row kend - 1 and are zeroed in stash()
+          const int gkc = min(gk, kend - 1);
+          src = gkc >= bsplit ? 1 : 0;
           S = src ? fS1 : fS0;
           const int ld = src ? fld1 : fld0;
-          bi = gk + (size_t)gj * ldb;
+          const size_t bi = gkc + (size_t)gj * ldb;
+          const T* __restrict__ p = B + bi;
+          size_t str = 0;
           if (S) {
-            p = (src ? fp1 : fp0) + (gk - (src ? bsplit : 0)) + (size_t)gj * ld;
+            p = (src ? fp1 : fp0) + (gkc - (src ? bsplit : 0)) + (size_t)gj * ld;
             str = (size_t)ld * n;
-          } else {
-            p = B + bi;
           }
-        }
-        const int last = S > 0 ? S - 1 : 0;
+          const int last = S > 0 ? S - 1 : 0;
 #pragma unroll
-        for (int u = 0; u < kFoldSlices; ++u) fw[q][u] = p[(size_t)min(u, last) * str];
-        rb[q] = B[bi];
-        // bit 0: inside the tile; bit 1: source; above: slices.  stash()
-        // drops slices beyond S and zeroes elements outside the tile.
+          for (int u = 0; u < kFoldSlices; ++u) fw[q][u] = p[(size_t)min(u, last) * str];
+          rb[q] = B[bi];
+        }
         fs[q] = ok ? (S << 2) | (src << 1) | 1 : 0;
       } else if constexpr (ROWS == 2) {
         int sr = opB == 0 ? gk : gj;   // stored row
@@ -2234,6 +2232,7 @@ __global__ __launch_bounds__(256) void spmv_kernel(const int* __restrict__ rowpt
       }
   }
   const int j0 = rowptr[row], j1 = rowptr[row + 1];
+  const int kmax = min(KB, nrhs);   // bound on kb shared by every lane: loads past it are not issued
   for (int k0 = c0; k0 < c1; k0 += KB) {
     const int kb = min(KB, c1 - k0);
     double acc[KB];
@@ -2242,14 +2241,16 @@ __global__ __launch_bounds__(256) void spmv_kernel(const int* __restrict__ rowpt
     for (int j = j0 + g; j < j1; j += G) {
       const double v = vals[j];
       const double* xc = x + colind[j] + (size_t)k0 * n;
-      // all KB loads in flight at once: columns past kb re-read column
-      // kb - 1 and are dropped (a load used right away, under a branch,
-      // would wait before the next one is issued)
+      // all loads in flight at once: columns past kb (up to kmax) re-read
+      // column kb - 1 and are dropped (a load used right away, under a
+      // per-lane branch, would wait before the next one is issued)
       double xv[KB];
 #pragma unroll
-      for (int q = 0; q < KB; ++q) xv[q] = xc[(size_t)min(q, kb - 1) * n];
+      for (int q = 0; q < KB; ++q)
+        if (q < kmax) xv[q] = xc[(size_t)min(q, kb - 1) * n];   // kmax is uniform: no per-lane branch
 #pragma unroll
-      for (int q = 0; q < KB; ++q) acc[q] += q < kb ? v * xv[q] : 0.0;
+      for (int q = 0; q < KB; ++q)
+        if (q < kmax) acc[q] += q < kb ? v * xv[q] : 0.0;
     }
 #pragma unroll
     for (int q = 0; q < KB; ++q)
