@@ -305,3 +305,27 @@ def test_apply_split_shape_changes_only_rounding(gpu_lib, method, n_c, chunk, ta
     f1.apply(_to_dev(b), z1)
     z0, z1 = _to_host(z0), _to_host(z1)
     assert np.abs(z1 - z0).max() <= 1e-12 * np.abs(z0).max()
+
+
+@pytest.mark.parametrize("method,n_c", [("hodlr", 64), ("dense", 0)])
+def test_apply_folds_split_outputs_into_their_reader(gpu_lib, method, n_c):
+    """With split K forced (64-wide k ranges), the products that read a split
+    product's output run in the fold kernel (partial slices summed while
+    loading B, no reduction launch for them), and the apply equals the
+    apply without any split to 1e-12 in FP64."""
+    mfh = gpu_lib
+    p = q1_grid(16, 3)
+    print(f"case fold {method}", flush=True)
+    sym = mfh.Symbolic.from_csr(p.A, p.coords, 32)
+    kw = dict(method=method, precision="fp64", n_c=n_c)
+    f0 = mfh.Factor(sym, p.A.vals, 1e-6, apply_split_target=1, **kw)
+    f1 = mfh.Factor(sym, p.A.vals, 1e-6, apply_split_chunk=64, apply_split_target=2048, **kw)
+    b = rhs(p.A.n, 5, "normal", 19)
+    z0, z1 = _to_dev(np.zeros_like(b)), _to_dev(np.zeros_like(b))
+    f0.apply(_to_dev(b), z0)
+    mfh.prof_start()
+    f1.apply(_to_dev(b), z1)
+    stats = {s["name"]: s for s in mfh.prof_stop()}
+    assert stats.get("gemm_narrow_fold_kernel<double>", {}).get("launches", 0) > 0, sorted(stats)
+    z0, z1 = _to_host(z0), _to_host(z1)
+    assert np.abs(z1 - z0).max() <= 1e-12 * np.abs(z0).max()
